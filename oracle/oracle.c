@@ -1,0 +1,636 @@
+/* FP64 CPU oracle — test infrastructure only (see oracle.h).
+ *
+ * Build: plain C99, -O2 -ffp-contract=off, single-threaded.  FP32 appears in
+ * exactly one place, the pair-membership predicate, which the readings list
+ * defines in FP32 so that pair *sets* can be compared exactly with the GPU.
+ * Everything else is FP64.
+ */
+#include "oracle.h"
+
+#include <float.h>
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define COULOMB_F 138.935458 /* kJ mol^-1 nm e^-2 */
+#define TWO_PI 6.283185307179586476925286766559
+#define FORCE_LIMIT 1.0e6 /* kJ/mol/nm: above this a replica is unstable */
+
+struct ora_ctx {
+  ora_sys s;
+  /* exclusions as sorted per-atom lists (CSR) */
+  int32_t *ex_start, *ex_list;
+  /* native contact map C~(X_f) for solute pairs, dense [ns][ns] */
+  double *cmap_f;
+  /* FP32 geometry of the pair predicate */
+  float L32[3], invL32[3], rc2_32;
+  /* reaction-field constants */
+  double krf, crf;
+  /* scratch */
+  double *f_tmp, *fb_tmp, *grad_tmp;
+};
+
+/* ------------------------------------------------------------------------ */
+/* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as   */
+/* easy as 1, 2, 3", SC'11): 10 rounds of two 32x32->64 multiplies on a      */
+/* 4-word counter with a 2-word key bumped by Weyl constants between rounds.  */
+/* Parity pinned by the published known-answer vectors.                      */
+/* ------------------------------------------------------------------------ */
+void ora_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
+  uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+  uint32_t k0 = key[0], k1 = key[1];
+  for (int r = 0; r < 10; ++r) {
+    uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+    uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+    uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+    uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+    uint32_t n0 = hi1 ^ c1 ^ k0;
+    uint32_t n1 = lo1;
+    uint32_t n2 = hi0 ^ c3 ^ k1;
+    uint32_t n3 = lo0;
+    c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* Noise stream: key = 64-bit replica seed, counter = (atom, step, tag, 0).
+ * Each word w gives the uniform ((w >> 9) + 1/2) * 2^-23, exactly
+ * representable in FP32 and strictly inside (0, 1). */
+void ora_uniforms(uint64_t seed, uint32_t atom, uint32_t step, uint32_t tag, double u[4]) {
+  uint32_t ctr[4] = {atom, step, tag, 0u};
+  uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+  uint32_t w[4];
+  ora_philox4x32_10(ctr, key, w);
+  for (int k = 0; k < 4; ++k) u[k] = ((double)(w[k] >> 9) + 0.5) * (1.0 / 8388608.0);
+}
+
+/* Box-Muller in FP64 on the exact uniforms: (g0, g1) from (u0, u1), g2 from
+ * (u2, u3).  White noise of the Langevin equation (Eq. Lang). */
+void ora_normals(uint64_t seed, uint32_t atom, uint32_t step, uint32_t tag, double g[3]) {
+  double u[4];
+  ora_uniforms(seed, atom, step, tag, u);
+  double rho = sqrt(-2.0 * log(u[0]));
+  g[0] = rho * cos(TWO_PI * u[1]);
+  g[1] = rho * sin(TWO_PI * u[1]);
+  g[2] = sqrt(-2.0 * log(u[2])) * cos(TWO_PI * u[3]);
+}
+
+/* ------------------------------------------------------------------------ */
+/* context                                                                   */
+/* ------------------------------------------------------------------------ */
+static int cmp_i32(const void *a, const void *b) {
+  int32_t x = *(const int32_t *)a, y = *(const int32_t *)b;
+  return (x > y) - (x < y);
+}
+
+/* Smoothly truncated contact value (supplement, "Collective coordinate"):
+ * C(r) = (1 - (r/r0)^6) / (1 - (r/r0)^10), evaluated in the equivalent form
+ * (1+u+u^2)/(1+u+u^2+u^3+u^4) with u = (r/r0)^2, which is finite at r = r0
+ * (value 3/5), times a quintic switch S(r) that is 1 below rs and 0 above rc.
+ * Returns C*S and its r-derivative. */
+double ora_contact_value(double r, double r0, double rs, double rc, double *dcdr) {
+  double u = (r / r0) * (r / r0);
+  double num = 1.0 + u + u * u;
+  double den = num + u * u * u + u * u * u * u;
+  double c = num / den;
+  double dnum = 1.0 + 2.0 * u;
+  double dden = dnum + 3.0 * u * u + 4.0 * u * u * u;
+  double dcdu = (dnum * den - num * dden) / (den * den);
+  double dc = dcdu * 2.0 * r / (r0 * r0);
+  double sw = 1.0, dsw = 0.0;
+  if (r >= rc) {
+    sw = 0.0;
+  } else if (r > rs) {
+    double t = (r - rs) / (rc - rs);
+    sw = 1.0 - t * t * t * (10.0 - 15.0 * t + 6.0 * t * t);
+    dsw = -30.0 * t * t * (1.0 - t) * (1.0 - t) / (rc - rs);
+  }
+  if (dcdr) *dcdr = dc * sw + c * dsw;
+  return c * sw;
+}
+
+ora_ctx *ora_create(const ora_sys *s) {
+  ora_ctx *c = (ora_ctx *)calloc(1, sizeof(ora_ctx));
+  if (!c) return NULL;
+  c->s = *s;
+  int n = s->n_atoms;
+  /* exclusions: both directions, sorted */
+  int32_t *cnt = (int32_t *)calloc((size_t)n + 1, sizeof(int32_t));
+  for (int e = 0; e < s->n_excl; ++e) {
+    cnt[s->excl[2 * e]]++;
+    cnt[s->excl[2 * e + 1]]++;
+  }
+  c->ex_start = (int32_t *)calloc((size_t)n + 1, sizeof(int32_t));
+  for (int i = 0; i < n; ++i) c->ex_start[i + 1] = c->ex_start[i] + cnt[i];
+  c->ex_list = (int32_t *)malloc(sizeof(int32_t) * (size_t)(c->ex_start[n] + 1));
+  memset(cnt, 0, sizeof(int32_t) * ((size_t)n + 1));
+  for (int e = 0; e < s->n_excl; ++e) {
+    int a = s->excl[2 * e], b = s->excl[2 * e + 1];
+    c->ex_list[c->ex_start[a] + cnt[a]++] = b;
+    c->ex_list[c->ex_start[b] + cnt[b]++] = a;
+  }
+  for (int i = 0; i < n; ++i)
+    qsort(c->ex_list + c->ex_start[i], (size_t)(c->ex_start[i + 1] - c->ex_start[i]),
+          sizeof(int32_t), cmp_i32);
+  free(cnt);
+  for (int a = 0; a < 3; ++a) {
+    c->L32[a] = (float)s->box[a];
+    c->invL32[a] = (float)(1.0 / (double)c->L32[a]);
+  }
+  c->rc2_32 = (float)(s->r_cut * s->r_cut);
+  double rc = s->r_cut;
+  c->krf = (s->eps_rf - 1.0) / ((2.0 * s->eps_rf + 1.0) * rc * rc * rc);
+  c->crf = 1.0 / rc + c->krf * rc * rc;
+  int ns = s->n_solute;
+  if ((s->bias == ORA_BIAS_CONTACT || s->bias == ORA_BIAS_RMD_CONTACT) && s->x_final && ns > 0) {
+    c->cmap_f = (double *)calloc((size_t)ns * ns, sizeof(double));
+    for (int i = 0; i < ns; ++i)
+      for (int j = 0; j < ns; ++j) {
+        if (abs(i - j) <= s->contact_min_sep) continue;
+        double d[3], r2 = 0.0;
+        for (int a = 0; a < 3; ++a) {
+          d[a] = s->x_final[3 * j + a] - s->x_final[3 * i + a];
+          r2 += d[a] * d[a];
+        }
+        c->cmap_f[(size_t)i * ns + j] =
+            ora_contact_value(sqrt(r2), s->contact_r0, s->contact_rs, s->contact_rc, NULL);
+      }
+  }
+  c->f_tmp = (double *)calloc((size_t)3 * n, sizeof(double));
+  c->fb_tmp = (double *)calloc((size_t)3 * n, sizeof(double));
+  c->grad_tmp = (double *)calloc((size_t)3 * (ns > 0 ? ns : 1), sizeof(double));
+  return c;
+}
+
+void ora_destroy(ora_ctx *c) {
+  if (!c) return;
+  free(c->ex_start);
+  free(c->ex_list);
+  free(c->cmap_f);
+  free(c->f_tmp);
+  free(c->fb_tmp);
+  free(c->grad_tmp);
+  free(c);
+}
+
+static int excluded(const ora_ctx *c, int i, int j) {
+  for (int k = c->ex_start[i]; k < c->ex_start[i + 1]; ++k)
+    if (c->ex_list[k] == j) return 1;
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Pair membership.  Minimum image on FP32 copies of the coordinates:        */
+/*   d = fl32(xj - xi);  n = rint(fl32(d * (1/L)));  d' = fma(-n, L, d);     */
+/*   r2 = fma(dz', dz', fma(dy', dy', fl32(dx' * dx')));  in <=> r2 < rc^2.  */
+/* The FP64 separation used for the force is (xj - xi) - n L in FP64.        */
+/* ------------------------------------------------------------------------ */
+static int pair_in(const ora_ctx *c, const double *x, int i, int j, double d[3]) {
+  float dp[3];
+  for (int a = 0; a < 3; ++a) {
+    float xi = (float)x[3 * i + a], xj = (float)x[3 * j + a];
+    float t = xj - xi;
+    float prod = t * c->invL32[a];
+    float n = rintf(prod);
+    dp[a] = fmaf(-n, c->L32[a], t);
+    d[a] = (x[3 * j + a] - x[3 * i + a]) - (double)n * c->s.box[a];
+  }
+  float sq = dp[0] * dp[0];
+  float r2 = fmaf(dp[2], dp[2], fmaf(dp[1], dp[1], sq));
+  return r2 < c->rc2_32;
+}
+
+/* Brute force: every unordered pair, definition of the interaction set. */
+static int64_t pairs_brute(const ora_ctx *c, const double *x, int32_t *out, int64_t cap,
+                           void (*visit)(ora_ctx *, int, int, const double *, void *), void *arg) {
+  int n = c->s.n_atoms;
+  int64_t np = 0;
+  double d[3];
+  for (int i = 0; i < n; ++i)
+    for (int j = i + 1; j < n; ++j) {
+      if (!pair_in(c, x, i, j, d)) continue;
+      if (excluded(c, i, j)) continue;
+      if (visit) visit((ora_ctx *)c, i, j, d, arg);
+      if (out && np < cap) {
+        out[2 * np] = i;
+        out[2 * np + 1] = j;
+      }
+      ++np;
+    }
+  return np;
+}
+
+/* Cell list (cells of side >= rc, FP64 wrapped coordinates); visits the same
+ * set as the brute force because the predicate is the same. */
+static int64_t pairs_cells(const ora_ctx *c, const double *x, int32_t *out, int64_t cap,
+                           void (*visit)(ora_ctx *, int, int, const double *, void *), void *arg) {
+  int n = c->s.n_atoms;
+  int nc[3];
+  for (int a = 0; a < 3; ++a) {
+    nc[a] = (int)floor(c->s.box[a] / (c->s.r_cut * (1.0 + 1e-5)));
+    if (nc[a] < 1) nc[a] = 1;
+  }
+  int ncell = nc[0] * nc[1] * nc[2];
+  int32_t *head = (int32_t *)malloc(sizeof(int32_t) * (size_t)ncell);
+  int32_t *next = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+  int32_t *cell = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+  for (int k = 0; k < ncell; ++k) head[k] = -1;
+  for (int i = n - 1; i >= 0; --i) {
+    int ci[3];
+    for (int a = 0; a < 3; ++a) {
+      double L = c->s.box[a];
+      double w = x[3 * i + a] - floor(x[3 * i + a] / L) * L;
+      int k = (int)floor(w * nc[a] / L);
+      if (k < 0) k = 0;
+      if (k >= nc[a]) k = nc[a] - 1;
+      ci[a] = k;
+    }
+    int id = (ci[2] * nc[1] + ci[1]) * nc[0] + ci[0];
+    cell[i] = id;
+    next[i] = head[id];
+    head[id] = i;
+  }
+  int64_t np = 0;
+  double d[3];
+  for (int cz = 0; cz < nc[2]; ++cz)
+    for (int cy = 0; cy < nc[1]; ++cy)
+      for (int cx = 0; cx < nc[0]; ++cx) {
+        int home = (cz * nc[1] + cy) * nc[0] + cx;
+        /* distinct neighbour cells (a box with < 3 cells per side wraps) */
+        int nb[27], nnb = 0;
+        for (int dz = -1; dz <= 1; ++dz)
+          for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx) {
+              int ox = ((cx + dx) % nc[0] + nc[0]) % nc[0];
+              int oy = ((cy + dy) % nc[1] + nc[1]) % nc[1];
+              int oz = ((cz + dz) % nc[2] + nc[2]) % nc[2];
+              int id = (oz * nc[1] + oy) * nc[0] + ox;
+              int dup = 0;
+              for (int k = 0; k < nnb; ++k) dup |= (nb[k] == id);
+              if (!dup) nb[nnb++] = id;
+            }
+        for (int i = head[home]; i >= 0; i = next[i])
+          for (int k = 0; k < nnb; ++k)
+            for (int j = head[nb[k]]; j >= 0; j = next[j]) {
+              if (j <= i) continue;
+              if (!pair_in(c, x, i, j, d)) continue;
+              if (excluded(c, i, j)) continue;
+              if (visit) visit((ora_ctx *)c, i, j, d, arg);
+              if (out && np < cap) {
+                out[2 * np] = i;
+                out[2 * np + 1] = j;
+              }
+              ++np;
+            }
+      }
+  free(head);
+  free(next);
+  free(cell);
+  return np;
+}
+
+int64_t ora_pairs(const ora_ctx *c, const double *x, int32_t use_cells, int32_t *out, int64_t cap) {
+  return use_cells ? pairs_cells(c, x, out, cap, NULL, NULL) : pairs_brute(c, x, out, cap, NULL, NULL);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Potential U(X,Y) of Eq. Lang: potential-shifted LJ with Lorentz-Berthelot */
+/* mixing + reaction-field Coulomb for non-excluded pairs inside rc,        */
+/* harmonic bonds and angles.                                               */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+  double *f;
+  double e_lj, e_rf;
+} nb_acc;
+
+static void nb_visit(ora_ctx *c, int i, int j, const double *d, void *arg) {
+  nb_acc *acc = (nb_acc *)arg;
+  const ora_sys *s = &c->s;
+  double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+  double r = sqrt(r2);
+  double sig = 0.5 * (s->sigma[i] + s->sigma[j]);
+  double eps = sqrt(s->epsilon[i] * s->epsilon[j]);
+  double fscal = 0.0; /* -(dV/dr)/r */
+  if (eps > 0.0) {
+    double sr2 = sig * sig / r2;
+    double sr6 = sr2 * sr2 * sr2;
+    double src2 = sig * sig / (s->r_cut * s->r_cut);
+    double src6 = src2 * src2 * src2;
+    acc->e_lj += 4.0 * eps * (sr6 * sr6 - sr6) - 4.0 * eps * (src6 * src6 - src6);
+    fscal += 24.0 * eps * (2.0 * sr6 * sr6 - sr6) / r2;
+  }
+  double qq = COULOMB_F * s->charge[i] * s->charge[j];
+  if (qq != 0.0) {
+    acc->e_rf += qq * (1.0 / r + c->krf * r2 - c->crf);
+    fscal += qq * (1.0 / (r2 * r) - 2.0 * c->krf);
+  }
+  for (int a = 0; a < 3; ++a) {
+    acc->f[3 * i + a] -= fscal * d[a];
+    acc->f[3 * j + a] += fscal * d[a];
+  }
+}
+
+static void bonded(const ora_ctx *c, const double *x, double *f, double *e_bond, double *e_angle) {
+  const ora_sys *s = &c->s;
+  double eb = 0.0, ea = 0.0;
+  for (int b = 0; b < s->n_bonds; ++b) {
+    int i = s->bonds[2 * b], j = s->bonds[2 * b + 1];
+    double d[3], r2 = 0.0;
+    for (int a = 0; a < 3; ++a) {
+      d[a] = x[3 * j + a] - x[3 * i + a];
+      r2 += d[a] * d[a];
+    }
+    double r = sqrt(r2);
+    double dr = r - s->bond_r0[b];
+    eb += 0.5 * s->bond_k[b] * dr * dr;
+    double g = s->bond_k[b] * dr / r; /* dV/dr / r */
+    for (int a = 0; a < 3; ++a) {
+      f[3 * i + a] += g * d[a];
+      f[3 * j + a] -= g * d[a];
+    }
+  }
+  for (int k = 0; k < s->n_angles; ++k) {
+    int ia = s->angles[3 * k], ic = s->angles[3 * k + 1], ib = s->angles[3 * k + 2];
+    double u[3], w[3], uu = 0.0, ww = 0.0, uw = 0.0;
+    for (int a = 0; a < 3; ++a) {
+      u[a] = x[3 * ia + a] - x[3 * ic + a];
+      w[a] = x[3 * ib + a] - x[3 * ic + a];
+      uu += u[a] * u[a];
+      ww += w[a] * w[a];
+      uw += u[a] * w[a];
+    }
+    double nu = sqrt(uu), nw = sqrt(ww);
+    double cs = uw / (nu * nw);
+    if (cs > 1.0) cs = 1.0;
+    if (cs < -1.0) cs = -1.0;
+    double th = acos(cs);
+    double sn = sqrt(1.0 - cs * cs);
+    if (sn < 1e-12) sn = 1e-12;
+    double dth = th - s->angle_theta0[k];
+    ea += 0.5 * s->angle_k[k] * dth * dth;
+    double dv = s->angle_k[k] * dth; /* dV/dtheta */
+    /* dtheta/du = -(w/(|u||w|) - cos u/|u|^2)/sin */
+    for (int a = 0; a < 3; ++a) {
+      double dcu = w[a] / (nu * nw) - cs * u[a] / uu;
+      double dcw = u[a] / (nu * nw) - cs * w[a] / ww;
+      double fa = dv / sn * dcu;
+      double fb = dv / sn * dcw;
+      f[3 * ia + a] += fa;
+      f[3 * ib + a] += fb;
+      f[3 * ic + a] -= fa + fb;
+    }
+  }
+  *e_bond = eb;
+  *e_angle = ea;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Collective variables (solute only, unwrapped coordinates, no periodic     */
+/* images: the solute is one connected molecule).                            */
+/*   RG:      mass-weighted radius of gyration.                              */
+/*   CONTACT: z = sum_{i<j, j-i > min_sep} (C~_ij(X) - C~_ij(X_f))^2         */
+/*            (supplement, "Collective coordinate"; unordered pairs).         */
+/* Returns z and writes dz/dx_i for solute atoms.                             */
+/* ------------------------------------------------------------------------ */
+double ora_cv(const ora_ctx *c, const double *x, double *grad) {
+  const ora_sys *s = &c->s;
+  int ns = s->n_solute;
+  if (grad) memset(grad, 0, sizeof(double) * 3 * (size_t)ns);
+  if (s->bias == ORA_BIAS_RG) {
+    double M = 0.0, cm[3] = {0, 0, 0};
+    for (int i = 0; i < ns; ++i) {
+      M += s->mass[i];
+      for (int a = 0; a < 3; ++a) cm[a] += s->mass[i] * x[3 * i + a];
+    }
+    for (int a = 0; a < 3; ++a) cm[a] /= M;
+    double acc = 0.0;
+    for (int i = 0; i < ns; ++i)
+      for (int a = 0; a < 3; ++a) {
+        double d = x[3 * i + a] - cm[a];
+        acc += s->mass[i] * d * d;
+      }
+    double rg = sqrt(acc / M);
+    if (grad && rg > 0.0)
+      for (int i = 0; i < ns; ++i)
+        for (int a = 0; a < 3; ++a) grad[3 * i + a] = s->mass[i] * (x[3 * i + a] - cm[a]) / (M * rg);
+    return rg;
+  }
+  if ((s->bias == ORA_BIAS_CONTACT || s->bias == ORA_BIAS_RMD_CONTACT) && c->cmap_f) {
+    double z = 0.0;
+    for (int i = 0; i < ns; ++i)
+      for (int j = i + s->contact_min_sep + 1; j < ns; ++j) {
+        double d[3], r2 = 0.0;
+        for (int a = 0; a < 3; ++a) {
+          d[a] = x[3 * j + a] - x[3 * i + a];
+          r2 += d[a] * d[a];
+        }
+        double r = sqrt(r2), dc;
+        double cij = ora_contact_value(r, s->contact_r0, s->contact_rs, s->contact_rc, &dc);
+        double diff = cij - c->cmap_f[(size_t)i * ns + j];
+        z += diff * diff;
+        if (grad) {
+          double g = 2.0 * diff * dc / r; /* dz/dr / r */
+          for (int a = 0; a < 3; ++a) {
+            grad[3 * j + a] += g * d[a];
+            grad[3 * i + a] -= g * d[a];
+          }
+        }
+      }
+    return z;
+  }
+  return 0.0;
+}
+
+/* Reference of the harmonic bias, ramped linearly from z(X_0) to z_target
+ * at rate rho (1/ps) and held there. */
+static double z_ref(const ora_sys *s, double z0, double t) {
+  double w = 1.0 - s->ramp_rate * t;
+  if (w < 0.0) w = 0.0;
+  return s->z_target + (z0 - s->z_target) * w;
+}
+
+/* Bias force on solute atoms (text after Eq. Lang; Eq. VR for the ratchet).
+ * Returns S = sum_i |F_i^bias|^2 / (gamma_i m_i), the integrand of the
+ * variational functional (Eq. VMDcondition). */
+static double bias_force(ora_ctx *c, const double *x, double t, double z0, double z_m,
+                         double *fb, double *terms) {
+  const ora_sys *s = &c->s;
+  int ns = s->n_solute;
+  memset(fb, 0, sizeof(double) * 3 * (size_t)s->n_atoms);
+  double z = 0.0, zr = 0.0, ub = 0.0;
+  if (s->bias == ORA_BIAS_CONST && s->const_force) {
+    for (int i = 0; i < 3 * ns; ++i) fb[i] = s->const_force[i];
+  } else if (s->bias == ORA_BIAS_RG || s->bias == ORA_BIAS_CONTACT) {
+    z = ora_cv(c, x, c->grad_tmp);
+    zr = z_ref(s, z0, t);
+    double k = s->bias_k;
+    ub = 0.5 * k * (z - zr) * (z - zr);
+    for (int i = 0; i < 3 * ns; ++i) fb[i] = -k * (z - zr) * c->grad_tmp[i];
+  } else if (s->bias == ORA_BIAS_RMD_CONTACT) {
+    z = ora_cv(c, x, c->grad_tmp);
+    double zm = z_m < z ? z_m : z; /* running minimum, updated first */
+    zr = zm;
+    if (z > zm) {
+      double k = s->bias_k;
+      ub = 0.25 * k * (z - zm) * (z - zm);
+      for (int i = 0; i < 3 * ns; ++i) fb[i] = -0.5 * k * (z - zm) * c->grad_tmp[i];
+    }
+  }
+  double S = 0.0;
+  for (int i = 0; i < ns; ++i) {
+    double f2 = fb[3 * i] * fb[3 * i] + fb[3 * i + 1] * fb[3 * i + 1] + fb[3 * i + 2] * fb[3 * i + 2];
+    S += f2 / (s->gamma[i] * s->mass[i]);
+  }
+  if (terms) {
+    terms[ORA_E_BIAS] = ub;
+    terms[ORA_Z] = z;
+    terms[ORA_ZREF] = zr;
+    terms[ORA_S] = S;
+  }
+  return S;
+}
+
+/* Total force F = -grad U + F^bias at time t.  f, fbias: [n][3] (fbias may be
+ * NULL).  terms: [ORA_N_TERMS] (may be NULL).  Returns 1 if any force is
+ * non-finite or above the instability limit. */
+int ora_forces(ora_ctx *c, const double *x, double t, const ora_state *st, int32_t use_cells,
+               double *f, double *fbias, double *terms) {
+  const ora_sys *s = &c->s;
+  int n = s->n_atoms;
+  double tl[ORA_N_TERMS];
+  memset(tl, 0, sizeof(tl));
+  memset(f, 0, sizeof(double) * 3 * (size_t)n);
+  nb_acc acc = {f, 0.0, 0.0};
+  if (use_cells)
+    pairs_cells(c, x, NULL, 0, nb_visit, &acc);
+  else
+    pairs_brute(c, x, NULL, 0, nb_visit, &acc);
+  tl[ORA_E_LJ] = acc.e_lj;
+  tl[ORA_E_RF] = acc.e_rf;
+  bonded(c, x, f, &tl[ORA_E_BOND], &tl[ORA_E_ANGLE]);
+  double z0 = st ? st->z0 : 0.0;
+  double zm = st ? st->z_m : DBL_MAX;
+  bias_force(c, x, t, z0, zm, c->fb_tmp, tl);
+  int bad = 0;
+  for (int i = 0; i < 3 * n; ++i) {
+    f[i] += c->fb_tmp[i];
+    if (!isfinite(f[i]) || fabs(f[i]) > FORCE_LIMIT) bad = 1;
+  }
+  if (fbias) memcpy(fbias, c->fb_tmp, sizeof(double) * 3 * (size_t)n);
+  if (terms) memcpy(terms, tl, sizeof(tl));
+  return bad;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Trajectories: BAOAB splitting of Eq. Lang with white noise of variance    */
+/* 2 m gamma kT per unit time (the weight 1/(4 kT gamma m) of Eq. StrVMD).    */
+/* Step n -> n+1:  v += dt/2 F_n/m;  x += dt/2 v;                             */
+/*                 v = c1 v + sqrt((1-c1^2) kT/m) g(n);  x += dt/2 v;         */
+/*                 F_{n+1} = F(x_{n+1}, t_{n+1});  v += dt/2 F_{n+1}/m.       */
+/* Functional (Eq. VMDcondition, prefactor of Eq. StrVMD), trapezoid in time: */
+/*   Phi = dt/(4 kT) * sum_n w_n S_n,  w_0 = w_N = 1/2, else 1.                */
+/* ------------------------------------------------------------------------ */
+void ora_maxwell(const ora_ctx *c, double *v) {
+  const ora_sys *s = &c->s;
+  for (int i = 0; i < s->n_atoms; ++i) {
+    double g[3];
+    ora_normals(s->seed, (uint32_t)i, 0u, 1u, g);
+    double sd = sqrt(s->kT / s->mass[i]);
+    for (int a = 0; a < 3; ++a) v[3 * i + a] = sd * g[a];
+  }
+}
+
+int ora_init(ora_ctx *c, const double *x0, ora_state *st) {
+  memset(st, 0, sizeof(*st));
+  st->z0 = ora_cv(c, x0, NULL);
+  st->z_m = st->z0;
+  double terms[ORA_N_TERMS];
+  int bad = ora_forces(c, x0, 0.0, st, 1, c->f_tmp, NULL, terms);
+  st->phi_acc = 0.5 * terms[ORA_S];
+  st->s_last = terms[ORA_S];
+  st->z_last = terms[ORA_Z];
+  st->status = bad;
+  return bad;
+}
+
+int ora_run(ora_ctx *c, double *x, double *v, ora_state *st, int32_t nsteps, int32_t use_cells,
+            double *traj) {
+  const ora_sys *s = &c->s;
+  int n = s->n_atoms;
+  double dt = s->dt;
+  double *f = c->f_tmp;
+  double terms[ORA_N_TERMS];
+  if (st->status) return st->status;
+  if (ora_forces(c, x, (double)st->step * dt, st, use_cells, f, NULL, terms)) {
+    st->status = 1;
+    return 1;
+  }
+  for (int it = 0; it < nsteps; ++it) {
+    uint32_t step = (uint32_t)st->step;
+    for (int i = 0; i < n; ++i) {
+      double m = s->mass[i];
+      double c1 = exp(-s->gamma[i] * dt);
+      double sd = sqrt((1.0 - c1 * c1) * s->kT / m);
+      double g[3];
+      ora_normals(s->seed, (uint32_t)i, step, 0u, g);
+      for (int a = 0; a < 3; ++a) {
+        double vv = v[3 * i + a] + 0.5 * dt * f[3 * i + a] / m;
+        double xx = x[3 * i + a] + 0.5 * dt * vv;
+        vv = c1 * vv + sd * g[a];
+        xx = xx + 0.5 * dt * vv;
+        v[3 * i + a] = vv;
+        x[3 * i + a] = xx;
+      }
+    }
+    st->step += 1;
+    /* ratchet minimum is updated before the force at the new step */
+    int bad = ora_forces(c, x, (double)st->step * dt, st, use_cells, f, NULL, terms);
+    if (s->bias == ORA_BIAS_RMD_CONTACT && terms[ORA_Z] < st->z_m) st->z_m = terms[ORA_Z];
+    for (int i = 0; i < n; ++i)
+      for (int a = 0; a < 3; ++a) v[3 * i + a] += 0.5 * dt * f[3 * i + a] / s->mass[i];
+    st->phi_acc += terms[ORA_S];
+    st->s_last = terms[ORA_S];
+    st->z_last = terms[ORA_Z];
+    if (traj) memcpy(traj + (size_t)it * 3 * n, x, sizeof(double) * 3 * (size_t)n);
+    if (bad) {
+      st->status = 1;
+      return 1;
+    }
+  }
+  return 0;
+}
+
+double ora_phi(const ora_ctx *c, const ora_state *st) {
+  if (st->status) return INFINITY;
+  return (st->phi_acc - 0.5 * st->s_last) * c->s.dt / (4.0 * c->s.kT);
+}
+
+/* Product reached: |z(X_T) - z_target| <= reach_tol (stands in for the
+ * RMSD < 2 A folding criterion of the main text). */
+int ora_reached(const ora_ctx *c, const ora_state *st) {
+  if (st->status) return 0;
+  return fabs(st->z_last - c->s.z_target) <= c->s.reach_tol;
+}
+
+/* Variational selection (Eq. VMDcondition and the folding-event criterion):
+ * least Phi over trials that reached the product, are eligible and finite;
+ * ties go to the lowest index.  Returns 0, or -1 if no trial qualifies. */
+int ora_select(int32_t n, const double *phi, const uint8_t *reached, const uint8_t *eligible,
+               int32_t *best, double *best_phi) {
+  int32_t b = -1;
+  double bp = INFINITY;
+  for (int32_t r = 0; r < n; ++r) {
+    if (reached && !reached[r]) continue;
+    if (eligible && !eligible[r]) continue;
+    if (!isfinite(phi[r])) continue;
+    if (b < 0 || phi[r] < bp) {
+      b = r;
+      bp = phi[r];
+    }
+  }
+  *best = b;
+  *best_phi = bp;
+  return b < 0 ? -1 : 0;
+}
