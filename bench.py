@@ -1,0 +1,172 @@
+#!/usr/bin/env python3
+"""Throughput of batched biased-Langevin trial paths on one MI355X.
+
+Workload: 64 trial trajectories of the 12,560-atom solvated system (560-atom
+synthetic solute + 4,000 flexible three-site waters, 5.0 nm box, 1.0 nm
+cutoff, dt = 1 fs, contact-map bias ramped toward a seeded target map), all
+replicas in one batch, every step replayed from captured hipGraphs.  Seeded
+synthetic inputs stand in for the paper's protein systems.
+
+One benchmark step = one pass of the whole hot path over the batch: a block
+of MD steps (pair-list maintenance, nonbonded + bonded forces, collective
+variable and bias, BAOAB integration with Philox noise, FP64 functional
+accumulation) followed by reading the functional and the variational
+selection.  The reported value is whole-job atom-steps per second.
+
+Beside it: the plain one-trajectory form (one replica, every kernel launched
+per step, no graph), the nonbonded kernel against the FP32 vector roofline
+(average duration from HIP events around every force launch in the timed
+region), and the FP64 CPU oracle timed on a bounded sample on the host.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FLOP_PER_PAIR = 35          # algorithmic flops per unique in-cutoff pair (force only)
+PEAK_FP32_TFLOPS = 157.3    # MI355X FP32 vector peak
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=30, help="timed benchmark steps")
+    ap.add_argument("--warmup", type=int, default=5, help="untimed benchmark steps")
+    ap.add_argument("--md-per-step", type=int, default=20, help="MD steps per benchmark step")
+    ap.add_argument("--replicas", type=int, default=64)
+    ap.add_argument("--plain-steps", type=int, default=200)
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the trial paths are "
+              "independent, so several GPUs would each run this benchmark on their own share.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1405_6104_amd import synth, vp
+
+    torch.cuda.set_device(0)
+    B = args.md_per_step
+    t0 = time.time()
+    base = synth.c2_single()
+    reps = synth.c3_batch(args.replicas, base=base, n_steps=B * (args.steps + args.warmup))
+    n_atoms = sum(int(d["n_atoms"]) for d in reps)
+    print(f"# generated {len(reps)} replicas, {n_atoms} atoms in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
+    system = vp.System(reps, steps_per_graph=B, timing=True)
+    print(f"# system created", file=sys.stderr, flush=True)
+
+    for _ in range(args.warmup):
+        system.step_batch(B)
+        system.functional()
+    system.kernel_timing(reset=True)
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        system.step_batch(B)
+        system.functional()
+        system.select_path()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    force_ms, n_launch = system.kernel_timing()
+    obs = system.observables()
+    unstable = int(np.sum((obs[:, 5].astype(int) & 1) != 0))
+    overflow = int(np.sum((obs[:, 5].astype(int) & 2) != 0))
+    pairs = [system.pair_count(r) for r in range(len(reps))]
+    pairs_total = int(sum(pairs))
+    md_steps = args.steps * B
+    value = n_atoms * md_steps / elapsed
+    ms_per_step = 1e3 * elapsed / args.steps
+    achieved = FLOP_PER_PAIR * pairs_total / (force_ms * 1e-3) / 1e12
+    dt_fs = float(base["dt"]) * 1000.0
+    ns_day = (md_steps / elapsed) * dt_fs * 1e-6 * 86400.0
+    print(f"# batched: {value:.4e} atom-steps/s, force kernel {force_ms:.4f} ms x {n_launch}, "
+          f"{pairs_total} pairs, rebuilds/replica {obs[:, 6].mean():.1f}, unstable {unstable}",
+          file=sys.stderr, flush=True)
+    del system
+    torch.cuda.empty_cache()
+
+    plain = None
+    if not args.no_plain:
+        ps = vp.System([dict(reps[0])], use_graph=False, steps_per_graph=1)
+        for _ in range(20):
+            ps.step_batch(1)
+        torch.cuda.synchronize()
+        tp = time.perf_counter()
+        for _ in range(args.plain_steps):
+            ps.step_batch(1)
+        torch.cuda.synchronize()
+        tp = time.perf_counter() - tp
+        plain = int(reps[0]["n_atoms"]) * args.plain_steps / tp
+        print(f"# plain: {plain:.4e} atom-steps/s ({1e3 * tp / args.plain_steps:.3f} ms/step)",
+              file=sys.stderr, flush=True)
+        del ps
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import oracle as O  # CPU baseline leg only
+        o = O.Oracle(base)
+        x = np.array(base["x0"], dtype=np.float64)
+        v = o.maxwell()
+        st = o.init(x)
+        n_cpu = 0
+        tc = time.perf_counter()
+        while time.perf_counter() - tc < args.cpu_seconds:
+            o.run(x, v, st, 1)
+            n_cpu += 1
+        tc = time.perf_counter() - tc
+        cpu = {"value": int(base["n_atoms"]) * n_cpu / tc, "unit": "atom-steps/s", "cores": 1,
+               "kind": "oracle",
+               "sample": f"{n_cpu} BAOAB steps of one 12,560-atom replica (FP64, single thread, "
+                         f"cell-list pairs), {tc:.1f} s"}
+        print(f"# cpu oracle: {cpu['value']:.4e} atom-steps/s over {n_cpu} steps", file=sys.stderr, flush=True)
+
+    out = {
+        "metric": "atom-steps/sec (ns/day) for batched biased Langevin MD vs plain form; % VALU peak",
+        "value": value,
+        "unit": "atom-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 pair arithmetic, i64 fixed-point forces, f64 functional",
+        "data": "synthetic",
+        "config": {
+            "workload": "64 trial paths x 12,560 atoms (560-atom solute + 4,000 flexible waters), "
+                        "5.0 nm box, rc 1.0 nm, dt 1 fs, contact-map bias, graph-captured batch",
+            "replicas": len(reps), "atoms_per_replica": int(base["n_atoms"]),
+            "md_steps_per_bench_step": B, "global_batch": n_atoms, "parallelism": "replicas",
+        },
+        "ns_per_day_per_replica": ns_day,
+        "plain_atom_steps_per_s": plain,
+        "batched_over_plain": (value / plain) if plain else None,
+        "pair_interactions_per_s": pairs_total / (force_ms * 1e-3),
+        "unstable_replicas": unstable,
+        "list_overflow_replicas": overflow,
+        "roofline": {
+            "bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+            "kernel": "k_forces (nonbonded LJ+RF + bonded)",
+            "flop_per_unit": FLOP_PER_PAIR, "units_per_launch": pairs_total,
+            "avg_launch_ms": force_ms, "launches_timed": n_launch,
+        },
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

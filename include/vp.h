@@ -1,0 +1,201 @@
+/* vp.h — C ABI of the MI355X (gfx950) library for batched biased-Langevin
+ * trial paths scored by the variational functional of
+ * S. a Beccara, L. Fant, P. Faccioli, "Variational scheme to compute protein
+ * reaction pathways using atomistic force fields with explicit solvent"
+ * (arXiv:1405.6104).
+ *
+ * The library integrates many independent trial trajectories of a solute X
+ * (atoms [0, n_solute)) in explicit solvent Y (the remaining atoms) with the
+ * Langevin equations of motion of the paper (Eq. Lang), adds an external,
+ * time-dependent bias force on the solute only (text after Eq. Lang; the
+ * ratchet form is Eq. VR), accumulates per trajectory the functional
+ *     Phi = 1/(4 kT) * int_0^t dtau sum_{i in X} |F_i^bias|^2 / (gamma_i m_i)
+ * (Eq. VMDcondition with the prefactor of the path action, Eq. StrVMD), and
+ * selects the trajectory with the least Phi among those that reached the
+ * product (main text, folding-event criterion).
+ *
+ * Conventions for every entry point:
+ *   - units: nm, ps, amu, kJ/mol, elementary charge; angles in radians;
+ *   - every function returns vp_status (VP_OK == 0); nothing throws or exits;
+ *     on error vp_last_error() returns a message (thread-local, valid until
+ *     the next call on the same thread);
+ *   - "host" pointers are read synchronously and may be freed on return;
+ *     "device" pointers are HIP device allocations that must stay valid
+ *     until the work enqueued on the given stream has completed;
+ *   - per-atom arrays of a batch concatenate the replicas in the order given
+ *     to vp_system_create, each replica's atoms in their original order
+ *     ("user order"); 3-vectors are stored as [atom][3] (AoS), FP32 unless
+ *     stated otherwise;
+ *   - hip_stream is a hipStream_t passed as void* (NULL = default stream).
+ *   - one vp_system must not be used from two threads at once.
+ */
+#ifndef VP_H
+#define VP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct vp_system vp_system; /* opaque; owned by the library */
+
+typedef enum {
+  VP_OK = 0,
+  VP_ERR_ARG = -1,    /* invalid argument (message says which) */
+  VP_ERR_HIP = -2,    /* a HIP runtime call or kernel failed */
+  VP_ERR_NOMEM = -3,  /* device or host allocation failed */
+  VP_ERR_STATE = -4,  /* call not valid in the current state */
+  VP_ERR_NOPATH = -5  /* vp_select_path: no eligible finite trajectory */
+} vp_status;
+
+typedef enum {
+  VP_BIAS_NONE = 0,
+  VP_BIAS_CONST = 1,       /* fixed force vector per solute atom (tests) */
+  VP_BIAS_RG = 2,          /* harmonic in the mass-weighted radius of gyration */
+  VP_BIAS_CONTACT = 3,     /* harmonic in the contact-map distance (supplement) */
+  VP_BIAS_RMD_CONTACT = 4  /* ratchet-and-pawl on the contact-map distance (Eq. VR) */
+} vp_bias_kind;
+
+/* Per-replica status word (vp_observables, column VP_OBS_STATUS). */
+enum { VP_REPLICA_OK = 0, VP_REPLICA_UNSTABLE = 1, VP_REPLICA_LIST_OVERFLOW = 2 };
+
+/* One trial trajectory: the problem statement of the paper (masses m_i,
+ * frictions gamma_i, kT, the potential U(X,Y), the bias F^bias(X,t), the
+ * initial configuration X_i (+ solvent) and the product X_f).  All pointers
+ * are HOST pointers, deep-copied by vp_system_create.
+ *
+ * Potential U(X,Y): Lennard-Jones, potential-shifted to zero at r_cut, with
+ * sigma_ij = (sigma_i+sigma_j)/2 and eps_ij = sqrt(eps_i eps_j); reaction-field
+ * Coulomb with dielectric eps_rf beyond r_cut (zero at r_cut); both over
+ * non-excluded pairs closer than r_cut under the minimum-image convention in
+ * an orthorhombic periodic box (r_cut < box/2); harmonic bonds 1/2 k (r-r0)^2
+ * and angles 1/2 k (theta-theta0)^2 on unwrapped coordinates.
+ *
+ * Bias (solute only): U_b = 1/2 bias_k (z(X) - z_ref(t))^2 with
+ * z_ref(t) = z_target + (z(X_0) - z_target) * max(0, 1 - ramp_rate * t);
+ * z is the radius of gyration (VP_BIAS_RG) or the contact-map distance
+ * sum_{i<j, j-i > contact_min_sep} (C~_ij(X) - C~_ij(X_f))^2 with
+ * C~ = C(r) S(r), C = (1-(r/r0)^6)/(1-(r/r0)^10), S a quintic switch from 1 at
+ * contact_rs to 0 at contact_rc.  VP_BIAS_RMD_CONTACT applies
+ * -(bias_k/2)(z - z_m) grad z while z > z_m, z_m the running minimum of z. */
+typedef struct {
+  int32_t n_atoms;   /* > 0 and <= 65536 */
+  int32_t n_solute;  /* 0 <= n_solute <= n_atoms; atoms [0, n_solute) are X */
+  const double *mass, *gamma, *charge, *sigma, *epsilon; /* [n_atoms] */
+  int32_t n_bonds;
+  const int32_t *bonds; /* [n_bonds][2] */
+  const double *bond_k, *bond_r0;
+  int32_t n_angles;
+  const int32_t *angles; /* [n_angles][3]: end, vertex, end */
+  const double *angle_k, *angle_theta0;
+  int32_t n_excl;
+  const int32_t *excl; /* [n_excl][2]: pairs without nonbonded interaction */
+  double box[3];       /* orthorhombic box edges */
+  double r_cut, eps_rf, kT, dt;
+  const double *x0;      /* [n_atoms][3] X_i (+ solvent), unwrapped */
+  const double *v0;      /* [n_atoms][3] or NULL: Maxwell-Boltzmann from the seed */
+  const double *x_final; /* [n_solute][3] X_f (defines the target contact map) or NULL */
+  int32_t bias;          /* vp_bias_kind */
+  double bias_k, ramp_rate, z_target;
+  double contact_r0, contact_rs, contact_rc;
+  int32_t contact_min_sep;
+  double reach_tol;          /* reached <=> |z(X_t) - z_target| <= reach_tol */
+  uint64_t seed;             /* Philox4x32-10 key of this trajectory's noise */
+  const double *const_force; /* [n_solute][3] for VP_BIAS_CONST, else NULL */
+} vp_replica_desc;
+
+typedef struct {
+  int32_t nstlist_max; /* upper bound on steps between pair-list builds (0: 100) */
+  double skin;         /* pair-list buffer in nm (0: 0.1) */
+  int32_t steps_per_graph; /* steps captured per hipGraph launch (0: 20) */
+  int32_t use_graph;       /* 1: replay captured graphs; 0: launch every kernel */
+  int32_t max_neighbors;   /* per-atom list capacity (0: derived from density) */
+  int32_t timing;          /* 1: record HIP events around every force-kernel launch
+                              (vp_step_batch then waits for each block; see
+                              vp_kernel_timing) */
+  int32_t reserved[6];
+} vp_options;
+
+/* Create a batch of trial trajectories.  reps: HOST array of n_reps
+ * descriptions (deep-copied).  opt: HOST, may be NULL for defaults.  Uploads
+ * parameters, draws Maxwell velocities where v0 is NULL, builds the pair
+ * lists and evaluates the forces and the functional integrand at t = 0.
+ * Returns VP_ERR_ARG for NULL pointers, n_reps <= 0, n_atoms out of range,
+ * r_cut >= box/2, indices out of range, negative masses/frictions, or a bias
+ * kind that lacks its data (x_final, const_force).  *out is NULL on error. */
+vp_status vp_system_create(const vp_replica_desc *reps, int32_t n_reps, const vp_options *opt,
+                           vp_system **out);
+
+/* Release every device and host resource.  NULL is accepted. */
+vp_status vp_system_destroy(vp_system *s);
+
+/* Total force F = -grad U + F^bias (Eq. Lang with the bias of the text after
+ * it) at time t for the positions x_dev of every replica, without touching
+ * the trajectory state.  x_dev: DEVICE [sum N][3] FP32 in user order;
+ * f_dev: DEVICE [sum N][3] FP32 output; energy_dev: DEVICE [n_reps][8] FP64
+ * output (or NULL) with columns LJ, RF, bond, angle, bias, z, z_ref, S where
+ * S = sum_i |F_i^bias|^2/(gamma_i m_i).  Ratchet replicas use their current
+ * running minimum.  Asynchronous on hip_stream. */
+vp_status vp_forces(vp_system *s, const float *x_dev, float *f_dev, double *energy_dev, double t,
+                    void *hip_stream);
+
+/* Advance every replica by n_steps BAOAB steps of Eq. Lang (>= 0),
+ * accumulating Phi.  Asynchronous on hip_stream. */
+vp_status vp_step_batch(vp_system *s, int32_t n_steps, void *hip_stream);
+
+/* Phi of every replica since creation (Eq. VMDcondition, trapezoid rule in
+ * time, 1/(4 kT) prefactor): phi_host HOST [n_reps]; +inf for an unstable
+ * replica.  dphi_dtheta_host must be NULL (reserved for the gradient with
+ * respect to (bias_k, ramp_rate)).  Synchronises the system's last stream. */
+vp_status vp_functional(vp_system *s, double *phi_host, double *dphi_dtheta_host);
+
+/* Variational selection: the replica with the least finite Phi among those
+ * that reached the product (|z - z_target| <= reach_tol at the current time)
+ * and whose eligible flag (HOST [n_reps], NULL = all) is nonzero; ties go to
+ * the lowest index.  Returns VP_ERR_NOPATH with *best = -1 when none
+ * qualifies.  Synchronises. */
+vp_status vp_select_path(vp_system *s, const uint8_t *eligible, int32_t *best, double *best_phi);
+
+/* Copy the current positions and velocities in user order into DEVICE
+ * buffers x_dev, v_dev ([sum N][3] FP32; either may be NULL). */
+vp_status vp_get_state(vp_system *s, float *x_dev, float *v_dev, void *hip_stream);
+
+/* Per-replica observables: obs_host HOST [n_reps][VP_OBS_COUNT] FP64. */
+enum { VP_OBS_STEP = 0, VP_OBS_Z, VP_OBS_ZREF, VP_OBS_ZMIN, VP_OBS_PHI, VP_OBS_STATUS,
+       VP_OBS_REBUILDS, VP_OBS_KE, VP_OBS_COUNT };
+vp_status vp_observables(vp_system *s, double *obs_host);
+
+/* Force-kernel timing (options.timing = 1): *avg_ms receives the mean
+ * duration of the nonbonded+bonded force kernel over the launches enqueued by
+ * vp_step_batch since the last reset, measured with HIP events on the stream
+ * it ran on, and *count their number.  reset != 0 clears the accumulators. */
+vp_status vp_kernel_timing(vp_system *s, double *avg_ms, int64_t *count, int32_t reset);
+
+/* Number of unordered pairs of replica rep whose current separation passes
+ * the force kernel's membership predicate (a diagnostic; synchronises). */
+vp_status vp_pair_count(vp_system *s, int32_t rep, int64_t *count);
+
+/* Sizes: total atoms of the batch and number of replicas. */
+vp_status vp_sizes(const vp_system *s, int64_t *n_atoms_total, int32_t *n_reps);
+
+/* Diagnostics for tests: copy the pair list of replica rep as unordered
+ * pairs (i < j, replica-local user indices) whose current FP32 separation
+ * passes the membership predicate, into pairs_host HOST [cap][2].
+ * *count receives the number of such pairs (which may exceed cap). */
+vp_status vp_debug_pairs(vp_system *s, int32_t rep, int32_t *pairs_host, int64_t cap,
+                         int64_t *count);
+
+/* Diagnostics for tests: draw the three Box-Muller normals the integrator
+ * uses for (seed, atom, step, tag) for n consecutive atoms starting at
+ * atom0.  out_dev: DEVICE [n][4] FP32 (g0, g1, g2, first uniform). */
+vp_status vp_debug_noise(uint64_t seed, uint32_t atom0, uint32_t step, uint32_t tag, int32_t n,
+                         float *out_dev, void *hip_stream);
+
+const char *vp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* VP_H */

@@ -1,0 +1,678 @@
+// Host runtime of the vp C ABI: validation, device layout, uploads, the step
+// schedule (direct launches or replayed hipGraphs), the functional and the
+// variational selection.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "vp_internal.h"
+#include "vp_launch.h"
+
+using namespace vp;
+
+namespace {
+
+thread_local std::string g_err;
+
+vp_status fail(vp_status st, const std::string &msg) {
+  g_err = msg;
+  return st;
+}
+
+#define HIPCHECK(expr)                                                              \
+  do {                                                                              \
+    hipError_t e_ = (expr);                                                         \
+    if (e_ != hipSuccess)                                                           \
+      return fail(VP_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_));   \
+  } while (0)
+
+template <class T>
+vp_status dalloc(vp_system *s, T **p, size_t count) {
+  *p = nullptr;
+  if (count == 0) count = 1;
+  void *q = nullptr;
+  hipError_t e = hipMalloc(&q, sizeof(T) * count);
+  if (e != hipSuccess) return fail(VP_ERR_NOMEM, "hipMalloc failed: " + std::to_string(sizeof(T) * count) + " bytes");
+  s->allocations.push_back(q);
+  *p = (T *)q;
+  return VP_OK;
+}
+
+template <class T>
+vp_status upload(vp_system *s, T **p, const std::vector<T> &h) {
+  vp_status st = dalloc(s, p, h.size());
+  if (st != VP_OK) return st;
+  if (!h.empty()) HIPCHECK(hipMemcpy(*p, h.data(), sizeof(T) * h.size(), hipMemcpyHostToDevice));
+  return VP_OK;
+}
+
+#define TRY(expr)                     \
+  do {                                \
+    vp_status s_ = (expr);            \
+    if (s_ != VP_OK) return s_;       \
+  } while (0)
+
+vp_status validate(const vp_replica_desc &d, int r) {
+  auto bad = [&](const std::string &m) { return fail(VP_ERR_ARG, "replica " + std::to_string(r) + ": " + m); };
+  if (d.n_atoms <= 0 || d.n_atoms > 65536) return bad("n_atoms must be in [1, 65536]");
+  if (d.n_solute < 0 || d.n_solute > d.n_atoms) return bad("n_solute out of range");
+  if (!d.mass || !d.gamma || !d.charge || !d.sigma || !d.epsilon || !d.x0)
+    return bad("NULL per-atom array");
+  for (int a = 0; a < 3; ++a)
+    if (!(d.box[a] > 0)) return bad("box edges must be positive");
+  if (!(d.r_cut > 0)) return bad("r_cut must be positive");
+  for (int a = 0; a < 3; ++a)
+    if (!(d.r_cut < 0.5 * d.box[a])) return bad("r_cut must be below half the box");
+  if (!(d.dt > 0) || !(d.kT > 0)) return bad("dt and kT must be positive");
+  for (int i = 0; i < d.n_atoms; ++i) {
+    if (!(d.mass[i] > 0)) return bad("masses must be positive");
+    if (!(d.gamma[i] >= 0)) return bad("frictions must be non-negative");
+    if (i < d.n_solute && d.bias != VP_BIAS_NONE && !(d.gamma[i] > 0))
+      return bad("solute frictions must be positive (the functional divides by gamma m)");
+    if (!(d.sigma[i] >= 0) || !(d.epsilon[i] >= 0)) return bad("sigma and epsilon must be >= 0");
+  }
+  if (d.n_bonds < 0 || (d.n_bonds > 0 && (!d.bonds || !d.bond_k || !d.bond_r0))) return bad("bond arrays");
+  for (int b = 0; b < d.n_bonds; ++b)
+    for (int k = 0; k < 2; ++k)
+      if (d.bonds[2 * b + k] < 0 || d.bonds[2 * b + k] >= d.n_atoms) return bad("bond index out of range");
+  if (d.n_angles < 0 || (d.n_angles > 0 && (!d.angles || !d.angle_k || !d.angle_theta0)))
+    return bad("angle arrays");
+  for (int b = 0; b < d.n_angles; ++b)
+    for (int k = 0; k < 3; ++k)
+      if (d.angles[3 * b + k] < 0 || d.angles[3 * b + k] >= d.n_atoms) return bad("angle index out of range");
+  if (d.n_excl < 0 || (d.n_excl > 0 && !d.excl)) return bad("exclusion array");
+  for (int b = 0; b < d.n_excl; ++b)
+    for (int k = 0; k < 2; ++k)
+      if (d.excl[2 * b + k] < 0 || d.excl[2 * b + k] >= d.n_atoms) return bad("excluded index out of range");
+  if (d.bias < VP_BIAS_NONE || d.bias > VP_BIAS_RMD_CONTACT) return bad("unknown bias kind");
+  if ((d.bias == VP_BIAS_CONTACT || d.bias == VP_BIAS_RMD_CONTACT)) {
+    if (!d.x_final) return bad("contact-map bias needs x_final");
+    if (d.n_solute > kMaxCvBlocks * kCvBlock) return bad("too many solute atoms for the contact map");
+    if (!(d.contact_r0 > 0) || !(d.contact_rc > d.contact_rs) || d.contact_min_sep < 0)
+      return bad("contact parameters");
+  }
+  if (d.bias == VP_BIAS_CONST && !d.const_force) return bad("constant bias needs const_force");
+  if (d.bias != VP_BIAS_NONE && d.n_solute < 1) return bad("a bias needs at least one solute atom");
+  if (d.bias == VP_BIAS_RG || d.bias == VP_BIAS_CONTACT || d.bias == VP_BIAS_RMD_CONTACT)
+    if (!(d.bias_k >= 0) || !(d.ramp_rate >= 0)) return bad("bias_k and ramp_rate must be >= 0");
+  if (d.bias != VP_BIAS_NONE && d.n_solute > kMaxSoluteLds) return bad("too many solute atoms");
+  return VP_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// native contact map: cmap[i][j] = C~(|xf_j - xf_i|) for |i - j| > min_sep
+// ---------------------------------------------------------------------------
+namespace vp {
+void launch_native_map(const float *xf, int ns, int min_sep, float r0, float rs, float rc,
+                       float *out, hipStream_t st);
+}
+
+static vp_status alloc_work(vp_system *s, Work &W, bool traj) {
+  size_t S = (size_t)s->n_slots, U = (size_t)s->n_users, R = (size_t)s->R;
+  TRY(dalloc(s, &W.xq, S));
+  if (traj) {
+    TRY(dalloc(s, &W.vel, S));
+    TRY(dalloc(s, &W.xref, S));
+  }
+  TRY(dalloc(s, &W.prm, S));
+  TRY(dalloc(s, &W.integ, S));
+  TRY(dalloc(s, &W.orig, S));
+  TRY(dalloc(s, &W.inv, U));
+  TRY(dalloc(s, &W.F, 3 * S));
+  W.fstride = (int64_t)S;
+  TRY(dalloc(s, &W.nbcnt, S));
+  TRY(dalloc(s, &W.nblist, (size_t)s->list_elems));
+  TRY(dalloc(s, &W.cell_start, (size_t)s->n_cells));
+  TRY(dalloc(s, &W.cell_of, S));
+  TRY(dalloc(s, &W.g, (size_t)std::max<int64_t>(1, s->n_solute_total)));
+  TRY(dalloc(s, &W.zpart, R * kMaxCvBlocks));
+  TRY(dalloc(s, &W.gpart, R * kMaxCvBlocks));
+  TRY(dalloc(s, &W.epart, 4 * (size_t)s->n_tiles));
+  TRY(dalloc(s, &W.flags, R));
+  HIPCHECK(hipMemset(W.nbcnt, 0, sizeof(int32_t) * S));
+  HIPCHECK(hipMemset(W.orig, 0xff, sizeof(int32_t) * S));
+  HIPCHECK(hipMemset(W.zpart, 0, sizeof(double) * R * kMaxCvBlocks));
+  HIPCHECK(hipMemset(W.gpart, 0, sizeof(double) * R * kMaxCvBlocks));
+  HIPCHECK(hipMemset(W.epart, 0, sizeof(double) * 4 * (size_t)s->n_tiles));
+  HIPCHECK(hipMemset(W.F, 0, sizeof(long long) * 3 * S));
+  return VP_OK;
+}
+
+static void free_all(vp_system *s) {
+  for (hipEvent_t e : s->ev_before) (void)hipEventDestroy(e);
+  for (hipEvent_t e : s->ev_after) (void)hipEventDestroy(e);
+  s->ev_before.clear();
+  s->ev_after.clear();
+  for (auto &g : s->graphs) {
+    (void)hipGraphExecDestroy(g.exec);
+  }
+  s->graphs.clear();
+  for (void *p : s->allocations) (void)hipFree(p);
+  s->allocations.clear();
+}
+
+static vp_status build(vp_system *s, const vp_replica_desc *reps, int32_t n_reps) {
+  const vp_options &o = s->opt;
+  s->R = n_reps;
+  s->info_h.resize(n_reps);
+  int64_t off = 0, uoff = 0, cell0 = 0, list_off = 0, sol_off = 0;
+  int32_t tile0 = 0;
+  std::vector<int32_t> tile_rep, tile_first;
+  // distinct native maps
+  struct MapKey {
+    const double *xf;
+    int ns, sep;
+    double r0, rs, rc;
+  };
+  std::vector<MapKey> maps;
+  std::vector<int64_t> map_off;
+  int64_t cmap_total = 0;
+  for (int r = 0; r < n_reps; ++r) {
+    const vp_replica_desc &d = reps[r];
+    RepInfo &R = s->info_h[r];
+    std::memset(&R, 0, sizeof(R));
+    R.n = d.n_atoms;
+    R.ns = d.n_solute;
+    R.npad = (d.n_atoms + kTile - 1) / kTile * kTile;
+    R.off = (int32_t)off;
+    R.uoff = (int32_t)uoff;
+    R.tile0 = tile0;
+    R.ntiles = R.npad / kTile;
+    for (int t = 0; t < R.ntiles; ++t) {
+      tile_rep.push_back(r);
+      tile_first.push_back(t * kTile);
+    }
+    R.bias = d.bias;
+    R.min_sep = d.contact_min_sep;
+    const double rl = d.r_cut + o.skin;
+    for (int a = 0; a < 3; ++a) {
+      int nc = (int)std::floor(d.box[a] / (rl * (1.0 + 1e-6)));
+      nc = std::max(1, std::min(nc, 16));
+      R.nc[a] = nc;
+      R.L[a] = (float)d.box[a];
+      R.invL[a] = (float)(1.0 / (double)R.L[a]);
+      R.Ld[a] = d.box[a];
+    }
+    if (!(rl < 0.5 * std::min({d.box[0], d.box[1], d.box[2]})))
+      return fail(VP_ERR_ARG, "replica " + std::to_string(r) + ": r_cut + skin must be below half the box");
+    R.ncell = R.nc[0] * R.nc[1] * R.nc[2];
+    R.cell0 = (int32_t)cell0;
+    const double vol = d.box[0] * d.box[1] * d.box[2];
+    const double expect = 4.0 / 3.0 * M_PI * rl * rl * rl * d.n_atoms / vol;
+    int maxnb = o.max_neighbors > 0 ? o.max_neighbors : (int)std::ceil(1.5 * expect + 64);
+    maxnb = std::min(maxnb, d.n_atoms);
+    maxnb = (maxnb + 15) / 16 * 16;
+    R.maxnb = maxnb;
+    R.list_off = list_off;
+    R.sol_off = (int32_t)sol_off;
+    R.nstlist_max = o.nstlist_max;
+    R.rc2 = (float)(d.r_cut * d.r_cut);
+    R.rl2 = (float)(rl * rl);
+    R.rc = d.r_cut;
+    R.krf = (d.eps_rf - 1.0) / ((2.0 * d.eps_rf + 1.0) * d.r_cut * d.r_cut * d.r_cut);
+    R.krf2 = (float)(2.0 * R.krf);
+    R.crf = (float)(1.0 / d.r_cut + R.krf * d.r_cut * d.r_cut);
+    R.half_skin_margin = (float)(0.5 * o.skin * 0.98);
+    R.cr0 = (float)d.contact_r0;
+    R.crs = (float)d.contact_rs;
+    R.crc = (float)d.contact_rc;
+    R.bias_k = d.bias_k;
+    R.ramp_rate = d.ramp_rate;
+    R.z_target = d.z_target;
+    R.kT = d.kT;
+    R.dt = d.dt;
+    R.reach_tol = d.reach_tol;
+    R.seed = d.seed;
+    const bool contact = d.bias == VP_BIAS_CONTACT || d.bias == VP_BIAS_RMD_CONTACT;
+    R.cv_blocks = contact ? std::max(1, (d.n_solute + kCvBlock - 1) / kCvBlock) : 1;
+    R.cmap_off = 0;
+    if (contact) {
+      int found = -1;
+      for (size_t m = 0; m < maps.size(); ++m) {
+        const MapKey &k = maps[m];
+        if (k.ns == d.n_solute && k.sep == d.contact_min_sep && k.r0 == d.contact_r0 &&
+            k.rs == d.contact_rs && k.rc == d.contact_rc &&
+            std::memcmp(k.xf, d.x_final, sizeof(double) * 3 * d.n_solute) == 0) {
+          found = (int)m;
+          break;
+        }
+      }
+      if (found < 0) {
+        maps.push_back({d.x_final, d.n_solute, d.contact_min_sep, d.contact_r0, d.contact_rs, d.contact_rc});
+        map_off.push_back(cmap_total);
+        cmap_total += (int64_t)d.n_solute * d.n_solute;
+        found = (int)maps.size() - 1;
+      }
+      R.cmap_off = map_off[found];
+    }
+    off += R.npad;
+    uoff += R.n;
+    cell0 += R.ncell + 1;
+    list_off += (int64_t)maxnb * R.npad;
+    sol_off += R.ns;
+    tile0 += R.ntiles;
+  }
+  s->n_slots = off;
+  s->n_users = uoff;
+  s->n_cells = cell0;
+  s->list_elems = list_off;
+  s->n_solute_total = sol_off;
+  s->n_tiles = tile0;
+
+  // ---------------- constant per-atom data (user order)
+  const size_t U = (size_t)s->n_users;
+  std::vector<float4> q0(U), integ0(U);
+  std::vector<float2> prm0(U);
+  std::vector<double> igm0(U), mass0(U);
+  std::vector<float> xh(3 * U), vh(3 * U, 0.0f);
+  std::vector<uint8_t> has_v(n_reps, 0);
+  std::vector<std::vector<BTerm>> terms(U);
+  std::vector<std::vector<int32_t>> excl(U);
+  std::vector<float4> cforce(std::max<int64_t>(1, s->n_solute_total), make_float4(0, 0, 0, 0));
+  for (int r = 0; r < n_reps; ++r) {
+    const vp_replica_desc &d = reps[r];
+    const RepInfo &R = s->info_h[r];
+    for (int i = 0; i < d.n_atoms; ++i) {
+      size_t u = (size_t)R.uoff + i;
+      q0[u] = make_float4(0, 0, 0, (float)d.charge[i]);
+      prm0[u] = make_float2((float)(0.5 * d.sigma[i]), (float)std::sqrt(d.epsilon[i]));
+      double c1 = std::exp(-d.gamma[i] * d.dt);
+      double sv = std::sqrt((1.0 - c1 * c1) * d.kT / d.mass[i]);
+      integ0[u] = make_float4((float)(1.0 / d.mass[i]), (float)c1, (float)sv, 0.0f);
+      igm0[u] = d.gamma[i] > 0 ? 1.0 / (d.gamma[i] * d.mass[i]) : 0.0;
+      mass0[u] = d.mass[i];
+      for (int a = 0; a < 3; ++a) {
+        xh[3 * u + a] = (float)d.x0[3 * i + a];
+        if (d.v0) vh[3 * u + a] = (float)d.v0[3 * i + a];
+      }
+    }
+    has_v[r] = d.v0 ? 1 : 0;
+    for (int b = 0; b < d.n_bonds; ++b) {
+      int i = d.bonds[2 * b], j = d.bonds[2 * b + 1];
+      terms[R.uoff + i].push_back({0, j, 0, 0, d.bond_k[b], d.bond_r0[b]});
+      terms[R.uoff + j].push_back({0, i, 0, 0, d.bond_k[b], d.bond_r0[b]});
+    }
+    for (int b = 0; b < d.n_angles; ++b) {
+      int i = d.angles[3 * b], c = d.angles[3 * b + 1], j = d.angles[3 * b + 2];
+      terms[R.uoff + i].push_back({1, c, j, 0, d.angle_k[b], d.angle_theta0[b]});
+      terms[R.uoff + j].push_back({1, c, i, 0, d.angle_k[b], d.angle_theta0[b]});
+      terms[R.uoff + c].push_back({2, i, j, 0, d.angle_k[b], d.angle_theta0[b]});
+    }
+    for (int e = 0; e < d.n_excl; ++e) {
+      int i = d.excl[2 * e], j = d.excl[2 * e + 1];
+      if (i == j) continue;
+      excl[R.uoff + i].push_back(j);
+      excl[R.uoff + j].push_back(i);
+    }
+    if (d.bias == VP_BIAS_CONST)
+      for (int i = 0; i < d.n_solute; ++i)
+        cforce[R.sol_off + i] = make_float4((float)d.const_force[3 * i], (float)d.const_force[3 * i + 1],
+                                            (float)d.const_force[3 * i + 2], 0.0f);
+  }
+  std::vector<int32_t> bt_start(U + 1, 0), ex_start(U + 1, 0), ex_list;
+  std::vector<BTerm> bterms;
+  for (size_t u = 0; u < U; ++u) {
+    bt_start[u] = (int32_t)bterms.size();
+    bterms.insert(bterms.end(), terms[u].begin(), terms[u].end());
+    std::sort(excl[u].begin(), excl[u].end());
+    excl[u].erase(std::unique(excl[u].begin(), excl[u].end()), excl[u].end());
+    ex_start[u] = (int32_t)ex_list.size();
+    ex_list.insert(ex_list.end(), excl[u].begin(), excl[u].end());
+  }
+  bt_start[U] = (int32_t)bterms.size();
+  ex_start[U] = (int32_t)ex_list.size();
+
+  // ---------------- device allocations and uploads
+  TRY(upload(s, &s->info, s->info_h));
+  std::vector<RepState> st(n_reps);
+  for (auto &x : st) {
+    std::memset(&x, 0, sizeof(x));
+    x.force_rebuild = 1;
+  }
+  TRY(upload(s, &s->state, st));
+  TRY(upload(s, &s->tile_rep, tile_rep));
+  TRY(upload(s, &s->tile_first, tile_first));
+  TRY(upload(s, &s->q0, q0));
+  TRY(upload(s, &s->prm0, prm0));
+  TRY(upload(s, &s->integ0, integ0));
+  TRY(upload(s, &s->igm0, igm0));
+  TRY(upload(s, &s->mass0, mass0));
+  TRY(upload(s, &s->bt_start, bt_start));
+  TRY(upload(s, &s->bterms, bterms));
+  TRY(upload(s, &s->ex_start, ex_start));
+  TRY(upload(s, &s->ex_list, ex_list));
+  TRY(upload(s, &s->cforce, cforce));
+  TRY(dalloc(s, &s->cmap, (size_t)std::max<int64_t>(1, cmap_total)));
+  for (size_t m = 0; m < maps.size(); ++m) {
+    const MapKey &k = maps[m];
+    std::vector<float> xf(3 * (size_t)k.ns);
+    for (int i = 0; i < 3 * k.ns; ++i) xf[i] = (float)k.xf[i];
+    float *dxf = nullptr;
+    TRY(dalloc(s, &dxf, xf.size()));
+    HIPCHECK(hipMemcpy(dxf, xf.data(), sizeof(float) * xf.size(), hipMemcpyHostToDevice));
+    launch_native_map(dxf, k.ns, k.sep, (float)k.r0, (float)k.rs, (float)k.rc, s->cmap + map_off[m], 0);
+  }
+  const size_t S = (size_t)s->n_slots;
+  TRY(dalloc(s, &s->xq_t, S));
+  TRY(dalloc(s, &s->vel_t, S));
+  TRY(dalloc(s, &s->orig_t, S));
+  TRY(dalloc(s, &s->src_t, S));
+  TRY(dalloc(s, &s->cellid_t, S));
+  TRY(dalloc(s, &s->bucket_t, S));
+  TRY(dalloc(s, &s->borig_t, S));
+  TRY(dalloc(s, &s->step, 1));
+  HIPCHECK(hipMemset(s->step, 0, sizeof(long long)));
+  TRY(alloc_work(s, s->traj, true));
+
+  // ---------------- initial state, list, forces, S_0
+  float *dx = nullptr, *dv = nullptr;
+  uint8_t *dhv = nullptr;
+  TRY(dalloc(s, &dx, xh.size()));
+  TRY(dalloc(s, &dv, vh.size()));
+  TRY(dalloc(s, &dhv, has_v.size()));
+  HIPCHECK(hipMemcpy(dx, xh.data(), sizeof(float) * xh.size(), hipMemcpyHostToDevice));
+  HIPCHECK(hipMemcpy(dv, vh.data(), sizeof(float) * vh.size(), hipMemcpyHostToDevice));
+  HIPCHECK(hipMemcpy(dhv, has_v.data(), has_v.size(), hipMemcpyHostToDevice));
+  launch_init_state(s, dx, dv, dhv, 0);
+  launch_rebuild(s, s->traj, 0, nullptr, 0);
+  launch_forces(s, s->traj, false, 0);
+  launch_cv(s, s->traj, 0, 0);
+  launch_integrate(s, INT_INIT, 0);
+  HIPCHECK(hipGetLastError());
+  HIPCHECK(hipDeviceSynchronize());
+  return VP_OK;
+}
+
+extern "C" vp_status vp_system_create(const vp_replica_desc *reps, int32_t n_reps,
+                                      const vp_options *opt, vp_system **out) {
+  if (!out) return fail(VP_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  if (!reps) return fail(VP_ERR_ARG, "reps is NULL");
+  if (n_reps <= 0) return fail(VP_ERR_ARG, "n_reps must be positive");
+  int64_t total = 0;
+  for (int r = 0; r < n_reps; ++r) {
+    vp_status st = validate(reps[r], r);
+    if (st != VP_OK) return st;
+    total += reps[r].n_atoms;
+  }
+  if (total > ((int64_t)1 << 31) - (int64_t)kTile * n_reps) return fail(VP_ERR_ARG, "batch too large");
+  vp_system *s = new (std::nothrow) vp_system();
+  if (!s) return fail(VP_ERR_NOMEM, "host allocation failed");
+  vp_options o{};
+  if (opt) o = *opt;
+  if (o.nstlist_max <= 0) o.nstlist_max = 100;
+  if (!(o.skin > 0)) o.skin = 0.1;
+  if (o.steps_per_graph <= 0) o.steps_per_graph = 20;
+  if (!opt) o.use_graph = 1;
+  s->opt = o;
+  vp_status st = VP_OK;
+  if (o.timing) {
+    for (int k = 0; k < o.steps_per_graph && st == VP_OK; ++k) {
+      hipEvent_t a, b;
+      if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess)
+        st = fail(VP_ERR_HIP, "hipEventCreate failed");
+      else {
+        s->ev_before.push_back(a);
+        s->ev_after.push_back(b);
+      }
+    }
+  }
+  if (st == VP_OK) st = build(s, reps, n_reps);
+  if (st != VP_OK) {
+    std::string msg = g_err;
+    free_all(s);
+    delete s;
+    g_err = msg;
+    return st;
+  }
+  *out = s;
+  return VP_OK;
+}
+
+extern "C" vp_status vp_system_destroy(vp_system *s) {
+  if (!s) return VP_OK;
+  (void)hipDeviceSynchronize();
+  free_all(s);
+  delete s;
+  return VP_OK;
+}
+
+// one block of steps: START ... FINISH, with FINISH|START fused inside
+static void enqueue_block(vp_system *s, int steps, hipStream_t st) {
+  const bool timing = s->opt.timing != 0;
+  for (int k = 0; k < steps; ++k) {
+    launch_integrate(s, k == 0 ? INT_START : (INT_FINISH | INT_START), st);
+    launch_rebuild(s, s->traj, 0, nullptr, st);
+    if (timing) (void)hipEventRecordWithFlags(s->ev_before[k], st, hipEventRecordExternal);
+    launch_forces(s, s->traj, false, st);
+    if (timing) (void)hipEventRecordWithFlags(s->ev_after[k], st, hipEventRecordExternal);
+    launch_cv(s, s->traj, 1, st);
+  }
+  launch_integrate(s, INT_FINISH, st);
+}
+
+static vp_status collect_timing(vp_system *s, int steps) {
+  HIPCHECK(hipEventSynchronize(s->ev_after[steps - 1]));
+  for (int k = 0; k < steps; ++k) {
+    float ms = 0.0f;
+    HIPCHECK(hipEventElapsedTime(&ms, s->ev_before[k], s->ev_after[k]));
+    s->timing_ms += ms;
+    s->timing_count += 1;
+  }
+  return VP_OK;
+}
+
+static vp_status graph_for(vp_system *s, int steps, hipGraphExec_t *exec) {
+  for (auto &g : s->graphs)
+    if (g.steps == steps) {
+      *exec = g.exec;
+      return VP_OK;
+    }
+  hipStream_t cs;
+  HIPCHECK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  hipGraph_t graph;
+  HIPCHECK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+  enqueue_block(s, steps, cs);
+  hipError_t e = hipStreamEndCapture(cs, &graph);
+  if (e != hipSuccess) {
+    (void)hipStreamDestroy(cs);
+    return fail(VP_ERR_HIP, std::string("graph capture: ") + hipGetErrorString(e));
+  }
+  hipGraphExec_t ex;
+  e = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  (void)hipStreamDestroy(cs);
+  if (e != hipSuccess) return fail(VP_ERR_HIP, std::string("graph instantiate: ") + hipGetErrorString(e));
+  s->graphs.push_back({steps, nullptr, ex});
+  *exec = ex;
+  return VP_OK;
+}
+
+extern "C" vp_status vp_step_batch(vp_system *s, int32_t n_steps, void *hip_stream) {
+  if (!s) return fail(VP_ERR_ARG, "system is NULL");
+  if (n_steps < 0) return fail(VP_ERR_ARG, "n_steps must be >= 0");
+  hipStream_t st = (hipStream_t)hip_stream;
+  s->last_stream = st;
+  if (n_steps == 0) return VP_OK;
+  const int B = s->opt.steps_per_graph;
+  int left = n_steps;
+  while (left > 0) {
+    int k = std::min(left, B);
+    if (s->opt.use_graph) {
+      hipGraphExec_t ex;
+      TRY(graph_for(s, k, &ex));
+      HIPCHECK(hipGraphLaunch(ex, st));
+    } else {
+      enqueue_block(s, k, st);
+      HIPCHECK(hipGetLastError());
+    }
+    if (s->opt.timing) TRY(collect_timing(s, k));
+    left -= k;
+  }
+  s->host_step += n_steps;
+  return VP_OK;
+}
+
+static vp_status fetch_state(vp_system *s, std::vector<RepState> &st) {
+  HIPCHECK(hipStreamSynchronize(s->last_stream));
+  HIPCHECK(hipGetLastError());
+  st.resize(s->R);
+  HIPCHECK(hipMemcpy(st.data(), s->state, sizeof(RepState) * s->R, hipMemcpyDeviceToHost));
+  return VP_OK;
+}
+
+static double phi_of(const RepInfo &R, const RepState &S) {
+  if (S.status & VP_REPLICA_UNSTABLE) return INFINITY;
+  return (S.phi_acc - 0.5 * S.s_last) * R.dt / (4.0 * R.kT);
+}
+
+extern "C" vp_status vp_functional(vp_system *s, double *phi_host, double *dphi_dtheta_host) {
+  if (!s || !phi_host) return fail(VP_ERR_ARG, "NULL argument");
+  if (dphi_dtheta_host) return fail(VP_ERR_ARG, "functional gradient is not available in this build");
+  std::vector<RepState> st;
+  TRY(fetch_state(s, st));
+  for (int r = 0; r < s->R; ++r) phi_host[r] = phi_of(s->info_h[r], st[r]);
+  return VP_OK;
+}
+
+extern "C" vp_status vp_select_path(vp_system *s, const uint8_t *eligible, int32_t *best,
+                                    double *best_phi) {
+  if (!s || !best || !best_phi) return fail(VP_ERR_ARG, "NULL argument");
+  *best = -1;
+  *best_phi = INFINITY;
+  std::vector<RepState> st;
+  TRY(fetch_state(s, st));
+  for (int r = 0; r < s->R; ++r) {
+    const RepInfo &R = s->info_h[r];
+    double phi = phi_of(R, st[r]);
+    bool reached = std::fabs(st[r].z_last - R.z_target) <= R.reach_tol;
+    if (!reached || (eligible && !eligible[r]) || !std::isfinite(phi)) continue;
+    if (*best < 0 || phi < *best_phi) {
+      *best = r;
+      *best_phi = phi;
+    }
+  }
+  if (*best < 0) return fail(VP_ERR_NOPATH, "no replica reached the product with a finite functional");
+  return VP_OK;
+}
+
+extern "C" vp_status vp_forces(vp_system *s, const float *x_dev, float *f_dev, double *energy_dev,
+                               double t, void *hip_stream) {
+  if (!s || !x_dev || !f_dev) return fail(VP_ERR_ARG, "NULL argument");
+  hipStream_t st = (hipStream_t)hip_stream;
+  if (!s->eval_ready) {
+    HIPCHECK(hipDeviceSynchronize());
+    TRY(alloc_work(s, s->eval, false));
+    s->eval_ready = true;
+  }
+  s->last_stream = st;
+  launch_rebuild(s, s->eval, 1, x_dev, st);
+  launch_forces(s, s->eval, energy_dev != nullptr, st);
+  launch_cv(s, s->eval, 0, st);
+  launch_force_out(s, s->eval, t, f_dev, energy_dev, st);
+  HIPCHECK(hipGetLastError());
+  return VP_OK;
+}
+
+extern "C" vp_status vp_get_state(vp_system *s, float *x_dev, float *v_dev, void *hip_stream) {
+  if (!s) return fail(VP_ERR_ARG, "NULL system");
+  hipStream_t st = (hipStream_t)hip_stream;
+  s->last_stream = st;
+  launch_gather_state(s, x_dev, v_dev, st);
+  HIPCHECK(hipGetLastError());
+  return VP_OK;
+}
+
+extern "C" vp_status vp_observables(vp_system *s, double *obs) {
+  if (!s || !obs) return fail(VP_ERR_ARG, "NULL argument");
+  std::vector<RepState> st;
+  TRY(fetch_state(s, st));
+  long long step = 0;
+  HIPCHECK(hipMemcpy(&step, s->step, sizeof(step), hipMemcpyDeviceToHost));
+  double *ke = nullptr;
+  HIPCHECK(hipMalloc(&ke, sizeof(double) * (size_t)s->n_tiles));
+  launch_kinetic(s, ke, 0);
+  std::vector<double> keh(s->n_tiles);
+  hipError_t e = hipMemcpy(keh.data(), ke, sizeof(double) * keh.size(), hipMemcpyDeviceToHost);
+  (void)hipFree(ke);
+  if (e != hipSuccess) return fail(VP_ERR_HIP, hipGetErrorString(e));
+  for (int r = 0; r < s->R; ++r) {
+    const RepInfo &R = s->info_h[r];
+    double k = 0.0;
+    for (int t = R.tile0; t < R.tile0 + R.ntiles; ++t) k += keh[t];
+    double *o = obs + (size_t)r * VP_OBS_COUNT;
+    o[VP_OBS_STEP] = (double)step;
+    o[VP_OBS_Z] = st[r].z_last;
+    o[VP_OBS_ZREF] = st[r].zref_last;
+    o[VP_OBS_ZMIN] = st[r].z_m;
+    o[VP_OBS_PHI] = phi_of(R, st[r]);
+    o[VP_OBS_STATUS] = st[r].status;
+    o[VP_OBS_REBUILDS] = st[r].rebuilds;
+    o[VP_OBS_KE] = k;
+  }
+  return VP_OK;
+}
+
+extern "C" vp_status vp_kernel_timing(vp_system *s, double *avg_ms, int64_t *count, int32_t reset) {
+  if (!s) return fail(VP_ERR_ARG, "NULL system");
+  if (avg_ms) *avg_ms = s->timing_count ? s->timing_ms / (double)s->timing_count : 0.0;
+  if (count) *count = s->timing_count;
+  if (reset) {
+    s->timing_ms = 0.0;
+    s->timing_count = 0;
+  }
+  return VP_OK;
+}
+
+extern "C" vp_status vp_pair_count(vp_system *s, int32_t rep, int64_t *count) {
+  return vp_debug_pairs(s, rep, nullptr, 0, count);
+}
+
+extern "C" vp_status vp_sizes(const vp_system *s, int64_t *n_atoms_total, int32_t *n_reps) {
+  if (!s) return fail(VP_ERR_ARG, "NULL system");
+  if (n_atoms_total) *n_atoms_total = s->n_users;
+  if (n_reps) *n_reps = s->R;
+  return VP_OK;
+}
+
+extern "C" vp_status vp_debug_pairs(vp_system *s, int32_t rep, int32_t *pairs_host, int64_t cap,
+                                    int64_t *count) {
+  if (!s || !count || (cap > 0 && !pairs_host)) return fail(VP_ERR_ARG, "NULL argument");
+  if (rep < 0 || rep >= s->R) return fail(VP_ERR_ARG, "replica index out of range");
+  HIPCHECK(hipStreamSynchronize(s->last_stream));
+  int2 *d = nullptr;
+  unsigned long long *cnt = nullptr;
+  HIPCHECK(hipMalloc(&d, sizeof(int2) * (size_t)std::max<int64_t>(1, cap)));
+  HIPCHECK(hipMalloc(&cnt, sizeof(unsigned long long)));
+  HIPCHECK(hipMemset(cnt, 0, sizeof(unsigned long long)));
+  launch_debug_pairs(s, s->traj, rep, d, (unsigned long long)cap, cnt, 0);
+  unsigned long long c = 0;
+  hipError_t e = hipMemcpy(&c, cnt, sizeof(c), hipMemcpyDeviceToHost);
+  if (e == hipSuccess && cap > 0)
+    e = hipMemcpy(pairs_host, d, sizeof(int2) * (size_t)std::min<int64_t>(cap, (int64_t)c),
+                  hipMemcpyDeviceToHost);
+  (void)hipFree(d);
+  (void)hipFree(cnt);
+  if (e != hipSuccess) return fail(VP_ERR_HIP, hipGetErrorString(e));
+  *count = (int64_t)c;
+  return VP_OK;
+}
+
+extern "C" vp_status vp_debug_noise(uint64_t seed, uint32_t atom0, uint32_t step, uint32_t tag,
+                                    int32_t n, float *out_dev, void *hip_stream) {
+  if (!out_dev || n < 0) return fail(VP_ERR_ARG, "bad argument");
+  if (n == 0) return VP_OK;
+  launch_debug_noise(seed, atom0, step, tag, n, out_dev, (hipStream_t)hip_stream);
+  HIPCHECK(hipGetLastError());
+  return VP_OK;
+}
+
+extern "C" const char *vp_last_error(void) { return g_err.c_str(); }

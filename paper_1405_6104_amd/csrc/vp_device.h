@@ -1,0 +1,179 @@
+// Device helpers shared by the vp kernels (gfx950, wave64).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "vp_internal.h"
+
+namespace vp {
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): counter = (atom, step,
+// tag, 0), key = 64-bit trajectory seed.  Ten rounds; the key advances by the
+// two Weyl constants after every round.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint32_t m0 = 0xD2511F53u, m1 = 0xCD9E8D57u;
+    uint32_t lo0 = m0 * c.x, hi0 = __umulhi(m0, c.x);
+    uint32_t lo1 = m1 * c.z, hi1 = __umulhi(m1, c.z);
+    c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return c;
+}
+
+// Uniform in (0,1) from a 32-bit word: ((w >> 9) + 1/2) 2^-23, exact in FP32.
+__device__ __forceinline__ float word_to_uniform(uint32_t w) {
+  return ((float)(w >> 9) + 0.5f) * 1.1920928955078125e-7f;
+}
+
+// Three standard normals by Box-Muller: (g0, g1) from (u0, u1), g2 from (u2, u3).
+__device__ __forceinline__ float3 noise3(uint64_t seed, uint32_t atom, uint32_t step, uint32_t tag,
+                                         float *u0_out = nullptr) {
+  uint4 w = philox4x32_10(make_uint4(atom, step, tag, 0u), (uint32_t)seed, (uint32_t)(seed >> 32));
+  float u0 = word_to_uniform(w.x), u1 = word_to_uniform(w.y);
+  float u2 = word_to_uniform(w.z), u3 = word_to_uniform(w.w);
+  float rho = sqrtf(-2.0f * logf(u0));
+  float s1, c1, s3, c3;
+  sincospif(2.0f * u1, &s1, &c1);
+  sincospif(2.0f * u3, &s3, &c3);
+  if (u0_out) *u0_out = u0;
+  return make_float3(rho * c1, rho * s1, sqrtf(-2.0f * logf(u2)) * c3);
+}
+
+// ---------------------------------------------------------------------------
+// Pair membership on FP32 coordinates with an exactly specified order of
+// operations (the CPU test oracle evaluates the same expression):
+//   d = fl(xj - xi); n = rint(fl(d * invL)); d' = fma(-n, L, d);
+//   r2 = fma(dz', dz', fma(dy', dy', fl(dx' * dx'))).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float min_image(float xi, float xj, float L, float invL) {
+  float t = xj - xi;
+  float n = __builtin_rintf(t * invL);
+  return __builtin_fmaf(-n, L, t);
+}
+
+__device__ __forceinline__ float pair_r2(const float4 &xi, const float4 &xj, const RepInfo &R,
+                                         float &dx, float &dy, float &dz) {
+  dx = min_image(xi.x, xj.x, R.L[0], R.invL[0]);
+  dy = min_image(xi.y, xj.y, R.L[1], R.invL[1]);
+  dz = min_image(xi.z, xj.z, R.L[2], R.invL[2]);
+  float sq = dx * dx;
+  return __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, sq));
+}
+
+// ---------------------------------------------------------------------------
+// Contact value of the collective variable: C = (1+u+u^2)/(1+u+u^2+u^3+u^4),
+// u = (r/r0)^2 (the smooth form of (1-(r/r0)^6)/(1-(r/r0)^10)), times a
+// quintic switch from 1 at rs to 0 at rc.  Returns C*S and d(C*S)/dr.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float contact_value(float r, float r0, float rs, float rc, float &dcdr) {
+  float ir0 = 1.0f / r0;
+  float u = (r * ir0) * (r * ir0);
+  float u2 = u * u;
+  float num = 1.0f + u + u2;
+  float den = num + u2 * u + u2 * u2;
+  float iden = 1.0f / den;
+  float c = num * iden;
+  float dnum = 1.0f + 2.0f * u;
+  float dden = dnum + 3.0f * u2 + 4.0f * u2 * u;
+  float dc = (dnum - c * dden) * iden * (2.0f * r * ir0 * ir0);
+  float sw = 1.0f, dsw = 0.0f;
+  if (r >= rc) {
+    sw = 0.0f;
+  } else if (r > rs) {
+    float w = 1.0f / (rc - rs);
+    float t = (r - rs) * w;
+    sw = 1.0f - t * t * t * (10.0f - 15.0f * t + 6.0f * t * t);
+    dsw = -30.0f * t * t * (1.0f - t) * (1.0f - t) * w;
+  }
+  dcdr = dc * sw + c * dsw;
+  return c * sw;
+}
+
+// ---------------------------------------------------------------------------
+// Fixed-point forces: round(F * 2^32) in int64, clamped to +-2^62.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ long long to_fix(double f) {
+  double s = f * kFixScale;
+  if (!(s > -4.6e18)) s = (s != s) ? 4.6e18 : -4.6e18;  // NaN marks as huge
+  if (s > 4.6e18) s = 4.6e18;
+  return __double2ll_rn(s);
+}
+__device__ __forceinline__ double from_fix(long long v) { return (double)v * (1.0 / kFixScale); }
+
+// ---------------------------------------------------------------------------
+// wave64 reductions
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// Block-wide FP64 sum in a fixed order (wave sums, then waves in order).
+template <int NT>
+__device__ __forceinline__ double block_sum(double v, double *lds) {
+  v = wave_sum(v);
+  int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) lds[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0) {
+    for (int k = 0; k < NT / 64; ++k) s += lds[k];
+  }
+  __syncthreads();
+  return s;  // valid in thread 0
+}
+
+// ---------------------------------------------------------------------------
+// Bias of one replica at time t, given z and its gradient direction: returns
+// the coefficient c with F_i^bias = c * dz/dx_i, the reference (or ratchet
+// minimum) zr and the bias energy.  INIT evaluates at t = 0 with z(X_0) = z.
+//   harmonic: c = -k (z - zr),  zr = z_t + (z_0 - z_t) max(0, 1 - rho t);
+//   ratchet (Eq. VR): zm = min(z_m, z), c = -(k/2)(z - zm) if z > zm else 0.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double bias_coef(const RepInfo &R, double z, double z0, double zm_prev,
+                                            double t, bool init, double &zr, double &ub) {
+  ub = 0.0;
+  zr = 0.0;
+  if (R.bias == VP_BIAS_CONST) return 1.0;
+  if (R.bias == VP_BIAS_RG || R.bias == VP_BIAS_CONTACT) {
+    double zz0 = init ? z : z0;
+    double w = 1.0 - R.ramp_rate * t;
+    w = w < 0.0 ? 0.0 : w;
+    zr = R.z_target + (zz0 - R.z_target) * w;
+    ub = 0.5 * R.bias_k * (z - zr) * (z - zr);
+    return -R.bias_k * (z - zr);
+  }
+  if (R.bias == VP_BIAS_RMD_CONTACT) {
+    double zm = init ? z : (zm_prev < z ? zm_prev : z);
+    zr = zm;
+    if (z > zm) {
+      ub = 0.25 * R.bias_k * (z - zm) * (z - zm);
+      return -0.5 * R.bias_k * (z - zm);
+    }
+    return 0.0;
+  }
+  return 0.0;
+}
+
+// Map a launch-order block index to a tile so that consecutive tiles of one
+// replica run on the same XCD (blocks are dealt round-robin over 8 XCDs).
+__device__ __forceinline__ int xcd_tile(int b, int nb) {
+  const int nx = 8;
+  int per = (nb + nx - 1) / nx;
+  int x = b % nx, k = b / nx;
+  int t = x * per + k;
+  return t < nb ? t : -1;
+}
+
+}  // namespace vp

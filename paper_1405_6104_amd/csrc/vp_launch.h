@@ -1,0 +1,25 @@
+// Host-side launchers of the vp kernels (one translation unit per kernel group).
+#pragma once
+#include "vp_internal.h"
+
+namespace vp {
+
+enum { INT_FINISH = 1, INT_START = 2, INT_INIT = 4 };
+
+// binning + permutation + lists; mode 0: trajectory (device decides), 1: from x_user
+void launch_rebuild(vp_system *s, Work &W, int mode, const float *x_user, hipStream_t st);
+void launch_debug_pairs(vp_system *s, Work &W, int rep, int2 *out, unsigned long long cap,
+                        unsigned long long *counter, hipStream_t st);
+void launch_forces(vp_system *s, Work &W, bool energy, hipStream_t st);
+void launch_cv(vp_system *s, Work &W, int inc_step, hipStream_t st);
+void launch_force_out(vp_system *s, Work &W, double t, float *f_user, double *e_out,
+                      hipStream_t st);
+void launch_integrate(vp_system *s, int mode, hipStream_t st);
+void launch_init_state(vp_system *s, const float *x_user, const float *v_user,
+                       const uint8_t *has_v, hipStream_t st);
+void launch_gather_state(vp_system *s, float *x_out, float *v_out, hipStream_t st);
+void launch_kinetic(vp_system *s, double *out, hipStream_t st);
+void launch_debug_noise(uint64_t seed, uint32_t atom0, uint32_t step, uint32_t tag, int n,
+                        float *out, hipStream_t st);
+
+}  // namespace vp

@@ -1,0 +1,287 @@
+"""Python binding of the vp C ABI (include/vp.h): argument marshalling only.
+
+Every computation runs in the HIP kernels of libvp.so; this module converts
+replica descriptions (dicts of numpy arrays, see ``synth``) into the C
+structures, hands device pointers of torch tensors and the current HIP stream
+to the library, and raises ``VpError`` on any non-zero status.  Importing it
+fails loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libvp.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"libvp.so is missing at {LIB_PATH}: build it with __graft_entry__.build()")
+
+_lib = C.CDLL(LIB_PATH)
+
+_dp = C.POINTER(C.c_double)
+_ip = C.POINTER(C.c_int32)
+
+BIAS_NONE, BIAS_CONST, BIAS_RG, BIAS_CONTACT, BIAS_RMD_CONTACT = 0, 1, 2, 3, 4
+OBS = ("step", "z", "z_ref", "z_min", "phi", "status", "rebuilds", "ke")
+ENERGY_COLUMNS = ("lj", "rf", "bond", "angle", "bias", "z", "z_ref", "S")
+REPLICA_UNSTABLE, REPLICA_LIST_OVERFLOW = 1, 2
+
+STATUS = {0: "VP_OK", -1: "VP_ERR_ARG", -2: "VP_ERR_HIP", -3: "VP_ERR_NOMEM", -4: "VP_ERR_STATE",
+          -5: "VP_ERR_NOPATH"}
+
+
+class VpError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class ReplicaDesc(C.Structure):
+    _fields_ = [
+        ("n_atoms", C.c_int32), ("n_solute", C.c_int32),
+        ("mass", _dp), ("gamma", _dp), ("charge", _dp), ("sigma", _dp), ("epsilon", _dp),
+        ("n_bonds", C.c_int32), ("bonds", _ip), ("bond_k", _dp), ("bond_r0", _dp),
+        ("n_angles", C.c_int32), ("angles", _ip), ("angle_k", _dp), ("angle_theta0", _dp),
+        ("n_excl", C.c_int32), ("excl", _ip),
+        ("box", C.c_double * 3), ("r_cut", C.c_double), ("eps_rf", C.c_double),
+        ("kT", C.c_double), ("dt", C.c_double),
+        ("x0", _dp), ("v0", _dp), ("x_final", _dp),
+        ("bias", C.c_int32), ("bias_k", C.c_double), ("ramp_rate", C.c_double),
+        ("z_target", C.c_double),
+        ("contact_r0", C.c_double), ("contact_rs", C.c_double), ("contact_rc", C.c_double),
+        ("contact_min_sep", C.c_int32), ("reach_tol", C.c_double), ("seed", C.c_uint64),
+        ("const_force", _dp),
+    ]
+
+
+class Options(C.Structure):
+    _fields_ = [("nstlist_max", C.c_int32), ("skin", C.c_double), ("steps_per_graph", C.c_int32),
+                ("use_graph", C.c_int32), ("max_neighbors", C.c_int32), ("timing", C.c_int32),
+                ("reserved", C.c_int32 * 6)]
+
+
+_vp = C.c_void_p
+_lib.vp_system_create.restype = C.c_int
+_lib.vp_system_create.argtypes = [C.POINTER(ReplicaDesc), C.c_int32, C.POINTER(Options), C.POINTER(_vp)]
+_lib.vp_system_destroy.restype = C.c_int
+_lib.vp_system_destroy.argtypes = [_vp]
+_lib.vp_forces.restype = C.c_int
+_lib.vp_forces.argtypes = [_vp, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_void_p]
+_lib.vp_step_batch.restype = C.c_int
+_lib.vp_step_batch.argtypes = [_vp, C.c_int32, C.c_void_p]
+_lib.vp_functional.restype = C.c_int
+_lib.vp_functional.argtypes = [_vp, _dp, _dp]
+_lib.vp_select_path.restype = C.c_int
+_lib.vp_select_path.argtypes = [_vp, C.POINTER(C.c_uint8), _ip, _dp]
+_lib.vp_get_state.restype = C.c_int
+_lib.vp_get_state.argtypes = [_vp, C.c_void_p, C.c_void_p, C.c_void_p]
+_lib.vp_observables.restype = C.c_int
+_lib.vp_observables.argtypes = [_vp, _dp]
+_lib.vp_sizes.restype = C.c_int
+_lib.vp_sizes.argtypes = [_vp, C.POINTER(C.c_int64), _ip]
+_lib.vp_debug_pairs.restype = C.c_int
+_lib.vp_debug_pairs.argtypes = [_vp, C.c_int32, _ip, C.c_int64, C.POINTER(C.c_int64)]
+_lib.vp_debug_noise.restype = C.c_int
+_lib.vp_debug_noise.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_int32,
+                                C.c_void_p, C.c_void_p]
+_lib.vp_kernel_timing.restype = C.c_int
+_lib.vp_kernel_timing.argtypes = [_vp, _dp, C.POINTER(C.c_int64), C.c_int32]
+_lib.vp_pair_count.restype = C.c_int
+_lib.vp_pair_count.argtypes = [_vp, C.c_int32, C.POINTER(C.c_int64)]
+_lib.vp_last_error.restype = C.c_char_p
+_lib.vp_last_error.argtypes = []
+
+EXPORTED = ("vp_system_create", "vp_system_destroy", "vp_forces", "vp_step_batch",
+            "vp_functional", "vp_select_path", "vp_get_state", "vp_observables", "vp_sizes",
+            "vp_debug_pairs", "vp_debug_noise", "vp_kernel_timing", "vp_pair_count",
+            "vp_last_error")
+
+
+def _check(st):
+    if st != 0:
+        raise VpError(st, (_lib.vp_last_error() or b"").decode(errors="replace"))
+
+
+def _stream():
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr())
+
+
+def _f64(a, shape=None):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a if shape is None else a.reshape(shape)
+
+
+def _desc(d, keep):
+    n, ns = int(d["n_atoms"]), int(d["n_solute"])
+    arrs = {}
+    for k in ("mass", "gamma", "charge", "sigma", "epsilon", "bond_k", "bond_r0", "angle_k",
+              "angle_theta0"):
+        arrs[k] = _f64(d[k])
+    for k in ("bonds", "angles", "excl"):
+        arrs[k] = np.ascontiguousarray(d[k], dtype=np.int32)
+    arrs["x0"] = _f64(d["x0"], (n, 3))
+    for k, shape in (("v0", (n, 3)), ("x_final", (ns, 3)), ("const_force", (ns, 3))):
+        v = d.get(k)
+        arrs[k] = None if v is None else _f64(v, shape)
+    keep.append(arrs)
+    s = ReplicaDesc()
+    s.n_atoms, s.n_solute = n, ns
+    for k in ("mass", "gamma", "charge", "sigma", "epsilon", "bond_k", "bond_r0", "angle_k",
+              "angle_theta0", "x0"):
+        setattr(s, k, arrs[k].ctypes.data_as(_dp))
+    for k in ("v0", "x_final", "const_force"):
+        setattr(s, k, arrs[k].ctypes.data_as(_dp) if arrs[k] is not None else _dp())
+    s.n_bonds, s.bonds = len(arrs["bonds"]), arrs["bonds"].ctypes.data_as(_ip)
+    s.n_angles, s.angles = len(arrs["angles"]), arrs["angles"].ctypes.data_as(_ip)
+    s.n_excl, s.excl = len(arrs["excl"]), arrs["excl"].ctypes.data_as(_ip)
+    for a in range(3):
+        s.box[a] = float(d["box"][a])
+    s.r_cut, s.eps_rf, s.kT, s.dt = (float(d[k]) for k in ("r_cut", "eps_rf", "kT", "dt"))
+    s.bias = int(d["bias"])
+    s.bias_k, s.ramp_rate, s.z_target = (float(d[k]) for k in ("bias_k", "ramp_rate", "z_target"))
+    s.contact_r0, s.contact_rs, s.contact_rc = (float(d[k]) for k in ("contact_r0", "contact_rs", "contact_rc"))
+    s.contact_min_sep = int(d["contact_min_sep"])
+    s.reach_tol = float(d["reach_tol"])
+    s.seed = int(d["seed"]) & 0xFFFFFFFFFFFFFFFF
+    return s
+
+
+class System:
+    """A batch of trial trajectories (vp_system)."""
+
+    def __init__(self, reps, nstlist_max=0, skin=0.0, steps_per_graph=0, use_graph=True,
+                 max_neighbors=0, timing=False):
+        keep = []
+        descs = (ReplicaDesc * len(reps))(*[_desc(d, keep) for d in reps])
+        opt = Options()
+        opt.nstlist_max, opt.skin, opt.steps_per_graph = nstlist_max, skin, steps_per_graph
+        opt.use_graph, opt.max_neighbors = int(bool(use_graph)), max_neighbors
+        opt.timing = int(bool(timing))
+        h = _vp()
+        _check(_lib.vp_system_create(descs, len(reps), C.byref(opt), C.byref(h)))
+        self._h = h
+        self.n_reps = len(reps)
+        self.counts = [int(d["n_atoms"]) for d in reps]
+        self.offsets = np.concatenate([[0], np.cumsum(self.counts)]).astype(np.int64)
+        self.n_total = int(self.offsets[-1])
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            _lib.vp_system_destroy(self._h)
+            self._h = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -------------------------------------------------------------------- calls
+    def forces(self, x, t=0.0, energies=False):
+        """Total forces (and the [R, 8] FP64 energy table) at positions x
+        (float32 CUDA tensor [N_total, 3], user order)."""
+        import torch
+        assert x.is_cuda and x.dtype == torch.float32 and x.is_contiguous() and x.shape == (self.n_total, 3)
+        f = torch.empty_like(x)
+        e = torch.zeros((self.n_reps, 8), dtype=torch.float64, device=x.device) if energies else None
+        _check(_lib.vp_forces(self._h, _ptr(x), _ptr(f), _ptr(e) if e is not None else None,
+                              float(t), _stream()))
+        return (f, e) if energies else f
+
+    def step_batch(self, n):
+        _check(_lib.vp_step_batch(self._h, int(n), _stream()))
+
+    def functional(self):
+        phi = np.zeros(self.n_reps)
+        _check(_lib.vp_functional(self._h, phi.ctypes.data_as(_dp), None))
+        return phi
+
+    def select_path(self, eligible=None):
+        """(best replica or -1, its functional)."""
+        best = C.c_int32()
+        bp = C.c_double()
+        el = None
+        if eligible is not None:
+            el = np.ascontiguousarray(eligible, dtype=np.uint8)
+        st = _lib.vp_select_path(self._h, el.ctypes.data_as(C.POINTER(C.c_uint8)) if el is not None else None,
+                                 C.byref(best), C.byref(bp))
+        if st == -5:
+            return -1, float("inf")
+        _check(st)
+        return best.value, bp.value
+
+    def get_state(self):
+        import torch
+        x = torch.empty((self.n_total, 3), dtype=torch.float32, device="cuda")
+        v = torch.empty_like(x)
+        _check(_lib.vp_get_state(self._h, _ptr(x), _ptr(v), _stream()))
+        return x, v
+
+    def observables(self):
+        o = np.zeros((self.n_reps, len(OBS)))
+        _check(_lib.vp_observables(self._h, o.ctypes.data_as(_dp)))
+        return o
+
+    def kernel_timing(self, reset=False):
+        """(mean force-kernel duration in ms, number of launches timed)."""
+        ms = C.c_double()
+        n = C.c_int64()
+        _check(_lib.vp_kernel_timing(self._h, C.byref(ms), C.byref(n), int(bool(reset))))
+        return ms.value, n.value
+
+    def pair_count(self, rep):
+        n = C.c_int64()
+        _check(_lib.vp_pair_count(self._h, int(rep), C.byref(n)))
+        return n.value
+
+    def debug_pairs(self, rep):
+        cnt = C.c_int64()
+        _check(_lib.vp_debug_pairs(self._h, int(rep), None, 0, C.byref(cnt)))
+        out = np.zeros((max(cnt.value, 1), 2), np.int32)
+        _check(_lib.vp_debug_pairs(self._h, int(rep), out.ctypes.data_as(_ip), cnt.value, C.byref(cnt)))
+        return out[: cnt.value]
+
+
+def debug_noise(seed, atom0, step, tag, n):
+    import torch
+    out = torch.empty((n, 4), dtype=torch.float32, device="cuda")
+    _check(_lib.vp_debug_noise(int(seed) & 0xFFFFFFFFFFFFFFFF, atom0, step, tag, n, _ptr(out), _stream()))
+    return out
+
+
+def _energy_autograd():
+    import torch
+
+    class VpEnergy(torch.autograd.Function):
+        """U(X,Y) + U_bias per replica as a differentiable function of the
+        positions: forward runs the energy kernels, backward the force kernels
+        (grad_x = -F scaled by the incoming gradient of each replica)."""
+
+        @staticmethod
+        def forward(ctx, x, system, t):
+            f, e = system.forces(x.detach().contiguous(), t, energies=True)
+            ctx.save_for_backward(f)
+            ctx.offsets = system.offsets
+            return e[:, :5].sum(1)
+
+        @staticmethod
+        def backward(ctx, gout):
+            (f,) = ctx.saved_tensors
+            reps = torch.repeat_interleave(
+                gout.to(f.dtype), torch.as_tensor(np.diff(ctx.offsets), device=f.device))
+            return -f * reps[:, None], None, None
+
+    return VpEnergy
+
+
+def energy(x, system, t=0.0):
+    """Differentiable total energy per replica (torch autograd)."""
+    return _energy_autograd().apply(x, system, t)

@@ -1,0 +1,305 @@
+"""GPU parity of the HIP path against the FP64 CPU oracle, through the C ABI.
+
+Tolerances (stated per quantity):
+  pair sets             exact (same FP32 membership predicate on both sides)
+  Philox words          exact (first uniform), normals <= 5e-6 absolute
+  forces                ||F_gpu - F_ora|| / ||F_ora|| <= 1e-5 and
+                        max_i |dF_i| <= 1e-4 * rms|F|   (FP32 pair arithmetic)
+  10-step trajectories  max |dx| <= 1e-4 nm
+  functional            relative 1e-4 (plus 1e-12 absolute)
+Both sides start from the generator's inputs; the oracle is evaluated at the
+same FP32-rounded positions for single-frame comparisons.
+"""
+import math
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from oracle import oracle as O  # noqa: E402
+from paper_1405_6104_amd import synth, vp  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+F_REL, F_MAX, X_TOL, PHI_REL = 1e-5, 1e-4, 1e-4, 1e-4
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def f32(x):
+    return np.asarray(x, np.float32).astype(np.float64)
+
+
+def force_errors(fg, fo):
+    rel = np.linalg.norm(fg - fo) / np.linalg.norm(fo)
+    mx = np.abs(fg - fo).max() / np.sqrt(np.mean(np.sum(fo ** 2, 1)))
+    return rel, mx
+
+
+def gpu_forces(system, x_list, t=0.0):
+    x = torch.from_numpy(np.concatenate([np.asarray(a, np.float32) for a in x_list])).cuda()
+    f, e = system.forces(x, t, energies=True)
+    torch.cuda.synchronize()
+    return f.cpu().numpy().astype(np.float64), e.cpu().numpy()
+
+
+@pytest.fixture(scope="module")
+def c2():
+    return synth.c2_single()
+
+
+# ------------------------------------------------------------------ noise
+def test_philox_normals_match_oracle():
+    say("noise: seed 0x1234, 5000 atoms")
+    seed = 0x1234_5678_9ABC
+    out = vp.debug_noise(seed, 0, 17, 0, 5000).cpu().numpy().astype(np.float64)
+    for a in range(0, 5000, 7):
+        u = O.uniforms(seed, a, 17, 0)
+        g = O.normals(seed, a, 17, 0)
+        assert out[a, 3] == u[0]
+        assert np.abs(out[a, :3] - g).max() <= 5e-6
+
+
+# ------------------------------------------------------------------ pair sets
+@pytest.mark.parametrize("name", ["tiny", "c1", "lj_small_box"])
+def test_pair_set_exact(name):
+    say("pairs:", name)
+    d = {"tiny": lambda: synth.tiny(seed=2), "c1": synth.c1_small,
+         "lj_small_box": lambda: synth.lj_box(seed=9, n=300, box=2.05, r_cut=1.0)}[name]()
+    system = vp.System([d], skin=0.02 if name == "lj_small_box" else 0.0)
+    got = system.debug_pairs(0)
+    got = set(map(tuple, np.sort(got, axis=1).tolist()))
+    want = set(map(tuple, O.Oracle(d).pairs(f32(d["x0"]), cells=True).tolist()))
+    assert got == want
+
+
+def test_pair_set_exact_c2(c2):
+    say("pairs: c2")
+    system = vp.System([c2])
+    got = set(map(tuple, np.sort(system.debug_pairs(0), axis=1).tolist()))
+    want = set(map(tuple, O.Oracle(c2).pairs(f32(c2["x0"]), cells=True).tolist()))
+    assert len(want) > 2_000_000
+    assert got == want
+
+
+# ------------------------------------------------------------------ forces
+@pytest.mark.parametrize("name", ["tiny", "c1", "tiny_rg", "no_solute"])
+def test_forces_small(name):
+    say("forces:", name)
+    d = {"tiny": lambda: dict(synth.tiny(seed=4), bias_k=0.05),
+         "c1": synth.c1_small,
+         "tiny_rg": lambda: synth.tiny(seed=5, bias=synth.BIAS_RG),
+         "no_solute": lambda: synth.lj_box(seed=3, n=500, box=2.6, r_cut=1.0)}[name]()
+    system = vp.System([d])
+    x = f32(d["x0"])
+    t = 0.05
+    fg, e = gpu_forces(system, [x], t)
+    o = O.Oracle(d)
+    st = o.init(x)
+    fo, fb, terms = o.forces(x, t, st)
+    rel, mx = force_errors(fg, fo)
+    say(f"  rel {rel:.2e} max {mx:.2e}")
+    assert rel <= F_REL and mx <= F_MAX
+    for k, col in (("e_lj", 0), ("e_rf", 1), ("e_bond", 2), ("e_angle", 3), ("e_bias", 4), ("z", 5),
+                   ("z_ref", 6), ("S", 7)):
+        scale = max(1.0, abs(terms["e_lj"]) if col < 4 else abs(terms[k]))
+        assert abs(e[0, col] - terms[k]) <= 2e-5 * scale + 1e-9, (k, e[0, col], terms[k])
+
+
+def test_forces_c2_frame(c2):
+    say("forces: c2 frame")
+    system = vp.System([c2])
+    x = f32(c2["x0"])
+    fg, e = gpu_forces(system, [x], 0.0)
+    o = O.Oracle(c2)
+    st = o.init(x)
+    fo, _, terms = o.forces(x, 0.0, st)
+    rel, mx = force_errors(fg, fo)
+    say(f"  rel {rel:.2e} max {mx:.2e}; z {e[0, 5]:.6f} vs {terms['z']:.6f}")
+    assert rel <= F_REL and mx <= F_MAX
+    assert abs(e[0, 5] - terms["z"]) <= 1e-5 * terms["z"]
+
+
+def test_forces_bias_midramp(c2):
+    """Contact-map bias at t with z_ref between z(X_0) and the target."""
+    say("forces: c2 bias mid-ramp")
+    d = dict(c2, bias_k=0.05, ramp_rate=20.0)
+    system = vp.System([d])
+    x0 = f32(d["x0"])
+    x = f32(synth.perturbed(d, 0.01, 5)["x0"])
+    fg, e = gpu_forces(system, [x], 0.02)
+    o = O.Oracle(d)
+    st = o.init(x0)
+    fo, fb, terms = o.forces(x, 0.02, st)
+    assert np.abs(fb).max() > 1.0
+    rel, mx = force_errors(fg, fo)
+    assert rel <= F_REL and mx <= F_MAX
+    assert abs(e[0, 7] - terms["S"]) <= 1e-4 * terms["S"]
+
+
+# ------------------------------------------------------------------ trajectories
+def oracle_traj(d, nsteps):
+    o = O.Oracle(d)
+    x = d["x0"].copy()
+    v = o.maxwell() if d.get("v0") is None else np.array(d["v0"], dtype=np.float64)
+    st = o.init(x)
+    o.run(x, v, st, nsteps)
+    return o, x, v, st
+
+
+@pytest.mark.parametrize("name,graph", [("tiny", True), ("tiny", False), ("c1", True), ("rmd", True)])
+def test_ten_step_trajectory(name, graph):
+    say("trajectory:", name, "graph" if graph else "direct")
+    d = {"tiny": lambda: dict(synth.tiny(seed=6), bias_k=0.08, ramp_rate=30.0),
+         "c1": synth.c1_small,
+         "rmd": lambda: dict(synth.tiny(seed=7, bias=synth.BIAS_RMD_CONTACT), bias_k=0.5)}[name]()
+    system = vp.System([d], use_graph=graph, steps_per_graph=4)
+    system.step_batch(3)
+    system.step_batch(7)
+    xg, vg = system.get_state()
+    xg = xg.cpu().numpy()
+    o, x, v, st = oracle_traj(d, 10)
+    dx = np.abs(xg - x).max()
+    say(f"  max dx {dx:.2e}")
+    assert dx <= X_TOL
+    phi_g, phi_o = system.functional()[0], o.phi(st)
+    assert abs(phi_g - phi_o) <= PHI_REL * abs(phi_o) + 1e-12, (phi_g, phi_o)
+    obs = system.observables()[0]
+    assert obs[0] == 10 and obs[5] == 0
+
+
+def test_ten_step_trajectory_c2(c2):
+    say("trajectory: c2 10 steps")
+    d = dict(c2, bias_k=0.05, ramp_rate=50.0)
+    system = vp.System([d])
+    system.step_batch(10)
+    xg, _ = system.get_state()
+    o, x, v, st = oracle_traj(d, 10)
+    dx = np.abs(xg.cpu().numpy() - x).max()
+    say(f"  max dx {dx:.2e}")
+    assert dx <= X_TOL
+    phi_g, phi_o = system.functional()[0], o.phi(st)
+    assert phi_o > 0
+    assert abs(phi_g - phi_o) <= PHI_REL * abs(phi_o), (phi_g, phi_o)
+
+
+def test_functional_constant_force_closed_form():
+    """Phi = T |F0|^2 / (4 kT gamma m) for a constant bias on one atom."""
+    say("functional: constant force")
+    d = synth.tiny(seed=3, bias=synth.BIAS_CONST)
+    cf = np.zeros((d["n_solute"], 3))
+    F0 = np.array([3.0, -4.0, 12.0])
+    cf[5] = F0
+    d["const_force"] = cf
+    system = vp.System([d])
+    system.step_batch(17)
+    T = 17 * d["dt"]
+    expect = T * float(F0 @ F0) / (4 * d["kT"] * d["gamma"][5] * d["mass"][5])
+    assert system.functional()[0] == pytest.approx(expect, rel=1e-6)
+
+
+# ------------------------------------------------------------------ batching
+def test_batch_matches_solo_runs_bitwise():
+    say("batch vs solo")
+    base = dict(synth.tiny(seed=11), bias_k=0.1, ramp_rate=20.0)
+    reps = [synth.with_seed(base, 100 + r) for r in range(3)] + [dict(synth.c1_small())]
+    batch = vp.System(reps, steps_per_graph=5)
+    batch.step_batch(12)
+    xb, vb = batch.get_state()
+    phib = batch.functional()
+    xb, vb = xb.cpu().numpy(), vb.cpu().numpy()
+    for r, d in enumerate(reps):
+        solo = vp.System([d], steps_per_graph=5)
+        solo.step_batch(12)
+        xs, vs = solo.get_state()
+        a, b = batch.offsets[r], batch.offsets[r + 1]
+        assert np.array_equal(xs.cpu().numpy(), xb[a:b])
+        assert np.array_equal(vs.cpu().numpy(), vb[a:b])
+        assert solo.functional()[0] == phib[r]
+
+
+def test_run_twice_and_graph_equal_direct_bitwise():
+    say("determinism")
+    d = dict(synth.tiny(seed=12), bias_k=0.1, ramp_rate=20.0)
+    outs = []
+    for graph in (True, True, False):
+        s = vp.System([d], use_graph=graph, steps_per_graph=6)
+        s.step_batch(15)
+        x, v = s.get_state()
+        outs.append((x.cpu().numpy(), v.cpu().numpy(), s.functional()[0]))
+    for o in outs[1:]:
+        assert np.array_equal(o[0], outs[0][0]) and np.array_equal(o[1], outs[0][1]) and o[2] == outs[0][2]
+
+
+def test_heterogeneous_batch_forces():
+    say("heterogeneous batch forces")
+    reps = [dict(synth.tiny(seed=21), bias_k=0.05), synth.c1_small(),
+            synth.lj_box(seed=4, n=777, box=3.0, r_cut=1.2),
+            synth.tiny(seed=22, n_solute=30, n_water=101, box=2.3, r_cut=0.95, bias=synth.BIAS_RG)]
+    system = vp.System(reps)
+    xs = [f32(d["x0"]) for d in reps]
+    fg, e = gpu_forces(system, xs, 0.0)
+    for r, d in enumerate(reps):
+        o = O.Oracle(d)
+        st = o.init(xs[r])
+        fo, _, _ = o.forces(xs[r], 0.0, st)
+        a, b = system.offsets[r], system.offsets[r + 1]
+        rel, mx = force_errors(fg[a:b], fo)
+        assert rel <= F_REL and mx <= F_MAX, (r, rel, mx)
+
+
+def test_selection_picks_least_functional():
+    say("selection")
+    base = dict(synth.tiny(seed=13), bias_k=0.2, ramp_rate=40.0)
+    reps = [synth.with_seed(base, 500 + r) for r in range(6)]
+    system = vp.System(reps)
+    system.step_batch(20)
+    phi = system.functional()
+    best, bp = system.select_path()
+    assert best == int(np.argmin(phi)) and bp == phi[best]
+    elig = np.ones(6, np.uint8)
+    elig[best] = 0
+    b2, _ = system.select_path(elig)
+    assert b2 != best and phi[b2] == np.min(np.where(elig > 0, phi, np.inf))
+    assert system.select_path(np.zeros(6, np.uint8))[0] == -1
+    # the oracle reproduces each trajectory's functional
+    for r in (0, best):
+        o, _, _, st = oracle_traj(reps[r], 20)
+        assert abs(phi[r] - o.phi(st)) <= PHI_REL * o.phi(st)
+
+
+def test_unstable_replica_is_flagged_and_never_selected():
+    say("instability")
+    base = dict(synth.tiny(seed=14), bias_k=0.2, ramp_rate=40.0)
+    bad = dict(base)
+    x0 = base["x0"].copy()
+    x0[20] = x0[1] + 0.01  # two non-bonded solute atoms 0.1 A apart
+    bad["x0"] = x0
+    system = vp.System([base, bad, synth.with_seed(base, 77)])
+    system.step_batch(5)
+    phi = system.functional()
+    obs = system.observables()
+    assert math.isinf(phi[1]) and int(obs[1, 5]) & vp.REPLICA_UNSTABLE
+    assert np.isfinite(phi[0]) and np.isfinite(phi[2])
+    assert system.select_path()[0] in (0, 2)
+    solo = vp.System([base])
+    solo.step_batch(5)
+    xs, _ = solo.get_state()
+    xb, _ = system.get_state()
+    assert np.array_equal(xs.cpu().numpy(), xb.cpu().numpy()[: base["n_atoms"]])
+
+
+def test_autograd_energy_backward_is_minus_force():
+    say("autograd")
+    d = dict(synth.tiny(seed=15), bias_k=0.05)
+    system = vp.System([d])
+    x = torch.from_numpy(d["x0"].astype(np.float32)).cuda().requires_grad_(True)
+    e = vp.energy(x, system, 0.0)
+    e.sum().backward()
+    f = system.forces(x.detach())
+    assert torch.equal(x.grad, -f)
