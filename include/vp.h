@@ -112,10 +112,7 @@ typedef struct {
   int32_t steps_per_graph; /* steps captured per hipGraph launch (0: 20) */
   int32_t use_graph;       /* 1: replay captured graphs; 0: launch every kernel */
   int32_t max_neighbors;   /* per-atom list capacity (0: derived from density) */
-  int32_t timing;          /* 1: record HIP events around every force-kernel launch
-                              (vp_step_batch then waits for each block; see
-                              vp_kernel_timing) */
-  int32_t reserved[6];
+  int32_t reserved[7];
 } vp_options;
 
 /* Create a batch of trial trajectories.  reps: HOST array of n_reps
@@ -167,10 +164,15 @@ enum { VP_OBS_STEP = 0, VP_OBS_Z, VP_OBS_ZREF, VP_OBS_ZMIN, VP_OBS_PHI, VP_OBS_S
        VP_OBS_REBUILDS, VP_OBS_KE, VP_OBS_COUNT };
 vp_status vp_observables(vp_system *s, double *obs_host);
 
-/* Force-kernel timing (options.timing = 1): *avg_ms receives the mean
- * duration of the nonbonded+bonded force kernel over the launches enqueued by
- * vp_step_batch since the last reset, measured with HIP events on the stream
- * it ran on, and *count their number.  reset != 0 clears the accumulators. */
+/* Force-kernel timing.  While on != 0, vp_step_batch enqueues its steps by
+ * direct kernel launches (no graph replay) with a HIP event recorded on the
+ * caller's stream before and after every nonbonded+bonded force launch, and
+ * waits for each block of steps to accumulate the elapsed times.  Results are
+ * bit-identical to the graph path. */
+vp_status vp_set_timing(vp_system *s, int32_t on);
+
+/* Mean duration (*avg_ms) and number (*count) of the force launches timed
+ * since the last reset; reset != 0 clears the accumulators. */
 vp_status vp_kernel_timing(vp_system *s, double *avg_ms, int64_t *count, int32_t reset);
 
 /* Number of unordered pairs of replica rep whose current separation passes

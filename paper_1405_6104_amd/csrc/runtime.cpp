@@ -413,19 +413,7 @@ extern "C" vp_status vp_system_create(const vp_replica_desc *reps, int32_t n_rep
   if (o.steps_per_graph <= 0) o.steps_per_graph = 20;
   if (!opt) o.use_graph = 1;
   s->opt = o;
-  vp_status st = VP_OK;
-  if (o.timing) {
-    for (int k = 0; k < o.steps_per_graph && st == VP_OK; ++k) {
-      hipEvent_t a, b;
-      if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess)
-        st = fail(VP_ERR_HIP, "hipEventCreate failed");
-      else {
-        s->ev_before.push_back(a);
-        s->ev_after.push_back(b);
-      }
-    }
-  }
-  if (st == VP_OK) st = build(s, reps, n_reps);
+  vp_status st = build(s, reps, n_reps);
   if (st != VP_OK) {
     std::string msg = g_err;
     free_all(s);
@@ -447,13 +435,13 @@ extern "C" vp_status vp_system_destroy(vp_system *s) {
 
 // one block of steps: START ... FINISH, with FINISH|START fused inside
 static void enqueue_block(vp_system *s, int steps, hipStream_t st) {
-  const bool timing = s->opt.timing != 0;
+  const bool timing = s->timing;
   for (int k = 0; k < steps; ++k) {
     launch_integrate(s, k == 0 ? INT_START : (INT_FINISH | INT_START), st);
     launch_rebuild(s, s->traj, 0, nullptr, st);
-    if (timing) (void)hipEventRecordWithFlags(s->ev_before[k], st, hipEventRecordExternal);
+    if (timing) (void)hipEventRecord(s->ev_before[k], st);
     launch_forces(s, s->traj, false, st);
-    if (timing) (void)hipEventRecordWithFlags(s->ev_after[k], st, hipEventRecordExternal);
+    if (timing) (void)hipEventRecord(s->ev_after[k], st);
     launch_cv(s, s->traj, 1, st);
   }
   launch_integrate(s, INT_FINISH, st);
@@ -506,7 +494,7 @@ extern "C" vp_status vp_step_batch(vp_system *s, int32_t n_steps, void *hip_stre
   int left = n_steps;
   while (left > 0) {
     int k = std::min(left, B);
-    if (s->opt.use_graph) {
+    if (s->opt.use_graph && !s->timing) {
       hipGraphExec_t ex;
       TRY(graph_for(s, k, &ex));
       HIPCHECK(hipGraphLaunch(ex, st));
@@ -514,7 +502,7 @@ extern "C" vp_status vp_step_batch(vp_system *s, int32_t n_steps, void *hip_stre
       enqueue_block(s, k, st);
       HIPCHECK(hipGetLastError());
     }
-    if (s->opt.timing) TRY(collect_timing(s, k));
+    if (s->timing) TRY(collect_timing(s, k));
     left -= k;
   }
   s->host_step += n_steps;
@@ -618,6 +606,19 @@ extern "C" vp_status vp_observables(vp_system *s, double *obs) {
     o[VP_OBS_REBUILDS] = st[r].rebuilds;
     o[VP_OBS_KE] = k;
   }
+  return VP_OK;
+}
+
+extern "C" vp_status vp_set_timing(vp_system *s, int32_t on) {
+  if (!s) return fail(VP_ERR_ARG, "NULL system");
+  while (on && (int)s->ev_before.size() < s->opt.steps_per_graph) {
+    hipEvent_t a, b;
+    HIPCHECK(hipEventCreate(&a));
+    HIPCHECK(hipEventCreate(&b));
+    s->ev_before.push_back(a);
+    s->ev_after.push_back(b);
+  }
+  s->timing = on != 0;
   return VP_OK;
 }
 

@@ -143,6 +143,7 @@ struct vp_system {
   int64_t host_step = 0;
   hipStream_t last_stream = nullptr;
   // force-kernel timing: one event pair per step of a block, reused per replay
+  bool timing = false;
   std::vector<hipEvent_t> ev_before, ev_after;
   double timing_ms = 0.0;
   int64_t timing_count = 0;

@@ -59,8 +59,8 @@ class ReplicaDesc(C.Structure):
 
 class Options(C.Structure):
     _fields_ = [("nstlist_max", C.c_int32), ("skin", C.c_double), ("steps_per_graph", C.c_int32),
-                ("use_graph", C.c_int32), ("max_neighbors", C.c_int32), ("timing", C.c_int32),
-                ("reserved", C.c_int32 * 6)]
+                ("use_graph", C.c_int32), ("max_neighbors", C.c_int32),
+                ("reserved", C.c_int32 * 7)]
 
 
 _vp = C.c_void_p
@@ -87,6 +87,8 @@ _lib.vp_debug_pairs.argtypes = [_vp, C.c_int32, _ip, C.c_int64, C.POINTER(C.c_in
 _lib.vp_debug_noise.restype = C.c_int
 _lib.vp_debug_noise.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_int32,
                                 C.c_void_p, C.c_void_p]
+_lib.vp_set_timing.restype = C.c_int
+_lib.vp_set_timing.argtypes = [_vp, C.c_int32]
 _lib.vp_kernel_timing.restype = C.c_int
 _lib.vp_kernel_timing.argtypes = [_vp, _dp, C.POINTER(C.c_int64), C.c_int32]
 _lib.vp_pair_count.restype = C.c_int
@@ -96,7 +98,7 @@ _lib.vp_last_error.argtypes = []
 
 EXPORTED = ("vp_system_create", "vp_system_destroy", "vp_forces", "vp_step_batch",
             "vp_functional", "vp_select_path", "vp_get_state", "vp_observables", "vp_sizes",
-            "vp_debug_pairs", "vp_debug_noise", "vp_kernel_timing", "vp_pair_count",
+            "vp_debug_pairs", "vp_debug_noise", "vp_set_timing", "vp_kernel_timing", "vp_pair_count",
             "vp_last_error")
 
 
@@ -158,13 +160,12 @@ class System:
     """A batch of trial trajectories (vp_system)."""
 
     def __init__(self, reps, nstlist_max=0, skin=0.0, steps_per_graph=0, use_graph=True,
-                 max_neighbors=0, timing=False):
+                 max_neighbors=0):
         keep = []
         descs = (ReplicaDesc * len(reps))(*[_desc(d, keep) for d in reps])
         opt = Options()
         opt.nstlist_max, opt.skin, opt.steps_per_graph = nstlist_max, skin, steps_per_graph
         opt.use_graph, opt.max_neighbors = int(bool(use_graph)), max_neighbors
-        opt.timing = int(bool(timing))
         h = _vp()
         _check(_lib.vp_system_create(descs, len(reps), C.byref(opt), C.byref(h)))
         self._h = h
@@ -229,6 +230,9 @@ class System:
         o = np.zeros((self.n_reps, len(OBS)))
         _check(_lib.vp_observables(self._h, o.ctypes.data_as(_dp)))
         return o
+
+    def set_timing(self, on):
+        _check(_lib.vp_set_timing(self._h, int(bool(on))))
 
     def kernel_timing(self, reset=False):
         """(mean force-kernel duration in ms, number of launches timed)."""
