@@ -1,9 +1,9 @@
 /* FP64 CPU oracle — test infrastructure only (see oracle.h).
  *
- * Build: plain C99, -O2 -ffp-contract=off, single-threaded.  FP32 appears in
- * exactly one place, the pair-membership predicate, which the readings list
- * defines in FP32 so that pair *sets* can be compared exactly with the GPU.
- * Everything else is FP64.
+ * Build: plain C99, -O2 -ffp-contract=off, single-threaded.  Everything is
+ * FP64 except the pair-membership predicate, which is defined on fixed-point
+ * coordinates (unit 2^-24 nm) with one FP32 rounding of the exact integer
+ * separation, so that pair *sets* can be compared exactly with the GPU.
  */
 #include "oracle.h"
 
@@ -15,6 +15,7 @@
 #define COULOMB_F 138.935458 /* kJ mol^-1 nm e^-2 */
 #define TWO_PI 6.283185307179586476925286766559
 #define FORCE_LIMIT 1.0e6 /* kJ/mol/nm: above this a replica is unstable */
+#define ORA_QSCALE 16777216.0 /* 2^24: fixed-point coordinates of the pair predicate */
 
 struct ora_ctx {
   ora_sys s;
@@ -22,8 +23,9 @@ struct ora_ctx {
   int32_t *ex_start, *ex_list;
   /* native contact map C~(X_f) for solute pairs, dense [ns][ns] */
   double *cmap_f;
-  /* FP32 geometry of the pair predicate */
-  float L32[3], invL32[3], rc2_32;
+  /* fixed-point geometry of the pair predicate (unit 2^-24 nm) */
+  int64_t Lq[3];
+  float rc2_q;
   /* reaction-field constants */
   double krf, crf;
   /* scratch */
@@ -135,11 +137,11 @@ ora_ctx *ora_create(const ora_sys *s) {
     qsort(c->ex_list + c->ex_start[i], (size_t)(c->ex_start[i + 1] - c->ex_start[i]),
           sizeof(int32_t), cmp_i32);
   free(cnt);
-  for (int a = 0; a < 3; ++a) {
-    c->L32[a] = (float)s->box[a];
-    c->invL32[a] = (float)(1.0 / (double)c->L32[a]);
+  for (int a = 0; a < 3; ++a) c->Lq[a] = llrint(s->box[a] * ORA_QSCALE);
+  {
+    double rq = s->r_cut * ORA_QSCALE;
+    c->rc2_q = (float)(rq * rq);
   }
-  c->rc2_32 = (float)(s->r_cut * s->r_cut);
   double rc = s->r_cut;
   c->krf = (s->eps_rf - 1.0) / ((2.0 * s->eps_rf + 1.0) * rc * rc * rc);
   c->crf = 1.0 / rc + c->krf * rc * rc;
@@ -182,24 +184,35 @@ static int excluded(const ora_ctx *c, int i, int j) {
 }
 
 /* ------------------------------------------------------------------------ */
-/* Pair membership.  Minimum image on FP32 copies of the coordinates:        */
-/*   d = fl32(xj - xi);  n = rint(fl32(d * (1/L)));  d' = fma(-n, L, d);     */
-/*   r2 = fma(dz', dz', fma(dy', dy', fl32(dx' * dx')));  in <=> r2 < rc^2.  */
-/* The FP64 separation used for the force is (xj - xi) - n L in FP64.        */
+/* Pair membership on fixed-point coordinates (unit q = 2^-24 nm):           */
+/*   X = round(x / q) (nearest, ties to even), Lq = round(L / q);            */
+/*   D = Xj - Xi - n Lq with n the nearest integer to (Xj - Xi) / Lq;        */
+/*   d = fl32(D);  r2 = fma(dz, dz, fma(dy, dy, fl32(dx * dx)));             */
+/*   in <=> r2 < fl32((rc / q)^2).                                           */
+/* Inside the cutoff the image n is unique, so the set does not depend on    */
+/* how n is found.  The FP64 separation used for the force is                */
+/* (xj - xi) - n L in FP64.                                                  */
 /* ------------------------------------------------------------------------ */
+static int64_t nearest_int_div(int64_t d, int64_t L) {
+  /* floor((2d + L) / (2L)) */
+  int64_t num = 2 * d + L, den = 2 * L;
+  int64_t q = num / den;
+  if ((num % den != 0) && ((num < 0) != (den < 0))) q -= 1;
+  return q;
+}
+
 static int pair_in(const ora_ctx *c, const double *x, int i, int j, double d[3]) {
   float dp[3];
   for (int a = 0; a < 3; ++a) {
-    float xi = (float)x[3 * i + a], xj = (float)x[3 * j + a];
-    float t = xj - xi;
-    float prod = t * c->invL32[a];
-    float n = rintf(prod);
-    dp[a] = fmaf(-n, c->L32[a], t);
+    int64_t xi = llrint(x[3 * i + a] * ORA_QSCALE), xj = llrint(x[3 * j + a] * ORA_QSCALE);
+    int64_t D = xj - xi;
+    int64_t n = nearest_int_div(D, c->Lq[a]);
+    dp[a] = (float)(D - n * c->Lq[a]);
     d[a] = (x[3 * j + a] - x[3 * i + a]) - (double)n * c->s.box[a];
   }
   float sq = dp[0] * dp[0];
   float r2 = fmaf(dp[2], dp[2], fmaf(dp[1], dp[1], sq));
-  return r2 < c->rc2_32;
+  return r2 < c->rc2_q;
 }
 
 /* Brute force: every unordered pair, definition of the interaction set. */

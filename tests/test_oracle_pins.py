@@ -121,21 +121,24 @@ def test_pair_forces_match_finite_differences(oracle_mod):
 
 # --------------------------------------------------------------- pair sets
 def _numpy_pairs(x, L, rc, excl):
-    """Independent vectorised statement of the FP32 membership predicate."""
-    x32 = x.astype(np.float32)
-    L32 = np.float32(L)
-    inv = np.float32(1.0 / float(L32))
+    """Independent vectorised statement of the fixed-point membership
+    predicate: X = round(x 2^24), nearest image in integers, one rounding to
+    FP32, r2 = fma(dz, dz, fma(dy, dy, dx*dx)) < fl32((rc 2^24)^2)."""
+    q = 2.0 ** 24
+    X = np.rint(x * q).astype(np.int64)
+    Lq = int(np.rint(L * q))
     n = len(x)
     i, j = np.triu_indices(n, 1)
-    d = x32[j] - x32[i]
-    nimg = np.rint((d * inv).astype(np.float32))
-    # fma(-n, L, d) is exact-then-rounded; compute it in float64 (exact for
-    # |n| <= 4 because n*L and d fit in 53 bits) and round once to float32
-    dp = (d.astype(np.float64) - nimg.astype(np.float64) * np.float64(L32)).astype(np.float32)
-    sq = (dp[:, 0] * dp[:, 0]).astype(np.float32)
-    r2 = (dp[:, 1].astype(np.float64) * dp[:, 1] + sq).astype(np.float32)
-    r2 = (dp[:, 2].astype(np.float64) * dp[:, 2] + r2).astype(np.float32)
-    keep = r2 < np.float32(rc * rc)
+    D = X[j] - X[i]
+    nimg = np.floor_divide(2 * D + Lq, 2 * Lq)
+    dp = (D - nimg * Lq).astype(np.float32)
+    # every FP32 value here is an integer below 2^31, so a*a + b is exact in
+    # int64 and one int64 -> FP32 conversion is the single rounding of fma
+    a = dp.astype(np.int64)
+    sq = (a[:, 0] * a[:, 0]).astype(np.float32)
+    r2 = (a[:, 1] * a[:, 1] + sq.astype(np.int64)).astype(np.float32)
+    r2 = (a[:, 2] * a[:, 2] + r2.astype(np.int64)).astype(np.float32)
+    keep = r2 < np.float32((rc * q) ** 2)
     s = set(zip(i[keep].tolist(), j[keep].tolist()))
     s -= set((min(a, b), max(a, b)) for a, b in excl.tolist())
     return s
