@@ -1,12 +1,19 @@
 // Forces of the potential U(X,Y) and the collective variable of the bias.
 //
-// k_forces: one thread per atom of the cell-sorted state.  The thread walks
-// its full Verlet list (both members of every pair hold it, so no atomics and
-// no cross-lane reductions are needed), evaluates potential-shifted LJ with
-// Lorentz-Berthelot mixing plus reaction-field Coulomb in FP32 for members
-// inside r_cut, adds the bonded terms it owns in FP64, and stores the total
-// as 64-bit fixed point.  The list order is fixed by the deterministic sort,
-// so the result does not depend on scheduling.
+// k_forces: one workgroup (4 waves) per block of 64 atoms.  The block's
+// neighbourhood (every atom within r_cut + skin of a block atom, with its
+// periodic image applied as an exact integer shift) is staged in LDS as
+// (x, y, z, type); the replica's (charge, sigma, epsilon) type table is read
+// through the cache; each wave
+// walks every fourth 8-entry chunk of the 64 atoms' full lists (16-bit LDS
+// indices), so every pair is read from LDS instead of gathered from memory
+// and no image arithmetic is left in the pair loop.  Potential-shifted LJ
+// (Lorentz-Berthelot) + reaction-field Coulomb in FP32 on integer-exact
+// separations; the four partial forces are summed in a fixed order, the
+// bonded terms the atom owns are added in FP64, and the total is stored as
+// 64-bit fixed point.  Both members of a pair evaluate it (no atomics); the
+// list order is fixed by the deterministic sort, so results do not depend on
+// scheduling.
 //
 // k_cv: collective variable z and dz/dx of the solute (contact map: several
 // workgroups per replica, each owning a range of solute rows; radius of
@@ -22,132 +29,191 @@ template <bool ENERGY>
 __global__ __launch_bounds__(kBlock) void k_forces(const RepInfo *__restrict__ info, Work W,
                                                    const int32_t *__restrict__ tile_rep,
                                                    const int32_t *__restrict__ tile_first,
-                                                   int ntiles,
+                                                   int nblk, const float4 *__restrict__ types,
                                                    const int32_t *__restrict__ bt_start,
                                                    const BTerm *__restrict__ bterms) {
+  extern __shared__ int4 lds[];
+  int4 *st = lds;
+  float *red = reinterpret_cast<float *>(lds);  // reuses the staging area after the pair loop
   __shared__ double s_red[kBlock / 64];
-  const int tile = xcd_tile(blockIdx.x, ntiles);
-  if (tile < 0) return;
+  const int b = xcd_tile(blockIdx.x, nblk);
+  if (b < 0) return;
+  const int tile = b / (kTile / kBlk);
   const int r = tile_rep[tile];
   const RepInfo &R = info[r];
-  const int p = tile_first[tile] + threadIdx.x;
+  const int p0 = tile_first[tile] + (b % (kTile / kBlk)) * kBlk;
+  const int tid = threadIdx.x;
+  if (p0 >= R.n) {
+    if (tid < kBlk) {
+      const int slot = R.off + p0 + tid;
+      W.F[slot] = 0;
+      W.F[W.fstride + slot] = 0;
+      W.F[2 * W.fstride + slot] = 0;
+    }
+    if (ENERGY && tid < 4) W.epart[4 * (size_t)b + tid] = 0.0;
+    return;
+  }
+  const int Lx = R.Lq[0], Ly = R.Lq[1], Lz = R.Lq[2];
+  // ---- stage the neighbourhood and the type table
+  const int nst = W.stage_n[b];
+  const uint32_t *stg = W.stage + (int64_t)b * kMaxStage;
+  const int4 *xr = W.xq + R.off;
+  for (int s = tid; s < nst; s += kBlock) {
+    const uint32_t e = stg[s];
+    const int j = (int)(e & 0xffffu);
+    const int sx = (int)((e >> 16) & 31) - 16, sy = (int)((e >> 21) & 31) - 16,
+              sz = (int)((e >> 26) & 31) - 16;
+    const int4 xj = xr[j];
+    st[s] = make_int4(xj.x + sx * Lx, xj.y + sy * Ly, xj.z + sz * Lz, xj.w);
+  }
+  if (tid == 0) st[R.stage_cap] = make_int4(kDummyCoord, kDummyCoord, kDummyCoord, R.ntypes);
+  const float4 *tab = types + R.type_off;  // small, cache-resident
+  __syncthreads();
+
+  const int lane = tid & (kBlk - 1), part = tid / kBlk;
+  const int p = p0 + lane;
   const int slot = R.off + p;
   const bool active = p < R.n;
-  double elj = 0.0, erf = 0.0, ebond = 0.0, eangle = 0.0;
-  long long fxs = 0, fys = 0, fzs = 0;
+  float fx = 0.0f, fy = 0.0f, fz = 0.0f;
+  double elj = 0.0, erf = 0.0;
+  int4 xi = make_int4(0, 0, 0, 0);
+  int wx = 0, wy = 0, wz = 0;
   if (active) {
-    const float4 xi = W.xq[slot];
-    const float2 pi = W.prm[slot];
-    const int a = W.orig[slot];
-    const float qi = (float)kCoulomb * xi.w;
-    const float se24 = 24.0f * pi.y;
-    const float sgi = pi.x;
-    const float rc2 = R.rc2, krf2 = R.krf2;
-    float fx = 0.0f, fy = 0.0f, fz = 0.0f;
-    const int cnt = W.nbcnt[slot];
-    const uint16_t *lst = W.nblist + R.list_off + p;
-    const float4 *xqr = W.xq + R.off;
-    const float2 *prr = W.prm + R.off;
-    const int npad = R.npad;
-    for (int k = 0; k < cnt; ++k) {
-      const int j = lst[(int64_t)k * npad];
-      const float4 xj = xqr[j];
-      const float2 pj = prr[j];
-      float dx, dy, dz;
-      const float r2 = pair_r2(xi, xj, R, dx, dy, dz);
-      if (r2 < rc2) {
-        const float rinv = __builtin_amdgcn_rsqf(r2);
-        const float r2inv = rinv * rinv;
-        const float sg = sgi + pj.x;
-        const float sr2 = sg * sg * r2inv;
-        const float sr6 = sr2 * sr2 * sr2;
-        const float e24 = se24 * pj.y;
-        const float flj = e24 * sr6 * __builtin_fmaf(2.0f, sr6, -1.0f) * r2inv;
-        const float qq = qi * xj.w;
-        const float fc = qq * __builtin_fmaf(rinv, r2inv, -krf2);
-        const float fs = flj + fc;
-        fx = __builtin_fmaf(-fs, dx, fx);
-        fy = __builtin_fmaf(-fs, dy, fy);
-        fz = __builtin_fmaf(-fs, dz, fz);
-        if (ENERGY) {
-          const double sgd = (double)sg;
-          const double s2c = sgd * sgd / (R.rc * R.rc);
-          const double s6c = s2c * s2c * s2c;
-          const double e4 = (double)e24 * (1.0 / 6.0);
-          elj += e4 * ((double)sr6 * sr6 - sr6) - e4 * (s6c * s6c - s6c);
-          erf += (double)qq * ((double)rinv + R.krf * (double)r2 - R.krf * R.rc * R.rc - 1.0 / R.rc);
+    xi = W.xq[slot];
+    const int wr = W.wrap[slot];
+    wx = xi.x - unpack_wrap(wr, 0) * Lx;
+    wy = xi.y - unpack_wrap(wr, 1) * Ly;
+    wz = xi.z - unpack_wrap(wr, 2) * Lz;
+    const float4 ti = tab[xi.w];
+    const float rc2 = R.rc2q, krf2 = R.krf2q;
+    const int nch = W.nbcnt[slot] >> 3;
+    const uint4 *lp = reinterpret_cast<const uint4 *>(W.nblist + R.list_off +
+                                                      (int64_t)(b - R.blk0) * R.maxnb * kBlk) + lane;
+    for (int c = part; c < nch; c += kParts) {
+      const uint4 e = lp[(int64_t)c * kBlk];
+      const uint32_t w[4] = {e.x, e.y, e.z, e.w};
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int L = (int)((w[u >> 1] >> (16 * (u & 1))) & 0xffffu);
+        const int4 sj = st[L];
+        const float4 tj = tab[sj.w];
+        const float dx = (float)(sj.x - wx), dy = (float)(sj.y - wy), dz = (float)(sj.z - wz);
+        const float r2 = qr2(dx, dy, dz);
+        if (r2 < rc2) {
+          const float rinv = __builtin_amdgcn_rsqf(r2);
+          const float r2inv = rinv * rinv;
+          const float sg = ti.y + tj.y;
+          const float sr2 = sg * sg * r2inv;
+          const float sr6 = sr2 * sr2 * sr2;
+          const float ee = ti.z * tj.z;
+          const float flj = ee * sr6 * __builtin_fmaf(2.0f, sr6, -1.0f) * r2inv;
+          const float qq = ti.x * tj.x;
+          const float fc = qq * __builtin_fmaf(rinv, r2inv, -krf2);
+          const float fs = flj + fc;
+          fx = __builtin_fmaf(-fs, dx, fx);
+          fy = __builtin_fmaf(-fs, dy, fy);
+          fz = __builtin_fmaf(-fs, dz, fz);
+          if (ENERGY) {
+            // ee = 24 eps 2^48, qq = f q q 2^72 (see the type table)
+            const double e4 = (double)ee * (1.0 / 6.0) * (kInvQ * kInvQ);
+            const double s2c = (double)sg * sg / ((double)rc2);
+            const double s6c = s2c * s2c * s2c;
+            elj += e4 * ((double)sr6 * sr6 - sr6) - e4 * (s6c * s6c - s6c);
+            const double fqq = (double)qq * (kInvQ * kInvQ * kInvQ);
+            erf += fqq * ((double)rinv * kQ + R.krf * (double)r2 * (kInvQ * kInvQ) - R.crf);
+          }
         }
       }
     }
-    // bonded terms owned by this atom (FP64)
-    double bx = 0.0, by = 0.0, bz = 0.0;
-    const int ga = R.uoff + a;
-    const int t0 = bt_start[ga], t1 = bt_start[ga + 1];
-    for (int t = t0; t < t1; ++t) {
-      const BTerm T = bterms[t];
-      if (T.kind == 0) {
-        const float4 xb = W.xq[W.inv[R.uoff + T.a]];
-        const double d0 = (double)xb.x - xi.x, d1 = (double)xb.y - xi.y, d2 = (double)xb.z - xi.z;
-        const double rr = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
-        const double g = T.k * (rr - T.r0) / rr;
-        bx += g * d0;
-        by += g * d1;
-        bz += g * d2;
-        if (ENERGY) ebond += 0.25 * T.k * (rr - T.r0) * (rr - T.r0);  // owned by both atoms
-      } else {
-        // angle end--vertex--end; this atom is an end (kind 1) or the vertex (kind 2)
-        float4 pa, pc, pb;
-        if (T.kind == 1) {
-          pa = xi;
-          pc = W.xq[W.inv[R.uoff + T.a]];
-          pb = W.xq[W.inv[R.uoff + T.b]];
-        } else {
-          pa = W.xq[W.inv[R.uoff + T.a]];
-          pc = xi;
-          pb = W.xq[W.inv[R.uoff + T.b]];
-        }
-        const double u0 = (double)pa.x - pc.x, u1 = (double)pa.y - pc.y, u2 = (double)pa.z - pc.z;
-        const double w0 = (double)pb.x - pc.x, w1 = (double)pb.y - pc.y, w2 = (double)pb.z - pc.z;
-        const double uu = u0 * u0 + u1 * u1 + u2 * u2, ww = w0 * w0 + w1 * w1 + w2 * w2;
-        const double uw = u0 * w0 + u1 * w1 + u2 * w2;
-        const double nn = sqrt(uu * ww);
-        double cs = uw / nn;
-        cs = cs > 1.0 ? 1.0 : (cs < -1.0 ? -1.0 : cs);
-        const double th = acos(cs);
-        double sn = sqrt(1.0 - cs * cs);
-        sn = sn < 1e-12 ? 1e-12 : sn;
-        const double dv = T.k * (th - T.r0) / sn;
-        if (T.kind == 1) {
-          bx += dv * (w0 / nn - cs * u0 / uu);
-          by += dv * (w1 / nn - cs * u1 / uu);
-          bz += dv * (w2 / nn - cs * u2 / uu);
-        } else {
-          bx -= dv * (w0 / nn - cs * u0 / uu + u0 / nn - cs * w0 / ww);
-          by -= dv * (w1 / nn - cs * u1 / uu + u1 / nn - cs * w1 / ww);
-          bz -= dv * (w2 / nn - cs * u2 / uu + u2 / nn - cs * w2 / ww);
-        }
-        if (ENERGY) eangle += (0.5 / 3.0) * T.k * (th - T.r0) * (th - T.r0);  // owned by 3 atoms
-      }
-    }
-    fxs = to_fix((double)fx + bx);
-    fys = to_fix((double)fy + by);
-    fzs = to_fix((double)fz + bz);
   }
-  if (p < R.npad) {
+  // ---- fixed-order sum of the four partial forces, bonded terms, store
+  __syncthreads();  // every wave is done with the staged neighbourhood
+  red[tid] = fx;
+  red[kBlock + tid] = fy;
+  red[2 * kBlock + tid] = fz;
+  __syncthreads();
+  double ebond = 0.0, eangle = 0.0;
+  if (part == 0) {
+    long long fxs = 0, fys = 0, fzs = 0;
+    if (active) {
+      float sx = red[lane], sy = red[kBlock + lane], sz = red[2 * kBlock + lane];
+#pragma unroll
+      for (int q = 1; q < kParts; ++q) {
+        sx += red[q * kBlk + lane];
+        sy += red[kBlock + q * kBlk + lane];
+        sz += red[2 * kBlock + q * kBlk + lane];
+      }
+      double bx = 0.0, by = 0.0, bz = 0.0;
+      const int a = W.orig[slot];
+      const int ga = R.uoff + a;
+      const int t0 = bt_start[ga], t1 = bt_start[ga + 1];
+      for (int t = t0; t < t1; ++t) {
+        const BTerm T = bterms[t];
+        if (T.kind == 0) {
+          const int4 xb = W.xq[W.inv[R.uoff + T.a]];
+          const double d0 = (double)(xb.x - xi.x) * kInvQ, d1 = (double)(xb.y - xi.y) * kInvQ,
+                       d2 = (double)(xb.z - xi.z) * kInvQ;
+          const double rr = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+          const double g = T.k * (rr - T.r0) / rr;
+          bx += g * d0;
+          by += g * d1;
+          bz += g * d2;
+          if (ENERGY) ebond += 0.25 * T.k * (rr - T.r0) * (rr - T.r0);  // owned by both atoms
+        } else {
+          // angle end--vertex--end; this atom is an end (kind 1) or the vertex (kind 2)
+          int4 pa, pc, pb;
+          if (T.kind == 1) {
+            pa = xi;
+            pc = W.xq[W.inv[R.uoff + T.a]];
+            pb = W.xq[W.inv[R.uoff + T.b]];
+          } else {
+            pa = W.xq[W.inv[R.uoff + T.a]];
+            pc = xi;
+            pb = W.xq[W.inv[R.uoff + T.b]];
+          }
+          const double u0 = (double)(pa.x - pc.x) * kInvQ, u1 = (double)(pa.y - pc.y) * kInvQ,
+                       u2 = (double)(pa.z - pc.z) * kInvQ;
+          const double w0 = (double)(pb.x - pc.x) * kInvQ, w1 = (double)(pb.y - pc.y) * kInvQ,
+                       w2 = (double)(pb.z - pc.z) * kInvQ;
+          const double uu = u0 * u0 + u1 * u1 + u2 * u2, ww = w0 * w0 + w1 * w1 + w2 * w2;
+          const double uw = u0 * w0 + u1 * w1 + u2 * w2;
+          const double nn = sqrt(uu * ww);
+          double cs = uw / nn;
+          cs = cs > 1.0 ? 1.0 : (cs < -1.0 ? -1.0 : cs);
+          const double th = acos(cs);
+          double sn = sqrt(1.0 - cs * cs);
+          sn = sn < 1e-12 ? 1e-12 : sn;
+          const double dv = T.k * (th - T.r0) / sn;
+          if (T.kind == 1) {
+            bx += dv * (w0 / nn - cs * u0 / uu);
+            by += dv * (w1 / nn - cs * u1 / uu);
+            bz += dv * (w2 / nn - cs * u2 / uu);
+          } else {
+            bx -= dv * (w0 / nn - cs * u0 / uu + u0 / nn - cs * w0 / ww);
+            by -= dv * (w1 / nn - cs * u1 / uu + u1 / nn - cs * w1 / ww);
+            bz -= dv * (w2 / nn - cs * u2 / uu + u2 / nn - cs * w2 / ww);
+          }
+          if (ENERGY) eangle += (0.5 / 3.0) * T.k * (th - T.r0) * (th - T.r0);  // owned by 3 atoms
+        }
+      }
+      fxs = to_fix((double)sx * kInvQ + bx);
+      fys = to_fix((double)sy * kInvQ + by);
+      fzs = to_fix((double)sz * kInvQ + bz);
+    }
     W.F[slot] = fxs;
     W.F[W.fstride + slot] = fys;
     W.F[2 * W.fstride + slot] = fzs;
   }
   if (ENERGY) {
-    double v0 = block_sum<kBlock>(0.5 * elj, s_red);
-    double v1 = block_sum<kBlock>(0.5 * erf, s_red);
-    double v2 = block_sum<kBlock>(ebond, s_red);
-    double v3 = block_sum<kBlock>(eangle, s_red);
-    if (threadIdx.x == 0) {
-      W.epart[4 * (size_t)tile + 0] = v0;
-      W.epart[4 * (size_t)tile + 1] = v1;
-      W.epart[4 * (size_t)tile + 2] = v2;
-      W.epart[4 * (size_t)tile + 3] = v3;
+    const double v0 = block_sum<kBlock>(0.5 * elj, s_red);
+    const double v1 = block_sum<kBlock>(0.5 * erf, s_red);
+    const double v2 = block_sum<kBlock>(ebond, s_red);
+    const double v3 = block_sum<kBlock>(eangle, s_red);
+    if (tid == 0) {
+      W.epart[4 * (size_t)b + 0] = v0;
+      W.epart[4 * (size_t)b + 1] = v1;
+      W.epart[4 * (size_t)b + 2] = v2;
+      W.epart[4 * (size_t)b + 3] = v3;
     }
   }
 }
@@ -161,7 +227,7 @@ __global__ __launch_bounds__(kCvBlock) void k_cv(const RepInfo *__restrict__ inf
                                                  const double *__restrict__ mass0,
                                                  const float4 *__restrict__ cforce, int inc_step,
                                                  long long *__restrict__ step) {
-  extern __shared__ float4 s_x[];  // solute positions of this replica
+  extern __shared__ int4 s_x[];  // solute positions of this replica
   __shared__ double s_red[kCvBlock / 64];
   __shared__ double s_cm[5];
   const int r = blockIdx.y, b = blockIdx.x;
@@ -176,15 +242,16 @@ __global__ __launch_bounds__(kCvBlock) void k_cv(const RepInfo *__restrict__ inf
       __syncthreads();
       const int i = b * kCvBlock + tid;
       if (i < ns) {
-        const float4 xi = s_x[i];
+        const int4 xi = s_x[i];
         const float *cf = cmap + R.cmap_off + i;
         float gx = 0.0f, gy = 0.0f, gz = 0.0f;
         const int msep = R.min_sep;
         for (int j = 0; j < ns; ++j) {
           if (abs(j - i) <= msep) continue;
-          const float4 xj = s_x[j];
-          const float dx = xj.x - xi.x, dy = xj.y - xi.y, dz = xj.z - xi.z;
-          const float rr = sqrtf(__builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx)));
+          const int4 xj = s_x[j];
+          const float dx = (float)(xj.x - xi.x) * kInvQf, dy = (float)(xj.y - xi.y) * kInvQf,
+                      dz = (float)(xj.z - xi.z) * kInvQf;
+          const float rr = sqrtf(qr2(dx, dy, dz));
           float dc;
           const float c = contact_value(rr, R.cr0, R.crs, R.crc, dc);
           const float diff = c - cf[(int64_t)j * ns];
@@ -198,16 +265,16 @@ __global__ __launch_bounds__(kCvBlock) void k_cv(const RepInfo *__restrict__ inf
         gq = ((double)gx * gx + (double)gy * gy + (double)gz * gz) * igm0[R.uoff + i];
       }
     } else if (R.bias == VP_BIAS_RG) {
-      // mass-weighted radius of gyration on unwrapped coordinates
+      // mass-weighted radius of gyration on unwrapped coordinates (FP64)
       double m = 0.0, cx = 0.0, cy = 0.0, cz = 0.0;
       for (int a = tid; a < ns; a += kCvBlock) {
-        const float4 x = W.xq[W.inv[R.uoff + a]];
+        const int4 x = W.xq[W.inv[R.uoff + a]];
         s_x[a] = x;
         const double ma = mass0[R.uoff + a];
         m += ma;
-        cx += ma * x.x;
-        cy += ma * x.y;
-        cz += ma * x.z;
+        cx += ma * (double)x.x * kInvQ;
+        cy += ma * (double)x.y * kInvQ;
+        cz += ma * (double)x.z * kInvQ;
       }
       double M = block_sum<kCvBlock>(m, s_red);
       double X = block_sum<kCvBlock>(cx, s_red);
@@ -223,8 +290,9 @@ __global__ __launch_bounds__(kCvBlock) void k_cv(const RepInfo *__restrict__ inf
       M = s_cm[4];  // block_sum leaves the total in thread 0 only
       double q = 0.0;
       for (int a = tid; a < ns; a += kCvBlock) {
-        const float4 x = s_x[a];
-        const double d0 = x.x - s_cm[0], d1 = x.y - s_cm[1], d2 = x.z - s_cm[2];
+        const int4 x = s_x[a];
+        const double d0 = (double)x.x * kInvQ - s_cm[0], d1 = (double)x.y * kInvQ - s_cm[1],
+                     d2 = (double)x.z * kInvQ - s_cm[2];
         q += mass0[R.uoff + a] * (d0 * d0 + d1 * d1 + d2 * d2);
       }
       double Q = block_sum<kCvBlock>(q, s_red);
@@ -232,9 +300,10 @@ __global__ __launch_bounds__(kCvBlock) void k_cv(const RepInfo *__restrict__ inf
       __syncthreads();
       const double rg = s_cm[3];
       for (int a = tid; a < ns; a += kCvBlock) {
-        const float4 x = s_x[a];
+        const int4 x = s_x[a];
         const double w = mass0[R.uoff + a] / (M * rg);
-        const double g0 = w * (x.x - s_cm[0]), g1 = w * (x.y - s_cm[1]), g2 = w * (x.z - s_cm[2]);
+        const double g0 = w * ((double)x.x * kInvQ - s_cm[0]), g1 = w * ((double)x.y * kInvQ - s_cm[1]),
+                     g2 = w * ((double)x.z * kInvQ - s_cm[2]);
         W.g[R.sol_off + a] = make_float4((float)g0, (float)g1, (float)g2, 0.0f);
         gq += (g0 * g0 + g1 * g1 + g2 * g2) * igm0[R.uoff + a];
       }
@@ -307,8 +376,8 @@ __global__ void k_energy_out(const RepInfo *__restrict__ info, const RepState *_
   if (threadIdx.x != 0) return;
   const RepInfo &R = info[r];
   double e[4] = {0, 0, 0, 0};
-  for (int tt = R.tile0; tt < R.tile0 + R.ntiles; ++tt)
-    for (int k = 0; k < 4; ++k) e[k] += W.epart[4 * (size_t)tt + k];
+  for (int bb = R.blk0; bb < R.blk0 + R.npad / kBlk; ++bb)
+    for (int k = 0; k < 4; ++k) e[k] += W.epart[4 * (size_t)bb + k];
   double z, G, zr, ub;
   cv_sums(R, W, r, z, G);
   const RepState &S = state[r];
@@ -335,7 +404,7 @@ __global__ void k_native_map(const float *__restrict__ xf, int ns, int min_sep, 
   if (abs(i - j) > min_sep) {
     const float dx = xf[3 * j] - xf[3 * i], dy = xf[3 * j + 1] - xf[3 * i + 1],
                 dz = xf[3 * j + 2] - xf[3 * i + 2];
-    const float rr = sqrtf(__builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx)));
+    const float rr = sqrtf(qr2(dx, dy, dz));
     float dc;
     v = contact_value(rr, r0, rs, rc, dc);
   }
@@ -345,6 +414,14 @@ __global__ void k_native_map(const float *__restrict__ xf, int ns, int min_sep, 
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
+static inline int xcd_grid(int nb) { return 8 * ((nb + 7) / 8); }
+
+size_t force_lds_bytes(const vp_system *s) {
+  size_t stage = sizeof(int4) * (size_t)(s->stage_cap_max + 1);
+  size_t red = sizeof(float) * 3 * kBlock;
+  return stage > red ? stage : red;
+}
+
 void launch_native_map(const float *xf, int ns, int min_sep, float r0, float rs, float rc,
                        float *out, hipStream_t st) {
   int64_t n = (int64_t)ns * ns;
@@ -352,15 +429,14 @@ void launch_native_map(const float *xf, int ns, int min_sep, float r0, float rs,
                      min_sep, r0, rs, rc, out);
 }
 
-static inline int xcd_grid(int nb) { return 8 * ((nb + 7) / 8); }
-
 void launch_forces(vp_system *s, Work &W, bool energy, hipStream_t st) {
+  size_t lds = force_lds_bytes(s);
   if (energy)
-    hipLaunchKernelGGL(k_forces<true>, dim3(xcd_grid(s->n_tiles)), dim3(kBlock), 0, st, s->info,
-                       W, s->tile_rep, s->tile_first, s->n_tiles, s->bt_start, s->bterms);
+    hipLaunchKernelGGL(k_forces<true>, dim3(xcd_grid(s->n_blocks)), dim3(kBlock), lds, st, s->info,
+                       W, s->tile_rep, s->tile_first, s->n_blocks, s->types, s->bt_start, s->bterms);
   else
-    hipLaunchKernelGGL(k_forces<false>, dim3(xcd_grid(s->n_tiles)), dim3(kBlock), 0, st, s->info,
-                       W, s->tile_rep, s->tile_first, s->n_tiles, s->bt_start, s->bterms);
+    hipLaunchKernelGGL(k_forces<false>, dim3(xcd_grid(s->n_blocks)), dim3(kBlock), lds, st, s->info,
+                       W, s->tile_rep, s->tile_first, s->n_blocks, s->types, s->bt_start, s->bterms);
 }
 
 void launch_cv(vp_system *s, Work &W, int inc_step, hipStream_t st) {
@@ -369,7 +445,7 @@ void launch_cv(vp_system *s, Work &W, int inc_step, hipStream_t st) {
     gx = R.cv_blocks > gx ? R.cv_blocks : gx;
     nsmax = R.ns > nsmax ? R.ns : nsmax;
   }
-  size_t lds = sizeof(float4) * (size_t)nsmax;
+  size_t lds = sizeof(int4) * (size_t)nsmax;
   hipLaunchKernelGGL(k_cv, dim3(gx, s->R), dim3(kCvBlock), lds, st, s->info, W, s->cmap, s->igm0,
                      s->mass0, s->cforce, inc_step, s->step);
 }

@@ -86,23 +86,26 @@ __global__ __launch_bounds__(kBlock) void k_integrate(const RepInfo *__restrict_
         v.z += kz;
       }
       if (MODE & MODE_START) {
-        float4 x = W.xq[slot];
+        // positions are fixed point (unit 2^-24 nm): each drift is rounded once
+        int4 x = W.xq[slot];
+        const float hq = hdt * kQf;
         v.x += kx;
         v.y += ky;
         v.z += kz;
-        x.x += hdt * v.x;
-        x.y += hdt * v.y;
-        x.z += hdt * v.z;
+        x.x += __float2int_rn(hq * v.x);
+        x.y += __float2int_rn(hq * v.y);
+        x.z += __float2int_rn(hq * v.z);
         const float3 g = noise3(R.seed, (uint32_t)a, (uint32_t)n, 0u);
         v.x = ig.y * v.x + ig.z * g.x;
         v.y = ig.y * v.y + ig.z * g.y;
         v.z = ig.y * v.z + ig.z * g.z;
-        x.x += hdt * v.x;
-        x.y += hdt * v.y;
-        x.z += hdt * v.z;
+        x.x += __float2int_rn(hq * v.x);
+        x.y += __float2int_rn(hq * v.y);
+        x.z += __float2int_rn(hq * v.z);
         W.xq[slot] = x;
-        const float4 x0 = W.xref[slot];
-        const float ex = x.x - x0.x, ey = x.y - x0.y, ez = x.z - x0.z;
+        const int4 x0 = W.xref[slot];
+        const float ex = (float)(x.x - x0.x) * kInvQf, ey = (float)(x.y - x0.y) * kInvQf,
+                    ez = (float)(x.z - x0.z) * kInvQf;
         disp = sqrtf(ex * ex + ey * ey + ez * ez);
       }
       W.vel[slot] = v;
@@ -120,16 +123,16 @@ __global__ __launch_bounds__(kBlock) void k_integrate(const RepInfo *__restrict_
   }
 }
 
-// Initial state in user order -> identity slots; velocities from v0 or from
-// the Maxwell-Boltzmann distribution (noise tag 1 at step 0).
+// Initial state in user order -> identity slots; positions already in fixed
+// point; velocities from v0 or from the Maxwell-Boltzmann distribution
+// (noise tag 1 at step 0).
 __global__ __launch_bounds__(kBlock) void k_init_state(const RepInfo *__restrict__ info, Work W,
                                                        const int32_t *__restrict__ tile_rep,
                                                        const int32_t *__restrict__ tile_first,
-                                                       int ntiles, const float4 *__restrict__ q0,
-                                                       const float2 *__restrict__ prm0,
+                                                       int ntiles, const int32_t *__restrict__ type0,
                                                        const float4 *__restrict__ integ0,
                                                        const double *__restrict__ mass0,
-                                                       const float *__restrict__ x_user,
+                                                       const int32_t *__restrict__ xq_user,
                                                        const float *__restrict__ v_user,
                                                        const uint8_t *__restrict__ has_v) {
   const int tile = xcd_tile(blockIdx.x, ntiles);
@@ -140,21 +143,21 @@ __global__ __launch_bounds__(kBlock) void k_init_state(const RepInfo *__restrict
   const int slot = R.off + p;
   if (p >= R.npad) return;
   if (p >= R.n) {
-    W.xq[slot] = make_float4(0.f, 0.f, 0.f, 0.f);
+    W.xq[slot] = make_int4(0, 0, 0, R.ntypes);
     W.vel[slot] = make_float4(0.f, 0.f, 0.f, 0.f);
     W.orig[slot] = -1;
-    W.prm[slot] = make_float2(0.f, 0.f);
+    W.wrap[slot] = 0;
     W.integ[slot] = make_float4(0.f, 0.f, 0.f, 0.f);
     W.nbcnt[slot] = 0;
     return;
   }
   const int u = R.uoff + p;
-  const float *xu = x_user + 3ll * u;
-  W.xq[slot] = make_float4(xu[0], xu[1], xu[2], q0[u].w);
+  const int32_t *xu = xq_user + 3ll * u;
+  W.xq[slot] = make_int4(xu[0], xu[1], xu[2], type0[u]);
   W.xref[slot] = W.xq[slot];
   W.orig[slot] = p;
+  W.wrap[slot] = 0;
   W.inv[u] = slot;
-  W.prm[slot] = prm0[u];
   W.integ[slot] = integ0[u];
   if (has_v[r]) {
     const float *vu = v_user + 3ll * u;
@@ -180,11 +183,12 @@ __global__ __launch_bounds__(kBlock) void k_gather_state(const RepInfo *__restri
   if (p >= R.n) return;
   const int slot = R.off + p;
   const int u = R.uoff + W.orig[slot];
-  const float4 x = W.xq[slot], v = W.vel[slot];
+  const int4 x = W.xq[slot];
+  const float4 v = W.vel[slot];
   if (x_out) {
-    x_out[3ll * u] = x.x;
-    x_out[3ll * u + 1] = x.y;
-    x_out[3ll * u + 2] = x.z;
+    x_out[3ll * u] = (float)((double)x.x * kInvQ);
+    x_out[3ll * u + 1] = (float)((double)x.y * kInvQ);
+    x_out[3ll * u + 2] = (float)((double)x.z * kInvQ);
   }
   if (v_out) {
     v_out[3ll * u] = v.x;
@@ -255,11 +259,11 @@ void launch_integrate(vp_system *s, int mode, hipStream_t st) {
   }
 }
 
-void launch_init_state(vp_system *s, const float *x_user, const float *v_user,
+void launch_init_state(vp_system *s, const int32_t *xq_user, const float *v_user,
                        const uint8_t *has_v, hipStream_t st) {
   hipLaunchKernelGGL(k_init_state, dim3(xcd_grid(s->n_tiles)), dim3(kBlock), 0, st, s->info,
-                     s->traj, s->tile_rep, s->tile_first, s->n_tiles, s->q0, s->prm0, s->integ0,
-                     s->mass0, x_user, v_user, has_v);
+                     s->traj, s->tile_rep, s->tile_first, s->n_tiles, s->type0, s->integ0,
+                     s->mass0, xq_user, v_user, has_v);
 }
 
 void launch_gather_state(vp_system *s, float *x_out, float *v_out, hipStream_t st) {

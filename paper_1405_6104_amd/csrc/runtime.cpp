@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <tuple>
 #include <string>
 #include <vector>
 
@@ -107,41 +108,38 @@ vp_status validate(const vp_replica_desc &d, int r) {
 
 }  // namespace
 
-// ---------------------------------------------------------------------------
-// native contact map: cmap[i][j] = C~(|xf_j - xf_i|) for |i - j| > min_sep
-// ---------------------------------------------------------------------------
-namespace vp {
-void launch_native_map(const float *xf, int ns, int min_sep, float r0, float rs, float rc,
-                       float *out, hipStream_t st);
-}
-
 static vp_status alloc_work(vp_system *s, Work &W, bool traj) {
-  size_t S = (size_t)s->n_slots, U = (size_t)s->n_users, R = (size_t)s->R;
+  size_t S = (size_t)s->n_slots, U = (size_t)s->n_users, R = (size_t)s->R, B = (size_t)s->n_blocks;
   TRY(dalloc(s, &W.xq, S));
   if (traj) {
     TRY(dalloc(s, &W.vel, S));
     TRY(dalloc(s, &W.xref, S));
   }
-  TRY(dalloc(s, &W.prm, S));
   TRY(dalloc(s, &W.integ, S));
   TRY(dalloc(s, &W.orig, S));
+  TRY(dalloc(s, &W.wrap, S));
   TRY(dalloc(s, &W.inv, U));
   TRY(dalloc(s, &W.F, 3 * S));
   W.fstride = (int64_t)S;
   TRY(dalloc(s, &W.nbcnt, S));
   TRY(dalloc(s, &W.nblist, (size_t)s->list_elems));
+  TRY(dalloc(s, &W.stage_n, B));
+  TRY(dalloc(s, &W.stage, B * kMaxStage));
   TRY(dalloc(s, &W.cell_start, (size_t)s->n_cells));
+  TRY(dalloc(s, &W.cell_slots, S));
   TRY(dalloc(s, &W.cell_of, S));
   TRY(dalloc(s, &W.g, (size_t)std::max<int64_t>(1, s->n_solute_total)));
   TRY(dalloc(s, &W.zpart, R * kMaxCvBlocks));
   TRY(dalloc(s, &W.gpart, R * kMaxCvBlocks));
-  TRY(dalloc(s, &W.epart, 4 * (size_t)s->n_tiles));
+  TRY(dalloc(s, &W.epart, 4 * B));
   TRY(dalloc(s, &W.flags, R));
   HIPCHECK(hipMemset(W.nbcnt, 0, sizeof(int32_t) * S));
+  HIPCHECK(hipMemset(W.stage_n, 0, sizeof(int32_t) * B));
   HIPCHECK(hipMemset(W.orig, 0xff, sizeof(int32_t) * S));
+  HIPCHECK(hipMemset(W.wrap, 0, sizeof(int32_t) * S));
   HIPCHECK(hipMemset(W.zpart, 0, sizeof(double) * R * kMaxCvBlocks));
   HIPCHECK(hipMemset(W.gpart, 0, sizeof(double) * R * kMaxCvBlocks));
-  HIPCHECK(hipMemset(W.epart, 0, sizeof(double) * 4 * (size_t)s->n_tiles));
+  HIPCHECK(hipMemset(W.epart, 0, sizeof(double) * 4 * B));
   HIPCHECK(hipMemset(W.F, 0, sizeof(long long) * 3 * S));
   return VP_OK;
 }
@@ -164,9 +162,10 @@ static vp_status build(vp_system *s, const vp_replica_desc *reps, int32_t n_reps
   s->R = n_reps;
   s->info_h.resize(n_reps);
   int64_t off = 0, uoff = 0, cell0 = 0, list_off = 0, sol_off = 0;
-  int32_t tile0 = 0;
+  int32_t tile0 = 0, type_off = 0;
   std::vector<int32_t> tile_rep, tile_first;
-  // distinct native maps
+  std::vector<float4> types;
+  std::vector<int32_t> type0;
   struct MapKey {
     const double *xf;
     int ns, sep;
@@ -175,6 +174,9 @@ static vp_status build(vp_system *s, const vp_replica_desc *reps, int32_t n_reps
   std::vector<MapKey> maps;
   std::vector<int64_t> map_off;
   int64_t cmap_total = 0;
+  int stage_cap_max = 0, ntypes_max = 0;
+  const double cell_target = 0.45;  // nm: fine cells of the candidate search
+  const double col_target = 0.8;    // nm: xy columns of the sort order
   for (int r = 0; r < n_reps; ++r) {
     const vp_replica_desc &d = reps[r];
     RepInfo &R = s->info_h[r];
@@ -186,6 +188,7 @@ static vp_status build(vp_system *s, const vp_replica_desc *reps, int32_t n_reps
     R.uoff = (int32_t)uoff;
     R.tile0 = tile0;
     R.ntiles = R.npad / kTile;
+    R.blk0 = tile0 * (kTile / kBlk);
     for (int t = 0; t < R.ntiles; ++t) {
       tile_rep.push_back(r);
       tile_first.push_back(t * kTile);
@@ -193,33 +196,44 @@ static vp_status build(vp_system *s, const vp_replica_desc *reps, int32_t n_reps
     R.bias = d.bias;
     R.min_sep = d.contact_min_sep;
     const double rl = d.r_cut + o.skin;
-    for (int a = 0; a < 3; ++a) {
-      int nc = (int)std::floor(d.box[a] / (rl * (1.0 + 1e-6)));
-      nc = std::max(1, std::min(nc, 16));
-      R.nc[a] = nc;
-      R.L[a] = (float)d.box[a];
-      R.invL[a] = (float)(1.0 / (double)R.L[a]);
-      R.Ld[a] = d.box[a];
-    }
     if (!(rl < 0.5 * std::min({d.box[0], d.box[1], d.box[2]})))
       return fail(VP_ERR_ARG, "replica " + std::to_string(r) + ": r_cut + skin must be below half the box");
+    for (int a = 0; a < 3; ++a) {
+      int nc = (int)std::floor(d.box[a] / cell_target);
+      R.nc[a] = std::max(1, std::min(nc, 16));
+      R.Lq[a] = (int32_t)std::llrint(d.box[a] * kQ);
+      R.Ld[a] = d.box[a];
+    }
     R.ncell = R.nc[0] * R.nc[1] * R.nc[2];
     R.cell0 = (int32_t)cell0;
+    for (int a = 0; a < 2; ++a) R.ncol[a] = std::max(1, std::min(16, (int)std::floor(d.box[a] / col_target)));
     const double vol = d.box[0] * d.box[1] * d.box[2];
-    const double expect = 4.0 / 3.0 * M_PI * rl * rl * rl * d.n_atoms / vol;
+    const double rho = d.n_atoms / vol;
+    const double expect = 4.0 / 3.0 * M_PI * rl * rl * rl * rho;
     int maxnb = o.max_neighbors > 0 ? o.max_neighbors : (int)std::ceil(1.5 * expect + 64);
-    maxnb = std::min(maxnb, d.n_atoms);
-    maxnb = (maxnb + 15) / 16 * 16;
+    maxnb = std::min(maxnb, d.n_atoms + 8);
+    maxnb = (maxnb + 7) / 8 * 8 + 8;
     R.maxnb = maxnb;
+    // staging estimate: atoms within rl of a compact 64-atom block (side
+    // ~0.93 (64/rho)^(1/3)), with a margin for the blocks that turn from one
+    // column into the next
+    const double a = 0.93 * std::cbrt(kBlk / rho);
+    const double vst = a * a * a + 6.0 * a * a * rl + 3.0 * M_PI * a * rl * rl + 4.0 / 3.0 * M_PI * rl * rl * rl;
+    int cap = (int)std::ceil(1.4 * vst * rho + 128);
+    cap = std::min(kMaxStage, std::min(cap, d.n_atoms * 27 + 8));
+    R.stage_cap = cap;
+    stage_cap_max = std::max(stage_cap_max, cap);
     R.list_off = list_off;
     R.sol_off = (int32_t)sol_off;
     R.nstlist_max = o.nstlist_max;
-    R.rc2 = (float)(d.r_cut * d.r_cut);
-    R.rl2 = (float)(rl * rl);
+    const double rcq = d.r_cut * kQ, rlq = rl * kQ;
+    R.rc2q = (float)(rcq * rcq);
+    R.rl2q = (float)(rlq * rlq);
+    R.rlq = (int32_t)std::ceil(rlq);
     R.rc = d.r_cut;
     R.krf = (d.eps_rf - 1.0) / ((2.0 * d.eps_rf + 1.0) * d.r_cut * d.r_cut * d.r_cut);
-    R.krf2 = (float)(2.0 * R.krf);
-    R.crf = (float)(1.0 / d.r_cut + R.krf * d.r_cut * d.r_cut);
+    R.crf = 1.0 / d.r_cut + R.krf * d.r_cut * d.r_cut;
+    R.krf2q = (float)(2.0 * R.krf / (kQ * kQ * kQ));
     R.half_skin_margin = (float)(0.5 * o.skin * 0.98);
     R.cr0 = (float)d.contact_r0;
     R.crs = (float)d.contact_rs;
@@ -231,6 +245,34 @@ static vp_status build(vp_system *s, const vp_replica_desc *reps, int32_t n_reps
     R.dt = d.dt;
     R.reach_tol = d.reach_tol;
     R.seed = d.seed;
+    // (charge, sigma, epsilon) classes of this replica; the last entry is inert
+    {
+      std::map<std::tuple<double, double, double>, int> cls;
+      std::vector<float4> tab;
+      for (int i = 0; i < d.n_atoms; ++i) {
+        auto key = std::make_tuple(d.charge[i], d.sigma[i], d.epsilon[i]);
+        auto it = cls.find(key);
+        int t;
+        if (it == cls.end()) {
+          t = (int)tab.size();
+          cls.emplace(key, t);
+          tab.push_back(make_float4((float)(d.charge[i] * std::sqrt(kCoulomb) * kQ * 4096.0),
+                                    (float)(0.5 * d.sigma[i] * kQ),
+                                    (float)(std::sqrt(24.0 * d.epsilon[i]) * kQ), 0.0f));
+        } else {
+          t = it->second;
+        }
+        type0.push_back(t);
+      }
+      if ((int)tab.size() >= kMaxTypes)
+        return fail(VP_ERR_ARG, "replica " + std::to_string(r) + ": more than 1023 distinct (charge, sigma, epsilon)");
+      R.ntypes = (int32_t)tab.size();
+      R.type_off = type_off;
+      tab.push_back(make_float4(0.f, 0.f, 0.f, 0.f));
+      types.insert(types.end(), tab.begin(), tab.end());
+      type_off += (int32_t)tab.size();
+      ntypes_max = std::max(ntypes_max, R.ntypes);
+    }
     const bool contact = d.bias == VP_BIAS_CONTACT || d.bias == VP_BIAS_RMD_CONTACT;
     R.cv_blocks = contact ? std::max(1, (d.n_solute + kCvBlock - 1) / kCvBlock) : 1;
     R.cmap_off = 0;
@@ -266,13 +308,24 @@ static vp_status build(vp_system *s, const vp_replica_desc *reps, int32_t n_reps
   s->list_elems = list_off;
   s->n_solute_total = sol_off;
   s->n_tiles = tile0;
+  s->n_blocks = tile0 * (kTile / kBlk);
+  s->stage_cap_max = stage_cap_max;
+  s->ntypes_max = ntypes_max;
+  {
+    // the force kernel's dynamic LDS (staged neighbourhood) plus its static
+    // LDS stays within 64 KB per workgroup
+    size_t need = force_lds_bytes(s) + sizeof(double) * (kBlock / 64);
+    if (need > (size_t)kMaxLds)
+      return fail(VP_ERR_ARG, "force kernel would need " + std::to_string(need) +
+                                  " bytes of LDS per workgroup (limit " + std::to_string(kMaxLds) + ")");
+  }
 
   // ---------------- constant per-atom data (user order)
   const size_t U = (size_t)s->n_users;
-  std::vector<float4> q0(U), integ0(U);
-  std::vector<float2> prm0(U);
+  std::vector<float4> integ0(U);
   std::vector<double> igm0(U), mass0(U);
-  std::vector<float> xh(3 * U), vh(3 * U, 0.0f);
+  std::vector<int32_t> xh(3 * U);
+  std::vector<float> vh(3 * U, 0.0f);
   std::vector<uint8_t> has_v(n_reps, 0);
   std::vector<std::vector<BTerm>> terms(U);
   std::vector<std::vector<int32_t>> excl(U);
@@ -282,15 +335,16 @@ static vp_status build(vp_system *s, const vp_replica_desc *reps, int32_t n_reps
     const RepInfo &R = s->info_h[r];
     for (int i = 0; i < d.n_atoms; ++i) {
       size_t u = (size_t)R.uoff + i;
-      q0[u] = make_float4(0, 0, 0, (float)d.charge[i]);
-      prm0[u] = make_float2((float)(0.5 * d.sigma[i]), (float)std::sqrt(d.epsilon[i]));
       double c1 = std::exp(-d.gamma[i] * d.dt);
       double sv = std::sqrt((1.0 - c1 * c1) * d.kT / d.mass[i]);
       integ0[u] = make_float4((float)(1.0 / d.mass[i]), (float)c1, (float)sv, 0.0f);
       igm0[u] = d.gamma[i] > 0 ? 1.0 / (d.gamma[i] * d.mass[i]) : 0.0;
       mass0[u] = d.mass[i];
       for (int a = 0; a < 3; ++a) {
-        xh[3 * u + a] = (float)d.x0[3 * i + a];
+        double xq = d.x0[3 * i + a] * kQ;
+        if (!(std::fabs(xq) < 1.0e9))
+          return fail(VP_ERR_ARG, "replica " + std::to_string(r) + ": coordinates must lie within 59 nm of the origin");
+        xh[3 * u + a] = (int32_t)std::llrint(xq);
         if (d.v0) vh[3 * u + a] = (float)d.v0[3 * i + a];
       }
     }
@@ -340,8 +394,8 @@ static vp_status build(vp_system *s, const vp_replica_desc *reps, int32_t n_reps
   TRY(upload(s, &s->state, st));
   TRY(upload(s, &s->tile_rep, tile_rep));
   TRY(upload(s, &s->tile_first, tile_first));
-  TRY(upload(s, &s->q0, q0));
-  TRY(upload(s, &s->prm0, prm0));
+  TRY(upload(s, &s->type0, type0));
+  TRY(upload(s, &s->types, types));
   TRY(upload(s, &s->integ0, integ0));
   TRY(upload(s, &s->igm0, igm0));
   TRY(upload(s, &s->mass0, mass0));
@@ -364,21 +418,25 @@ static vp_status build(vp_system *s, const vp_replica_desc *reps, int32_t n_reps
   TRY(dalloc(s, &s->xq_t, S));
   TRY(dalloc(s, &s->vel_t, S));
   TRY(dalloc(s, &s->orig_t, S));
-  TRY(dalloc(s, &s->src_t, S));
+  TRY(dalloc(s, &s->wrap_t, S));
   TRY(dalloc(s, &s->cellid_t, S));
+  TRY(dalloc(s, &s->zkey_t, S));
+  TRY(dalloc(s, &s->fcell_t, S));
   TRY(dalloc(s, &s->bucket_t, S));
+  TRY(dalloc(s, &s->bkey_t, S));
   TRY(dalloc(s, &s->borig_t, S));
   TRY(dalloc(s, &s->step, 1));
   HIPCHECK(hipMemset(s->step, 0, sizeof(long long)));
   TRY(alloc_work(s, s->traj, true));
 
   // ---------------- initial state, list, forces, S_0
-  float *dx = nullptr, *dv = nullptr;
+  int32_t *dx = nullptr;
+  float *dv = nullptr;
   uint8_t *dhv = nullptr;
   TRY(dalloc(s, &dx, xh.size()));
   TRY(dalloc(s, &dv, vh.size()));
   TRY(dalloc(s, &dhv, has_v.size()));
-  HIPCHECK(hipMemcpy(dx, xh.data(), sizeof(float) * xh.size(), hipMemcpyHostToDevice));
+  HIPCHECK(hipMemcpy(dx, xh.data(), sizeof(int32_t) * xh.size(), hipMemcpyHostToDevice));
   HIPCHECK(hipMemcpy(dv, vh.data(), sizeof(float) * vh.size(), hipMemcpyHostToDevice));
   HIPCHECK(hipMemcpy(dhv, has_v.data(), has_v.size(), hipMemcpyHostToDevice));
   launch_init_state(s, dx, dv, dhv, 0);

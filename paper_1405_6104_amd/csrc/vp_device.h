@@ -45,24 +45,26 @@ __device__ __forceinline__ float3 noise3(uint64_t seed, uint32_t atom, uint32_t 
 }
 
 // ---------------------------------------------------------------------------
-// Pair membership on FP32 coordinates with an exactly specified order of
-// operations (the CPU test oracle evaluates the same expression):
-//   d = fl(xj - xi); n = rint(fl(d * invL)); d' = fma(-n, L, d);
-//   r2 = fma(dz', dz', fma(dy', dy', fl(dx' * dx'))).
+// Pair membership on fixed-point coordinates (unit 2^-24 nm).  The integer
+// difference of two images is exact; its single rounding to FP32 and the
+// FMA chain below are the exact operation order the CPU test oracle uses:
+//   d = fl(Xj - Xi - n Lq);  r2 = fma(dz, dz, fma(dy, dy, fl(dx * dx))).
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ float min_image(float xi, float xj, float L, float invL) {
-  float t = xj - xi;
-  float n = __builtin_rintf(t * invL);
-  return __builtin_fmaf(-n, L, t);
+__host__ __device__ __forceinline__ long long floordiv(long long a, long long b) {
+  long long q = a / b;
+  if ((a % b != 0) && ((a < 0) != (b < 0))) --q;
+  return q;
 }
 
-__device__ __forceinline__ float pair_r2(const float4 &xi, const float4 &xj, const RepInfo &R,
-                                         float &dx, float &dy, float &dz) {
-  dx = min_image(xi.x, xj.x, R.L[0], R.invL[0]);
-  dy = min_image(xi.y, xj.y, R.L[1], R.invL[1]);
-  dz = min_image(xi.z, xj.z, R.L[2], R.invL[2]);
+__device__ __forceinline__ float qr2(float dx, float dy, float dz) {
   float sq = dx * dx;
   return __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, sq));
+}
+
+// minimum image of an integer displacement (exact for |d| < L/2 + list radius)
+__device__ __forceinline__ int qimage(int d, int Lq) {
+  int n = (int)__builtin_rintf((float)d / (float)Lq);
+  return d - n * Lq;
 }
 
 // ---------------------------------------------------------------------------
@@ -166,7 +168,7 @@ __device__ __forceinline__ double bias_coef(const RepInfo &R, double z, double z
   return 0.0;
 }
 
-// Map a launch-order block index to a tile so that consecutive tiles of one
+// Map a launch-order workgroup index to a tile (or block) so that consecutive tiles of one
 // replica run on the same XCD (blocks are dealt round-robin over 8 XCDs).
 __device__ __forceinline__ int xcd_tile(int b, int nb) {
   const int nx = 8;

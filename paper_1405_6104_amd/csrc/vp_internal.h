@@ -12,34 +12,51 @@ namespace vp {
 
 constexpr int kBlock = 256;          // threads per workgroup of the per-atom kernels
 constexpr int kTile = 256;           // slots per tile (a tile never crosses replicas)
+constexpr int kBlk = 64;             // atoms per neighbourhood block (one wave)
+constexpr int kParts = kBlock / kBlk;  // waves sharing one block in the force kernel
 constexpr int kBinThreads = 1024;    // workgroup of the binning kernel
 constexpr int kMaxCells = 4096;      // cells per replica held in LDS by the binning kernel
+constexpr int kMaxStage = 4093;      // staged neighbourhood atoms per block (LDS, + 1 inert entry)
+constexpr int kMaxLds = 65536;       // LDS bytes per workgroup used by any kernel
+constexpr int kMaxCols = 256;        // xy columns per replica (sort order)
+constexpr int kMaxTypes = 1024;      // (charge, sigma, epsilon) classes per replica
 constexpr int kCvBlock = 256;        // solute atoms per contact-map workgroup
 constexpr int kMaxCvBlocks = 64;     // => at most 16384 solute atoms
-constexpr int kMaxSoluteLds = 8192;  // solute positions staged in LDS (float4, dynamic)
+constexpr int kMaxSoluteLds = 8192;  // solute positions staged in LDS (dynamic)
 constexpr double kFixScale = 4294967296.0;  // 2^32: fixed-point force unit
 constexpr double kForceLimit = 1.0e6;       // kJ/mol/nm: above this a replica is unstable
 constexpr double kCoulomb = 138.935458;
+constexpr double kQ = 16777216.0;           // 2^24: coordinate unit is 2^-24 nm
+constexpr float kQf = 16777216.0f;
+constexpr float kInvQf = 5.9604644775390625e-8f;  // 2^-24
+constexpr double kInvQ = 5.9604644775390625e-8;
+constexpr int kDummyCoord = 1 << 30;  // staged position of the list padding entry
 
 // Constant per-replica data (device copy in an array indexed by replica).
 struct RepInfo {
   int32_t n, ns, npad, off;     // atoms, solute atoms, padded slots, first slot
   int32_t uoff;                 // first user-order index
   int32_t tile0, ntiles;        // tiles [tile0, tile0+ntiles)
+  int32_t blk0;                 // first neighbourhood block
   int32_t bias, min_sep;
-  int32_t nc[3], ncell, cell0;  // cell grid and offset into the cell arrays
-  int32_t maxnb;                // per-atom list capacity
-  int64_t list_off;             // first element of this replica's list block
+  int32_t nc[3], ncell, cell0;  // fine cell grid (candidate search) and offset into the cell arrays
+  int32_t ncol[2];              // xy columns of the sort order
+  int32_t Lq[3];                // box edges in coordinate units
+  int32_t maxnb;                // per-atom list capacity (multiple of 8)
+  int32_t stage_cap;            // staged atoms per block (<= kMaxStage)
+  int32_t ntypes, type_off;     // type table (ntypes + 1 entries, last is inert)
+  int64_t list_off;             // first element of this replica's list storage
   int64_t cmap_off;             // first element of the native contact map (FP32 [ns][ns])
   int32_t cv_blocks;            // contact-map workgroups used by this replica
   int32_t sol_off;              // first index in per-solute arrays
   int32_t nstlist_max;
-  float L[3], invL[3];
-  float rc2, rl2, krf2, crf;    // cutoff^2, list radius^2, 2*k_rf, c_rf
-  float half_skin_margin;       // displacement that forces a rebuild
-  float cr0, crs, crc;          // contact r0, switch start, switch end
+  float rc2q, rl2q;             // (rc/q)^2 and (rl/q)^2 in FP32
+  float krf2q;                  // 2 k_rf q^3 (RF term in coordinate units)
+  float half_skin_margin;       // displacement (nm) that forces a rebuild
+  float cr0, crs, crc;          // contact r0, switch start, switch end (nm)
+  int32_t rlq;                  // list radius in coordinate units
   double Ld[3];
-  double rc, krf;
+  double rc, krf, crf;
   double bias_k, ramp_rate, z_target;
   double kT, dt, reach_tol;
   uint64_t seed;
@@ -71,27 +88,37 @@ struct BTerm {
 
 // Device buffers of one evaluation context (trajectory or vp_forces).
 struct Work {
-  float4 *xq = nullptr;     // [slots] x, y, z (unwrapped), charge
+  int4 *xq = nullptr;       // [slots] x, y, z (unwrapped, units of 2^-24 nm), type
   float4 *vel = nullptr;    // [slots] vx, vy, vz, 0
-  float2 *prm = nullptr;    // [slots] sigma/2, sqrt(eps)
   float4 *integ = nullptr;  // [slots] 1/m, c1, sigma_v, 0
   int32_t *orig = nullptr;  // [slots] replica-local user index or -1
-  float4 *xref = nullptr;   // [slots] positions at the last list build
+  int32_t *wrap = nullptr;  // [slots] periodic image of the atom at the last build (packed)
+  int4 *xref = nullptr;     // [slots] positions at the last list build
   int32_t *inv = nullptr;   // [users] global slot of each atom
   long long *F = nullptr;   // [3][slots] fixed-point forces (without bias), SoA
   int64_t fstride = 0;      // slots: distance between the x, y and z planes of F
-  int32_t *nbcnt = nullptr;     // [slots]
-  uint16_t *nblist = nullptr;   // per replica [maxnb][npad]
-  int32_t *cell_start = nullptr;  // [sum ncell + R]
-  int32_t *cell_of = nullptr;     // [slots] cell of each new slot
+  int32_t *nbcnt = nullptr;     // [slots] list length (multiple of 8)
+  uint16_t *nblist = nullptr;   // per block [maxnb/8][64][8] staged indices
+  int32_t *stage_n = nullptr;   // [blocks]
+  uint32_t *stage = nullptr;    // [blocks][kMaxStage] slot | image shifts
+  int32_t *cell_start = nullptr;  // [sum ncell + R] fine-cell CSR offsets (replica-local)
+  int32_t *cell_slots = nullptr;  // [slots] slots of each fine cell, ascending
+  int32_t *cell_of = nullptr;     // [slots] fine cell of each new slot
   float4 *g = nullptr;            // [solute total] dz/dx (xyz) of each solute atom
   double *zpart = nullptr;        // [R][kMaxCvBlocks]
   double *gpart = nullptr;        // [R][kMaxCvBlocks] sum |g|^2/(gamma m)
-  double *epart = nullptr;        // [tiles][4] energy partials (LJ, RF, bond, angle)
+  double *epart = nullptr;        // [blocks][4] energy partials (LJ, RF, bond, angle)
   int32_t *flags = nullptr;       // [R] rebuild flag for the eval context
 };
 
-struct Timing;
+// packed periodic image (3 x 10-bit signed)
+__host__ __device__ inline int32_t pack_wrap(int kx, int ky, int kz) {
+  return ((kx & 1023)) | ((ky & 1023) << 10) | ((kz & 1023) << 20);
+}
+__host__ __device__ inline int unpack_wrap(int32_t w, int d) {
+  int v = (w >> (10 * d)) & 1023;
+  return v >= 512 ? v - 1024 : v;
+}
 
 }  // namespace vp
 
@@ -100,18 +127,20 @@ struct vp_system {
   int64_t n_users = 0;   // sum of atoms
   int64_t n_slots = 0;   // sum of padded atoms
   int32_t n_tiles = 0;
+  int32_t n_blocks = 0;
   int64_t n_cells = 0;
   int64_t list_elems = 0;
   int64_t n_solute_total = 0;
+  int32_t stage_cap_max = 0, ntypes_max = 0;
   vp_options opt{};
   std::vector<vp::RepInfo> info_h;
   vp::RepInfo *info = nullptr;    // device
   vp::RepState *state = nullptr;  // device
-  int32_t *tile_rep = nullptr;    // [tiles] replica of each tile (XCD-aware order)
+  int32_t *tile_rep = nullptr;    // [tiles] replica of each tile
   int32_t *tile_first = nullptr;  // [tiles] first slot of each tile
   // constant per-atom data in user order
-  float4 *q0 = nullptr;      // [users] charge in .w (xyz unused)
-  float2 *prm0 = nullptr;    // [users]
+  int32_t *type0 = nullptr;  // [users] type of each atom
+  float4 *types = nullptr;   // type tables: (q sqrt(f) 2^36, sigma/2 2^24, sqrt(24 eps) 2^24, 0)
   float4 *integ0 = nullptr;  // [users]
   double *igm0 = nullptr;    // [users] 1/(gamma m) (solute entries used)
   double *mass0 = nullptr;   // [users] masses
@@ -122,27 +151,27 @@ struct vp_system {
   float *cmap = nullptr;        // native contact maps, [ns][ns] per distinct map
   float4 *cforce = nullptr;     // [solute total] constant bias force
   // scratch shared by both contexts (list rebuild)
-  float4 *xq_t = nullptr;
+  int4 *xq_t = nullptr;
   float4 *vel_t = nullptr;
   int32_t *orig_t = nullptr;
-  int32_t *src_t = nullptr;
-  int32_t *cellid_t = nullptr;
-  int32_t *bucket_t = nullptr;
-  int32_t *borig_t = nullptr;
+  int32_t *wrap_t = nullptr;
+  int32_t *cellid_t = nullptr;  // [slots] column of each old slot
+  int32_t *zkey_t = nullptr;    // [slots] serpentine z key of each old slot
+  int32_t *fcell_t = nullptr;   // [slots] fine cell of each old slot
+  int32_t *bucket_t = nullptr;  // [slots] old slots grouped by column / new slots by cell
+  int32_t *bkey_t = nullptr;    // [slots] z keys in bucket order
+  int32_t *borig_t = nullptr;   // [slots] user indices in bucket order
   long long *step = nullptr;  // device step counter
   vp::Work traj, eval;
   bool eval_ready = false;
-  // graphs keyed by (steps, first-block) shape
   struct GraphEntry {
     int32_t steps;
     hipStream_t stream;
     hipGraphExec_t exec;
   };
   std::vector<GraphEntry> graphs;
-  bool started = false;       // a step has begun since the last finishing half-kick
   int64_t host_step = 0;
   hipStream_t last_stream = nullptr;
-  // force-kernel timing: one event pair per step of a block, reused per replay
   bool timing = false;
   std::vector<hipEvent_t> ev_before, ev_after;
   double timing_ms = 0.0;

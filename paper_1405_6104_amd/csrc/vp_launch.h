@@ -15,8 +15,11 @@ void launch_cv(vp_system *s, Work &W, int inc_step, hipStream_t st);
 void launch_force_out(vp_system *s, Work &W, double t, float *f_user, double *e_out,
                       hipStream_t st);
 void launch_integrate(vp_system *s, int mode, hipStream_t st);
-void launch_init_state(vp_system *s, const float *x_user, const float *v_user,
+void launch_init_state(vp_system *s, const int32_t *xq_user, const float *v_user,
                        const uint8_t *has_v, hipStream_t st);
+void launch_native_map(const float *xf, int ns, int min_sep, float r0, float rs, float rc,
+                       float *out, hipStream_t st);
+size_t force_lds_bytes(const vp_system *s);
 void launch_gather_state(vp_system *s, float *x_out, float *v_out, hipStream_t st);
 void launch_kinetic(vp_system *s, double *out, hipStream_t st);
 void launch_debug_noise(uint64_t seed, uint32_t atom0, uint32_t step, uint32_t tag, int n,
