@@ -94,7 +94,7 @@ typedef struct {
   const int32_t *excl; /* [n_excl][2]: pairs without nonbonded interaction */
   double box[3];       /* orthorhombic box edges */
   double r_cut, eps_rf, kT, dt;
-  const double *x0;      /* [n_atoms][3] X_i (+ solvent), unwrapped */
+  const double *x0;      /* [n_atoms][3] X_i (+ solvent), unwrapped; |x| < 59 nm */
   const double *v0;      /* [n_atoms][3] or NULL: Maxwell-Boltzmann from the seed */
   const double *x_final; /* [n_solute][3] X_f (defines the target contact map) or NULL */
   int32_t bias;          /* vp_bias_kind */
@@ -115,7 +115,13 @@ typedef struct {
   int32_t reserved[7];
 } vp_options;
 
-/* Create a batch of trial trajectories.  reps: HOST array of n_reps
+/* Positions are held as 32-bit fixed point in units of 2^-24 nm, so that
+ * periodic images are exact integer shifts: x0 and x_dev are rounded to the
+ * nearest multiple of 2^-24 nm (ties to even) on entry and every drift of the
+ * integrator is rounded to that grid.  Coordinates must stay within 59 nm of
+ * the origin.
+ *
+ * Create a batch of trial trajectories.  reps: HOST array of n_reps
  * descriptions (deep-copied).  opt: HOST, may be NULL for defaults.  Uploads
  * parameters, draws Maxwell velocities where v0 is NULL, builds the pair
  * lists and evaluates the forces and the functional integrand at t = 0.

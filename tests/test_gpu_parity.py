@@ -31,14 +31,24 @@ def say(*a):
     print(*a, flush=True)
 
 
+GRID = 2.0 ** 24  # the library holds positions in units of 2^-24 nm
+
+
 def f32(x):
-    return np.asarray(x, np.float32).astype(np.float64)
+    """FP32 positions on the library's grid, as float64.  The library rounds
+    every position it receives to the nearest multiple of 2^-24 nm; below
+    1 nm that moves an FP32 value by up to 3e-8 nm, which alone changes the
+    net forces of stiff water by ~1e-5 relative, so the oracle is given the
+    configuration the library evaluates.  The values are exact in FP32, so
+    the library's rounding leaves them unchanged."""
+    x = np.asarray(x, np.float32).astype(np.float64)
+    return np.rint(x * GRID) / GRID
 
 
 def x0_of(d):
-    """Initial positions as the library receives them (FP64; the library
-    rounds them once to its 2^-24 nm grid, exactly as the oracle does)."""
-    return np.ascontiguousarray(d["x0"], np.float64)
+    """Initial positions of a description as the library holds them (the FP64
+    x0 rounded once to the 2^-24 nm grid)."""
+    return np.rint(np.asarray(d["x0"], np.float64) * GRID) / GRID
 
 
 def assert_same_pairs(got, want):
@@ -165,7 +175,7 @@ def test_forces_bias_midramp(c2):
 # ------------------------------------------------------------------ trajectories
 def oracle_traj(d, nsteps):
     o = O.Oracle(d)
-    x = d["x0"].copy()
+    x = x0_of(d)
     v = o.maxwell() if d.get("v0") is None else np.array(d["v0"], dtype=np.float64)
     st = o.init(x)
     o.run(x, v, st, nsteps)
