@@ -107,7 +107,10 @@ typedef struct {
 } vp_replica_desc;
 
 typedef struct {
-  int32_t nstlist_max; /* upper bound on steps between pair-list builds (0: 100) */
+  int32_t nstlist;     /* pair lists are rebuilt when the step count n + 1 is a
+                          multiple of nstlist (the same steps in every replica)
+                          and whenever an atom has moved half the skin since
+                          its replica's last build (0: 4) */
   double skin;         /* pair-list buffer in nm (0: 0.1) */
   int32_t steps_per_graph; /* steps captured per hipGraph launch (0: 20) */
   int32_t use_graph;       /* 1: replay captured graphs; 0: launch every kernel */

@@ -1,15 +1,15 @@
 // Forces of the potential U(X,Y) and the collective variable of the bias.
 //
-// k_forces: one workgroup (4 waves) per block of 64 atoms.  The block's
+// k_forces: one workgroup (8 waves) per block of 64 atoms.  The block's
 // neighbourhood (every atom within r_cut + skin of a block atom, with its
 // periodic image applied as an exact integer shift) is staged in LDS as
-// (x, y, z, type); the replica's (charge, sigma, epsilon) type table is read
-// through the cache; each wave
-// walks every fourth 8-entry chunk of the 64 atoms' full lists (16-bit LDS
+// (x, y, z, type), followed by the replica's (charge, sigma, epsilon) type
+// table; each wave
+// walks every eighth 8-entry chunk of the 64 atoms' full lists (16-bit LDS
 // indices), so every pair is read from LDS instead of gathered from memory
 // and no image arithmetic is left in the pair loop.  Potential-shifted LJ
 // (Lorentz-Berthelot) + reaction-field Coulomb in FP32 on integer-exact
-// separations; the four partial forces are summed in a fixed order, the
+// separations; the eight partial forces are summed in a fixed order, the
 // bonded terms the atom owns are added in FP64, and the total is stored as
 // 64-bit fixed point.  Both members of a pair evaluate it (no atomics); the
 // list order is fixed by the deterministic sort, so results do not depend on
@@ -26,16 +26,18 @@
 namespace vp {
 
 template <bool ENERGY>
-__global__ __launch_bounds__(kBlock) void k_forces(const RepInfo *__restrict__ info, Work W,
+__global__ __launch_bounds__(kForceThreads) void k_forces(const RepInfo *__restrict__ info, Work W,
                                                    const int32_t *__restrict__ tile_rep,
                                                    const int32_t *__restrict__ tile_first,
                                                    int nblk, const float4 *__restrict__ types,
                                                    const int32_t *__restrict__ bt_start,
-                                                   const BTerm *__restrict__ bterms) {
+                                                   const BTerm *__restrict__ bterms,
+                                                   int stage_slots) {
   extern __shared__ int4 lds[];
-  int4 *st = lds;
+  int4 *st = lds;                                              // [stage_slots] staged atoms
+  float4 *tab = reinterpret_cast<float4 *>(lds + stage_slots);  // the replica's type table
   float *red = reinterpret_cast<float *>(lds);  // reuses the staging area after the pair loop
-  __shared__ double s_red[kBlock / 64];
+  __shared__ double s_red[kForceThreads / 64];
   const int b = xcd_tile(blockIdx.x, nblk);
   if (b < 0) return;
   const int tile = b / (kTile / kBlk);
@@ -58,7 +60,7 @@ __global__ __launch_bounds__(kBlock) void k_forces(const RepInfo *__restrict__ i
   const int nst = W.stage_n[b];
   const uint32_t *stg = W.stage + (int64_t)b * kMaxStage;
   const int4 *xr = W.xq + R.off;
-  for (int s = tid; s < nst; s += kBlock) {
+  for (int s = tid; s < nst; s += kForceThreads) {
     const uint32_t e = stg[s];
     const int j = (int)(e & 0xffffu);
     const int sx = (int)((e >> 16) & 31) - 16, sy = (int)((e >> 21) & 31) - 16,
@@ -67,7 +69,7 @@ __global__ __launch_bounds__(kBlock) void k_forces(const RepInfo *__restrict__ i
     st[s] = make_int4(xj.x + sx * Lx, xj.y + sy * Ly, xj.z + sz * Lz, xj.w);
   }
   if (tid == 0) st[R.stage_cap] = make_int4(kDummyCoord, kDummyCoord, kDummyCoord, R.ntypes);
-  const float4 *tab = types + R.type_off;  // small, cache-resident
+  for (int t = tid; t <= R.ntypes; t += kForceThreads) tab[t] = types[R.type_off + t];
   __syncthreads();
 
   const int lane = tid & (kBlk - 1), part = tid / kBlk;
@@ -89,59 +91,66 @@ __global__ __launch_bounds__(kBlock) void k_forces(const RepInfo *__restrict__ i
     const int nch = W.nbcnt[slot] >> 3;
     const uint4 *lp = reinterpret_cast<const uint4 *>(W.nblist + R.list_off +
                                                       (int64_t)(b - R.blk0) * R.maxnb * kBlk) + lane;
+    uint4 e = lp[(int64_t)min(part, max(nch - 1, 0)) * kBlk];
     for (int c = part; c < nch; c += kParts) {
-      const uint4 e = lp[(int64_t)c * kBlk];
+      // the next chunk's indices are fetched while this one is evaluated (the
+      // last chunk is fetched again rather than reading past the list)
+      const uint4 en = lp[(int64_t)min(c + kParts, nch - 1) * kBlk];
       const uint32_t w[4] = {e.x, e.y, e.z, e.w};
+      int4 sj[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) sj[u] = st[(w[u >> 1] >> (16 * (u & 1))) & 0xffffu];
+      float4 tj[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) tj[u] = tab[sj[u].w];
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
-        const int L = (int)((w[u >> 1] >> (16 * (u & 1))) & 0xffffu);
-        const int4 sj = st[L];
-        const float4 tj = tab[sj.w];
-        const float dx = (float)(sj.x - wx), dy = (float)(sj.y - wy), dz = (float)(sj.z - wz);
+        // every entry is evaluated; the cutoff selects (no divergent branch)
+        const float dx = (float)(sj[u].x - wx), dy = (float)(sj[u].y - wy), dz = (float)(sj[u].z - wz);
         const float r2 = qr2(dx, dy, dz);
-        if (r2 < rc2) {
-          const float rinv = __builtin_amdgcn_rsqf(r2);
-          const float r2inv = rinv * rinv;
-          const float sg = ti.y + tj.y;
-          const float sr2 = sg * sg * r2inv;
-          const float sr6 = sr2 * sr2 * sr2;
-          const float ee = ti.z * tj.z;
-          const float flj = ee * sr6 * __builtin_fmaf(2.0f, sr6, -1.0f) * r2inv;
-          const float qq = ti.x * tj.x;
-          const float fc = qq * __builtin_fmaf(rinv, r2inv, -krf2);
-          const float fs = flj + fc;
-          fx = __builtin_fmaf(-fs, dx, fx);
-          fy = __builtin_fmaf(-fs, dy, fy);
-          fz = __builtin_fmaf(-fs, dz, fz);
-          if (ENERGY) {
-            // ee = 24 eps 2^48, qq = f q q 2^72 (see the type table)
-            const double e4 = (double)ee * (1.0 / 6.0) * (kInvQ * kInvQ);
-            const double s2c = (double)sg * sg / ((double)rc2);
-            const double s6c = s2c * s2c * s2c;
-            elj += e4 * ((double)sr6 * sr6 - sr6) - e4 * (s6c * s6c - s6c);
-            const double fqq = (double)qq * (kInvQ * kInvQ * kInvQ);
-            erf += fqq * ((double)rinv * kQ + R.krf * (double)r2 * (kInvQ * kInvQ) - R.crf);
-          }
+        const bool in = r2 < rc2;
+        const float rinv = __builtin_amdgcn_rsqf(r2);
+        const float r2inv = rinv * rinv;
+        const float sg = ti.y + tj[u].y;
+        const float sr2 = sg * sg * r2inv;
+        const float sr6 = sr2 * sr2 * sr2;
+        const float ee = ti.z * tj[u].z;
+        const float flj = ee * sr6 * __builtin_fmaf(2.0f, sr6, -1.0f) * r2inv;
+        const float qq = ti.x * tj[u].x;
+        const float fc = qq * __builtin_fmaf(rinv, r2inv, -krf2);
+        const float fs = in ? flj + fc : 0.0f;
+        fx = __builtin_fmaf(-fs, dx, fx);
+        fy = __builtin_fmaf(-fs, dy, fy);
+        fz = __builtin_fmaf(-fs, dz, fz);
+        if (ENERGY && in) {
+          // ee = 24 eps 2^48, qq = f q q 2^72 (see the type table)
+          const double e4 = (double)ee * (1.0 / 6.0) * (kInvQ * kInvQ);
+          const double s2c = (double)sg * sg / ((double)rc2);
+          const double s6c = s2c * s2c * s2c;
+          elj += e4 * ((double)sr6 * sr6 - sr6) - e4 * (s6c * s6c - s6c);
+          const double fqq = (double)qq * (kInvQ * kInvQ * kInvQ);
+          erf += fqq * ((double)rinv * kQ + R.krf * (double)r2 * (kInvQ * kInvQ) - R.crf);
         }
       }
+      e = en;
     }
   }
-  // ---- fixed-order sum of the four partial forces, bonded terms, store
+  // ---- fixed-order sum of the partial forces of the waves, bonded terms, store
   __syncthreads();  // every wave is done with the staged neighbourhood
   red[tid] = fx;
-  red[kBlock + tid] = fy;
-  red[2 * kBlock + tid] = fz;
+  red[kForceThreads + tid] = fy;
+  red[2 * kForceThreads + tid] = fz;
   __syncthreads();
   double ebond = 0.0, eangle = 0.0;
   if (part == 0) {
     long long fxs = 0, fys = 0, fzs = 0;
     if (active) {
-      float sx = red[lane], sy = red[kBlock + lane], sz = red[2 * kBlock + lane];
+      float sx = red[lane], sy = red[kForceThreads + lane], sz = red[2 * kForceThreads + lane];
 #pragma unroll
       for (int q = 1; q < kParts; ++q) {
         sx += red[q * kBlk + lane];
-        sy += red[kBlock + q * kBlk + lane];
-        sz += red[2 * kBlock + q * kBlk + lane];
+        sy += red[kForceThreads + q * kBlk + lane];
+        sz += red[2 * kForceThreads + q * kBlk + lane];
       }
       double bx = 0.0, by = 0.0, bz = 0.0;
       const int a = W.orig[slot];
@@ -205,10 +214,10 @@ __global__ __launch_bounds__(kBlock) void k_forces(const RepInfo *__restrict__ i
     W.F[2 * W.fstride + slot] = fzs;
   }
   if (ENERGY) {
-    const double v0 = block_sum<kBlock>(0.5 * elj, s_red);
-    const double v1 = block_sum<kBlock>(0.5 * erf, s_red);
-    const double v2 = block_sum<kBlock>(ebond, s_red);
-    const double v3 = block_sum<kBlock>(eangle, s_red);
+    const double v0 = block_sum<kForceThreads>(0.5 * elj, s_red);
+    const double v1 = block_sum<kForceThreads>(0.5 * erf, s_red);
+    const double v2 = block_sum<kForceThreads>(ebond, s_red);
+    const double v3 = block_sum<kForceThreads>(eangle, s_red);
     if (tid == 0) {
       W.epart[4 * (size_t)b + 0] = v0;
       W.epart[4 * (size_t)b + 1] = v1;
@@ -417,8 +426,8 @@ __global__ void k_native_map(const float *__restrict__ xf, int ns, int min_sep, 
 static inline int xcd_grid(int nb) { return 8 * ((nb + 7) / 8); }
 
 size_t force_lds_bytes(const vp_system *s) {
-  size_t stage = sizeof(int4) * (size_t)(s->stage_cap_max + 1);
-  size_t red = sizeof(float) * 3 * kBlock;
+  size_t stage = sizeof(int4) * ((size_t)(s->stage_cap_max + 1) + (size_t)(s->ntypes_max + 1));
+  size_t red = sizeof(float) * 3 * kForceThreads;
   return stage > red ? stage : red;
 }
 
@@ -431,12 +440,15 @@ void launch_native_map(const float *xf, int ns, int min_sep, float r0, float rs,
 
 void launch_forces(vp_system *s, Work &W, bool energy, hipStream_t st) {
   size_t lds = force_lds_bytes(s);
+  const int slots = s->stage_cap_max + 1;
   if (energy)
-    hipLaunchKernelGGL(k_forces<true>, dim3(xcd_grid(s->n_blocks)), dim3(kBlock), lds, st, s->info,
-                       W, s->tile_rep, s->tile_first, s->n_blocks, s->types, s->bt_start, s->bterms);
+    hipLaunchKernelGGL(k_forces<true>, dim3(xcd_grid(s->n_blocks)), dim3(kForceThreads), lds, st, s->info,
+                       W, s->tile_rep, s->tile_first, s->n_blocks, s->types, s->bt_start, s->bterms,
+                       slots);
   else
-    hipLaunchKernelGGL(k_forces<false>, dim3(xcd_grid(s->n_blocks)), dim3(kBlock), lds, st, s->info,
-                       W, s->tile_rep, s->tile_first, s->n_blocks, s->types, s->bt_start, s->bterms);
+    hipLaunchKernelGGL(k_forces<false>, dim3(xcd_grid(s->n_blocks)), dim3(kForceThreads), lds, st, s->info,
+                       W, s->tile_rep, s->tile_first, s->n_blocks, s->types, s->bt_start, s->bterms,
+                       slots);
 }
 
 void launch_cv(vp_system *s, Work &W, int inc_step, hipStream_t st) {

@@ -3,10 +3,12 @@
 // Coordinates are 32-bit fixed point (unit 2^-24 nm), so image shifts by the
 // box edge are exact integer additions.  The trajectory state is kept sorted
 // along serpentine xy columns, z inside a column, so 64 consecutive slots form
-// a compact block.  A rebuild (first step, largest displacement since the last
-// build reaching half the skin, or nstlist_max steps) is decided on the
-// device, so the kernels of a captured step graph run every step and return
-// at once for replicas that keep their lists.
+// a compact block.  A rebuild (creation, every step whose count n + 1 is a
+// multiple of nstlist -- the same steps in every replica, so that rebuilding
+// replicas share launches -- or a largest displacement since the last build
+// reaching half the skin) is decided on the device, so the kernels of a
+// captured step graph run every step and return at once for replicas that
+// keep their lists.
 //
 //   k_bin      one workgroup per replica: periodic image, column and fine cell
 //              of every atom, counting sorts whose in-bucket order is fixed by
@@ -71,22 +73,26 @@ __device__ __forceinline__ void block_scan(const int *cnt, int *start, int count
 // Sort order: xy columns (~0.8 nm) visited in a serpentine, atoms of a column
 // by z (ascending in even, descending in odd columns) and then by user index,
 // so consecutive slots are spatial neighbours and 64 of them form a compact
-// block.  A second index lists the slots of every fine cell (~0.45 nm) in
-// ascending order for the candidate search of the list build.  Both orders
-// are fixed by keys, not by the order of atomic operations.
+// block.  The sort is a counting sort over (column, z slab) buckets, whose
+// order agrees with the z key, followed by a rank by (z key, user index)
+// inside each bucket (a few atoms).  A second index lists the slots of every
+// fine cell (~0.45 nm) in ascending order for the candidate search of the
+// list build.  Both orders are fixed by keys, not by the order of atomic
+// operations.
 // MODE 0: trajectory (old sorted order, device decides whether to rebuild);
 // MODE 1: evaluation from user-order FP32 positions x_user (always rebuilds).
 template <int MODE>
 __global__ __launch_bounds__(kBinThreads) void k_bin(const RepInfo *__restrict__ info,
                                                      RepState *__restrict__ state, Work W,
                                                      const float *__restrict__ x_user,
-                                                     int32_t *__restrict__ colid_t,
+                                                     int32_t *__restrict__ bkt_t,
                                                      int32_t *__restrict__ zkey_t,
                                                      int32_t *__restrict__ fcell_t,
                                                      int32_t *__restrict__ bucket_t,
                                                      int32_t *__restrict__ bkey_t,
                                                      int32_t *__restrict__ borig_t,
                                                      int32_t *__restrict__ orig_t,
+                                                     int32_t *__restrict__ cellpos_t,
                                                      const long long *__restrict__ step) {
   const int r = blockIdx.x;
   const RepInfo R = info[r];
@@ -101,7 +107,7 @@ __global__ __launch_bounds__(kBinThreads) void k_bin(const RepInfo *__restrict__
       RepState &S = state[r];
       long long n = *step;
       float md = __uint_as_float(S.maxdisp_bits);
-      need = S.force_rebuild || (md >= R.half_skin_margin) || (n - S.last_build >= R.nstlist_max);
+      need = S.force_rebuild || (md >= R.half_skin_margin) || ((n + 1) % R.nstlist == 0);
       S.rebuild = need;
       S.maxdisp_bits = 0u;
       if (need) {
@@ -114,8 +120,9 @@ __global__ __launch_bounds__(kBinThreads) void k_bin(const RepInfo *__restrict__
     }
     s_need = need;
   }
-  const int ncols = R.ncol[0] * R.ncol[1];
-  for (int c = tid; c < ncols; c += kBinThreads) s_cnt[c] = 0;
+  const int nzb = R.nzb;
+  const int nbk = R.ncol[0] * R.ncol[1] * nzb;  // <= kMaxCells (checked at creation)
+  for (int c = tid; c < nbk; c += kBinThreads) s_cnt[c] = 0;
   __syncthreads();
   if (!s_need) return;
   const int off = R.off;
@@ -138,39 +145,44 @@ __global__ __launch_bounds__(kBinThreads) void k_bin(const RepInfo *__restrict__
     cx = min(cx, R.ncol[0] - 1);
     cy = min(cy, R.ncol[1] - 1);
     const int col = cy * R.ncol[0] + ((cy & 1) ? R.ncol[0] - 1 - cx : cx);
+    // z key: ascending z in even columns, descending in odd ones; the slab
+    // index is a nondecreasing function of the key
+    const long long zk = (col & 1) ? (long long)R.Lq[2] - 1 - wz : wz;
+    const int zb = min(nzb - 1, (int)((zk * nzb) / R.Lq[2]));
     int fx = (int)((wx * R.nc[0]) / R.Lq[0]), fy = (int)((wy * R.nc[1]) / R.Lq[1]),
         fz = (int)((wz * R.nc[2]) / R.Lq[2]);
     fx = min(fx, R.nc[0] - 1);
     fy = min(fy, R.nc[1] - 1);
     fz = min(fz, R.nc[2] - 1);
-    colid_t[off + p] = col;
+    const int bk = col * nzb + zb;
+    bkt_t[off + p] = bk;
     zkey_t[off + p] = (col & 1) ? -(int)wz : (int)wz;
     fcell_t[off + p] = (fz * R.nc[1] + fy) * R.nc[0] + fx;
-    atomicAdd(&s_cnt[col], 1);
+    atomicAdd(&s_cnt[bk], 1);
   }
   __syncthreads();
-  block_scan(s_cnt, s_start, ncols, R.n, s_wsum);
-  for (int c = tid; c < ncols; c += kBinThreads) s_cnt[c] = s_start[c];
+  block_scan(s_cnt, s_start, nbk, R.n, s_wsum);
+  for (int c = tid; c < nbk; c += kBinThreads) s_cnt[c] = s_start[c];
   __syncthreads();
   for (int p = tid; p < R.n; p += kBinThreads) {
-    const int col = colid_t[off + p];
-    const int pos = atomicAdd(&s_cnt[col], 1);
+    const int bk = bkt_t[off + p];
+    const int pos = atomicAdd(&s_cnt[bk], 1);
     bucket_t[off + pos] = p;
     bkey_t[off + pos] = zkey_t[off + p];
     borig_t[off + pos] = (MODE == 0) ? W.orig[off + p] : p;
   }
   __syncthreads();
-  // ---- rank inside a column by (z key, user index)
+  // ---- rank inside a bucket by (z key, user index)
   for (int s = tid; s < R.n; s += kBinThreads) {
     const int p = bucket_t[off + s];
-    const int col = colid_t[off + p];
+    const int bk = bkt_t[off + p];
     const int key = bkey_t[off + s], me = borig_t[off + s];
     int rank = 0;
-    for (int q = s_start[col]; q < s_start[col + 1]; ++q) {
+    for (int q = s_start[bk]; q < s_start[bk + 1]; ++q) {
       const int kq = bkey_t[off + q];
       rank += (kq < key) || (kq == key && borig_t[off + q] < me);
     }
-    const int ns = s_start[col] + rank;
+    const int ns = s_start[bk] + rank;
     orig_t[off + ns] = me;
     W.cell_of[off + ns] = fcell_t[off + p];
   }
@@ -195,11 +207,13 @@ __global__ __launch_bounds__(kBinThreads) void k_bin(const RepInfo *__restrict__
     int rank = 0;
     for (int t = s_start[c]; t < s_start[c + 1]; ++t) rank += (bucket_t[off + t] < s);
     W.cell_slots[off + s_start[c] + rank] = s;
+    cellpos_t[off + s] = s_start[c] + rank;
   }
 }
 
 // New slot -> source (old slot through the old inverse map, or user index);
-// also records the atom's periodic image at this build.
+// also records the atom's periodic image at this build and writes its wrapped
+// position, user index, slot and image in fine-cell order.
 template <int MODE>
 __global__ __launch_bounds__(kBlock) void k_permute(const RepInfo *__restrict__ info,
                                                     const RepState *__restrict__ state, Work W,
@@ -210,7 +224,10 @@ __global__ __launch_bounds__(kBlock) void k_permute(const RepInfo *__restrict__ 
                                                     const int32_t *__restrict__ orig_t,
                                                     int4 *__restrict__ xq_t,
                                                     float4 *__restrict__ vel_t,
-                                                    int32_t *__restrict__ wrap_t) {
+                                                    int32_t *__restrict__ wrap_t,
+                                                    const int32_t *__restrict__ cellpos_t,
+                                                    int4 *__restrict__ cellx_t,
+                                                    int2 *__restrict__ celljw_t) {
   int tile = xcd_tile(blockIdx.x, ntiles);
   if (tile < 0) return;
   const int r = tile_rep[tile];
@@ -233,7 +250,12 @@ __global__ __launch_bounds__(kBlock) void k_permute(const RepInfo *__restrict__ 
   xq_t[slot] = x;
   int kx = (int)floordiv(x.x, R.Lq[0]), ky = (int)floordiv(x.y, R.Lq[1]),
       kz = (int)floordiv(x.z, R.Lq[2]);
-  wrap_t[slot] = pack_wrap(kx, ky, kz);
+  const int wr = pack_wrap(kx, ky, kz);
+  wrap_t[slot] = wr;
+  // the same atom in fine-cell order (wrapped position) for the candidate search
+  const int q = R.off + cellpos_t[slot];
+  cellx_t[q] = make_int4(x.x - kx * R.Lq[0], x.y - ky * R.Lq[1], x.z - kz * R.Lq[2], a);
+  celljw_t[q] = make_int2(p, wr);
 }
 
 __device__ __forceinline__ int wave_min_i(int v) {
@@ -247,6 +269,35 @@ __device__ __forceinline__ int wave_max_i(int v) {
   return v;
 }
 
+// Append one 16-bit staging index to a lane's pending group of 8 list
+// entries (four 32-bit words); a full group is stored as one 16-byte write.
+__device__ __forceinline__ void list_push(uint32_t v, int cnt, uint32_t &w0, uint32_t &w1,
+                                          uint32_t &w2, uint32_t &w3, uint16_t *lst, int lane) {
+  const uint32_t add = v << (16 * (cnt & 1));
+  const int w = (cnt >> 1) & 3;
+  w0 |= (w == 0) ? add : 0u;
+  w1 |= (w == 1) ? add : 0u;
+  w2 |= (w == 2) ? add : 0u;
+  w3 |= (w == 3) ? add : 0u;
+  if ((cnt & 7) == 7) {
+    *reinterpret_cast<uint4 *>(lst + ((size_t)(cnt >> 3) * kBlk + lane) * 8) = make_uint4(w0, w1, w2, w3);
+    w0 = w1 = w2 = w3 = 0u;
+  }
+}
+
+// One wave per block of 64 sorted atoms.  The cells that can hold a neighbour
+// of the block (fine cells within the list radius of the block's bounding
+// box, with their periodic images) are visited row by row; the cells of one
+// row that share an image are consecutive, so their atoms form one range of
+// the fine-cell ordered copy of the positions.  Each range is read 64
+// candidates at a time (one coalesced load per lane): every lane applies the
+// cell's image to its candidate and keeps it if it lies within the list
+// radius of the bounding box; the kept candidates are compacted into LDS in
+// range order and then tested by all 64 lanes, one candidate per iteration,
+// against the lanes' own atoms.  A candidate within the list radius of at
+// least one atom (exclusions removed) gets the next staging index and the
+// lanes' lists receive that index; the staging entries (slot | image shift)
+// of a batch are stored together after it.
 template <int MODE>
 __global__ __launch_bounds__(kBlk) void k_list(const RepInfo *__restrict__ info,
                                                RepState *__restrict__ state, Work W,
@@ -256,9 +307,13 @@ __global__ __launch_bounds__(kBlk) void k_list(const RepInfo *__restrict__ info,
                                                const float4 *__restrict__ vel_t,
                                                const int32_t *__restrict__ orig_t,
                                                const int32_t *__restrict__ wrap_t,
+                                               const int4 *__restrict__ cellx_t,
+                                               const int2 *__restrict__ celljw_t,
                                                const int32_t *__restrict__ ex_start,
                                                const int32_t *__restrict__ ex_list,
                                                const float4 *__restrict__ integ0) {
+  __shared__ int4 s_pos[kBlk];  // kept candidates: shifted position, user index
+  __shared__ int s_cidx[3][18];  // fine-cell edges of the replica
   const int b = xcd_tile(blockIdx.x, nblk);
   if (b < 0) return;
   const int tile = b / (kTile / kBlk);
@@ -275,99 +330,179 @@ __global__ __launch_bounds__(kBlk) void k_list(const RepInfo *__restrict__ info,
     if (lane == 0) W.stage_n[b] = 0;
     return;
   }
+  const int off = R.off;
   const int Lx = R.Lq[0], Ly = R.Lq[1], Lz = R.Lq[2];
+  const int ncx = R.nc[0], ncy = R.nc[1], ncz = R.nc[2];
+  if (lane < 3 * 17) s_cidx[lane / 17][lane % 17] = R.cedge[lane / 17][lane % 17];
+  // the lane's atom; an inactive lane sits far away and never matches
   int4 xi = make_int4(0, 0, 0, 0);
-  int wx = 0, wy = 0, wz = 0, a = -1, e0 = 0, e1 = 0;
-  if (active) {
-    xi = xq_t[slot];
-    const int wr = wrap_t[slot];
-    wx = xi.x - unpack_wrap(wr, 0) * Lx;
-    wy = xi.y - unpack_wrap(wr, 1) * Ly;
-    wz = xi.z - unpack_wrap(wr, 2) * Lz;
-    a = orig_t[slot];
-    e0 = ex_start[R.uoff + a];
-    e1 = ex_start[R.uoff + a + 1];
+  int wx = kDummyCoord, wy = kDummyCoord, wz = kDummyCoord, a = -(1 << 20), e0 = 0, e1 = 0;
+  // exclusions of the lane's atom: user-index offsets in [-32, 31] as a bit
+  // mask (offset 0 is the atom itself), any others checked against the list
+  uint64_t exm = 0;
+  bool exfar = false;
+  int bx0 = 0, bx1 = 0, by0 = 0, by1 = 0, bz0 = 0, bz1 = 0;
+  {
+    int ax = 0, ay = 0, az = 0;
+    if (active) {
+      xi = xq_t[slot];
+      const int wr = wrap_t[slot];
+      ax = wx = xi.x - unpack_wrap(wr, 0) * Lx;
+      ay = wy = xi.y - unpack_wrap(wr, 1) * Ly;
+      az = wz = xi.z - unpack_wrap(wr, 2) * Lz;
+      a = orig_t[slot];
+      e0 = ex_start[R.uoff + a];
+      e1 = ex_start[R.uoff + a + 1];
+      exm = 1ull << 32;
+      for (int e = e0; e < e1; ++e) {
+        const int d = ex_list[e] - a;
+        if (d >= -32 && d < 32) exm |= 1ull << (d + 32);
+        else exfar = true;
+      }
+    }
+    // bounding box of the block (wrapped frame)
+    const int big = 0x7fffffff;
+    bx0 = wave_min_i(active ? ax : big);
+    bx1 = wave_max_i(active ? ax : -big);
+    by0 = wave_min_i(active ? ay : big);
+    by1 = wave_max_i(active ? ay : -big);
+    bz0 = wave_min_i(active ? az : big);
+    bz1 = wave_max_i(active ? az : -big);
   }
-  // bounding box of the block (wrapped frame)
-  const int big = 0x7fffffff;
-  const int bx0 = wave_min_i(active ? wx : big), bx1 = wave_max_i(active ? wx : -big);
-  const int by0 = wave_min_i(active ? wy : big), by1 = wave_max_i(active ? wy : -big);
-  const int bz0 = wave_min_i(active ? wz : big), bz1 = wave_max_i(active ? wz : -big);
+  const bool anyfar = __ballot(exfar) != 0ull;
   const long long rl = R.rlq;
-  const int ux0 = (int)floordiv(((long long)bx0 - rl) * R.nc[0], Lx);
-  const int ux1 = (int)floordiv(((long long)bx1 + rl) * R.nc[0], Lx);
-  const int uy0 = (int)floordiv(((long long)by0 - rl) * R.nc[1], Ly);
-  const int uy1 = (int)floordiv(((long long)by1 + rl) * R.nc[1], Ly);
-  const int uz0 = (int)floordiv(((long long)bz0 - rl) * R.nc[2], Lz);
-  const int uz1 = (int)floordiv(((long long)bz1 + rl) * R.nc[2], Lz);
+  // cell ranges (unfolded: u = image * nc + cell)
+  const int ux0 = (int)floordiv(((long long)bx0 - rl) * ncx, Lx);
+  const int ux1 = (int)floordiv(((long long)bx1 + rl) * ncx, Lx);
+  const int uy0 = (int)floordiv(((long long)by0 - rl) * ncy, Ly);
+  const int uy1 = (int)floordiv(((long long)by1 + rl) * ncy, Ly);
+  const int uz0 = (int)floordiv(((long long)bz0 - rl) * ncz, Lz);
+  const int uz1 = (int)floordiv(((long long)bz1 + rl) * ncz, Lz);
   const double rl2d = (double)rl * (double)rl;
+  const float rl2 = R.rl2q;
   const int lb = b - R.blk0;
   uint16_t *lst = W.nblist + R.list_off + (int64_t)lb * R.maxnb * kBlk;
   uint32_t *stg = W.stage + (int64_t)b * kMaxStage;
   const int cap = R.stage_cap, maxnb = R.maxnb;
+  const int *cstart = W.cell_start + R.cell0;
   int nst = 0, cnt = 0;
+  uint32_t w0 = 0u, w1 = 0u, w2 = 0u, w3 = 0u;
   bool bad = false;
+  __syncthreads();  // cell edges in LDS
+  // unfolded cell u = i nc + c (image i, cell c); its lower edge is i L + edge[c]
+  int iz = uz0 >= 0 ? uz0 / ncz : -((-uz0 + ncz - 1) / ncz);
+  int cz = uz0 - iz * ncz;
   for (int uz = uz0; uz <= uz1; ++uz) {
-    const int iz = (int)floordiv(uz, R.nc[2]);
-    const int cz = uz - iz * R.nc[2];
     // gap between the cell's slab and the block box along z (coordinate units)
-    const long long zl = floordiv((long long)uz * Lz, R.nc[2]), zh = floordiv((long long)(uz + 1) * Lz, R.nc[2]);
+    const long long zl = (long long)iz * Lz + s_cidx[2][cz], zh = (long long)iz * Lz + s_cidx[2][cz + 1];
     const double gz = (double)max(0ll, max(zl - bz1, (long long)bz0 - zh));
+    int iy = uy0 >= 0 ? uy0 / ncy : -((-uy0 + ncy - 1) / ncy);
+    int cy = uy0 - iy * ncy;
     for (int uy = uy0; uy <= uy1; ++uy) {
-      const int iy = (int)floordiv(uy, R.nc[1]);
-      const int cy = uy - iy * R.nc[1];
-      const long long yl = floordiv((long long)uy * Ly, R.nc[1]), yh = floordiv((long long)(uy + 1) * Ly, R.nc[1]);
+      const long long yl = (long long)iy * Ly + s_cidx[1][cy], yh = (long long)iy * Ly + s_cidx[1][cy + 1];
       const double gy = (double)max(0ll, max(yl - by1, (long long)by0 - yh));
-      if (gz * gz + gy * gy > rl2d) continue;
-      for (int ux = ux0; ux <= ux1; ++ux) {
-        const int ix = (int)floordiv(ux, R.nc[0]);
-        const int cx = ux - ix * R.nc[0];
-        const long long xl = floordiv((long long)ux * Lx, R.nc[0]), xh = floordiv((long long)(ux + 1) * Lx, R.nc[0]);
-        const double gx = (double)max(0ll, max(xl - bx1, (long long)bx0 - xh));
-        if (gz * gz + gy * gy + gx * gx > rl2d) continue;
-        const int cell = (cz * R.nc[1] + cy) * R.nc[0] + cx;
-        const int q0 = W.cell_start[R.cell0 + cell], q1 = W.cell_start[R.cell0 + cell + 1];
-        const bool self_image = (ix == 0 && iy == 0 && iz == 0);
-        for (int q = q0; q < q1; ++q) {
-          const int j = W.cell_slots[R.off + q];
-          const int4 xj = xq_t[R.off + j];
-          const int wj = wrap_t[R.off + j];
-          const int sx = ix - unpack_wrap(wj, 0), sy = iy - unpack_wrap(wj, 1),
-                    sz = iz - unpack_wrap(wj, 2);
-          const int px = xj.x + sx * Lx, py = xj.y + sy * Ly, pz = xj.z + sz * Lz;
-          const float dx = (float)(px - wx), dy = (float)(py - wy), dz = (float)(pz - wz);
-          bool in = active && (qr2(dx, dy, dz) < R.rl2q) && !(self_image && j == p);
-          if (in) {
-            const int oj = orig_t[R.off + j];
-            for (int e = e0; e < e1; ++e) in = in && (ex_list[e] != oj);
+      const double gyz = gz * gz + gy * gy;
+      if (gyz <= rl2d) {
+        int ix = ux0 >= 0 ? ux0 / ncx : -((-ux0 + ncx - 1) / ncx);
+        int cx = ux0 - ix * ncx;
+        int ux = ux0;
+        while (ux <= ux1) {
+          // the next run of cells of this row that pass the gap test and share an image
+          const long long xl = (long long)ix * Lx + s_cidx[0][cx], xh = (long long)ix * Lx + s_cidx[0][cx + 1];
+          const double gx = (double)max(0ll, max(xl - bx1, (long long)bx0 - xh));
+          if (gyz + gx * gx > rl2d) {
+            ++ux;
+            if (++cx == ncx) { cx = 0; ++ix; }
+            continue;
           }
-          if (__ballot(in)) {
-            if (nst < cap) {
-              if (lane == 0)
-                stg[nst] = (uint32_t)j | ((uint32_t)((sx + 16) & 31) << 16) |
-                           ((uint32_t)((sy + 16) & 31) << 21) | ((uint32_t)((sz + 16) & 31) << 26);
-              if (in) {
-                if (cnt < maxnb) lst[(((cnt >> 3) * kBlk) + lane) * 8 + (cnt & 7)] = (uint16_t)nst;
-                ++cnt;  // entries past maxnb are counted only to flag the overflow
+          int ce = cx;  // last cell of the run
+          while (ux + (ce - cx) + 1 <= ux1 && ce + 1 < ncx) {
+            // cells to the right only grow apart from the box
+            const double gx2 = (double)max(0ll, (long long)ix * Lx + s_cidx[0][ce + 1] - (long long)bx1);
+            if (gyz + gx2 * gx2 > rl2d) break;
+            ++ce;
+          }
+          const int c0 = (cz * ncy + cy) * ncx + cx;
+          const int q0 = cstart[c0], q1 = cstart[c0 + (ce - cx) + 1];
+          const int six = ix, siy = iy, siz = iz;
+          ux += ce - cx + 1;
+          cx = ce + 1;
+          if (cx == ncx) { cx = 0; ++ix; }
+          for (int qb = q0; qb < q1; qb += kBlk) {
+            // ---- load 64 candidates, keep those within the list radius of the box
+            const int q = qb + lane;
+            bool keep = false;
+            int4 cpos = make_int4(0, 0, 0, 0);
+            uint32_t code = 0u;
+            if (q < q1) {
+              const int4 cxq = cellx_t[off + q];
+              const int2 jw = celljw_t[off + q];
+              const int px = cxq.x + six * Lx, py = cxq.y + siy * Ly, pz = cxq.z + siz * Lz;
+              const float gxq = (float)max(0, max(bx0 - px, px - bx1));
+              const float gyq = (float)max(0, max(by0 - py, py - by1));
+              const float gzq = (float)max(0, max(bz0 - pz, pz - bz1));
+              // the box distance never exceeds an atom distance, also after rounding
+              keep = qr2(gxq, gyq, gzq) < rl2;
+              const int sx = six - unpack_wrap(jw.y, 0), sy = siy - unpack_wrap(jw.y, 1),
+                        sz = siz - unpack_wrap(jw.y, 2);
+              if (keep && (sx < -16 || sx > 15 || sy < -16 || sy > 15 || sz < -16 || sz > 15)) {
+                bad = true;  // shift not representable: the replica is flagged
+                keep = false;
               }
-              ++nst;
-            } else {
-              bad = true;  // staging full: the candidate is dropped and the replica flagged
+              cpos = make_int4(px, py, pz, cxq.w);
+              code = (uint32_t)jw.x | ((uint32_t)((sx + 16) & 31) << 16) |
+                     ((uint32_t)((sy + 16) & 31) << 21) | ((uint32_t)((sz + 16) & 31) << 26);
             }
-            bad = bad || (sx < -16 || sx > 15 || sy < -16 || sy > 15 || sz < -16 || sz > 15);
+            const uint64_t km = __ballot(keep);
+            const int at = __popcll(km & ((1ull << lane) - 1ull));
+            if (keep) s_pos[at] = cpos;
+            const int nk = __popcll(km);
+            __syncthreads();
+            // ---- every kept candidate against the 64 atoms of the block
+            const int nst0 = nst;
+            uint64_t acc = 0ull;  // kept candidates that received a staging index
+            for (int k = 0; k < nk; ++k) {
+              const int4 c = s_pos[k];
+              const float dx = (float)(c.x - wx), dy = (float)(c.y - wy), dz = (float)(c.z - wz);
+              const int d = c.w - a + 32;
+              const bool win = (unsigned)d < 64u;
+              const bool exw = win && ((exm >> (d & 63)) & 1ull);
+              bool in = (qr2(dx, dy, dz) < rl2) && !exw;
+              if (anyfar && __ballot(in && !win && exfar)) {
+                if (in && !win && exfar)
+                  for (int e = e0; e < e1; ++e) in = in && (ex_list[e] != c.w);
+              }
+              if (__ballot(in)) {
+                if (nst < cap) {
+                  if (in) {
+                    if (cnt < maxnb) list_push((uint32_t)nst, cnt, w0, w1, w2, w3, lst, lane);
+                    ++cnt;  // entries past maxnb are counted only to flag the overflow
+                  }
+                  acc |= 1ull << k;
+                  ++nst;
+                } else {
+                  bad = true;  // staging full: the candidate is dropped and the replica flagged
+                }
+              }
+            }
+            // staging entries of this batch, in candidate order
+            if (keep && ((acc >> at) & 1ull))
+              stg[nst0 + __popcll(acc & ((1ull << at) - 1ull))] = code;
+            __syncthreads();
           }
         }
       }
+      if (++cy == ncy) { cy = 0; ++iy; }
     }
+    if (++cz == ncz) { cz = 0; ++iz; }
   }
   if (cnt > maxnb - 8) {
     bad = true;
     cnt = maxnb - 8;
-  }
-  if (active) {
+  } else if (active) {
     // pad to a multiple of 8 with the inert staging entry (index cap)
     while (cnt & 7) {
-      lst[(((cnt >> 3) * kBlk) + lane) * 8 + (cnt & 7)] = (uint16_t)cap;
+      list_push((uint32_t)cap, cnt, w0, w1, w2, w3, lst, lane);
       ++cnt;
     }
   }
@@ -441,23 +576,27 @@ void launch_rebuild(vp_system *s, Work &W, int mode, const float *x_user, hipStr
   if (mode == 0) {
     hipLaunchKernelGGL(k_bin<0>, dim3(s->R), dim3(kBinThreads), 0, st, s->info, s->state, W,
                        x_user, s->cellid_t, s->zkey_t, s->fcell_t, s->bucket_t, s->bkey_t,
-                       s->borig_t, s->orig_t, s->step);
+                       s->borig_t, s->orig_t, s->cellpos_t, s->step);
     hipLaunchKernelGGL(k_permute<0>, dim3(xcd_grid(s->n_tiles)), dim3(kBlock), 0, st, s->info,
                        s->state, W, s->tile_rep, s->tile_first, s->n_tiles, x_user, s->type0,
-                       s->orig_t, s->xq_t, s->vel_t, s->wrap_t);
+                       s->orig_t, s->xq_t, s->vel_t, s->wrap_t, s->cellpos_t, s->cellx_t,
+                       s->celljw_t);
     hipLaunchKernelGGL(k_list<0>, dim3(xcd_grid(s->n_blocks)), dim3(kBlk), 0, st, s->info,
                        s->state, W, s->tile_rep, s->tile_first, s->n_blocks, s->xq_t, s->vel_t,
-                       s->orig_t, s->wrap_t, s->ex_start, s->ex_list, s->integ0);
+                       s->orig_t, s->wrap_t, s->cellx_t, s->celljw_t, s->ex_start, s->ex_list,
+                       s->integ0);
   } else {
     hipLaunchKernelGGL(k_bin<1>, dim3(s->R), dim3(kBinThreads), 0, st, s->info, s->state, W,
                        x_user, s->cellid_t, s->zkey_t, s->fcell_t, s->bucket_t, s->bkey_t,
-                       s->borig_t, s->orig_t, s->step);
+                       s->borig_t, s->orig_t, s->cellpos_t, s->step);
     hipLaunchKernelGGL(k_permute<1>, dim3(xcd_grid(s->n_tiles)), dim3(kBlock), 0, st, s->info,
                        s->state, W, s->tile_rep, s->tile_first, s->n_tiles, x_user, s->type0,
-                       s->orig_t, s->xq_t, s->vel_t, s->wrap_t);
+                       s->orig_t, s->xq_t, s->vel_t, s->wrap_t, s->cellpos_t, s->cellx_t,
+                       s->celljw_t);
     hipLaunchKernelGGL(k_list<1>, dim3(xcd_grid(s->n_blocks)), dim3(kBlk), 0, st, s->info,
                        s->state, W, s->tile_rep, s->tile_first, s->n_blocks, s->xq_t, s->vel_t,
-                       s->orig_t, s->wrap_t, s->ex_start, s->ex_list, s->integ0);
+                       s->orig_t, s->wrap_t, s->cellx_t, s->celljw_t, s->ex_start, s->ex_list,
+                       s->integ0);
   }
 }
 

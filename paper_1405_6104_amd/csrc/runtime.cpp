@@ -66,7 +66,7 @@ vp_status validate(const vp_replica_desc &d, int r) {
   if (!d.mass || !d.gamma || !d.charge || !d.sigma || !d.epsilon || !d.x0)
     return bad("NULL per-atom array");
   for (int a = 0; a < 3; ++a)
-    if (!(d.box[a] > 0)) return bad("box edges must be positive");
+    if (!(d.box[a] > 0) || !(d.box[a] <= 30.0)) return bad("box edges must lie in (0, 30] nm");
   if (!(d.r_cut > 0)) return bad("r_cut must be positive");
   for (int a = 0; a < 3; ++a)
     if (!(d.r_cut < 0.5 * d.box[a])) return bad("r_cut must be below half the box");
@@ -205,8 +205,12 @@ static vp_status build(vp_system *s, const vp_replica_desc *reps, int32_t n_reps
       R.Ld[a] = d.box[a];
     }
     R.ncell = R.nc[0] * R.nc[1] * R.nc[2];
+    for (int a = 0; a < 3; ++a)
+      for (int k = 0; k <= R.nc[a]; ++k)
+        R.cedge[a][k] = (int32_t)(((int64_t)k * R.Lq[a]) / R.nc[a]);
     R.cell0 = (int32_t)cell0;
     for (int a = 0; a < 2; ++a) R.ncol[a] = std::max(1, std::min(16, (int)std::floor(d.box[a] / col_target)));
+    R.nzb = std::max(1, std::min(64, kMaxCells / (R.ncol[0] * R.ncol[1])));
     const double vol = d.box[0] * d.box[1] * d.box[2];
     const double rho = d.n_atoms / vol;
     const double expect = 4.0 / 3.0 * M_PI * rl * rl * rl * rho;
@@ -225,7 +229,7 @@ static vp_status build(vp_system *s, const vp_replica_desc *reps, int32_t n_reps
     stage_cap_max = std::max(stage_cap_max, cap);
     R.list_off = list_off;
     R.sol_off = (int32_t)sol_off;
-    R.nstlist_max = o.nstlist_max;
+    R.nstlist = o.nstlist;
     const double rcq = d.r_cut * kQ, rlq = rl * kQ;
     R.rc2q = (float)(rcq * rcq);
     R.rl2q = (float)(rlq * rlq);
@@ -314,7 +318,7 @@ static vp_status build(vp_system *s, const vp_replica_desc *reps, int32_t n_reps
   {
     // the force kernel's dynamic LDS (staged neighbourhood) plus its static
     // LDS stays within 64 KB per workgroup
-    size_t need = force_lds_bytes(s) + sizeof(double) * (kBlock / 64);
+    size_t need = force_lds_bytes(s) + sizeof(double) * (kForceThreads / 64);
     if (need > (size_t)kMaxLds)
       return fail(VP_ERR_ARG, "force kernel would need " + std::to_string(need) +
                                   " bytes of LDS per workgroup (limit " + std::to_string(kMaxLds) + ")");
@@ -425,6 +429,9 @@ static vp_status build(vp_system *s, const vp_replica_desc *reps, int32_t n_reps
   TRY(dalloc(s, &s->bucket_t, S));
   TRY(dalloc(s, &s->bkey_t, S));
   TRY(dalloc(s, &s->borig_t, S));
+  TRY(dalloc(s, &s->cellpos_t, S));
+  TRY(dalloc(s, &s->cellx_t, S));
+  TRY(dalloc(s, &s->celljw_t, S));
   TRY(dalloc(s, &s->step, 1));
   HIPCHECK(hipMemset(s->step, 0, sizeof(long long)));
   TRY(alloc_work(s, s->traj, true));
@@ -466,7 +473,7 @@ extern "C" vp_status vp_system_create(const vp_replica_desc *reps, int32_t n_rep
   if (!s) return fail(VP_ERR_NOMEM, "host allocation failed");
   vp_options o{};
   if (opt) o = *opt;
-  if (o.nstlist_max <= 0) o.nstlist_max = 100;
+  if (o.nstlist <= 0) o.nstlist = 4;
   if (!(o.skin > 0)) o.skin = 0.1;
   if (o.steps_per_graph <= 0) o.steps_per_graph = 20;
   if (!opt) o.use_graph = 1;

@@ -13,7 +13,8 @@ namespace vp {
 constexpr int kBlock = 256;          // threads per workgroup of the per-atom kernels
 constexpr int kTile = 256;           // slots per tile (a tile never crosses replicas)
 constexpr int kBlk = 64;             // atoms per neighbourhood block (one wave)
-constexpr int kParts = kBlock / kBlk;  // waves sharing one block in the force kernel
+constexpr int kParts = 8;            // waves sharing one block in the force kernel
+constexpr int kForceThreads = kParts * kBlk;
 constexpr int kBinThreads = 1024;    // workgroup of the binning kernel
 constexpr int kMaxCells = 4096;      // cells per replica held in LDS by the binning kernel
 constexpr int kMaxStage = 4093;      // staged neighbourhood atoms per block (LDS, + 1 inert entry)
@@ -41,6 +42,8 @@ struct RepInfo {
   int32_t bias, min_sep;
   int32_t nc[3], ncell, cell0;  // fine cell grid (candidate search) and offset into the cell arrays
   int32_t ncol[2];              // xy columns of the sort order
+  int32_t nzb;                  // z slabs per column in the sort's buckets
+  int32_t cedge[3][17];         // fine-cell edges floor(k Lq / nc), k = 0..nc
   int32_t Lq[3];                // box edges in coordinate units
   int32_t maxnb;                // per-atom list capacity (multiple of 8)
   int32_t stage_cap;            // staged atoms per block (<= kMaxStage)
@@ -49,7 +52,7 @@ struct RepInfo {
   int64_t cmap_off;             // first element of the native contact map (FP32 [ns][ns])
   int32_t cv_blocks;            // contact-map workgroups used by this replica
   int32_t sol_off;              // first index in per-solute arrays
-  int32_t nstlist_max;
+  int32_t nstlist;              // lists are rebuilt when (step + 1) % nstlist == 0
   float rc2q, rl2q;             // (rc/q)^2 and (rl/q)^2 in FP32
   float krf2q;                  // 2 k_rf q^3 (RF term in coordinate units)
   float half_skin_margin;       // displacement (nm) that forces a rebuild
@@ -155,12 +158,15 @@ struct vp_system {
   float4 *vel_t = nullptr;
   int32_t *orig_t = nullptr;
   int32_t *wrap_t = nullptr;
-  int32_t *cellid_t = nullptr;  // [slots] column of each old slot
+  int32_t *cellid_t = nullptr;  // [slots] sort bucket (column, z slab) of each old slot
   int32_t *zkey_t = nullptr;    // [slots] serpentine z key of each old slot
   int32_t *fcell_t = nullptr;   // [slots] fine cell of each old slot
   int32_t *bucket_t = nullptr;  // [slots] old slots grouped by column / new slots by cell
   int32_t *bkey_t = nullptr;    // [slots] z keys in bucket order
   int32_t *borig_t = nullptr;   // [slots] user indices in bucket order
+  int32_t *cellpos_t = nullptr; // [slots] position of each new slot in fine-cell order
+  int4 *cellx_t = nullptr;      // [slots] fine-cell order: wrapped x, y, z and user index
+  int2 *celljw_t = nullptr;     // [slots] fine-cell order: slot and packed image
   long long *step = nullptr;  // device step counter
   vp::Work traj, eval;
   bool eval_ready = false;

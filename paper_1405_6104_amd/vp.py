@@ -58,7 +58,7 @@ class ReplicaDesc(C.Structure):
 
 
 class Options(C.Structure):
-    _fields_ = [("nstlist_max", C.c_int32), ("skin", C.c_double), ("steps_per_graph", C.c_int32),
+    _fields_ = [("nstlist", C.c_int32), ("skin", C.c_double), ("steps_per_graph", C.c_int32),
                 ("use_graph", C.c_int32), ("max_neighbors", C.c_int32),
                 ("reserved", C.c_int32 * 7)]
 
@@ -159,12 +159,12 @@ def _desc(d, keep):
 class System:
     """A batch of trial trajectories (vp_system)."""
 
-    def __init__(self, reps, nstlist_max=0, skin=0.0, steps_per_graph=0, use_graph=True,
+    def __init__(self, reps, nstlist=0, skin=0.0, steps_per_graph=0, use_graph=True,
                  max_neighbors=0):
         keep = []
         descs = (ReplicaDesc * len(reps))(*[_desc(d, keep) for d in reps])
         opt = Options()
-        opt.nstlist_max, opt.skin, opt.steps_per_graph = nstlist_max, skin, steps_per_graph
+        opt.nstlist, opt.skin, opt.steps_per_graph = nstlist, skin, steps_per_graph
         opt.use_graph, opt.max_neighbors = int(bool(use_graph)), max_neighbors
         h = _vp()
         _check(_lib.vp_system_create(descs, len(reps), C.byref(opt), C.byref(h)))
