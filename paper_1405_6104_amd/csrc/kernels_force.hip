@@ -15,11 +15,12 @@
 // list order is fixed by the deterministic sort, so results do not depend on
 // scheduling.
 //
-// k_cv: collective variable z and dz/dx of the solute (contact map: several
-// workgroups per replica, each owning a range of solute rows; radius of
-// gyration, constant force and no bias: one workgroup), with per-workgroup
-// FP64 partial sums of z and of sum_i |dz/dx_i|^2/(gamma_i m_i) that the
-// consumers reduce in a fixed order.
+// k_cv_pairs / k_cv_reduce / k_cv: collective variable z and dz/dx of the
+// solute (contact map: one wave per 64 x 64 tile of solute pairs, then one
+// wave per row tile; radius of gyration, constant force and no bias: one
+// workgroup), with FP64 partial sums of z and of
+// sum_i |dz/dx_i|^2/(gamma_i m_i) per row tile that the consumers reduce in a
+// fixed order.
 #include "vp_device.h"
 #include "vp_launch.h"
 
@@ -230,8 +231,111 @@ __global__ __launch_bounds__(kForceThreads) void k_forces(const RepInfo *__restr
 // ---------------------------------------------------------------------------
 // collective variable of the bias
 // ---------------------------------------------------------------------------
+
+// Contact-map CV (supplement, "Collective coordinate"), one wave per tile of
+// 64 rows i x 64 columns j of one replica's solute:
+//   z = sum_{i<j, j-i>min_sep} (C~(r_ij) - C~f_ij)^2,
+//   dz/dx_i = -sum_j 2 (C~(r_ij) - C~f_ij) (dC~/dr)/r (x_j - x_i),
+// with C = (1+u+u^2)/(1+u+u^2+u^3+u^4), u = (r/r0)^2, times a quintic switch
+// from 1 at r_s to 0 at r_c.  Both orderings of a pair are visited, each
+// contributing to its own row's gradient; z takes the pairs j > i.  The
+// column-tile partials are reduced in a fixed order by k_cv_reduce.
+__global__ __launch_bounds__(kCvTile) void k_cv_pairs(const RepInfo *__restrict__ info, Work W,
+                                                      const float *__restrict__ cmap) {
+  __shared__ int4 s_x[kCvTile];
+  const int r = blockIdx.y;
+  const RepInfo &R = info[r];
+  if (R.bias != VP_BIAS_CONTACT && R.bias != VP_BIAS_RMD_CONTACT) return;
+  const int nt = R.cv_blocks;
+  if ((int)blockIdx.x >= nt * nt) return;
+  const int it = blockIdx.x / nt, jc = blockIdx.x % nt;
+  const int lane = threadIdx.x, ns = R.ns;
+  const int i = it * kCvTile + lane;
+  const int j0 = jc * kCvTile, jn = min(kCvTile, ns - j0);
+  if (lane < jn) s_x[lane] = W.xq[W.inv[R.uoff + j0 + lane]];
+  const bool row = i < ns;
+  const int4 xi = row ? W.xq[W.inv[R.uoff + i]] : make_int4(0, 0, 0, 0);
+  __syncthreads();
+  const float *cf = cmap + R.cmap_off + (int64_t)j0 * ns + (row ? i : 0);
+  const float ir02 = R.cinv_r02, iw = R.cinv_w, rs = R.crs, rs2 = R.crs2, rc2 = R.crc2;
+  const int msep = R.min_sep;
+  float gx = 0.0f, gy = 0.0f, gz = 0.0f;
+  double zacc = 0.0;
+  for (int k = 0; k < jn; ++k) {
+    const int j = j0 + k;
+    const int4 xj = s_x[k];
+    const float dx = (float)(xj.x - xi.x) * kInvQf, dy = (float)(xj.y - xi.y) * kInvQf,
+                dz = (float)(xj.z - xi.z) * kInvQf;
+    const float r2 = qr2(dx, dy, dz);
+    const float rinv = __builtin_amdgcn_rsqf(r2);
+    // C(u) and dC/du
+    const float u = r2 * ir02, u2 = u * u;
+    const float num = 1.0f + u + u2;
+    const float den = num + u2 * u + u2 * u2;
+    const float iden = __builtin_amdgcn_rcpf(den);
+    const float c = num * iden;
+    const float dnum = __builtin_fmaf(2.0f, u, 1.0f);
+    const float dden = dnum + u2 * __builtin_fmaf(4.0f, u, 3.0f);
+    const float dcdu = (dnum - c * dden) * iden;
+    // quintic switch on r
+    const float rr = r2 * rinv;
+    const float t = (rr - rs) * iw;
+    const float t2 = t * t;
+    const float swp = 1.0f - t2 * t * __builtin_fmaf(t, __builtin_fmaf(6.0f, t, -15.0f), 10.0f);
+    const float dswp = -30.0f * t2 * (1.0f - t) * (1.0f - t) * iw;
+    const bool inner = r2 <= rs2, outer = r2 >= rc2;
+    const float sw = inner ? 1.0f : (outer ? 0.0f : swp);
+    const float dsw = (inner || outer) ? 0.0f : dswp;
+    // C~ and (dC~/dr)/r
+    const float ct = c * sw;
+    const float dct_r = 2.0f * ir02 * dcdu * sw + c * dsw * rinv;
+    const bool valid = row && abs(j - i) > msep;
+    const float diff = ct - cf[(int64_t)k * ns];
+    const float coef = valid ? 2.0f * diff * dct_r : 0.0f;
+    gx = __builtin_fmaf(-coef, dx, gx);
+    gy = __builtin_fmaf(-coef, dy, gy);
+    gz = __builtin_fmaf(-coef, dz, gz);
+    if (valid && j > i) zacc += (double)diff * (double)diff;
+  }
+  W.gtile[(R.cvt_off + (int64_t)jc * nt + it) * kCvTile + lane] = make_float4(gx, gy, gz, 0.0f);
+  const double zs = wave_sum(zacc);
+  if (lane == 0) W.ztile[R.cvt_off + (int64_t)it * nt + jc] = zs;
+}
+
+// Row tile it of a contact-map replica: dz/dx_i summed over the column tiles
+// in order, sum_i |dz/dx_i|^2/(gamma_i m_i) and the tile's part of z.
+__global__ __launch_bounds__(kCvTile) void k_cv_reduce(const RepInfo *__restrict__ info, Work W,
+                                                       const double *__restrict__ igm0) {
+  const int r = blockIdx.y;
+  const RepInfo &R = info[r];
+  if (R.bias != VP_BIAS_CONTACT && R.bias != VP_BIAS_RMD_CONTACT) return;
+  const int nt = R.cv_blocks, it = blockIdx.x;
+  if (it >= nt) return;
+  const int lane = threadIdx.x, i = it * kCvTile + lane;
+  float gx = 0.0f, gy = 0.0f, gz = 0.0f;
+  for (int jc = 0; jc < nt; ++jc) {
+    const float4 g = W.gtile[(R.cvt_off + (int64_t)jc * nt + it) * kCvTile + lane];
+    gx += g.x;
+    gy += g.y;
+    gz += g.z;
+  }
+  double gq = 0.0;
+  if (i < R.ns) {
+    W.g[R.sol_off + i] = make_float4(gx, gy, gz, 0.0f);
+    gq = ((double)gx * gx + (double)gy * gy + (double)gz * gz) * igm0[R.uoff + i];
+  }
+  const double gs = wave_sum(gq);
+  if (lane == 0) {
+    double z = 0.0;
+    for (int jc = 0; jc < nt; ++jc) z += W.ztile[R.cvt_off + (int64_t)it * nt + jc];
+    W.zpart[(size_t)r * kMaxCvBlocks + it] = z;
+    W.gpart[(size_t)r * kMaxCvBlocks + it] = gs;
+  }
+}
+
+// The other CV kinds, one workgroup per replica: radius of gyration (FP64 on
+// unwrapped coordinates), constant force; also advances the step counter.
 __global__ __launch_bounds__(kCvBlock) void k_cv(const RepInfo *__restrict__ info, Work W,
-                                                 const float *__restrict__ cmap,
                                                  const double *__restrict__ igm0,
                                                  const double *__restrict__ mass0,
                                                  const float4 *__restrict__ cforce, int inc_step,
@@ -239,41 +343,13 @@ __global__ __launch_bounds__(kCvBlock) void k_cv(const RepInfo *__restrict__ inf
   extern __shared__ int4 s_x[];  // solute positions of this replica
   __shared__ double s_red[kCvBlock / 64];
   __shared__ double s_cm[5];
-  const int r = blockIdx.y, b = blockIdx.x;
+  const int r = blockIdx.x;
   const RepInfo &R = info[r];
   const int tid = threadIdx.x;
   const int ns = R.ns;
-  const bool contact = (R.bias == VP_BIAS_CONTACT || R.bias == VP_BIAS_RMD_CONTACT);
-  if (b < R.cv_blocks) {
+  if (R.bias == VP_BIAS_RG || R.bias == VP_BIAS_CONST || R.bias == VP_BIAS_NONE) {
     double zacc = 0.0, gq = 0.0;
-    if (contact) {
-      for (int a = tid; a < ns; a += kCvBlock) s_x[a] = W.xq[W.inv[R.uoff + a]];
-      __syncthreads();
-      const int i = b * kCvBlock + tid;
-      if (i < ns) {
-        const int4 xi = s_x[i];
-        const float *cf = cmap + R.cmap_off + i;
-        float gx = 0.0f, gy = 0.0f, gz = 0.0f;
-        const int msep = R.min_sep;
-        for (int j = 0; j < ns; ++j) {
-          if (abs(j - i) <= msep) continue;
-          const int4 xj = s_x[j];
-          const float dx = (float)(xj.x - xi.x) * kInvQf, dy = (float)(xj.y - xi.y) * kInvQf,
-                      dz = (float)(xj.z - xi.z) * kInvQf;
-          const float rr = sqrtf(qr2(dx, dy, dz));
-          float dc;
-          const float c = contact_value(rr, R.cr0, R.crs, R.crc, dc);
-          const float diff = c - cf[(int64_t)j * ns];
-          if (j > i) zacc += (double)diff * (double)diff;
-          const float coef = 2.0f * diff * dc / rr;  // dz/dr_ij / r_ij
-          gx = __builtin_fmaf(-coef, dx, gx);
-          gy = __builtin_fmaf(-coef, dy, gy);
-          gz = __builtin_fmaf(-coef, dz, gz);
-        }
-        W.g[R.sol_off + i] = make_float4(gx, gy, gz, 0.0f);
-        gq = ((double)gx * gx + (double)gy * gy + (double)gz * gz) * igm0[R.uoff + i];
-      }
-    } else if (R.bias == VP_BIAS_RG) {
+    if (R.bias == VP_BIAS_RG) {
       // mass-weighted radius of gyration on unwrapped coordinates (FP64)
       double m = 0.0, cx = 0.0, cy = 0.0, cz = 0.0;
       for (int a = tid; a < ns; a += kCvBlock) {
@@ -327,11 +403,11 @@ __global__ __launch_bounds__(kCvBlock) void k_cv(const RepInfo *__restrict__ inf
     const double zs = block_sum<kCvBlock>(zacc, s_red);
     const double gs = block_sum<kCvBlock>(gq, s_red);
     if (tid == 0) {
-      W.zpart[(size_t)r * kMaxCvBlocks + b] = zs;
-      W.gpart[(size_t)r * kMaxCvBlocks + b] = gs;
+      W.zpart[(size_t)r * kMaxCvBlocks] = zs;
+      W.gpart[(size_t)r * kMaxCvBlocks] = gs;
     }
   }
-  if (inc_step && r == 0 && b == 0 && tid == 0) *step += 1;
+  if (inc_step && r == 0 && tid == 0) *step += 1;
 }
 
 // replica scalars from the CV partials (fixed order)
@@ -452,14 +528,23 @@ void launch_forces(vp_system *s, Work &W, bool energy, hipStream_t st) {
 }
 
 void launch_cv(vp_system *s, Work &W, int inc_step, hipStream_t st) {
-  int gx = 1, nsmax = 1;
+  int nt = 0, nsmax = 1;
+  bool any_single = false;
   for (const RepInfo &R : s->info_h) {
-    gx = R.cv_blocks > gx ? R.cv_blocks : gx;
-    nsmax = R.ns > nsmax ? R.ns : nsmax;
+    if (R.bias == VP_BIAS_CONTACT || R.bias == VP_BIAS_RMD_CONTACT) {
+      nt = R.cv_blocks > nt ? R.cv_blocks : nt;
+    } else {
+      any_single = any_single || R.bias == VP_BIAS_RG;
+      if (R.bias == VP_BIAS_RG) nsmax = R.ns > nsmax ? R.ns : nsmax;
+    }
   }
-  size_t lds = sizeof(int4) * (size_t)nsmax;
-  hipLaunchKernelGGL(k_cv, dim3(gx, s->R), dim3(kCvBlock), lds, st, s->info, W, s->cmap, s->igm0,
-                     s->mass0, s->cforce, inc_step, s->step);
+  if (nt > 0) {
+    hipLaunchKernelGGL(k_cv_pairs, dim3(nt * nt, s->R), dim3(kCvTile), 0, st, s->info, W, s->cmap);
+    hipLaunchKernelGGL(k_cv_reduce, dim3(nt, s->R), dim3(kCvTile), 0, st, s->info, W, s->igm0);
+  }
+  size_t lds = any_single ? sizeof(int4) * (size_t)nsmax : 0;
+  hipLaunchKernelGGL(k_cv, dim3(s->R), dim3(kCvBlock), lds, st, s->info, W, s->igm0, s->mass0,
+                     s->cforce, inc_step, s->step);
 }
 
 void launch_force_out(vp_system *s, Work &W, double t, float *f_user, double *e_out,

@@ -94,7 +94,7 @@ vp_status validate(const vp_replica_desc &d, int r) {
   if (d.bias < VP_BIAS_NONE || d.bias > VP_BIAS_RMD_CONTACT) return bad("unknown bias kind");
   if ((d.bias == VP_BIAS_CONTACT || d.bias == VP_BIAS_RMD_CONTACT)) {
     if (!d.x_final) return bad("contact-map bias needs x_final");
-    if (d.n_solute > kMaxCvBlocks * kCvBlock) return bad("too many solute atoms for the contact map");
+    if (d.n_solute > kMaxCvBlocks * kCvTile) return bad("too many solute atoms for the contact map");
     if (!(d.contact_r0 > 0) || !(d.contact_rc > d.contact_rs) || d.contact_min_sep < 0)
       return bad("contact parameters");
   }
@@ -102,7 +102,8 @@ vp_status validate(const vp_replica_desc &d, int r) {
   if (d.bias != VP_BIAS_NONE && d.n_solute < 1) return bad("a bias needs at least one solute atom");
   if (d.bias == VP_BIAS_RG || d.bias == VP_BIAS_CONTACT || d.bias == VP_BIAS_RMD_CONTACT)
     if (!(d.bias_k >= 0) || !(d.ramp_rate >= 0)) return bad("bias_k and ramp_rate must be >= 0");
-  if (d.bias != VP_BIAS_NONE && d.n_solute > kMaxSoluteLds) return bad("too many solute atoms");
+  if (d.bias == VP_BIAS_RG && d.n_solute > kMaxSoluteLds)
+    return bad("the radius-of-gyration bias takes at most 4096 solute atoms");
   return VP_OK;
 }
 
@@ -129,6 +130,8 @@ static vp_status alloc_work(vp_system *s, Work &W, bool traj) {
   TRY(dalloc(s, &W.cell_slots, S));
   TRY(dalloc(s, &W.cell_of, S));
   TRY(dalloc(s, &W.g, (size_t)std::max<int64_t>(1, s->n_solute_total)));
+  TRY(dalloc(s, &W.gtile, (size_t)std::max<int64_t>(1, s->n_cv_tiles) * kCvTile));
+  TRY(dalloc(s, &W.ztile, (size_t)std::max<int64_t>(1, s->n_cv_tiles)));
   TRY(dalloc(s, &W.zpart, R * kMaxCvBlocks));
   TRY(dalloc(s, &W.gpart, R * kMaxCvBlocks));
   TRY(dalloc(s, &W.epart, 4 * B));
@@ -161,7 +164,7 @@ static vp_status build(vp_system *s, const vp_replica_desc *reps, int32_t n_reps
   const vp_options &o = s->opt;
   s->R = n_reps;
   s->info_h.resize(n_reps);
-  int64_t off = 0, uoff = 0, cell0 = 0, list_off = 0, sol_off = 0;
+  int64_t off = 0, uoff = 0, cell0 = 0, list_off = 0, sol_off = 0, cv_tiles = 0;
   int32_t tile0 = 0, type_off = 0;
   std::vector<int32_t> tile_rep, tile_first;
   std::vector<float4> types;
@@ -278,7 +281,13 @@ static vp_status build(vp_system *s, const vp_replica_desc *reps, int32_t n_reps
       ntypes_max = std::max(ntypes_max, R.ntypes);
     }
     const bool contact = d.bias == VP_BIAS_CONTACT || d.bias == VP_BIAS_RMD_CONTACT;
-    R.cv_blocks = contact ? std::max(1, (d.n_solute + kCvBlock - 1) / kCvBlock) : 1;
+    R.cv_blocks = contact ? std::max(1, (d.n_solute + kCvTile - 1) / kCvTile) : 1;
+    R.cvt_off = cv_tiles;
+    if (contact) cv_tiles += (int64_t)R.cv_blocks * R.cv_blocks;
+    R.cinv_r02 = (float)(1.0 / (d.contact_r0 * d.contact_r0));
+    R.cinv_w = (float)(1.0 / (d.contact_rc - d.contact_rs));
+    R.crs2 = (float)(d.contact_rs * d.contact_rs);
+    R.crc2 = (float)(d.contact_rc * d.contact_rc);
     R.cmap_off = 0;
     if (contact) {
       int found = -1;
@@ -311,6 +320,7 @@ static vp_status build(vp_system *s, const vp_replica_desc *reps, int32_t n_reps
   s->n_cells = cell0;
   s->list_elems = list_off;
   s->n_solute_total = sol_off;
+  s->n_cv_tiles = cv_tiles;
   s->n_tiles = tile0;
   s->n_blocks = tile0 * (kTile / kBlk);
   s->stage_cap_max = stage_cap_max;

@@ -21,9 +21,10 @@ constexpr int kMaxStage = 4093;      // staged neighbourhood atoms per block (LD
 constexpr int kMaxLds = 65536;       // LDS bytes per workgroup used by any kernel
 constexpr int kMaxCols = 256;        // xy columns per replica (sort order)
 constexpr int kMaxTypes = 1024;      // (charge, sigma, epsilon) classes per replica
-constexpr int kCvBlock = 256;        // solute atoms per contact-map workgroup
-constexpr int kMaxCvBlocks = 64;     // => at most 16384 solute atoms
-constexpr int kMaxSoluteLds = 8192;  // solute positions staged in LDS (dynamic)
+constexpr int kCvBlock = 256;        // workgroup of the single-workgroup CV kinds (Rg, constant)
+constexpr int kCvTile = 64;          // solute rows (and columns) of one contact-map tile
+constexpr int kMaxCvBlocks = 256;    // row tiles per replica => at most 16384 solute atoms
+constexpr int kMaxSoluteLds = 4096;  // solute positions staged in LDS by the Rg kernel
 constexpr double kFixScale = 4294967296.0;  // 2^32: fixed-point force unit
 constexpr double kForceLimit = 1.0e6;       // kJ/mol/nm: above this a replica is unstable
 constexpr double kCoulomb = 138.935458;
@@ -50,7 +51,10 @@ struct RepInfo {
   int32_t ntypes, type_off;     // type table (ntypes + 1 entries, last is inert)
   int64_t list_off;             // first element of this replica's list storage
   int64_t cmap_off;             // first element of the native contact map (FP32 [ns][ns])
-  int32_t cv_blocks;            // contact-map workgroups used by this replica
+  int32_t cv_blocks;            // contact map: row tiles (ceil(ns / 64)); other kinds: 1
+  int64_t cvt_off;              // first entry of this replica's contact-map tile partials
+  float cinv_r02, cinv_w;       // contact map: 1/r0^2, 1/(r_c - r_s) (nm)
+  float crs2, crc2;             // r_s^2, r_c^2 (nm^2)
   int32_t sol_off;              // first index in per-solute arrays
   int32_t nstlist;              // lists are rebuilt when (step + 1) % nstlist == 0
   float rc2q, rl2q;             // (rc/q)^2 and (rl/q)^2 in FP32
@@ -108,6 +112,8 @@ struct Work {
   int32_t *cell_slots = nullptr;  // [slots] slots of each fine cell, ascending
   int32_t *cell_of = nullptr;     // [slots] fine cell of each new slot
   float4 *g = nullptr;            // [solute total] dz/dx (xyz) of each solute atom
+  float4 *gtile = nullptr;        // contact map: dz/dx partials per (column tile, row tile, row)
+  double *ztile = nullptr;        // contact map: z partials per (row tile, column tile)
   double *zpart = nullptr;        // [R][kMaxCvBlocks]
   double *gpart = nullptr;        // [R][kMaxCvBlocks] sum |g|^2/(gamma m)
   double *epart = nullptr;        // [blocks][4] energy partials (LJ, RF, bond, angle)
@@ -134,6 +140,7 @@ struct vp_system {
   int64_t n_cells = 0;
   int64_t list_elems = 0;
   int64_t n_solute_total = 0;
+  int64_t n_cv_tiles = 0;  // sum over contact-map replicas of (row tiles)^2
   int32_t stage_cap_max = 0, ntypes_max = 0;
   vp_options opt{};
   std::vector<vp::RepInfo> info_h;
