@@ -268,21 +268,24 @@ __device__ __forceinline__ int wave_max_i(int v) {
   for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
   return v;
 }
+// minimum / maximum over the 16 lanes of a quarter wave
+__device__ __forceinline__ int quarter_min_i(int v) {
+#pragma unroll
+  for (int o = 8; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ __forceinline__ int quarter_max_i(int v) {
+#pragma unroll
+  for (int o = 8; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+  return v;
+}
 
-// Append one 16-bit staging index to a lane's pending group of 8 list
-// entries (four 32-bit words); a full group is stored as one 16-byte write.
-__device__ __forceinline__ void list_push(uint32_t v, int cnt, uint32_t &w0, uint32_t &w1,
-                                          uint32_t &w2, uint32_t &w3, uint16_t *lst, int lane) {
-  const uint32_t add = v << (16 * (cnt & 1));
-  const int w = (cnt >> 1) & 3;
-  w0 |= (w == 0) ? add : 0u;
-  w1 |= (w == 1) ? add : 0u;
-  w2 |= (w == 2) ? add : 0u;
-  w3 |= (w == 3) ? add : 0u;
-  if ((cnt & 7) == 7) {
-    *reinterpret_cast<uint4 *>(lst + ((size_t)(cnt >> 3) * kBlk + lane) * 8) = make_uint4(w0, w1, w2, w3);
-    w0 = w1 = w2 = w3 = 0u;
-  }
+// A lane's list entries are collected four at a time in a 64-bit shift
+// register and stored as one 8-byte write into the [chunk][lane][8] layout
+// (the order of the four entries inside a group is reversed, which only
+// changes the fixed order in which the force kernel visits them).
+__device__ __forceinline__ void list_store4(uint16_t *lst, int e0, int lane, uint64_t v) {
+  *reinterpret_cast<uint64_t *>(lst + ((size_t)(e0 >> 3) * kBlk + lane) * 8 + (e0 & 4)) = v;
 }
 
 // One wave per block of 64 sorted atoms.  The cells that can hold a neighbour
@@ -292,12 +295,15 @@ __device__ __forceinline__ void list_push(uint32_t v, int cnt, uint32_t &w0, uin
 // the fine-cell ordered copy of the positions.  Each range is read 64
 // candidates at a time (one coalesced load per lane): every lane applies the
 // cell's image to its candidate and keeps it if it lies within the list
-// radius of the bounding box; the kept candidates are compacted into LDS in
-// range order and then tested by all 64 lanes, one candidate per iteration,
-// against the lanes' own atoms.  A candidate within the list radius of at
-// least one atom (exclusions removed) gets the next staging index and the
-// lanes' lists receive that index; the staging entries (slot | image shift)
-// of a batch are stored together after it.
+// radius of the bounding box of one of the block's quarters (16 atoms).  Every kept candidate receives the next staging
+// index (its slot | image shift is stored) and its position is compacted into
+// LDS; then each lane tests the batch against its own atom, with no
+// communication between lanes, and appends the staging indices of the
+// candidates within the list radius (exclusions removed) to its list.  This
+// test runs in FP32 on coordinates relative to the block's corner, with the
+// radius enlarged by a bound on the rounding (a few units of 2^-24 nm): the
+// list is a superset of the exact list radius, and the force kernel applies
+// the exact cutoff.
 template <int MODE>
 __global__ __launch_bounds__(kBlk) void k_list(const RepInfo *__restrict__ info,
                                                RepState *__restrict__ state, Work W,
@@ -312,7 +318,7 @@ __global__ __launch_bounds__(kBlk) void k_list(const RepInfo *__restrict__ info,
                                                const int32_t *__restrict__ ex_start,
                                                const int32_t *__restrict__ ex_list,
                                                const float4 *__restrict__ integ0) {
-  __shared__ int4 s_pos[kBlk];  // kept candidates: shifted position, user index
+  __shared__ float4 s_pos[kBlk];  // kept candidates: position relative to the block, user index
   __shared__ int s_cidx[3][18];  // fine-cell edges of the replica
   const int b = xcd_tile(blockIdx.x, nblk);
   if (b < 0) return;
@@ -342,6 +348,8 @@ __global__ __launch_bounds__(kBlk) void k_list(const RepInfo *__restrict__ info,
   uint64_t exm = 0;
   bool exfar = false;
   int bx0 = 0, bx1 = 0, by0 = 0, by1 = 0, bz0 = 0, bz1 = 0;
+  int sb[4][6];      // quarter boxes: x0, x1, y0, y1, z0, z1
+  bool sbact[4];     // quarter has at least one atom
   {
     int ax = 0, ay = 0, az = 0;
     if (active) {
@@ -368,6 +376,21 @@ __global__ __launch_bounds__(kBlk) void k_list(const RepInfo *__restrict__ info,
     by1 = wave_max_i(active ? ay : -big);
     bz0 = wave_min_i(active ? az : big);
     bz1 = wave_max_i(active ? az : -big);
+    // bounding boxes of the four quarters (16 consecutive atoms each)
+    const int qx0 = quarter_min_i(active ? ax : big), qx1 = quarter_max_i(active ? ax : -big);
+    const int qy0 = quarter_min_i(active ? ay : big), qy1 = quarter_max_i(active ? ay : -big);
+    const int qz0 = quarter_min_i(active ? az : big), qz1 = quarter_max_i(active ? az : -big);
+    const bool qact = __ballot(active) & (0xffffull << (lane & 48));
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      sb[g][0] = __builtin_amdgcn_readlane(qx0, 16 * g);
+      sb[g][1] = __builtin_amdgcn_readlane(qx1, 16 * g);
+      sb[g][2] = __builtin_amdgcn_readlane(qy0, 16 * g);
+      sb[g][3] = __builtin_amdgcn_readlane(qy1, 16 * g);
+      sb[g][4] = __builtin_amdgcn_readlane(qz0, 16 * g);
+      sb[g][5] = __builtin_amdgcn_readlane(qz1, 16 * g);
+      sbact[g] = __builtin_amdgcn_readlane((int)qact, 16 * g) != 0;
+    }
   }
   const bool anyfar = __ballot(exfar) != 0ull;
   const long long rl = R.rlq;
@@ -380,13 +403,24 @@ __global__ __launch_bounds__(kBlk) void k_list(const RepInfo *__restrict__ info,
   const int uz1 = (int)floordiv(((long long)bz1 + rl) * ncz, Lz);
   const double rl2d = (double)rl * (double)rl;
   const float rl2 = R.rl2q;
+  // enlarged radius of the FP32 relative test: coordinates of kept candidates
+  // stay within M = block extent + rl of the corner, each FP32 rounding moves
+  // a coordinate by at most M 2^-24 and a separation by 2^-24 relative, so
+  // 8 + (4 M + 8 rl) 2^-24 units bound the change of a computed distance
+  const long long ext = max(bx1 - bx0, max(by1 - by0, bz1 - bz0));
+  const float rlx = (float)(rl + 8 + ((4 * (ext + rl) + 8 * rl) >> 24) + 1);
+  const float rl2x = rlx * rlx;
+  // the lane's atom relative to the block corner (inactive lanes far away)
+  const float ax = active ? (float)(wx - bx0) : 1.0e9f, ay = active ? (float)(wy - by0) : 1.0e9f,
+              az = active ? (float)(wz - bz0) : 1.0e9f;
+  const int a32 = a - 32;
   const int lb = b - R.blk0;
   uint16_t *lst = W.nblist + R.list_off + (int64_t)lb * R.maxnb * kBlk;
   uint32_t *stg = W.stage + (int64_t)b * kMaxStage;
   const int cap = R.stage_cap, maxnb = R.maxnb;
   const int *cstart = W.cell_start + R.cell0;
   int nst = 0, cnt = 0;
-  uint32_t w0 = 0u, w1 = 0u, w2 = 0u, w3 = 0u;
+  uint64_t pend = 0ull;  // pending list entries (up to four)
   bool bad = false;
   __syncthreads();  // cell edges in LDS
   // unfolded cell u = i nc + c (image i, cell c); its lower edge is i L + edge[c]
@@ -432,62 +466,76 @@ __global__ __launch_bounds__(kBlk) void k_list(const RepInfo *__restrict__ info,
             // ---- load 64 candidates, keep those within the list radius of the box
             const int q = qb + lane;
             bool keep = false;
-            int4 cpos = make_int4(0, 0, 0, 0);
+            float4 cpos = make_float4(0.f, 0.f, 0.f, 0.f);
             uint32_t code = 0u;
             if (q < q1) {
               const int4 cxq = cellx_t[off + q];
               const int2 jw = celljw_t[off + q];
               const int px = cxq.x + six * Lx, py = cxq.y + siy * Ly, pz = cxq.z + siz * Lz;
-              const float gxq = (float)max(0, max(bx0 - px, px - bx1));
-              const float gyq = (float)max(0, max(by0 - py, py - by1));
-              const float gzq = (float)max(0, max(bz0 - pz, pz - bz1));
-              // the box distance never exceeds an atom distance, also after rounding
-              keep = qr2(gxq, gyq, gzq) < rl2;
+              // kept if within the list radius of a quarter box; a box distance
+              // never exceeds an atom distance, also after rounding
+#pragma unroll
+              for (int g = 0; g < 4; ++g) {
+                const float gxq = (float)max(0, max(sb[g][0] - px, px - sb[g][1]));
+                const float gyq = (float)max(0, max(sb[g][2] - py, py - sb[g][3]));
+                const float gzq = (float)max(0, max(sb[g][4] - pz, pz - sb[g][5]));
+                keep = keep || (sbact[g] && qr2(gxq, gyq, gzq) < rl2);
+              }
               const int sx = six - unpack_wrap(jw.y, 0), sy = siy - unpack_wrap(jw.y, 1),
                         sz = siz - unpack_wrap(jw.y, 2);
               if (keep && (sx < -16 || sx > 15 || sy < -16 || sy > 15 || sz < -16 || sz > 15)) {
                 bad = true;  // shift not representable: the replica is flagged
                 keep = false;
               }
-              cpos = make_int4(px, py, pz, cxq.w);
+              cpos = make_float4((float)(px - bx0), (float)(py - by0), (float)(pz - bz0),
+                                 __int_as_float(cxq.w));
               code = (uint32_t)jw.x | ((uint32_t)((sx + 16) & 31) << 16) |
                      ((uint32_t)((sy + 16) & 31) << 21) | ((uint32_t)((sz + 16) & 31) << 26);
             }
             const uint64_t km = __ballot(keep);
             const int at = __popcll(km & ((1ull << lane) - 1ull));
-            if (keep) s_pos[at] = cpos;
-            const int nk = __popcll(km);
+            int nk = __popcll(km);
+            if (nst + nk > cap) {  // staging full: the rest is dropped and the replica flagged
+              bad = true;
+              nk = cap - nst;
+            }
+            // every kept candidate is staged, in range order
+            if (keep && at < nk) {
+              s_pos[at] = cpos;
+              stg[nst + at] = code;
+            }
             __syncthreads();
-            // ---- every kept candidate against the 64 atoms of the block
-            const int nst0 = nst;
-            uint64_t acc = 0ull;  // kept candidates that received a staging index
-            for (int k = 0; k < nk; ++k) {
-              const int4 c = s_pos[k];
-              const float dx = (float)(c.x - wx), dy = (float)(c.y - wy), dz = (float)(c.z - wz);
-              const int d = c.w - a + 32;
-              const bool win = (unsigned)d < 64u;
-              const bool exw = win && ((exm >> (d & 63)) & 1ull);
-              bool in = (qr2(dx, dy, dz) < rl2) && !exw;
-              if (anyfar && __ballot(in && !win && exfar)) {
-                if (in && !win && exfar)
-                  for (int e = e0; e < e1; ++e) in = in && (ex_list[e] != c.w);
+            // ---- every staged candidate against the lane's own atom
+            if (!anyfar) {
+              for (int k = 0; k < nk; ++k) {
+                const float4 c = s_pos[k];
+                const float dx = c.x - ax, dy = c.y - ay, dz = c.z - az;
+                const int d = __float_as_int(c.w) - a32;
+                const bool exw = (unsigned)d < 64u && ((exm >> (d & 63)) & 1ull);
+                if (qr2(dx, dy, dz) < rl2x && !exw) {
+                  pend = (pend << 16) | (uint64_t)(uint32_t)(nst + k);
+                  ++cnt;  // entries past maxnb are counted only to flag the overflow
+                  if ((cnt & 3) == 0 && cnt <= maxnb) list_store4(lst, cnt - 4, lane, pend);
+                }
               }
-              if (__ballot(in)) {
-                if (nst < cap) {
-                  if (in) {
-                    if (cnt < maxnb) list_push((uint32_t)nst, cnt, w0, w1, w2, w3, lst, lane);
-                    ++cnt;  // entries past maxnb are counted only to flag the overflow
-                  }
-                  acc |= 1ull << k;
-                  ++nst;
-                } else {
-                  bad = true;  // staging full: the candidate is dropped and the replica flagged
+            } else {
+              for (int k = 0; k < nk; ++k) {
+                const float4 c = s_pos[k];
+                const float dx = c.x - ax, dy = c.y - ay, dz = c.z - az;
+                const int oj = __float_as_int(c.w);
+                const int d = oj - a32;
+                const bool win = (unsigned)d < 64u;
+                bool in = qr2(dx, dy, dz) < rl2x && !(win && ((exm >> (d & 63)) & 1ull));
+                if (in && !win && exfar)
+                  for (int e = e0; e < e1; ++e) in = in && (ex_list[e] != oj);
+                if (in) {
+                  pend = (pend << 16) | (uint64_t)(uint32_t)(nst + k);
+                  ++cnt;
+                  if ((cnt & 3) == 0 && cnt <= maxnb) list_store4(lst, cnt - 4, lane, pend);
                 }
               }
             }
-            // staging entries of this batch, in candidate order
-            if (keep && ((acc >> at) & 1ull))
-              stg[nst0 + __popcll(acc & ((1ull << at) - 1ull))] = code;
+            nst += nk;
             __syncthreads();
           }
         }
@@ -502,8 +550,9 @@ __global__ __launch_bounds__(kBlk) void k_list(const RepInfo *__restrict__ info,
   } else if (active) {
     // pad to a multiple of 8 with the inert staging entry (index cap)
     while (cnt & 7) {
-      list_push((uint32_t)cap, cnt, w0, w1, w2, w3, lst, lane);
+      pend = (pend << 16) | (uint64_t)cap;
       ++cnt;
+      if ((cnt & 3) == 0) list_store4(lst, cnt - 4, lane, pend);
     }
   }
   W.nbcnt[slot] = active ? cnt : 0;

@@ -223,10 +223,10 @@ static vp_status build(vp_system *s, const vp_replica_desc *reps, int32_t n_reps
     R.maxnb = maxnb;
     // staging estimate: atoms within rl of a compact 64-atom block (side
     // ~0.93 (64/rho)^(1/3)), with a margin for the blocks that turn from one
-    // column into the next
+    // column into the next (every atom within rl of a quarter's box is staged)
     const double a = 0.93 * std::cbrt(kBlk / rho);
     const double vst = a * a * a + 6.0 * a * a * rl + 3.0 * M_PI * a * rl * rl + 4.0 / 3.0 * M_PI * rl * rl * rl;
-    int cap = (int)std::ceil(1.4 * vst * rho + 128);
+    int cap = (int)std::ceil(1.5 * vst * rho + 128);
     cap = std::min(kMaxStage, std::min(cap, d.n_atoms * 27 + 8));
     R.stage_cap = cap;
     stage_cap_max = std::max(stage_cap_max, cap);
