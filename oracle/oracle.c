@@ -647,3 +647,387 @@ int ora_select(int32_t n, const double *phi, const uint8_t *reached, const uint8
   *best_phi = bp;
   return b < 0 ? -1 : 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Pathwise derivative of the functional with respect to the bias           */
+/* parameters theta = (bias_k, ramp_rate), the noise held fixed.            */
+/*                                                                          */
+/* Every quantity is carried as a dual number: its value and its            */
+/* derivatives along two directions (direction 0: bias_k, direction 1:      */
+/* ramp_rate).  Evaluating the same potential, collective variable, bias,   */
+/* BAOAB step and functional on dual numbers applies the chain rule         */
+/* mechanically, so the derivative parts are d/dtheta of exactly the        */
+/* computation above.  The pair set is fixed by the values (a pair moving   */
+/* across the cutoff is a measure-zero event for the derivative).           */
+/* Parity pinned by central differences of the plain computation.           */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+  double v, d[2];
+} dual2;
+
+static dual2 dn(double v) {
+  dual2 r = {v, {0.0, 0.0}};
+  return r;
+}
+static dual2 dadd(dual2 a, dual2 b) {
+  dual2 r = {a.v + b.v, {a.d[0] + b.d[0], a.d[1] + b.d[1]}};
+  return r;
+}
+static dual2 dsub(dual2 a, dual2 b) {
+  dual2 r = {a.v - b.v, {a.d[0] - b.d[0], a.d[1] - b.d[1]}};
+  return r;
+}
+static dual2 dmul(dual2 a, dual2 b) {
+  dual2 r = {a.v * b.v, {a.d[0] * b.v + a.v * b.d[0], a.d[1] * b.v + a.v * b.d[1]}};
+  return r;
+}
+static dual2 dscale(double s, dual2 a) {
+  dual2 r = {s * a.v, {s * a.d[0], s * a.d[1]}};
+  return r;
+}
+static dual2 ddiv(dual2 a, dual2 b) {
+  dual2 r;
+  r.v = a.v / b.v;
+  for (int k = 0; k < 2; ++k) r.d[k] = (a.d[k] - r.v * b.d[k]) / b.v;
+  return r;
+}
+static dual2 dsqrt(dual2 a) {
+  dual2 r;
+  r.v = sqrt(a.v);
+  for (int k = 0; k < 2; ++k) r.d[k] = a.d[k] / (2.0 * r.v);
+  return r;
+}
+/* acos with the derivative -1/sin, sin bounded below as in the angle force */
+static dual2 dacos(dual2 a, double sn) {
+  dual2 r;
+  r.v = acos(a.v);
+  for (int k = 0; k < 2; ++k) r.d[k] = -a.d[k] / sn;
+  return r;
+}
+
+typedef struct {
+  const dual2 *X;
+  dual2 *F;
+} nb_dual_acc;
+
+/* pair force of the potential on dual positions: the separation's value is
+ * the minimum-image one found by the pair search, its derivative that of
+ * x_j - x_i (the image shift is a constant) */
+static void nb_visit_dual(ora_ctx *c, int i, int j, const double *dv, void *arg) {
+  nb_dual_acc *acc = (nb_dual_acc *)arg;
+  const ora_sys *s = &c->s;
+  dual2 d[3];
+  for (int a = 0; a < 3; ++a) {
+    d[a].v = dv[a];
+    for (int k = 0; k < 2; ++k) d[a].d[k] = acc->X[3 * j + a].d[k] - acc->X[3 * i + a].d[k];
+  }
+  dual2 r2 = dadd(dadd(dmul(d[0], d[0]), dmul(d[1], d[1])), dmul(d[2], d[2]));
+  dual2 r = dsqrt(r2);
+  double sig = 0.5 * (s->sigma[i] + s->sigma[j]);
+  double eps = sqrt(s->epsilon[i] * s->epsilon[j]);
+  dual2 fscal = dn(0.0);
+  if (eps > 0.0) {
+    dual2 sr2 = ddiv(dn(sig * sig), r2);
+    dual2 sr6 = dmul(dmul(sr2, sr2), sr2);
+    dual2 lj = dsub(dscale(2.0, dmul(sr6, sr6)), sr6);
+    fscal = dadd(fscal, ddiv(dscale(24.0 * eps, lj), r2));
+  }
+  double qq = COULOMB_F * s->charge[i] * s->charge[j];
+  if (qq != 0.0) {
+    dual2 inv3 = ddiv(dn(1.0), dmul(r2, r));
+    fscal = dadd(fscal, dscale(qq, dsub(inv3, dn(2.0 * c->krf))));
+  }
+  for (int a = 0; a < 3; ++a) {
+    dual2 fa = dmul(fscal, d[a]);
+    acc->F[3 * i + a] = dsub(acc->F[3 * i + a], fa);
+    acc->F[3 * j + a] = dadd(acc->F[3 * j + a], fa);
+  }
+}
+
+static void bonded_dual(const ora_ctx *c, const dual2 *X, dual2 *F) {
+  const ora_sys *s = &c->s;
+  for (int b = 0; b < s->n_bonds; ++b) {
+    int i = s->bonds[2 * b], j = s->bonds[2 * b + 1];
+    dual2 d[3], r2 = dn(0.0);
+    for (int a = 0; a < 3; ++a) {
+      d[a] = dsub(X[3 * j + a], X[3 * i + a]);
+      r2 = dadd(r2, dmul(d[a], d[a]));
+    }
+    dual2 r = dsqrt(r2);
+    dual2 g = ddiv(dscale(s->bond_k[b], dsub(r, dn(s->bond_r0[b]))), r);
+    for (int a = 0; a < 3; ++a) {
+      F[3 * i + a] = dadd(F[3 * i + a], dmul(g, d[a]));
+      F[3 * j + a] = dsub(F[3 * j + a], dmul(g, d[a]));
+    }
+  }
+  for (int k = 0; k < s->n_angles; ++k) {
+    int ia = s->angles[3 * k], ic = s->angles[3 * k + 1], ib = s->angles[3 * k + 2];
+    dual2 u[3], w[3], uu = dn(0.0), ww = dn(0.0), uw = dn(0.0);
+    for (int a = 0; a < 3; ++a) {
+      u[a] = dsub(X[3 * ia + a], X[3 * ic + a]);
+      w[a] = dsub(X[3 * ib + a], X[3 * ic + a]);
+      uu = dadd(uu, dmul(u[a], u[a]));
+      ww = dadd(ww, dmul(w[a], w[a]));
+      uw = dadd(uw, dmul(u[a], w[a]));
+    }
+    dual2 nuw = dmul(dsqrt(uu), dsqrt(ww));
+    dual2 cs = ddiv(uw, nuw);
+    if (cs.v > 1.0) cs = dn(1.0);
+    if (cs.v < -1.0) cs = dn(-1.0);
+    double snv = sqrt(1.0 - cs.v * cs.v);
+    if (snv < 1e-12) snv = 1e-12;
+    dual2 sn = snv > 1e-12 ? dsqrt(dsub(dn(1.0), dmul(cs, cs))) : dn(1e-12);
+    dual2 th = dacos(cs, snv);
+    dual2 dvs = ddiv(dscale(s->angle_k[k], dsub(th, dn(s->angle_theta0[k]))), sn);
+    for (int a = 0; a < 3; ++a) {
+      dual2 dcu = dsub(ddiv(w[a], nuw), ddiv(dmul(cs, u[a]), uu));
+      dual2 dcw = dsub(ddiv(u[a], nuw), ddiv(dmul(cs, w[a]), ww));
+      dual2 fa = dmul(dvs, dcu), fb = dmul(dvs, dcw);
+      F[3 * ia + a] = dadd(F[3 * ia + a], fa);
+      F[3 * ib + a] = dadd(F[3 * ib + a], fb);
+      F[3 * ic + a] = dsub(F[3 * ic + a], dadd(fa, fb));
+    }
+  }
+}
+
+/* contact value and its r-derivative on a dual distance */
+static dual2 contact_dual(dual2 r, double r0, double rs, double rc, dual2 *dcdr) {
+  dual2 u = dmul(dscale(1.0 / r0, r), dscale(1.0 / r0, r));
+  dual2 u2 = dmul(u, u);
+  dual2 num = dadd(dadd(dn(1.0), u), u2);
+  dual2 den = dadd(dadd(num, dmul(u2, u)), dmul(u2, u2));
+  dual2 cv = ddiv(num, den);
+  dual2 dnum = dadd(dn(1.0), dscale(2.0, u));
+  dual2 dden = dadd(dadd(dnum, dscale(3.0, u2)), dscale(4.0, dmul(u2, u)));
+  dual2 dcdu = ddiv(dsub(dmul(dnum, den), dmul(num, dden)), dmul(den, den));
+  dual2 dc = dmul(dcdu, dscale(2.0 / (r0 * r0), r));
+  dual2 sw = dn(1.0), dsw = dn(0.0);
+  if (r.v >= rc) {
+    sw = dn(0.0);
+  } else if (r.v > rs) {
+    dual2 t = dscale(1.0 / (rc - rs), dsub(r, dn(rs)));
+    dual2 t2 = dmul(t, t), t3 = dmul(t2, t);
+    dual2 poly = dadd(dsub(dn(10.0), dscale(15.0, t)), dscale(6.0, t2));
+    sw = dsub(dn(1.0), dmul(t3, poly));
+    dual2 omt = dsub(dn(1.0), t);
+    dsw = dscale(-30.0 / (rc - rs), dmul(t2, dmul(omt, omt)));
+  }
+  *dcdr = dadd(dmul(dc, sw), dmul(cv, dsw));
+  return dmul(cv, sw);
+}
+
+/* collective variable and its gradient on dual positions (as ora_cv) */
+static dual2 cv_dual(const ora_ctx *c, const dual2 *X, dual2 *G) {
+  const ora_sys *s = &c->s;
+  int ns = s->n_solute;
+  for (int i = 0; i < 3 * ns; ++i) G[i] = dn(0.0);
+  if (s->bias == ORA_BIAS_RG) {
+    double M = 0.0;
+    dual2 cm[3] = {dn(0.0), dn(0.0), dn(0.0)};
+    for (int i = 0; i < ns; ++i) {
+      M += s->mass[i];
+      for (int a = 0; a < 3; ++a) cm[a] = dadd(cm[a], dscale(s->mass[i], X[3 * i + a]));
+    }
+    for (int a = 0; a < 3; ++a) cm[a] = dscale(1.0 / M, cm[a]);
+    dual2 acc = dn(0.0);
+    for (int i = 0; i < ns; ++i)
+      for (int a = 0; a < 3; ++a) {
+        dual2 d = dsub(X[3 * i + a], cm[a]);
+        acc = dadd(acc, dscale(s->mass[i], dmul(d, d)));
+      }
+    dual2 rg = dsqrt(dscale(1.0 / M, acc));
+    for (int i = 0; i < ns; ++i)
+      for (int a = 0; a < 3; ++a)
+        G[3 * i + a] = ddiv(dscale(s->mass[i], dsub(X[3 * i + a], cm[a])), dscale(M, rg));
+    return rg;
+  }
+  dual2 z = dn(0.0);
+  if (s->bias == ORA_BIAS_CONTACT || s->bias == ORA_BIAS_RMD_CONTACT) {
+    for (int i = 0; i < ns; ++i)
+      for (int j = i + s->contact_min_sep + 1; j < ns; ++j) {
+        dual2 d[3], r2 = dn(0.0);
+        for (int a = 0; a < 3; ++a) {
+          d[a] = dsub(X[3 * j + a], X[3 * i + a]);
+          r2 = dadd(r2, dmul(d[a], d[a]));
+        }
+        dual2 r = dsqrt(r2), dc;
+        dual2 cij = contact_dual(r, s->contact_r0, s->contact_rs, s->contact_rc, &dc);
+        dual2 diff = dsub(cij, dn(c->cmap_f[(size_t)i * ns + j]));
+        z = dadd(z, dmul(diff, diff));
+        dual2 g = ddiv(dscale(2.0, dmul(diff, dc)), r);
+        for (int a = 0; a < 3; ++a) {
+          G[3 * j + a] = dadd(G[3 * j + a], dmul(g, d[a]));
+          G[3 * i + a] = dsub(G[3 * i + a], dmul(g, d[a]));
+        }
+      }
+  }
+  return z;
+}
+
+/* total force and functional integrand on dual positions; theta != 0 seeds
+ * the bias parameters (direction 0: bias_k, direction 1: ramp_rate).
+ * Returns 1 if a force is non-finite or above the limit, -1 for the ratchet
+ * bias (its running minimum makes the pathwise derivative undefined here). */
+static int forces_dual(ora_ctx *c, const dual2 *X, int theta, double t, double z0, int use_cells,
+                       dual2 *F, dual2 *S) {
+  const ora_sys *s = &c->s;
+  int n = s->n_atoms, ns = s->n_solute;
+  if (s->bias == ORA_BIAS_RMD_CONTACT) return -1;
+  double *xv = (double *)malloc(sizeof(double) * 3 * (size_t)n);
+  dual2 *G = (dual2 *)malloc(sizeof(dual2) * 3 * (size_t)(ns > 0 ? ns : 1));
+  for (int i = 0; i < 3 * n; ++i) {
+    xv[i] = X[i].v;
+    F[i] = dn(0.0);
+  }
+  nb_dual_acc acc = {X, F};
+  if (use_cells)
+    pairs_cells(c, xv, NULL, 0, nb_visit_dual, &acc);
+  else
+    pairs_brute(c, xv, NULL, 0, nb_visit_dual, &acc);
+  bonded_dual(c, X, F);
+  dual2 k = dn(s->bias_k), rho = dn(s->ramp_rate);
+  if (theta) {
+    k.d[0] = 1.0;
+    rho.d[1] = 1.0;
+  }
+  dual2 Sd = dn(0.0);
+  if (s->bias == ORA_BIAS_RG || s->bias == ORA_BIAS_CONTACT) {
+    dual2 z = cv_dual(c, X, G);
+    dual2 w = dsub(dn(1.0), dscale(t, rho));
+    if (w.v < 0.0) w = dn(0.0);
+    dual2 zr = dadd(dn(s->z_target), dscale(z0 - s->z_target, w));
+    dual2 cb = dscale(-1.0, dmul(k, dsub(z, zr)));
+    for (int i = 0; i < ns; ++i) {
+      dual2 f2 = dn(0.0);
+      for (int a = 0; a < 3; ++a) {
+        dual2 fb = dmul(cb, G[3 * i + a]);
+        F[3 * i + a] = dadd(F[3 * i + a], fb);
+        f2 = dadd(f2, dmul(fb, fb));
+      }
+      Sd = dadd(Sd, dscale(1.0 / (s->gamma[i] * s->mass[i]), f2));
+    }
+  } else if (s->bias == ORA_BIAS_CONST && s->const_force) {
+    for (int i = 0; i < ns; ++i) {
+      double f2 = 0.0;
+      for (int a = 0; a < 3; ++a) {
+        F[3 * i + a] = dadd(F[3 * i + a], dn(s->const_force[3 * i + a]));
+        f2 += s->const_force[3 * i + a] * s->const_force[3 * i + a];
+      }
+      Sd = dadd(Sd, dn(f2 / (s->gamma[i] * s->mass[i])));
+    }
+  }
+  *S = Sd;
+  int bad = 0;
+  for (int i = 0; i < 3 * n; ++i)
+    if (!isfinite(F[i].v) || fabs(F[i].v) > FORCE_LIMIT) bad = 1;
+  free(xv);
+  free(G);
+  return bad;
+}
+
+int ora_forces_dir(ora_ctx *c, const double *x, const double *dx, int32_t theta, double t,
+                   const ora_state *st, int32_t use_cells, double *f, double *fdot, double *S,
+                   double *Sdot) {
+  int n = c->s.n_atoms;
+  dual2 *X = (dual2 *)malloc(sizeof(dual2) * 3 * (size_t)n);
+  dual2 *F = (dual2 *)malloc(sizeof(dual2) * 3 * (size_t)n);
+  for (int i = 0; i < 3 * n; ++i) {
+    X[i] = dn(x[i]);
+    if (dx)
+      for (int k = 0; k < 2; ++k) X[i].d[k] = dx[(size_t)k * 3 * n + i];
+  }
+  dual2 Sd;
+  int bad = forces_dual(c, X, theta, t, st ? st->z0 : 0.0, use_cells, F, &Sd);
+  for (int i = 0; i < 3 * n; ++i) {
+    if (f) f[i] = F[i].v;
+    if (fdot)
+      for (int k = 0; k < 2; ++k) fdot[(size_t)k * 3 * n + i] = F[i].d[k];
+  }
+  if (S) *S = Sd.v;
+  if (Sdot) {
+    Sdot[0] = Sd.d[0];
+    Sdot[1] = Sd.d[1];
+  }
+  free(X);
+  free(F);
+  return bad;
+}
+
+int ora_init_tangent(ora_ctx *c, const double *x0, const ora_state *st, double *pd) {
+  double Sd[2], S;
+  int bad = ora_forces_dir(c, x0, NULL, 1, 0.0, st, 1, NULL, NULL, &S, Sd);
+  for (int k = 0; k < 2; ++k) {
+    pd[k] = 0.5 * Sd[k];
+    pd[2 + k] = Sd[k];
+  }
+  return bad;
+}
+
+int ora_run_tangent(ora_ctx *c, double *x, double *v, ora_state *st, double *xt, double *vt,
+                    double *pd, int32_t nsteps, int32_t use_cells) {
+  const ora_sys *s = &c->s;
+  int n = s->n_atoms;
+  double dt = s->dt;
+  if (st->status) return st->status;
+  if (s->bias == ORA_BIAS_RMD_CONTACT) return -1;
+  size_t m = 3 * (size_t)n;
+  dual2 *X = (dual2 *)malloc(sizeof(dual2) * m);
+  dual2 *V = (dual2 *)malloc(sizeof(dual2) * m);
+  dual2 *F = (dual2 *)malloc(sizeof(dual2) * m);
+  for (size_t i = 0; i < m; ++i) {
+    X[i] = dn(x[i]);
+    V[i] = dn(v[i]);
+    for (int k = 0; k < 2; ++k) {
+      X[i].d[k] = xt[k * m + i];
+      V[i].d[k] = vt[k * m + i];
+    }
+  }
+  dual2 S;
+  int bad = forces_dual(c, X, 1, (double)st->step * dt, st->z0, use_cells, F, &S);
+  for (int it = 0; it < nsteps && !bad; ++it) {
+    uint32_t step = (uint32_t)st->step;
+    for (int i = 0; i < n; ++i) {
+      double mi = s->mass[i];
+      double c1 = exp(-s->gamma[i] * dt);
+      double sd = sqrt((1.0 - c1 * c1) * s->kT / mi);
+      double g[3];
+      ora_normals(s->seed, (uint32_t)i, step, 0u, g);
+      for (int a = 0; a < 3; ++a) {
+        size_t q = 3 * (size_t)i + a;
+        dual2 vv = dadd(V[q], dscale(0.5 * dt / mi, F[q]));
+        dual2 xx = dadd(X[q], dscale(0.5 * dt, vv));
+        vv = dadd(dscale(c1, vv), dn(sd * g[a]));
+        xx = dadd(xx, dscale(0.5 * dt, vv));
+        V[q] = vv;
+        X[q] = xx;
+      }
+    }
+    st->step += 1;
+    bad = forces_dual(c, X, 1, (double)st->step * dt, st->z0, use_cells, F, &S);
+    for (size_t q = 0; q < m; ++q) V[q] = dadd(V[q], dscale(0.5 * dt / s->mass[q / 3], F[q]));
+    st->phi_acc += S.v;
+    st->s_last = S.v;
+    for (int k = 0; k < 2; ++k) {
+      pd[k] += S.d[k];
+      pd[2 + k] = S.d[k];
+    }
+  }
+  for (size_t i = 0; i < m; ++i) {
+    x[i] = X[i].v;
+    v[i] = V[i].v;
+    for (int k = 0; k < 2; ++k) {
+      xt[k * m + i] = X[i].d[k];
+      vt[k * m + i] = V[i].d[k];
+    }
+  }
+  free(X);
+  free(V);
+  free(F);
+  if (bad) st->status = 1;
+  return bad;
+}
+
+void ora_phi_grad(const ora_ctx *c, const ora_state *st, const double *pd, double *out) {
+  for (int k = 0; k < 2; ++k)
+    out[k] = st->status ? NAN : (pd[k] - 0.5 * pd[2 + k]) * c->s.dt / (4.0 * c->s.kT);
+}

@@ -13,6 +13,8 @@
  *     with the 1/(4 kT) prefactor of the path action              (Eq. StrVMD, Eq. VMDcondition)
  *   - selection of the trial with the least functional among
  *     trials that reached the product                             (main text, folding-event criterion)
+ *   - derivative of the functional with respect to the bias stiffness and
+ *     ramp rate along a trajectory, the noise held fixed (dual numbers)
  *
  * Parity status per function is stated in the comment above it.
  */
@@ -87,6 +89,27 @@ double ora_phi(const ora_ctx *c, const ora_state *st);
 int ora_reached(const ora_ctx *c, const ora_state *st);
 int ora_select(int32_t n, const double *phi, const uint8_t *reached, const uint8_t *eligible,
                int32_t *best, double *best_phi);
+
+/* Pathwise derivative with respect to theta = (bias_k, ramp_rate), the noise
+ * held fixed, by dual-number evaluation of the functions above.
+ *
+ * ora_forces_dir: F = -grad U + F^bias at (x, t) and its derivatives along
+ *   two directions: a displacement dx ([2][n][3], NULL = none) and, if
+ *   theta != 0, the parameters (direction 0: bias_k, 1: ramp_rate).
+ *   f [n][3], fdot [2][n][3], S and Sdot[2] may each be NULL.
+ * ora_init_tangent: trapezoid accumulators pd[4] = (sum w dS/dk,
+ *   sum w dS/drho, last dS/dk, last dS/drho) at step 0 (tangents zero).
+ * ora_run_tangent: as ora_run, also advancing xt, vt ([2][n][3]: dx/dtheta,
+ *   dv/dtheta) and pd.  Returns -1 for the ratchet bias (not differentiable
+ *   through its running minimum).
+ * ora_phi_grad: dPhi/dtheta [2] from pd (NaN for an unstable trajectory). */
+int ora_forces_dir(ora_ctx *c, const double *x, const double *dx, int32_t theta, double t,
+                   const ora_state *st, int32_t use_cells, double *f, double *fdot, double *S,
+                   double *Sdot);
+int ora_init_tangent(ora_ctx *c, const double *x0, const ora_state *st, double *pd);
+int ora_run_tangent(ora_ctx *c, double *x, double *v, ora_state *st, double *xt, double *vt,
+                    double *pd, int32_t nsteps, int32_t use_cells);
+void ora_phi_grad(const ora_ctx *c, const ora_state *st, const double *pd, double *out);
 
 #ifdef __cplusplus
 }

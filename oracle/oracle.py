@@ -81,6 +81,15 @@ def lib():
         L.ora_reached.argtypes = [C.c_void_p, C.POINTER(State)]
         L.ora_select.restype = C.c_int
         L.ora_select.argtypes = [C.c_int32, _dp, _u8p, _u8p, _ip, _dp]
+        L.ora_forces_dir.restype = C.c_int
+        L.ora_forces_dir.argtypes = [C.c_void_p, _dp, _dp, C.c_int32, C.c_double, C.POINTER(State),
+                                     C.c_int32, _dp, _dp, _dp, _dp]
+        L.ora_init_tangent.restype = C.c_int
+        L.ora_init_tangent.argtypes = [C.c_void_p, _dp, C.POINTER(State), _dp]
+        L.ora_run_tangent.restype = C.c_int
+        L.ora_run_tangent.argtypes = [C.c_void_p, _dp, _dp, C.POINTER(State), _dp, _dp, _dp,
+                                      C.c_int32, C.c_int32]
+        L.ora_phi_grad.argtypes = [C.c_void_p, C.POINTER(State), _dp, _dp]
         _lib = L
     return _lib
 
@@ -190,6 +199,40 @@ class Oracle:
 
     def phi(self, state):
         return lib().ora_phi(self.ctx, C.byref(state))
+
+    # ------------------------------------------- derivative w.r.t. (k, rho)
+    def forces_dir(self, x, dx=None, theta=False, t=0.0, state=None, cells=True):
+        """Forces and S with their derivatives along dx ([2][n][3]) and, if
+        theta, the bias parameters (direction 0: bias_k, 1: ramp_rate)."""
+        x = _f64(x, (self.n, 3))
+        dxa = None if dx is None else _f64(dx, (2, self.n, 3))
+        f = np.zeros((self.n, 3))
+        fdot = np.zeros((2, self.n, 3))
+        S = C.c_double()
+        Sdot = np.zeros(2)
+        st = C.byref(state) if state is not None else None
+        bad = lib().ora_forces_dir(self.ctx, _d(x), _d(dxa) if dxa is not None else None, int(theta),
+                                   float(t), st, int(cells), _d(f), _d(fdot), C.byref(S), _d(Sdot))
+        return f, fdot, S.value, Sdot, bool(bad)
+
+    def init_tangent(self, x0, state):
+        """Trapezoid accumulators of dS/dtheta at step 0."""
+        pd = np.zeros(4)
+        lib().ora_init_tangent(self.ctx, _d(_f64(x0, (self.n, 3))), C.byref(state), _d(pd))
+        return pd
+
+    def run_tangent(self, x, v, state, xt, vt, pd, nsteps, cells=True):
+        """Advance (x, v, state) and the tangents xt, vt ([2][n][3]) and pd in place."""
+        for a, shape in ((x, (self.n, 3)), (v, (self.n, 3)), (xt, (2, self.n, 3)),
+                         (vt, (2, self.n, 3)), (pd, (4,))):
+            assert a.dtype == np.float64 and a.flags.c_contiguous and a.shape == shape
+        return lib().ora_run_tangent(self.ctx, _d(x), _d(v), C.byref(state), _d(xt), _d(vt), _d(pd),
+                                     int(nsteps), int(cells))
+
+    def phi_grad(self, state, pd):
+        out = np.zeros(2)
+        lib().ora_phi_grad(self.ctx, C.byref(state), _d(pd), _d(out))
+        return out
 
     def reached(self, state):
         return bool(lib().ora_reached(self.ctx, C.byref(state)))

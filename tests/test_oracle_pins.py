@@ -502,3 +502,110 @@ def test_selection_brute_force(oracle_mod):
         else:
             m = min(phi[r] for r in ok)
             assert best == min(r for r in ok if phi[r] == m) and bp == m
+
+
+# ------------------------------------------- derivative w.r.t. (bias_k, ramp_rate)
+def _tangent_systems():
+    return {"contact": dict(synth.tiny(seed=31), bias_k=0.08, ramp_rate=30.0),
+            "rg": dict(synth.tiny(seed=32, bias=synth.BIAS_RG), ramp_rate=20.0)}
+
+
+@pytest.mark.parametrize("kind", ["contact", "rg"])
+def test_force_directional_derivative_matches_central_differences(oracle_mod, kind):
+    """d/dh F(x + h dx) at h = 0 (dual numbers) against (F(x+h dx) - F(x-h dx))/2h,
+    for the whole force including the bias and for the functional integrand S."""
+    d = _tangent_systems()[kind]
+    o = oracle_mod.Oracle(d)
+    x = np.asarray(d["x0"], np.float64)
+    st = o.init(x)
+    rng = np.random.default_rng(5)
+    dx = rng.normal(size=(2, o.n, 3))
+    t = 0.013
+    f, fdot, S, Sdot, bad = o.forces_dir(x, dx, False, t, st, cells=False)
+    assert not bad
+    h = 1e-6
+    for k in range(2):
+        fp, _, tp = o.forces(x + h * dx[k], t, st, cells=False)
+        fm, _, tm = o.forces(x - h * dx[k], t, st, cells=False)
+        fd = (fp - fm) / (2 * h)
+        assert np.linalg.norm(fdot[k] - fd) <= 1e-6 * np.linalg.norm(fd)
+        sd = (tp["S"] - tm["S"]) / (2 * h)
+        assert abs(Sdot[k] - sd) <= 1e-6 * abs(sd) + 1e-12
+
+
+@pytest.mark.parametrize("kind", ["contact", "rg"])
+def test_force_parameter_derivative_matches_central_differences(oracle_mod, kind):
+    d = _tangent_systems()[kind]
+    o = oracle_mod.Oracle(d)
+    x = np.asarray(d["x0"], np.float64)
+    st = o.init(x)
+    t = 0.011
+    _, fdot, _, Sdot, _ = o.forces_dir(x, None, True, t, st, cells=False)
+    for k, key in enumerate(("bias_k", "ramp_rate")):
+        h = 1e-6 * d[key]
+        out = []
+        for sgn in (1, -1):
+            dd = dict(d)
+            dd[key] = d[key] + sgn * h
+            f, _, terms = oracle_mod.Oracle(dd).forces(x, t, st, cells=False)
+            out.append((f, terms["S"]))
+        fd = (out[0][0] - out[1][0]) / (2 * h)
+        assert np.linalg.norm(fdot[k] - fd) <= 1e-6 * np.linalg.norm(fd)
+        assert abs(Sdot[k] - (out[0][1] - out[1][1]) / (2 * h)) <= 1e-6 * abs(Sdot[k])
+
+
+def _phi_and_grad(oracle_mod, d, nsteps):
+    o = oracle_mod.Oracle(d)
+    x = np.array(d["x0"], np.float64)
+    v = o.maxwell()
+    st = o.init(x)
+    pd = o.init_tangent(x, st)
+    xt = np.zeros((2, o.n, 3))
+    vt = np.zeros((2, o.n, 3))
+    assert o.run_tangent(x, v, st, xt, vt, pd, nsteps) == 0
+    return o.phi(st), o.phi_grad(st, pd), x, v
+
+
+def _phi_plain(oracle_mod, d, nsteps):
+    o = oracle_mod.Oracle(d)
+    x = np.array(d["x0"], np.float64)
+    v = o.maxwell()
+    st = o.init(x)
+    assert o.run(x, v, st, nsteps) == 0
+    return o.phi(st), x, v
+
+
+@pytest.mark.parametrize("kind", ["contact", "rg"])
+def test_functional_gradient_matches_central_differences(oracle_mod, kind):
+    """dPhi/d(bias_k, ramp_rate) along a 30-step trajectory with the noise held
+    fixed, against central differences of separate plain runs."""
+    d = _tangent_systems()[kind]
+    n = 30
+    phi, grad, x, v = _phi_and_grad(oracle_mod, d, n)
+    phi0, x0, v0 = _phi_plain(oracle_mod, d, n)
+    # the dual run's values are the plain run
+    assert abs(phi - phi0) <= 1e-12 * phi0
+    assert np.abs(x - x0).max() <= 1e-12 and np.abs(v - v0).max() <= 1e-9
+    for k, key in enumerate(("bias_k", "ramp_rate")):
+        h = 1e-5 * d[key]
+        pp = _phi_plain(oracle_mod, dict(d, **{key: d[key] + h}), n)[0]
+        pm = _phi_plain(oracle_mod, dict(d, **{key: d[key] - h}), n)[0]
+        fd = (pp - pm) / (2 * h)
+        assert abs(grad[k] - fd) <= 1e-6 * abs(fd), (key, grad[k], fd)
+        assert abs(grad[k]) > 0
+
+
+def test_functional_gradient_vanishes_at_zero_stiffness(oracle_mod):
+    """Phi is quadratic in the bias force, so at bias_k = 0 both derivatives are 0."""
+    d = dict(_tangent_systems()["contact"], bias_k=0.0)
+    _, grad, _, _ = _phi_and_grad(oracle_mod, d, 10)
+    assert np.all(grad == 0.0)
+
+
+def test_ramp_rate_derivative_vanishes_when_the_ramp_ends_in_the_first_step(oracle_mod):
+    """With rho dt > 1 the reference sits at z_target from step 1 on and
+    z_ref(0) = z(X_0) for every rho, so Phi does not depend on rho."""
+    d = _tangent_systems()["contact"]
+    d = dict(d, ramp_rate=2.0 / d["dt"])
+    _, grad, _, _ = _phi_and_grad(oracle_mod, d, 10)
+    assert grad[1] == 0.0 and grad[0] != 0.0
