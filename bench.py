@@ -95,6 +95,12 @@ def main():
     obs = system.observables()
     unstable = int(np.sum((obs[:, 5].astype(int) & 1) != 0))
     overflow = int(np.sum((obs[:, 5].astype(int) & 2) != 0))
+    col = {k: i for i, k in enumerate(vp.OBS)}
+    list_stats = {"stage_max": int(obs[:, col["stage_max"]].max()),
+                  "stage_cap": int(obs[:, col["stage_cap"]].max()),
+                  "list_max": int(obs[:, col["list_max"]].max()),
+                  "list_cap": int(obs[:, col["list_cap"]].max()),
+                  "exact_builds": int(obs[:, col["exact_builds"]].sum())}
     pairs = [system.pair_count(r) for r in range(len(reps))]
     pairs_total = int(sum(pairs))
     md_steps = args.steps * B
@@ -104,7 +110,8 @@ def main():
     dt_fs = float(base["dt"]) * 1000.0
     ns_day = (md_steps / elapsed) * dt_fs * 1e-6 * 86400.0
     print(f"# batched: {value:.4e} atom-steps/s, force kernel {force_ms:.4f} ms x {n_launch}, "
-          f"{pairs_total} pairs, rebuilds/replica {obs[:, 6].mean():.1f}, unstable {unstable}",
+          f"{pairs_total} pairs, rebuilds/replica {obs[:, 6].mean():.1f}, unstable {unstable}, "
+          f"lists {list_stats}",
           file=sys.stderr, flush=True)
     del system
     torch.cuda.empty_cache()
@@ -179,6 +186,7 @@ def main():
         "pair_interactions_per_s": pairs_total / (force_ms * 1e-3),
         "unstable_replicas": unstable,
         "list_overflow_replicas": overflow,
+        "list_stats": list_stats,
         "roofline": {
             "bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,

@@ -115,7 +115,9 @@ typedef struct {
   int32_t steps_per_graph; /* steps captured per hipGraph launch (0: 20) */
   int32_t use_graph;       /* 1: replay captured graphs; 0: launch every kernel */
   int32_t max_neighbors;   /* per-atom list capacity (0: derived from density) */
-  int32_t reserved[7];
+  int32_t tangent;         /* 1: also propagate dPhi/d(bias_k, ramp_rate) (vp_functional);
+                              harmonic and constant biases only */
+  int32_t reserved[6];
 } vp_options;
 
 /* Positions are held as 32-bit fixed point in units of 2^-24 nm, so that
@@ -153,8 +155,12 @@ vp_status vp_step_batch(vp_system *s, int32_t n_steps, void *hip_stream);
 
 /* Phi of every replica since creation (Eq. VMDcondition, trapezoid rule in
  * time, 1/(4 kT) prefactor): phi_host HOST [n_reps]; +inf for an unstable
- * replica.  dphi_dtheta_host must be NULL (reserved for the gradient with
- * respect to (bias_k, ramp_rate)).  Synchronises the system's last stream. */
+ * replica.  dphi_dtheta_host: HOST [n_reps][2] or NULL; if given, receives
+ * dPhi/d(bias_k) and dPhi/d(ramp_rate) along each trajectory with its noise
+ * held fixed (pathwise derivative of the discrete BAOAB trajectory, carried
+ * forward by tangents), NaN for an unstable replica; VP_ERR_STATE unless
+ * the system was created with vp_options.tangent = 1.  Synchronises the
+ * system's last stream. */
 vp_status vp_functional(vp_system *s, double *phi_host, double *dphi_dtheta_host);
 
 /* Variational selection: the replica with the least finite Phi among those
@@ -168,9 +174,13 @@ vp_status vp_select_path(vp_system *s, const uint8_t *eligible, int32_t *best, d
  * buffers x_dev, v_dev ([sum N][3] FP32; either may be NULL). */
 vp_status vp_get_state(vp_system *s, float *x_dev, float *v_dev, void *hip_stream);
 
-/* Per-replica observables: obs_host HOST [n_reps][VP_OBS_COUNT] FP64. */
+/* Per-replica observables: obs_host HOST [n_reps][VP_OBS_COUNT] FP64.
+ * Pair-list statistics since creation: largest staged neighbourhood of a
+ * 64-atom block and its capacity, longest per-atom list and its capacity,
+ * number of blocks built again in exact mode (staging capacity reached). */
 enum { VP_OBS_STEP = 0, VP_OBS_Z, VP_OBS_ZREF, VP_OBS_ZMIN, VP_OBS_PHI, VP_OBS_STATUS,
-       VP_OBS_REBUILDS, VP_OBS_KE, VP_OBS_COUNT };
+       VP_OBS_REBUILDS, VP_OBS_KE, VP_OBS_STAGE_MAX, VP_OBS_STAGE_CAP, VP_OBS_LIST_MAX,
+       VP_OBS_LIST_CAP, VP_OBS_EXACT_BUILDS, VP_OBS_COUNT };
 vp_status vp_observables(vp_system *s, double *obs_host);
 
 /* Force-kernel timing.  While on != 0, vp_step_batch enqueues its steps by
@@ -195,6 +205,15 @@ vp_status vp_sizes(const vp_system *s, int64_t *n_atoms_total, int32_t *n_reps);
  * pairs (i < j, replica-local user indices) whose current FP32 separation
  * passes the membership predicate, into pairs_host HOST [cap][2].
  * *count receives the number of such pairs (which may exceed cap). */
+/* Diagnostic (derivative checks): the directional derivatives of the total
+ * force of vp_forces along two displacements of the positions, parameters
+ * fixed -- the Hessian-vector products that carry the tangents.
+ * x_dev: DEVICE [sum N][3] FP32 positions; dx_dev: DEVICE [2][sum N][3] FP32
+ * directions; out_dev: DEVICE [2][sum N][3] FP32.  VP_ERR_STATE unless the
+ * system was created with vp_options.tangent = 1.  Asynchronous. */
+vp_status vp_debug_force_dir(vp_system *s, const float *x_dev, const float *dx_dev, float *out_dev,
+                             double t, void *hip_stream);
+
 vp_status vp_debug_pairs(vp_system *s, int32_t rep, int32_t *pairs_host, int64_t cap,
                          int64_t *count);
 

@@ -228,6 +228,187 @@ __global__ __launch_bounds__(kForceThreads) void k_forces(const RepInfo *__restr
   }
 }
 
+// Directional derivative of the potential force along a tangent dx/dtheta_p
+// (one direction p per launch): -H_U . xi, the Hessian-vector product that
+// carries the pathwise derivative of a trajectory.  Same blocks, lists and
+// staging as k_forces; the staged neighbourhood carries its tangents too.
+// For a pair, F_i = -f(s) d with s = r^2 and d = x_j - x_i, so
+//   dF_i = -f(s) delta - 2 f'(s) (d . delta) d,   delta = xi_j - xi_i,
+// with f the LJ + reaction-field force scalar of k_forces; the bonded terms
+// are differentiated in FP64 (dual numbers for the angle).  The pair set is
+// the force kernel's (exact cutoff).
+__global__ __launch_bounds__(kForceThreads) void k_tangent_forces(
+    const RepInfo *__restrict__ info, Work W, const int32_t *__restrict__ tile_rep,
+    const int32_t *__restrict__ tile_first, int nblk, const float4 *__restrict__ types,
+    const int32_t *__restrict__ bt_start, const BTerm *__restrict__ bterms, int stage_slots,
+    int dir) {
+  extern __shared__ int4 lds[];
+  int4 *st = lds;                                                     // staged atoms
+  float4 *sxi = reinterpret_cast<float4 *>(lds + stage_slots);        // their tangents
+  float4 *tab = reinterpret_cast<float4 *>(lds + 2 * stage_slots);    // type table
+  float *red = reinterpret_cast<float *>(lds);
+  const int b = xcd_tile(blockIdx.x, nblk);
+  if (b < 0) return;
+  const int tile = b / (kTile / kBlk);
+  const int r = tile_rep[tile];
+  const RepInfo &R = info[r];
+  const int p0 = tile_first[tile] + (b % (kTile / kBlk)) * kBlk;
+  const int tid = threadIdx.x;
+  const float4 *txp = W.tx + (size_t)dir * W.fstride;
+  float4 *tfp = W.tf + (size_t)dir * W.fstride;
+  if (p0 >= R.n) {
+    if (tid < kBlk) tfp[R.off + p0 + tid] = make_float4(0.f, 0.f, 0.f, 0.f);
+    return;
+  }
+  const int Lx = R.Lq[0], Ly = R.Lq[1], Lz = R.Lq[2];
+  const int nst = W.stage_n[b];
+  const uint32_t *stg = W.stage + (int64_t)b * kMaxStage;
+  const int4 *xr = W.xq + R.off;
+  for (int q = tid; q < nst; q += kForceThreads) {
+    const uint32_t e = stg[q];
+    const int j = (int)(e & 0xffffu);
+    const int sx = (int)((e >> 16) & 31) - 16, sy = (int)((e >> 21) & 31) - 16,
+              sz = (int)((e >> 26) & 31) - 16;
+    const int4 xj = xr[j];
+    st[q] = make_int4(xj.x + sx * Lx, xj.y + sy * Ly, xj.z + sz * Lz, xj.w);
+    sxi[q] = txp[R.off + j];
+  }
+  if (tid == 0) {
+    st[R.stage_cap] = make_int4(kDummyCoord, kDummyCoord, kDummyCoord, R.ntypes);
+    sxi[R.stage_cap] = make_float4(0.f, 0.f, 0.f, 0.f);
+  }
+  for (int t = tid; t <= R.ntypes; t += kForceThreads) tab[t] = types[R.type_off + t];
+  __syncthreads();
+
+  const int lane = tid & (kBlk - 1), part = tid / kBlk;
+  const int p = p0 + lane;
+  const int slot = R.off + p;
+  const bool active = p < R.n;
+  float gx = 0.0f, gy = 0.0f, gz = 0.0f;
+  int4 xi = make_int4(0, 0, 0, 0);
+  float4 ti4 = make_float4(0.f, 0.f, 0.f, 0.f);
+  if (active) {
+    xi = W.xq[slot];
+    ti4 = txp[slot];
+    const int wr = W.wrap[slot];
+    const int wx = xi.x - unpack_wrap(wr, 0) * Lx, wy = xi.y - unpack_wrap(wr, 1) * Ly,
+              wz = xi.z - unpack_wrap(wr, 2) * Lz;
+    const float4 ti = tab[xi.w];
+    const float rc2 = R.rc2q, krf2 = R.krf2q;
+    const int nch = W.nbcnt[slot] >> 3;
+    const uint4 *lp = reinterpret_cast<const uint4 *>(W.nblist + R.list_off +
+                                                      (int64_t)(b - R.blk0) * R.maxnb * kBlk) + lane;
+    for (int c = part; c < nch; c += kParts) {
+      const uint4 e = lp[(int64_t)c * kBlk];
+      const uint32_t w[4] = {e.x, e.y, e.z, e.w};
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int L = (int)((w[u >> 1] >> (16 * (u & 1))) & 0xffffu);
+        const int4 sj = st[L];
+        const float4 tj = tab[sj.w];
+        const float4 xj = sxi[L];
+        const float dx = (float)(sj.x - wx), dy = (float)(sj.y - wy), dz = (float)(sj.z - wz);
+        const float r2 = qr2(dx, dy, dz);
+        const bool in = r2 < rc2;
+        const float rinv = __builtin_amdgcn_rsqf(r2);
+        const float r2inv = rinv * rinv;
+        const float sg = ti.y + tj.y;
+        const float sr2 = sg * sg * r2inv;
+        const float sr6 = sr2 * sr2 * sr2;
+        const float ee = ti.z * tj.z;
+        const float qq = ti.x * tj.x;
+        // f(s) and f'(s) in the units of k_forces (coordinates in 2^-24 nm)
+        const float fs = ee * sr6 * __builtin_fmaf(2.0f, sr6, -1.0f) * r2inv +
+                         qq * __builtin_fmaf(rinv, r2inv, -krf2);
+        const float fsp = r2inv * r2inv *
+                          (ee * sr6 * __builtin_fmaf(-14.0f, sr6, 4.0f) - 1.5f * qq * rinv);
+        const float ddx = (xj.x - ti4.x) * kQf, ddy = (xj.y - ti4.y) * kQf, ddz = (xj.z - ti4.z) * kQf;
+        const float dot = __builtin_fmaf(dz, ddz, __builtin_fmaf(dy, ddy, dx * ddx));
+        const float a = in ? fs : 0.0f, bq = in ? 2.0f * fsp * dot : 0.0f;
+        gx = __builtin_fmaf(-a, ddx, __builtin_fmaf(-bq, dx, gx));
+        gy = __builtin_fmaf(-a, ddy, __builtin_fmaf(-bq, dy, gy));
+        gz = __builtin_fmaf(-a, ddz, __builtin_fmaf(-bq, dz, gz));
+      }
+    }
+  }
+  __syncthreads();
+  red[tid] = gx;
+  red[kForceThreads + tid] = gy;
+  red[2 * kForceThreads + tid] = gz;
+  __syncthreads();
+  if (part != 0 || !active) return;
+  float sx = red[lane], sy = red[kForceThreads + lane], sz = red[2 * kForceThreads + lane];
+#pragma unroll
+  for (int q = 1; q < kParts; ++q) {
+    sx += red[q * kBlk + lane];
+    sy += red[kForceThreads + q * kBlk + lane];
+    sz += red[2 * kForceThreads + q * kBlk + lane];
+  }
+  // bonded terms owned by this atom, differentiated along the tangent
+  double bx = 0.0, by = 0.0, bz = 0.0;
+  const int a = W.orig[slot];
+  const int t0 = bt_start[R.uoff + a], t1 = bt_start[R.uoff + a + 1];
+  auto pos = [&](int atom, int k) -> dual1 {
+    const int sl = W.inv[R.uoff + atom];
+    const int4 xa = W.xq[sl];
+    const float4 ta = txp[sl];
+    const int c = k == 0 ? xa.x : (k == 1 ? xa.y : xa.z);
+    const float tc = k == 0 ? ta.x : (k == 1 ? ta.y : ta.z);
+    return {(double)c * kInvQ, (double)tc};
+  };
+  for (int t = t0; t < t1; ++t) {
+    const BTerm T = bterms[t];
+    dual1 self[3], A[3], B[3];
+    for (int k = 0; k < 3; ++k) {
+      self[k] = pos(a, k);
+      A[k] = pos(T.a, k);
+      if (T.kind != 0) B[k] = pos(T.b, k);
+    }
+    if (T.kind == 0) {
+      dual1 d[3] = {A[0] - self[0], A[1] - self[1], A[2] - self[2]};
+      const dual1 rr = dsqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+      const dual1 g = (T.k * (rr - dual1{T.r0, 0.0})) / rr;
+      bx += (g * d[0]).d;
+      by += (g * d[1]).d;
+      bz += (g * d[2]).d;
+    } else {
+      const dual1 *pa = T.kind == 1 ? self : A, *pc = T.kind == 1 ? A : self;
+      const dual1 *pb = B;
+      dual1 u[3], v[3];
+      for (int k = 0; k < 3; ++k) {
+        u[k] = pa[k] - pc[k];
+        v[k] = pb[k] - pc[k];
+      }
+      const dual1 uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+      const dual1 vv = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+      const dual1 uv = u[0] * v[0] + u[1] * v[1] + u[2] * v[2];
+      const dual1 nn = dsqrt(uu * vv);
+      dual1 cs = uv / nn;
+      if (cs.v > 1.0) cs = {1.0, 0.0};
+      if (cs.v < -1.0) cs = {-1.0, 0.0};
+      const double snv = sqrt(1.0 - cs.v * cs.v);
+      const dual1 sn = snv > 1e-12 ? dsqrt(dual1{1.0, 0.0} - cs * cs) : dual1{1e-12, 0.0};
+      const dual1 th = {acos(cs.v), -cs.d / (snv > 1e-12 ? snv : 1e-12)};
+      const dual1 dv = (T.k * (th - dual1{T.r0, 0.0})) / sn;
+      double f[3];
+      for (int k = 0; k < 3; ++k) {
+        const dual1 e1 = v[k] / nn - (cs * u[k]) / uu;
+        if (T.kind == 1) {
+          f[k] = (dv * e1).d;
+        } else {
+          const dual1 e2 = u[k] / nn - (cs * v[k]) / vv;
+          f[k] = -(dv * (e1 + e2)).d;
+        }
+      }
+      bx += f[0];
+      by += f[1];
+      bz += f[2];
+    }
+  }
+  tfp[slot] = make_float4((float)((double)sx * kInvQ + bx), (float)((double)sy * kInvQ + by),
+                          (float)((double)sz * kInvQ + bz), 0.0f);
+}
+
 // ---------------------------------------------------------------------------
 // collective variable of the bias
 // ---------------------------------------------------------------------------
@@ -302,8 +483,114 @@ __global__ __launch_bounds__(kCvTile) void k_cv_pairs(const RepInfo *__restrict_
   if (lane == 0) W.ztile[R.cvt_off + (int64_t)it * nt + jc] = zs;
 }
 
+// Tangent of the contact-map gradient, one wave per 64 x 64 tile as in
+// k_cv_pairs: for both directions p,
+//   d(dz/dx_i)[xi] = -sum_j 2 [ (phi'^2 + diff phi'') rdot e
+//                               + diff phi' (delta - e rdot) / r ],
+// with phi = C~(r), e = (x_j - x_i)/r, delta = xi_j - xi_i, rdot = e . delta.
+__global__ __launch_bounds__(kCvTile) void k_cv_tangent_pairs(const RepInfo *__restrict__ info,
+                                                              Work W,
+                                                              const float *__restrict__ cmap) {
+  __shared__ int4 s_x[kCvTile];
+  __shared__ float4 s_t[2][kCvTile];
+  const int r = blockIdx.y;
+  const RepInfo &R = info[r];
+  if (R.bias != VP_BIAS_CONTACT && R.bias != VP_BIAS_RMD_CONTACT) return;
+  const int nt = R.cv_blocks;
+  if ((int)blockIdx.x >= nt * nt) return;
+  const int it = blockIdx.x / nt, jc = blockIdx.x % nt;
+  const int lane = threadIdx.x, ns = R.ns;
+  const int i = it * kCvTile + lane;
+  const int j0 = jc * kCvTile, jn = min(kCvTile, ns - j0);
+  if (lane < jn) {
+    const int sl = W.inv[R.uoff + j0 + lane];
+    s_x[lane] = W.xq[sl];
+    s_t[0][lane] = W.tx[sl];
+    s_t[1][lane] = W.tx[W.fstride + sl];
+  }
+  const bool row = i < ns;
+  int4 xi = make_int4(0, 0, 0, 0);
+  float4 t0 = make_float4(0.f, 0.f, 0.f, 0.f), t1 = t0;
+  if (row) {
+    const int sl = W.inv[R.uoff + i];
+    xi = W.xq[sl];
+    t0 = W.tx[sl];
+    t1 = W.tx[W.fstride + sl];
+  }
+  __syncthreads();
+  const float *cf = cmap + R.cmap_off + (int64_t)j0 * ns + (row ? i : 0);
+  const float ir02 = R.cinv_r02, iw = R.cinv_w, rs = R.crs, rs2 = R.crs2, rc2 = R.crc2;
+  const int msep = R.min_sep;
+  float ax = 0.f, ay = 0.f, az = 0.f, bx = 0.f, by = 0.f, bz = 0.f;
+  for (int k = 0; k < jn; ++k) {
+    const int j = j0 + k;
+    const int4 xj = s_x[k];
+    const float dx = (float)(xj.x - xi.x) * kInvQf, dy = (float)(xj.y - xi.y) * kInvQf,
+                dz = (float)(xj.z - xi.z) * kInvQf;
+    const float r2 = qr2(dx, dy, dz);
+    const float rinv = __builtin_amdgcn_rsqf(r2);
+    const float rr = r2 * rinv;
+    // C(u), C'(u), C''(u)
+    const float u = r2 * ir02, u2 = u * u;
+    const float num = 1.0f + u + u2;
+    const float den = num + u2 * u + u2 * u2;
+    const float iden = __builtin_amdgcn_rcpf(den);
+    const float c = num * iden;
+    const float dnum = __builtin_fmaf(2.0f, u, 1.0f);
+    const float dden = dnum + u2 * __builtin_fmaf(4.0f, u, 3.0f);
+    const float d2den = 2.0f + u * __builtin_fmaf(12.0f, u, 6.0f);
+    const float c1 = (dnum - c * dden) * iden;
+    const float c2 = (2.0f - 2.0f * c1 * dden - c * d2den) * iden;
+    // r-derivatives of C: u_r = 2 r / r0^2, u_rr = 2 / r0^2
+    const float ur = 2.0f * rr * ir02;
+    const float cr = c1 * ur, crr = c2 * ur * ur + c1 * 2.0f * ir02;
+    // quintic switch and its r-derivatives
+    const float t = (rr - rs) * iw;
+    const float omt = 1.0f - t;
+    const float swp = 1.0f - t * t * t * __builtin_fmaf(t, __builtin_fmaf(6.0f, t, -15.0f), 10.0f);
+    const float dswp = -30.0f * t * t * omt * omt * iw;
+    const float d2swp = -60.0f * t * omt * (1.0f - 2.0f * t) * iw * iw;
+    const bool inner = r2 <= rs2, outer = r2 >= rc2;
+    const float sw = inner ? 1.0f : (outer ? 0.0f : swp);
+    const float sr = (inner || outer) ? 0.0f : dswp;
+    const float srr = (inner || outer) ? 0.0f : d2swp;
+    const float ph = c * sw, ph1 = cr * sw + c * sr, ph2 = crr * sw + 2.0f * cr * sr + c * srr;
+    const bool valid = row && abs(j - i) > msep;
+    const float diff = ph - cf[(int64_t)k * ns];
+    const float A = valid ? ph1 * ph1 + diff * ph2 : 0.0f;
+    const float B = valid ? diff * ph1 * rinv : 0.0f;
+    // unit vector only for contributing pairs (i == j would give 0 * inf)
+    const float ri = valid ? rinv : 0.0f;
+    const float ex = dx * ri, ey = dy * ri, ez = dz * ri;
+    {
+      const float4 tj = s_t[0][k];
+      const float hx = tj.x - t0.x, hy = tj.y - t0.y, hz = tj.z - t0.z;
+      const float rd = __builtin_fmaf(ez, hz, __builtin_fmaf(ey, hy, ex * hx));
+      const float q = 2.0f * (A - B) * rd;  // coefficient of e
+      ax = __builtin_fmaf(-q, ex, __builtin_fmaf(-2.0f * B, hx, ax));
+      ay = __builtin_fmaf(-q, ey, __builtin_fmaf(-2.0f * B, hy, ay));
+      az = __builtin_fmaf(-q, ez, __builtin_fmaf(-2.0f * B, hz, az));
+    }
+    {
+      const float4 tj = s_t[1][k];
+      const float hx = tj.x - t1.x, hy = tj.y - t1.y, hz = tj.z - t1.z;
+      const float rd = __builtin_fmaf(ez, hz, __builtin_fmaf(ey, hy, ex * hx));
+      const float q = 2.0f * (A - B) * rd;
+      bx = __builtin_fmaf(-q, ex, __builtin_fmaf(-2.0f * B, hx, bx));
+      by = __builtin_fmaf(-q, ey, __builtin_fmaf(-2.0f * B, hy, by));
+      bz = __builtin_fmaf(-q, ez, __builtin_fmaf(-2.0f * B, hz, bz));
+    }
+  }
+  const int64_t o = (R.cvt_off + (int64_t)jc * nt + it) * kCvTile + lane;
+  W.tgtile[o] = make_float4(ax, ay, az, 0.0f);
+  W.tgtile[W.cvstride + o] = make_float4(bx, by, bz, 0.0f);
+}
+
 // Row tile it of a contact-map replica: dz/dx_i summed over the column tiles
 // in order, sum_i |dz/dx_i|^2/(gamma_i m_i) and the tile's part of z.
+// With TAN, also the tangents: (d grad z)[xi_p] summed over the column tiles,
+// dz/dtheta_p = sum_i g_i . xi_p,i and sum_i 2 g_i . (d g_i)[xi_p] / (gamma_i m_i).
+template <bool TAN>
 __global__ __launch_bounds__(kCvTile) void k_cv_reduce(const RepInfo *__restrict__ info, Work W,
                                                        const double *__restrict__ igm0) {
   const int r = blockIdx.y;
@@ -331,15 +618,43 @@ __global__ __launch_bounds__(kCvTile) void k_cv_reduce(const RepInfo *__restrict
     W.zpart[(size_t)r * kMaxCvBlocks + it] = z;
     W.gpart[(size_t)r * kMaxCvBlocks + it] = gs;
   }
+  if (TAN) {
+    for (int d = 0; d < 2; ++d) {
+      float hx = 0.0f, hy = 0.0f, hz = 0.0f;
+      for (int jc = 0; jc < nt; ++jc) {
+        const float4 h = W.tgtile[d * W.cvstride + (R.cvt_off + (int64_t)jc * nt + it) * kCvTile + lane];
+        hx += h.x;
+        hy += h.y;
+        hz += h.z;
+      }
+      double zd = 0.0, gd = 0.0;
+      if (i < R.ns) {
+        W.tg[d * W.solstride + R.sol_off + i] = make_float4(hx, hy, hz, 0.0f);
+        const float4 t = W.tx[d * W.fstride + W.inv[R.uoff + i]];
+        zd = (double)gx * t.x + (double)gy * t.y + (double)gz * t.z;
+        gd = 2.0 * ((double)gx * hx + (double)gy * hy + (double)gz * hz) * igm0[R.uoff + i];
+      }
+      zd = wave_sum(zd);
+      gd = wave_sum(gd);
+      if (lane == 0) {
+        W.tzpart[((size_t)r * kMaxCvBlocks + it) * 2 + d] = zd;
+        W.tgpart[((size_t)r * kMaxCvBlocks + it) * 2 + d] = gd;
+      }
+    }
+  }
 }
 
 // The other CV kinds, one workgroup per replica: radius of gyration (FP64 on
 // unwrapped coordinates), constant force; also advances the step counter.
+// With tan != 0, also the tangents of the radius of gyration (g_i =
+// m_i (x_i - X_cm) / (M Rg)): dz = sum_i g_i . xi_i and
+// (d g_i)[xi] = m_i (xi_i - Xi_cm) / (M Rg) - g_i dz / Rg; zero for the other
+// kinds handled here.
 __global__ __launch_bounds__(kCvBlock) void k_cv(const RepInfo *__restrict__ info, Work W,
                                                  const double *__restrict__ igm0,
                                                  const double *__restrict__ mass0,
                                                  const float4 *__restrict__ cforce, int inc_step,
-                                                 long long *__restrict__ step) {
+                                                 long long *__restrict__ step, int tan) {
   extern __shared__ int4 s_x[];  // solute positions of this replica
   __shared__ double s_red[kCvBlock / 64];
   __shared__ double s_cm[5];
@@ -393,6 +708,48 @@ __global__ __launch_bounds__(kCvBlock) void k_cv(const RepInfo *__restrict__ inf
         gq += (g0 * g0 + g1 * g1 + g2 * g2) * igm0[R.uoff + a];
       }
       zacc = (tid == 0) ? rg : 0.0;
+      if (tan) {
+        for (int d = 0; d < 2; ++d) {
+          // centre of mass of the tangent and dz = sum_i g_i . xi_i
+          double tm[3] = {0.0, 0.0, 0.0}, zd = 0.0;
+          for (int a = tid; a < ns; a += kCvBlock) {
+            const float4 t = W.tx[d * W.fstride + W.inv[R.uoff + a]];
+            const double ma = mass0[R.uoff + a];
+            tm[0] += ma * t.x;
+            tm[1] += ma * t.y;
+            tm[2] += ma * t.z;
+            const float4 g = W.g[R.sol_off + a];
+            zd += (double)g.x * t.x + (double)g.y * t.y + (double)g.z * t.z;
+          }
+          const double TX = block_sum<kCvBlock>(tm[0], s_red), TY = block_sum<kCvBlock>(tm[1], s_red),
+                       TZ = block_sum<kCvBlock>(tm[2], s_red), ZD = block_sum<kCvBlock>(zd, s_red);
+          if (tid == 0) {
+            s_cm[0] = TX / M;
+            s_cm[1] = TY / M;
+            s_cm[2] = TZ / M;
+            s_cm[3] = ZD;
+          }
+          __syncthreads();
+          const double tcx = s_cm[0], tcy = s_cm[1], tcz = s_cm[2], zdot = s_cm[3];
+          double gd = 0.0;
+          for (int a = tid; a < ns; a += kCvBlock) {
+            const float4 t = W.tx[d * W.fstride + W.inv[R.uoff + a]];
+            const float4 g = W.g[R.sol_off + a];
+            const double w = mass0[R.uoff + a] / (M * rg);
+            const double h0 = w * ((double)t.x - tcx) - (double)g.x * zdot / rg;
+            const double h1 = w * ((double)t.y - tcy) - (double)g.y * zdot / rg;
+            const double h2 = w * ((double)t.z - tcz) - (double)g.z * zdot / rg;
+            W.tg[d * W.solstride + R.sol_off + a] = make_float4((float)h0, (float)h1, (float)h2, 0.0f);
+            gd += 2.0 * ((double)g.x * h0 + (double)g.y * h1 + (double)g.z * h2) * igm0[R.uoff + a];
+          }
+          const double GD = block_sum<kCvBlock>(gd, s_red);
+          if (tid == 0) {
+            W.tzpart[(size_t)r * kMaxCvBlocks * 2 + d] = zdot;
+            W.tgpart[(size_t)r * kMaxCvBlocks * 2 + d] = GD;
+          }
+          __syncthreads();
+        }
+      }
     } else if (R.bias == VP_BIAS_CONST) {
       for (int a = tid; a < ns; a += kCvBlock) {
         const float4 f = cforce[R.sol_off + a];
@@ -405,7 +762,15 @@ __global__ __launch_bounds__(kCvBlock) void k_cv(const RepInfo *__restrict__ inf
     if (tid == 0) {
       W.zpart[(size_t)r * kMaxCvBlocks] = zs;
       W.gpart[(size_t)r * kMaxCvBlocks] = gs;
+      if (tan && R.bias != VP_BIAS_RG)
+        for (int d = 0; d < 2; ++d) {
+          W.tzpart[(size_t)r * kMaxCvBlocks * 2 + d] = 0.0;
+          W.tgpart[(size_t)r * kMaxCvBlocks * 2 + d] = 0.0;
+        }
     }
+    if (tan && R.bias == VP_BIAS_CONST)
+      for (int a = tid; a < ns; a += kCvBlock)
+        for (int d = 0; d < 2; ++d) W.tg[d * W.solstride + R.sol_off + a] = make_float4(0.f, 0.f, 0.f, 0.f);
   }
   if (inc_step && r == 0 && tid == 0) *step += 1;
 }
@@ -452,6 +817,71 @@ __global__ __launch_bounds__(kBlock) void k_force_out(const RepInfo *__restrict_
   o[0] = (float)f0;
   o[1] = (float)f1;
   o[2] = (float)f2;
+}
+
+// Directional derivative of the total force along the two tangents held in
+// W.tx, the parameters fixed: out [2][users][3] =
+//   -H_U xi_p + (dc/dz dz_p) g + c (d g)[xi_p]   (bias terms on solute atoms).
+__global__ __launch_bounds__(kBlock) void k_force_dir_out(const RepInfo *__restrict__ info,
+                                                          const RepState *__restrict__ state, Work W,
+                                                          const int32_t *__restrict__ tile_rep,
+                                                          const int32_t *__restrict__ tile_first,
+                                                          int ntiles, double t, int64_t users,
+                                                          float *__restrict__ out) {
+  const int tile = xcd_tile(blockIdx.x, ntiles);
+  if (tile < 0) return;
+  const int r = tile_rep[tile];
+  const RepInfo &R = info[r];
+  const int p = tile_first[tile] + threadIdx.x;
+  if (p >= R.n) return;
+  const int slot = R.off + p;
+  double z, G, zr, ub;
+  cv_sums(R, W, r, z, G);
+  const RepState &S = state[r];
+  const double c = bias_coef(R, z, S.z0, S.z_m, t, false, zr, ub);
+  double dcdz, dcdth[2];
+  bias_coef_deriv(R, z, S.z0, t, false, dcdz, dcdth);
+  const int a = W.orig[slot];
+  for (int d = 0; d < 2; ++d) {
+    double zd = 0.0;
+    for (int b = 0; b < R.cv_blocks; ++b) zd += W.tzpart[((size_t)r * kMaxCvBlocks + b) * 2 + d];
+    const float4 h = W.tf[d * W.fstride + slot];
+    double f0 = h.x, f1 = h.y, f2 = h.z;
+    if (a < R.ns) {
+      const float4 g = W.g[R.sol_off + a];
+      const float4 dg = W.tg[d * W.solstride + R.sol_off + a];
+      const double cd = dcdz * zd;
+      f0 += cd * g.x + c * dg.x;
+      f1 += cd * g.y + c * dg.y;
+      f2 += cd * g.z + c * dg.z;
+    }
+    float *o = out + (size_t)d * 3 * users + 3ll * (R.uoff + a);
+    o[0] = (float)f0;
+    o[1] = (float)f1;
+    o[2] = (float)f2;
+  }
+}
+
+// Tangent directions given in user order ([2][users][3] FP32) into slot order.
+__global__ __launch_bounds__(kBlock) void k_scatter_dirs(const RepInfo *__restrict__ info, Work W,
+                                                         const int32_t *__restrict__ tile_rep,
+                                                         const int32_t *__restrict__ tile_first,
+                                                         int ntiles, int64_t users,
+                                                         const float *__restrict__ dx) {
+  const int tile = xcd_tile(blockIdx.x, ntiles);
+  if (tile < 0) return;
+  const int r = tile_rep[tile];
+  const RepInfo &R = info[r];
+  const int p = tile_first[tile] + threadIdx.x;
+  const int slot = R.off + p;
+  for (int d = 0; d < 2; ++d) {
+    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (p < R.n) {
+      const float *u = dx + (size_t)d * 3 * users + 3ll * (R.uoff + W.orig[slot]);
+      v = make_float4(u[0], u[1], u[2], 0.0f);
+    }
+    W.tx[d * W.fstride + slot] = v;
+  }
 }
 
 // energy columns: LJ, RF, bond, angle, bias, z, z_ref, S
@@ -507,6 +937,14 @@ size_t force_lds_bytes(const vp_system *s) {
   return stage > red ? stage : red;
 }
 
+hipError_t prepare_forces(const vp_system *s) {
+  const int lds = (int)force_lds_bytes(s);
+  hipError_t e = hipFuncSetAttribute((const void *)k_forces<false>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute((const void *)k_forces<true>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+}
+
 void launch_native_map(const float *xf, int ns, int min_sep, float r0, float rs, float rc,
                        float *out, hipStream_t st) {
   int64_t n = (int64_t)ns * ns;
@@ -527,7 +965,7 @@ void launch_forces(vp_system *s, Work &W, bool energy, hipStream_t st) {
                        slots);
 }
 
-void launch_cv(vp_system *s, Work &W, int inc_step, hipStream_t st) {
+void launch_cv(vp_system *s, Work &W, int inc_step, hipStream_t st, bool tan) {
   int nt = 0, nsmax = 1;
   bool any_single = false;
   for (const RepInfo &R : s->info_h) {
@@ -540,11 +978,46 @@ void launch_cv(vp_system *s, Work &W, int inc_step, hipStream_t st) {
   }
   if (nt > 0) {
     hipLaunchKernelGGL(k_cv_pairs, dim3(nt * nt, s->R), dim3(kCvTile), 0, st, s->info, W, s->cmap);
-    hipLaunchKernelGGL(k_cv_reduce, dim3(nt, s->R), dim3(kCvTile), 0, st, s->info, W, s->igm0);
+    if (tan) {
+      hipLaunchKernelGGL(k_cv_tangent_pairs, dim3(nt * nt, s->R), dim3(kCvTile), 0, st, s->info, W,
+                         s->cmap);
+      hipLaunchKernelGGL(k_cv_reduce<true>, dim3(nt, s->R), dim3(kCvTile), 0, st, s->info, W, s->igm0);
+    } else {
+      hipLaunchKernelGGL(k_cv_reduce<false>, dim3(nt, s->R), dim3(kCvTile), 0, st, s->info, W, s->igm0);
+    }
   }
   size_t lds = any_single ? sizeof(int4) * (size_t)nsmax : 0;
   hipLaunchKernelGGL(k_cv, dim3(s->R), dim3(kCvBlock), lds, st, s->info, W, s->igm0, s->mass0,
-                     s->cforce, inc_step, s->step);
+                     s->cforce, inc_step, s->step, tan ? 1 : 0);
+}
+
+size_t tangent_lds_bytes(const vp_system *s) {
+  size_t stage = 2 * sizeof(int4) * (size_t)(s->stage_cap_max + 1) + sizeof(int4) * (size_t)(s->ntypes_max + 1);
+  size_t red = sizeof(float) * 3 * kForceThreads;
+  return stage > red ? stage : red;
+}
+
+hipError_t prepare_tangent(const vp_system *s) {
+  return hipFuncSetAttribute((const void *)k_tangent_forces, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)tangent_lds_bytes(s));
+}
+
+void launch_tangent_forces(vp_system *s, Work &W, hipStream_t st) {
+  const size_t lds = tangent_lds_bytes(s);
+  for (int d = 0; d < 2; ++d)
+    hipLaunchKernelGGL(k_tangent_forces, dim3(xcd_grid(s->n_blocks)), dim3(kForceThreads), lds, st,
+                       s->info, W, s->tile_rep, s->tile_first, s->n_blocks, s->types, s->bt_start,
+                       s->bterms, s->stage_cap_max + 1, d);
+}
+
+void launch_force_dir(vp_system *s, Work &W, const float *dx_user, double t, float *out,
+                      hipStream_t st) {
+  hipLaunchKernelGGL(k_scatter_dirs, dim3(xcd_grid(s->n_tiles)), dim3(kBlock), 0, st, s->info, W,
+                     s->tile_rep, s->tile_first, s->n_tiles, (int64_t)s->n_users, dx_user);
+  launch_tangent_forces(s, W, st);
+  launch_cv(s, W, 0, st, true);
+  hipLaunchKernelGGL(k_force_dir_out, dim3(xcd_grid(s->n_tiles)), dim3(kBlock), 0, st, s->info,
+                     s->state, W, s->tile_rep, s->tile_first, s->n_tiles, t, (int64_t)s->n_users, out);
 }
 
 void launch_force_out(vp_system *s, Work &W, double t, float *f_user, double *e_out,

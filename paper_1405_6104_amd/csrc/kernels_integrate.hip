@@ -17,7 +17,13 @@ namespace vp {
 
 enum { MODE_FINISH = 1, MODE_START = 2, MODE_INIT = 4 };
 
-template <int MODE>
+// With TAN, the same steps carry the tangents xi_p = dx/dtheta_p and
+// eta_p = dv/dtheta_p (theta = (bias_k, ramp_rate), the noise held fixed):
+//   B: eta += dt/2 dF_p/m;  A: xi += dt/2 eta;  O: eta = c1 eta;  A: xi += dt/2 eta,
+// where dF_p = -H_U xi_p + (dc/dz dz_p + dc/dtheta_p) g + c (d g)[xi_p] on
+// solute atoms, and the derivative of Phi accumulates
+//   dS_p = 2 c dc_p G + c^2 dG_p   (trapezoid weights as for Phi).
+template <int MODE, bool TAN>
 __global__ __launch_bounds__(kBlock) void k_integrate(const RepInfo *__restrict__ info,
                                                       RepState *__restrict__ state, Work W,
                                                       const int32_t *__restrict__ tile_rep,
@@ -45,6 +51,25 @@ __global__ __launch_bounds__(kBlock) void k_integrate(const RepInfo *__restrict_
   }
   const bool init = (MODE & MODE_INIT) != 0;
   const double c = bias_coef(R, z, S.z0, S.z_m, t, init, zr, ub);
+  double cd[2] = {0.0, 0.0};  // total dc/dtheta_p
+  if (TAN) {
+    double dcdz, dcdth[2];
+    bias_coef_deriv(R, z, S.z0, t, init, dcdz, dcdth);
+    double zd[2] = {0.0, 0.0}, gd[2] = {0.0, 0.0};
+    for (int b = 0; b < R.cv_blocks; ++b)
+      for (int d = 0; d < 2; ++d) {
+        zd[d] += W.tzpart[((size_t)r * kMaxCvBlocks + b) * 2 + d];
+        gd[d] += W.tgpart[((size_t)r * kMaxCvBlocks + b) * 2 + d];
+      }
+    for (int d = 0; d < 2; ++d) cd[d] = dcdz * zd[d] + dcdth[d];
+    if (p == 0 && (MODE & (MODE_INIT | MODE_FINISH)) && !(S.status & VP_REPLICA_UNSTABLE)) {
+      for (int d = 0; d < 2; ++d) {
+        const double sd = 2.0 * c * cd[d] * G + c * c * gd[d];
+        S.pd_acc[d] = init ? 0.5 * sd : S.pd_acc[d] + sd;
+        S.pd_last[d] = sd;
+      }
+    }
+  }
   if (p == 0 && (MODE & (MODE_INIT | MODE_FINISH))) {
     const double Sn = c * c * G;
     if (init) {
@@ -109,6 +134,43 @@ __global__ __launch_bounds__(kBlock) void k_integrate(const RepInfo *__restrict_
         disp = sqrtf(ex * ex + ey * ey + ez * ez);
       }
       W.vel[slot] = v;
+      if (TAN) {
+        for (int d = 0; d < 2; ++d) {
+          const float4 h = W.tf[d * W.fstride + slot];
+          double q0 = h.x, q1 = h.y, q2 = h.z;
+          if (a < R.ns) {
+            const float4 g = W.g[R.sol_off + a];
+            const float4 dg = W.tg[d * W.solstride + R.sol_off + a];
+            q0 += cd[d] * g.x + c * dg.x;
+            q1 += cd[d] * g.y + c * dg.y;
+            q2 += cd[d] * g.z + c * dg.z;
+          }
+          const float hx = hdt * ig.x * (float)q0, hy = hdt * ig.x * (float)q1, hz = hdt * ig.x * (float)q2;
+          float4 e = W.tv[d * W.fstride + slot];
+          if (MODE & MODE_FINISH) {
+            e.x += hx;
+            e.y += hy;
+            e.z += hz;
+          }
+          if (MODE & MODE_START) {
+            float4 xt = W.tx[d * W.fstride + slot];
+            e.x += hx;
+            e.y += hy;
+            e.z += hz;
+            xt.x += hdt * e.x;
+            xt.y += hdt * e.y;
+            xt.z += hdt * e.z;
+            e.x *= ig.y;
+            e.y *= ig.y;
+            e.z *= ig.y;
+            xt.x += hdt * e.x;
+            xt.y += hdt * e.y;
+            xt.z += hdt * e.z;
+            W.tx[d * W.fstride + slot] = xt;
+          }
+          W.tv[d * W.fstride + slot] = e;
+        }
+      }
     }
   }
   if (MODE & MODE_START) {
@@ -142,6 +204,13 @@ __global__ __launch_bounds__(kBlock) void k_init_state(const RepInfo *__restrict
   const int p = tile_first[tile] + threadIdx.x;
   const int slot = R.off + p;
   if (p >= R.npad) return;
+  if (W.tx) {
+    for (int d = 0; d < 2; ++d) {
+      W.tx[d * W.fstride + slot] = make_float4(0.f, 0.f, 0.f, 0.f);
+      W.tv[d * W.fstride + slot] = make_float4(0.f, 0.f, 0.f, 0.f);
+      W.tf[d * W.fstride + slot] = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+  }
   if (p >= R.n) {
     W.xq[slot] = make_int4(0, 0, 0, R.ntypes);
     W.vel[slot] = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -237,26 +306,34 @@ __global__ void k_debug_noise(uint64_t seed, uint32_t atom0, uint32_t step, uint
 // ---------------------------------------------------------------------------
 static inline int xcd_grid(int nb) { return 8 * ((nb + 7) / 8); }
 
-void launch_integrate(vp_system *s, int mode, hipStream_t st) {
+template <bool TAN>
+static void launch_integrate_t(vp_system *s, int mode, hipStream_t st) {
   dim3 g(xcd_grid(s->n_tiles)), b(kBlock);
   Work &W = s->traj;
   switch (mode) {
     case MODE_START:
-      hipLaunchKernelGGL(k_integrate<MODE_START>, g, b, 0, st, s->info, s->state, W, s->tile_rep,
-                         s->tile_first, s->n_tiles, s->step);
-      break;
-    case MODE_FINISH:
-      hipLaunchKernelGGL(k_integrate<MODE_FINISH>, g, b, 0, st, s->info, s->state, W, s->tile_rep,
-                         s->tile_first, s->n_tiles, s->step);
-      break;
-    case MODE_FINISH | MODE_START:
-      hipLaunchKernelGGL(k_integrate<MODE_FINISH | MODE_START>, g, b, 0, st, s->info, s->state, W,
+      hipLaunchKernelGGL((k_integrate<MODE_START, TAN>), g, b, 0, st, s->info, s->state, W,
                          s->tile_rep, s->tile_first, s->n_tiles, s->step);
       break;
+    case MODE_FINISH:
+      hipLaunchKernelGGL((k_integrate<MODE_FINISH, TAN>), g, b, 0, st, s->info, s->state, W,
+                         s->tile_rep, s->tile_first, s->n_tiles, s->step);
+      break;
+    case MODE_FINISH | MODE_START:
+      hipLaunchKernelGGL((k_integrate<MODE_FINISH | MODE_START, TAN>), g, b, 0, st, s->info,
+                         s->state, W, s->tile_rep, s->tile_first, s->n_tiles, s->step);
+      break;
     default:
-      hipLaunchKernelGGL(k_integrate<MODE_INIT>, g, b, 0, st, s->info, s->state, W, s->tile_rep,
-                         s->tile_first, s->n_tiles, s->step);
+      hipLaunchKernelGGL((k_integrate<MODE_INIT, TAN>), g, b, 0, st, s->info, s->state, W,
+                         s->tile_rep, s->tile_first, s->n_tiles, s->step);
   }
+}
+
+void launch_integrate(vp_system *s, int mode, hipStream_t st) {
+  if (s->tangent)
+    launch_integrate_t<true>(s, mode, st);
+  else
+    launch_integrate_t<false>(s, mode, st);
 }
 
 void launch_init_state(vp_system *s, const int32_t *xq_user, const float *v_user,

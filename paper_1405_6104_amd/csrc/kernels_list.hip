@@ -227,7 +227,9 @@ __global__ __launch_bounds__(kBlock) void k_permute(const RepInfo *__restrict__ 
                                                     int32_t *__restrict__ wrap_t,
                                                     const int32_t *__restrict__ cellpos_t,
                                                     int4 *__restrict__ cellx_t,
-                                                    int2 *__restrict__ celljw_t) {
+                                                    int2 *__restrict__ celljw_t,
+                                                    float4 *__restrict__ tx_t,
+                                                    float4 *__restrict__ tv_t) {
   int tile = xcd_tile(blockIdx.x, ntiles);
   if (tile < 0) return;
   const int r = tile_rep[tile];
@@ -242,6 +244,11 @@ __global__ __launch_bounds__(kBlock) void k_permute(const RepInfo *__restrict__ 
     int old = W.inv[R.uoff + a];
     x = W.xq[old];
     vel_t[slot] = W.vel[old];
+    if (W.tx)  // tangents follow their atoms
+      for (int d = 0; d < 2; ++d) {
+        tx_t[d * W.fstride + slot] = W.tx[d * W.fstride + old];
+        tv_t[d * W.fstride + slot] = W.tv[d * W.fstride + old];
+      }
   } else {
     const float *u = x_user + 3ll * (R.uoff + a);
     x = make_int4((int)__builtin_rintf(u[0] * kQf), (int)__builtin_rintf(u[1] * kQf),
@@ -317,7 +324,9 @@ __global__ __launch_bounds__(kBlk) void k_list(const RepInfo *__restrict__ info,
                                                const int2 *__restrict__ celljw_t,
                                                const int32_t *__restrict__ ex_start,
                                                const int32_t *__restrict__ ex_list,
-                                               const float4 *__restrict__ integ0) {
+                                               const float4 *__restrict__ integ0,
+                                               const float4 *__restrict__ tx_t,
+                                               const float4 *__restrict__ tv_t) {
   __shared__ float4 s_pos[kBlk];  // kept candidates: position relative to the block, user index
   __shared__ int s_cidx[3][18];  // fine-cell edges of the replica
   const int b = xcd_tile(blockIdx.x, nblk);
@@ -423,126 +432,165 @@ __global__ __launch_bounds__(kBlk) void k_list(const RepInfo *__restrict__ info,
   uint64_t pend = 0ull;  // pending list entries (up to four)
   bool bad = false;
   __syncthreads();  // cell edges in LDS
-  // unfolded cell u = i nc + c (image i, cell c); its lower edge is i L + edge[c]
-  int iz = uz0 >= 0 ? uz0 / ncz : -((-uz0 + ncz - 1) / ncz);
-  int cz = uz0 - iz * ncz;
-  for (int uz = uz0; uz <= uz1; ++uz) {
-    // gap between the cell's slab and the block box along z (coordinate units)
-    const long long zl = (long long)iz * Lz + s_cidx[2][cz], zh = (long long)iz * Lz + s_cidx[2][cz + 1];
-    const double gz = (double)max(0ll, max(zl - bz1, (long long)bz0 - zh));
-    int iy = uy0 >= 0 ? uy0 / ncy : -((-uy0 + ncy - 1) / ncy);
-    int cy = uy0 - iy * ncy;
-    for (int uy = uy0; uy <= uy1; ++uy) {
-      const long long yl = (long long)iy * Ly + s_cidx[1][cy], yh = (long long)iy * Ly + s_cidx[1][cy + 1];
-      const double gy = (double)max(0ll, max(yl - by1, (long long)by0 - yh));
-      const double gyz = gz * gz + gy * gy;
-      if (gyz <= rl2d) {
-        int ix = ux0 >= 0 ? ux0 / ncx : -((-ux0 + ncx - 1) / ncx);
-        int cx = ux0 - ix * ncx;
-        int ux = ux0;
-        while (ux <= ux1) {
-          // the next run of cells of this row that pass the gap test and share an image
-          const long long xl = (long long)ix * Lx + s_cidx[0][cx], xh = (long long)ix * Lx + s_cidx[0][cx + 1];
-          const double gx = (double)max(0ll, max(xl - bx1, (long long)bx0 - xh));
-          if (gyz + gx * gx > rl2d) {
-            ++ux;
-            if (++cx == ncx) { cx = 0; ++ix; }
-            continue;
-          }
-          int ce = cx;  // last cell of the run
-          while (ux + (ce - cx) + 1 <= ux1 && ce + 1 < ncx) {
-            // cells to the right only grow apart from the box
-            const double gx2 = (double)max(0ll, (long long)ix * Lx + s_cidx[0][ce + 1] - (long long)bx1);
-            if (gyz + gx2 * gx2 > rl2d) break;
-            ++ce;
-          }
-          const int c0 = (cz * ncy + cy) * ncx + cx;
-          const int q0 = cstart[c0], q1 = cstart[c0 + (ce - cx) + 1];
-          const int six = ix, siy = iy, siz = iz;
-          ux += ce - cx + 1;
-          cx = ce + 1;
-          if (cx == ncx) { cx = 0; ++ix; }
-          for (int qb = q0; qb < q1; qb += kBlk) {
-            // ---- load 64 candidates, keep those within the list radius of the box
-            const int q = qb + lane;
-            bool keep = false;
-            float4 cpos = make_float4(0.f, 0.f, 0.f, 0.f);
-            uint32_t code = 0u;
-            if (q < q1) {
-              const int4 cxq = cellx_t[off + q];
-              const int2 jw = celljw_t[off + q];
-              const int px = cxq.x + six * Lx, py = cxq.y + siy * Ly, pz = cxq.z + siz * Lz;
-              // kept if within the list radius of a quarter box; a box distance
-              // never exceeds an atom distance, also after rounding
+  // Fast mode stages every candidate kept by the quarter boxes.  If that
+  // would exceed the block's staging capacity, the block is built again in
+  // exact mode, which stages only candidates within the list radius of at
+  // least one atom (a ballot per candidate; rare).
+  bool exact = false;
+  for (int mode = 0; mode < 2; ++mode) {
+    exact = mode == 1;
+    nst = 0;
+    cnt = 0;
+    pend = 0ull;
+    bool full = false;
+    int iz = uz0 >= 0 ? uz0 / ncz : -((-uz0 + ncz - 1) / ncz);
+    int cz = uz0 - iz * ncz;
+    for (int uz = uz0; uz <= uz1 && !full; ++uz) {
+      // gap between the cell's slab and the block box along z (coordinate units)
+      const long long zl = (long long)iz * Lz + s_cidx[2][cz], zh = (long long)iz * Lz + s_cidx[2][cz + 1];
+      const double gz = (double)max(0ll, max(zl - bz1, (long long)bz0 - zh));
+      int iy = uy0 >= 0 ? uy0 / ncy : -((-uy0 + ncy - 1) / ncy);
+      int cy = uy0 - iy * ncy;
+      for (int uy = uy0; uy <= uy1 && !full; ++uy) {
+        const long long yl = (long long)iy * Ly + s_cidx[1][cy], yh = (long long)iy * Ly + s_cidx[1][cy + 1];
+        const double gy = (double)max(0ll, max(yl - by1, (long long)by0 - yh));
+        const double gyz = gz * gz + gy * gy;
+        if (gyz <= rl2d) {
+          int ix = ux0 >= 0 ? ux0 / ncx : -((-ux0 + ncx - 1) / ncx);
+          int cx = ux0 - ix * ncx;
+          int ux = ux0;
+          while (ux <= ux1 && !full) {
+            // the next run of cells of this row that pass the gap test and share an image
+            const long long xl = (long long)ix * Lx + s_cidx[0][cx], xh = (long long)ix * Lx + s_cidx[0][cx + 1];
+            const double gx = (double)max(0ll, max(xl - bx1, (long long)bx0 - xh));
+            if (gyz + gx * gx > rl2d) {
+              ++ux;
+              if (++cx == ncx) { cx = 0; ++ix; }
+              continue;
+            }
+            int ce = cx;  // last cell of the run
+            while (ux + (ce - cx) + 1 <= ux1 && ce + 1 < ncx) {
+              // cells to the right only grow apart from the box
+              const double gx2 = (double)max(0ll, (long long)ix * Lx + s_cidx[0][ce + 1] - (long long)bx1);
+              if (gyz + gx2 * gx2 > rl2d) break;
+              ++ce;
+            }
+            const int c0 = (cz * ncy + cy) * ncx + cx;
+            const int q0 = cstart[c0], q1 = cstart[c0 + (ce - cx) + 1];
+            const int six = ix, siy = iy, siz = iz;
+            ux += ce - cx + 1;
+            cx = ce + 1;
+            if (cx == ncx) { cx = 0; ++ix; }
+            for (int qb = q0; qb < q1 && !full; qb += kBlk) {
+              // ---- load 64 candidates, keep those near one of the quarter boxes
+              const int q = qb + lane;
+              bool keep = false;
+              float4 cpos = make_float4(0.f, 0.f, 0.f, 0.f);
+              uint32_t code = 0u;
+              if (q < q1) {
+                const int4 cxq = cellx_t[off + q];
+                const int2 jw = celljw_t[off + q];
+                const int px = cxq.x + six * Lx, py = cxq.y + siy * Ly, pz = cxq.z + siz * Lz;
+                // kept if within the list radius of a quarter box; a box distance
+                // never exceeds an atom distance, also after rounding
 #pragma unroll
-              for (int g = 0; g < 4; ++g) {
-                const float gxq = (float)max(0, max(sb[g][0] - px, px - sb[g][1]));
-                const float gyq = (float)max(0, max(sb[g][2] - py, py - sb[g][3]));
-                const float gzq = (float)max(0, max(sb[g][4] - pz, pz - sb[g][5]));
-                keep = keep || (sbact[g] && qr2(gxq, gyq, gzq) < rl2);
-              }
-              const int sx = six - unpack_wrap(jw.y, 0), sy = siy - unpack_wrap(jw.y, 1),
-                        sz = siz - unpack_wrap(jw.y, 2);
-              if (keep && (sx < -16 || sx > 15 || sy < -16 || sy > 15 || sz < -16 || sz > 15)) {
-                bad = true;  // shift not representable: the replica is flagged
-                keep = false;
-              }
-              cpos = make_float4((float)(px - bx0), (float)(py - by0), (float)(pz - bz0),
-                                 __int_as_float(cxq.w));
-              code = (uint32_t)jw.x | ((uint32_t)((sx + 16) & 31) << 16) |
-                     ((uint32_t)((sy + 16) & 31) << 21) | ((uint32_t)((sz + 16) & 31) << 26);
-            }
-            const uint64_t km = __ballot(keep);
-            const int at = __popcll(km & ((1ull << lane) - 1ull));
-            int nk = __popcll(km);
-            if (nst + nk > cap) {  // staging full: the rest is dropped and the replica flagged
-              bad = true;
-              nk = cap - nst;
-            }
-            // every kept candidate is staged, in range order
-            if (keep && at < nk) {
-              s_pos[at] = cpos;
-              stg[nst + at] = code;
-            }
-            __syncthreads();
-            // ---- every staged candidate against the lane's own atom
-            if (!anyfar) {
-              for (int k = 0; k < nk; ++k) {
-                const float4 c = s_pos[k];
-                const float dx = c.x - ax, dy = c.y - ay, dz = c.z - az;
-                const int d = __float_as_int(c.w) - a32;
-                const bool exw = (unsigned)d < 64u && ((exm >> (d & 63)) & 1ull);
-                if (qr2(dx, dy, dz) < rl2x && !exw) {
-                  pend = (pend << 16) | (uint64_t)(uint32_t)(nst + k);
-                  ++cnt;  // entries past maxnb are counted only to flag the overflow
-                  if ((cnt & 3) == 0 && cnt <= maxnb) list_store4(lst, cnt - 4, lane, pend);
+                for (int g = 0; g < 4; ++g) {
+                  const float gxq = (float)max(0, max(sb[g][0] - px, px - sb[g][1]));
+                  const float gyq = (float)max(0, max(sb[g][2] - py, py - sb[g][3]));
+                  const float gzq = (float)max(0, max(sb[g][4] - pz, pz - sb[g][5]));
+                  keep = keep || (sbact[g] && qr2(gxq, gyq, gzq) < rl2);
                 }
-              }
-            } else {
-              for (int k = 0; k < nk; ++k) {
-                const float4 c = s_pos[k];
-                const float dx = c.x - ax, dy = c.y - ay, dz = c.z - az;
-                const int oj = __float_as_int(c.w);
-                const int d = oj - a32;
-                const bool win = (unsigned)d < 64u;
-                bool in = qr2(dx, dy, dz) < rl2x && !(win && ((exm >> (d & 63)) & 1ull));
-                if (in && !win && exfar)
-                  for (int e = e0; e < e1; ++e) in = in && (ex_list[e] != oj);
-                if (in) {
-                  pend = (pend << 16) | (uint64_t)(uint32_t)(nst + k);
-                  ++cnt;
-                  if ((cnt & 3) == 0 && cnt <= maxnb) list_store4(lst, cnt - 4, lane, pend);
+                const int sx = six - unpack_wrap(jw.y, 0), sy = siy - unpack_wrap(jw.y, 1),
+                          sz = siz - unpack_wrap(jw.y, 2);
+                if (keep && (sx < -16 || sx > 15 || sy < -16 || sy > 15 || sz < -16 || sz > 15)) {
+                  bad = true;  // shift not representable: the replica is flagged
+                  keep = false;
                 }
+                cpos = make_float4((float)(px - bx0), (float)(py - by0), (float)(pz - bz0),
+                                   __int_as_float(cxq.w));
+                code = (uint32_t)jw.x | ((uint32_t)((sx + 16) & 31) << 16) |
+                       ((uint32_t)((sy + 16) & 31) << 21) | ((uint32_t)((sz + 16) & 31) << 26);
               }
+              const uint64_t km = __ballot(keep);
+              const int at = __popcll(km & ((1ull << lane) - 1ull));
+              const int nk = __popcll(km);
+              if (!exact && nst + nk > cap) {
+                full = true;  // uniform: the block is redone in exact mode
+                break;
+              }
+              if (keep) s_pos[at] = cpos;
+              if (!exact && keep) stg[nst + at] = code;  // every kept candidate is staged
+              __syncthreads();
+              if (!exact) {
+                // ---- every staged candidate against the lane's own atom
+                if (!anyfar) {
+                  for (int k = 0; k < nk; ++k) {
+                    const float4 c = s_pos[k];
+                    const float dx = c.x - ax, dy = c.y - ay, dz = c.z - az;
+                    const int d = __float_as_int(c.w) - a32;
+                    const bool exw = (unsigned)d < 64u && ((exm >> (d & 63)) & 1ull);
+                    if (qr2(dx, dy, dz) < rl2x && !exw) {
+                      pend = (pend << 16) | (uint64_t)(uint32_t)(nst + k);
+                      ++cnt;  // entries past maxnb are counted only to flag the overflow
+                      if ((cnt & 3) == 0 && cnt <= maxnb) list_store4(lst, cnt - 4, lane, pend);
+                    }
+                  }
+                } else {
+                  for (int k = 0; k < nk; ++k) {
+                    const float4 c = s_pos[k];
+                    const float dx = c.x - ax, dy = c.y - ay, dz = c.z - az;
+                    const int oj = __float_as_int(c.w);
+                    const int d = oj - a32;
+                    const bool win = (unsigned)d < 64u;
+                    bool in = qr2(dx, dy, dz) < rl2x && !(win && ((exm >> (d & 63)) & 1ull));
+                    if (in && !win && exfar)
+                      for (int e = e0; e < e1; ++e) in = in && (ex_list[e] != oj);
+                    if (in) {
+                      pend = (pend << 16) | (uint64_t)(uint32_t)(nst + k);
+                      ++cnt;
+                      if ((cnt & 3) == 0 && cnt <= maxnb) list_store4(lst, cnt - 4, lane, pend);
+                    }
+                  }
+                }
+                nst += nk;
+              } else {
+                // ---- exact mode: a candidate is staged only if some atom needs it
+                const int nst0 = nst;
+                uint64_t acc = 0ull;
+                for (int k = 0; k < nk; ++k) {
+                  const float4 c = s_pos[k];
+                  const float dx = c.x - ax, dy = c.y - ay, dz = c.z - az;
+                  const int oj = __float_as_int(c.w);
+                  const int d = oj - a32;
+                  const bool win = (unsigned)d < 64u;
+                  bool in = qr2(dx, dy, dz) < rl2x && !(win && ((exm >> (d & 63)) & 1ull));
+                  if (in && !win && exfar)
+                    for (int e = e0; e < e1; ++e) in = in && (ex_list[e] != oj);
+                  if (__ballot(in)) {
+                    if (nst < cap) {
+                      if (in) {
+                        pend = (pend << 16) | (uint64_t)(uint32_t)nst;
+                        ++cnt;
+                        if ((cnt & 3) == 0 && cnt <= maxnb) list_store4(lst, cnt - 4, lane, pend);
+                      }
+                      acc |= 1ull << k;
+                      ++nst;
+                    } else {
+                      bad = true;  // staging full even in exact mode: the replica is flagged
+                    }
+                  }
+                }
+                if (keep && ((acc >> at) & 1ull)) stg[nst0 + __popcll(acc & ((1ull << at) - 1ull))] = code;
+              }
+              __syncthreads();
             }
-            nst += nk;
-            __syncthreads();
           }
         }
+        if (++cy == ncy) { cy = 0; ++iy; }
       }
-      if (++cy == ncy) { cy = 0; ++iy; }
+      if (++cz == ncz) { cz = 0; ++iz; }
     }
-    if (++cz == ncz) { cz = 0; ++iz; }
+    if (!full) break;
   }
   if (cnt > maxnb - 8) {
     bad = true;
@@ -555,11 +603,17 @@ __global__ __launch_bounds__(kBlk) void k_list(const RepInfo *__restrict__ info,
       if ((cnt & 3) == 0) list_store4(lst, cnt - 4, lane, pend);
     }
   }
+  const int cmax = wave_max_i(active ? cnt : 0);
   W.nbcnt[slot] = active ? cnt : 0;
   if (lane == 0) W.stage_n[b] = nst;
   if (__ballot(bad) && lane == 0) {
     if (MODE == 0) atomicOr(&state[r].status, VP_REPLICA_LIST_OVERFLOW);
     else atomicOr(&W.flags[r], 2);
+  }
+  if (MODE == 0 && lane == 0) {
+    atomicMax(&state[r].stage_max, nst);
+    atomicMax(&state[r].list_max, cmax);
+    if (exact) atomicAdd(&state[r].exact_builds, 1);
   }
   if (!active) return;
   // the new order becomes the state
@@ -567,6 +621,11 @@ __global__ __launch_bounds__(kBlk) void k_list(const RepInfo *__restrict__ info,
   if (MODE == 0) {
     W.vel[slot] = vel_t[slot];
     W.xref[slot] = xi;
+    if (W.tx)
+      for (int d = 0; d < 2; ++d) {
+        W.tx[d * W.fstride + slot] = tx_t[d * W.fstride + slot];
+        W.tv[d * W.fstride + slot] = tv_t[d * W.fstride + slot];
+      }
   }
   W.orig[slot] = a;
   W.wrap[slot] = wrap_t[slot];
@@ -629,11 +688,11 @@ void launch_rebuild(vp_system *s, Work &W, int mode, const float *x_user, hipStr
     hipLaunchKernelGGL(k_permute<0>, dim3(xcd_grid(s->n_tiles)), dim3(kBlock), 0, st, s->info,
                        s->state, W, s->tile_rep, s->tile_first, s->n_tiles, x_user, s->type0,
                        s->orig_t, s->xq_t, s->vel_t, s->wrap_t, s->cellpos_t, s->cellx_t,
-                       s->celljw_t);
+                       s->celljw_t, s->tx_t, s->tv_t);
     hipLaunchKernelGGL(k_list<0>, dim3(xcd_grid(s->n_blocks)), dim3(kBlk), 0, st, s->info,
                        s->state, W, s->tile_rep, s->tile_first, s->n_blocks, s->xq_t, s->vel_t,
                        s->orig_t, s->wrap_t, s->cellx_t, s->celljw_t, s->ex_start, s->ex_list,
-                       s->integ0);
+                       s->integ0, s->tx_t, s->tv_t);
   } else {
     hipLaunchKernelGGL(k_bin<1>, dim3(s->R), dim3(kBinThreads), 0, st, s->info, s->state, W,
                        x_user, s->cellid_t, s->zkey_t, s->fcell_t, s->bucket_t, s->bkey_t,
@@ -641,11 +700,11 @@ void launch_rebuild(vp_system *s, Work &W, int mode, const float *x_user, hipStr
     hipLaunchKernelGGL(k_permute<1>, dim3(xcd_grid(s->n_tiles)), dim3(kBlock), 0, st, s->info,
                        s->state, W, s->tile_rep, s->tile_first, s->n_tiles, x_user, s->type0,
                        s->orig_t, s->xq_t, s->vel_t, s->wrap_t, s->cellpos_t, s->cellx_t,
-                       s->celljw_t);
+                       s->celljw_t, s->tx_t, s->tv_t);
     hipLaunchKernelGGL(k_list<1>, dim3(xcd_grid(s->n_blocks)), dim3(kBlk), 0, st, s->info,
                        s->state, W, s->tile_rep, s->tile_first, s->n_blocks, s->xq_t, s->vel_t,
                        s->orig_t, s->wrap_t, s->cellx_t, s->celljw_t, s->ex_start, s->ex_list,
-                       s->integ0);
+                       s->integ0, s->tx_t, s->tv_t);
   }
 }
 

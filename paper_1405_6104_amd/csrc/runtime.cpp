@@ -59,7 +59,7 @@ vp_status upload(vp_system *s, T **p, const std::vector<T> &h) {
     if (s_ != VP_OK) return s_;       \
   } while (0)
 
-vp_status validate(const vp_replica_desc &d, int r) {
+vp_status validate(const vp_replica_desc &d, int r, bool tangent) {
   auto bad = [&](const std::string &m) { return fail(VP_ERR_ARG, "replica " + std::to_string(r) + ": " + m); };
   if (d.n_atoms <= 0 || d.n_atoms > 65536) return bad("n_atoms must be in [1, 65536]");
   if (d.n_solute < 0 || d.n_solute > d.n_atoms) return bad("n_solute out of range");
@@ -92,6 +92,8 @@ vp_status validate(const vp_replica_desc &d, int r) {
     for (int k = 0; k < 2; ++k)
       if (d.excl[2 * b + k] < 0 || d.excl[2 * b + k] >= d.n_atoms) return bad("excluded index out of range");
   if (d.bias < VP_BIAS_NONE || d.bias > VP_BIAS_RMD_CONTACT) return bad("unknown bias kind");
+  if (tangent && d.bias == VP_BIAS_RMD_CONTACT)
+    return bad("derivatives are not available for the ratchet bias (its running minimum is not differentiable)");
   if ((d.bias == VP_BIAS_CONTACT || d.bias == VP_BIAS_RMD_CONTACT)) {
     if (!d.x_final) return bad("contact-map bias needs x_final");
     if (d.n_solute > kMaxCvBlocks * kCvTile) return bad("too many solute atoms for the contact map");
@@ -136,6 +138,26 @@ static vp_status alloc_work(vp_system *s, Work &W, bool traj) {
   TRY(dalloc(s, &W.gpart, R * kMaxCvBlocks));
   TRY(dalloc(s, &W.epart, 4 * B));
   TRY(dalloc(s, &W.flags, R));
+  if (s->tangent) {
+    const size_t CT = (size_t)std::max<int64_t>(1, s->n_cv_tiles) * kCvTile;
+    const size_t NS = (size_t)std::max<int64_t>(1, s->n_solute_total);
+    W.cvstride = (int64_t)CT;
+    W.solstride = (int64_t)NS;
+    TRY(dalloc(s, &W.tx, 2 * S));
+    TRY(dalloc(s, &W.tv, 2 * S));
+    TRY(dalloc(s, &W.tf, 2 * S));
+    TRY(dalloc(s, &W.tg, 2 * NS));
+    TRY(dalloc(s, &W.tgtile, 2 * CT));
+    TRY(dalloc(s, &W.tzpart, 2 * R * kMaxCvBlocks));
+    TRY(dalloc(s, &W.tgpart, 2 * R * kMaxCvBlocks));
+    HIPCHECK(hipMemset(W.tx, 0, sizeof(float4) * 2 * S));
+    HIPCHECK(hipMemset(W.tv, 0, sizeof(float4) * 2 * S));
+    HIPCHECK(hipMemset(W.tf, 0, sizeof(float4) * 2 * S));
+    HIPCHECK(hipMemset(W.tg, 0, sizeof(float4) * 2 * NS));
+    HIPCHECK(hipMemset(W.tgtile, 0, sizeof(float4) * 2 * CT));
+    HIPCHECK(hipMemset(W.tzpart, 0, sizeof(double) * 2 * R * kMaxCvBlocks));
+    HIPCHECK(hipMemset(W.tgpart, 0, sizeof(double) * 2 * R * kMaxCvBlocks));
+  }
   HIPCHECK(hipMemset(W.nbcnt, 0, sizeof(int32_t) * S));
   HIPCHECK(hipMemset(W.stage_n, 0, sizeof(int32_t) * B));
   HIPCHECK(hipMemset(W.orig, 0xff, sizeof(int32_t) * S));
@@ -323,15 +345,40 @@ static vp_status build(vp_system *s, const vp_replica_desc *reps, int32_t n_reps
   s->n_cv_tiles = cv_tiles;
   s->n_tiles = tile0;
   s->n_blocks = tile0 * (kTile / kBlk);
-  s->stage_cap_max = stage_cap_max;
   s->ntypes_max = ntypes_max;
   {
-    // the force kernel's dynamic LDS (staged neighbourhood) plus its static
-    // LDS stays within 64 KB per workgroup
+    // Staging capacity: every block may use the LDS that still lets two
+    // force workgroups share a CU (up to the staging array's size), and never
+    // less than the estimate above; a block whose candidates would overflow
+    // it is built again in exact mode.
+    const long long budget =
+        ((long long)kMaxLds - (long long)sizeof(double) * (kForceThreads / 64)) / (long long)sizeof(int4) -
+        (ntypes_max + 1) - 1;
+    stage_cap_max = 0;
+    for (int r = 0; r < n_reps; ++r) {
+      RepInfo &R = s->info_h[r];
+      const long long want = std::min<long long>({(long long)kMaxStage, budget, 27ll * R.n + 8});
+      if (want < R.stage_cap)
+        return fail(VP_ERR_ARG, "replica " + std::to_string(r) + ": its neighbourhoods need " +
+                                    std::to_string(R.stage_cap) + " staged atoms; the force kernel's LDS holds " +
+                                    std::to_string(want));
+      R.stage_cap = (int32_t)want;
+      stage_cap_max = std::max(stage_cap_max, R.stage_cap);
+    }
+    s->stage_cap_max = stage_cap_max;
     size_t need = force_lds_bytes(s) + sizeof(double) * (kForceThreads / 64);
     if (need > (size_t)kMaxLds)
       return fail(VP_ERR_ARG, "force kernel would need " + std::to_string(need) +
                                   " bytes of LDS per workgroup (limit " + std::to_string(kMaxLds) + ")");
+    HIPCHECK(prepare_forces(s));
+    if (s->tangent) {
+      const size_t tneed = tangent_lds_bytes(s);
+      if (tneed > (size_t)kMaxLdsTangent)
+        return fail(VP_ERR_ARG, "tangent force kernel would need " + std::to_string(tneed) +
+                                    " bytes of LDS per workgroup (limit " +
+                                    std::to_string(kMaxLdsTangent) + ")");
+      HIPCHECK(prepare_tangent(s));
+    }
   }
 
   // ---------------- constant per-atom data (user order)
@@ -442,6 +489,10 @@ static vp_status build(vp_system *s, const vp_replica_desc *reps, int32_t n_reps
   TRY(dalloc(s, &s->cellpos_t, S));
   TRY(dalloc(s, &s->cellx_t, S));
   TRY(dalloc(s, &s->celljw_t, S));
+  if (s->tangent) {
+    TRY(dalloc(s, &s->tx_t, 2 * S));
+    TRY(dalloc(s, &s->tv_t, 2 * S));
+  }
   TRY(dalloc(s, &s->step, 1));
   HIPCHECK(hipMemset(s->step, 0, sizeof(long long)));
   TRY(alloc_work(s, s->traj, true));
@@ -459,7 +510,7 @@ static vp_status build(vp_system *s, const vp_replica_desc *reps, int32_t n_reps
   launch_init_state(s, dx, dv, dhv, 0);
   launch_rebuild(s, s->traj, 0, nullptr, 0);
   launch_forces(s, s->traj, false, 0);
-  launch_cv(s, s->traj, 0, 0);
+  launch_cv(s, s->traj, 0, 0, s->tangent);
   launch_integrate(s, INT_INIT, 0);
   HIPCHECK(hipGetLastError());
   HIPCHECK(hipDeviceSynchronize());
@@ -474,7 +525,7 @@ extern "C" vp_status vp_system_create(const vp_replica_desc *reps, int32_t n_rep
   if (n_reps <= 0) return fail(VP_ERR_ARG, "n_reps must be positive");
   int64_t total = 0;
   for (int r = 0; r < n_reps; ++r) {
-    vp_status st = validate(reps[r], r);
+    vp_status st = validate(reps[r], r, opt && opt->tangent != 0);
     if (st != VP_OK) return st;
     total += reps[r].n_atoms;
   }
@@ -488,6 +539,7 @@ extern "C" vp_status vp_system_create(const vp_replica_desc *reps, int32_t n_rep
   if (o.steps_per_graph <= 0) o.steps_per_graph = 20;
   if (!opt) o.use_graph = 1;
   s->opt = o;
+  s->tangent = o.tangent != 0;
   vp_status st = build(s, reps, n_reps);
   if (st != VP_OK) {
     std::string msg = g_err;
@@ -517,7 +569,8 @@ static void enqueue_block(vp_system *s, int steps, hipStream_t st) {
     if (timing) (void)hipEventRecord(s->ev_before[k], st);
     launch_forces(s, s->traj, false, st);
     if (timing) (void)hipEventRecord(s->ev_after[k], st);
-    launch_cv(s, s->traj, 1, st);
+    if (s->tangent) launch_tangent_forces(s, s->traj, st);
+    launch_cv(s, s->traj, 1, st, s->tangent);
   }
   launch_integrate(s, INT_FINISH, st);
 }
@@ -599,10 +652,38 @@ static double phi_of(const RepInfo &R, const RepState &S) {
 
 extern "C" vp_status vp_functional(vp_system *s, double *phi_host, double *dphi_dtheta_host) {
   if (!s || !phi_host) return fail(VP_ERR_ARG, "NULL argument");
-  if (dphi_dtheta_host) return fail(VP_ERR_ARG, "functional gradient is not available in this build");
+  if (dphi_dtheta_host && !s->tangent)
+    return fail(VP_ERR_STATE, "the functional gradient needs derivatives enabled at creation (vp_options.tangent)");
   std::vector<RepState> st;
   TRY(fetch_state(s, st));
-  for (int r = 0; r < s->R; ++r) phi_host[r] = phi_of(s->info_h[r], st[r]);
+  for (int r = 0; r < s->R; ++r) {
+    const RepInfo &R = s->info_h[r];
+    phi_host[r] = phi_of(R, st[r]);
+    if (dphi_dtheta_host)
+      for (int d = 0; d < 2; ++d)
+        dphi_dtheta_host[2 * r + d] = (st[r].status & VP_REPLICA_UNSTABLE)
+                                          ? NAN
+                                          : (st[r].pd_acc[d] - 0.5 * st[r].pd_last[d]) * R.dt / (4.0 * R.kT);
+  }
+  return VP_OK;
+}
+
+extern "C" vp_status vp_debug_force_dir(vp_system *s, const float *x_dev, const float *dx_dev,
+                                        float *out_dev, double t, void *hip_stream) {
+  if (!s || !x_dev || !dx_dev || !out_dev) return fail(VP_ERR_ARG, "NULL argument");
+  if (!s->tangent) return fail(VP_ERR_STATE, "derivatives were not enabled at creation (vp_options.tangent)");
+  hipStream_t st = (hipStream_t)hip_stream;
+  if (!s->eval_ready) {
+    HIPCHECK(hipDeviceSynchronize());
+    TRY(alloc_work(s, s->eval, false));
+    s->eval_ready = true;
+  }
+  s->last_stream = st;
+  launch_rebuild(s, s->eval, 1, x_dev, st);
+  launch_forces(s, s->eval, false, st);
+  launch_cv(s, s->eval, 0, st, false);
+  launch_force_dir(s, s->eval, dx_dev, t, out_dev, st);
+  HIPCHECK(hipGetLastError());
   return VP_OK;
 }
 
@@ -639,7 +720,7 @@ extern "C" vp_status vp_forces(vp_system *s, const float *x_dev, float *f_dev, d
   s->last_stream = st;
   launch_rebuild(s, s->eval, 1, x_dev, st);
   launch_forces(s, s->eval, energy_dev != nullptr, st);
-  launch_cv(s, s->eval, 0, st);
+  launch_cv(s, s->eval, 0, st, false);
   launch_force_out(s, s->eval, t, f_dev, energy_dev, st);
   HIPCHECK(hipGetLastError());
   return VP_OK;
@@ -680,6 +761,11 @@ extern "C" vp_status vp_observables(vp_system *s, double *obs) {
     o[VP_OBS_STATUS] = st[r].status;
     o[VP_OBS_REBUILDS] = st[r].rebuilds;
     o[VP_OBS_KE] = k;
+    o[VP_OBS_STAGE_MAX] = st[r].stage_max;
+    o[VP_OBS_STAGE_CAP] = R.stage_cap;
+    o[VP_OBS_LIST_MAX] = st[r].list_max;
+    o[VP_OBS_LIST_CAP] = R.maxnb;
+    o[VP_OBS_EXACT_BUILDS] = st[r].exact_builds;
   }
   return VP_OK;
 }

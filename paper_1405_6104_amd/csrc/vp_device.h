@@ -168,6 +168,43 @@ __device__ __forceinline__ double bias_coef(const RepInfo &R, double z, double z
   return 0.0;
 }
 
+// Derivatives of the bias coefficient c of bias_coef for the harmonic kinds:
+// dc/dz and the explicit dc/dtheta_p, theta = (bias_k, ramp_rate), with
+//   c = -k (z - z_ref),  z_ref = z_t + (z_0 - z_t) max(0, 1 - rho t),
+// so dc/dk = -(z - z_ref) and dc/drho = -k (z_0 - z_t) t while the ramp runs.
+// Other kinds: zero (constant force) -- the ratchet is not differentiated.
+__device__ __forceinline__ void bias_coef_deriv(const RepInfo &R, double z, double z0, double t,
+                                                bool init, double &dcdz, double dcdth[2]) {
+  dcdz = 0.0;
+  dcdth[0] = dcdth[1] = 0.0;
+  if (R.bias == VP_BIAS_RG || R.bias == VP_BIAS_CONTACT) {
+    const double zz0 = init ? z : z0;
+    const double w = 1.0 - R.ramp_rate * t;
+    const double zr = R.z_target + (zz0 - R.z_target) * (w < 0.0 ? 0.0 : w);
+    dcdz = -R.bias_k;
+    dcdth[0] = -(z - zr);
+    dcdth[1] = w < 0.0 ? 0.0 : -R.bias_k * (zz0 - R.z_target) * t;
+  }
+}
+
+// Value and one directional derivative (forward-mode differentiation of the
+// FP64 bonded terms along a tangent).
+struct dual1 {
+  double v, d;
+};
+__device__ __forceinline__ dual1 operator+(dual1 a, dual1 b) { return {a.v + b.v, a.d + b.d}; }
+__device__ __forceinline__ dual1 operator-(dual1 a, dual1 b) { return {a.v - b.v, a.d - b.d}; }
+__device__ __forceinline__ dual1 operator*(dual1 a, dual1 b) { return {a.v * b.v, a.d * b.v + a.v * b.d}; }
+__device__ __forceinline__ dual1 operator*(double s, dual1 a) { return {s * a.v, s * a.d}; }
+__device__ __forceinline__ dual1 operator/(dual1 a, dual1 b) {
+  const double q = a.v / b.v;
+  return {q, (a.d - q * b.d) / b.v};
+}
+__device__ __forceinline__ dual1 dsqrt(dual1 a) {
+  const double r = sqrt(a.v);
+  return {r, a.d / (2.0 * r)};
+}
+
 // Map a launch-order workgroup index to a tile (or block) so that consecutive tiles of one
 // replica run on the same XCD (blocks are dealt round-robin over 8 XCDs).
 __device__ __forceinline__ int xcd_tile(int b, int nb) {

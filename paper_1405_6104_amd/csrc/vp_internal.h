@@ -18,7 +18,8 @@ constexpr int kForceThreads = kParts * kBlk;
 constexpr int kBinThreads = 1024;    // workgroup of the binning kernel
 constexpr int kMaxCells = 4096;      // cells per replica held in LDS by the binning kernel
 constexpr int kMaxStage = 4093;      // staged neighbourhood atoms per block (LDS, + 1 inert entry)
-constexpr int kMaxLds = 65536;       // LDS bytes per workgroup used by any kernel
+constexpr int kMaxLds = 81920;       // LDS bytes per force workgroup (two share a 160 KB CU)
+constexpr int kMaxLdsTangent = 163840;  // LDS bytes per workgroup of the tangent force kernel
 constexpr int kMaxCols = 256;        // xy columns per replica (sort order)
 constexpr int kMaxTypes = 1024;      // (charge, sigma, epsilon) classes per replica
 constexpr int kCvBlock = 256;        // workgroup of the single-workgroup CV kinds (Rg, constant)
@@ -82,7 +83,13 @@ struct RepState {
   int32_t rebuild;        // 1 when this step rebuilds the pair list
   int32_t force_rebuild;
   int32_t rebuilds;
+  int32_t stage_max;     // largest staged neighbourhood of a block so far
+  int32_t list_max;      // longest per-atom list so far (entries, padded)
+  int32_t exact_builds;  // blocks built again in exact mode (staging capacity reached)
   int32_t pad;
+  // derivative of the functional with respect to (bias_k, ramp_rate)
+  double pd_acc[2];   // sum_n w_n dS_n/dtheta, w_0 = 1/2
+  double pd_last[2];  // dS/dtheta at the latest step
 };
 
 // One bonded contribution evaluated by the atom that owns it.
@@ -118,6 +125,17 @@ struct Work {
   double *gpart = nullptr;        // [R][kMaxCvBlocks] sum |g|^2/(gamma m)
   double *epart = nullptr;        // [blocks][4] energy partials (LJ, RF, bond, angle)
   int32_t *flags = nullptr;       // [R] rebuild flag for the eval context
+  // tangents along (bias_k, ramp_rate) when derivatives are on: [2][slots]
+  // (index p * fstride + slot), xyz used
+  int64_t cvstride = 0;     // entries per direction of tgtile (cv tiles * 64)
+  int64_t solstride = 0;    // entries per direction of tg (solute total)
+  float4 *tx = nullptr;     // dx/dtheta_p
+  float4 *tv = nullptr;     // dv/dtheta_p
+  float4 *tf = nullptr;     // -H_U dx/dtheta_p (potential part of the tangent force)
+  float4 *tg = nullptr;     // [2][solute total] (d grad z)[dx/dtheta_p]
+  float4 *tgtile = nullptr; // [2][cv tiles * 64] partials of tg per column tile
+  double *tzpart = nullptr; // [R][kMaxCvBlocks][2] parts of dz/dtheta_p = grad z . dx/dtheta_p
+  double *tgpart = nullptr; // [R][kMaxCvBlocks][2] parts of sum_i 2 g_i . tg_i / (gamma_i m_i)
 };
 
 // packed periodic image (3 x 10-bit signed)
@@ -172,11 +190,14 @@ struct vp_system {
   int32_t *bkey_t = nullptr;    // [slots] z keys in bucket order
   int32_t *borig_t = nullptr;   // [slots] user indices in bucket order
   int32_t *cellpos_t = nullptr; // [slots] position of each new slot in fine-cell order
+  float4 *tx_t = nullptr;       // [2][slots] tangents in the new order (rebuild)
+  float4 *tv_t = nullptr;
   int4 *cellx_t = nullptr;      // [slots] fine-cell order: wrapped x, y, z and user index
   int2 *celljw_t = nullptr;     // [slots] fine-cell order: slot and packed image
   long long *step = nullptr;  // device step counter
   vp::Work traj, eval;
   bool eval_ready = false;
+  bool tangent = false;  // derivatives of the functional are propagated
   struct GraphEntry {
     int32_t steps;
     hipStream_t stream;

@@ -11,15 +11,23 @@ void launch_rebuild(vp_system *s, Work &W, int mode, const float *x_user, hipStr
 void launch_debug_pairs(vp_system *s, Work &W, int rep, int2 *out, unsigned long long cap,
                         unsigned long long *counter, hipStream_t st);
 void launch_forces(vp_system *s, Work &W, bool energy, hipStream_t st);
-void launch_cv(vp_system *s, Work &W, int inc_step, hipStream_t st);
+void launch_cv(vp_system *s, Work &W, int inc_step, hipStream_t st, bool tan);
+// derivatives along the tangents in W.tx (both directions)
+void launch_tangent_forces(vp_system *s, Work &W, hipStream_t st);
+size_t tangent_lds_bytes(const vp_system *s);
+hipError_t prepare_tangent(const vp_system *s);
+// total force derivative along user-order directions dx_user [2][users][3] (eval context)
+void launch_force_dir(vp_system *s, Work &W, const float *dx_user, double t, float *out,
+                      hipStream_t st);
 void launch_force_out(vp_system *s, Work &W, double t, float *f_user, double *e_out,
                       hipStream_t st);
-void launch_integrate(vp_system *s, int mode, hipStream_t st);
+void launch_integrate(vp_system *s, int mode, hipStream_t st);  // tangents too when s->tangent
 void launch_init_state(vp_system *s, const int32_t *xq_user, const float *v_user,
                        const uint8_t *has_v, hipStream_t st);
 void launch_native_map(const float *xf, int ns, int min_sep, float r0, float rs, float rc,
                        float *out, hipStream_t st);
 size_t force_lds_bytes(const vp_system *s);
+hipError_t prepare_forces(const vp_system *s);  // dynamic LDS above 64 KB
 void launch_gather_state(vp_system *s, float *x_out, float *v_out, hipStream_t st);
 void launch_kinetic(vp_system *s, double *out, hipStream_t st);
 void launch_debug_noise(uint64_t seed, uint32_t atom0, uint32_t step, uint32_t tag, int n,

@@ -25,7 +25,8 @@ _dp = C.POINTER(C.c_double)
 _ip = C.POINTER(C.c_int32)
 
 BIAS_NONE, BIAS_CONST, BIAS_RG, BIAS_CONTACT, BIAS_RMD_CONTACT = 0, 1, 2, 3, 4
-OBS = ("step", "z", "z_ref", "z_min", "phi", "status", "rebuilds", "ke")
+OBS = ("step", "z", "z_ref", "z_min", "phi", "status", "rebuilds", "ke", "stage_max", "stage_cap",
+       "list_max", "list_cap", "exact_builds")
 ENERGY_COLUMNS = ("lj", "rf", "bond", "angle", "bias", "z", "z_ref", "S")
 REPLICA_UNSTABLE, REPLICA_LIST_OVERFLOW = 1, 2
 
@@ -60,7 +61,7 @@ class ReplicaDesc(C.Structure):
 class Options(C.Structure):
     _fields_ = [("nstlist", C.c_int32), ("skin", C.c_double), ("steps_per_graph", C.c_int32),
                 ("use_graph", C.c_int32), ("max_neighbors", C.c_int32),
-                ("reserved", C.c_int32 * 7)]
+                ("tangent", C.c_int32), ("reserved", C.c_int32 * 6)]
 
 
 _vp = C.c_void_p
@@ -91,6 +92,8 @@ _lib.vp_set_timing.restype = C.c_int
 _lib.vp_set_timing.argtypes = [_vp, C.c_int32]
 _lib.vp_kernel_timing.restype = C.c_int
 _lib.vp_kernel_timing.argtypes = [_vp, _dp, C.POINTER(C.c_int64), C.c_int32]
+_lib.vp_debug_force_dir.restype = C.c_int
+_lib.vp_debug_force_dir.argtypes = [_vp, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_void_p]
 _lib.vp_pair_count.restype = C.c_int
 _lib.vp_pair_count.argtypes = [_vp, C.c_int32, C.POINTER(C.c_int64)]
 _lib.vp_last_error.restype = C.c_char_p
@@ -99,7 +102,7 @@ _lib.vp_last_error.argtypes = []
 EXPORTED = ("vp_system_create", "vp_system_destroy", "vp_forces", "vp_step_batch",
             "vp_functional", "vp_select_path", "vp_get_state", "vp_observables", "vp_sizes",
             "vp_debug_pairs", "vp_debug_noise", "vp_set_timing", "vp_kernel_timing", "vp_pair_count",
-            "vp_last_error")
+            "vp_debug_force_dir", "vp_last_error")
 
 
 def _check(st):
@@ -160,12 +163,13 @@ class System:
     """A batch of trial trajectories (vp_system)."""
 
     def __init__(self, reps, nstlist=0, skin=0.0, steps_per_graph=0, use_graph=True,
-                 max_neighbors=0):
+                 max_neighbors=0, tangent=False):
         keep = []
         descs = (ReplicaDesc * len(reps))(*[_desc(d, keep) for d in reps])
         opt = Options()
         opt.nstlist, opt.skin, opt.steps_per_graph = nstlist, skin, steps_per_graph
         opt.use_graph, opt.max_neighbors = int(bool(use_graph)), max_neighbors
+        opt.tangent = int(bool(tangent))
         h = _vp()
         _check(_lib.vp_system_create(descs, len(reps), C.byref(opt), C.byref(h)))
         self._h = h
@@ -200,10 +204,23 @@ class System:
     def step_batch(self, n):
         _check(_lib.vp_step_batch(self._h, int(n), _stream()))
 
-    def functional(self):
+    def functional(self, gradient=False):
+        """Phi per replica; with gradient=True also dPhi/d(bias_k, ramp_rate)
+        as an [R, 2] array (needs tangent=True at creation)."""
         phi = np.zeros(self.n_reps)
-        _check(_lib.vp_functional(self._h, phi.ctypes.data_as(_dp), None))
-        return phi
+        g = np.zeros((self.n_reps, 2)) if gradient else None
+        _check(_lib.vp_functional(self._h, phi.ctypes.data_as(_dp), g.ctypes.data_as(_dp) if gradient else None))
+        return (phi, g) if gradient else phi
+
+    def force_dir(self, x, dx, t=0.0):
+        """Directional derivatives of the total force along dx ([2, N_total, 3]
+        float32 CUDA tensor), parameters fixed (needs tangent=True)."""
+        import torch
+        assert x.is_cuda and x.dtype == torch.float32 and x.is_contiguous() and x.shape == (self.n_total, 3)
+        assert dx.is_cuda and dx.dtype == torch.float32 and dx.is_contiguous() and dx.shape == (2, self.n_total, 3)
+        out = torch.empty_like(dx)
+        _check(_lib.vp_debug_force_dir(self._h, _ptr(x), _ptr(dx), _ptr(out), float(t), _stream()))
+        return out
 
     def select_path(self, eligible=None):
         """(best replica or -1, its functional)."""

@@ -7,8 +7,10 @@ Tolerances (stated per quantity):
                         max_i |dF_i| <= 1e-4 * rms|F|   (FP32 pair arithmetic)
   10-step trajectories  max |dx| <= 1e-4 nm
   functional            relative 1e-4 (plus 1e-12 absolute)
+  dPhi/d(k, rho), force directional derivatives   relative 1e-4
 Both sides start from the generator's inputs; the oracle is evaluated at the
-same FP32-rounded positions for single-frame comparisons.
+positions the library holds (FP32 values on its 2^-24 nm grid) for
+single-frame comparisons.
 """
 import math
 
@@ -333,3 +335,97 @@ def test_autograd_energy_backward_is_minus_force():
     e.sum().backward()
     f = system.forces(x.detach())
     assert torch.equal(x.grad, -f)
+
+
+# ------------------------------------------- derivative w.r.t. (bias_k, ramp_rate)
+G_REL = 1e-4  # functional gradients and their ingredients, relative to the FP64 oracle
+
+
+def _tangent_case(name):
+    return {"tiny": lambda: dict(synth.tiny(seed=31), bias_k=0.08, ramp_rate=30.0),
+            "tiny_rg": lambda: dict(synth.tiny(seed=32, bias=synth.BIAS_RG), ramp_rate=20.0),
+            "c1": synth.c1_small,
+            "c2": lambda: dict(synth.c2_single(), bias_k=0.05, ramp_rate=50.0)}[name]()
+
+
+@pytest.mark.parametrize("name", ["tiny", "tiny_rg", "c1", "c2"])
+def test_force_directional_derivative(name):
+    """-H_U dx + bias terms along two random displacements against the oracle's
+    dual-number derivative at the same (grid) positions."""
+    say("force derivative:", name)
+    d = _tangent_case(name)
+    system = vp.System([d], tangent=True)
+    x = f32(d["x0"])
+    rng = np.random.default_rng(7)
+    dx = rng.normal(scale=1e-2, size=(2, d["n_atoms"], 3)).astype(np.float32)
+    t = 0.003
+    out = system.force_dir(torch.from_numpy(x.astype(np.float32)).cuda(), torch.from_numpy(dx).cuda(), t)
+    torch.cuda.synchronize()
+    out = out.cpu().numpy().astype(np.float64)
+    o = O.Oracle(d)
+    st = o.init(x0_of(d))
+    _, fdot, _, _, _ = o.forces_dir(x, dx.astype(np.float64), False, t, st)
+    for k in range(2):
+        rel = np.linalg.norm(out[k] - fdot[k]) / np.linalg.norm(fdot[k])
+        say(f"  direction {k}: rel {rel:.2e}")
+        assert rel <= G_REL
+
+
+@pytest.mark.parametrize("name,nsteps", [("tiny", 20), ("tiny_rg", 20), ("c1", 20), ("c2", 10)])
+def test_functional_gradient(name, nsteps):
+    """dPhi/d(bias_k, ramp_rate) carried by the tangents along a trajectory,
+    against the oracle's dual-number run of the same trajectory."""
+    say("functional gradient:", name, nsteps)
+    d = _tangent_case(name)
+    system = vp.System([d], tangent=True, steps_per_graph=5)
+    system.step_batch(nsteps)
+    phi, grad = system.functional(gradient=True)
+    o = O.Oracle(d)
+    x = x0_of(d)
+    v = o.maxwell()
+    st = o.init(x)
+    pd = o.init_tangent(x, st)
+    xt = np.zeros((2, o.n, 3))
+    vt = np.zeros((2, o.n, 3))
+    assert o.run_tangent(x, v, st, xt, vt, pd, nsteps) == 0
+    go = o.phi_grad(st, pd)
+    say(f"  phi {phi[0]:.6e} vs {o.phi(st):.6e}; grad {grad[0]} vs {go}")
+    for k in range(2):
+        assert abs(grad[0, k] - go[k]) <= G_REL * abs(go[k]), (k, grad[0, k], go[k])
+
+
+def test_tangents_leave_the_trajectory_unchanged():
+    say("tangents: primal unchanged")
+    d = _tangent_case("tiny")
+    outs = []
+    for tan in (False, True):
+        s = vp.System([d], tangent=tan, steps_per_graph=6)
+        s.step_batch(14)
+        x, v = s.get_state()
+        outs.append((x.cpu().numpy(), v.cpu().numpy(), s.functional()[0]))
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+    assert outs[0][2] == outs[1][2]
+
+
+def test_tangent_batch_matches_solo_runs_bitwise():
+    say("tangents: batch vs solo")
+    base = _tangent_case("tiny")
+    reps = [synth.with_seed(base, 200 + r) for r in range(3)] + [_tangent_case("tiny_rg")]
+    batch = vp.System(reps, tangent=True, steps_per_graph=5)
+    batch.step_batch(12)
+    phib, gb = batch.functional(gradient=True)
+    for r, d in enumerate(reps):
+        solo = vp.System([d], tangent=True, steps_per_graph=5)
+        solo.step_batch(12)
+        phis, gs = solo.functional(gradient=True)
+        assert phis[0] == phib[r] and np.array_equal(gs[0], gb[r])
+
+
+def test_tangent_errors():
+    say("tangents: errors")
+    d = _tangent_case("tiny")
+    s = vp.System([d])
+    with pytest.raises(vp.VpError):
+        s.functional(gradient=True)
+    with pytest.raises(vp.VpError):
+        vp.System([dict(synth.tiny(seed=7, bias=synth.BIAS_RMD_CONTACT), bias_k=0.5)], tangent=True)
