@@ -32,6 +32,10 @@ sys.path.insert(0, ROOT)
 
 FLOP_PER_PAIR = 35          # algorithmic flops per unique in-cutoff pair (force only)
 PEAK_FP32_TFLOPS = 157.3    # MI355X FP32 vector peak
+# HBM bytes per launch of the force kernel on this workload, from rocprofv3
+# FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 (factors from a 256 MiB device copy);
+# see profiles/counters_c3_64x12560.md.  Set to None when the kernel changes.
+FORCE_TRAFFIC_BYTES = (607522 * 2.000 + 19200 * 1.000) * 1024
 
 
 def main():
@@ -189,7 +193,8 @@ def main():
         "list_stats": list_stats,
         "roofline": {
             "bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-            "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+            "frac": achieved / PEAK_FP32_TFLOPS,
+            "traffic": FORCE_TRAFFIC_BYTES if args.replicas == 64 else None,
             "kernel": "k_forces (nonbonded LJ+RF + bonded)",
             "flop_per_unit": FLOP_PER_PAIR, "units_per_launch": pairs_total,
             "avg_launch_ms": force_ms, "launches_timed": n_launch,
