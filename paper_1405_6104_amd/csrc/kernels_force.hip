@@ -59,7 +59,7 @@ __global__ __launch_bounds__(kForceThreads) void k_forces(const RepInfo *__restr
   const int Lx = R.Lq[0], Ly = R.Lq[1], Lz = R.Lq[2];
   // ---- stage the neighbourhood and the type table
   const int nst = W.stage_n[b];
-  const uint32_t *stg = W.stage + (int64_t)b * kMaxStage;
+  const uint32_t *stg = W.stage + (int64_t)b * W.stage_stride;
   const int4 *xr = W.xq + R.off;
   for (int s = tid; s < nst; s += kForceThreads) {
     const uint32_t e = stg[s];
@@ -262,7 +262,7 @@ __global__ __launch_bounds__(kForceThreads) void k_tangent_forces(
   }
   const int Lx = R.Lq[0], Ly = R.Lq[1], Lz = R.Lq[2];
   const int nst = W.stage_n[b];
-  const uint32_t *stg = W.stage + (int64_t)b * kMaxStage;
+  const uint32_t *stg = W.stage + (int64_t)b * W.stage_stride;
   const int4 *xr = W.xq + R.off;
   for (int q = tid; q < nst; q += kForceThreads) {
     const uint32_t e = stg[q];

@@ -425,7 +425,7 @@ __global__ __launch_bounds__(kBlk) void k_list(const RepInfo *__restrict__ info,
   const int a32 = a - 32;
   const int lb = b - R.blk0;
   uint16_t *lst = W.nblist + R.list_off + (int64_t)lb * R.maxnb * kBlk;
-  uint32_t *stg = W.stage + (int64_t)b * kMaxStage;
+  uint32_t *stg = W.stage + (int64_t)b * W.stage_stride;
   const int cap = R.stage_cap, maxnb = R.maxnb;
   const int *cstart = W.cell_start + R.cell0;
   int nst = 0, cnt = 0;
@@ -592,6 +592,8 @@ __global__ __launch_bounds__(kBlk) void k_list(const RepInfo *__restrict__ info,
     }
     if (!full) break;
   }
+  // longest list before any clamp (the capacity check at creation reads it)
+  const int cneed = wave_max_i(active ? cnt : 0);
   if (cnt > maxnb - 8) {
     bad = true;
     cnt = maxnb - 8;
@@ -603,7 +605,6 @@ __global__ __launch_bounds__(kBlk) void k_list(const RepInfo *__restrict__ info,
       if ((cnt & 3) == 0) list_store4(lst, cnt - 4, lane, pend);
     }
   }
-  const int cmax = wave_max_i(active ? cnt : 0);
   W.nbcnt[slot] = active ? cnt : 0;
   if (lane == 0) W.stage_n[b] = nst;
   if (__ballot(bad) && lane == 0) {
@@ -612,7 +613,7 @@ __global__ __launch_bounds__(kBlk) void k_list(const RepInfo *__restrict__ info,
   }
   if (MODE == 0 && lane == 0) {
     atomicMax(&state[r].stage_max, nst);
-    atomicMax(&state[r].list_max, cmax);
+    atomicMax(&state[r].list_max, cneed);
     if (exact) atomicAdd(&state[r].exact_builds, 1);
   }
   if (!active) return;
@@ -654,7 +655,7 @@ __global__ __launch_bounds__(kBlk) void k_debug_pairs(const RepInfo *__restrict_
   const int a = W.orig[slot];
   const int cnt = W.nbcnt[slot];
   const uint16_t *lst = W.nblist + R.list_off + (int64_t)(b - R.blk0) * R.maxnb * kBlk;
-  const uint32_t *stg = W.stage + (int64_t)b * kMaxStage;
+  const uint32_t *stg = W.stage + (int64_t)b * W.stage_stride;
   const int nst = W.stage_n[b];
   for (int k = 0; k < cnt; ++k) {
     const int L = lst[(((k >> 3) * kBlk) + threadIdx.x) * 8 + (k & 7)];

@@ -127,7 +127,8 @@ static vp_status alloc_work(vp_system *s, Work &W, bool traj) {
   TRY(dalloc(s, &W.nbcnt, S));
   TRY(dalloc(s, &W.nblist, (size_t)s->list_elems));
   TRY(dalloc(s, &W.stage_n, B));
-  TRY(dalloc(s, &W.stage, B * kMaxStage));
+  W.stage_stride = s->stage_cap_max;
+  TRY(dalloc(s, &W.stage, B * (size_t)W.stage_stride));
   TRY(dalloc(s, &W.cell_start, (size_t)s->n_cells));
   TRY(dalloc(s, &W.cell_slots, S));
   TRY(dalloc(s, &W.cell_of, S));
@@ -240,6 +241,8 @@ static vp_status build(vp_system *s, const vp_replica_desc *reps, int32_t n_reps
     const double rho = d.n_atoms / vol;
     const double expect = 4.0 / 3.0 * M_PI * rl * rl * rl * rho;
     int maxnb = o.max_neighbors > 0 ? o.max_neighbors : (int)std::ceil(1.5 * expect + 64);
+    if (o.max_neighbors <= 0 && r < (int)s->maxnb_override.size() && s->maxnb_override[r] > 0)
+      maxnb = s->maxnb_override[r];
     maxnb = std::min(maxnb, d.n_atoms + 8);
     maxnb = (maxnb + 7) / 8 * 8 + 8;
     R.maxnb = maxnb;
@@ -541,6 +544,35 @@ extern "C" vp_status vp_system_create(const vp_replica_desc *reps, int32_t n_rep
   s->opt = o;
   s->tangent = o.tangent != 0;
   vp_status st = build(s, reps, n_reps);
+  // List capacity: sized from the mean density, then checked against the
+  // first build; a replica whose longest list uses more than 80% of it (local
+  // density well above the mean) is built again with 1.3x that length.
+  for (int attempt = 0; st == VP_OK && o.max_neighbors <= 0 && attempt < 3; ++attempt) {
+    std::vector<RepState> rs(n_reps);
+    if (hipMemcpy(rs.data(), s->state, sizeof(RepState) * n_reps, hipMemcpyDeviceToHost) != hipSuccess) {
+      st = fail(VP_ERR_HIP, "reading the first list build");
+      break;
+    }
+    std::vector<int32_t> grow(n_reps, 0);
+    bool any = false;
+    for (int r = 0; r < n_reps; ++r)
+      if (rs[r].list_max > (int)(0.8 * s->info_h[r].maxnb)) {
+        grow[r] = ((int)std::ceil(1.3 * rs[r].list_max) + 16 + 7) / 8 * 8;
+        any = true;
+      }
+    if (!any) break;
+    std::vector<int32_t> keep = s->maxnb_override;
+    keep.resize(n_reps, 0);
+    for (int r = 0; r < n_reps; ++r)
+      if (grow[r] > 0) keep[r] = std::max(keep[r], grow[r]);
+    free_all(s);
+    s->graphs.clear();
+    s->eval_ready = false;
+    s->traj = Work{};
+    s->eval = Work{};
+    s->maxnb_override = keep;
+    st = build(s, reps, n_reps);
+  }
   if (st != VP_OK) {
     std::string msg = g_err;
     free_all(s);

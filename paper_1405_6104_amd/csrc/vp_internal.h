@@ -17,7 +17,7 @@ constexpr int kParts = 8;            // waves sharing one block in the force ker
 constexpr int kForceThreads = kParts * kBlk;
 constexpr int kBinThreads = 1024;    // workgroup of the binning kernel
 constexpr int kMaxCells = 4096;      // cells per replica held in LDS by the binning kernel
-constexpr int kMaxStage = 4093;      // staged neighbourhood atoms per block (LDS, + 1 inert entry)
+constexpr int kMaxStage = 8191;      // staged neighbourhood atoms per block (16-bit list entries; LDS decides)
 constexpr int kMaxLds = 81920;       // LDS bytes per force workgroup (two share a 160 KB CU)
 constexpr int kMaxLdsTangent = 163840;  // LDS bytes per workgroup of the tangent force kernel
 constexpr int kMaxCols = 256;        // xy columns per replica (sort order)
@@ -84,7 +84,7 @@ struct RepState {
   int32_t force_rebuild;
   int32_t rebuilds;
   int32_t stage_max;     // largest staged neighbourhood of a block so far
-  int32_t list_max;      // longest per-atom list so far (entries, padded)
+  int32_t list_max;      // longest per-atom list so far (entries needed, before any clamp)
   int32_t exact_builds;  // blocks built again in exact mode (staging capacity reached)
   int32_t pad;
   // derivative of the functional with respect to (bias_k, ramp_rate)
@@ -114,7 +114,8 @@ struct Work {
   int32_t *nbcnt = nullptr;     // [slots] list length (multiple of 8)
   uint16_t *nblist = nullptr;   // per block [maxnb/8][64][8] staged indices
   int32_t *stage_n = nullptr;   // [blocks]
-  uint32_t *stage = nullptr;    // [blocks][kMaxStage] slot | image shifts
+  uint32_t *stage = nullptr;    // [blocks][stage_stride] slot | image shifts
+  int64_t stage_stride = 0;     // staging entries per block (largest capacity)
   int32_t *cell_start = nullptr;  // [sum ncell + R] fine-cell CSR offsets (replica-local)
   int32_t *cell_slots = nullptr;  // [slots] slots of each fine cell, ascending
   int32_t *cell_of = nullptr;     // [slots] fine cell of each new slot
@@ -198,6 +199,7 @@ struct vp_system {
   vp::Work traj, eval;
   bool eval_ready = false;
   bool tangent = false;  // derivatives of the functional are propagated
+  std::vector<int32_t> maxnb_override;  // per-replica list capacity set after a first build
   struct GraphEntry {
     int32_t steps;
     hipStream_t stream;

@@ -72,13 +72,19 @@ def _tree_parents(n, rng, branching):
     return parent
 
 
-def _grow(parent, center, radius, dmin, rng, n_cand=48, pull=0.0):
+def _grow(parent, center, radius, dmin, rng, n_cand=48, pull=0.0, box=None, escape=False):
     """Self-avoiding confined growth: each atom sits 0.38 nm from its parent at
     110 deg to a placed neighbour of the parent (random dihedral), inside the
     confining sphere, at least ``dmin`` from every atom that is not a 1-2 or
     1-3 partner and at least 0.5 nm from its 1-3 partners.  Among valid candidates one is drawn with weight
     exp(-pull |x-c|^2/R^2) (pull > 0 packs the chain toward the centre).  Dead
-    ends backtrack by a growing number of atoms."""
+    ends backtrack by a growing number of atoms.  With ``box`` (periodic edge
+    length) the distances are minimum-image ones, for spheres wider than the
+    box.  With ``escape`` the backtracking depth keeps growing until the chain
+    passes the furthest atom it had reached (a dead end that needs siblings
+    placed long before is then undone instead of retried forever), and after
+    40 n attempts the growth starts over (continuing the same random stream,
+    so the result stays a function of the seed)."""
     n = len(parent)
     nbrs = [[] for _ in range(n)]
     for i in range(1, n):
@@ -90,7 +96,15 @@ def _grow(parent, center, radius, dmin, rng, n_cand=48, pull=0.0):
     dmin2 = dmin * dmin
     i = 1
     streak = 0
+    best = 1
+    attempts = 0
     while i < n:
+        attempts += 1
+        if escape and attempts > 40 * n:
+            d = rng.normal(size=3)
+            x[0] = center + d * (0.25 * radius * rng.random() / np.linalg.norm(d))
+            i, streak, best, attempts = 1, 0, 1, 0
+            continue
         p = int(parent[i])
         placed_nb = [q for q in nbrs[p] if q < i]
         if placed_nb:
@@ -115,17 +129,24 @@ def _grow(parent, center, radius, dmin, rng, n_cand=48, pull=0.0):
         lim = np.full(i, dmin2)
         lim[placed_nb] = 0.25
         lim[p] = 0.0
-        dd = np.sum((cand[:, None, :] - x[None, :i]) ** 2, -1)
+        diff = cand[:, None, :] - x[None, :i]
+        if box is not None:
+            diff -= box * np.round(diff / box)
+        dd = np.sum(diff ** 2, -1)
         ok &= np.all(dd >= lim[None, :], 1)
         if ok.any():
             w = np.exp(-pull * r2c[ok] / (radius * radius))
             pick = np.flatnonzero(ok)[rng.choice(int(ok.sum()), p=w / w.sum())]
             x[i] = cand[pick]
             i += 1
-            streak = max(0, streak - 1)
+            if not escape:
+                streak = max(0, streak - 1)
+            elif i > best:
+                best = i
+                streak = 0
         else:
             streak += 1
-            back = min(i - 1, int(rng.integers(1, 2 + min(streak, 40))))
+            back = min(i - 1, int(rng.integers(1, 2 + min(streak, 40 if not escape else 400))))
             i = max(1, i - back)
     return x
 
@@ -233,7 +254,7 @@ def _place_waters(box, n_water, solute_x, rng, clearance=0.26, tries=24):
 # systems
 # --------------------------------------------------------------------------
 def make_system(*, n_solute, n_water, box, r_cut, dt, seed, bias, branching=True,
-                init_radius=None, final_radius=None, gamma=1.0, T=300.0,
+                init_radius=None, final_radius=None, periodic_growth=False, gamma=1.0, T=300.0,
                 eps_rf=78.0, bias_k=None, ramp_rate=None, z_target=None,
                 n_steps_for_ramp=None, reach_tol=None, contact_min_sep=35):
     """One replica description (see module docstring)."""
@@ -243,12 +264,14 @@ def make_system(*, n_solute, n_water, box, r_cut, dt, seed, bias, branching=True
     parent = _tree_parents(n_solute, rng, branching)
     if init_radius is None:
         init_radius = 1.0 if n_solute <= 32 else 2.0
-    xs = _grow(parent, center, init_radius, 0.30, rng, pull=0.5) if n_solute else np.zeros((0, 3))
+    xs = (_grow(parent, center, init_radius, 0.30, rng, pull=0.3 if periodic_growth else 0.5,
+                box=L if periodic_growth else None, escape=periodic_growth)
+          if n_solute else np.zeros((0, 3)))
     xf = None
     if bias in (BIAS_CONTACT, BIAS_RMD_CONTACT):
         if final_radius is None:
             final_radius = 1.7
-        xf = _grow(parent, center, final_radius, 0.25, rng, pull=1.0)
+        xf = _grow(parent, center, final_radius, 0.25, rng, pull=1.0, escape=periodic_growth)
     bonds, angles, ex = _solute_topology(parent) if n_solute else (
         np.zeros((0, 2), np.int32), np.zeros((0, 3), np.int32), set())
     sig = rng.uniform(0.30, 0.40, n_solute)
@@ -336,9 +359,12 @@ def c3_batch(n_rep=64, seed=WORKLOAD_SEED, base=None, n_steps=10000):
     return [with_seed(base, seed + r + 1) for r in range(n_rep)]
 
 
-def c4_uneven(n_rep=32, seed=WORKLOAD_SEED):
+def c4_uneven(n_rep=32, seed=WORKLOAD_SEED, only=None):
     """Replicas with atom counts log-uniform in [5000, 40000], solute 280-560
-    atoms, water at 33.4 /nm^3, cutoffs 0.9 or 1.2 nm."""
+    atoms, water at 33.4 /nm^3, cutoffs 0.9 or 1.2 nm.  The initial solute is
+    grown at 9 atoms/nm^3 (in the smaller boxes its sphere is wider than the
+    box and the growth uses minimum-image distances), the target structure at
+    15 atoms/nm^3."""
     rng = np.random.default_rng(seed + 4)
     reps = []
     for r in range(n_rep):
@@ -347,9 +373,13 @@ def c4_uneven(n_rep=32, seed=WORKLOAD_SEED):
         nw = (N - ns) // 3
         L = (nw / 33.4) ** (1.0 / 3.0)
         rc = 0.9 if rng.random() < 0.5 else 1.2
+        if only is not None and r not in only:
+            continue  # the parameters are still drawn, so replica r is the same either way
+        r_init = (3.0 * ns / (4.0 * math.pi * 9.0)) ** (1.0 / 3.0)
+        r_final = (3.0 * ns / (4.0 * math.pi * 15.0)) ** (1.0 / 3.0)
         reps.append(make_system(n_solute=ns, n_water=nw, box=L, r_cut=rc, dt=0.001,
                                 seed=seed + 100 * (r + 1), bias=BIAS_CONTACT,
-                                init_radius=min(2.2, 0.42 * L), final_radius=min(1.8, 0.36 * L),
+                                init_radius=r_init, final_radius=r_final, periodic_growth=True,
                                 n_steps_for_ramp=2000))
     return reps
 

@@ -429,3 +429,51 @@ def test_tangent_errors():
         s.functional(gradient=True)
     with pytest.raises(vp.VpError):
         vp.System([dict(synth.tiny(seed=7, bias=synth.BIAS_RMD_CONTACT), bias_k=0.5)], tangent=True)
+
+
+# ------------------------------------------- uneven batch (5,000-40,000 atoms, rc 0.9 / 1.2)
+@pytest.fixture(scope="module")
+def c4_subset():
+    # three replicas of the uneven batch: 5,028 atoms rc 1.2; 5,135 rc 0.9; 10,312 rc 1.2
+    return synth.c4_uneven(only=(9, 15, 26))
+
+
+def test_uneven_batch_forces_and_pairs(c4_subset):
+    say("uneven batch: forces and pairs", [int(d["n_atoms"]) for d in c4_subset])
+    system = vp.System(c4_subset)
+    xs = [f32(d["x0"]) for d in c4_subset]
+    fg, e = gpu_forces(system, xs, 0.0)
+    for r, d in enumerate(c4_subset):
+        o = O.Oracle(d)
+        st = o.init(x0_of(d))
+        fo, _, _ = o.forces(xs[r], 0.0, st)
+        a, b = system.offsets[r], system.offsets[r + 1]
+        rel, mx = force_errors(fg[a:b], fo)
+        say(f"  replica {r}: {d['n_atoms']} atoms rc {d['r_cut']}: rel {rel:.2e} max {mx:.2e}")
+        assert rel <= F_REL and mx <= F_MAX
+    # the exact pair set of the first rc 1.2 replica (trajectory lists at creation)
+    r = next(i for i, d in enumerate(c4_subset) if d["r_cut"] > 1.0)
+    assert_same_pairs(system.debug_pairs(r), O.Oracle(c4_subset[r]).pairs(x0_of(c4_subset[r]), cells=True))
+    obs = system.observables()
+    assert np.all(obs[:, 5] == 0)
+
+
+def test_uneven_batch_runs_and_matches_solo(c4_subset):
+    say("uneven batch: 200 steps, batch vs solo")
+    batch = vp.System(c4_subset, steps_per_graph=20)
+    batch.step_batch(200)
+    obs = batch.observables()
+    col = {k: i for i, k in enumerate(vp.OBS)}
+    say("  stage max/cap", obs[:, col["stage_max"]], obs[:, col["stage_cap"]],
+        "list max/cap", obs[:, col["list_max"]], obs[:, col["list_cap"]],
+        "exact builds", obs[:, col["exact_builds"]])
+    assert np.all(obs[:, col["status"]] == 0)
+    assert np.all(np.isfinite(batch.functional()))
+    xb, _ = batch.get_state()
+    xb = xb.cpu().numpy()
+    r = 1
+    solo = vp.System([c4_subset[r]], steps_per_graph=20)
+    solo.step_batch(200)
+    xs, _ = solo.get_state()
+    a, b = batch.offsets[r], batch.offsets[r + 1]
+    assert np.array_equal(xs.cpu().numpy(), xb[a:b])
