@@ -50,6 +50,8 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--force-shape", type=int, default=0,
+                    help="tile shape of the force kernel (vp_options.force_shape)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="also run one device-to-device copy of MIB MiB (a known amount of HBM "
                          "traffic that calibrates rocprofv3's FETCH_SIZE/WRITE_SIZE counters)")
@@ -73,7 +75,7 @@ def main():
                           n_steps=B * (args.steps + args.warmup + args.timing_steps))
     n_atoms = sum(int(d["n_atoms"]) for d in reps)
     print(f"# generated {len(reps)} replicas, {n_atoms} atoms in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
-    system = vp.System(reps, steps_per_graph=B)
+    system = vp.System(reps, steps_per_graph=B, force_shape=args.force_shape)
     print(f"# system created", file=sys.stderr, flush=True)
 
     for _ in range(args.warmup):

@@ -117,7 +117,9 @@ typedef struct {
   int32_t max_neighbors;   /* per-atom list capacity (0: derived from density) */
   int32_t tangent;         /* 1: also propagate dPhi/d(bias_k, ramp_rate) (vp_functional);
                               harmonic and constant biases only */
-  int32_t reserved[6];
+  int32_t force_shape;     /* tile shape of the force kernel (waves per 64-atom block x list
+                              entries per batch): 0: 8x8 (default), 1: 16x4, 2: 16x8, 3: 4x8 */
+  int32_t reserved[5];
 } vp_options;
 
 /* Positions are held as 32-bit fixed point in units of 2^-24 nm, so that
@@ -213,6 +215,14 @@ vp_status vp_sizes(const vp_system *s, int64_t *n_atoms_total, int32_t *n_reps);
  * system was created with vp_options.tangent = 1.  Asynchronous. */
 vp_status vp_debug_force_dir(vp_system *s, const float *x_dev, const float *dx_dev, float *out_dev,
                              double t, void *hip_stream);
+
+/* Diagnostic (derivative checks): the exact trajectory state in user order,
+ * HOST FP64 buffers: x_host, v_host [sum N][3] (positions are the grid values);
+ * xt_host, vt_host [2][sum N][3] dx/dtheta, dv/dtheta and pd_host [n_reps][4]
+ * (sum_n w_n dS_n/dtheta for bias_k and ramp_rate, then the latest dS/dtheta),
+ * each NULL or, when given, requiring vp_options.tangent = 1.  Synchronises. */
+vp_status vp_debug_trajectory_state(vp_system *s, double *x_host, double *v_host, double *xt_host,
+                                    double *vt_host, double *pd_host);
 
 vp_status vp_debug_pairs(vp_system *s, int32_t rep, int32_t *pairs_host, int64_t cap,
                          int64_t *count);

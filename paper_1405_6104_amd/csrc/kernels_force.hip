@@ -26,21 +26,29 @@
 
 namespace vp {
 
-template <bool ENERGY>
-__global__ __launch_bounds__(kForceThreads) void k_forces(const RepInfo *__restrict__ info, Work W,
-                                                   const int32_t *__restrict__ tile_rep,
-                                                   const int32_t *__restrict__ tile_first,
-                                                   int nblk, const float4 *__restrict__ types,
-                                                   const int32_t *__restrict__ bt_start,
-                                                   const BTerm *__restrict__ bterms,
-                                                   int stage_slots) {
+// Tile shape: PARTS waves share one block's staged neighbourhood (each walks
+// every PARTS-th chunk of the lists) and evaluate UNROLL list entries per
+// batch of LDS reads; MINW asks the compiler for registers that let MINW
+// waves share a SIMD.  blist (or NULL for all blocks) selects the blocks of
+// one launch.
+template <bool ENERGY, int PARTS, int UNROLL, int MINW>
+__global__ __launch_bounds__(64 * PARTS) __attribute__((amdgpu_waves_per_eu(MINW))) void k_forces(const RepInfo *__restrict__ info, Work W,
+                                                       const int32_t *__restrict__ tile_rep,
+                                                       const int32_t *__restrict__ tile_first,
+                                                       const int32_t *__restrict__ blist, int nblk,
+                                                       const float4 *__restrict__ types,
+                                                       const int32_t *__restrict__ bt_start,
+                                                       const BTerm *__restrict__ bterms,
+                                                       int stage_slots) {
+  constexpr int NT = 64 * PARTS;
   extern __shared__ int4 lds[];
   int4 *st = lds;                                              // [stage_slots] staged atoms
   float4 *tab = reinterpret_cast<float4 *>(lds + stage_slots);  // the replica's type table
   float *red = reinterpret_cast<float *>(lds);  // reuses the staging area after the pair loop
-  __shared__ double s_red[kForceThreads / 64];
-  const int b = xcd_tile(blockIdx.x, nblk);
-  if (b < 0) return;
+  __shared__ double s_red[PARTS];
+  const int bt = xcd_tile(blockIdx.x, nblk);
+  if (bt < 0) return;
+  const int b = blist ? blist[bt] : bt;
   const int tile = b / (kTile / kBlk);
   const int r = tile_rep[tile];
   const RepInfo &R = info[r];
@@ -61,7 +69,7 @@ __global__ __launch_bounds__(kForceThreads) void k_forces(const RepInfo *__restr
   const int nst = W.stage_n[b];
   const uint32_t *stg = W.stage + (int64_t)b * W.stage_stride;
   const int4 *xr = W.xq + R.off;
-  for (int s = tid; s < nst; s += kForceThreads) {
+  for (int s = tid; s < nst; s += NT) {
     const uint32_t e = stg[s];
     const int j = (int)(e & 0xffffu);
     const int sx = (int)((e >> 16) & 31) - 16, sy = (int)((e >> 21) & 31) - 16,
@@ -70,7 +78,7 @@ __global__ __launch_bounds__(kForceThreads) void k_forces(const RepInfo *__restr
     st[s] = make_int4(xj.x + sx * Lx, xj.y + sy * Ly, xj.z + sz * Lz, xj.w);
   }
   if (tid == 0) st[R.stage_cap] = make_int4(kDummyCoord, kDummyCoord, kDummyCoord, R.ntypes);
-  for (int t = tid; t <= R.ntypes; t += kForceThreads) tab[t] = types[R.type_off + t];
+  for (int t = tid; t <= R.ntypes; t += NT) tab[t] = types[R.type_off + t];
   __syncthreads();
 
   const int lane = tid & (kBlk - 1), part = tid / kBlk;
@@ -93,19 +101,24 @@ __global__ __launch_bounds__(kForceThreads) void k_forces(const RepInfo *__restr
     const uint4 *lp = reinterpret_cast<const uint4 *>(W.nblist + R.list_off +
                                                       (int64_t)(b - R.blk0) * R.maxnb * kBlk) + lane;
     uint4 e = lp[(int64_t)min(part, max(nch - 1, 0)) * kBlk];
-    for (int c = part; c < nch; c += kParts) {
+    for (int c = part; c < nch; c += PARTS) {
       // the next chunk's indices are fetched while this one is evaluated (the
       // last chunk is fetched again rather than reading past the list)
-      const uint4 en = lp[(int64_t)min(c + kParts, nch - 1) * kBlk];
+      const uint4 en = lp[(int64_t)min(c + PARTS, nch - 1) * kBlk];
       const uint32_t w[4] = {e.x, e.y, e.z, e.w};
-      int4 sj[8];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) sj[u] = st[(w[u >> 1] >> (16 * (u & 1))) & 0xffffu];
-      float4 tj[8];
+      for (int h = 0; h < 8; h += UNROLL) {
+      int4 sj[UNROLL];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) tj[u] = tab[sj[u].w];
+      for (int v = 0; v < UNROLL; ++v) {
+        const int u = h + v;
+        sj[v] = st[(w[u >> 1] >> (16 * (u & 1))) & 0xffffu];
+      }
+      float4 tj[UNROLL];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
+      for (int v = 0; v < UNROLL; ++v) tj[v] = tab[sj[v].w];
+#pragma unroll
+      for (int u = 0; u < UNROLL; ++u) {
         // every entry is evaluated; the cutoff selects (no divergent branch)
         const float dx = (float)(sj[u].x - wx), dy = (float)(sj[u].y - wy), dz = (float)(sj[u].z - wz);
         const float r2 = qr2(dx, dy, dz);
@@ -133,25 +146,26 @@ __global__ __launch_bounds__(kForceThreads) void k_forces(const RepInfo *__restr
           erf += fqq * ((double)rinv * kQ + R.krf * (double)r2 * (kInvQ * kInvQ) - R.crf);
         }
       }
+      }
       e = en;
     }
   }
   // ---- fixed-order sum of the partial forces of the waves, bonded terms, store
   __syncthreads();  // every wave is done with the staged neighbourhood
   red[tid] = fx;
-  red[kForceThreads + tid] = fy;
-  red[2 * kForceThreads + tid] = fz;
+  red[NT + tid] = fy;
+  red[2 * NT + tid] = fz;
   __syncthreads();
   double ebond = 0.0, eangle = 0.0;
   if (part == 0) {
     long long fxs = 0, fys = 0, fzs = 0;
     if (active) {
-      float sx = red[lane], sy = red[kForceThreads + lane], sz = red[2 * kForceThreads + lane];
+      float sx = red[lane], sy = red[NT + lane], sz = red[2 * NT + lane];
 #pragma unroll
-      for (int q = 1; q < kParts; ++q) {
+      for (int q = 1; q < PARTS; ++q) {
         sx += red[q * kBlk + lane];
-        sy += red[kForceThreads + q * kBlk + lane];
-        sz += red[2 * kForceThreads + q * kBlk + lane];
+        sy += red[NT + q * kBlk + lane];
+        sz += red[2 * NT + q * kBlk + lane];
       }
       double bx = 0.0, by = 0.0, bz = 0.0;
       const int a = W.orig[slot];
@@ -215,10 +229,10 @@ __global__ __launch_bounds__(kForceThreads) void k_forces(const RepInfo *__restr
     W.F[2 * W.fstride + slot] = fzs;
   }
   if (ENERGY) {
-    const double v0 = block_sum<kForceThreads>(0.5 * elj, s_red);
-    const double v1 = block_sum<kForceThreads>(0.5 * erf, s_red);
-    const double v2 = block_sum<kForceThreads>(ebond, s_red);
-    const double v3 = block_sum<kForceThreads>(eangle, s_red);
+    const double v0 = block_sum<NT>(0.5 * elj, s_red);
+    const double v1 = block_sum<NT>(0.5 * erf, s_red);
+    const double v2 = block_sum<NT>(ebond, s_red);
+    const double v3 = block_sum<NT>(eangle, s_red);
     if (tid == 0) {
       W.epart[4 * (size_t)b + 0] = v0;
       W.epart[4 * (size_t)b + 1] = v1;
@@ -933,16 +947,28 @@ static inline int xcd_grid(int nb) { return 8 * ((nb + 7) / 8); }
 
 size_t force_lds_bytes(const vp_system *s) {
   size_t stage = sizeof(int4) * ((size_t)(s->stage_cap_max + 1) + (size_t)(s->ntypes_max + 1));
-  size_t red = sizeof(float) * 3 * kForceThreads;
+  size_t red = sizeof(float) * 3 * 64 * kMaxForceParts;
   return stage > red ? stage : red;
+}
+
+// the tile shapes the force kernel is built for: (waves per block, entries per batch)
+const ForceShape kForceShapes[kNumForceShapes] = {{8, 8}, {16, 4}, {16, 8}, {4, 8}};
+
+template <bool E, int P, int U, int M>
+static hipError_t set_lds(int lds) {
+  return hipFuncSetAttribute((const void *)k_forces<E, P, U, M>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             lds);
 }
 
 hipError_t prepare_forces(const vp_system *s) {
   const int lds = (int)force_lds_bytes(s);
-  hipError_t e = hipFuncSetAttribute((const void *)k_forces<false>,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-  if (e != hipSuccess) return e;
-  return hipFuncSetAttribute((const void *)k_forces<true>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+  hipError_t e = hipSuccess;
+  for (hipError_t x : {set_lds<false, 8, 8, 1>(lds), set_lds<true, 8, 8, 1>(lds),
+                       set_lds<false, 16, 4, 1>(lds), set_lds<true, 16, 4, 1>(lds),
+                       set_lds<false, 16, 8, 1>(lds), set_lds<true, 16, 8, 1>(lds),
+                       set_lds<false, 4, 8, 1>(lds), set_lds<true, 4, 8, 1>(lds)})
+    if (x != hipSuccess) e = x;
+  return e;
 }
 
 void launch_native_map(const float *xf, int ns, int min_sep, float r0, float rs, float rc,
@@ -952,17 +978,29 @@ void launch_native_map(const float *xf, int ns, int min_sep, float r0, float rs,
                      min_sep, r0, rs, rc, out);
 }
 
+template <bool E, int P, int U, int M>
+static void launch_forces_t(vp_system *s, Work &W, const int32_t *blist, int nblk, hipStream_t st) {
+  hipLaunchKernelGGL((k_forces<E, P, U, M>), dim3(xcd_grid(nblk)), dim3(64 * P), force_lds_bytes(s), st,
+                     s->info, W, s->tile_rep, s->tile_first, blist, nblk, s->types, s->bt_start,
+                     s->bterms, s->stage_cap_max + 1);
+}
+
+void launch_forces_shape(vp_system *s, Work &W, bool energy, int shape, const int32_t *blist, int nblk,
+                         hipStream_t st) {
+  switch (shape * 2 + (energy ? 1 : 0)) {
+    case 0: launch_forces_t<false, 8, 8, 1>(s, W, blist, nblk, st); break;
+    case 1: launch_forces_t<true, 8, 8, 1>(s, W, blist, nblk, st); break;
+    case 2: launch_forces_t<false, 16, 4, 1>(s, W, blist, nblk, st); break;
+    case 3: launch_forces_t<true, 16, 4, 1>(s, W, blist, nblk, st); break;
+    case 4: launch_forces_t<false, 16, 8, 1>(s, W, blist, nblk, st); break;
+    case 5: launch_forces_t<true, 16, 8, 1>(s, W, blist, nblk, st); break;
+    case 6: launch_forces_t<false, 4, 8, 1>(s, W, blist, nblk, st); break;
+    default: launch_forces_t<true, 4, 8, 1>(s, W, blist, nblk, st); break;
+  }
+}
+
 void launch_forces(vp_system *s, Work &W, bool energy, hipStream_t st) {
-  size_t lds = force_lds_bytes(s);
-  const int slots = s->stage_cap_max + 1;
-  if (energy)
-    hipLaunchKernelGGL(k_forces<true>, dim3(xcd_grid(s->n_blocks)), dim3(kForceThreads), lds, st, s->info,
-                       W, s->tile_rep, s->tile_first, s->n_blocks, s->types, s->bt_start, s->bterms,
-                       slots);
-  else
-    hipLaunchKernelGGL(k_forces<false>, dim3(xcd_grid(s->n_blocks)), dim3(kForceThreads), lds, st, s->info,
-                       W, s->tile_rep, s->tile_first, s->n_blocks, s->types, s->bt_start, s->bterms,
-                       slots);
+  launch_forces_shape(s, W, energy, s->force_shape, nullptr, s->n_blocks, st);
 }
 
 void launch_cv(vp_system *s, Work &W, int inc_step, hipStream_t st, bool tan) {

@@ -266,6 +266,45 @@ __global__ __launch_bounds__(kBlock) void k_gather_state(const RepInfo *__restri
   }
 }
 
+// Exact trajectory state in user order, FP64: positions (grid values),
+// velocities and, when derivatives are on, the tangents [2][users][3].
+__global__ __launch_bounds__(kBlock) void k_export_state(const RepInfo *__restrict__ info, Work W,
+                                                         const int32_t *__restrict__ tile_rep,
+                                                         const int32_t *__restrict__ tile_first,
+                                                         int ntiles, int64_t users,
+                                                         double *__restrict__ x_out,
+                                                         double *__restrict__ v_out,
+                                                         double *__restrict__ xt_out,
+                                                         double *__restrict__ vt_out) {
+  const int tile = xcd_tile(blockIdx.x, ntiles);
+  if (tile < 0) return;
+  const int r = tile_rep[tile];
+  const RepInfo &R = info[r];
+  const int p = tile_first[tile] + threadIdx.x;
+  if (p >= R.n) return;
+  const int slot = R.off + p;
+  const int64_t u = R.uoff + W.orig[slot];
+  const int4 x = W.xq[slot];
+  const float4 v = W.vel[slot];
+  x_out[3 * u] = (double)x.x * kInvQ;
+  x_out[3 * u + 1] = (double)x.y * kInvQ;
+  x_out[3 * u + 2] = (double)x.z * kInvQ;
+  v_out[3 * u] = v.x;
+  v_out[3 * u + 1] = v.y;
+  v_out[3 * u + 2] = v.z;
+  if (xt_out && W.tx)
+    for (int d = 0; d < 2; ++d) {
+      const float4 a = W.tx[d * W.fstride + slot], b = W.tv[d * W.fstride + slot];
+      double *xo = xt_out + (size_t)d * 3 * users + 3 * u, *vo = vt_out + (size_t)d * 3 * users + 3 * u;
+      xo[0] = a.x;
+      xo[1] = a.y;
+      xo[2] = a.z;
+      vo[0] = b.x;
+      vo[1] = b.y;
+      vo[2] = b.z;
+    }
+}
+
 // Kinetic energy partials per tile (fixed-order reduction on the host).
 __global__ __launch_bounds__(kBlock) void k_kinetic(const RepInfo *__restrict__ info, Work W,
                                                     const int32_t *__restrict__ tile_rep,
@@ -346,6 +385,11 @@ void launch_init_state(vp_system *s, const int32_t *xq_user, const float *v_user
 void launch_gather_state(vp_system *s, float *x_out, float *v_out, hipStream_t st) {
   hipLaunchKernelGGL(k_gather_state, dim3(xcd_grid(s->n_tiles)), dim3(kBlock), 0, st, s->info,
                      s->traj, s->tile_rep, s->tile_first, s->n_tiles, x_out, v_out);
+}
+
+void launch_export_state(vp_system *s, double *x, double *v, double *xt, double *vt, hipStream_t st) {
+  hipLaunchKernelGGL(k_export_state, dim3(xcd_grid(s->n_tiles)), dim3(kBlock), 0, st, s->info, s->traj,
+                     s->tile_rep, s->tile_first, s->n_tiles, (int64_t)s->n_users, x, v, xt, vt);
 }
 
 void launch_kinetic(vp_system *s, double *out, hipStream_t st) {

@@ -355,7 +355,7 @@ static vp_status build(vp_system *s, const vp_replica_desc *reps, int32_t n_reps
     // less than the estimate above; a block whose candidates would overflow
     // it is built again in exact mode.
     const long long budget =
-        ((long long)kMaxLds - (long long)sizeof(double) * (kForceThreads / 64)) / (long long)sizeof(int4) -
+        ((long long)kMaxLds - (long long)sizeof(double) * kMaxForceParts) / (long long)sizeof(int4) -
         (ntypes_max + 1) - 1;
     stage_cap_max = 0;
     for (int r = 0; r < n_reps; ++r) {
@@ -369,7 +369,7 @@ static vp_status build(vp_system *s, const vp_replica_desc *reps, int32_t n_reps
       stage_cap_max = std::max(stage_cap_max, R.stage_cap);
     }
     s->stage_cap_max = stage_cap_max;
-    size_t need = force_lds_bytes(s) + sizeof(double) * (kForceThreads / 64);
+    size_t need = force_lds_bytes(s) + sizeof(double) * kMaxForceParts;
     if (need > (size_t)kMaxLds)
       return fail(VP_ERR_ARG, "force kernel would need " + std::to_string(need) +
                                   " bytes of LDS per workgroup (limit " + std::to_string(kMaxLds) + ")");
@@ -533,6 +533,8 @@ extern "C" vp_status vp_system_create(const vp_replica_desc *reps, int32_t n_rep
     total += reps[r].n_atoms;
   }
   if (total > ((int64_t)1 << 31) - (int64_t)kTile * n_reps) return fail(VP_ERR_ARG, "batch too large");
+  if (opt && (opt->force_shape < 0 || opt->force_shape >= kNumForceShapes))
+    return fail(VP_ERR_ARG, "unknown force_shape");
   vp_system *s = new (std::nothrow) vp_system();
   if (!s) return fail(VP_ERR_NOMEM, "host allocation failed");
   vp_options o{};
@@ -543,6 +545,7 @@ extern "C" vp_status vp_system_create(const vp_replica_desc *reps, int32_t n_rep
   if (!opt) o.use_graph = 1;
   s->opt = o;
   s->tangent = o.tangent != 0;
+  s->force_shape = o.force_shape;
   vp_status st = build(s, reps, n_reps);
   // List capacity: sized from the mean density, then checked against the
   // first build; a replica whose longest list uses more than 80% of it (local
@@ -696,6 +699,36 @@ extern "C" vp_status vp_functional(vp_system *s, double *phi_host, double *dphi_
         dphi_dtheta_host[2 * r + d] = (st[r].status & VP_REPLICA_UNSTABLE)
                                           ? NAN
                                           : (st[r].pd_acc[d] - 0.5 * st[r].pd_last[d]) * R.dt / (4.0 * R.kT);
+  }
+  return VP_OK;
+}
+
+extern "C" vp_status vp_debug_trajectory_state(vp_system *s, double *x_host, double *v_host,
+                                               double *xt_host, double *vt_host, double *pd_host) {
+  if (!s || !x_host || !v_host) return fail(VP_ERR_ARG, "NULL argument");
+  if ((xt_host || vt_host || pd_host) && !s->tangent)
+    return fail(VP_ERR_STATE, "derivatives were not enabled at creation (vp_options.tangent)");
+  if ((xt_host == nullptr) != (vt_host == nullptr)) return fail(VP_ERR_ARG, "xt and vt go together");
+  HIPCHECK(hipStreamSynchronize(s->last_stream));
+  const size_t n3 = 3 * (size_t)s->n_users;
+  double *d = nullptr;
+  HIPCHECK(hipMalloc(&d, sizeof(double) * n3 * 6));
+  launch_export_state(s, d, d + n3, xt_host ? d + 2 * n3 : nullptr, xt_host ? d + 4 * n3 : nullptr, 0);
+  hipError_t e = hipDeviceSynchronize();
+  if (e == hipSuccess) e = hipMemcpy(x_host, d, sizeof(double) * n3, hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = hipMemcpy(v_host, d + n3, sizeof(double) * n3, hipMemcpyDeviceToHost);
+  if (e == hipSuccess && xt_host) e = hipMemcpy(xt_host, d + 2 * n3, sizeof(double) * 2 * n3, hipMemcpyDeviceToHost);
+  if (e == hipSuccess && vt_host) e = hipMemcpy(vt_host, d + 4 * n3, sizeof(double) * 2 * n3, hipMemcpyDeviceToHost);
+  (void)hipFree(d);
+  if (e != hipSuccess) return fail(VP_ERR_HIP, hipGetErrorString(e));
+  if (pd_host) {
+    std::vector<RepState> st;
+    TRY(fetch_state(s, st));
+    for (int r = 0; r < s->R; ++r)
+      for (int k = 0; k < 2; ++k) {
+        pd_host[4 * r + k] = st[r].pd_acc[k];
+        pd_host[4 * r + 2 + k] = st[r].pd_last[k];
+      }
   }
   return VP_OK;
 }

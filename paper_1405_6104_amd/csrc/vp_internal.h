@@ -15,6 +15,12 @@ constexpr int kTile = 256;           // slots per tile (a tile never crosses rep
 constexpr int kBlk = 64;             // atoms per neighbourhood block (one wave)
 constexpr int kParts = 8;            // waves sharing one block in the force kernel
 constexpr int kForceThreads = kParts * kBlk;
+constexpr int kMaxForceParts = 16;   // largest number of waves per block among the force tile shapes
+constexpr int kNumForceShapes = 4;
+struct ForceShape {
+  int parts, unroll;  // waves per 64-atom block, list entries per batch of LDS reads
+};
+extern const ForceShape kForceShapes[kNumForceShapes];
 constexpr int kBinThreads = 1024;    // workgroup of the binning kernel
 constexpr int kMaxCells = 4096;      // cells per replica held in LDS by the binning kernel
 constexpr int kMaxStage = 8191;      // staged neighbourhood atoms per block (16-bit list entries; LDS decides)
@@ -199,6 +205,7 @@ struct vp_system {
   vp::Work traj, eval;
   bool eval_ready = false;
   bool tangent = false;  // derivatives of the functional are propagated
+  int force_shape = 0;   // index into kForceShapes used by the force launches
   std::vector<int32_t> maxnb_override;  // per-replica list capacity set after a first build
   struct GraphEntry {
     int32_t steps;

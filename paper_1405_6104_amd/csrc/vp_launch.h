@@ -11,6 +11,9 @@ void launch_rebuild(vp_system *s, Work &W, int mode, const float *x_user, hipStr
 void launch_debug_pairs(vp_system *s, Work &W, int rep, int2 *out, unsigned long long cap,
                         unsigned long long *counter, hipStream_t st);
 void launch_forces(vp_system *s, Work &W, bool energy, hipStream_t st);
+// one tile shape (index into kForceShapes) over a list of blocks (NULL: all nblk blocks)
+void launch_forces_shape(vp_system *s, Work &W, bool energy, int shape, const int32_t *blist, int nblk,
+                         hipStream_t st);
 void launch_cv(vp_system *s, Work &W, int inc_step, hipStream_t st, bool tan);
 // derivatives along the tangents in W.tx (both directions)
 void launch_tangent_forces(vp_system *s, Work &W, hipStream_t st);
@@ -30,6 +33,8 @@ size_t force_lds_bytes(const vp_system *s);
 hipError_t prepare_forces(const vp_system *s);  // dynamic LDS above 64 KB
 void launch_gather_state(vp_system *s, float *x_out, float *v_out, hipStream_t st);
 void launch_kinetic(vp_system *s, double *out, hipStream_t st);
+// exact state in user order (device FP64 buffers; xt, vt may be NULL)
+void launch_export_state(vp_system *s, double *x, double *v, double *xt, double *vt, hipStream_t st);
 void launch_debug_noise(uint64_t seed, uint32_t atom0, uint32_t step, uint32_t tag, int n,
                         float *out, hipStream_t st);
 

@@ -61,7 +61,7 @@ class ReplicaDesc(C.Structure):
 class Options(C.Structure):
     _fields_ = [("nstlist", C.c_int32), ("skin", C.c_double), ("steps_per_graph", C.c_int32),
                 ("use_graph", C.c_int32), ("max_neighbors", C.c_int32),
-                ("tangent", C.c_int32), ("reserved", C.c_int32 * 6)]
+                ("tangent", C.c_int32), ("force_shape", C.c_int32), ("reserved", C.c_int32 * 5)]
 
 
 _vp = C.c_void_p
@@ -94,6 +94,8 @@ _lib.vp_kernel_timing.restype = C.c_int
 _lib.vp_kernel_timing.argtypes = [_vp, _dp, C.POINTER(C.c_int64), C.c_int32]
 _lib.vp_debug_force_dir.restype = C.c_int
 _lib.vp_debug_force_dir.argtypes = [_vp, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_void_p]
+_lib.vp_debug_trajectory_state.restype = C.c_int
+_lib.vp_debug_trajectory_state.argtypes = [_vp, _dp, _dp, _dp, _dp, _dp]
 _lib.vp_pair_count.restype = C.c_int
 _lib.vp_pair_count.argtypes = [_vp, C.c_int32, C.POINTER(C.c_int64)]
 _lib.vp_last_error.restype = C.c_char_p
@@ -102,7 +104,7 @@ _lib.vp_last_error.argtypes = []
 EXPORTED = ("vp_system_create", "vp_system_destroy", "vp_forces", "vp_step_batch",
             "vp_functional", "vp_select_path", "vp_get_state", "vp_observables", "vp_sizes",
             "vp_debug_pairs", "vp_debug_noise", "vp_set_timing", "vp_kernel_timing", "vp_pair_count",
-            "vp_debug_force_dir", "vp_last_error")
+            "vp_debug_force_dir", "vp_debug_trajectory_state", "vp_last_error")
 
 
 def _check(st):
@@ -163,13 +165,14 @@ class System:
     """A batch of trial trajectories (vp_system)."""
 
     def __init__(self, reps, nstlist=0, skin=0.0, steps_per_graph=0, use_graph=True,
-                 max_neighbors=0, tangent=False):
+                 max_neighbors=0, tangent=False, force_shape=0):
         keep = []
         descs = (ReplicaDesc * len(reps))(*[_desc(d, keep) for d in reps])
         opt = Options()
         opt.nstlist, opt.skin, opt.steps_per_graph = nstlist, skin, steps_per_graph
         opt.use_graph, opt.max_neighbors = int(bool(use_graph)), max_neighbors
         opt.tangent = int(bool(tangent))
+        opt.force_shape = int(force_shape)
         h = _vp()
         _check(_lib.vp_system_create(descs, len(reps), C.byref(opt), C.byref(h)))
         self._h = h
@@ -211,6 +214,23 @@ class System:
         g = np.zeros((self.n_reps, 2)) if gradient else None
         _check(_lib.vp_functional(self._h, phi.ctypes.data_as(_dp), g.ctypes.data_as(_dp) if gradient else None))
         return (phi, g) if gradient else phi
+
+    def trajectory_state(self, tangents=False):
+        """Exact state in user order (FP64): x, v [N, 3]; with tangents also
+        xt, vt [2, N, 3] and the derivative accumulators pd [R, 4]."""
+        x = np.zeros((self.n_total, 3))
+        v = np.zeros((self.n_total, 3))
+        if not tangents:
+            _check(_lib.vp_debug_trajectory_state(self._h, x.ctypes.data_as(_dp), v.ctypes.data_as(_dp),
+                                                  None, None, None))
+            return x, v
+        xt = np.zeros((2, self.n_total, 3))
+        vt = np.zeros((2, self.n_total, 3))
+        pd = np.zeros((self.n_reps, 4))
+        _check(_lib.vp_debug_trajectory_state(self._h, x.ctypes.data_as(_dp), v.ctypes.data_as(_dp),
+                                              xt.ctypes.data_as(_dp), vt.ctypes.data_as(_dp),
+                                              pd.ctypes.data_as(_dp)))
+        return x, v, xt, vt, pd
 
     def force_dir(self, x, dx, t=0.0):
         """Directional derivatives of the total force along dx ([2, N_total, 3]

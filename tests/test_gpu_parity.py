@@ -477,3 +477,36 @@ def test_uneven_batch_runs_and_matches_solo(c4_subset):
     xs, _ = solo.get_state()
     a, b = batch.offsets[r], batch.offsets[r + 1]
     assert np.array_equal(xs.cpu().numpy(), xb[a:b])
+
+
+def test_functional_gradient_late_in_a_2000_step_segment():
+    """Trials of the 12,560-atom system with the 2,000-step ramp: after 1,990
+    GPU steps the oracle continues the GPU's exact state and tangents for 10
+    steps; the tangents and the increments of the derivative accumulators
+    must agree (the trajectories themselves diverge chaotically over 2,000
+    steps, so only a continuation from the same state is comparable)."""
+    say("functional gradient: steps 1990-2000 of a 2000-step segment")
+    reps = synth.c5_adjoint(n_rep=2)
+    system = vp.System(reps, tangent=True, steps_per_graph=10)
+    system.step_batch(1990)
+    x, v, xt, vt, pd0 = system.trajectory_state(tangents=True)
+    system.step_batch(10)
+    x1, _, xt1, _, pd1 = system.trajectory_state(tangents=True)
+    for r, d in enumerate(reps):
+        a, b = system.offsets[r], system.offsets[r + 1]
+        o = O.Oracle(d)
+        st = o.init(x0_of(d))        # z(X_0) of the ramp
+        st.step = 1990
+        xr, vr = x[a:b].copy(), v[a:b].copy()
+        xtr, vtr = np.ascontiguousarray(xt[:, a:b]), np.ascontiguousarray(vt[:, a:b])
+        pd = np.zeros(4)
+        assert o.run_tangent(xr, vr, st, xtr, vtr, pd, 10) == 0
+        dx = np.abs(xr - x1[a:b]).max()
+        rel_t = [np.linalg.norm(xtr[k] - xt1[k, a:b]) / np.linalg.norm(xtr[k]) for k in range(2)]
+        inc = pd1[r, :2] - pd0[r, :2]
+        say(f"  replica {r}: 10-step dx {dx:.2e}, tangent rel {rel_t[0]:.2e} {rel_t[1]:.2e}, "
+            f"dS/dtheta sums {inc} vs {pd[:2]}")
+        assert dx <= X_TOL
+        for k in range(2):
+            assert rel_t[k] <= G_REL
+            assert abs(inc[k] - pd[k]) <= G_REL * abs(pd[k])
