@@ -50,8 +50,14 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--workload", choices=("c3", "c4"), default="c3",
+                    help="c3: 64 replicas of the 12,560-atom system; c4: 32 replicas of "
+                         "5,000-40,000 atoms with cutoffs 0.9 / 1.2 nm")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="run every block with --force-shape instead of timing the tile shapes "
+                         "per size bucket at creation")
     ap.add_argument("--force-shape", type=int, default=0,
-                    help="tile shape of the force kernel (vp_options.force_shape)")
+                    help="tile shape of the force kernel with --no-autotune (vp_options.force_shape)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="also run one device-to-device copy of MIB MiB (a known amount of HBM "
                          "traffic that calibrates rocprofv3's FETCH_SIZE/WRITE_SIZE counters)")
@@ -67,16 +73,33 @@ def main():
 
     from paper_1405_6104_amd import synth, vp
 
-    torch.cuda.set_device(0)
     B = args.md_per_step
     t0 = time.time()
-    base = synth.c2_single()
-    reps = synth.c3_batch(args.replicas, base=base,
-                          n_steps=B * (args.steps + args.warmup + args.timing_steps))
+    if args.workload == "c3":
+        base = synth.c2_single()
+        reps = synth.c3_batch(args.replicas, base=base,
+                              n_steps=B * (args.steps + args.warmup + args.timing_steps))
+        workload = ("64 trial paths x 12,560 atoms (560-atom solute + 4,000 flexible waters), "
+                    "5.0 nm box, rc 1.0 nm, dt 1 fs, contact-map bias, graph-captured batch")
+    else:
+        # replicas are independent: built by forked workers before the GPU is touched
+        workers = max(1, min(16, os.cpu_count() or 1))
+        reps = synth.c4_uneven(workers=workers, progress=lambda r, n: print(
+            f"# replica {r}: {n} atoms ({time.time() - t0:.0f} s)", file=sys.stderr, flush=True))
+        base = reps[0]
+        workload = ("32 trial paths of 5,000-40,000 atoms (log-uniform; 280-560-atom solute, "
+                    "water at 33.4 /nm^3), rc 0.9 or 1.2 nm, dt 1 fs, contact-map bias, "
+                    "graph-captured batch")
     n_atoms = sum(int(d["n_atoms"]) for d in reps)
     print(f"# generated {len(reps)} replicas, {n_atoms} atoms in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
-    system = vp.System(reps, steps_per_graph=B, force_shape=args.force_shape)
-    print(f"# system created", file=sys.stderr, flush=True)
+    torch.cuda.set_device(0)
+    system = vp.System(reps, steps_per_graph=B, force_shape=args.force_shape,
+                       autotune=not args.no_autotune)
+    buckets, split = system.tile_buckets()
+    for b in buckets:
+        print(f"# bucket rc {b['r_cut']} 2^{b['log2_atoms']}: {b['replicas']} replicas, tile {b['tile']}, "
+              f"ms per shape {['%.4f' % t for t in b['ms']]}", file=sys.stderr, flush=True)
+    print(f"# system created (split launches: {split})", file=sys.stderr, flush=True)
 
     for _ in range(args.warmup):
         system.step_batch(B)
@@ -151,7 +174,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         from oracle import oracle as O  # CPU baseline leg only
-        o = O.Oracle(base)
+        o = O.Oracle(base)  # the first replica of the batch
         x = np.array(base["x0"], dtype=np.float64)
         v = o.maxwell()
         st = o.init(x)
@@ -163,8 +186,8 @@ def main():
         tc = time.perf_counter() - tc
         cpu = {"value": int(base["n_atoms"]) * n_cpu / tc, "unit": "atom-steps/s", "cores": 1,
                "kind": "oracle",
-               "sample": f"{n_cpu} BAOAB steps of one 12,560-atom replica (FP64, single thread, "
-                         f"cell-list pairs), {tc:.1f} s"}
+               "sample": f"{n_cpu} BAOAB steps of one {int(base['n_atoms']):,}-atom replica (FP64, "
+                         f"single thread, cell-list pairs), {tc:.1f} s"}
         print(f"# cpu oracle: {cpu['value']:.4e} atom-steps/s over {n_cpu} steps", file=sys.stderr, flush=True)
 
     out = {
@@ -181,9 +204,10 @@ def main():
         "dtype": "f32 pair arithmetic, i64 fixed-point forces, f64 functional",
         "data": "synthetic",
         "config": {
-            "workload": "64 trial paths x 12,560 atoms (560-atom solute + 4,000 flexible waters), "
-                        "5.0 nm box, rc 1.0 nm, dt 1 fs, contact-map bias, graph-captured batch",
-            "replicas": len(reps), "atoms_per_replica": int(base["n_atoms"]),
+            "workload": workload,
+            "replicas": len(reps),
+            "atoms_per_replica": (int(base["n_atoms"]) if args.workload == "c3"
+                                  else [int(d["n_atoms"]) for d in reps]),
             "md_steps_per_bench_step": B, "global_batch": n_atoms, "parallelism": "replicas",
         },
         "ns_per_day_per_replica": ns_day,
@@ -193,10 +217,14 @@ def main():
         "unstable_replicas": unstable,
         "list_overflow_replicas": overflow,
         "list_stats": list_stats,
+        "tiles": {"autotuned": not args.no_autotune, "split_launches": split,
+                  "buckets": [{k: b[k] for k in ("r_cut", "log2_atoms", "replicas", "blocks", "tile", "ms")}
+                              for b in buckets]},
         "roofline": {
             "bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32_TFLOPS,
-            "traffic": FORCE_TRAFFIC_BYTES if args.replicas == 64 else None,
+            "traffic": (FORCE_TRAFFIC_BYTES if args.workload == "c3" and args.replicas == 64
+                        else None),
             "kernel": "k_forces (nonbonded LJ+RF + bonded)",
             "flop_per_unit": FLOP_PER_PAIR, "units_per_launch": pairs_total,
             "avg_launch_ms": force_ms, "launches_timed": n_launch,

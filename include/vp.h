@@ -119,8 +119,27 @@ typedef struct {
                               harmonic and constant biases only */
   int32_t force_shape;     /* tile shape of the force kernel (waves per 64-atom block x list
                               entries per batch): 0: 8x8 (default), 1: 16x4, 2: 16x8, 3: 4x8 */
-  int32_t reserved[5];
+  int32_t autotune;        /* 1: time every tile shape on each size bucket at creation and
+                              launch each bucket with its fastest (force_shape is ignored);
+                              the forces are bitwise the same for every shape */
+  int32_t reserved[4];
 } vp_options;
+
+#define VP_FORCE_SHAPES 4
+
+/* One size bucket of a batch: the replicas that share a cutoff and
+ * floor(log2 n_atoms), and the force-kernel tile shape their blocks run with.
+ * With vp_options.autotune, ms[k] is the shortest of several timed force
+ * launches of shape k over the bucket's blocks alone; otherwise ms is zero. */
+typedef struct {
+  double r_cut;        /* nm */
+  int32_t log2_atoms;  /* floor(log2 n_atoms) of its replicas */
+  int32_t n_replicas;
+  int32_t n_blocks;    /* 64-atom blocks (padding included) */
+  int32_t shape;       /* the vp_options.force_shape index its blocks run with */
+  int32_t waves, entries;  /* that shape: waves per block, list entries per batch */
+  double ms[VP_FORCE_SHAPES];
+} vp_tile_bucket;
 
 /* Positions are held as 32-bit fixed point in units of 2^-24 nm, so that
  * periodic images are exact integer shifts: x0 and x_dev are rounded to the
@@ -207,6 +226,14 @@ vp_status vp_sizes(const vp_system *s, int64_t *n_atoms_total, int32_t *n_reps);
  * pairs (i < j, replica-local user indices) whose current FP32 separation
  * passes the membership predicate, into pairs_host HOST [cap][2].
  * *count receives the number of such pairs (which may exceed cap). */
+/* The size buckets of the batch and their force tile shapes, in order of
+ * first appearance in the batch: writes min(cap, count) entries to out (HOST,
+ * may be NULL when cap is 0) and the count to *n_buckets.  With autotuning,
+ * *split (may be NULL) is 1 when the buckets run as one launch per chosen
+ * shape and 0 when one shape over every block timed faster. */
+vp_status vp_tile_buckets(vp_system *s, vp_tile_bucket *out, int32_t cap, int32_t *n_buckets,
+                          int32_t *split);
+
 /* Diagnostic (derivative checks): the directional derivatives of the total
  * force of vp_forces along two displacements of the positions, parameters
  * fixed -- the Hessian-vector products that carry the tangents.

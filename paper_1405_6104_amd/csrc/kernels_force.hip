@@ -26,11 +26,70 @@
 
 namespace vp {
 
-// Tile shape: PARTS waves share one block's staged neighbourhood (each walks
-// every PARTS-th chunk of the lists) and evaluate UNROLL list entries per
-// batch of LDS reads; MINW asks the compiler for registers that let MINW
-// waves share a SIMD.  blist (or NULL for all blocks) selects the blocks of
-// one launch.
+// One list chunk (8 entries of one atom's list) evaluated against the staged
+// neighbourhood: LJ + reaction-field forces accumulated in the chunk's order
+// into (fx, fy, fz), energies into (elj, erf) when ENERGY.  UNROLL entries
+// share one batch of LDS reads.
+template <bool ENERGY, int UNROLL>
+__device__ __forceinline__ void eval_chunk(const uint4 e, const int4 *__restrict__ st,
+                                           const float4 *__restrict__ tab, const float4 ti, int wx,
+                                           int wy, int wz, float rc2, float krf2, const RepInfo &R,
+                                           float &fx, float &fy, float &fz, double &elj, double &erf) {
+  const uint32_t w[4] = {e.x, e.y, e.z, e.w};
+#pragma unroll
+  for (int h = 0; h < 8; h += UNROLL) {
+    int4 sj[UNROLL];
+#pragma unroll
+    for (int v = 0; v < UNROLL; ++v) {
+      const int u = h + v;
+      sj[v] = st[(w[u >> 1] >> (16 * (u & 1))) & 0xffffu];
+    }
+    float4 tj[UNROLL];
+#pragma unroll
+    for (int v = 0; v < UNROLL; ++v) tj[v] = tab[sj[v].w];
+#pragma unroll
+    for (int u = 0; u < UNROLL; ++u) {
+      // every entry is evaluated; the cutoff selects (no divergent branch)
+      const float dx = (float)(sj[u].x - wx), dy = (float)(sj[u].y - wy), dz = (float)(sj[u].z - wz);
+      const float r2 = qr2(dx, dy, dz);
+      const bool in = r2 < rc2;
+      const float rinv = __builtin_amdgcn_rsqf(r2);
+      const float r2inv = rinv * rinv;
+      const float sg = ti.y + tj[u].y;
+      const float sr2 = sg * sg * r2inv;
+      const float sr6 = sr2 * sr2 * sr2;
+      const float ee = ti.z * tj[u].z;
+      const float flj = ee * sr6 * __builtin_fmaf(2.0f, sr6, -1.0f) * r2inv;
+      const float qq = ti.x * tj[u].x;
+      const float fc = qq * __builtin_fmaf(rinv, r2inv, -krf2);
+      const float fs = in ? flj + fc : 0.0f;
+      fx = __builtin_fmaf(-fs, dx, fx);
+      fy = __builtin_fmaf(-fs, dy, fy);
+      fz = __builtin_fmaf(-fs, dz, fz);
+      if (ENERGY && in) {
+        // ee = 24 eps 2^48, qq = f q q 2^72 (see the type table)
+        const double e4 = (double)ee * (1.0 / 6.0) * (kInvQ * kInvQ);
+        const double s2c = (double)sg * sg / ((double)rc2);
+        const double s6c = s2c * s2c * s2c;
+        elj += e4 * ((double)sr6 * sr6 - sr6) - e4 * (s6c * s6c - s6c);
+        const double fqq = (double)qq * (kInvQ * kInvQ * kInvQ);
+        erf += fqq * ((double)rinv * kQ + R.krf * (double)r2 * (kInvQ * kInvQ) - R.crf);
+      }
+    }
+  }
+}
+
+// Tile shape: PARTS waves share one block's staged neighbourhood and UNROLL
+// list entries share one batch of LDS reads; MINW asks the compiler for
+// registers that let MINW waves share a SIMD.  blist (or NULL for all blocks)
+// selects the blocks of one launch.
+//
+// The result does not depend on the shape: chunk c of an atom's list is summed
+// into logical accumulator c mod kLogicalParts (each wave holds
+// kLogicalParts / PARTS of them, in chunk order), and the accumulators are
+// added in index order at the end.  Every shape therefore performs the same
+// FP32 operations in the same order, and forces and energies agree bit for
+// bit whichever shape a launch uses.
 template <bool ENERGY, int PARTS, int UNROLL, int MINW>
 __global__ __launch_bounds__(64 * PARTS) __attribute__((amdgpu_waves_per_eu(MINW))) void k_forces(const RepInfo *__restrict__ info, Work W,
                                                        const int32_t *__restrict__ tile_rep,
@@ -41,11 +100,15 @@ __global__ __launch_bounds__(64 * PARTS) __attribute__((amdgpu_waves_per_eu(MINW
                                                        const BTerm *__restrict__ bterms,
                                                        int stage_slots) {
   constexpr int NT = 64 * PARTS;
+  constexpr int SETS = kLogicalParts / PARTS;
+  static_assert(kLogicalParts % PARTS == 0, "PARTS must divide the logical accumulator count");
   extern __shared__ int4 lds[];
   int4 *st = lds;                                              // [stage_slots] staged atoms
   float4 *tab = reinterpret_cast<float4 *>(lds + stage_slots);  // the replica's type table
-  float *red = reinterpret_cast<float *>(lds);  // reuses the staging area after the pair loop
-  __shared__ double s_red[PARTS];
+  // after the pair loop the staging area holds the logical partial sums:
+  // forces [3][kLogicalParts][64] FP32, then energies [2][kLogicalParts][64] FP64
+  float *red = reinterpret_cast<float *>(lds);
+  double *ered = reinterpret_cast<double *>(lds) + 3 * kLogicalParts * kBlk / 2;
   const int bt = xcd_tile(blockIdx.x, nblk);
   if (bt < 0) return;
   const int b = blist ? blist[bt] : bt;
@@ -85,16 +148,21 @@ __global__ __launch_bounds__(64 * PARTS) __attribute__((amdgpu_waves_per_eu(MINW
   const int p = p0 + lane;
   const int slot = R.off + p;
   const bool active = p < R.n;
-  float fx = 0.0f, fy = 0.0f, fz = 0.0f;
-  double elj = 0.0, erf = 0.0;
+  float fx[SETS], fy[SETS], fz[SETS];
+  double elj[SETS], erf[SETS];
+#pragma unroll
+  for (int k = 0; k < SETS; ++k) {
+    fx[k] = fy[k] = fz[k] = 0.0f;
+    elj[k] = erf[k] = 0.0;
+  }
   int4 xi = make_int4(0, 0, 0, 0);
-  int wx = 0, wy = 0, wz = 0;
+  int nrot = 0;  // chunks this wave evaluated: set k then holds logical (k + nrot) mod SETS
   if (active) {
     xi = W.xq[slot];
     const int wr = W.wrap[slot];
-    wx = xi.x - unpack_wrap(wr, 0) * Lx;
-    wy = xi.y - unpack_wrap(wr, 1) * Ly;
-    wz = xi.z - unpack_wrap(wr, 2) * Lz;
+    const int wx = xi.x - unpack_wrap(wr, 0) * Lx;
+    const int wy = xi.y - unpack_wrap(wr, 1) * Ly;
+    const int wz = xi.z - unpack_wrap(wr, 2) * Lz;
     const float4 ti = tab[xi.w];
     const float rc2 = R.rc2q, krf2 = R.krf2q;
     const int nch = W.nbcnt[slot] >> 3;
@@ -102,71 +170,57 @@ __global__ __launch_bounds__(64 * PARTS) __attribute__((amdgpu_waves_per_eu(MINW
                                                       (int64_t)(b - R.blk0) * R.maxnb * kBlk) + lane;
     uint4 e = lp[(int64_t)min(part, max(nch - 1, 0)) * kBlk];
     for (int c = part; c < nch; c += PARTS) {
-      // the next chunk's indices are fetched while this one is evaluated (the
-      // last chunk is fetched again rather than reading past the list)
+      // the next chunk's indices are fetched while this one is evaluated
+      // (the last chunk is fetched again rather than reading past the list)
       const uint4 en = lp[(int64_t)min(c + PARTS, nch - 1) * kBlk];
-      const uint32_t w[4] = {e.x, e.y, e.z, e.w};
+      eval_chunk<ENERGY, UNROLL>(e, st, tab, ti, wx, wy, wz, rc2, krf2, R, fx[0], fy[0], fz[0],
+                                 elj[0], erf[0]);
+      // the sets rotate so that set 0 is always the one the next chunk feeds
 #pragma unroll
-      for (int h = 0; h < 8; h += UNROLL) {
-      int4 sj[UNROLL];
-#pragma unroll
-      for (int v = 0; v < UNROLL; ++v) {
-        const int u = h + v;
-        sj[v] = st[(w[u >> 1] >> (16 * (u & 1))) & 0xffffu];
-      }
-      float4 tj[UNROLL];
-#pragma unroll
-      for (int v = 0; v < UNROLL; ++v) tj[v] = tab[sj[v].w];
-#pragma unroll
-      for (int u = 0; u < UNROLL; ++u) {
-        // every entry is evaluated; the cutoff selects (no divergent branch)
-        const float dx = (float)(sj[u].x - wx), dy = (float)(sj[u].y - wy), dz = (float)(sj[u].z - wz);
-        const float r2 = qr2(dx, dy, dz);
-        const bool in = r2 < rc2;
-        const float rinv = __builtin_amdgcn_rsqf(r2);
-        const float r2inv = rinv * rinv;
-        const float sg = ti.y + tj[u].y;
-        const float sr2 = sg * sg * r2inv;
-        const float sr6 = sr2 * sr2 * sr2;
-        const float ee = ti.z * tj[u].z;
-        const float flj = ee * sr6 * __builtin_fmaf(2.0f, sr6, -1.0f) * r2inv;
-        const float qq = ti.x * tj[u].x;
-        const float fc = qq * __builtin_fmaf(rinv, r2inv, -krf2);
-        const float fs = in ? flj + fc : 0.0f;
-        fx = __builtin_fmaf(-fs, dx, fx);
-        fy = __builtin_fmaf(-fs, dy, fy);
-        fz = __builtin_fmaf(-fs, dz, fz);
-        if (ENERGY && in) {
-          // ee = 24 eps 2^48, qq = f q q 2^72 (see the type table)
-          const double e4 = (double)ee * (1.0 / 6.0) * (kInvQ * kInvQ);
-          const double s2c = (double)sg * sg / ((double)rc2);
-          const double s6c = s2c * s2c * s2c;
-          elj += e4 * ((double)sr6 * sr6 - sr6) - e4 * (s6c * s6c - s6c);
-          const double fqq = (double)qq * (kInvQ * kInvQ * kInvQ);
-          erf += fqq * ((double)rinv * kQ + R.krf * (double)r2 * (kInvQ * kInvQ) - R.crf);
+      for (int k = 0; k + 1 < SETS; ++k) {
+        float t = fx[k]; fx[k] = fx[k + 1]; fx[k + 1] = t;
+        t = fy[k]; fy[k] = fy[k + 1]; fy[k + 1] = t;
+        t = fz[k]; fz[k] = fz[k + 1]; fz[k + 1] = t;
+        if (ENERGY) {
+          double u = elj[k]; elj[k] = elj[k + 1]; elj[k + 1] = u;
+          u = erf[k]; erf[k] = erf[k + 1]; erf[k + 1] = u;
         }
-      }
       }
       e = en;
     }
+    nrot = nch > part ? (nch - part + PARTS - 1) / PARTS : 0;
   }
-  // ---- fixed-order sum of the partial forces of the waves, bonded terms, store
+  // ---- fixed-order sum of the logical partial sums, bonded terms, store
   __syncthreads();  // every wave is done with the staged neighbourhood
-  red[tid] = fx;
-  red[NT + tid] = fy;
-  red[2 * NT + tid] = fz;
+#pragma unroll
+  for (int k = 0; k < SETS; ++k) {
+    const int q = ((k + nrot) % SETS) * PARTS + part;  // logical accumulator held in set k
+    red[(0 * kLogicalParts + q) * kBlk + lane] = fx[k];
+    red[(1 * kLogicalParts + q) * kBlk + lane] = fy[k];
+    red[(2 * kLogicalParts + q) * kBlk + lane] = fz[k];
+    if (ENERGY) {
+      ered[(0 * kLogicalParts + q) * kBlk + lane] = elj[k];
+      ered[(1 * kLogicalParts + q) * kBlk + lane] = erf[k];
+    }
+  }
   __syncthreads();
-  double ebond = 0.0, eangle = 0.0;
   if (part == 0) {
     long long fxs = 0, fys = 0, fzs = 0;
+    double ebond = 0.0, eangle = 0.0, el = 0.0, er = 0.0;
     if (active) {
-      float sx = red[lane], sy = red[NT + lane], sz = red[2 * NT + lane];
-#pragma unroll
-      for (int q = 1; q < PARTS; ++q) {
+      float sx = red[lane], sy = red[kLogicalParts * kBlk + lane], sz = red[2 * kLogicalParts * kBlk + lane];
+#pragma unroll 4
+      for (int q = 1; q < kLogicalParts; ++q) {
         sx += red[q * kBlk + lane];
-        sy += red[NT + q * kBlk + lane];
-        sz += red[2 * NT + q * kBlk + lane];
+        sy += red[(kLogicalParts + q) * kBlk + lane];
+        sz += red[(2 * kLogicalParts + q) * kBlk + lane];
       }
+      if (ENERGY)
+#pragma unroll 2
+        for (int q = 0; q < kLogicalParts; ++q) {
+          el += ered[q * kBlk + lane];
+          er += ered[(kLogicalParts + q) * kBlk + lane];
+        }
       double bx = 0.0, by = 0.0, bz = 0.0;
       const int a = W.orig[slot];
       const int ga = R.uoff + a;
@@ -227,17 +281,16 @@ __global__ __launch_bounds__(64 * PARTS) __attribute__((amdgpu_waves_per_eu(MINW
     W.F[slot] = fxs;
     W.F[W.fstride + slot] = fys;
     W.F[2 * W.fstride + slot] = fzs;
-  }
-  if (ENERGY) {
-    const double v0 = block_sum<NT>(0.5 * elj, s_red);
-    const double v1 = block_sum<NT>(0.5 * erf, s_red);
-    const double v2 = block_sum<NT>(ebond, s_red);
-    const double v3 = block_sum<NT>(eangle, s_red);
-    if (tid == 0) {
-      W.epart[4 * (size_t)b + 0] = v0;
-      W.epart[4 * (size_t)b + 1] = v1;
-      W.epart[4 * (size_t)b + 2] = v2;
-      W.epart[4 * (size_t)b + 3] = v3;
+    if (ENERGY) {
+      // the block's sums over its 64 atoms (wave 0 alone, fixed butterfly order)
+      const double v0 = wave_sum(0.5 * el), v1 = wave_sum(0.5 * er);
+      const double v2 = wave_sum(ebond), v3 = wave_sum(eangle);
+      if (lane == 0) {
+        W.epart[4 * (size_t)b + 0] = v0;
+        W.epart[4 * (size_t)b + 1] = v1;
+        W.epart[4 * (size_t)b + 2] = v2;
+        W.epart[4 * (size_t)b + 3] = v3;
+      }
     }
   }
 }
@@ -947,7 +1000,8 @@ static inline int xcd_grid(int nb) { return 8 * ((nb + 7) / 8); }
 
 size_t force_lds_bytes(const vp_system *s) {
   size_t stage = sizeof(int4) * ((size_t)(s->stage_cap_max + 1) + (size_t)(s->ntypes_max + 1));
-  size_t red = sizeof(float) * 3 * 64 * kMaxForceParts;
+  // logical partial sums: forces FP32 [3][kLogicalParts][64], energies FP64 [2][kLogicalParts][64]
+  size_t red = (sizeof(float) * 3 + sizeof(double) * 2) * kLogicalParts * kBlk;
   return stage > red ? stage : red;
 }
 
@@ -1000,7 +1054,11 @@ void launch_forces_shape(vp_system *s, Work &W, bool energy, int shape, const in
 }
 
 void launch_forces(vp_system *s, Work &W, bool energy, hipStream_t st) {
-  launch_forces_shape(s, W, energy, s->force_shape, nullptr, s->n_blocks, st);
+  if (s->force_plan.empty()) {
+    launch_forces_shape(s, W, energy, s->force_shape, nullptr, s->n_blocks, st);
+    return;
+  }
+  for (const auto &g : s->force_plan) launch_forces_shape(s, W, energy, g.shape, g.blist, g.nblk, st);
 }
 
 void launch_cv(vp_system *s, Work &W, int inc_step, hipStream_t st, bool tan) {

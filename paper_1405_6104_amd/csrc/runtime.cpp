@@ -354,9 +354,7 @@ static vp_status build(vp_system *s, const vp_replica_desc *reps, int32_t n_reps
     // force workgroups share a CU (up to the staging array's size), and never
     // less than the estimate above; a block whose candidates would overflow
     // it is built again in exact mode.
-    const long long budget =
-        ((long long)kMaxLds - (long long)sizeof(double) * kMaxForceParts) / (long long)sizeof(int4) -
-        (ntypes_max + 1) - 1;
+    const long long budget = (long long)kMaxLds / (long long)sizeof(int4) - (ntypes_max + 1) - 1;
     stage_cap_max = 0;
     for (int r = 0; r < n_reps; ++r) {
       RepInfo &R = s->info_h[r];
@@ -369,7 +367,7 @@ static vp_status build(vp_system *s, const vp_replica_desc *reps, int32_t n_reps
       stage_cap_max = std::max(stage_cap_max, R.stage_cap);
     }
     s->stage_cap_max = stage_cap_max;
-    size_t need = force_lds_bytes(s) + sizeof(double) * kMaxForceParts;
+    size_t need = force_lds_bytes(s);
     if (need > (size_t)kMaxLds)
       return fail(VP_ERR_ARG, "force kernel would need " + std::to_string(need) +
                                   " bytes of LDS per workgroup (limit " + std::to_string(kMaxLds) + ")");
@@ -520,6 +518,132 @@ static vp_status build(vp_system *s, const vp_replica_desc *reps, int32_t n_reps
   return VP_OK;
 }
 
+// ---------------- tile shapes per size bucket
+static_assert(kNumForceShapes == VP_FORCE_SHAPES, "shape count of the ABI");
+
+static void make_buckets(vp_system *s) {
+  s->buckets.clear();
+  for (int r = 0; r < s->R; ++r) {
+    const RepInfo &R = s->info_h[r];
+    const double rc = R.rc;
+    int lg = 0;
+    while ((2ll << lg) <= (long long)R.n) ++lg;
+    vp_system::TileBucket *b = nullptr;
+    for (auto &x : s->buckets)
+      if (x.r_cut == rc && x.log2n == lg) b = &x;
+    if (!b) {
+      s->buckets.push_back({rc, lg, 0, {}, s->force_shape, {0.0}});
+      b = &s->buckets.back();
+    }
+    b->nrep += 1;
+    for (int k = 0; k < R.ntiles * (kTile / kBlk); ++k) b->blocks.push_back(R.blk0 + k);
+  }
+}
+
+// Shortest of `reps` timed executions of the launches `plan` (after one untimed).
+static vp_status time_plan(vp_system *s, const std::vector<vp_system::ForceLaunch> &plan, int reps,
+                           double *ms) {
+  hipEvent_t a, b;
+  HIPCHECK(hipEventCreate(&a));
+  HIPCHECK(hipEventCreate(&b));
+  double best = 1e30;
+  hipError_t e = hipSuccess;
+  for (int k = 0; k <= reps && e == hipSuccess; ++k) {
+    e = hipEventRecord(a, 0);
+    for (const auto &g : plan) launch_forces_shape(s, s->traj, false, g.shape, g.blist, g.nblk, 0);
+    if (e == hipSuccess) e = hipEventRecord(b, 0);
+    if (e == hipSuccess) e = hipEventSynchronize(b);
+    float t = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, a, b);
+    if (k > 0 && t < best) best = t;
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  if (e == hipSuccess) e = hipGetLastError();
+  if (e != hipSuccess) return fail(VP_ERR_HIP, std::string("autotune: ") + hipGetErrorString(e));
+  *ms = best;
+  return VP_OK;
+}
+
+// Times every shape on every bucket's blocks, groups the buckets by their
+// fastest shape into one launch per shape, and keeps that split plan only if it
+// beats the fastest single shape over all blocks.  The forces do not depend on
+// the shape, so the choice affects time only.
+static vp_status autotune(vp_system *s) {
+  constexpr int kReps = 5;
+  std::vector<const int32_t *> dev(s->buckets.size());
+  for (size_t i = 0; i < s->buckets.size(); ++i) {
+    auto &b = s->buckets[i];
+    int32_t *p = nullptr;
+    TRY(upload(s, &p, b.blocks));
+    dev[i] = p;
+    int best = 0;
+    for (int k = 0; k < kNumForceShapes; ++k) {
+      TRY(time_plan(s, {{k, p, (int)b.blocks.size()}}, kReps, &b.ms[k]));
+      if (b.ms[k] < b.ms[best]) best = k;
+    }
+    b.shape = best;
+  }
+  std::vector<vp_system::ForceLaunch> split;
+  for (int k = 0; k < kNumForceShapes; ++k) {
+    std::vector<int32_t> blocks;
+    for (const auto &b : s->buckets)
+      if (b.shape == k) blocks.insert(blocks.end(), b.blocks.begin(), b.blocks.end());
+    if (blocks.empty()) continue;
+    std::sort(blocks.begin(), blocks.end());
+    int32_t *p = nullptr;
+    TRY(upload(s, &p, blocks));
+    split.push_back({k, p, (int)blocks.size()});
+  }
+  if (split.size() == 1) {  // one shape everywhere: a plain launch over all blocks
+    s->force_shape = split[0].shape;
+    s->force_plan.clear();
+    s->plan_split = false;
+    return VP_OK;
+  }
+  double t_split = 0.0, t_one = 1e30;
+  int one = 0;
+  TRY(time_plan(s, split, kReps, &t_split));
+  for (int k = 0; k < kNumForceShapes; ++k) {
+    double t = 0.0;
+    TRY(time_plan(s, {{k, nullptr, s->n_blocks}}, kReps, &t));
+    if (t < t_one) {
+      t_one = t;
+      one = k;
+    }
+  }
+  if (t_split < t_one) {
+    s->force_plan = split;
+    s->plan_split = true;
+  } else {
+    s->force_shape = one;
+    s->force_plan.clear();
+    s->plan_split = false;
+    for (auto &b : s->buckets) b.shape = one;
+  }
+  return VP_OK;
+}
+
+extern "C" vp_status vp_tile_buckets(vp_system *s, vp_tile_bucket *out, int32_t cap,
+                                     int32_t *n_buckets, int32_t *split) {
+  if (!s || !n_buckets || cap < 0 || (cap > 0 && !out)) return fail(VP_ERR_ARG, "invalid argument");
+  *n_buckets = (int32_t)s->buckets.size();
+  if (split) *split = s->plan_split ? 1 : 0;
+  for (int i = 0; i < (int)s->buckets.size() && i < cap; ++i) {
+    const auto &b = s->buckets[i];
+    vp_tile_bucket &o = out[i];
+    o.r_cut = b.r_cut;
+    o.log2_atoms = b.log2n;
+    o.n_replicas = b.nrep;
+    o.n_blocks = (int32_t)b.blocks.size();
+    o.shape = b.shape;
+    o.waves = kForceShapes[b.shape].parts;
+    o.entries = kForceShapes[b.shape].unroll;
+    for (int k = 0; k < kNumForceShapes; ++k) o.ms[k] = b.ms[k];
+  }
+  return VP_OK;
+}
+
 extern "C" vp_status vp_system_create(const vp_replica_desc *reps, int32_t n_reps,
                                       const vp_options *opt, vp_system **out) {
   if (!out) return fail(VP_ERR_ARG, "out is NULL");
@@ -575,6 +699,10 @@ extern "C" vp_status vp_system_create(const vp_replica_desc *reps, int32_t n_rep
     s->eval = Work{};
     s->maxnb_override = keep;
     st = build(s, reps, n_reps);
+  }
+  if (st == VP_OK) {
+    make_buckets(s);
+    if (o.autotune) st = autotune(s);
   }
   if (st != VP_OK) {
     std::string msg = g_err;

@@ -16,6 +16,7 @@ constexpr int kBlk = 64;             // atoms per neighbourhood block (one wave)
 constexpr int kParts = 8;            // waves sharing one block in the force kernel
 constexpr int kForceThreads = kParts * kBlk;
 constexpr int kMaxForceParts = 16;   // largest number of waves per block among the force tile shapes
+constexpr int kLogicalParts = 16;    // force partial sums per atom: list chunk c goes to c mod 16
 constexpr int kNumForceShapes = 4;
 struct ForceShape {
   int parts, unroll;  // waves per 64-atom block, list entries per batch of LDS reads
@@ -206,6 +207,23 @@ struct vp_system {
   bool eval_ready = false;
   bool tangent = false;  // derivatives of the functional are propagated
   int force_shape = 0;   // index into kForceShapes used by the force launches
+  // size buckets (cutoff, floor(log2 n)) with their blocks and tile shapes
+  struct TileBucket {
+    double r_cut;
+    int log2n, nrep;
+    std::vector<int32_t> blocks;
+    int shape;
+    double ms[vp::kNumForceShapes];
+  };
+  std::vector<TileBucket> buckets;
+  // force launches of one step: empty = one launch of force_shape over every block
+  struct ForceLaunch {
+    int shape;
+    const int32_t *blist;  // device
+    int nblk;
+  };
+  std::vector<ForceLaunch> force_plan;
+  bool plan_split = false;
   std::vector<int32_t> maxnb_override;  // per-replica list capacity set after a first build
   struct GraphEntry {
     int32_t steps;

@@ -359,14 +359,21 @@ def c3_batch(n_rep=64, seed=WORKLOAD_SEED, base=None, n_steps=10000):
     return [with_seed(base, seed + r + 1) for r in range(n_rep)]
 
 
-def c4_uneven(n_rep=32, seed=WORKLOAD_SEED, only=None):
+def _make_system_kw(kw):
+    return make_system(**kw)
+
+
+def c4_uneven(n_rep=32, seed=WORKLOAD_SEED, only=None, workers=1, progress=None):
     """Replicas with atom counts log-uniform in [5000, 40000], solute 280-560
     atoms, water at 33.4 /nm^3, cutoffs 0.9 or 1.2 nm.  The initial solute is
     grown at 9 atoms/nm^3 (in the smaller boxes its sphere is wider than the
     box and the growth uses minimum-image distances), the target structure at
-    15 atoms/nm^3."""
+    15 atoms/nm^3.  Each replica depends on its own seed only, so ``workers``
+    processes (forked; call this before the GPU is initialised) may build them
+    in parallel with the same result; ``progress(r, n_atoms)`` is called as
+    each one is done."""
     rng = np.random.default_rng(seed + 4)
-    reps = []
+    jobs = []
     for r in range(n_rep):
         N = int(math.exp(rng.uniform(math.log(5000), math.log(40000))))
         ns = int(rng.integers(280, 561))
@@ -377,10 +384,25 @@ def c4_uneven(n_rep=32, seed=WORKLOAD_SEED, only=None):
             continue  # the parameters are still drawn, so replica r is the same either way
         r_init = (3.0 * ns / (4.0 * math.pi * 9.0)) ** (1.0 / 3.0)
         r_final = (3.0 * ns / (4.0 * math.pi * 15.0)) ** (1.0 / 3.0)
-        reps.append(make_system(n_solute=ns, n_water=nw, box=L, r_cut=rc, dt=0.001,
-                                seed=seed + 100 * (r + 1), bias=BIAS_CONTACT,
-                                init_radius=r_init, final_radius=r_final, periodic_growth=True,
-                                n_steps_for_ramp=2000))
+        jobs.append((r, dict(n_solute=ns, n_water=nw, box=L, r_cut=rc, dt=0.001,
+                             seed=seed + 100 * (r + 1), bias=BIAS_CONTACT,
+                             init_radius=r_init, final_radius=r_final, periodic_growth=True,
+                             n_steps_for_ramp=2000)))
+    if workers <= 1 or len(jobs) <= 1:
+        reps = []
+        for r, kw in jobs:
+            reps.append(make_system(**kw))
+            if progress:
+                progress(r, reps[-1]["n_atoms"])
+        return reps
+    import multiprocessing as mp
+    with mp.get_context("fork").Pool(min(workers, len(jobs))) as pool:
+        pending = [pool.apply_async(_make_system_kw, (kw,)) for _, kw in jobs]
+        reps = []
+        for (r, _), p in zip(jobs, pending):
+            reps.append(p.get())
+            if progress:
+                progress(r, reps[-1]["n_atoms"])
     return reps
 
 

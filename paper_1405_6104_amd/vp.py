@@ -61,7 +61,16 @@ class ReplicaDesc(C.Structure):
 class Options(C.Structure):
     _fields_ = [("nstlist", C.c_int32), ("skin", C.c_double), ("steps_per_graph", C.c_int32),
                 ("use_graph", C.c_int32), ("max_neighbors", C.c_int32),
-                ("tangent", C.c_int32), ("force_shape", C.c_int32), ("reserved", C.c_int32 * 5)]
+                ("tangent", C.c_int32), ("force_shape", C.c_int32), ("autotune", C.c_int32),
+                ("reserved", C.c_int32 * 4)]
+
+FORCE_SHAPES = 4
+
+
+class TileBucket(C.Structure):
+    _fields_ = [("r_cut", C.c_double), ("log2_atoms", C.c_int32), ("n_replicas", C.c_int32),
+                ("n_blocks", C.c_int32), ("shape", C.c_int32), ("waves", C.c_int32),
+                ("entries", C.c_int32), ("ms", C.c_double * FORCE_SHAPES)]
 
 
 _vp = C.c_void_p
@@ -96,6 +105,9 @@ _lib.vp_debug_force_dir.restype = C.c_int
 _lib.vp_debug_force_dir.argtypes = [_vp, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_void_p]
 _lib.vp_debug_trajectory_state.restype = C.c_int
 _lib.vp_debug_trajectory_state.argtypes = [_vp, _dp, _dp, _dp, _dp, _dp]
+_lib.vp_tile_buckets.restype = C.c_int
+_lib.vp_tile_buckets.argtypes = [_vp, C.POINTER(TileBucket), C.c_int32, C.POINTER(C.c_int32),
+                                 C.POINTER(C.c_int32)]
 _lib.vp_pair_count.restype = C.c_int
 _lib.vp_pair_count.argtypes = [_vp, C.c_int32, C.POINTER(C.c_int64)]
 _lib.vp_last_error.restype = C.c_char_p
@@ -104,7 +116,8 @@ _lib.vp_last_error.argtypes = []
 EXPORTED = ("vp_system_create", "vp_system_destroy", "vp_forces", "vp_step_batch",
             "vp_functional", "vp_select_path", "vp_get_state", "vp_observables", "vp_sizes",
             "vp_debug_pairs", "vp_debug_noise", "vp_set_timing", "vp_kernel_timing", "vp_pair_count",
-            "vp_debug_force_dir", "vp_debug_trajectory_state", "vp_last_error")
+            "vp_debug_force_dir", "vp_debug_trajectory_state", "vp_tile_buckets",
+            "vp_last_error")
 
 
 def _check(st):
@@ -165,7 +178,7 @@ class System:
     """A batch of trial trajectories (vp_system)."""
 
     def __init__(self, reps, nstlist=0, skin=0.0, steps_per_graph=0, use_graph=True,
-                 max_neighbors=0, tangent=False, force_shape=0):
+                 max_neighbors=0, tangent=False, force_shape=0, autotune=False):
         keep = []
         descs = (ReplicaDesc * len(reps))(*[_desc(d, keep) for d in reps])
         opt = Options()
@@ -173,6 +186,7 @@ class System:
         opt.use_graph, opt.max_neighbors = int(bool(use_graph)), max_neighbors
         opt.tangent = int(bool(tangent))
         opt.force_shape = int(force_shape)
+        opt.autotune = int(bool(autotune))
         h = _vp()
         _check(_lib.vp_system_create(descs, len(reps), C.byref(opt), C.byref(h)))
         self._h = h
@@ -214,6 +228,22 @@ class System:
         g = np.zeros((self.n_reps, 2)) if gradient else None
         _check(_lib.vp_functional(self._h, phi.ctypes.data_as(_dp), g.ctypes.data_as(_dp) if gradient else None))
         return (phi, g) if gradient else phi
+
+    def tile_buckets(self):
+        """Size buckets (cutoff, floor(log2 n)) with the force tile shape each
+        runs with and, when autotuned, the timed ms per shape; plus whether the
+        buckets run as separate launches."""
+        n = C.c_int32(0)
+        split = C.c_int32(0)
+        _check(_lib.vp_tile_buckets(self._h, None, 0, C.byref(n), C.byref(split)))
+        arr = (TileBucket * max(n.value, 1))()
+        _check(_lib.vp_tile_buckets(self._h, arr, n.value, C.byref(n), C.byref(split)))
+        out = []
+        for b in arr[:n.value]:
+            out.append({"r_cut": b.r_cut, "log2_atoms": b.log2_atoms, "replicas": b.n_replicas,
+                        "blocks": b.n_blocks, "shape": b.shape, "tile": f"{b.waves}x{b.entries}",
+                        "ms": [float(t) for t in b.ms]})
+        return out, bool(split.value)
 
     def trajectory_state(self, tangents=False):
         """Exact state in user order (FP64): x, v [N, 3]; with tangents also

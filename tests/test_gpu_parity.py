@@ -510,3 +510,43 @@ def test_functional_gradient_late_in_a_2000_step_segment():
         for k in range(2):
             assert rel_t[k] <= G_REL
             assert abs(inc[k] - pd[k]) <= G_REL * abs(pd[k])
+
+
+# ------------------------------------------------------------------ tile shapes
+def test_every_force_tile_shape_gives_the_same_bits(c4_subset):
+    """The force kernel sums list chunk c of an atom into partial sum c mod 16
+    whatever its tile shape, so forces and energies agree bit for bit."""
+    reps = list(c4_subset) + [synth.tiny(seed=3), synth.lj_box()]
+    say("tile shapes: bitwise agreement", [int(d["n_atoms"]) for d in reps])
+    xs = [f32(d["x0"]) for d in reps]
+    ref = None
+    for k in range(vp.FORCE_SHAPES):
+        f, e = gpu_forces(vp.System(reps, force_shape=k), xs, 0.0)
+        if ref is None:
+            ref = (f, e)
+            continue
+        assert np.array_equal(f, ref[0]), k
+        assert np.array_equal(e, ref[1]), k
+
+
+def test_autotuned_uneven_batch(c4_subset):
+    say("autotune: uneven batch buckets")
+    tuned = vp.System(c4_subset, autotune=True, steps_per_graph=10)
+    buckets, split = tuned.tile_buckets()
+    for b in buckets:
+        say(f"  rc {b['r_cut']} 2^{b['log2_atoms']}: {b['replicas']} replicas, {b['blocks']} blocks, "
+            f"tile {b['tile']}, ms {['%.4f' % t for t in b['ms']]}")
+    say("  split launches:", split)
+    keys = sorted((d["r_cut"], int(np.floor(np.log2(d["n_atoms"])))) for d in c4_subset)
+    assert sorted((b["r_cut"], b["log2_atoms"]) for b in buckets) == sorted(set(keys))
+    assert sum(b["replicas"] for b in buckets) == len(c4_subset)
+    for b in buckets:
+        assert 0 <= b["shape"] < vp.FORCE_SHAPES and all(t > 0 for t in b["ms"])
+        if not split:
+            assert b["shape"] == buckets[0]["shape"]
+    plain = vp.System(c4_subset, steps_per_graph=10)
+    for s in (tuned, plain):
+        s.step_batch(40)
+    assert np.array_equal(tuned.get_state()[0].cpu().numpy(), plain.get_state()[0].cpu().numpy())
+    b0, _ = plain.tile_buckets()
+    assert all(b["shape"] == 0 and b["ms"] == [0.0] * vp.FORCE_SHAPES for b in b0)
