@@ -53,6 +53,14 @@ def main():
     ap.add_argument("--workload", choices=("c3", "c4"), default="c3",
                     help="c3: 64 replicas of the 12,560-atom system; c4: 32 replicas of "
                          "5,000-40,000 atoms with cutoffs 0.9 / 1.2 nm")
+    ap.add_argument("--equilibrate", type=int, default=6000, metavar="MD_STEPS",
+                    help="untimed MD steps without bias before the trials start: the synthetic "
+                         "start relaxes from ~800 K to 300 K, and the trials then begin at t = 0 "
+                         "from that thermal state (0: start from the generated structures)")
+    ap.add_argument("--nstlist", type=int, default=0,
+                    help="pair-list rebuild interval (vp_options.nstlist; 0: the library default)")
+    ap.add_argument("--skin", type=float, default=0.0,
+                    help="pair-list buffer in nm (vp_options.skin; 0: the library default)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="run every block with --force-shape instead of timing the tile shapes "
                          "per size bucket at creation")
@@ -93,8 +101,27 @@ def main():
     n_atoms = sum(int(d["n_atoms"]) for d in reps)
     print(f"# generated {len(reps)} replicas, {n_atoms} atoms in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
     torch.cuda.set_device(0)
+    if args.equilibrate > 0:
+        # thermalise every replica without bias, then start its trial from that state
+        te = time.time()
+        eq = vp.System([dict(d, bias=vp.BIAS_NONE) for d in reps], steps_per_graph=B,
+                       nstlist=args.nstlist, skin=args.skin)
+        for k in range(0, args.equilibrate, 1000):
+            eq.step_batch(min(1000, args.equilibrate - k))
+            torch.cuda.synchronize()
+            print(f"# equilibration: {k + min(1000, args.equilibrate - k)} steps "
+                  f"({time.time() - te:.1f} s)", file=sys.stderr, flush=True)
+        obs = eq.observables()
+        ke = obs[:, list(vp.OBS).index("ke")]
+        temp = [2.0 * ke[r] / (3.0 * int(d["n_atoms"]) * 0.0083144626) for r, d in enumerate(reps)]
+        xe, ve = (t.cpu().numpy().astype(np.float64) for t in eq.get_state())
+        reps = [dict(d, x0=xe[eq.offsets[r]:eq.offsets[r + 1]].copy(),
+                     v0=ve[eq.offsets[r]:eq.offsets[r + 1]].copy()) for r, d in enumerate(reps)]
+        del eq
+        print(f"# equilibrated: T = {np.mean(temp):.1f} K (min {np.min(temp):.1f}, max {np.max(temp):.1f})",
+              file=sys.stderr, flush=True)
     system = vp.System(reps, steps_per_graph=B, force_shape=args.force_shape,
-                       autotune=not args.no_autotune)
+                       autotune=not args.no_autotune, nstlist=args.nstlist, skin=args.skin)
     buckets, split = system.tile_buckets()
     for b in buckets:
         print(f"# bucket rc {b['r_cut']} 2^{b['log2_atoms']}: {b['replicas']} replicas, tile {b['tile']}, "
@@ -204,7 +231,8 @@ def main():
         "dtype": "f32 pair arithmetic, i64 fixed-point forces, f64 functional",
         "data": "synthetic",
         "config": {
-            "workload": workload,
+            "workload": workload + (f"; trials start at t = 0 from a {args.equilibrate}-step unbiased "
+                                    "equilibration of each replica" if args.equilibrate > 0 else ""),
             "replicas": len(reps),
             "atoms_per_replica": (int(base["n_atoms"]) if args.workload == "c3"
                                   else [int(d["n_atoms"]) for d in reps]),

@@ -108,10 +108,17 @@ typedef struct {
 
 typedef struct {
   int32_t nstlist;     /* pair lists are rebuilt when the step count n + 1 is a
-                          multiple of nstlist (the same steps in every replica)
-                          and whenever an atom has moved half the skin since
-                          its replica's last build (0: 4) */
-  double skin;         /* pair-list buffer in nm (0: 0.1) */
+                          multiple of nstlist and whenever an atom has moved
+                          half the skin since its replica's last build.
+                          0: per replica, the steps a fast atom (4 sigma of the
+                          lightest atom's Maxwell speed at kT) needs to move
+                          half the skin (10 for 12,560-atom water at 300 K,
+                          1 fs, skin 0.14 nm) */
+  double skin;         /* pair-list buffer in nm.  0: per replica, the largest
+                          of 0.14, 0.13, ... nm whose staged neighbourhood fits
+                          the force kernel's LDS and whose r_cut + skin stays
+                          below half the box (VP_OBS_SKIN and VP_OBS_NSTLIST
+                          report the values taken) */
   int32_t steps_per_graph; /* steps captured per hipGraph launch (0: 20) */
   int32_t use_graph;       /* 1: replay captured graphs; 0: launch every kernel */
   int32_t max_neighbors;   /* per-atom list capacity (0: derived from density) */
@@ -198,10 +205,11 @@ vp_status vp_get_state(vp_system *s, float *x_dev, float *v_dev, void *hip_strea
 /* Per-replica observables: obs_host HOST [n_reps][VP_OBS_COUNT] FP64.
  * Pair-list statistics since creation: largest staged neighbourhood of a
  * 64-atom block and its capacity, longest per-atom list and its capacity,
- * number of blocks built again in exact mode (staging capacity reached). */
+ * number of blocks built again in exact mode (staging capacity reached);
+ * the replica's pair-list buffer (nm) and rebuild interval. */
 enum { VP_OBS_STEP = 0, VP_OBS_Z, VP_OBS_ZREF, VP_OBS_ZMIN, VP_OBS_PHI, VP_OBS_STATUS,
        VP_OBS_REBUILDS, VP_OBS_KE, VP_OBS_STAGE_MAX, VP_OBS_STAGE_CAP, VP_OBS_LIST_MAX,
-       VP_OBS_LIST_CAP, VP_OBS_EXACT_BUILDS, VP_OBS_COUNT };
+       VP_OBS_LIST_CAP, VP_OBS_EXACT_BUILDS, VP_OBS_SKIN, VP_OBS_NSTLIST, VP_OBS_COUNT };
 vp_status vp_observables(vp_system *s, double *obs_host);
 
 /* Force-kernel timing.  While on != 0, vp_step_batch enqueues its steps by

@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <set>
 #include <tuple>
 #include <string>
 #include <vector>
@@ -183,8 +184,56 @@ static void free_all(vp_system *s) {
   s->allocations.clear();
 }
 
+// distinct (charge, sigma, epsilon) classes of a replica (its type-table size)
+static int count_types(const vp_replica_desc &d) {
+  std::set<std::tuple<double, double, double>> cls;
+  for (int i = 0; i < d.n_atoms; ++i) cls.emplace(d.charge[i], d.sigma[i], d.epsilon[i]);
+  return (int)cls.size();
+}
+
+// Staged neighbourhood a 64-atom block may need: atoms within rl of a compact
+// block (side ~0.93 (64/rho)^(1/3)), with a margin for the blocks that turn
+// from one column into the next (every atom within rl of a quarter's box is
+// staged).
+static int stage_estimate(double rl, double rho) {
+  const double a = 0.93 * std::cbrt(kBlk / rho);
+  const double vst = a * a * a + 6.0 * a * a * rl + 3.0 * M_PI * a * rl * rl + 4.0 / 3.0 * M_PI * rl * rl * rl;
+  return (int)std::ceil(1.5 * vst * rho + 128);
+}
+
+// Pair-list buffer and rebuild interval of one replica.  Given values are used
+// as they are.  By default the skin is the largest of 0.14, 0.13, ... nm whose
+// staged neighbourhood fits the force kernel's LDS and whose list radius stays
+// below half the box, and the interval is the number of steps a fast atom
+// (4 sigma of the Maxwell speed of the lightest atom) needs to cover half the
+// skin; a rebuild still happens earlier whenever an atom has moved that far.
+static void list_params(const vp_replica_desc &d, const vp_options &o, int ntypes_max, double *skin,
+                        int *nstlist) {
+  const double rho = d.n_atoms / (d.box[0] * d.box[1] * d.box[2]);
+  const double half = 0.5 * std::min({d.box[0], d.box[1], d.box[2]});
+  double sk = o.skin;
+  if (!(sk > 0)) {
+    const long long budget = (long long)kMaxLds / (long long)sizeof(int4) - (ntypes_max + 1) - 1;
+    sk = 0.14;
+    while (sk > 0.055 && (stage_estimate(d.r_cut + sk, rho) > std::min<long long>(budget, kMaxStage) ||
+                          !(d.r_cut + sk < half)))
+      sk -= 0.01;
+  }
+  *skin = sk;
+  if (o.nstlist > 0) {
+    *nstlist = o.nstlist;
+  } else {
+    double mmin = d.mass[0];
+    for (int i = 1; i < d.n_atoms; ++i) mmin = std::min(mmin, d.mass[i]);
+    const double vfast = 4.0 * std::sqrt(d.kT / mmin);  // nm/ps
+    *nstlist = std::max(1, std::min(50, (int)std::floor(0.49 * sk / (vfast * d.dt))));
+  }
+}
+
 static vp_status build(vp_system *s, const vp_replica_desc *reps, int32_t n_reps) {
   const vp_options &o = s->opt;
+  int ntypes_all = 0;
+  for (int r = 0; r < n_reps; ++r) ntypes_all = std::max(ntypes_all, count_types(reps[r]));
   s->R = n_reps;
   s->info_h.resize(n_reps);
   int64_t off = 0, uoff = 0, cell0 = 0, list_off = 0, sol_off = 0, cv_tiles = 0;
@@ -221,7 +270,10 @@ static vp_status build(vp_system *s, const vp_replica_desc *reps, int32_t n_reps
     }
     R.bias = d.bias;
     R.min_sep = d.contact_min_sep;
-    const double rl = d.r_cut + o.skin;
+    double skin = 0.0;
+    int nstlist = 1;
+    list_params(d, o, ntypes_all, &skin, &nstlist);
+    const double rl = d.r_cut + skin;
     if (!(rl < 0.5 * std::min({d.box[0], d.box[1], d.box[2]})))
       return fail(VP_ERR_ARG, "replica " + std::to_string(r) + ": r_cut + skin must be below half the box");
     for (int a = 0; a < 3; ++a) {
@@ -246,18 +298,13 @@ static vp_status build(vp_system *s, const vp_replica_desc *reps, int32_t n_reps
     maxnb = std::min(maxnb, d.n_atoms + 8);
     maxnb = (maxnb + 7) / 8 * 8 + 8;
     R.maxnb = maxnb;
-    // staging estimate: atoms within rl of a compact 64-atom block (side
-    // ~0.93 (64/rho)^(1/3)), with a margin for the blocks that turn from one
-    // column into the next (every atom within rl of a quarter's box is staged)
-    const double a = 0.93 * std::cbrt(kBlk / rho);
-    const double vst = a * a * a + 6.0 * a * a * rl + 3.0 * M_PI * a * rl * rl + 4.0 / 3.0 * M_PI * rl * rl * rl;
-    int cap = (int)std::ceil(1.5 * vst * rho + 128);
-    cap = std::min(kMaxStage, std::min(cap, d.n_atoms * 27 + 8));
+    int cap = std::min(kMaxStage, std::min(stage_estimate(rl, rho), d.n_atoms * 27 + 8));
     R.stage_cap = cap;
     stage_cap_max = std::max(stage_cap_max, cap);
     R.list_off = list_off;
     R.sol_off = (int32_t)sol_off;
-    R.nstlist = o.nstlist;
+    R.nstlist = nstlist;
+    R.skin = skin;
     const double rcq = d.r_cut * kQ, rlq = rl * kQ;
     R.rc2q = (float)(rcq * rcq);
     R.rl2q = (float)(rlq * rlq);
@@ -266,7 +313,7 @@ static vp_status build(vp_system *s, const vp_replica_desc *reps, int32_t n_reps
     R.krf = (d.eps_rf - 1.0) / ((2.0 * d.eps_rf + 1.0) * d.r_cut * d.r_cut * d.r_cut);
     R.crf = 1.0 / d.r_cut + R.krf * d.r_cut * d.r_cut;
     R.krf2q = (float)(2.0 * R.krf / (kQ * kQ * kQ));
-    R.half_skin_margin = (float)(0.5 * o.skin * 0.98);
+    R.half_skin_margin = (float)(0.5 * skin * 0.98);
     R.cr0 = (float)d.contact_r0;
     R.crs = (float)d.contact_rs;
     R.crc = (float)d.contact_rc;
@@ -663,8 +710,6 @@ extern "C" vp_status vp_system_create(const vp_replica_desc *reps, int32_t n_rep
   if (!s) return fail(VP_ERR_NOMEM, "host allocation failed");
   vp_options o{};
   if (opt) o = *opt;
-  if (o.nstlist <= 0) o.nstlist = 4;
-  if (!(o.skin > 0)) o.skin = 0.1;
   if (o.steps_per_graph <= 0) o.steps_per_graph = 20;
   if (!opt) o.use_graph = 1;
   s->opt = o;
@@ -959,6 +1004,8 @@ extern "C" vp_status vp_observables(vp_system *s, double *obs) {
     o[VP_OBS_LIST_MAX] = st[r].list_max;
     o[VP_OBS_LIST_CAP] = R.maxnb;
     o[VP_OBS_EXACT_BUILDS] = st[r].exact_builds;
+    o[VP_OBS_SKIN] = R.skin;
+    o[VP_OBS_NSTLIST] = R.nstlist;
   }
   return VP_OK;
 }

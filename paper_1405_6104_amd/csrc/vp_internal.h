@@ -68,6 +68,7 @@ struct RepInfo {
   float rc2q, rl2q;             // (rc/q)^2 and (rl/q)^2 in FP32
   float krf2q;                  // 2 k_rf q^3 (RF term in coordinate units)
   float half_skin_margin;       // displacement (nm) that forces a rebuild
+  double skin;                  // pair-list buffer (nm)
   float cr0, crs, crc;          // contact r0, switch start, switch end (nm)
   int32_t rlq;                  // list radius in coordinate units
   double Ld[3];

@@ -26,7 +26,7 @@ _ip = C.POINTER(C.c_int32)
 
 BIAS_NONE, BIAS_CONST, BIAS_RG, BIAS_CONTACT, BIAS_RMD_CONTACT = 0, 1, 2, 3, 4
 OBS = ("step", "z", "z_ref", "z_min", "phi", "status", "rebuilds", "ke", "stage_max", "stage_cap",
-       "list_max", "list_cap", "exact_builds")
+       "list_max", "list_cap", "exact_builds", "skin", "nstlist")
 ENERGY_COLUMNS = ("lj", "rf", "bond", "angle", "bias", "z", "z_ref", "S")
 REPLICA_UNSTABLE, REPLICA_LIST_OVERFLOW = 1, 2
 
