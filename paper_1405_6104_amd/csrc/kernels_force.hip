@@ -26,6 +26,35 @@
 
 namespace vp {
 
+// Copies a block's staged neighbourhood into LDS: entry s (slot | 3 x 5-bit
+// image shift) becomes that atom's position shifted by the image, with its
+// type.  Each thread keeps kStageBatch entries in flight (their codes, then
+// their positions) so that the gathers cost two memory latencies per batch
+// rather than two per entry.
+constexpr int kStageBatch = 8;
+template <int NT>
+__device__ __forceinline__ void stage_neighbourhood(const uint32_t *__restrict__ stg, int nst,
+                                                    const int4 *__restrict__ xr, int Lx, int Ly, int Lz,
+                                                    int tid, int4 *__restrict__ st) {
+  for (int s0 = 0; s0 < nst; s0 += NT * kStageBatch) {
+    // loads past the end read the last entry again (no branch between the
+    // loads, so they stay in flight together); only the stores are guarded
+    uint32_t e[kStageBatch];
+#pragma unroll
+    for (int k = 0; k < kStageBatch; ++k) e[k] = stg[min(s0 + k * NT + tid, nst - 1)];
+    int4 xj[kStageBatch];
+#pragma unroll
+    for (int k = 0; k < kStageBatch; ++k) xj[k] = xr[e[k] & 0xffffu];
+#pragma unroll
+    for (int k = 0; k < kStageBatch; ++k) {
+      const int s = s0 + k * NT + tid;
+      const int sx = (int)((e[k] >> 16) & 31) - 16, sy = (int)((e[k] >> 21) & 31) - 16,
+                sz = (int)((e[k] >> 26) & 31) - 16;
+      if (s < nst) st[s] = make_int4(xj[k].x + sx * Lx, xj[k].y + sy * Ly, xj[k].z + sz * Lz, xj[k].w);
+    }
+  }
+}
+
 // One list chunk (8 entries of one atom's list) evaluated against the staged
 // neighbourhood: LJ + reaction-field forces accumulated in the chunk's order
 // into (fx, fy, fz), energies into (elj, erf) when ENERGY.  UNROLL entries
@@ -129,17 +158,8 @@ __global__ __launch_bounds__(64 * PARTS) __attribute__((amdgpu_waves_per_eu(MINW
   }
   const int Lx = R.Lq[0], Ly = R.Lq[1], Lz = R.Lq[2];
   // ---- stage the neighbourhood and the type table
-  const int nst = W.stage_n[b];
-  const uint32_t *stg = W.stage + (int64_t)b * W.stage_stride;
-  const int4 *xr = W.xq + R.off;
-  for (int s = tid; s < nst; s += NT) {
-    const uint32_t e = stg[s];
-    const int j = (int)(e & 0xffffu);
-    const int sx = (int)((e >> 16) & 31) - 16, sy = (int)((e >> 21) & 31) - 16,
-              sz = (int)((e >> 26) & 31) - 16;
-    const int4 xj = xr[j];
-    st[s] = make_int4(xj.x + sx * Lx, xj.y + sy * Ly, xj.z + sz * Lz, xj.w);
-  }
+  stage_neighbourhood<NT>(W.stage + (int64_t)b * W.stage_stride, W.stage_n[b], W.xq + R.off, Lx, Ly, Lz,
+                          tid, st);
   if (tid == 0) st[R.stage_cap] = make_int4(kDummyCoord, kDummyCoord, kDummyCoord, R.ntypes);
   for (int t = tid; t <= R.ntypes; t += NT) tab[t] = types[R.type_off + t];
   __syncthreads();
@@ -331,14 +351,16 @@ __global__ __launch_bounds__(kForceThreads) void k_tangent_forces(
   const int nst = W.stage_n[b];
   const uint32_t *stg = W.stage + (int64_t)b * W.stage_stride;
   const int4 *xr = W.xq + R.off;
-  for (int q = tid; q < nst; q += kForceThreads) {
-    const uint32_t e = stg[q];
-    const int j = (int)(e & 0xffffu);
-    const int sx = (int)((e >> 16) & 31) - 16, sy = (int)((e >> 21) & 31) - 16,
-              sz = (int)((e >> 26) & 31) - 16;
-    const int4 xj = xr[j];
-    st[q] = make_int4(xj.x + sx * Lx, xj.y + sy * Ly, xj.z + sz * Lz, xj.w);
-    sxi[q] = txp[R.off + j];
+  stage_neighbourhood<kForceThreads>(stg, nst, xr, Lx, Ly, Lz, tid, st);
+  for (int q0 = 0; q0 < nst; q0 += kForceThreads * kStageBatch) {
+    // the staged atoms' tangents, kStageBatch loads in flight per thread
+    float4 t[kStageBatch];
+#pragma unroll
+    for (int k = 0; k < kStageBatch; ++k)
+      t[k] = txp[R.off + (stg[min(q0 + k * kForceThreads + tid, nst - 1)] & 0xffffu)];
+#pragma unroll
+    for (int k = 0; k < kStageBatch; ++k)
+      if (q0 + k * kForceThreads + tid < nst) sxi[q0 + k * kForceThreads + tid] = t[k];
   }
   if (tid == 0) {
     st[R.stage_cap] = make_int4(kDummyCoord, kDummyCoord, kDummyCoord, R.ntypes);
