@@ -110,15 +110,19 @@ typedef struct {
   int32_t nstlist;     /* pair lists are rebuilt when the step count n + 1 is a
                           multiple of nstlist and whenever an atom has moved
                           half the skin since its replica's last build.
-                          0: per replica, the steps a fast atom (4 sigma of the
-                          lightest atom's Maxwell speed at kT) needs to move
-                          half the skin (10 for 12,560-atom water at 300 K,
-                          1 fs, skin 0.14 nm) */
-  double skin;         /* pair-list buffer in nm.  0: per replica, the largest
-                          of 0.14, 0.13, ... nm whose staged neighbourhood fits
-                          the force kernel's LDS and whose r_cut + skin stays
-                          below half the box (VP_OBS_SKIN and VP_OBS_NSTLIST
-                          report the values taken) */
+                          0: per replica, the largest power of two (<= 32) in
+                          which a fast atom (5 sigma of the lightest atom's
+                          Maxwell speed at kT) moves less than half of the
+                          largest admissible skin (8 for 12,560-atom water at
+                          300 K and 1 fs); powers of two keep the rebuild steps
+                          of different replicas aligned */
+  double skin;         /* pair-list buffer in nm.  0: per replica, just large
+                          enough for the interval (rounded up to 0.01 nm; 0.13
+                          in the case above) and at most the largest of 0.14,
+                          0.13, ... nm whose staged neighbourhood fits the
+                          force kernel's LDS and whose r_cut + skin stays below
+                          half the box (VP_OBS_SKIN and VP_OBS_NSTLIST report
+                          the values taken) */
   int32_t steps_per_graph; /* steps captured per hipGraph launch (0: 20) */
   int32_t use_graph;       /* 1: replay captured graphs; 0: launch every kernel */
   int32_t max_neighbors;   /* per-atom list capacity (0: derived from density) */

@@ -202,31 +202,45 @@ static int stage_estimate(double rl, double rho) {
 }
 
 // Pair-list buffer and rebuild interval of one replica.  Given values are used
-// as they are.  By default the skin is the largest of 0.14, 0.13, ... nm whose
-// staged neighbourhood fits the force kernel's LDS and whose list radius stays
-// below half the box, and the interval is the number of steps a fast atom
-// (4 sigma of the Maxwell speed of the lightest atom) needs to cover half the
-// skin; a rebuild still happens earlier whenever an atom has moved that far.
+// as they are.  By default:
+//  - the skin may be at most the largest of 0.14, 0.13, ... nm whose staged
+//    neighbourhood fits the force kernel's LDS and whose list radius stays
+//    below half the box;
+//  - the interval is the largest power of two (up to 32) in which a fast atom
+//    (5 sigma of the Maxwell speed of the lightest atom, the onset of the
+//    displacement rebuilds measured in water at 300 K) moves less than half of
+//    that maximal skin, and the skin is then just large enough for that
+//    interval (rounded up to 0.01 nm).
+// Powers of two keep the rebuild steps of replicas with different intervals
+// aligned (every rebuild step of a replica with interval 2k is one of a
+// replica with interval k), so rebuilds share launches; a rebuild still
+// happens earlier whenever an atom has moved half the skin.
 static void list_params(const vp_replica_desc &d, const vp_options &o, int ntypes_max, double *skin,
                         int *nstlist) {
   const double rho = d.n_atoms / (d.box[0] * d.box[1] * d.box[2]);
   const double half = 0.5 * std::min({d.box[0], d.box[1], d.box[2]});
-  double sk = o.skin;
-  if (!(sk > 0)) {
+  double cap = o.skin;
+  if (!(cap > 0)) {
     const long long budget = (long long)kMaxLds / (long long)sizeof(int4) - (ntypes_max + 1) - 1;
-    sk = 0.14;
-    while (sk > 0.055 && (stage_estimate(d.r_cut + sk, rho) > std::min<long long>(budget, kMaxStage) ||
-                          !(d.r_cut + sk < half)))
-      sk -= 0.01;
+    cap = 0.14;
+    while (cap > 0.025 && (stage_estimate(d.r_cut + cap, rho) > std::min<long long>(budget, kMaxStage) ||
+                           !(d.r_cut + cap < half)))
+      cap -= 0.01;
   }
-  *skin = sk;
-  if (o.nstlist > 0) {
-    *nstlist = o.nstlist;
+  double mmin = d.mass[0];
+  for (int i = 1; i < d.n_atoms; ++i) mmin = std::min(mmin, d.mass[i]);
+  const double step_disp = 5.0 * std::sqrt(d.kT / mmin) * d.dt;  // nm per step of a fast atom
+  int nst = o.nstlist;
+  if (nst <= 0) {
+    nst = 1;
+    while (nst < 32 && 2 * nst * step_disp <= 0.49 * cap) nst *= 2;
+  }
+  *nstlist = nst;
+  if (o.skin > 0) {
+    *skin = o.skin;
   } else {
-    double mmin = d.mass[0];
-    for (int i = 1; i < d.n_atoms; ++i) mmin = std::min(mmin, d.mass[i]);
-    const double vfast = 4.0 * std::sqrt(d.kT / mmin);  // nm/ps
-    *nstlist = std::max(1, std::min(50, (int)std::floor(0.49 * sk / (vfast * d.dt))));
+    const double need = std::ceil(nst * step_disp / 0.49 * 100.0 - 1e-9) / 100.0;
+    *skin = std::max(0.02, std::min(cap, need));
   }
 }
 

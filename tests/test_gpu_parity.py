@@ -553,21 +553,24 @@ def test_autotuned_uneven_batch(c4_subset):
 
 
 def test_default_list_parameters_per_replica(c4_subset):
-    """Default skin: 0.14 nm unless the staged neighbourhood or half the box
-    limits it; default interval: steps for a 4-sigma-fast lightest atom to move
-    half the skin.  Given values are taken as they are."""
+    """Default interval: the largest power of two in which a 5-sigma-fast
+    lightest atom moves less than half the largest admissible skin (at most
+    0.14 nm, less where the staged neighbourhood or half the box limits it);
+    default skin: just enough for that interval.  Given values are taken as
+    they are."""
     say("list parameters per replica")
     reps = [synth.c2_single(), synth.c1_small(), synth.tiny(seed=3)] + list(c4_subset)
     obs = vp.System(reps).observables()
     col = {k: i for i, k in enumerate(vp.OBS)}
     for r, d in enumerate(reps):
         skin, nst = obs[r, col["skin"]], int(obs[r, col["nstlist"]])
-        mmin = float(np.min(d["mass"]))
-        want = max(1, min(50, int(np.floor(0.49 * skin / (4.0 * np.sqrt(d["kT"] / mmin) * d["dt"])))))
+        step = 5.0 * np.sqrt(d["kT"] / float(np.min(d["mass"]))) * d["dt"]
         say(f"  replica {r}: {d['n_atoms']} atoms rc {d['r_cut']} dt {d['dt']}: skin {skin:.2f} nstlist {nst}")
-        assert 0.05 < skin <= 0.14 + 1e-12 and d["r_cut"] + skin < 0.5 * min(d["box"])
-        assert nst == want
+        assert nst in (1, 2, 4, 8, 16, 32)
+        assert 0.02 <= skin <= 0.14 + 1e-12 and d["r_cut"] + skin < 0.5 * min(d["box"])
+        assert nst * step <= 0.49 * skin + 1e-12            # the interval fits the skin
         assert obs[r, col["stage_max"]] <= obs[r, col["stage_cap"]]
-    assert abs(obs[0, col["skin"]] - 0.14) < 1e-12 and int(obs[0, col["nstlist"]]) == 10
+    assert abs(obs[0, col["skin"]] - 0.13) < 1e-12 and int(obs[0, col["nstlist"]]) == 8
+    assert int(obs[1, col["nstlist"]]) == 16            # C1 at 0.5 fs
     given = vp.System(reps[:1], nstlist=4, skin=0.1).observables()
     assert abs(given[0, col["skin"]] - 0.1) < 1e-12 and int(given[0, col["nstlist"]]) == 4
