@@ -287,12 +287,22 @@ __device__ __forceinline__ int quarter_max_i(int v) {
   return v;
 }
 
-// A lane's list entries are collected four at a time in a 64-bit shift
-// register and stored as one 8-byte write into the [chunk][lane][8] layout
-// (the order of the four entries inside a group is reversed, which only
-// changes the fixed order in which the force kernel visits them).
-__device__ __forceinline__ void list_store4(uint16_t *lst, int e0, int lane, uint64_t v) {
-  *reinterpret_cast<uint64_t *>(lst + ((size_t)(e0 >> 3) * kBlk + lane) * 8 + (e0 & 4)) = v;
+// A lane's list entries are collected eight at a time in a 128-bit shift
+// register (lo: the four newest, hi: the four before) and stored as one
+// 16-byte write, a whole row of the [chunk][lane][8] layout, so a wave writes
+// 1 KB of contiguous list per store (the order of the eight entries inside a
+// chunk is reversed, which only changes the fixed order in which the force
+// kernel visits them).
+struct Pending {
+  uint64_t lo, hi;
+};
+__device__ __forceinline__ void list_push(Pending &p, uint32_t e) {
+  p.hi = (p.hi << 16) | (p.lo >> 48);
+  p.lo = (p.lo << 16) | (uint64_t)e;
+}
+__device__ __forceinline__ void list_store8(uint16_t *lst, int e0, int lane, const Pending &p) {
+  *reinterpret_cast<uint4 *>(lst + ((size_t)(e0 >> 3) * kBlk + lane) * 8) =
+      make_uint4((uint32_t)p.lo, (uint32_t)(p.lo >> 32), (uint32_t)p.hi, (uint32_t)(p.hi >> 32));
 }
 
 // One wave per block of 64 sorted atoms.  The cells that can hold a neighbour
@@ -429,7 +439,7 @@ __global__ __launch_bounds__(kBlk) void k_list(const RepInfo *__restrict__ info,
   const int cap = R.stage_cap, maxnb = R.maxnb;
   const int *cstart = W.cell_start + R.cell0;
   int nst = 0, cnt = 0;
-  uint64_t pend = 0ull;  // pending list entries (up to four)
+  Pending pend{0ull, 0ull};  // pending list entries (up to eight)
   bool bad = false;
   __syncthreads();  // cell edges in LDS
   // Fast mode stages every candidate kept by the quarter boxes.  If that
@@ -441,7 +451,7 @@ __global__ __launch_bounds__(kBlk) void k_list(const RepInfo *__restrict__ info,
     exact = mode == 1;
     nst = 0;
     cnt = 0;
-    pend = 0ull;
+    pend = Pending{0ull, 0ull};
     bool full = false;
     int iz = uz0 >= 0 ? uz0 / ncz : -((-uz0 + ncz - 1) / ncz);
     int cz = uz0 - iz * ncz;
@@ -530,9 +540,9 @@ __global__ __launch_bounds__(kBlk) void k_list(const RepInfo *__restrict__ info,
                     const int d = __float_as_int(c.w) - a32;
                     const bool exw = (unsigned)d < 64u && ((exm >> (d & 63)) & 1ull);
                     if (qr2(dx, dy, dz) < rl2x && !exw) {
-                      pend = (pend << 16) | (uint64_t)(uint32_t)(nst + k);
+                      list_push(pend, (uint32_t)(nst + k));
                       ++cnt;  // entries past maxnb are counted only to flag the overflow
-                      if ((cnt & 3) == 0 && cnt <= maxnb) list_store4(lst, cnt - 4, lane, pend);
+                      if ((cnt & 7) == 0 && cnt <= maxnb) list_store8(lst, cnt - 8, lane, pend);
                     }
                   }
                 } else {
@@ -546,9 +556,9 @@ __global__ __launch_bounds__(kBlk) void k_list(const RepInfo *__restrict__ info,
                     if (in && !win && exfar)
                       for (int e = e0; e < e1; ++e) in = in && (ex_list[e] != oj);
                     if (in) {
-                      pend = (pend << 16) | (uint64_t)(uint32_t)(nst + k);
+                      list_push(pend, (uint32_t)(nst + k));
                       ++cnt;
-                      if ((cnt & 3) == 0 && cnt <= maxnb) list_store4(lst, cnt - 4, lane, pend);
+                      if ((cnt & 7) == 0 && cnt <= maxnb) list_store8(lst, cnt - 8, lane, pend);
                     }
                   }
                 }
@@ -569,9 +579,9 @@ __global__ __launch_bounds__(kBlk) void k_list(const RepInfo *__restrict__ info,
                   if (__ballot(in)) {
                     if (nst < cap) {
                       if (in) {
-                        pend = (pend << 16) | (uint64_t)(uint32_t)nst;
+                        list_push(pend, (uint32_t)nst);
                         ++cnt;
-                        if ((cnt & 3) == 0 && cnt <= maxnb) list_store4(lst, cnt - 4, lane, pend);
+                        if ((cnt & 7) == 0 && cnt <= maxnb) list_store8(lst, cnt - 8, lane, pend);
                       }
                       acc |= 1ull << k;
                       ++nst;
@@ -600,9 +610,9 @@ __global__ __launch_bounds__(kBlk) void k_list(const RepInfo *__restrict__ info,
   } else if (active) {
     // pad to a multiple of 8 with the inert staging entry (index cap)
     while (cnt & 7) {
-      pend = (pend << 16) | (uint64_t)cap;
+      list_push(pend, (uint32_t)cap);
       ++cnt;
-      if ((cnt & 3) == 0) list_store4(lst, cnt - 4, lane, pend);
+      if ((cnt & 7) == 0) list_store8(lst, cnt - 8, lane, pend);
     }
   }
   W.nbcnt[slot] = active ? cnt : 0;
