@@ -38,6 +38,23 @@ PEAK_FP32_TFLOPS = 157.3    # MI355X FP32 vector peak
 FORCE_TRAFFIC_BYTES = (651722 * 2.000 + 19200 * 1.000) * 1024
 
 
+def _oracle_rate(job):
+    """Run the oracle on one replica for about `seconds`: (atom-steps, seconds, steps)."""
+    desc, seconds = job
+    import numpy as np
+    from oracle import oracle as O  # CPU baseline leg only
+    o = O.Oracle(desc)
+    x = np.array(desc["x0"], dtype=np.float64)
+    v = o.maxwell()
+    st = o.init(x)
+    n = 0
+    t = time.perf_counter()
+    while time.perf_counter() - t < seconds:
+        o.run(x, v, st, 1)
+        n += 1
+    return int(desc["n_atoms"]) * n, time.perf_counter() - t, n
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -49,10 +66,14 @@ def main():
     ap.add_argument("--timing-steps", type=int, default=5, help="blocks timed with HIP events")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--workload", choices=("c3", "c4"), default="c3",
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+                    help="seconds of oracle work per process for the CPU baseline")
+    ap.add_argument("--cpu-procs", type=int, default=0,
+                    help="oracle processes for the CPU baseline (0: one per core, at most 16)")
+    ap.add_argument("--workload", choices=("c3", "c4", "c5"), default="c3",
                     help="c3: 64 replicas of the 12,560-atom system; c4: 32 replicas of "
-                         "5,000-40,000 atoms with cutoffs 0.9 / 1.2 nm")
+                         "5,000-40,000 atoms with cutoffs 0.9 / 1.2 nm; c5: 16 replicas of the "
+                         "12,560-atom system carrying dPhi/d(bias_k, ramp_rate)")
     ap.add_argument("--equilibrate", type=int, default=6000, metavar="MD_STEPS",
                     help="untimed MD steps without bias before the trials start: the synthetic "
                          "start relaxes from ~800 K to 300 K, and the trials then begin at t = 0 "
@@ -89,6 +110,11 @@ def main():
                               n_steps=B * (args.steps + args.warmup + args.timing_steps))
         workload = ("64 trial paths x 12,560 atoms (560-atom solute + 4,000 flexible waters), "
                     "5.0 nm box, rc 1.0 nm, dt 1 fs, contact-map bias, graph-captured batch")
+    elif args.workload == "c5":
+        base = synth.c2_single()
+        reps = synth.c5_adjoint(16, base=base)
+        workload = ("16 trial paths x 12,560 atoms with forward tangents of dPhi/d(bias_k, ramp_rate), "
+                    "2,000-step bias ramp, rc 1.0 nm, dt 1 fs, contact-map bias, graph-captured batch")
     else:
         # replicas are independent: built by forked workers before the GPU is touched
         workers = max(1, min(16, os.cpu_count() or 1))
@@ -100,6 +126,25 @@ def main():
                     "graph-captured batch")
     n_atoms = sum(int(d["n_atoms"]) for d in reps)
     print(f"# generated {len(reps)} replicas, {n_atoms} atoms in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
+    cpu = None
+    if not args.no_cpu_baseline:
+        # the oracle on the host's cores: one single-threaded oracle process per
+        # core, each on its own replica of the batch, forked before the GPU is used
+        import multiprocessing as mp
+        procs = args.cpu_procs if args.cpu_procs > 0 else max(1, min(16, os.cpu_count() or 1))
+        tc = time.time()
+        with mp.get_context("fork").Pool(procs) as pool:
+            res = pool.map(_oracle_rate, [(reps[k % len(reps)], args.cpu_seconds) for k in range(procs)])
+        steps_cpu = sum(n for _, _, n in res)
+        sizes = sorted({int(reps[k % len(reps)]["n_atoms"]) for k in range(procs)})
+        cpu = {"value": sum(a / t for a, t, _ in res), "unit": "atom-steps/s", "cores": procs,
+               "kind": "oracle",
+               "sample": f"{procs} processes in parallel, each the single-threaded FP64 oracle (cell-list "
+                         f"pairs) on its own replica of the batch ({', '.join(f'{n:,}' for n in sizes)} "
+                         f"atoms) for ~{args.cpu_seconds:.0f} s; {steps_cpu} BAOAB steps in all; one "
+                         f"process alone: {res[0][0] / res[0][1]:.3e} atom-steps/s"}
+        print(f"# cpu oracle: {cpu['value']:.4e} atom-steps/s on {procs} cores ({time.time() - tc:.1f} s)",
+              file=sys.stderr, flush=True)
     torch.cuda.set_device(0)
     if args.equilibrate > 0:
         # thermalise every replica without bias, then start its trial from that state
@@ -120,8 +165,10 @@ def main():
         del eq
         print(f"# equilibrated: T = {np.mean(temp):.1f} K (min {np.min(temp):.1f}, max {np.max(temp):.1f})",
               file=sys.stderr, flush=True)
+    tangent = args.workload == "c5"
     system = vp.System(reps, steps_per_graph=B, force_shape=args.force_shape,
-                       autotune=not args.no_autotune, nstlist=args.nstlist, skin=args.skin)
+                       autotune=not args.no_autotune, nstlist=args.nstlist, skin=args.skin,
+                       tangent=tangent)
     buckets, split = system.tile_buckets()
     for b in buckets:
         print(f"# bucket rc {b['r_cut']} 2^{b['log2_atoms']}: {b['replicas']} replicas, tile {b['tile']}, "
@@ -130,12 +177,12 @@ def main():
 
     for _ in range(args.warmup):
         system.step_batch(B)
-        system.functional()
+        system.functional(gradient=tangent)
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     for _ in range(args.steps):
         system.step_batch(B)
-        system.functional()
+        system.functional(gradient=tangent)
         system.select_path()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
@@ -184,7 +231,7 @@ def main():
 
     plain = None
     if not args.no_plain:
-        ps = vp.System([dict(reps[0])], use_graph=False, steps_per_graph=1)
+        ps = vp.System([dict(reps[0])], use_graph=False, steps_per_graph=1, tangent=tangent)
         for _ in range(20):
             ps.step_batch(1)
         torch.cuda.synchronize()
@@ -197,25 +244,6 @@ def main():
         print(f"# plain: {plain:.4e} atom-steps/s ({1e3 * tp / args.plain_steps:.3f} ms/step)",
               file=sys.stderr, flush=True)
         del ps
-
-    cpu = None
-    if not args.no_cpu_baseline:
-        from oracle import oracle as O  # CPU baseline leg only
-        o = O.Oracle(base)  # the first replica of the batch
-        x = np.array(base["x0"], dtype=np.float64)
-        v = o.maxwell()
-        st = o.init(x)
-        n_cpu = 0
-        tc = time.perf_counter()
-        while time.perf_counter() - tc < args.cpu_seconds:
-            o.run(x, v, st, 1)
-            n_cpu += 1
-        tc = time.perf_counter() - tc
-        cpu = {"value": int(base["n_atoms"]) * n_cpu / tc, "unit": "atom-steps/s", "cores": 1,
-               "kind": "oracle",
-               "sample": f"{n_cpu} BAOAB steps of one {int(base['n_atoms']):,}-atom replica (FP64, "
-                         f"single thread, cell-list pairs), {tc:.1f} s"}
-        print(f"# cpu oracle: {cpu['value']:.4e} atom-steps/s over {n_cpu} steps", file=sys.stderr, flush=True)
 
     out = {
         "metric": "atom-steps/sec (ns/day) for batched biased Langevin MD vs plain form; % VALU peak",
@@ -234,7 +262,7 @@ def main():
             "workload": workload + (f"; trials start at t = 0 from a {args.equilibrate}-step unbiased "
                                     "equilibration of each replica" if args.equilibrate > 0 else ""),
             "replicas": len(reps),
-            "atoms_per_replica": (int(base["n_atoms"]) if args.workload == "c3"
+            "atoms_per_replica": (int(base["n_atoms"]) if args.workload != "c4"
                                   else [int(d["n_atoms"]) for d in reps]),
             "md_steps_per_bench_step": B, "global_batch": n_atoms, "parallelism": "replicas",
         },
