@@ -129,7 +129,7 @@ typedef struct {
   int32_t tangent;         /* 1: also propagate dPhi/d(bias_k, ramp_rate) (vp_functional);
                               harmonic and constant biases only */
   int32_t force_shape;     /* tile shape of the force kernel (waves per 64-atom block x list
-                              entries per batch): 0: 8x8 (default), 1: 16x4, 2: 16x8, 3: 4x8 */
+                              entries per batch): 0: 8x8 (default), 1: 16x4, 2: 8x4, 3: 4x8 */
   int32_t autotune;        /* 1: time every tile shape on each size bucket at creation and
                               launch each bucket with its fastest (force_shape is ignored);
                               the forces are bitwise the same for every shape */
@@ -245,6 +245,12 @@ vp_status vp_sizes(const vp_system *s, int64_t *n_atoms_total, int32_t *n_reps);
  * shape and 0 when one shape over every block timed faster. */
 vp_status vp_tile_buckets(vp_system *s, vp_tile_bucket *out, int32_t cap, int32_t *n_buckets,
                           int32_t *split);
+
+/* Diagnostic (tests of the launch plan): runs the force kernel of size bucket
+ * i (in vp_tile_buckets order) with tile shape shapes[i] (HOST, n = number of
+ * buckets), as one launch per shape over its buckets' blocks, whatever the
+ * shapes.  Synchronises; captured step graphs are rebuilt on the next call. */
+vp_status vp_debug_set_tiles(vp_system *s, const int32_t *shapes, int32_t n);
 
 /* Diagnostic (derivative checks): the directional derivatives of the total
  * force of vp_forces along two displacements of the positions, parameters

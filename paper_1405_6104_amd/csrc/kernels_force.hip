@@ -1028,7 +1028,7 @@ size_t force_lds_bytes(const vp_system *s) {
 }
 
 // the tile shapes the force kernel is built for: (waves per block, entries per batch)
-const ForceShape kForceShapes[kNumForceShapes] = {{8, 8}, {16, 4}, {16, 8}, {4, 8}};
+const ForceShape kForceShapes[kNumForceShapes] = {{8, 8}, {16, 4}, {8, 4}, {4, 8}};
 
 template <bool E, int P, int U, int M>
 static hipError_t set_lds(int lds) {
@@ -1041,7 +1041,7 @@ hipError_t prepare_forces(const vp_system *s) {
   hipError_t e = hipSuccess;
   for (hipError_t x : {set_lds<false, 8, 8, 1>(lds), set_lds<true, 8, 8, 1>(lds),
                        set_lds<false, 16, 4, 1>(lds), set_lds<true, 16, 4, 1>(lds),
-                       set_lds<false, 16, 8, 1>(lds), set_lds<true, 16, 8, 1>(lds),
+                       set_lds<false, 8, 4, 1>(lds), set_lds<true, 8, 4, 1>(lds),
                        set_lds<false, 4, 8, 1>(lds), set_lds<true, 4, 8, 1>(lds)})
     if (x != hipSuccess) e = x;
   return e;
@@ -1068,8 +1068,8 @@ void launch_forces_shape(vp_system *s, Work &W, bool energy, int shape, const in
     case 1: launch_forces_t<true, 8, 8, 1>(s, W, blist, nblk, st); break;
     case 2: launch_forces_t<false, 16, 4, 1>(s, W, blist, nblk, st); break;
     case 3: launch_forces_t<true, 16, 4, 1>(s, W, blist, nblk, st); break;
-    case 4: launch_forces_t<false, 16, 8, 1>(s, W, blist, nblk, st); break;
-    case 5: launch_forces_t<true, 16, 8, 1>(s, W, blist, nblk, st); break;
+    case 4: launch_forces_t<false, 8, 4, 1>(s, W, blist, nblk, st); break;
+    case 5: launch_forces_t<true, 8, 4, 1>(s, W, blist, nblk, st); break;
     case 6: launch_forces_t<false, 4, 8, 1>(s, W, blist, nblk, st); break;
     default: launch_forces_t<true, 4, 8, 1>(s, W, blist, nblk, st); break;
   }

@@ -626,6 +626,22 @@ static vp_status time_plan(vp_system *s, const std::vector<vp_system::ForceLaunc
   return VP_OK;
 }
 
+// One force launch per shape that some bucket uses, over those buckets' blocks.
+static vp_status split_plan(vp_system *s, std::vector<vp_system::ForceLaunch> &plan) {
+  plan.clear();
+  for (int k = 0; k < kNumForceShapes; ++k) {
+    std::vector<int32_t> blocks;
+    for (const auto &b : s->buckets)
+      if (b.shape == k) blocks.insert(blocks.end(), b.blocks.begin(), b.blocks.end());
+    if (blocks.empty()) continue;
+    std::sort(blocks.begin(), blocks.end());
+    int32_t *p = nullptr;
+    TRY(upload(s, &p, blocks));
+    plan.push_back({k, p, (int)blocks.size()});
+  }
+  return VP_OK;
+}
+
 // Times every shape on every bucket's blocks, groups the buckets by their
 // fastest shape into one launch per shape, and keeps that split plan only if it
 // beats the fastest single shape over all blocks.  The forces do not depend on
@@ -646,16 +662,7 @@ static vp_status autotune(vp_system *s) {
     b.shape = best;
   }
   std::vector<vp_system::ForceLaunch> split;
-  for (int k = 0; k < kNumForceShapes; ++k) {
-    std::vector<int32_t> blocks;
-    for (const auto &b : s->buckets)
-      if (b.shape == k) blocks.insert(blocks.end(), b.blocks.begin(), b.blocks.end());
-    if (blocks.empty()) continue;
-    std::sort(blocks.begin(), blocks.end());
-    int32_t *p = nullptr;
-    TRY(upload(s, &p, blocks));
-    split.push_back({k, p, (int)blocks.size()});
-  }
+  TRY(split_plan(s, split));
   if (split.size() == 1) {  // one shape everywhere: a plain launch over all blocks
     s->force_shape = split[0].shape;
     s->force_plan.clear();
@@ -682,6 +689,20 @@ static vp_status autotune(vp_system *s) {
     s->plan_split = false;
     for (auto &b : s->buckets) b.shape = one;
   }
+  return VP_OK;
+}
+
+extern "C" vp_status vp_debug_set_tiles(vp_system *s, const int32_t *shapes, int32_t n) {
+  if (!s || !shapes) return fail(VP_ERR_ARG, "NULL argument");
+  if (n != (int32_t)s->buckets.size()) return fail(VP_ERR_ARG, "one shape per size bucket expected");
+  for (int i = 0; i < n; ++i)
+    if (shapes[i] < 0 || shapes[i] >= kNumForceShapes) return fail(VP_ERR_ARG, "unknown force shape");
+  HIPCHECK(hipDeviceSynchronize());
+  for (auto &g : s->graphs) (void)hipGraphExecDestroy(g.exec);  // they hold the old launches
+  s->graphs.clear();
+  for (int i = 0; i < n; ++i) s->buckets[i].shape = shapes[i];
+  TRY(split_plan(s, s->force_plan));
+  s->plan_split = true;
   return VP_OK;
 }
 

@@ -108,6 +108,8 @@ _lib.vp_debug_trajectory_state.argtypes = [_vp, _dp, _dp, _dp, _dp, _dp]
 _lib.vp_tile_buckets.restype = C.c_int
 _lib.vp_tile_buckets.argtypes = [_vp, C.POINTER(TileBucket), C.c_int32, C.POINTER(C.c_int32),
                                  C.POINTER(C.c_int32)]
+_lib.vp_debug_set_tiles.restype = C.c_int
+_lib.vp_debug_set_tiles.argtypes = [_vp, C.POINTER(C.c_int32), C.c_int32]
 _lib.vp_pair_count.restype = C.c_int
 _lib.vp_pair_count.argtypes = [_vp, C.c_int32, C.POINTER(C.c_int64)]
 _lib.vp_last_error.restype = C.c_char_p
@@ -116,7 +118,7 @@ _lib.vp_last_error.argtypes = []
 EXPORTED = ("vp_system_create", "vp_system_destroy", "vp_forces", "vp_step_batch",
             "vp_functional", "vp_select_path", "vp_get_state", "vp_observables", "vp_sizes",
             "vp_debug_pairs", "vp_debug_noise", "vp_set_timing", "vp_kernel_timing", "vp_pair_count",
-            "vp_debug_force_dir", "vp_debug_trajectory_state", "vp_tile_buckets",
+            "vp_debug_force_dir", "vp_debug_trajectory_state", "vp_tile_buckets", "vp_debug_set_tiles",
             "vp_last_error")
 
 
@@ -244,6 +246,12 @@ class System:
                         "blocks": b.n_blocks, "shape": b.shape, "tile": f"{b.waves}x{b.entries}",
                         "ms": [float(t) for t in b.ms]})
         return out, bool(split.value)
+
+    def set_tiles(self, shapes):
+        """Diagnostic: force tile shape per size bucket (tile_buckets order),
+        one launch per shape."""
+        arr = (C.c_int32 * len(shapes))(*[int(k) for k in shapes])
+        _check(_lib.vp_debug_set_tiles(self._h, arr, len(shapes)))
 
     def trajectory_state(self, tangents=False):
         """Exact state in user order (FP64): x, v [N, 3]; with tangents also

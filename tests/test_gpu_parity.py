@@ -574,3 +574,28 @@ def test_default_list_parameters_per_replica(c4_subset):
     assert int(obs[1, col["nstlist"]]) == 16            # C1 at 0.5 fs
     given = vp.System(reps[:1], nstlist=4, skin=0.1).observables()
     assert abs(given[0, col["skin"]] - 0.1) < 1e-12 and int(given[0, col["nstlist"]]) == 4
+
+
+def test_split_launch_plan_matches_single_launch(c4_subset):
+    """Every size bucket on its own tile shape (one launch per shape over
+    per-bucket block lists) gives bitwise the trajectories of the plain
+    single-shape launch: each block is covered exactly once."""
+    reps = list(c4_subset) + [synth.tiny(seed=3)]
+    say("split launch plan", [int(d["n_atoms"]) for d in reps])
+    plain = vp.System(reps, steps_per_graph=10)
+    split = vp.System(reps, steps_per_graph=10)
+    buckets, _ = split.tile_buckets()
+    shapes = [(i + 1) % vp.FORCE_SHAPES for i in range(len(buckets))]
+    split.set_tiles(shapes)
+    got, was_split = split.tile_buckets()
+    assert was_split and [b["shape"] for b in got] == shapes
+    for s in (plain, split):
+        s.step_batch(30)
+    assert np.array_equal(plain.get_state()[0].cpu().numpy(), split.get_state()[0].cpu().numpy())
+    assert np.array_equal(plain.functional(), split.functional())
+    xs = [f32(d["x0"]) for d in reps]
+    fa, ea = gpu_forces(plain, xs, 0.0)
+    fb, eb = gpu_forces(split, xs, 0.0)
+    assert np.array_equal(fa, fb) and np.array_equal(ea, eb)
+    with pytest.raises(vp.VpError):
+        split.set_tiles(shapes[:-1])
