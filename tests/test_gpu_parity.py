@@ -599,3 +599,67 @@ def test_split_launch_plan_matches_single_launch(c4_subset):
     assert np.array_equal(fa, fb) and np.array_equal(ea, eb)
     with pytest.raises(vp.VpError):
         split.set_tiles(shapes[:-1])
+
+
+def test_forces_match_central_differences():
+    """Force kernel against central differences (h = 1e-5 nm) on a 300-atom
+    subset of the 1,512-atom system: of the oracle's FP64 energy (the
+    definition of U; the difference quotient is exact to ~1e-8 here), and of
+    the GPU's own energies.  Every displaced configuration is one replica of
+    a single batched evaluation.  Atoms with a pair within 2h of the cutoff
+    are left out: the potential-shifted LJ and the reaction field are
+    continuous at r_c but their forces jump there (~2 kJ/mol/nm for an O-O
+    pair), so a difference quotient across r_c is not a derivative.
+
+    The GPU energies are FP64 sums of pair terms computed from FP32
+    intermediates (relative rounding ~2e-7 per term); moving one atom changes
+    the rounding of its ~300 pair terms (Coulomb pairs up to ~300 kJ/mol), so
+    E(x+h) - E(x-h) carries ~1e-4 to 1e-3 kJ/mol of noise against a
+    difference of ~F 2h = 2e-2 kJ/mol: that check can only hold to a few
+    times 1e-2."""
+    d = synth.c1_small()
+    n, ns = int(d["n_atoms"]), int(d["n_solute"])
+    rng = np.random.default_rng(7)
+    x0 = f32(d["x0"])
+    h = 1e-5
+    box = np.asarray(d["box"], float)
+
+    def straddles_cutoff(a):
+        dd = x0.astype(np.float64) - x0[a].astype(np.float64)
+        dd -= box * np.rint(dd / box)
+        r = np.sqrt((dd ** 2).sum(1))
+        r[a] = np.inf
+        return bool(np.any(np.abs(r - d["r_cut"]) < 2 * h))
+
+    solute = [a for a in range(ns) if not straddles_cutoff(a)]
+    pool = [a for a in rng.permutation(np.arange(ns, n)) if not straddles_cutoff(a)]
+    atoms = np.array(solute + sorted(pool[:300 - len(solute)]), dtype=np.int64)
+    assert len(atoms) == 300
+    axis = rng.integers(0, 3, len(atoms))  # one Cartesian direction per atom
+    xs = [x0]
+    for a, k in zip(atoms, axis):
+        for sgn in (1.0, -1.0):
+            x = x0.copy()
+            x[a, k] = np.float32(float(x0[a, k]) + sgn * h)
+            xs.append(x)
+    say("forces vs central differences:", len(xs), "configurations")
+    f, e = gpu_forces(vp.System([d] * len(xs)), xs)
+    o = O.Oracle(d)
+    st = o.init(x0_of(d))
+    terms = ("e_lj", "e_rf", "e_bond", "e_angle", "e_bias")
+    e_ora = np.array([sum(o.forces(x.astype(np.float64), 0.0, st)[2][k] for k in terms) for x in xs])
+    e_gpu = e[:, :5].sum(1)
+    fd_ora = np.zeros(len(atoms))
+    fd_gpu = np.zeros(len(atoms))
+    for i, (a, k) in enumerate(zip(atoms, axis)):
+        rp = 1 + 2 * i
+        step = float(xs[rp][a, k]) - float(xs[rp + 1][a, k])  # the displacement actually taken
+        fd_ora[i] = -(e_ora[rp] - e_ora[rp + 1]) / step
+        fd_gpu[i] = -(e_gpu[rp] - e_gpu[rp + 1]) / step
+    fa = f[:n][atoms, axis]
+    rms = np.sqrt(np.mean(fa ** 2))
+    rel_o, mx_o = np.linalg.norm(fa - fd_ora) / np.linalg.norm(fa), np.abs(fa - fd_ora).max() / rms
+    rel_g, mx_g = np.linalg.norm(fa - fd_gpu) / np.linalg.norm(fa), np.abs(fa - fd_gpu).max() / rms
+    say(f"  vs oracle energies: rel {rel_o:.2e} max {mx_o:.2e}; vs GPU energies: rel {rel_g:.2e} max {mx_g:.2e}")
+    assert rel_o <= F_REL and mx_o <= F_MAX
+    assert rel_g <= 3e-2 and mx_g <= 1e-1

@@ -51,3 +51,26 @@ def test_invalid_arguments_are_rejected_without_a_gpu():
     assert "x_final" in str(e.value)
     with pytest.raises(vp.VpError):
         vp.System([])
+
+
+def test_binding_fails_loudly_without_the_library(tmp_path):
+    """A copy of the package without libvp.so cannot be imported: there is no
+    fallback path."""
+    import shutil
+    import subprocess
+    import sys
+    pkg = tmp_path / "paper_1405_6104_amd"
+    shutil.copytree(os.path.join(ROOT, "paper_1405_6104_amd"), pkg,
+                    ignore=shutil.ignore_patterns("*.so", "__pycache__", "csrc"))
+    r = subprocess.run([sys.executable, "-c", "import paper_1405_6104_amd.vp"], cwd=tmp_path,
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode != 0
+    assert "libvp.so" in (r.stderr + r.stdout)
+
+
+def test_bench_refuses_more_than_one_gpu():
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr
