@@ -281,7 +281,7 @@ def main():
             "frac": achieved / PEAK_FP32_TFLOPS,
             "traffic": (FORCE_TRAFFIC_BYTES if args.workload == "c3" and args.replicas == 64
                         else None),
-            "kernel": "k_forces (nonbonded LJ+RF + bonded)",
+            "kernel": "k_forces (nonbonded LJ + reaction field)",
             "flop_per_unit": FLOP_PER_PAIR, "units_per_launch": pairs_total,
             "avg_launch_ms": force_ms, "launches_timed": n_launch,
         },

@@ -226,7 +226,7 @@ __global__ __launch_bounds__(64 * PARTS) __attribute__((amdgpu_waves_per_eu(MINW
   __syncthreads();
   if (part == 0) {
     long long fxs = 0, fys = 0, fzs = 0;
-    double ebond = 0.0, eangle = 0.0, el = 0.0, er = 0.0;
+    double el = 0.0, er = 0.0;
     if (active) {
       float sx = red[lane], sy = red[kLogicalParts * kBlk + lane], sz = red[2 * kLogicalParts * kBlk + lane];
 #pragma unroll 4
@@ -241,62 +241,9 @@ __global__ __launch_bounds__(64 * PARTS) __attribute__((amdgpu_waves_per_eu(MINW
           el += ered[q * kBlk + lane];
           er += ered[(kLogicalParts + q) * kBlk + lane];
         }
-      double bx = 0.0, by = 0.0, bz = 0.0;
-      const int a = W.orig[slot];
-      const int ga = R.uoff + a;
-      const int t0 = bt_start[ga], t1 = bt_start[ga + 1];
-      for (int t = t0; t < t1; ++t) {
-        const BTerm T = bterms[t];
-        if (T.kind == 0) {
-          const int4 xb = W.xq[W.inv[R.uoff + T.a]];
-          const double d0 = (double)(xb.x - xi.x) * kInvQ, d1 = (double)(xb.y - xi.y) * kInvQ,
-                       d2 = (double)(xb.z - xi.z) * kInvQ;
-          const double rr = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
-          const double g = T.k * (rr - T.r0) / rr;
-          bx += g * d0;
-          by += g * d1;
-          bz += g * d2;
-          if (ENERGY) ebond += 0.25 * T.k * (rr - T.r0) * (rr - T.r0);  // owned by both atoms
-        } else {
-          // angle end--vertex--end; this atom is an end (kind 1) or the vertex (kind 2)
-          int4 pa, pc, pb;
-          if (T.kind == 1) {
-            pa = xi;
-            pc = W.xq[W.inv[R.uoff + T.a]];
-            pb = W.xq[W.inv[R.uoff + T.b]];
-          } else {
-            pa = W.xq[W.inv[R.uoff + T.a]];
-            pc = xi;
-            pb = W.xq[W.inv[R.uoff + T.b]];
-          }
-          const double u0 = (double)(pa.x - pc.x) * kInvQ, u1 = (double)(pa.y - pc.y) * kInvQ,
-                       u2 = (double)(pa.z - pc.z) * kInvQ;
-          const double w0 = (double)(pb.x - pc.x) * kInvQ, w1 = (double)(pb.y - pc.y) * kInvQ,
-                       w2 = (double)(pb.z - pc.z) * kInvQ;
-          const double uu = u0 * u0 + u1 * u1 + u2 * u2, ww = w0 * w0 + w1 * w1 + w2 * w2;
-          const double uw = u0 * w0 + u1 * w1 + u2 * w2;
-          const double nn = sqrt(uu * ww);
-          double cs = uw / nn;
-          cs = cs > 1.0 ? 1.0 : (cs < -1.0 ? -1.0 : cs);
-          const double th = acos(cs);
-          double sn = sqrt(1.0 - cs * cs);
-          sn = sn < 1e-12 ? 1e-12 : sn;
-          const double dv = T.k * (th - T.r0) / sn;
-          if (T.kind == 1) {
-            bx += dv * (w0 / nn - cs * u0 / uu);
-            by += dv * (w1 / nn - cs * u1 / uu);
-            bz += dv * (w2 / nn - cs * u2 / uu);
-          } else {
-            bx -= dv * (w0 / nn - cs * u0 / uu + u0 / nn - cs * w0 / ww);
-            by -= dv * (w1 / nn - cs * u1 / uu + u1 / nn - cs * w1 / ww);
-            bz -= dv * (w2 / nn - cs * u2 / uu + u2 / nn - cs * w2 / ww);
-          }
-          if (ENERGY) eangle += (0.5 / 3.0) * T.k * (th - T.r0) * (th - T.r0);  // owned by 3 atoms
-        }
-      }
-      fxs = to_fix((double)sx * kInvQ + bx);
-      fys = to_fix((double)sy * kInvQ + by);
-      fzs = to_fix((double)sz * kInvQ + bz);
+      fxs = to_fix((double)sx * kInvQ);
+      fys = to_fix((double)sy * kInvQ);
+      fzs = to_fix((double)sz * kInvQ);
     }
     W.F[slot] = fxs;
     W.F[W.fstride + slot] = fys;
@@ -304,13 +251,106 @@ __global__ __launch_bounds__(64 * PARTS) __attribute__((amdgpu_waves_per_eu(MINW
     if (ENERGY) {
       // the block's sums over its 64 atoms (wave 0 alone, fixed butterfly order)
       const double v0 = wave_sum(0.5 * el), v1 = wave_sum(0.5 * er);
-      const double v2 = wave_sum(ebond), v3 = wave_sum(eangle);
       if (lane == 0) {
         W.epart[4 * (size_t)b + 0] = v0;
         W.epart[4 * (size_t)b + 1] = v1;
-        W.epart[4 * (size_t)b + 2] = v2;
-        W.epart[4 * (size_t)b + 3] = v3;
+        W.epart[4 * (size_t)b + 2] = 0.0;  // bonded energies: k_bonded
+        W.epart[4 * (size_t)b + 3] = 0.0;
       }
+    }
+  }
+}
+
+// Bonded forces (harmonic bonds and angles, FP64 on the exact integer
+// separations), one thread per atom of a 64-atom block, added to the
+// fixed-point forces the pair kernel stored: every atom evaluates the terms
+// it belongs to (an angle by its two ends and its vertex), so each force is
+// written by its own thread.  Separate from k_forces so that these dependent
+// gathers and long FP64 chains run over the whole chip instead of on one wave
+// of each pair block.  ENERGY: the block's bond and angle energies.
+template <bool ENERGY>
+__global__ __launch_bounds__(kBlk) void k_bonded(const RepInfo *__restrict__ info, Work W,
+                                                 const int32_t *__restrict__ tile_rep,
+                                                 const int32_t *__restrict__ tile_first, int nblk,
+                                                 const int32_t *__restrict__ bt_start,
+                                                 const BTerm *__restrict__ bterms) {
+  const int b = xcd_tile(blockIdx.x, nblk);
+  if (b < 0) return;
+  const int tile = b / (kTile / kBlk);
+  const RepInfo &R = info[tile_rep[tile]];
+  const int p0 = tile_first[tile] + (b % (kTile / kBlk)) * kBlk;
+  if (p0 >= R.n) return;  // padding block: the pair kernel zeroed its forces and energies
+  const int lane = threadIdx.x;
+  const int p = p0 + lane;
+  const int slot = R.off + p;
+  const bool active = p < R.n;
+  double ebond = 0.0, eangle = 0.0;
+  if (active) {
+    const int4 xi = W.xq[slot];
+    double bx = 0.0, by = 0.0, bz = 0.0;
+    const int a = W.orig[slot];
+    const int ga = R.uoff + a;
+    const int t0 = bt_start[ga], t1 = bt_start[ga + 1];
+    for (int t = t0; t < t1; ++t) {
+      const BTerm T = bterms[t];
+      if (T.kind == 0) {
+        const int4 xb = W.xq[W.inv[R.uoff + T.a]];
+        const double d0 = (double)(xb.x - xi.x) * kInvQ, d1 = (double)(xb.y - xi.y) * kInvQ,
+                     d2 = (double)(xb.z - xi.z) * kInvQ;
+        const double rr = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+        const double g = T.k * (rr - T.r0) / rr;
+        bx += g * d0;
+        by += g * d1;
+        bz += g * d2;
+        if (ENERGY) ebond += 0.25 * T.k * (rr - T.r0) * (rr - T.r0);  // owned by both atoms
+      } else {
+        // angle end--vertex--end; this atom is an end (kind 1) or the vertex (kind 2)
+        int4 pa, pc, pb;
+        if (T.kind == 1) {
+          pa = xi;
+          pc = W.xq[W.inv[R.uoff + T.a]];
+          pb = W.xq[W.inv[R.uoff + T.b]];
+        } else {
+          pa = W.xq[W.inv[R.uoff + T.a]];
+          pc = xi;
+          pb = W.xq[W.inv[R.uoff + T.b]];
+        }
+        const double u0 = (double)(pa.x - pc.x) * kInvQ, u1 = (double)(pa.y - pc.y) * kInvQ,
+                     u2 = (double)(pa.z - pc.z) * kInvQ;
+        const double w0 = (double)(pb.x - pc.x) * kInvQ, w1 = (double)(pb.y - pc.y) * kInvQ,
+                     w2 = (double)(pb.z - pc.z) * kInvQ;
+        const double uu = u0 * u0 + u1 * u1 + u2 * u2, ww = w0 * w0 + w1 * w1 + w2 * w2;
+        const double uw = u0 * w0 + u1 * w1 + u2 * w2;
+        const double nn = sqrt(uu * ww);
+        double cs = uw / nn;
+        cs = cs > 1.0 ? 1.0 : (cs < -1.0 ? -1.0 : cs);
+        const double th = acos(cs);
+        double sn = sqrt(1.0 - cs * cs);
+        sn = sn < 1e-12 ? 1e-12 : sn;
+        const double dv = T.k * (th - T.r0) / sn;
+        if (T.kind == 1) {
+          bx += dv * (w0 / nn - cs * u0 / uu);
+          by += dv * (w1 / nn - cs * u1 / uu);
+          bz += dv * (w2 / nn - cs * u2 / uu);
+        } else {
+          bx -= dv * (w0 / nn - cs * u0 / uu + u0 / nn - cs * w0 / ww);
+          by -= dv * (w1 / nn - cs * u1 / uu + u1 / nn - cs * w1 / ww);
+          bz -= dv * (w2 / nn - cs * u2 / uu + u2 / nn - cs * w2 / ww);
+        }
+        if (ENERGY) eangle += (0.5 / 3.0) * T.k * (th - T.r0) * (th - T.r0);  // owned by 3 atoms
+      }
+    }
+    if (bt_start[ga + 1] > bt_start[ga]) {
+      W.F[slot] += to_fix(bx);
+      W.F[W.fstride + slot] += to_fix(by);
+      W.F[2 * W.fstride + slot] += to_fix(bz);
+    }
+  }
+  if (ENERGY) {
+    const double v2 = wave_sum(ebond), v3 = wave_sum(eangle);
+    if (lane == 0) {
+      W.epart[4 * (size_t)b + 2] = v2;
+      W.epart[4 * (size_t)b + 3] = v3;
     }
   }
 }
@@ -1075,12 +1115,26 @@ void launch_forces_shape(vp_system *s, Work &W, bool energy, int shape, const in
   }
 }
 
-void launch_forces(vp_system *s, Work &W, bool energy, hipStream_t st) {
+void launch_pair_forces(vp_system *s, Work &W, bool energy, hipStream_t st) {
   if (s->force_plan.empty()) {
     launch_forces_shape(s, W, energy, s->force_shape, nullptr, s->n_blocks, st);
     return;
   }
   for (const auto &g : s->force_plan) launch_forces_shape(s, W, energy, g.shape, g.blist, g.nblk, st);
+}
+
+void launch_bonded(vp_system *s, Work &W, bool energy, hipStream_t st) {
+  if (energy)
+    hipLaunchKernelGGL(k_bonded<true>, dim3(xcd_grid(s->n_blocks)), dim3(kBlk), 0, st, s->info, W,
+                       s->tile_rep, s->tile_first, s->n_blocks, s->bt_start, s->bterms);
+  else
+    hipLaunchKernelGGL(k_bonded<false>, dim3(xcd_grid(s->n_blocks)), dim3(kBlk), 0, st, s->info, W,
+                       s->tile_rep, s->tile_first, s->n_blocks, s->bt_start, s->bterms);
+}
+
+void launch_forces(vp_system *s, Work &W, bool energy, hipStream_t st) {
+  launch_pair_forces(s, W, energy, st);
+  launch_bonded(s, W, energy, st);
 }
 
 void launch_cv(vp_system *s, Work &W, int inc_step, hipStream_t st, bool tan) {

@@ -601,6 +601,16 @@ static void make_buckets(vp_system *s) {
   }
 }
 
+// The timed launches leave pair forces only in the trajectory's force arrays:
+// recompute the full forces of the current state (the same values as before,
+// whatever the tile shape).
+static vp_status restore_forces(vp_system *s) {
+  launch_forces(s, s->traj, false, 0);
+  HIPCHECK(hipGetLastError());
+  HIPCHECK(hipDeviceSynchronize());
+  return VP_OK;
+}
+
 // Shortest of `reps` timed executions of the launches `plan` (after one untimed).
 static vp_status time_plan(vp_system *s, const std::vector<vp_system::ForceLaunch> &plan, int reps,
                            double *ms) {
@@ -667,7 +677,7 @@ static vp_status autotune(vp_system *s) {
     s->force_shape = split[0].shape;
     s->force_plan.clear();
     s->plan_split = false;
-    return VP_OK;
+    return restore_forces(s);
   }
   double t_split = 0.0, t_one = 1e30;
   int one = 0;
@@ -689,7 +699,7 @@ static vp_status autotune(vp_system *s) {
     s->plan_split = false;
     for (auto &b : s->buckets) b.shape = one;
   }
-  return VP_OK;
+  return restore_forces(s);
 }
 
 extern "C" vp_status vp_debug_set_tiles(vp_system *s, const int32_t *shapes, int32_t n) {
@@ -810,8 +820,9 @@ static void enqueue_block(vp_system *s, int steps, hipStream_t st) {
     launch_integrate(s, k == 0 ? INT_START : (INT_FINISH | INT_START), st);
     launch_rebuild(s, s->traj, 0, nullptr, st);
     if (timing) (void)hipEventRecord(s->ev_before[k], st);
-    launch_forces(s, s->traj, false, st);
+    launch_pair_forces(s, s->traj, false, st);
     if (timing) (void)hipEventRecord(s->ev_after[k], st);
+    launch_bonded(s, s->traj, false, st);
     if (s->tangent) launch_tangent_forces(s, s->traj, st);
     launch_cv(s, s->traj, 1, st, s->tangent);
   }

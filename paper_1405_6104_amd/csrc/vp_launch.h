@@ -10,7 +10,9 @@ enum { INT_FINISH = 1, INT_START = 2, INT_INIT = 4 };
 void launch_rebuild(vp_system *s, Work &W, int mode, const float *x_user, hipStream_t st);
 void launch_debug_pairs(vp_system *s, Work &W, int rep, int2 *out, unsigned long long cap,
                         unsigned long long *counter, hipStream_t st);
-void launch_forces(vp_system *s, Work &W, bool energy, hipStream_t st);
+void launch_forces(vp_system *s, Work &W, bool energy, hipStream_t st);  // pair + bonded
+void launch_pair_forces(vp_system *s, Work &W, bool energy, hipStream_t st);  // k_forces launches only
+void launch_bonded(vp_system *s, Work &W, bool energy, hipStream_t st);  // adds the bonded forces
 // one tile shape (index into kForceShapes) over a list of blocks (NULL: all nblk blocks)
 void launch_forces_shape(vp_system *s, Work &W, bool energy, int shape, const int32_t *blist, int nblk,
                          hipStream_t st);
