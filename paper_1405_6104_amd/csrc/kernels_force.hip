@@ -261,6 +261,65 @@ __global__ __launch_bounds__(64 * PARTS) __attribute__((amdgpu_waves_per_eu(MINW
   }
 }
 
+// One bonded term of an atom at xi: a bond to the atom at p1, or an angle with
+// vertex p1 and other end p2 (kind 1) or with ends p1 and p2 (kind 2).
+template <bool ENERGY>
+__device__ __forceinline__ void bonded_term(const BTerm &T, const int4 xi, const int4 p1, const int4 p2,
+                                            double &bx, double &by, double &bz, double &ebond,
+                                            double &eangle) {
+  if (T.kind == 0) {
+    const int4 xb = p1;
+    const double d0 = (double)(xb.x - xi.x) * kInvQ, d1 = (double)(xb.y - xi.y) * kInvQ,
+                 d2 = (double)(xb.z - xi.z) * kInvQ;
+    const double rr = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+    const double g = T.k * (rr - T.r0) / rr;
+    bx += g * d0;
+    by += g * d1;
+    bz += g * d2;
+    if (ENERGY) ebond += 0.25 * T.k * (rr - T.r0) * (rr - T.r0);  // owned by both atoms
+  } else {
+    // angle end--vertex--end; this atom is an end (kind 1) or the vertex (kind 2)
+    int4 pa, pc, pb;
+    if (T.kind == 1) {
+      pa = xi;
+      pc = p1;
+      pb = p2;
+    } else {
+      pa = p1;
+      pc = xi;
+      pb = p2;
+    }
+    const double u0 = (double)(pa.x - pc.x) * kInvQ, u1 = (double)(pa.y - pc.y) * kInvQ,
+                 u2 = (double)(pa.z - pc.z) * kInvQ;
+    const double w0 = (double)(pb.x - pc.x) * kInvQ, w1 = (double)(pb.y - pc.y) * kInvQ,
+                 w2 = (double)(pb.z - pc.z) * kInvQ;
+    const double uu = u0 * u0 + u1 * u1 + u2 * u2, ww = w0 * w0 + w1 * w1 + w2 * w2;
+    const double uw = u0 * w0 + u1 * w1 + u2 * w2;
+    const double nn = sqrt(uu * ww);
+    double cs = uw / nn;
+    cs = cs > 1.0 ? 1.0 : (cs < -1.0 ? -1.0 : cs);
+    const double th = acos(cs);
+    double sn = sqrt(1.0 - cs * cs);
+    sn = sn < 1e-12 ? 1e-12 : sn;
+    const double dv = T.k * (th - T.r0) / sn;
+    if (T.kind == 1) {
+      bx += dv * (w0 / nn - cs * u0 / uu);
+      by += dv * (w1 / nn - cs * u1 / uu);
+      bz += dv * (w2 / nn - cs * u2 / uu);
+    } else {
+      bx -= dv * (w0 / nn - cs * u0 / uu + u0 / nn - cs * w0 / ww);
+      by -= dv * (w1 / nn - cs * u1 / uu + u1 / nn - cs * w1 / ww);
+      bz -= dv * (w2 / nn - cs * u2 / uu + u2 / nn - cs * w2 / ww);
+    }
+    if (ENERGY) eangle += (0.5 / 3.0) * T.k * (th - T.r0) * (th - T.r0);  // owned by 3 atoms
+  }
+}
+
+// Terms gathered per pass of k_bonded: their records, partner slots and
+// partner positions are each loaded together, so an atom's terms cost three
+// dependent loads per pass instead of three per term.
+constexpr int kBondBatch = 4;
+
 // Bonded forces (harmonic bonds and angles, FP64 on the exact integer
 // separations), one thread per atom of a 64-atom block, added to the
 // fixed-point forces the pair kernel stored: every atom evaluates the terms
@@ -291,54 +350,25 @@ __global__ __launch_bounds__(kBlk) void k_bonded(const RepInfo *__restrict__ inf
     const int a = W.orig[slot];
     const int ga = R.uoff + a;
     const int t0 = bt_start[ga], t1 = bt_start[ga + 1];
-    for (int t = t0; t < t1; ++t) {
-      const BTerm T = bterms[t];
-      if (T.kind == 0) {
-        const int4 xb = W.xq[W.inv[R.uoff + T.a]];
-        const double d0 = (double)(xb.x - xi.x) * kInvQ, d1 = (double)(xb.y - xi.y) * kInvQ,
-                     d2 = (double)(xb.z - xi.z) * kInvQ;
-        const double rr = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
-        const double g = T.k * (rr - T.r0) / rr;
-        bx += g * d0;
-        by += g * d1;
-        bz += g * d2;
-        if (ENERGY) ebond += 0.25 * T.k * (rr - T.r0) * (rr - T.r0);  // owned by both atoms
-      } else {
-        // angle end--vertex--end; this atom is an end (kind 1) or the vertex (kind 2)
-        int4 pa, pc, pb;
-        if (T.kind == 1) {
-          pa = xi;
-          pc = W.xq[W.inv[R.uoff + T.a]];
-          pb = W.xq[W.inv[R.uoff + T.b]];
-        } else {
-          pa = W.xq[W.inv[R.uoff + T.a]];
-          pc = xi;
-          pb = W.xq[W.inv[R.uoff + T.b]];
-        }
-        const double u0 = (double)(pa.x - pc.x) * kInvQ, u1 = (double)(pa.y - pc.y) * kInvQ,
-                     u2 = (double)(pa.z - pc.z) * kInvQ;
-        const double w0 = (double)(pb.x - pc.x) * kInvQ, w1 = (double)(pb.y - pc.y) * kInvQ,
-                     w2 = (double)(pb.z - pc.z) * kInvQ;
-        const double uu = u0 * u0 + u1 * u1 + u2 * u2, ww = w0 * w0 + w1 * w1 + w2 * w2;
-        const double uw = u0 * w0 + u1 * w1 + u2 * w2;
-        const double nn = sqrt(uu * ww);
-        double cs = uw / nn;
-        cs = cs > 1.0 ? 1.0 : (cs < -1.0 ? -1.0 : cs);
-        const double th = acos(cs);
-        double sn = sqrt(1.0 - cs * cs);
-        sn = sn < 1e-12 ? 1e-12 : sn;
-        const double dv = T.k * (th - T.r0) / sn;
-        if (T.kind == 1) {
-          bx += dv * (w0 / nn - cs * u0 / uu);
-          by += dv * (w1 / nn - cs * u1 / uu);
-          bz += dv * (w2 / nn - cs * u2 / uu);
-        } else {
-          bx -= dv * (w0 / nn - cs * u0 / uu + u0 / nn - cs * w0 / ww);
-          by -= dv * (w1 / nn - cs * u1 / uu + u1 / nn - cs * w1 / ww);
-          bz -= dv * (w2 / nn - cs * u2 / uu + u2 / nn - cs * w2 / ww);
-        }
-        if (ENERGY) eangle += (0.5 / 3.0) * T.k * (th - T.r0) * (th - T.r0);  // owned by 3 atoms
+    for (int t = t0; t < t1; t += kBondBatch) {
+      BTerm T[kBondBatch];
+#pragma unroll
+      for (int u = 0; u < kBondBatch; ++u) T[u] = bterms[min(t + u, t1 - 1)];
+      int s1[kBondBatch], s2[kBondBatch];
+#pragma unroll
+      for (int u = 0; u < kBondBatch; ++u) {
+        s1[u] = W.inv[R.uoff + T[u].a];
+        s2[u] = W.inv[R.uoff + (T[u].kind == 0 ? T[u].a : T[u].b)];
       }
+      int4 p1[kBondBatch], p2[kBondBatch];
+#pragma unroll
+      for (int u = 0; u < kBondBatch; ++u) {
+        p1[u] = W.xq[s1[u]];
+        p2[u] = W.xq[s2[u]];
+      }
+#pragma unroll
+      for (int u = 0; u < kBondBatch; ++u)
+        if (t + u < t1) bonded_term<ENERGY>(T[u], xi, p1[u], p2[u], bx, by, bz, ebond, eangle);
     }
     if (bt_start[ga + 1] > bt_start[ga]) {
       W.F[slot] += to_fix(bx);
