@@ -27,15 +27,16 @@
 namespace vp {
 
 // Copies a block's staged neighbourhood into LDS: entry s (slot | 3 x 5-bit
-// image shift) becomes that atom's position shifted by the image, with its
-// type.  Each thread keeps kStageBatch entries in flight (their codes, then
+// image shift) becomes that atom's position shifted by the image, with the
+// LDS byte address of its type-table row (trow + 16 type) in place of the
+// type, so a pair reads the row without an address computation.  Each thread keeps kStageBatch entries in flight (their codes, then
 // their positions) so that the gathers cost two memory latencies per batch
 // rather than two per entry.
 constexpr int kStageBatch = 8;
 template <int NT>
 __device__ __forceinline__ void stage_neighbourhood(const uint32_t *__restrict__ stg, int nst,
                                                     const int4 *__restrict__ xr, int Lx, int Ly, int Lz,
-                                                    int tid, int4 *__restrict__ st) {
+                                                    int trow, int tid, int4 *__restrict__ st) {
   for (int s0 = 0; s0 < nst; s0 += NT * kStageBatch) {
     // loads past the end read the last entry again (no branch between the
     // loads, so they stay in flight together); only the stores are guarded
@@ -50,7 +51,8 @@ __device__ __forceinline__ void stage_neighbourhood(const uint32_t *__restrict__
       const int s = s0 + k * NT + tid;
       const int sx = (int)((e[k] >> 16) & 31) - 16, sy = (int)((e[k] >> 21) & 31) - 16,
                 sz = (int)((e[k] >> 26) & 31) - 16;
-      if (s < nst) st[s] = make_int4(xj[k].x + sx * Lx, xj[k].y + sy * Ly, xj[k].z + sz * Lz, xj[k].w);
+      if (s < nst)
+        st[s] = make_int4(xj[k].x + sx * Lx, xj[k].y + sy * Ly, xj[k].z + sz * Lz, trow + 16 * xj[k].w);
     }
   }
 }
@@ -61,7 +63,7 @@ __device__ __forceinline__ void stage_neighbourhood(const uint32_t *__restrict__
 // share one batch of LDS reads.
 template <bool ENERGY, int UNROLL>
 __device__ __forceinline__ void eval_chunk(const uint4 e, const int4 *__restrict__ st,
-                                           const float4 *__restrict__ tab, const float4 ti, int wx,
+                                           const char *__restrict__ ldsb, const float4 ti, int wx,
                                            int wy, int wz, float rc2, float krf2, const RepInfo &R,
                                            float &fx, float &fy, float &fz, double &elj, double &erf) {
   const uint32_t w[4] = {e.x, e.y, e.z, e.w};
@@ -75,7 +77,7 @@ __device__ __forceinline__ void eval_chunk(const uint4 e, const int4 *__restrict
     }
     float4 tj[UNROLL];
 #pragma unroll
-    for (int v = 0; v < UNROLL; ++v) tj[v] = tab[sj[v].w];
+    for (int v = 0; v < UNROLL; ++v) tj[v] = *reinterpret_cast<const float4 *>(ldsb + sj[v].w);
 #pragma unroll
     for (int u = 0; u < UNROLL; ++u) {
       // every entry is evaluated; the cutoff selects (no divergent branch)
@@ -88,10 +90,11 @@ __device__ __forceinline__ void eval_chunk(const uint4 e, const int4 *__restrict
       const float sr2 = sg * sg * r2inv;
       const float sr6 = sr2 * sr2 * sr2;
       const float ee = ti.z * tj[u].z;
-      const float flj = ee * sr6 * __builtin_fmaf(2.0f, sr6, -1.0f) * r2inv;
+      // force scalar (LJ + reaction field) / r, both terms over one 1/r^2
+      const float c6 = ee * sr6 * __builtin_fmaf(2.0f, sr6, -1.0f);
       const float qq = ti.x * tj[u].x;
-      const float fc = qq * __builtin_fmaf(rinv, r2inv, -krf2);
-      const float fs = in ? flj + fc : 0.0f;
+      const float cq = qq * __builtin_fmaf(rinv, r2inv, -krf2);
+      const float fs = in ? __builtin_fmaf(c6, r2inv, cq) : 0.0f;
       fx = __builtin_fmaf(-fs, dx, fx);
       fy = __builtin_fmaf(-fs, dy, fy);
       fz = __builtin_fmaf(-fs, dz, fz);
@@ -158,9 +161,10 @@ __global__ __launch_bounds__(64 * PARTS) __attribute__((amdgpu_waves_per_eu(MINW
   }
   const int Lx = R.Lq[0], Ly = R.Lq[1], Lz = R.Lq[2];
   // ---- stage the neighbourhood and the type table
+  const int trow = (int)sizeof(int4) * stage_slots;  // LDS byte address of the type table
   stage_neighbourhood<NT>(W.stage + (int64_t)b * W.stage_stride, W.stage_n[b], W.xq + R.off, Lx, Ly, Lz,
-                          tid, st);
-  if (tid == 0) st[R.stage_cap] = make_int4(kDummyCoord, kDummyCoord, kDummyCoord, R.ntypes);
+                          trow, tid, st);
+  if (tid == 0) st[R.stage_cap] = make_int4(kDummyCoord, kDummyCoord, kDummyCoord, trow + 16 * R.ntypes);
   for (int t = tid; t <= R.ntypes; t += NT) tab[t] = types[R.type_off + t];
   __syncthreads();
 
@@ -193,8 +197,8 @@ __global__ __launch_bounds__(64 * PARTS) __attribute__((amdgpu_waves_per_eu(MINW
       // the next chunk's indices are fetched while this one is evaluated
       // (the last chunk is fetched again rather than reading past the list)
       const uint4 en = lp[(int64_t)min(c + PARTS, nch - 1) * kBlk];
-      eval_chunk<ENERGY, UNROLL>(e, st, tab, ti, wx, wy, wz, rc2, krf2, R, fx[0], fy[0], fz[0],
-                                 elj[0], erf[0]);
+      eval_chunk<ENERGY, UNROLL>(e, st, reinterpret_cast<const char *>(lds), ti, wx, wy, wz, rc2, krf2, R,
+                                 fx[0], fy[0], fz[0], elj[0], erf[0]);
       // the sets rotate so that set 0 is always the one the next chunk feeds
 #pragma unroll
       for (int k = 0; k + 1 < SETS; ++k) {
@@ -421,7 +425,8 @@ __global__ __launch_bounds__(kForceThreads) void k_tangent_forces(
   const int nst = W.stage_n[b];
   const uint32_t *stg = W.stage + (int64_t)b * W.stage_stride;
   const int4 *xr = W.xq + R.off;
-  stage_neighbourhood<kForceThreads>(stg, nst, xr, Lx, Ly, Lz, tid, st);
+  const int trow = (int)sizeof(int4) * 2 * stage_slots;  // LDS byte address of the type table
+  stage_neighbourhood<kForceThreads>(stg, nst, xr, Lx, Ly, Lz, trow, tid, st);
   for (int q0 = 0; q0 < nst; q0 += kForceThreads * kStageBatch) {
     // the staged atoms' tangents, kStageBatch loads in flight per thread
     float4 t[kStageBatch];
@@ -433,7 +438,7 @@ __global__ __launch_bounds__(kForceThreads) void k_tangent_forces(
       if (q0 + k * kForceThreads + tid < nst) sxi[q0 + k * kForceThreads + tid] = t[k];
   }
   if (tid == 0) {
-    st[R.stage_cap] = make_int4(kDummyCoord, kDummyCoord, kDummyCoord, R.ntypes);
+    st[R.stage_cap] = make_int4(kDummyCoord, kDummyCoord, kDummyCoord, trow + 16 * R.ntypes);
     sxi[R.stage_cap] = make_float4(0.f, 0.f, 0.f, 0.f);
   }
   for (int t = tid; t <= R.ntypes; t += kForceThreads) tab[t] = types[R.type_off + t];
@@ -464,7 +469,7 @@ __global__ __launch_bounds__(kForceThreads) void k_tangent_forces(
       for (int u = 0; u < 8; ++u) {
         const int L = (int)((w[u >> 1] >> (16 * (u & 1))) & 0xffffu);
         const int4 sj = st[L];
-        const float4 tj = tab[sj.w];
+        const float4 tj = *reinterpret_cast<const float4 *>(reinterpret_cast<const char *>(lds) + sj.w);
         const float4 xj = sxi[L];
         const float dx = (float)(sj.x - wx), dy = (float)(sj.y - wy), dz = (float)(sj.z - wz);
         const float r2 = qr2(dx, dy, dz);
