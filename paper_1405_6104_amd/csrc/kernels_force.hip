@@ -508,7 +508,28 @@ __global__ __launch_bounds__(kForceThreads) void k_tangent_forces(
     sy += red[kForceThreads + q * kBlk + lane];
     sz += red[2 * kForceThreads + q * kBlk + lane];
   }
-  // bonded terms owned by this atom, differentiated along the tangent
+  tfp[slot] = make_float4((float)((double)sx * kInvQ), (float)((double)sy * kInvQ),
+                          (float)((double)sz * kInvQ), 0.0f);
+}
+
+// Bonded part of the tangent forces (one direction per launch): the FP64
+// bonds and angles of each atom differentiated along the tangent on dual
+// numbers, one thread per atom, added to the pair part k_tangent_forces
+// stored (separate for the same reason as k_bonded).
+__global__ __launch_bounds__(kBlk) void k_tangent_bonded(const RepInfo *__restrict__ info, Work W,
+                                                         const int32_t *__restrict__ tile_rep,
+                                                         const int32_t *__restrict__ tile_first, int nblk,
+                                                         const int32_t *__restrict__ bt_start,
+                                                         const BTerm *__restrict__ bterms, int dir) {
+  const int b = xcd_tile(blockIdx.x, nblk);
+  if (b < 0) return;
+  const int tile = b / (kTile / kBlk);
+  const RepInfo &R = info[tile_rep[tile]];
+  const int p = tile_first[tile] + (b % (kTile / kBlk)) * kBlk + (int)threadIdx.x;
+  if (p >= R.n) return;
+  const int slot = R.off + p;
+  const float4 *txp = W.tx + (size_t)dir * W.fstride;
+  float4 *tfp = W.tf + (size_t)dir * W.fstride;
   double bx = 0.0, by = 0.0, bz = 0.0;
   const int a = W.orig[slot];
   const int t0 = bt_start[R.uoff + a], t1 = bt_start[R.uoff + a + 1];
@@ -520,11 +541,12 @@ __global__ __launch_bounds__(kForceThreads) void k_tangent_forces(
     const float tc = k == 0 ? ta.x : (k == 1 ? ta.y : ta.z);
     return {(double)c * kInvQ, (double)tc};
   };
+  dual1 self[3];
+  for (int k = 0; k < 3; ++k) self[k] = pos(a, k);
   for (int t = t0; t < t1; ++t) {
     const BTerm T = bterms[t];
-    dual1 self[3], A[3], B[3];
+    dual1 A[3], B[3];
     for (int k = 0; k < 3; ++k) {
-      self[k] = pos(a, k);
       A[k] = pos(T.a, k);
       if (T.kind != 0) B[k] = pos(T.b, k);
     }
@@ -569,9 +591,15 @@ __global__ __launch_bounds__(kForceThreads) void k_tangent_forces(
       bz += f[2];
     }
   }
-  tfp[slot] = make_float4((float)((double)sx * kInvQ + bx), (float)((double)sy * kInvQ + by),
-                          (float)((double)sz * kInvQ + bz), 0.0f);
+  if (t1 > t0) {
+    float4 g = tfp[slot];
+    g.x = (float)((double)g.x + bx);
+    g.y = (float)((double)g.y + by);
+    g.z = (float)((double)g.z + bz);
+    tfp[slot] = g;
+  }
 }
+
 
 // ---------------------------------------------------------------------------
 // collective variable of the bias
@@ -1211,10 +1239,13 @@ hipError_t prepare_tangent(const vp_system *s) {
 
 void launch_tangent_forces(vp_system *s, Work &W, hipStream_t st) {
   const size_t lds = tangent_lds_bytes(s);
-  for (int d = 0; d < 2; ++d)
+  for (int d = 0; d < 2; ++d) {
     hipLaunchKernelGGL(k_tangent_forces, dim3(xcd_grid(s->n_blocks)), dim3(kForceThreads), lds, st,
                        s->info, W, s->tile_rep, s->tile_first, s->n_blocks, s->types, s->bt_start,
                        s->bterms, s->stage_cap_max + 1, d);
+    hipLaunchKernelGGL(k_tangent_bonded, dim3(xcd_grid(s->n_blocks)), dim3(kBlk), 0, st, s->info, W,
+                       s->tile_rep, s->tile_first, s->n_blocks, s->bt_start, s->bterms, d);
+  }
 }
 
 void launch_force_dir(vp_system *s, Work &W, const float *dx_user, double t, float *out,
