@@ -533,23 +533,22 @@ __global__ __launch_bounds__(kBlk) void k_tangent_bonded(const RepInfo *__restri
   double bx = 0.0, by = 0.0, bz = 0.0;
   const int a = W.orig[slot];
   const int t0 = bt_start[R.uoff + a], t1 = bt_start[R.uoff + a + 1];
-  auto pos = [&](int atom, int k) -> dual1 {
+  // an atom's position and tangent as three dual numbers (one gather each)
+  auto load = [&](int atom, dual1 out[3]) {
     const int sl = W.inv[R.uoff + atom];
     const int4 xa = W.xq[sl];
     const float4 ta = txp[sl];
-    const int c = k == 0 ? xa.x : (k == 1 ? xa.y : xa.z);
-    const float tc = k == 0 ? ta.x : (k == 1 ? ta.y : ta.z);
-    return {(double)c * kInvQ, (double)tc};
+    out[0] = {(double)xa.x * kInvQ, (double)ta.x};
+    out[1] = {(double)xa.y * kInvQ, (double)ta.y};
+    out[2] = {(double)xa.z * kInvQ, (double)ta.z};
   };
   dual1 self[3];
-  for (int k = 0; k < 3; ++k) self[k] = pos(a, k);
+  load(a, self);
   for (int t = t0; t < t1; ++t) {
     const BTerm T = bterms[t];
     dual1 A[3], B[3];
-    for (int k = 0; k < 3; ++k) {
-      A[k] = pos(T.a, k);
-      if (T.kind != 0) B[k] = pos(T.b, k);
-    }
+    load(T.a, A);
+    if (T.kind != 0) load(T.b, B);
     if (T.kind == 0) {
       dual1 d[3] = {A[0] - self[0], A[1] - self[1], A[2] - self[2]};
       const dual1 rr = dsqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
