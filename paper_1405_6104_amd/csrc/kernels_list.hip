@@ -287,23 +287,27 @@ __device__ __forceinline__ int quarter_max_i(int v) {
   return v;
 }
 
-// A lane's list entries are collected eight at a time in a 128-bit shift
-// register (lo: the four newest, hi: the four before) and stored as one
-// 16-byte write, a whole row of the [chunk][lane][8] layout, so a wave writes
-// 1 KB of contiguous list per store (the order of the eight entries inside a
-// chunk is reversed, which only changes the fixed order in which the force
-// kernel visits them).
-struct Pending {
-  uint64_t lo, hi;
-};
-__device__ __forceinline__ void list_push(Pending &p, uint32_t e) {
-  p.hi = (p.hi << 16) | (p.lo >> 48);
-  p.lo = (p.lo << 16) | (uint64_t)e;
+// A lane's list entries are collected in its own 16-byte row of LDS (one
+// 16-bit LDS store per entry, no register shuffling) and each full row of
+// eight is copied as one 16-byte write into the [chunk][lane][8] layout
+// through a pointer that advances one chunk (64 rows) per copy; rows past the
+// list's capacity are not stored (entries are still counted: the overflow is
+// flagged).
+__device__ __forceinline__ void list_append(uint16_t (*row)[8], int lane, uint32_t e, int &cnt,
+                                            uint4 *&rowp, const uint4 *rowend) {
+  const int k = cnt & 7;
+  row[lane][k] = (uint16_t)e;
+  ++cnt;
+  if (k == 7) {
+    if (rowp < rowend) *rowp = *reinterpret_cast<const uint4 *>(row[lane]);
+    rowp += kBlk;
+  }
 }
-__device__ __forceinline__ void list_store8(uint16_t *lst, int e0, int lane, const Pending &p) {
-  *reinterpret_cast<uint4 *>(lst + ((size_t)(e0 >> 3) * kBlk + lane) * 8) =
-      make_uint4((uint32_t)p.lo, (uint32_t)(p.lo >> 32), (uint32_t)p.hi, (uint32_t)(p.hi >> 32));
-}
+
+// Staged candidates tested together per step of the list kernel's inner loop
+// (kBlk is a multiple, so reads stay inside the 64-entry batch buffer).
+constexpr int kListBatch = 4;
+static_assert(kBlk % kListBatch == 0, "batch must divide the candidate buffer");
 
 // One wave per block of 64 sorted atoms.  The cells that can hold a neighbour
 // of the block (fine cells within the list radius of the block's bounding
@@ -322,7 +326,12 @@ __device__ __forceinline__ void list_store8(uint16_t *lst, int e0, int lane, con
 // list is a superset of the exact list radius, and the force kernel applies
 // the exact cutoff.
 template <int MODE>
-__global__ __launch_bounds__(kBlk) void k_list(const RepInfo *__restrict__ info,
+// Register budget for seven waves per SIMD (measured: a full rebuild of the
+// 64 x 12,560 batch takes 1.89 ms at seven waves with a few spilled
+// registers, 2.26 ms at the four that the unconstrained allocation allows,
+// 2.20 ms at eight with more spills): the candidate loop is latency-bound,
+// so more waves in flight beat spill-free code.
+__global__ __launch_bounds__(kBlk) __attribute__((amdgpu_waves_per_eu(7))) void k_list(const RepInfo *__restrict__ info,
                                                RepState *__restrict__ state, Work W,
                                                const int32_t *__restrict__ tile_rep,
                                                const int32_t *__restrict__ tile_first, int nblk,
@@ -338,6 +347,7 @@ __global__ __launch_bounds__(kBlk) void k_list(const RepInfo *__restrict__ info,
                                                const float4 *__restrict__ tx_t,
                                                const float4 *__restrict__ tv_t) {
   __shared__ float4 s_pos[kBlk];  // kept candidates: position relative to the block, user index
+  __shared__ __align__(16) uint16_t s_row[kBlk][8];  // each lane's list entries not yet stored
   __shared__ int s_cidx[3][18];  // fine-cell edges of the replica
   const int b = xcd_tile(blockIdx.x, nblk);
   if (b < 0) return;
@@ -435,11 +445,15 @@ __global__ __launch_bounds__(kBlk) void k_list(const RepInfo *__restrict__ info,
   const int a32 = a - 32;
   const int lb = b - R.blk0;
   uint16_t *lst = W.nblist + R.list_off + (int64_t)lb * R.maxnb * kBlk;
+  // this lane's row of list chunk 0, and the end of the block's list
+  uint4 *const row0 = reinterpret_cast<uint4 *>(lst) + lane;
+  const uint4 *const rowend = reinterpret_cast<const uint4 *>(lst) + (size_t)(R.maxnb >> 3) * kBlk;
+  uint4 *rowp = row0;
   uint32_t *stg = W.stage + (int64_t)b * W.stage_stride;
   const int cap = R.stage_cap, maxnb = R.maxnb;
   const int *cstart = W.cell_start + R.cell0;
   int nst = 0, cnt = 0;
-  Pending pend{0ull, 0ull};  // pending list entries (up to eight)
+
   bool bad = false;
   __syncthreads();  // cell edges in LDS
   // Fast mode stages every candidate kept by the quarter boxes.  If that
@@ -451,7 +465,7 @@ __global__ __launch_bounds__(kBlk) void k_list(const RepInfo *__restrict__ info,
     exact = mode == 1;
     nst = 0;
     cnt = 0;
-    pend = Pending{0ull, 0ull};
+    rowp = row0;
     bool full = false;
     int iz = uz0 >= 0 ? uz0 / ncz : -((-uz0 + ncz - 1) / ncz);
     int cz = uz0 - iz * ncz;
@@ -534,16 +548,25 @@ __global__ __launch_bounds__(kBlk) void k_list(const RepInfo *__restrict__ info,
               if (!exact) {
                 // ---- every staged candidate against the lane's own atom
                 if (!anyfar) {
-                  for (int k = 0; k < nk; ++k) {
-                    const float4 c = s_pos[k];
-                    const float dx = c.x - ax, dy = c.y - ay, dz = c.z - az;
-                    const int d = __float_as_int(c.w) - a32;
-                    const bool exw = (unsigned)d < 64u && ((exm >> (d & 63)) & 1ull);
-                    if (qr2(dx, dy, dz) < rl2x && !exw) {
-                      list_push(pend, (uint32_t)(nst + k));
-                      ++cnt;  // entries past maxnb are counted only to flag the overflow
-                      if ((cnt & 7) == 0 && cnt <= maxnb) list_store8(lst, cnt - 8, lane, pend);
+                  // kListBatch candidates read and tested together (their LDS
+                  // reads overlap), then appended in order; entries of s_pos
+                  // past nk are stale and masked out
+                  for (int k0 = 0; k0 < nk; k0 += kListBatch) {
+                    float4 c[kListBatch];
+#pragma unroll
+                    for (int u = 0; u < kListBatch; ++u) c[u] = s_pos[k0 + u];
+                    bool in[kListBatch];
+#pragma unroll
+                    for (int u = 0; u < kListBatch; ++u) {
+                      const float dx = c[u].x - ax, dy = c[u].y - ay, dz = c[u].z - az;
+                      const int d = __float_as_int(c[u].w) - a32;
+                      const bool exw = (unsigned)d < 64u && ((exm >> (d & 63)) & 1ull);
+                      in[u] = k0 + u < nk && qr2(dx, dy, dz) < rl2x && !exw;
                     }
+#pragma unroll
+                    for (int u = 0; u < kListBatch; ++u)
+                      if (in[u])  // entries past maxnb are counted only to flag the overflow
+                        list_append(s_row, lane, (uint32_t)(nst + k0 + u), cnt, rowp, rowend);
                   }
                 } else {
                   for (int k = 0; k < nk; ++k) {
@@ -556,9 +579,7 @@ __global__ __launch_bounds__(kBlk) void k_list(const RepInfo *__restrict__ info,
                     if (in && !win && exfar)
                       for (int e = e0; e < e1; ++e) in = in && (ex_list[e] != oj);
                     if (in) {
-                      list_push(pend, (uint32_t)(nst + k));
-                      ++cnt;
-                      if ((cnt & 7) == 0 && cnt <= maxnb) list_store8(lst, cnt - 8, lane, pend);
+                      list_append(s_row, lane, (uint32_t)(nst + k), cnt, rowp, rowend);
                     }
                   }
                 }
@@ -579,9 +600,7 @@ __global__ __launch_bounds__(kBlk) void k_list(const RepInfo *__restrict__ info,
                   if (__ballot(in)) {
                     if (nst < cap) {
                       if (in) {
-                        list_push(pend, (uint32_t)nst);
-                        ++cnt;
-                        if ((cnt & 7) == 0 && cnt <= maxnb) list_store8(lst, cnt - 8, lane, pend);
+                        list_append(s_row, lane, (uint32_t)nst, cnt, rowp, rowend);
                       }
                       acc |= 1ull << k;
                       ++nst;
@@ -609,11 +628,7 @@ __global__ __launch_bounds__(kBlk) void k_list(const RepInfo *__restrict__ info,
     cnt = maxnb - 8;
   } else if (active) {
     // pad to a multiple of 8 with the inert staging entry (index cap)
-    while (cnt & 7) {
-      list_push(pend, (uint32_t)cap);
-      ++cnt;
-      if ((cnt & 7) == 0) list_store8(lst, cnt - 8, lane, pend);
-    }
+    while (cnt & 7) list_append(s_row, lane, (uint32_t)cap, cnt, rowp, rowend);
   }
   W.nbcnt[slot] = active ? cnt : 0;
   if (lane == 0) W.stage_n[b] = nst;
