@@ -57,8 +57,8 @@ def assert_same_pairs(got, want):
     """Exact equality of two pair sets, reported by counts and a few examples
     (a plain set comparison of millions of pairs makes pytest render a diff
     whose cost grows far faster than the sets)."""
-    got = np.sort(np.asarray(got, np.int64), axis=1)
-    want = np.asarray(want, np.int64)
+    got = np.sort(np.asarray(got, np.int64).reshape(-1, 2), axis=1)
+    want = np.asarray(want, np.int64).reshape(-1, 2)
     key = lambda a: a[:, 0] * (1 << 32) + a[:, 1]
     kg, kw = np.unique(key(got)), np.unique(key(want))
     dup = len(got) - len(kg)
@@ -663,3 +663,40 @@ def test_forces_match_central_differences():
     say(f"  vs oracle energies: rel {rel_o:.2e} max {mx_o:.2e}; vs GPU energies: rel {rel_g:.2e} max {mx_g:.2e}")
     assert rel_o <= F_REL and mx_o <= F_MAX
     assert rel_g <= 3e-2 and mx_g <= 1e-1
+
+
+def test_degenerate_replicas_in_a_batch():
+    """A one-atom replica (empty lists), a lone pair inside the cutoff and a
+    256-atom replica that fills its tile exactly, batched with a ragged one:
+    forces and 10-step trajectories against the oracle, pair sets exact."""
+    one = synth.lj_box(seed=11, n=1)
+    two = synth.lj_box(seed=12, n=2)
+    two["x0"] = np.array([[1.0, 1.0, 1.0], [1.37, 1.1, 0.95]])
+    full_tile = synth.lj_box(seed=13, n=256)
+    ragged = synth.lj_box(seed=14, n=199)
+    reps = [one, two, full_tile, ragged]
+    say("degenerate replicas:", [d["n_atoms"] for d in reps])
+    system = vp.System(reps, steps_per_graph=5)
+    xs = [f32(d["x0"]) for d in reps]
+    fg, _ = gpu_forces(system, xs, 0.0)
+    for r, d in enumerate(reps):
+        a, b = system.offsets[r], system.offsets[r + 1]
+        o = O.Oracle(d)
+        fo, _, _ = o.forces(xs[r], 0.0, o.init(x0_of(d)))
+        if r == 0:
+            assert np.all(fg[a:b] == 0.0) and np.all(fo == 0.0)
+        else:
+            rel, mx = force_errors(fg[a:b], fo)
+            say(f"  replica {r}: rel {rel:.2e} max {mx:.2e}")
+            assert rel <= F_REL and mx <= F_MAX
+        assert_same_pairs(system.debug_pairs(r), o.pairs(x0_of(d), cells=True))
+    assert np.array_equal(fg[system.offsets[1]], -fg[system.offsets[1] + 1])  # the lone pair: action = reaction
+    system.step_batch(10)
+    xg = system.get_state()[0].cpu().numpy()
+    for r, d in enumerate(reps):
+        a, b = system.offsets[r], system.offsets[r + 1]
+        _, x, _, _ = oracle_traj(d, 10)
+        dx = np.abs(xg[a:b] - x).max()
+        say(f"  replica {r}: 10-step max dx {dx:.2e}")
+        assert dx <= X_TOL
+    assert np.all(system.observables()[:, 5] == 0)
