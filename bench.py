@@ -34,7 +34,7 @@ FLOP_PER_PAIR = 35          # algorithmic flops per unique in-cutoff pair (force
 PEAK_FP32_TFLOPS = 157.3    # MI355X FP32 vector peak
 # HBM bytes per launch of the force kernel on this workload, from rocprofv3
 # FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 (factors from a 256 MiB device copy);
-# see profiles/counters_c3_64x12560.md.  Set to None when the kernel changes.
+# see profiles/counters_64x12560.md.  Set to None when the kernel changes.
 FORCE_TRAFFIC_BYTES = (614344 * 2.000 + 19200 * 1.000) * 1024
 
 
@@ -70,9 +70,9 @@ def main():
                     help="seconds of oracle work per process for the CPU baseline")
     ap.add_argument("--cpu-procs", type=int, default=0,
                     help="oracle processes for the CPU baseline (0: one per core, at most 16)")
-    ap.add_argument("--workload", choices=("c3", "c4", "c5"), default="c3",
-                    help="c3: 64 replicas of the 12,560-atom system; c4: 32 replicas of "
-                         "5,000-40,000 atoms with cutoffs 0.9 / 1.2 nm; c5: 16 replicas of the "
+    ap.add_argument("--workload", choices=("batch", "uneven", "derivative"), default="batch",
+                    help="batch: 64 replicas of the 12,560-atom system; uneven: 32 replicas of "
+                         "5,000-40,000 atoms with cutoffs 0.9 / 1.2 nm; derivative: 16 replicas of the "
                          "12,560-atom system carrying dPhi/d(bias_k, ramp_rate)")
     ap.add_argument("--equilibrate", type=int, default=6000, metavar="MD_STEPS",
                     help="untimed MD steps without bias before the trials start: the synthetic "
@@ -104,21 +104,21 @@ def main():
 
     B = args.md_per_step
     t0 = time.time()
-    if args.workload == "c3":
-        base = synth.c2_single()
-        reps = synth.c3_batch(args.replicas, base=base,
+    if args.workload == "batch":
+        base = synth.solvated_chain_12560()
+        reps = synth.trial_batch(args.replicas, base=base,
                               n_steps=B * (args.steps + args.warmup + args.timing_steps))
         workload = ("64 trial paths x 12,560 atoms (560-atom solute + 4,000 flexible waters), "
                     "5.0 nm box, rc 1.0 nm, dt 1 fs, contact-map bias, graph-captured batch")
-    elif args.workload == "c5":
-        base = synth.c2_single()
-        reps = synth.c5_adjoint(16, base=base)
+    elif args.workload == "derivative":
+        base = synth.solvated_chain_12560()
+        reps = synth.derivative_batch(16, base=base)
         workload = ("16 trial paths x 12,560 atoms with forward tangents of dPhi/d(bias_k, ramp_rate), "
                     "2,000-step bias ramp, rc 1.0 nm, dt 1 fs, contact-map bias, graph-captured batch")
     else:
         # replicas are independent: built by forked workers before the GPU is touched
         workers = max(1, min(16, os.cpu_count() or 1))
-        reps = synth.c4_uneven(workers=workers, progress=lambda r, n: print(
+        reps = synth.uneven_batch(workers=workers, progress=lambda r, n: print(
             f"# replica {r}: {n} atoms ({time.time() - t0:.0f} s)", file=sys.stderr, flush=True))
         base = reps[0]
         workload = ("32 trial paths of 5,000-40,000 atoms (log-uniform; 280-560-atom solute, "
@@ -165,7 +165,7 @@ def main():
         del eq
         print(f"# equilibrated: T = {np.mean(temp):.1f} K (min {np.min(temp):.1f}, max {np.max(temp):.1f})",
               file=sys.stderr, flush=True)
-    tangent = args.workload == "c5"
+    tangent = args.workload == "derivative"
     system = vp.System(reps, steps_per_graph=B, force_shape=args.force_shape,
                        autotune=not args.no_autotune, nstlist=args.nstlist, skin=args.skin,
                        tangent=tangent)
@@ -262,7 +262,7 @@ def main():
             "workload": workload + (f"; trials start at t = 0 from a {args.equilibrate}-step unbiased "
                                     "equilibration of each replica" if args.equilibrate > 0 else ""),
             "replicas": len(reps),
-            "atoms_per_replica": (int(base["n_atoms"]) if args.workload != "c4"
+            "atoms_per_replica": (int(base["n_atoms"]) if args.workload != "uneven"
                                   else [int(d["n_atoms"]) for d in reps]),
             "md_steps_per_bench_step": B, "global_batch": n_atoms, "parallelism": "replicas",
         },
@@ -279,7 +279,7 @@ def main():
         "roofline": {
             "bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32_TFLOPS,
-            "traffic": (FORCE_TRAFFIC_BYTES if args.workload == "c3" and args.replicas == 64
+            "traffic": (FORCE_TRAFFIC_BYTES if args.workload == "batch" and args.replicas == 64
                         else None),
             "kernel": "k_forces (nonbonded LJ + reaction field)",
             "flop_per_unit": FLOP_PER_PAIR, "units_per_launch": pairs_total,

@@ -334,14 +334,14 @@ def with_seed(desc, seed):
 
 
 # Workload recipes -----------------------------------------------------------
-def c1_small(seed=WORKLOAD_SEED):
+def small_chain_system(seed=WORKLOAD_SEED):
     """12-bead chain + 500 waters, 2.5 nm box, rc 0.9, dt 0.5 fs, Rg bias."""
     return make_system(n_solute=12, n_water=500, box=2.5, r_cut=0.9, dt=0.0005,
                        seed=seed, bias=BIAS_RG, branching=False, init_radius=1.0,
                        n_steps_for_ramp=2000)
 
 
-def c2_single(seed=WORKLOAD_SEED, bias=BIAS_CONTACT):
+def solvated_chain_12560(seed=WORKLOAD_SEED, bias=BIAS_CONTACT):
     """560-atom solute + 4000 waters (12,560 atoms), 5.0 nm box, rc 1.0,
     dt 1 fs, contact-map bias toward a seeded target map."""
     return make_system(n_solute=560, n_water=4000, box=5.0, r_cut=1.0, dt=0.001,
@@ -349,11 +349,11 @@ def c2_single(seed=WORKLOAD_SEED, bias=BIAS_CONTACT):
                        n_steps_for_ramp=20000)
 
 
-def c3_batch(n_rep=64, seed=WORKLOAD_SEED, base=None, n_steps=10000):
-    """n_rep trial paths of the C2 system: same start, independent Philox keys
+def trial_batch(n_rep=64, seed=WORKLOAD_SEED, base=None, n_steps=10000):
+    """n_rep trial paths of the 12,560-atom system: same start, independent Philox keys
     (seed + r + 1), so independent Maxwell velocities and noise."""
     if base is None:
-        base = c2_single(seed)
+        base = solvated_chain_12560(seed)
     base = dict(base)
     base["ramp_rate"] = 1.0 / (n_steps * base["dt"])
     return [with_seed(base, seed + r + 1) for r in range(n_rep)]
@@ -363,7 +363,7 @@ def _make_system_kw(kw):
     return make_system(**kw)
 
 
-def c4_uneven(n_rep=32, seed=WORKLOAD_SEED, only=None, workers=1, progress=None):
+def uneven_batch(n_rep=32, seed=WORKLOAD_SEED, only=None, workers=1, progress=None):
     """Replicas with atom counts log-uniform in [5000, 40000], solute 280-560
     atoms, water at 33.4 /nm^3, cutoffs 0.9 or 1.2 nm.  The initial solute is
     grown at 9 atoms/nm^3 (in the smaller boxes its sphere is wider than the
@@ -406,10 +406,10 @@ def c4_uneven(n_rep=32, seed=WORKLOAD_SEED, only=None, workers=1, progress=None)
     return reps
 
 
-def c5_adjoint(n_rep=16, seed=WORKLOAD_SEED, base=None):
-    """16 trial paths of the C2 system for the functional gradient."""
+def derivative_batch(n_rep=16, seed=WORKLOAD_SEED, base=None):
+    """16 trial paths of the 12,560-atom system for the functional gradient."""
     if base is None:
-        base = c2_single(seed)
+        base = solvated_chain_12560(seed)
     base = dict(base)
     base["ramp_rate"] = 1.0 / (2000 * base["dt"])
     return [with_seed(base, seed + r + 1) for r in range(n_rep)]

@@ -83,8 +83,8 @@ def gpu_forces(system, x_list, t=0.0):
 
 
 @pytest.fixture(scope="module")
-def c2():
-    return synth.c2_single()
+def solvated():
+    return synth.solvated_chain_12560()
 
 
 # ------------------------------------------------------------------ noise
@@ -100,31 +100,31 @@ def test_philox_normals_match_oracle():
 
 
 # ------------------------------------------------------------------ pair sets
-@pytest.mark.parametrize("name", ["tiny", "c1", "lj_small_box"])
+@pytest.mark.parametrize("name", ["tiny", "small", "lj_small_box"])
 def test_pair_set_exact(name):
     say("pairs:", name)
-    d = {"tiny": lambda: synth.tiny(seed=2), "c1": synth.c1_small,
+    d = {"tiny": lambda: synth.tiny(seed=2), "small": synth.small_chain_system,
          "lj_small_box": lambda: synth.lj_box(seed=9, n=300, box=2.05, r_cut=1.0)}[name]()
     system = vp.System([d], skin=0.02 if name == "lj_small_box" else 0.0)
     assert system.observables()[0][5] == 0  # no list overflow
     assert_same_pairs(system.debug_pairs(0), O.Oracle(d).pairs(x0_of(d), cells=True))
 
 
-def test_pair_set_exact_c2(c2):
-    say("pairs: c2")
-    system = vp.System([c2])
+def test_pair_set_exact_solvated(solvated):
+    say("pairs: solvated")
+    system = vp.System([solvated])
     assert system.observables()[0][5] == 0  # no list overflow
-    want = O.Oracle(c2).pairs(x0_of(c2), cells=True)
+    want = O.Oracle(solvated).pairs(x0_of(solvated), cells=True)
     assert len(want) > 2_000_000
     assert_same_pairs(system.debug_pairs(0), want)
 
 
 # ------------------------------------------------------------------ forces
-@pytest.mark.parametrize("name", ["tiny", "c1", "tiny_rg", "no_solute"])
+@pytest.mark.parametrize("name", ["tiny", "small", "tiny_rg", "no_solute"])
 def test_forces_small(name):
     say("forces:", name)
     d = {"tiny": lambda: dict(synth.tiny(seed=4), bias_k=0.05),
-         "c1": synth.c1_small,
+         "small": synth.small_chain_system,
          "tiny_rg": lambda: synth.tiny(seed=5, bias=synth.BIAS_RG),
          "no_solute": lambda: synth.lj_box(seed=3, n=500, box=2.6, r_cut=1.0)}[name]()
     system = vp.System([d])
@@ -143,12 +143,12 @@ def test_forces_small(name):
         assert abs(e[0, col] - terms[k]) <= 2e-5 * scale + 1e-9, (k, e[0, col], terms[k])
 
 
-def test_forces_c2_frame(c2):
-    say("forces: c2 frame")
-    system = vp.System([c2])
-    x = f32(c2["x0"])
+def test_forces_c2_frame(solvated):
+    say("forces: solvated frame")
+    system = vp.System([solvated])
+    x = f32(solvated["x0"])
     fg, e = gpu_forces(system, [x], 0.0)
-    o = O.Oracle(c2)
+    o = O.Oracle(solvated)
     st = o.init(x)
     fo, _, terms = o.forces(x, 0.0, st)
     rel, mx = force_errors(fg, fo)
@@ -157,10 +157,10 @@ def test_forces_c2_frame(c2):
     assert abs(e[0, 5] - terms["z"]) <= 1e-5 * terms["z"]
 
 
-def test_forces_bias_midramp(c2):
+def test_forces_bias_midramp(solvated):
     """Contact-map bias at t with z_ref between z(X_0) and the target."""
-    say("forces: c2 bias mid-ramp")
-    d = dict(c2, bias_k=0.05, ramp_rate=20.0)
+    say("forces: solvated bias mid-ramp")
+    d = dict(solvated, bias_k=0.05, ramp_rate=20.0)
     system = vp.System([d])
     x0 = x0_of(d)
     x = f32(synth.perturbed(d, 0.01, 5)["x0"])
@@ -184,11 +184,11 @@ def oracle_traj(d, nsteps):
     return o, x, v, st
 
 
-@pytest.mark.parametrize("name,graph", [("tiny", True), ("tiny", False), ("c1", True), ("rmd", True)])
+@pytest.mark.parametrize("name,graph", [("tiny", True), ("tiny", False), ("small", True), ("rmd", True)])
 def test_ten_step_trajectory(name, graph):
     say("trajectory:", name, "graph" if graph else "direct")
     d = {"tiny": lambda: dict(synth.tiny(seed=6), bias_k=0.08, ramp_rate=30.0),
-         "c1": synth.c1_small,
+         "small": synth.small_chain_system,
          "rmd": lambda: dict(synth.tiny(seed=7, bias=synth.BIAS_RMD_CONTACT), bias_k=0.5)}[name]()
     system = vp.System([d], use_graph=graph, steps_per_graph=4)
     system.step_batch(3)
@@ -205,9 +205,9 @@ def test_ten_step_trajectory(name, graph):
     assert obs[0] == 10 and obs[5] == 0
 
 
-def test_ten_step_trajectory_c2(c2):
-    say("trajectory: c2 10 steps")
-    d = dict(c2, bias_k=0.05, ramp_rate=50.0)
+def test_ten_step_trajectory_solvated(solvated):
+    say("trajectory: solvated 10 steps")
+    d = dict(solvated, bias_k=0.05, ramp_rate=50.0)
     system = vp.System([d])
     system.step_batch(10)
     xg, _ = system.get_state()
@@ -239,7 +239,7 @@ def test_functional_constant_force_closed_form():
 def test_batch_matches_solo_runs_bitwise():
     say("batch vs solo")
     base = dict(synth.tiny(seed=11), bias_k=0.1, ramp_rate=20.0)
-    reps = [synth.with_seed(base, 100 + r) for r in range(3)] + [dict(synth.c1_small())]
+    reps = [synth.with_seed(base, 100 + r) for r in range(3)] + [dict(synth.small_chain_system())]
     batch = vp.System(reps, steps_per_graph=5)
     batch.step_batch(12)
     xb, vb = batch.get_state()
@@ -270,7 +270,7 @@ def test_run_twice_and_graph_equal_direct_bitwise():
 
 def test_heterogeneous_batch_forces():
     say("heterogeneous batch forces")
-    reps = [dict(synth.tiny(seed=21), bias_k=0.05), synth.c1_small(),
+    reps = [dict(synth.tiny(seed=21), bias_k=0.05), synth.small_chain_system(),
             synth.lj_box(seed=4, n=777, box=3.0, r_cut=1.2),
             synth.tiny(seed=22, n_solute=30, n_water=101, box=2.3, r_cut=0.95, bias=synth.BIAS_RG)]
     system = vp.System(reps)
@@ -344,11 +344,11 @@ G_REL = 1e-4  # functional gradients and their ingredients, relative to the FP64
 def _tangent_case(name):
     return {"tiny": lambda: dict(synth.tiny(seed=31), bias_k=0.08, ramp_rate=30.0),
             "tiny_rg": lambda: dict(synth.tiny(seed=32, bias=synth.BIAS_RG), ramp_rate=20.0),
-            "c1": synth.c1_small,
-            "c2": lambda: dict(synth.c2_single(), bias_k=0.05, ramp_rate=50.0)}[name]()
+            "small": synth.small_chain_system,
+            "solvated": lambda: dict(synth.solvated_chain_12560(), bias_k=0.05, ramp_rate=50.0)}[name]()
 
 
-@pytest.mark.parametrize("name", ["tiny", "tiny_rg", "c1", "c2"])
+@pytest.mark.parametrize("name", ["tiny", "tiny_rg", "small", "solvated"])
 def test_force_directional_derivative(name):
     """-H_U dx + bias terms along two random displacements against the oracle's
     dual-number derivative at the same (grid) positions."""
@@ -371,7 +371,7 @@ def test_force_directional_derivative(name):
         assert rel <= G_REL
 
 
-@pytest.mark.parametrize("name,nsteps", [("tiny", 20), ("tiny_rg", 20), ("c1", 20), ("c2", 10)])
+@pytest.mark.parametrize("name,nsteps", [("tiny", 20), ("tiny_rg", 20), ("small", 20), ("solvated", 10)])
 def test_functional_gradient(name, nsteps):
     """dPhi/d(bias_k, ramp_rate) carried by the tangents along a trajectory,
     against the oracle's dual-number run of the same trajectory."""
@@ -433,17 +433,17 @@ def test_tangent_errors():
 
 # ------------------------------------------- uneven batch (5,000-40,000 atoms, rc 0.9 / 1.2)
 @pytest.fixture(scope="module")
-def c4_subset():
+def uneven_subset():
     # three replicas of the uneven batch: 5,028 atoms rc 1.2; 5,135 rc 0.9; 10,312 rc 1.2
-    return synth.c4_uneven(only=(9, 15, 26))
+    return synth.uneven_batch(only=(9, 15, 26))
 
 
-def test_uneven_batch_forces_and_pairs(c4_subset):
-    say("uneven batch: forces and pairs", [int(d["n_atoms"]) for d in c4_subset])
-    system = vp.System(c4_subset)
-    xs = [f32(d["x0"]) for d in c4_subset]
+def test_uneven_batch_forces_and_pairs(uneven_subset):
+    say("uneven batch: forces and pairs", [int(d["n_atoms"]) for d in uneven_subset])
+    system = vp.System(uneven_subset)
+    xs = [f32(d["x0"]) for d in uneven_subset]
     fg, e = gpu_forces(system, xs, 0.0)
-    for r, d in enumerate(c4_subset):
+    for r, d in enumerate(uneven_subset):
         o = O.Oracle(d)
         st = o.init(x0_of(d))
         fo, _, _ = o.forces(xs[r], 0.0, st)
@@ -452,15 +452,15 @@ def test_uneven_batch_forces_and_pairs(c4_subset):
         say(f"  replica {r}: {d['n_atoms']} atoms rc {d['r_cut']}: rel {rel:.2e} max {mx:.2e}")
         assert rel <= F_REL and mx <= F_MAX
     # the exact pair set of the first rc 1.2 replica (trajectory lists at creation)
-    r = next(i for i, d in enumerate(c4_subset) if d["r_cut"] > 1.0)
-    assert_same_pairs(system.debug_pairs(r), O.Oracle(c4_subset[r]).pairs(x0_of(c4_subset[r]), cells=True))
+    r = next(i for i, d in enumerate(uneven_subset) if d["r_cut"] > 1.0)
+    assert_same_pairs(system.debug_pairs(r), O.Oracle(uneven_subset[r]).pairs(x0_of(uneven_subset[r]), cells=True))
     obs = system.observables()
     assert np.all(obs[:, 5] == 0)
 
 
-def test_uneven_batch_runs_and_matches_solo(c4_subset):
+def test_uneven_batch_runs_and_matches_solo(uneven_subset):
     say("uneven batch: 200 steps, batch vs solo")
-    batch = vp.System(c4_subset, steps_per_graph=20)
+    batch = vp.System(uneven_subset, steps_per_graph=20)
     batch.step_batch(200)
     obs = batch.observables()
     col = {k: i for i, k in enumerate(vp.OBS)}
@@ -472,7 +472,7 @@ def test_uneven_batch_runs_and_matches_solo(c4_subset):
     xb, _ = batch.get_state()
     xb = xb.cpu().numpy()
     r = 1
-    solo = vp.System([c4_subset[r]], steps_per_graph=20)
+    solo = vp.System([uneven_subset[r]], steps_per_graph=20)
     solo.step_batch(200)
     xs, _ = solo.get_state()
     a, b = batch.offsets[r], batch.offsets[r + 1]
@@ -486,7 +486,7 @@ def test_functional_gradient_late_in_a_2000_step_segment():
     must agree (the trajectories themselves diverge chaotically over 2,000
     steps, so only a continuation from the same state is comparable)."""
     say("functional gradient: steps 1990-2000 of a 2000-step segment")
-    reps = synth.c5_adjoint(n_rep=2)
+    reps = synth.derivative_batch(n_rep=2)
     system = vp.System(reps, tangent=True, steps_per_graph=10)
     system.step_batch(1990)
     x, v, xt, vt, pd0 = system.trajectory_state(tangents=True)
@@ -513,10 +513,10 @@ def test_functional_gradient_late_in_a_2000_step_segment():
 
 
 # ------------------------------------------------------------------ tile shapes
-def test_every_force_tile_shape_gives_the_same_bits(c4_subset):
+def test_every_force_tile_shape_gives_the_same_bits(uneven_subset):
     """The force kernel sums list chunk c of an atom into partial sum c mod 16
     whatever its tile shape, so forces and energies agree bit for bit."""
-    reps = list(c4_subset) + [synth.tiny(seed=3), synth.lj_box()]
+    reps = list(uneven_subset) + [synth.tiny(seed=3), synth.lj_box()]
     say("tile shapes: bitwise agreement", [int(d["n_atoms"]) for d in reps])
     xs = [f32(d["x0"]) for d in reps]
     ref = None
@@ -529,22 +529,22 @@ def test_every_force_tile_shape_gives_the_same_bits(c4_subset):
         assert np.array_equal(e, ref[1]), k
 
 
-def test_autotuned_uneven_batch(c4_subset):
+def test_autotuned_uneven_batch(uneven_subset):
     say("autotune: uneven batch buckets")
-    tuned = vp.System(c4_subset, autotune=True, steps_per_graph=10)
+    tuned = vp.System(uneven_subset, autotune=True, steps_per_graph=10)
     buckets, split = tuned.tile_buckets()
     for b in buckets:
         say(f"  rc {b['r_cut']} 2^{b['log2_atoms']}: {b['replicas']} replicas, {b['blocks']} blocks, "
             f"tile {b['tile']}, ms {['%.4f' % t for t in b['ms']]}")
     say("  split launches:", split)
-    keys = sorted((d["r_cut"], int(np.floor(np.log2(d["n_atoms"])))) for d in c4_subset)
+    keys = sorted((d["r_cut"], int(np.floor(np.log2(d["n_atoms"])))) for d in uneven_subset)
     assert sorted((b["r_cut"], b["log2_atoms"]) for b in buckets) == sorted(set(keys))
-    assert sum(b["replicas"] for b in buckets) == len(c4_subset)
+    assert sum(b["replicas"] for b in buckets) == len(uneven_subset)
     for b in buckets:
         assert 0 <= b["shape"] < vp.FORCE_SHAPES and all(t > 0 for t in b["ms"])
         if not split:
             assert b["shape"] == buckets[0]["shape"]
-    plain = vp.System(c4_subset, steps_per_graph=10)
+    plain = vp.System(uneven_subset, steps_per_graph=10)
     for s in (tuned, plain):
         s.step_batch(40)
     assert np.array_equal(tuned.get_state()[0].cpu().numpy(), plain.get_state()[0].cpu().numpy())
@@ -552,14 +552,14 @@ def test_autotuned_uneven_batch(c4_subset):
     assert all(b["shape"] == 0 and b["ms"] == [0.0] * vp.FORCE_SHAPES for b in b0)
 
 
-def test_default_list_parameters_per_replica(c4_subset):
+def test_default_list_parameters_per_replica(uneven_subset):
     """Default interval: the largest power of two in which a 5-sigma-fast
     lightest atom moves less than half the largest admissible skin (at most
     0.14 nm, less where the staged neighbourhood or half the box limits it);
     default skin: just enough for that interval.  Given values are taken as
     they are."""
     say("list parameters per replica")
-    reps = [synth.c2_single(), synth.c1_small(), synth.tiny(seed=3)] + list(c4_subset)
+    reps = [synth.solvated_chain_12560(), synth.small_chain_system(), synth.tiny(seed=3)] + list(uneven_subset)
     obs = vp.System(reps).observables()
     col = {k: i for i, k in enumerate(vp.OBS)}
     for r, d in enumerate(reps):
@@ -571,16 +571,16 @@ def test_default_list_parameters_per_replica(c4_subset):
         assert nst * step <= 0.49 * skin + 1e-12            # the interval fits the skin
         assert obs[r, col["stage_max"]] <= obs[r, col["stage_cap"]]
     assert abs(obs[0, col["skin"]] - 0.13) < 1e-12 and int(obs[0, col["nstlist"]]) == 8
-    assert int(obs[1, col["nstlist"]]) == 16            # C1 at 0.5 fs
+    assert int(obs[1, col["nstlist"]]) == 16            # the 1,512-atom system at 0.5 fs
     given = vp.System(reps[:1], nstlist=4, skin=0.1).observables()
     assert abs(given[0, col["skin"]] - 0.1) < 1e-12 and int(given[0, col["nstlist"]]) == 4
 
 
-def test_split_launch_plan_matches_single_launch(c4_subset):
+def test_split_launch_plan_matches_single_launch(uneven_subset):
     """Every size bucket on its own tile shape (one launch per shape over
     per-bucket block lists) gives bitwise the trajectories of the plain
     single-shape launch: each block is covered exactly once."""
-    reps = list(c4_subset) + [synth.tiny(seed=3)]
+    reps = list(uneven_subset) + [synth.tiny(seed=3)]
     say("split launch plan", [int(d["n_atoms"]) for d in reps])
     plain = vp.System(reps, steps_per_graph=10)
     split = vp.System(reps, steps_per_graph=10)
@@ -617,7 +617,7 @@ def test_forces_match_central_differences():
     E(x+h) - E(x-h) carries ~1e-4 to 1e-3 kJ/mol of noise against a
     difference of ~F 2h = 2e-2 kJ/mol: that check can only hold to a few
     times 1e-2."""
-    d = synth.c1_small()
+    d = synth.small_chain_system()
     n, ns = int(d["n_atoms"]), int(d["n_solute"])
     rng = np.random.default_rng(7)
     x0 = f32(d["x0"])

@@ -161,8 +161,8 @@ def test_pair_sets_brute_cells_and_independent_predicate(oracle_mod, L, rc, n):
     assert (0, 1) not in pb
 
 
-def test_c1_box_has_two_cells_per_side_and_matches(oracle_mod):
-    d = synth.c1_small()
+def test_small_system_box_has_two_cells_per_side_and_matches(oracle_mod):
+    d = synth.small_chain_system()
     o = oracle_mod.Oracle(d)
     x = d["x0"].astype(np.float32).astype(np.float64)
     assert int(2.5 // 0.9) == 2
