@@ -75,9 +75,10 @@ def main():
                          "5,000-40,000 atoms with cutoffs 0.9 / 1.2 nm; derivative: 16 replicas of the "
                          "12,560-atom system carrying dPhi/d(bias_k, ramp_rate)")
     ap.add_argument("--equilibrate", type=int, default=6000, metavar="MD_STEPS",
-                    help="untimed MD steps without bias before the trials start: the synthetic "
-                         "start relaxes from ~800 K to 300 K, and the trials then begin at t = 0 "
-                         "from that thermal state (0: start from the generated structures)")
+                    help="untimed MD steps without bias of each distinct system before the trials "
+                         "start: the synthetic start relaxes from ~800 K to 300 K, and the trials "
+                         "then begin at t = 0 from the relaxed structure with Maxwell velocities "
+                         "(0: start from the generated structures)")
     ap.add_argument("--nstlist", type=int, default=0,
                     help="pair-list rebuild interval (vp_options.nstlist; 0: the library default)")
     ap.add_argument("--skin", type=float, default=0.0,
@@ -147,9 +148,15 @@ def main():
               file=sys.stderr, flush=True)
     torch.cuda.set_device(0)
     if args.equilibrate > 0:
-        # thermalise every replica without bias, then start its trial from that state
+        # Thermalise each distinct system without bias (the batch and derivative
+        # workloads run one system 64 / 16 times; the uneven batch has 32), then
+        # start every trial at t = 0 from its system's equilibrated structure
+        # with fresh Maxwell velocities at kT from the trial's own seed: all
+        # trials of a system share the initial configuration and differ in noise.
         te = time.time()
-        eq = vp.System([dict(d, bias=vp.BIAS_NONE) for d in reps], steps_per_graph=B,
+        distinct = list(range(len(reps))) if args.workload == "uneven" else [0]
+        src = (lambda r: r) if args.workload == "uneven" else (lambda r: 0)
+        eq = vp.System([dict(reps[i], bias=vp.BIAS_NONE) for i in distinct], steps_per_graph=B,
                        nstlist=args.nstlist, skin=args.skin)
         for k in range(0, args.equilibrate, 1000):
             eq.step_batch(min(1000, args.equilibrate - k))
@@ -158,13 +165,13 @@ def main():
                   f"({time.time() - te:.1f} s)", file=sys.stderr, flush=True)
         obs = eq.observables()
         ke = obs[:, list(vp.OBS).index("ke")]
-        temp = [2.0 * ke[r] / (3.0 * int(d["n_atoms"]) * 0.0083144626) for r, d in enumerate(reps)]
-        xe, ve = (t.cpu().numpy().astype(np.float64) for t in eq.get_state())
-        reps = [dict(d, x0=xe[eq.offsets[r]:eq.offsets[r + 1]].copy(),
-                     v0=ve[eq.offsets[r]:eq.offsets[r + 1]].copy()) for r, d in enumerate(reps)]
+        temp = [2.0 * ke[k] / (3.0 * int(reps[i]["n_atoms"]) * 0.0083144626) for k, i in enumerate(distinct)]
+        xe = eq.get_state()[0].cpu().numpy().astype(np.float64)
+        reps = [dict(d, x0=xe[eq.offsets[src(r)]:eq.offsets[src(r) + 1]].copy(), v0=None)
+                for r, d in enumerate(reps)]
         del eq
-        print(f"# equilibrated: T = {np.mean(temp):.1f} K (min {np.min(temp):.1f}, max {np.max(temp):.1f})",
-              file=sys.stderr, flush=True)
+        print(f"# equilibrated {len(distinct)} system(s): T = {np.mean(temp):.1f} K "
+              f"(min {np.min(temp):.1f}, max {np.max(temp):.1f})", file=sys.stderr, flush=True)
     tangent = args.workload == "derivative"
     system = vp.System(reps, steps_per_graph=B, force_shape=args.force_shape,
                        autotune=not args.no_autotune, nstlist=args.nstlist, skin=args.skin,
@@ -259,8 +266,9 @@ def main():
         "dtype": "f32 pair arithmetic, i64 fixed-point forces, f64 functional",
         "data": "synthetic",
         "config": {
-            "workload": workload + (f"; trials start at t = 0 from a {args.equilibrate}-step unbiased "
-                                    "equilibration of each replica" if args.equilibrate > 0 else ""),
+            "workload": workload + (f"; trials start at t = 0 from the structure of a {args.equilibrate}-step "
+                                    "unbiased equilibration of their system, with Maxwell velocities "
+                                    "from their own seeds" if args.equilibrate > 0 else ""),
             "replicas": len(reps),
             "atoms_per_replica": (int(base["n_atoms"]) if args.workload != "uneven"
                                   else [int(d["n_atoms"]) for d in reps]),
