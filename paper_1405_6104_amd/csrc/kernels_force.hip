@@ -128,8 +128,6 @@ __global__ __launch_bounds__(64 * PARTS) __attribute__((amdgpu_waves_per_eu(MINW
                                                        const int32_t *__restrict__ tile_first,
                                                        const int32_t *__restrict__ blist, int nblk,
                                                        const float4 *__restrict__ types,
-                                                       const int32_t *__restrict__ bt_start,
-                                                       const BTerm *__restrict__ bterms,
                                                        int stage_slots) {
   constexpr int NT = 64 * PARTS;
   constexpr int SETS = kLogicalParts / PARTS;
@@ -400,8 +398,7 @@ __global__ __launch_bounds__(kBlk) void k_bonded(const RepInfo *__restrict__ inf
 // the force kernel's (exact cutoff).
 __global__ __launch_bounds__(kForceThreads) void k_tangent_forces(
     const RepInfo *__restrict__ info, Work W, const int32_t *__restrict__ tile_rep,
-    const int32_t *__restrict__ tile_first, int nblk, const float4 *__restrict__ types,
-    const int32_t *__restrict__ bt_start, const BTerm *__restrict__ bterms, int stage_slots,
+    const int32_t *__restrict__ tile_first, int nblk, const float4 *__restrict__ types, int stage_slots,
     int dir) {
   extern __shared__ int4 lds[];
   int4 *st = lds;                                                     // staged atoms
@@ -1159,8 +1156,7 @@ void launch_native_map(const float *xf, int ns, int min_sep, float r0, float rs,
 template <bool E, int P, int U, int M>
 static void launch_forces_t(vp_system *s, Work &W, const int32_t *blist, int nblk, hipStream_t st) {
   hipLaunchKernelGGL((k_forces<E, P, U, M>), dim3(xcd_grid(nblk)), dim3(64 * P), force_lds_bytes(s), st,
-                     s->info, W, s->tile_rep, s->tile_first, blist, nblk, s->types, s->bt_start,
-                     s->bterms, s->stage_cap_max + 1);
+                     s->info, W, s->tile_rep, s->tile_first, blist, nblk, s->types, s->stage_cap_max + 1);
 }
 
 void launch_forces_shape(vp_system *s, Work &W, bool energy, int shape, const int32_t *blist, int nblk,
@@ -1240,8 +1236,7 @@ void launch_tangent_forces(vp_system *s, Work &W, hipStream_t st) {
   const size_t lds = tangent_lds_bytes(s);
   for (int d = 0; d < 2; ++d) {
     hipLaunchKernelGGL(k_tangent_forces, dim3(xcd_grid(s->n_blocks)), dim3(kForceThreads), lds, st,
-                       s->info, W, s->tile_rep, s->tile_first, s->n_blocks, s->types, s->bt_start,
-                       s->bterms, s->stage_cap_max + 1, d);
+                       s->info, W, s->tile_rep, s->tile_first, s->n_blocks, s->types, s->stage_cap_max + 1, d);
     hipLaunchKernelGGL(k_tangent_bonded, dim3(xcd_grid(s->n_blocks)), dim3(kBlk), 0, st, s->info, W,
                        s->tile_rep, s->tile_first, s->n_blocks, s->bt_start, s->bterms, d);
   }
