@@ -323,10 +323,12 @@ __device__ __forceinline__ void bonded_term(const BTerm &T, const int4 xi, const
 constexpr int kBondBatch = 4;
 
 // Bonded forces (harmonic bonds and angles, FP64 on the exact integer
-// separations), one thread per atom of a 64-atom block, added to the
-// fixed-point forces the pair kernel stored: every atom evaluates the terms
-// it belongs to (an angle by its two ends and its vertex), so each force is
-// written by its own thread.  Separate from k_forces so that these dependent
+// separations), one thread per atom, added to the fixed-point forces the pair
+// kernel stored: every atom evaluates the terms it belongs to (an angle by its
+// two ends and its vertex), so each force is written by its own thread.
+// Threads take atoms in their original order (block b, lane l: atom 64 b + l
+// of the replica), so the term ranges and records are read coalesced and the
+// atom's slot comes from one lookup.  Separate from k_forces so that these dependent
 // gathers and long FP64 chains run over the whole chip instead of on one wave
 // of each pair block.  ENERGY: the block's bond and angle energies.
 template <bool ENERGY>
@@ -342,15 +344,14 @@ __global__ __launch_bounds__(kBlk) void k_bonded(const RepInfo *__restrict__ inf
   const int p0 = tile_first[tile] + (b % (kTile / kBlk)) * kBlk;
   if (p0 >= R.n) return;  // padding block: the pair kernel zeroed its forces and energies
   const int lane = threadIdx.x;
-  const int p = p0 + lane;
-  const int slot = R.off + p;
-  const bool active = p < R.n;
+  const int a = p0 + lane;  // the atom's index in the replica's original order
+  const bool active = a < R.n;
   double ebond = 0.0, eangle = 0.0;
   if (active) {
+    const int ga = R.uoff + a;
+    const int slot = W.inv[ga];
     const int4 xi = W.xq[slot];
     double bx = 0.0, by = 0.0, bz = 0.0;
-    const int a = W.orig[slot];
-    const int ga = R.uoff + a;
     const int t0 = bt_start[ga], t1 = bt_start[ga + 1];
     for (int t = t0; t < t1; t += kBondBatch) {
       BTerm T[kBondBatch];
@@ -372,7 +373,7 @@ __global__ __launch_bounds__(kBlk) void k_bonded(const RepInfo *__restrict__ inf
       for (int u = 0; u < kBondBatch; ++u)
         if (t + u < t1) bonded_term<ENERGY>(T[u], xi, p1[u], p2[u], bx, by, bz, ebond, eangle);
     }
-    if (bt_start[ga + 1] > bt_start[ga]) {
+    if (t1 > t0) {
       W.F[slot] += to_fix(bx);
       W.F[W.fstride + slot] += to_fix(by);
       W.F[2 * W.fstride + slot] += to_fix(bz);
@@ -522,13 +523,13 @@ __global__ __launch_bounds__(kBlk) void k_tangent_bonded(const RepInfo *__restri
   if (b < 0) return;
   const int tile = b / (kTile / kBlk);
   const RepInfo &R = info[tile_rep[tile]];
-  const int p = tile_first[tile] + (b % (kTile / kBlk)) * kBlk + (int)threadIdx.x;
-  if (p >= R.n) return;
-  const int slot = R.off + p;
+  // atoms in their original order, as in k_bonded
+  const int a = tile_first[tile] + (b % (kTile / kBlk)) * kBlk + (int)threadIdx.x;
+  if (a >= R.n) return;
+  const int slot = W.inv[R.uoff + a];
   const float4 *txp = W.tx + (size_t)dir * W.fstride;
   float4 *tfp = W.tf + (size_t)dir * W.fstride;
   double bx = 0.0, by = 0.0, bz = 0.0;
-  const int a = W.orig[slot];
   const int t0 = bt_start[R.uoff + a], t1 = bt_start[R.uoff + a + 1];
   // an atom's position and tangent as three dual numbers (one gather each)
   auto load = [&](int atom, dual1 out[3]) {
