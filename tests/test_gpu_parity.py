@@ -143,7 +143,7 @@ def test_forces_small(name):
         assert abs(e[0, col] - terms[k]) <= 2e-5 * scale + 1e-9, (k, e[0, col], terms[k])
 
 
-def test_forces_c2_frame(solvated):
+def test_forces_solvated_frame(solvated):
     say("forces: solvated frame")
     system = vp.System([solvated])
     x = f32(solvated["x0"])
