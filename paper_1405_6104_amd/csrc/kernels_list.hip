@@ -377,8 +377,9 @@ __global__ __launch_bounds__(kBlk) __attribute__((amdgpu_waves_per_eu(7))) void 
   uint64_t exm = 0;
   bool exfar = false;
   int bx0 = 0, bx1 = 0, by0 = 0, by1 = 0, bz0 = 0, bz1 = 0;
-  int sb[4][6];      // quarter boxes: x0, x1, y0, y1, z0, z1
-  bool sbact[4];     // quarter has at least one atom
+  // quarter boxes in LDS (x0, x1, y0, y1 | z0, z1, has an atom): read once per
+  // candidate batch rather than held in scalar registers across the cell loops
+  __shared__ int4 s_qb[4][2];
   {
     int ax = 0, ay = 0, az = 0;
     if (active) {
@@ -410,15 +411,9 @@ __global__ __launch_bounds__(kBlk) __attribute__((amdgpu_waves_per_eu(7))) void 
     const int qy0 = quarter_min_i(active ? ay : big), qy1 = quarter_max_i(active ? ay : -big);
     const int qz0 = quarter_min_i(active ? az : big), qz1 = quarter_max_i(active ? az : -big);
     const bool qact = __ballot(active) & (0xffffull << (lane & 48));
-#pragma unroll
-    for (int g = 0; g < 4; ++g) {
-      sb[g][0] = __builtin_amdgcn_readlane(qx0, 16 * g);
-      sb[g][1] = __builtin_amdgcn_readlane(qx1, 16 * g);
-      sb[g][2] = __builtin_amdgcn_readlane(qy0, 16 * g);
-      sb[g][3] = __builtin_amdgcn_readlane(qy1, 16 * g);
-      sb[g][4] = __builtin_amdgcn_readlane(qz0, 16 * g);
-      sb[g][5] = __builtin_amdgcn_readlane(qz1, 16 * g);
-      sbact[g] = __builtin_amdgcn_readlane((int)qact, 16 * g) != 0;
+    if ((lane & 15) == 0) {
+      s_qb[lane >> 4][0] = make_int4(qx0, qx1, qy0, qy1);
+      s_qb[lane >> 4][1] = make_int4(qz0, qz1, qact ? 1 : 0, 0);
     }
   }
   const bool anyfar = __ballot(exfar) != 0ull;
@@ -519,10 +514,11 @@ __global__ __launch_bounds__(kBlk) __attribute__((amdgpu_waves_per_eu(7))) void 
                 // never exceeds an atom distance, also after rounding
 #pragma unroll
                 for (int g = 0; g < 4; ++g) {
-                  const float gxq = (float)max(0, max(sb[g][0] - px, px - sb[g][1]));
-                  const float gyq = (float)max(0, max(sb[g][2] - py, py - sb[g][3]));
-                  const float gzq = (float)max(0, max(sb[g][4] - pz, pz - sb[g][5]));
-                  keep = keep || (sbact[g] && qr2(gxq, gyq, gzq) < rl2);
+                  const int4 q0 = s_qb[g][0], q1 = s_qb[g][1];
+                  const float gxq = (float)max(0, max(q0.x - px, px - q0.y));
+                  const float gyq = (float)max(0, max(q0.z - py, py - q0.w));
+                  const float gzq = (float)max(0, max(q1.x - pz, pz - q1.y));
+                  keep = keep || (q1.z != 0 && qr2(gxq, gyq, gzq) < rl2);
                 }
                 const int sx = six - unpack_wrap(jw.y, 0), sy = siy - unpack_wrap(jw.y, 1),
                           sz = siz - unpack_wrap(jw.y, 2);
