@@ -297,22 +297,22 @@ __device__ __forceinline__ void bonded_term(const BTerm &T, const int4 xi, const
                  w2 = (double)(pb.z - pc.z) * kInvQ;
     const double uu = u0 * u0 + u1 * u1 + u2 * u2, ww = w0 * w0 + w1 * w1 + w2 * w2;
     const double uw = u0 * w0 + u1 * w1 + u2 * w2;
-    const double nn = sqrt(uu * ww);
-    double cs = uw / nn;
+    // three reciprocals instead of a division per force component
+    const double inn = 1.0 / sqrt(uu * ww), iuu = 1.0 / uu, iww = 1.0 / ww;
+    double cs = uw * inn;
     cs = cs > 1.0 ? 1.0 : (cs < -1.0 ? -1.0 : cs);
     const double th = acos(cs);
     double sn = sqrt(1.0 - cs * cs);
     sn = sn < 1e-12 ? 1e-12 : sn;
     const double dv = T.k * (th - T.r0) / sn;
-    if (T.kind == 1) {
-      bx += dv * (w0 / nn - cs * u0 / uu);
-      by += dv * (w1 / nn - cs * u1 / uu);
-      bz += dv * (w2 / nn - cs * u2 / uu);
-    } else {
-      bx -= dv * (w0 / nn - cs * u0 / uu + u0 / nn - cs * w0 / ww);
-      by -= dv * (w1 / nn - cs * u1 / uu + u1 / nn - cs * w1 / ww);
-      bz -= dv * (w2 / nn - cs * u2 / uu + u2 / nn - cs * w2 / ww);
-    }
+    // gradient of theta at the end a (ga) and at the end b (gb); the vertex
+    // takes -(ga + gb); a select rather than a branch keeps the wave together
+    const double ga0 = w0 * inn - cs * u0 * iuu, ga1 = w1 * inn - cs * u1 * iuu, ga2 = w2 * inn - cs * u2 * iuu;
+    const double gb0 = u0 * inn - cs * w0 * iww, gb1 = u1 * inn - cs * w1 * iww, gb2 = u2 * inn - cs * w2 * iww;
+    const bool end = T.kind == 1;
+    bx += dv * (end ? ga0 : -(ga0 + gb0));
+    by += dv * (end ? ga1 : -(ga1 + gb1));
+    bz += dv * (end ? ga2 : -(ga2 + gb2));
     if (ENERGY) eangle += (0.5 / 3.0) * T.k * (th - T.r0) * (th - T.r0);  // owned by 3 atoms
   }
 }
