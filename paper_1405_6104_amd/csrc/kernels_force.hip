@@ -565,23 +565,23 @@ __global__ __launch_bounds__(kBlk) void k_tangent_bonded(const RepInfo *__restri
       const dual1 uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
       const dual1 vv = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
       const dual1 uv = u[0] * v[0] + u[1] * v[1] + u[2] * v[2];
-      const dual1 nn = dsqrt(uu * vv);
-      dual1 cs = uv / nn;
+      // reciprocals formed once (dual divisions cost two FP64 divisions each)
+      const dual1 one = {1.0, 0.0};
+      const dual1 inn = one / dsqrt(uu * vv), iuu = one / uu, ivv = one / vv;
+      dual1 cs = uv * inn;
       if (cs.v > 1.0) cs = {1.0, 0.0};
       if (cs.v < -1.0) cs = {-1.0, 0.0};
       const double snv = sqrt(1.0 - cs.v * cs.v);
       const dual1 sn = snv > 1e-12 ? dsqrt(dual1{1.0, 0.0} - cs * cs) : dual1{1e-12, 0.0};
       const dual1 th = {acos(cs.v), -cs.d / (snv > 1e-12 ? snv : 1e-12)};
       const dual1 dv = (T.k * (th - dual1{T.r0, 0.0})) / sn;
+      // end a: dv e1; vertex: -dv (e1 + e2) (a select, so the wave stays together)
       double f[3];
       for (int k = 0; k < 3; ++k) {
-        const dual1 e1 = v[k] / nn - (cs * u[k]) / uu;
-        if (T.kind == 1) {
-          f[k] = (dv * e1).d;
-        } else {
-          const dual1 e2 = u[k] / nn - (cs * v[k]) / vv;
-          f[k] = -(dv * (e1 + e2)).d;
-        }
+        const dual1 e1 = v[k] * inn - (cs * u[k]) * iuu;
+        const dual1 e2 = u[k] * inn - (cs * v[k]) * ivv;
+        const double fe = (dv * e1).d, fv = -(dv * (e1 + e2)).d;
+        f[k] = T.kind == 1 ? fe : fv;
       }
       bx += f[0];
       by += f[1];
