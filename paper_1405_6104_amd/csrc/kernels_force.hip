@@ -637,6 +637,16 @@ __global__ __launch_bounds__(kCvTile) void k_cv_pairs(const RepInfo *__restrict_
     const float dx = (float)(xj.x - xi.x) * kInvQf, dy = (float)(xj.y - xi.y) * kInvQf,
                 dz = (float)(xj.z - xi.z) * kInvQf;
     const float r2 = qr2(dx, dy, dz);
+    const bool valid = row && abs(j - i) > msep;
+    const float cref = cf[(int64_t)k * ns];
+    if (__ballot(row && r2 < rc2) == 0ull) {
+      // every row of the tile is beyond the switch: C~ and its derivative are
+      // exactly 0 there, so the gradient gains nothing and z only the
+      // reference term (the same bits as the full evaluation below)
+      const float diff = 0.0f - cref;
+      if (valid && j > i) zacc += (double)diff * (double)diff;
+      continue;
+    }
     const float rinv = __builtin_amdgcn_rsqf(r2);
     // C(u) and dC/du
     const float u = r2 * ir02, u2 = u * u;
@@ -659,8 +669,7 @@ __global__ __launch_bounds__(kCvTile) void k_cv_pairs(const RepInfo *__restrict_
     // C~ and (dC~/dr)/r
     const float ct = c * sw;
     const float dct_r = 2.0f * ir02 * dcdu * sw + c * dsw * rinv;
-    const bool valid = row && abs(j - i) > msep;
-    const float diff = ct - cf[(int64_t)k * ns];
+    const float diff = ct - cref;
     const float coef = valid ? 2.0f * diff * dct_r : 0.0f;
     gx = __builtin_fmaf(-coef, dx, gx);
     gy = __builtin_fmaf(-coef, dy, gy);
