@@ -316,6 +316,7 @@ int64_t ora_pairs(const ora_ctx *c, const double *x, int32_t use_cells, int32_t 
 typedef struct {
   double *f;
   double e_lj, e_rf;
+  double vir[9]; /* sum over pairs of d_a F_b, d = x_j - x_i, F the force on j */
 } nb_acc;
 
 static void nb_visit(ora_ctx *c, int i, int j, const double *d, void *arg) {
@@ -343,9 +344,15 @@ static void nb_visit(ora_ctx *c, int i, int j, const double *d, void *arg) {
     acc->f[3 * i + a] -= fscal * d[a];
     acc->f[3 * j + a] += fscal * d[a];
   }
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) acc->vir[3 * a + b] += d[a] * (fscal * d[b]);
 }
 
-static void bonded(const ora_ctx *c, const double *x, double *f, double *e_bond, double *e_angle) {
+/* Bonds and angles; vir accumulates, per term, the separation of each moved
+ * atom from the term's reference atom (i for a bond, the vertex for an angle)
+ * times the force on it. */
+static void bonded(const ora_ctx *c, const double *x, double *f, double *e_bond, double *e_angle,
+                   double *vir) {
   const ora_sys *s = &c->s;
   double eb = 0.0, ea = 0.0;
   for (int b = 0; b < s->n_bonds; ++b) {
@@ -363,6 +370,8 @@ static void bonded(const ora_ctx *c, const double *x, double *f, double *e_bond,
       f[3 * i + a] += g * d[a];
       f[3 * j + a] -= g * d[a];
     }
+    for (int a = 0; a < 3; ++a)
+      for (int e = 0; e < 3; ++e) vir[3 * a + e] += d[a] * (-g * d[e]);
   }
   for (int k = 0; k < s->n_angles; ++k) {
     int ia = s->angles[3 * k], ic = s->angles[3 * k + 1], ib = s->angles[3 * k + 2];
@@ -384,6 +393,7 @@ static void bonded(const ora_ctx *c, const double *x, double *f, double *e_bond,
     double dth = th - s->angle_theta0[k];
     ea += 0.5 * s->angle_k[k] * dth * dth;
     double dv = s->angle_k[k] * dth; /* dV/dtheta */
+    double fu[3], fw[3];
     /* dtheta/du = -(w/(|u||w|) - cos u/|u|^2)/sin */
     for (int a = 0; a < 3; ++a) {
       double dcu = w[a] / (nu * nw) - cs * u[a] / uu;
@@ -393,7 +403,11 @@ static void bonded(const ora_ctx *c, const double *x, double *f, double *e_bond,
       f[3 * ia + a] += fa;
       f[3 * ib + a] += fb;
       f[3 * ic + a] -= fa + fb;
+      fu[a] = fa;
+      fw[a] = fb;
     }
+    for (int a = 0; a < 3; ++a)
+      for (int e = 0; e < 3; ++e) vir[3 * a + e] += u[a] * fu[e] + w[a] * fw[e];
   }
   *e_bond = eb;
   *e_angle = ea;
@@ -474,7 +488,13 @@ static double bias_force(ora_ctx *c, const double *x, double t, double z0, doubl
   memset(fb, 0, sizeof(double) * 3 * (size_t)s->n_atoms);
   double z = 0.0, zr = 0.0, ub = 0.0;
   if (s->bias == ORA_BIAS_CONST && s->const_force) {
-    for (int i = 0; i < 3 * ns; ++i) fb[i] = s->const_force[i];
+    /* constant force F0 on each solute atom: the gradient of -sum_i F0_i . x_i
+     * (z is taken as that projection, so U_b = -z) */
+    for (int i = 0; i < 3 * ns; ++i) {
+      fb[i] = s->const_force[i];
+      z += s->const_force[i] * x[i];
+    }
+    ub = -z;
   } else if (s->bias == ORA_BIAS_RG || s->bias == ORA_BIAS_CONTACT) {
     z = ora_cv(c, x, c->grad_tmp);
     zr = z_ref(s, z0, t);
@@ -515,17 +535,19 @@ int ora_forces(ora_ctx *c, const double *x, double t, const ora_state *st, int32
   double tl[ORA_N_TERMS];
   memset(tl, 0, sizeof(tl));
   memset(f, 0, sizeof(double) * 3 * (size_t)n);
-  nb_acc acc = {f, 0.0, 0.0};
+  nb_acc acc = {f, 0.0, 0.0, {0.0}};
   if (use_cells)
     pairs_cells(c, x, NULL, 0, nb_visit, &acc);
   else
     pairs_brute(c, x, NULL, 0, nb_visit, &acc);
   tl[ORA_E_LJ] = acc.e_lj;
   tl[ORA_E_RF] = acc.e_rf;
-  bonded(c, x, f, &tl[ORA_E_BOND], &tl[ORA_E_ANGLE]);
+  for (int k = 0; k < 9; ++k) tl[ORA_VIR + k] = acc.vir[k];
+  bonded(c, x, f, &tl[ORA_E_BOND], &tl[ORA_E_ANGLE], &tl[ORA_VIR]);
   double z0 = st ? st->z0 : 0.0;
   double zm = st ? st->z_m : DBL_MAX;
   bias_force(c, x, t, z0, zm, c->fb_tmp, tl);
+  tl[ORA_U_TOTAL] = tl[ORA_E_LJ] + tl[ORA_E_RF] + tl[ORA_E_BOND] + tl[ORA_E_ANGLE] + tl[ORA_E_BIAS];
   int bad = 0;
   for (int i = 0; i < 3 * n; ++i) {
     f[i] += c->fb_tmp[i];
@@ -620,11 +642,116 @@ double ora_phi(const ora_ctx *c, const ora_state *st) {
   return (st->phi_acc - 0.5 * st->s_last) * c->s.dt / (4.0 * c->s.kT);
 }
 
-/* Product reached: |z(X_T) - z_target| <= reach_tol (stands in for the
- * RMSD < 2 A folding criterion of the main text). */
-int ora_reached(const ora_ctx *c, const ora_state *st) {
+/* ------------------------------------------------------------------------ */
+/* RMSD to the product after the optimal rigid superposition (the folding     */
+/* criterion of the main text: final RMSD to the native structure).          */
+/* Both structures are centred; the rotation that brings the centred X onto  */
+/* the centred X_f is found by the quaternion method of Horn (J. Opt. Soc.   */
+/* Am. A 4, 629 (1987)): the unit quaternion is the eigenvector of the       */
+/* largest eigenvalue of a symmetric 4x4 matrix built from the correlation    */
+/* matrix S_ab = sum_i x_ia y_ib.  The rotation is then applied and the mean  */
+/* squared distance summed directly.                                          */
+/* ------------------------------------------------------------------------ */
+/* cyclic Jacobi rotations of a symmetric n x n matrix (n <= 4): a becomes
+ * diagonal (its eigenvalues), v collects the eigenvectors as columns */
+static void jacobi_eigen(int n, double a[4][4], double v[4][4]) {
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) v[i][j] = (i == j) ? 1.0 : 0.0;
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0.0, scale = 0.0;
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) {
+        if (i != j) off += a[i][j] * a[i][j];
+        scale += a[i][j] * a[i][j];
+      }
+    if (off <= 1e-32 * scale || off == 0.0) break;
+    for (int p = 0; p < n; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        if (a[p][q] == 0.0) continue;
+        /* rotation angle that zeroes a[p][q] */
+        double theta = (a[q][q] - a[p][p]) / (2.0 * a[p][q]);
+        double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+        double cs = 1.0 / sqrt(t * t + 1.0), sn = t * cs;
+        for (int k = 0; k < n; ++k) { /* columns p, q */
+          double akp = a[k][p], akq = a[k][q];
+          a[k][p] = cs * akp - sn * akq;
+          a[k][q] = sn * akp + cs * akq;
+        }
+        for (int k = 0; k < n; ++k) { /* rows p, q */
+          double apk = a[p][k], aqk = a[q][k];
+          a[p][k] = cs * apk - sn * aqk;
+          a[q][k] = sn * apk + cs * aqk;
+        }
+        for (int k = 0; k < n; ++k) {
+          double vkp = v[k][p], vkq = v[k][q];
+          v[k][p] = cs * vkp - sn * vkq;
+          v[k][q] = sn * vkp + cs * vkq;
+        }
+      }
+  }
+}
+
+double ora_rmsd(const ora_ctx *c, const double *x) {
+  const ora_sys *s = &c->s;
+  int ns = s->n_solute;
+  if (!s->x_final || ns <= 0) return NAN;
+  double cx[3] = {0, 0, 0}, cy[3] = {0, 0, 0};
+  for (int i = 0; i < ns; ++i)
+    for (int a = 0; a < 3; ++a) {
+      cx[a] += x[3 * i + a];
+      cy[a] += s->x_final[3 * i + a];
+    }
+  for (int a = 0; a < 3; ++a) {
+    cx[a] /= ns;
+    cy[a] /= ns;
+  }
+  double S[3][3] = {{0}};
+  for (int i = 0; i < ns; ++i)
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b)
+        S[a][b] += (x[3 * i + a] - cx[a]) * (s->x_final[3 * i + b] - cy[b]);
+  double N[4][4] = {
+      {S[0][0] + S[1][1] + S[2][2], S[1][2] - S[2][1], S[2][0] - S[0][2], S[0][1] - S[1][0]},
+      {S[1][2] - S[2][1], S[0][0] - S[1][1] - S[2][2], S[0][1] + S[1][0], S[2][0] + S[0][2]},
+      {S[2][0] - S[0][2], S[0][1] + S[1][0], -S[0][0] + S[1][1] - S[2][2], S[1][2] + S[2][1]},
+      {S[0][1] - S[1][0], S[2][0] + S[0][2], S[1][2] + S[2][1], -S[0][0] - S[1][1] + S[2][2]}};
+  double V[4][4];
+  jacobi_eigen(4, N, V);
+  int m = 0;
+  for (int k = 1; k < 4; ++k)
+    if (N[k][k] > N[m][m]) m = k;
+  double q0 = V[0][m], q1 = V[1][m], q2 = V[2][m], q3 = V[3][m];
+  double qn = sqrt(q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3);
+  q0 /= qn; q1 /= qn; q2 /= qn; q3 /= qn;
+  double R[3][3] = {
+      {q0 * q0 + q1 * q1 - q2 * q2 - q3 * q3, 2.0 * (q1 * q2 - q0 * q3), 2.0 * (q1 * q3 + q0 * q2)},
+      {2.0 * (q1 * q2 + q0 * q3), q0 * q0 - q1 * q1 + q2 * q2 - q3 * q3, 2.0 * (q2 * q3 - q0 * q1)},
+      {2.0 * (q1 * q3 - q0 * q2), 2.0 * (q2 * q3 + q0 * q1), q0 * q0 - q1 * q1 - q2 * q2 + q3 * q3}};
+  double acc = 0.0;
+  for (int i = 0; i < ns; ++i) {
+    double p[3];
+    for (int a = 0; a < 3; ++a) p[a] = x[3 * i + a] - cx[a];
+    for (int a = 0; a < 3; ++a) {
+      double r = R[a][0] * p[0] + R[a][1] * p[1] + R[a][2] * p[2];
+      double d = r - (s->x_final[3 * i + a] - cy[a]);
+      acc += d * d;
+    }
+  }
+  return sqrt(acc / ns);
+}
+
+/* Product reached: a stable trajectory with |z(X_T) - z_target| <= reach_tol
+ * and, when reach_rmsd is finite, an RMSD to X_f of at most reach_rmsd (the
+ * folding criterion of the main text, RMSD < 2 A). */
+int ora_reached(const ora_ctx *c, const ora_state *st, const double *x) {
   if (st->status) return 0;
-  return fabs(st->z_last - c->s.z_target) <= c->s.reach_tol;
+  if (!(fabs(st->z_last - c->s.z_target) <= c->s.reach_tol)) return 0;
+  if (isfinite(c->s.reach_rmsd)) {
+    if (!x) return 0;
+    double r = ora_rmsd(c, x);
+    if (!(r <= c->s.reach_rmsd)) return 0;
+  }
+  return 1;
 }
 
 /* Variational selection (Eq. VMDcondition and the folding-event criterion):

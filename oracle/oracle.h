@@ -46,6 +46,7 @@ typedef struct {
   double reach_tol;
   uint64_t seed;
   const double *const_force; /* [n_solute][3] for ORA_BIAS_CONST */
+  double reach_rmsd;         /* nm: RMSD to X_f after optimal superposition; +inf = not used */
 } ora_sys;
 
 enum { ORA_BIAS_NONE = 0, ORA_BIAS_CONST = 1, ORA_BIAS_RG = 2, ORA_BIAS_CONTACT = 3,
@@ -63,9 +64,14 @@ typedef struct {
   int32_t pad;
 } ora_state;
 
-/* energies/diagnostics of one force evaluation */
+/* energies/diagnostics of one force evaluation: the four terms of U(X,Y),
+ * the bias energy, z, z_ref, S = sum_i |F_i^bias|^2/(gamma_i m_i), the total
+ * U + U_bias, and the virial W_ab = sum over the pair and bonded terms of U of
+ * r_a F_b (row-major, a, b in x, y, z; r the separation vector of a term's
+ * atoms from a reference atom of the term, F the force on the displaced atom;
+ * the bias is an external force and takes no part) */
 enum { ORA_E_LJ = 0, ORA_E_RF, ORA_E_BOND, ORA_E_ANGLE, ORA_E_BIAS, ORA_Z, ORA_ZREF, ORA_S,
-       ORA_N_TERMS };
+       ORA_U_TOTAL, ORA_VIR, ORA_N_TERMS = ORA_VIR + 9 };
 
 typedef struct ora_ctx ora_ctx;
 
@@ -86,7 +92,15 @@ void ora_maxwell(const ora_ctx *c, double *v);
 int ora_run(ora_ctx *c, double *x, double *v, ora_state *st, int32_t nsteps, int32_t use_cells,
             double *traj);
 double ora_phi(const ora_ctx *c, const ora_state *st);
-int ora_reached(const ora_ctx *c, const ora_state *st);
+/* root-mean-square deviation of the solute positions x (first n_solute rows
+ * of [n][3]) from X_f after the optimal rigid superposition (rotation and
+ * translation, no reflection), unweighted; NAN without x_final */
+double ora_rmsd(const ora_ctx *c, const double *x);
+/* product reached (main text, folding-event criterion): stable trajectory,
+ * |z(X_t) - z_target| <= reach_tol and, when reach_rmsd is finite,
+ * ora_rmsd(x) <= reach_rmsd; x are the current positions (may be NULL when
+ * reach_rmsd is infinite) */
+int ora_reached(const ora_ctx *c, const ora_state *st, const double *x);
 int ora_select(int32_t n, const double *phi, const uint8_t *reached, const uint8_t *eligible,
                int32_t *best, double *best_phi);
 

@@ -36,6 +36,7 @@ class _Sys(C.Structure):
         ("contact_r0", C.c_double), ("contact_rs", C.c_double), ("contact_rc", C.c_double),
         ("contact_min_sep", C.c_int32),
         ("reach_tol", C.c_double), ("seed", C.c_uint64), ("const_force", _dp),
+        ("reach_rmsd", C.c_double),
     ]
 
 
@@ -45,7 +46,8 @@ class State(C.Structure):
                 ("status", C.c_int32), ("pad", C.c_int32)]
 
 
-TERMS = ("e_lj", "e_rf", "e_bond", "e_angle", "e_bias", "z", "z_ref", "S")
+TERMS = ("e_lj", "e_rf", "e_bond", "e_angle", "e_bias", "z", "z_ref", "S", "u_total",
+         "w_xx", "w_xy", "w_xz", "w_yx", "w_yy", "w_yz", "w_zx", "w_zy", "w_zz")
 
 _lib = None
 
@@ -78,7 +80,9 @@ def lib():
         L.ora_phi.restype = C.c_double
         L.ora_phi.argtypes = [C.c_void_p, C.POINTER(State)]
         L.ora_reached.restype = C.c_int
-        L.ora_reached.argtypes = [C.c_void_p, C.POINTER(State)]
+        L.ora_reached.argtypes = [C.c_void_p, C.POINTER(State), _dp]
+        L.ora_rmsd.restype = C.c_double
+        L.ora_rmsd.argtypes = [C.c_void_p, _dp]
         L.ora_select.restype = C.c_int
         L.ora_select.argtypes = [C.c_int32, _dp, _u8p, _u8p, _ip, _dp]
         L.ora_forces_dir.restype = C.c_int
@@ -143,6 +147,7 @@ class Oracle:
         s.reach_tol = float(desc["reach_tol"])
         s.seed = int(desc["seed"]) & 0xFFFFFFFFFFFFFFFF
         s.const_force = _d(keep["const_force"]) if keep["const_force"] is not None else _dp()
+        s.reach_rmsd = float(desc.get("reach_rmsd", float("inf")))
         self._sys = s
         self.ctx = lib().ora_create(C.byref(s))
         if not self.ctx:
@@ -234,8 +239,13 @@ class Oracle:
         lib().ora_phi_grad(self.ctx, C.byref(state), _d(pd), _d(out))
         return out
 
-    def reached(self, state):
-        return bool(lib().ora_reached(self.ctx, C.byref(state)))
+    def reached(self, state, x=None):
+        xa = None if x is None else _f64(x, (self.n, 3))
+        return bool(lib().ora_reached(self.ctx, C.byref(state), _d(xa) if xa is not None else None))
+
+    def rmsd(self, x):
+        """RMSD of the solute of x ([n][3]) from X_f after optimal superposition."""
+        return lib().ora_rmsd(self.ctx, _d(_f64(x, (self.n, 3))))
 
 
 # ------------------------------------------------------------------ helpers

@@ -609,3 +609,258 @@ def test_ramp_rate_derivative_vanishes_when_the_ramp_ends_in_the_first_step(orac
     d = dict(d, ramp_rate=2.0 / d["dt"])
     _, grad, _, _ = _phi_and_grad(oracle_mod, d, 10)
     assert grad[1] == 0.0 and grad[0] != 0.0
+
+
+# --------------------------------------------------------------- contact-sum range
+def _line_solute(n, spacing=1.5, box=30.0, min_sep=3, bias=synth.BIAS_CONTACT):
+    """n solute beads and no solvent in a large box: every bead starts on a line
+    with `spacing` between neighbours (all pairs beyond the 1.2 nm switch)."""
+    d = synth.lj_box(n=n, box=box, r_cut=1.0, charged=False)
+    x = np.zeros((n, 3)) + 1.0
+    x[:, 0] += spacing * np.arange(n)
+    d.update(n_solute=n, x0=x, x_final=x.copy(), bias=bias, contact_min_sep=min_sep,
+             contact_r0=0.75, contact_rs=1.0, contact_rc=1.2, bias_k=0.1, gamma=np.full(n, 1.0))
+    return d
+
+
+def test_contact_sum_runs_over_unordered_pairs_beyond_the_separation(oracle_mod):
+    """Supplement, collective coordinate: z sums over pairs with |i - j| > 35
+    (here min_sep = 3) once per unordered pair.  With the target map empty
+    (every X_f pair beyond the switch), one pair (i, i + min_sep + 1) at
+    r = r0 gives z = C(r0)^2 = (3/5)^2, and a pair at separation exactly
+    min_sep adds nothing; counting |i - j| >= min_sep or ordered pairs would
+    give a different z."""
+    d = _line_solute(12, min_sep=3)
+    x = d["x0"].copy()
+    x[4] = x[0] + np.array([0.0, 0.75, 0.0])   # pair (0, 4): separation 4 > 3, at r0
+    x[9] = x[6] + np.array([0.0, 0.0, 0.5])    # pair (6, 9): separation 3, not counted
+    o = oracle_mod.Oracle(d)
+    assert o.cv(d["x_final"])[0] == 0.0
+    z, g = o.cv(x)
+    assert z == pytest.approx(0.36, rel=1e-14)
+    # only the counted pair carries a gradient: equal and opposite on atoms 0 and 4
+    moved = np.flatnonzero(np.abs(g).sum(1) > 0)
+    assert list(moved) == [0, 4] and np.array_equal(g[0], -g[4])
+
+
+# --------------------------------------------------------------- reached
+def _two_bead_rg(tol, z_target, reach_rmsd=float("inf")):
+    d = _line_solute(2, spacing=0.5, bias=synth.BIAS_RG)
+    d.update(bias_k=0.0, ramp_rate=0.0, z_target=z_target, reach_tol=tol, reach_rmsd=reach_rmsd,
+             sigma=np.full(2, 0.3), epsilon=np.full(2, 0.5))
+    return d
+
+
+def test_reached_compares_the_final_z_with_the_tolerance_inclusively(oracle_mod):
+    """Folding-event criterion read as |z(X_T) - z_target| <= reach_tol on the
+    z of the last step, never for an unstable trajectory.  Two equal masses
+    0.5 nm apart: Rg = 0.25 exactly."""
+    O = oracle_mod
+    d = _two_bead_rg(0.125, 0.375)
+    o = O.Oracle(d)
+    st = o.init(d["x0"])
+    assert st.z_last == 0.25
+    assert o.reached(st)
+    assert not O.Oracle(dict(d, reach_tol=np.nextafter(0.125, 0.0))).reached(st)
+    # after some steps z_last differs from z(X_0): the decision follows z_last
+    x, v = d["x0"].copy(), o.maxwell()
+    o.run(x, v, st, 40)
+    delta = st.z_last - 0.25
+    assert abs(delta) > 1e-6
+    zt = st.z_last + delta            # |z_last - zt| = |delta|, |z(X_0) - zt| = 2 |delta|
+    tol = abs(st.z_last - zt)
+    assert O.Oracle(dict(d, z_target=zt, reach_tol=tol)).reached(st)
+    assert not O.Oracle(dict(d, z_target=zt, reach_tol=np.nextafter(tol, 0.0))).reached(st)
+    st.status = 1
+    assert not O.Oracle(dict(d, reach_tol=np.inf)).reached(st)
+
+
+# --------------------------------------------------------------- ratchet prefactor
+def test_ratchet_force_is_half_the_harmonic_force_toward_the_running_minimum(oracle_mod):
+    """Eq. VR: F = -(k_R/2)(z - z_m) grad z while z > z_m.  At a configuration
+    with z > z_m this is exactly half of the harmonic bias -k (z - z_ref) grad z
+    with z_ref = z_m, and it is the gradient of (k_R/4)(z - z_m)^2 at fixed z_m."""
+    O = oracle_mod
+    base = dict(synth.tiny(seed=10, bias=synth.BIAS_RMD_CONTACT), bias_k=0.05)
+    x = np.asarray(base["x0"], np.float64)
+    ornd = O.Oracle(base)
+    st = ornd.init(x)
+    z = st.z0
+    st.z_m = 0.8 * z                                  # z > z_m: the ratchet acts
+    _, f_rmd, t_rmd = ornd.forces(x, 0.0, st)
+    harm = dict(base, bias=synth.BIAS_CONTACT, ramp_rate=0.0)
+    oh = O.Oracle(harm)
+    sh = oh.init(x)
+    sh.z0 = st.z_m                                    # z_ref(t) = z0 when the ramp is off
+    _, f_h, t_h = oh.forces(x, 0.0, sh)
+    assert t_h["z_ref"] == st.z_m and np.abs(f_h).max() > 0
+    assert np.array_equal(f_rmd, 0.5 * f_h)
+    assert t_rmd["e_bias"] == pytest.approx(0.5 * t_h["e_bias"], rel=1e-15)
+    assert t_rmd["e_bias"] == pytest.approx(0.25 * 0.05 * (z - st.z_m) ** 2, rel=1e-14)
+    h = 1e-6
+    ns = base["n_solute"]
+    for i, a in ((0, 0), (ns // 2, 1), (ns - 1, 2)):
+        xp, xm = x.copy(), x.copy()
+        xp[i, a] += h
+        xm[i, a] -= h
+        fd = -(ornd.forces(xp, 0.0, st)[2]["e_bias"] - ornd.forces(xm, 0.0, st)[2]["e_bias"]) / (2 * h)
+        assert fd == pytest.approx(f_rmd[i, a], rel=1e-6, abs=1e-10)
+    st.z_m = z                                        # at the minimum: no force
+    assert np.all(ornd.forces(x, 0.0, st)[1] == 0.0)
+
+
+def test_constant_bias_is_the_gradient_of_minus_its_projection(oracle_mod):
+    """The constant test force F0 derives from U_b = -sum_i F0_i . x_i."""
+    d = synth.tiny(seed=3, bias=synth.BIAS_CONST)
+    rng = np.random.default_rng(4)
+    d["const_force"] = rng.normal(size=(d["n_solute"], 3))
+    o = oracle_mod.Oracle(d)
+    x = np.asarray(d["x0"], np.float64)
+    st = o.init(x)
+    _, fb, t = o.forces(x, 0.0, st)
+    assert t["e_bias"] == pytest.approx(-float(np.sum(d["const_force"] * x[: d["n_solute"]])), rel=1e-13)
+    h = 1e-6
+    for i, a in ((0, 0), (7, 2)):
+        xp, xm = x.copy(), x.copy()
+        xp[i, a] += h
+        xm[i, a] -= h
+        fd = -(o.forces(xp, 0.0, st)[2]["e_bias"] - o.forces(xm, 0.0, st)[2]["e_bias"]) / (2 * h)
+        assert fd == pytest.approx(fb[i, a], rel=1e-8)
+
+
+# --------------------------------------------------------------- virial
+VIR = ("w_xx", "w_xy", "w_xz", "w_yx", "w_yy", "w_yz", "w_zx", "w_zy", "w_zz")
+
+
+def _virial(terms):
+    return np.array([terms[k] for k in VIR]).reshape(3, 3)
+
+
+def _u_of(oracle_mod, d, x):
+    o = oracle_mod.Oracle(dict(d, bias=synth.BIAS_NONE))
+    t = o.forces(x, 0.0, None)[2]
+    return t["e_lj"] + t["e_rf"] + t["e_bond"] + t["e_angle"]
+
+
+def test_virial_is_minus_the_box_scaling_derivative_of_the_energy(oracle_mod):
+    """W_aa = -dU/d(ln L_a) when the box edge a and every coordinate along a
+    are scaled together (periodic solvated system, pair and bonded terms);
+    the shifted potentials are continuous at r_c, so the difference quotient
+    is a derivative even if a pair crosses the cutoff."""
+    d = dict(synth.tiny(seed=8), bias=synth.BIAS_NONE)
+    x = np.asarray(synth.perturbed(d, 0.005, 1)["x0"], np.float64)  # bonds and angles off rest
+    W = _virial(oracle_mod.Oracle(d).forces(x, 0.0, None)[2])
+    h = 1e-6
+    for a in range(3):
+        ups = []
+        for lam in (1 + h, 1 - h):
+            xs, box = x.copy(), np.array(d["box"], float)
+            xs[:, a] *= lam
+            box[a] *= lam
+            ups.append(_u_of(oracle_mod, dict(d, box=box), xs))
+        fd = -(ups[0] - ups[1]) / (2 * h)
+        assert fd == pytest.approx(W[a, a], rel=1e-6, abs=1e-6)
+    assert np.allclose(W, W.T, rtol=1e-12, atol=1e-9)
+
+
+def test_virial_of_an_isolated_molecule_equals_sum_of_position_times_force(oracle_mod):
+    """Without periodic images every term is internal to the cluster, so the
+    pair/term form of the virial equals sum_i x_i (x) F_i, and a homogeneous
+    deformation x -> (1 + h E_ab) x changes U by -h W_ba."""
+    t = synth.tiny(seed=9)
+    ns = t["n_solute"]
+    keep = {k: t[k] for k in ("bonds", "angles", "excl")}
+    d = dict(t, n_atoms=ns, mass=t["mass"][:ns], gamma=t["gamma"][:ns], charge=t["charge"][:ns],
+             sigma=t["sigma"][:ns], epsilon=t["epsilon"][:ns], x0=t["x0"][:ns] + 5.0,
+             box=np.full(3, 20.0), r_cut=2.5, bias=synth.BIAS_NONE,
+             bonds=keep["bonds"][np.all(keep["bonds"] < ns, 1)],
+             excl=keep["excl"][np.all(keep["excl"] < ns, 1)])
+    sel = np.all(keep["angles"] < ns, 1)
+    d["angles"] = keep["angles"][sel]
+    d["angle_k"], d["angle_theta0"] = t["angle_k"][sel], t["angle_theta0"][sel]
+    bsel = np.all(keep["bonds"] < ns, 1)
+    d["bond_k"], d["bond_r0"] = t["bond_k"][bsel], t["bond_r0"][bsel]
+    x = np.asarray(synth.perturbed(d, 0.01, 2)["x0"], np.float64)  # bonds and angles off rest
+    o = oracle_mod.Oracle(d)
+    f, _, terms = o.forces(x, 0.0, None)
+    W = _virial(terms)
+    assert terms["e_bond"] > 1.0 and terms["e_angle"] > 0 and terms["e_lj"] != 0
+    assert np.allclose(W, x.T @ f, rtol=1e-10, atol=1e-8)
+    h = 1e-6
+    for a in range(3):
+        for b in range(3):
+            E = np.zeros((3, 3))
+            E[a, b] = 1.0
+            up = _u_of(oracle_mod, d, x @ (np.eye(3) + h * E).T)
+            um = _u_of(oracle_mod, d, x @ (np.eye(3) - h * E).T)
+            assert -(up - um) / (2 * h) == pytest.approx(W[b, a], rel=1e-6, abs=1e-6)
+
+
+# --------------------------------------------------------------- RMSD to the product
+def _rmsd_oracle(oracle_mod, xf):
+    n = len(xf)
+    d = _line_solute(n)
+    d["x_final"] = np.asarray(xf, np.float64)
+    return oracle_mod.Oracle(d)
+
+
+def test_rmsd_of_a_rigidly_moved_copy_is_zero(oracle_mod):
+    rng = np.random.default_rng(1)
+    xf = rng.normal(size=(30, 3))
+    o = _rmsd_oracle(oracle_mod, xf)
+    R = scipy.stats.special_ortho_group.rvs(3, random_state=2)
+    assert o.rmsd(xf @ R.T + np.array([3.0, -2.0, 0.5])) < 1e-12
+    assert o.rmsd(xf + 0.7) < 1e-12
+
+
+def test_rmsd_two_points_closed_form(oracle_mod):
+    """Two atoms d1 and d2 apart: after centring and aligning the axes each
+    atom is off by |d1 - d2| / 2."""
+    xf = np.array([[0.0, 0.0, 0.0], [1.0, 0.0, 0.0]])
+    o = _rmsd_oracle(oracle_mod, xf)
+    x = np.array([[2.0, 1.0, 0.0], [2.0, 1.0 + 0.6, 0.8]])  # distance 1.0 as well
+    assert o.rmsd(x) < 1e-12
+    x[1] = [2.0, 1.0, 1.4]                                 # distance 1.4
+    assert o.rmsd(x) == pytest.approx(0.2, rel=1e-12)
+
+
+def test_rmsd_matches_the_kabsch_alignment_of_scipy(oracle_mod):
+    """scipy's Rotation.align_vectors solves the same least-squares rotation
+    (Kabsch); its root-sum-square residual over centred sets, divided by
+    sqrt(n), is the RMSD."""
+    from scipy.spatial.transform import Rotation
+    rng = np.random.default_rng(5)
+    for n in (3, 7, 40):
+        xf = rng.normal(size=(n, 3))
+        x = xf @ scipy.stats.special_ortho_group.rvs(3, random_state=n).T + rng.normal(scale=0.3, size=(n, 3))
+        o = _rmsd_oracle(oracle_mod, xf)
+        a, b = xf - xf.mean(0), x - x.mean(0)
+        _, rssd = Rotation.align_vectors(a, b)
+        assert o.rmsd(x) == pytest.approx(rssd / np.sqrt(n), rel=1e-9)
+
+
+def test_rmsd_admits_no_reflection(oracle_mod):
+    """Superposition by proper rotations only: the mirror image of a chiral
+    set keeps a positive RMSD, that of a planar set (a rotation away) none."""
+    chiral = np.array([[0, 0, 0], [1, 0, 0], [0, 2, 0], [0, 0, 3]], float)
+    o = _rmsd_oracle(oracle_mod, chiral)
+    mirror = chiral * np.array([-1.0, 1.0, 1.0])
+    assert o.rmsd(mirror) > 0.1
+    planar = np.array([[0, 0, 0], [1, 0, 0], [0, 2, 0], [3, 1, 0]], float)
+    assert _rmsd_oracle(oracle_mod, planar).rmsd(planar * np.array([1.0, 1.0, -1.0]) + 0.0) < 1e-12
+    assert _rmsd_oracle(oracle_mod, planar).rmsd(planar * np.array([-1.0, 1.0, 1.0])) < 1e-12
+
+
+def test_reached_with_an_rmsd_criterion(oracle_mod):
+    """With reach_rmsd finite, the product is reached only within that RMSD of X_f."""
+    O = oracle_mod
+    d = _line_solute(6, min_sep=1)
+    rng = np.random.default_rng(3)
+    d["x_final"] = d["x0"] + rng.normal(scale=0.4, size=(6, 3))
+    d.update(reach_tol=np.inf)
+    x = d["x0"].copy()
+    r = O.Oracle(d).rmsd(x)
+    st = O.Oracle(d).init(x)
+    assert O.Oracle(dict(d, reach_rmsd=r)).reached(st, x)
+    assert not O.Oracle(dict(d, reach_rmsd=np.nextafter(r, 0.0))).reached(st, x)
+    assert not O.Oracle(dict(d, reach_rmsd=r)).reached(st, None)
