@@ -27,6 +27,10 @@
  *     ("user order"); 3-vectors are stored as [atom][3] (AoS), FP32 unless
  *     stated otherwise;
  *   - hip_stream is a hipStream_t passed as void* (NULL = default stream).
+ *     The calls of one system are ordered: each asynchronous call records an
+ *     event on its stream, and a later call on another stream first waits on
+ *     it, so work enqueued on different streams never overlaps (the calls
+ *     share device buffers); synchronising calls wait on that event.
  *   - one vp_system must not be used from two threads at once.
  */
 #ifndef VP_H
@@ -58,7 +62,12 @@ typedef enum {
   VP_BIAS_RMD_CONTACT = 4  /* ratchet-and-pawl on the contact-map distance (Eq. VR) */
 } vp_bias_kind;
 
-/* Per-replica status word (vp_observables, column VP_OBS_STATUS). */
+/* Per-replica status word (vp_observables, column VP_OBS_STATUS).  Either
+ * flag freezes the replica at the step where it was raised: a force above
+ * 1e6 kJ/mol/nm or a non-finite force (UNSTABLE), or a pair list that did
+ * not fit its per-atom capacity or its block's staging capacity, so that
+ * pairs were left out of the forces (LIST_OVERFLOW).  A flagged replica's
+ * functional is +inf and it is never selected. */
 enum { VP_REPLICA_OK = 0, VP_REPLICA_UNSTABLE = 1, VP_REPLICA_LIST_OVERFLOW = 2 };
 
 /* One trial trajectory: the problem statement of the paper (masses m_i,
@@ -101,9 +110,16 @@ typedef struct {
   double bias_k, ramp_rate, z_target;
   double contact_r0, contact_rs, contact_rc;
   int32_t contact_min_sep;
-  double reach_tol;          /* reached <=> |z(X_t) - z_target| <= reach_tol */
+  double reach_tol;          /* reached requires |z(X_t) - z_target| <= reach_tol */
   uint64_t seed;             /* Philox4x32-10 key of this trajectory's noise */
-  const double *const_force; /* [n_solute][3] for VP_BIAS_CONST, else NULL */
+  const double *const_force; /* [n_solute][3] for VP_BIAS_CONST (the force of
+                                U_b = -sum_i F0_i . x_i; z reports sum_i F0_i . x_i),
+                                else NULL */
+  double reach_rmsd;         /* nm; when finite, reached also requires the RMSD of
+                                the solute from X_f after the optimal rotation and
+                                translation (unweighted, no reflection; the folding
+                                criterion of the main text) to be <= reach_rmsd;
+                                needs x_final.  +inf: not used */
 } vp_replica_desc;
 
 typedef struct {
@@ -133,8 +149,42 @@ typedef struct {
   int32_t autotune;        /* 1: time every tile shape on each size bucket at creation and
                               launch each bucket with its fastest (force_shape is ignored);
                               the forces are bitwise the same for every shape */
-  int32_t reserved[4];
+  int32_t nst_out;         /* > 0: an energy record (VP_REC_*) of every replica at creation and
+                              after every step whose count is a multiple of nst_out
+                              (vp_energy_records); 0: none */
+  int32_t out_capacity;    /* records kept per replica, the latest ones (0: 1024) */
+  int32_t stage_cap;       /* > 0: staged neighbourhood atoms per 64-atom block at most this
+                              (a diagnostic: blocks that need more are built again in exact
+                              mode, which stages only atoms within the list radius of one of
+                              the block's atoms); 0: as large as the force kernel's LDS allows */
+  int32_t reserved;
+  /* Device memory: when dev_alloc is not NULL every device buffer the system
+   * holds is obtained from dev_alloc(bytes, alloc_ctx) (NULL = out of memory)
+   * and returned with dev_free(ptr, alloc_ctx) by vp_system_destroy, or by a
+   * failing vp_system_create; temporary buffers of the diagnostic calls too.
+   * The memory must be device memory usable on every stream the system is
+   * used with.  NULL: hipMalloc / hipFree. */
+  void *(*dev_alloc)(size_t bytes, void *alloc_ctx);
+  void (*dev_free)(void *ptr, void *alloc_ctx);
+  void *alloc_ctx;
 } vp_options;
+
+/* Columns of the FP64 energy table written by vp_forces (one row per
+ * replica) and the first columns of an energy record: Lennard-Jones,
+ * reaction field, bond and angle energies, bias energy, z, z_ref (the ratchet
+ * minimum for VP_BIAS_RMD_CONTACT), S = sum_i |F_i^bias|^2/(gamma_i m_i), the
+ * total U + U_b, the virial W_ab = sum over the pair and bonded terms of U of
+ * r_a F_b (r the separation of a moved atom from the term's other atom or
+ * vertex, F the force on the moved atom; row-major; the bias, an external
+ * force, takes no part), and the replica's status bits of that evaluation. */
+enum { VP_E_LJ = 0, VP_E_RF, VP_E_BOND, VP_E_ANGLE, VP_E_BIAS, VP_E_Z, VP_E_ZREF, VP_E_S,
+       VP_E_TOTAL, VP_E_WXX, VP_E_WXY, VP_E_WXZ, VP_E_WYX, VP_E_WYY, VP_E_WYZ, VP_E_WZX,
+       VP_E_WZY, VP_E_WZZ, VP_E_STATUS, VP_E_COUNT };
+
+/* An energy record of a trajectory (vp_energy_records): the VP_E_* columns at
+ * step n, then n, the kinetic energy (1/2) sum m v^2 of the velocities of step
+ * n, and Phi accumulated up to step n (trapezoid rule closed at n). */
+enum { VP_REC_STEP = VP_E_COUNT, VP_REC_KE, VP_REC_PHI, VP_REC_COUNT };
 
 #define VP_FORCE_SHAPES 4
 
@@ -174,10 +224,13 @@ vp_status vp_system_destroy(vp_system *s);
 /* Total force F = -grad U + F^bias (Eq. Lang with the bias of the text after
  * it) at time t for the positions x_dev of every replica, without touching
  * the trajectory state.  x_dev: DEVICE [sum N][3] FP32 in user order;
- * f_dev: DEVICE [sum N][3] FP32 output; energy_dev: DEVICE [n_reps][8] FP64
- * output (or NULL) with columns LJ, RF, bond, angle, bias, z, z_ref, S where
- * S = sum_i |F_i^bias|^2/(gamma_i m_i).  Ratchet replicas use their current
- * running minimum.  Asynchronous on hip_stream. */
+ * f_dev: DEVICE [sum N][3] FP32 output; energy_dev: DEVICE [n_reps][VP_E_COUNT]
+ * FP64 output (or NULL), the columns VP_E_*.  Ratchet replicas use their
+ * current running minimum.  Asynchronous on hip_stream, so a replica whose
+ * pair list overflowed (positions denser than the capacities sized at
+ * creation allow) cannot be reported by the return value: its forces are
+ * written as NaN and its VP_E_STATUS column and its VP_OBS_EVAL_STATUS
+ * observable carry VP_REPLICA_LIST_OVERFLOW. */
 vp_status vp_forces(vp_system *s, const float *x_dev, float *f_dev, double *energy_dev, double t,
                     void *hip_stream);
 
@@ -196,14 +249,18 @@ vp_status vp_step_batch(vp_system *s, int32_t n_steps, void *hip_stream);
 vp_status vp_functional(vp_system *s, double *phi_host, double *dphi_dtheta_host);
 
 /* Variational selection: the replica with the least finite Phi among those
- * that reached the product (|z - z_target| <= reach_tol at the current time)
+ * that reached the product (status clear, |z - z_target| <= reach_tol at the
+ * current step and, where reach_rmsd is finite, RMSD to X_f <= reach_rmsd)
  * and whose eligible flag (HOST [n_reps], NULL = all) is nonzero; ties go to
  * the lowest index.  Returns VP_ERR_NOPATH with *best = -1 when none
  * qualifies.  Synchronises. */
 vp_status vp_select_path(vp_system *s, const uint8_t *eligible, int32_t *best, double *best_phi);
 
 /* Copy the current positions and velocities in user order into DEVICE
- * buffers x_dev, v_dev ([sum N][3] FP32; either may be NULL). */
+ * buffers x_dev, v_dev ([sum N][3] FP32; either may be NULL).  Asynchronous.
+ * The trajectory state itself lives in the library's own sorted, fixed-point
+ * layout (positions in units of 2^-24 nm, reordered at every list rebuild),
+ * so it is copied out rather than lent as views. */
 vp_status vp_get_state(vp_system *s, float *x_dev, float *v_dev, void *hip_stream);
 
 /* Per-replica observables: obs_host HOST [n_reps][VP_OBS_COUNT] FP64.
@@ -211,10 +268,26 @@ vp_status vp_get_state(vp_system *s, float *x_dev, float *v_dev, void *hip_strea
  * 64-atom block and its capacity, longest per-atom list and its capacity,
  * number of blocks built again in exact mode (staging capacity reached);
  * the replica's pair-list buffer (nm) and rebuild interval. */
+/* Also: the RMSD of the solute from X_f after optimal superposition (NaN
+ * without x_final), whether the replica counts as having reached the product
+ * (the criterion of vp_select_path), and the status bits of its latest
+ * vp_forces evaluation.  Synchronises. */
 enum { VP_OBS_STEP = 0, VP_OBS_Z, VP_OBS_ZREF, VP_OBS_ZMIN, VP_OBS_PHI, VP_OBS_STATUS,
        VP_OBS_REBUILDS, VP_OBS_KE, VP_OBS_STAGE_MAX, VP_OBS_STAGE_CAP, VP_OBS_LIST_MAX,
-       VP_OBS_LIST_CAP, VP_OBS_EXACT_BUILDS, VP_OBS_SKIN, VP_OBS_NSTLIST, VP_OBS_COUNT };
+       VP_OBS_LIST_CAP, VP_OBS_EXACT_BUILDS, VP_OBS_SKIN, VP_OBS_NSTLIST, VP_OBS_RMSD,
+       VP_OBS_REACHED, VP_OBS_EVAL_STATUS, VP_OBS_COUNT };
 vp_status vp_observables(vp_system *s, double *obs_host);
+
+/* Energy records of the trajectories (vp_options.nst_out > 0): writes the
+ * number of records held per replica to *n_records (the same for every
+ * replica: at most vp_options.out_capacity, the latest ones) and, if out_host
+ * is not NULL, min(cap, *n_records) of them per replica, oldest first, as
+ * HOST FP64 [n_reps][min(cap, *n_records)][VP_REC_COUNT].  VP_ERR_STATE when
+ * the system records nothing.  Synchronises. */
+vp_status vp_energy_records(vp_system *s, double *out_host, int32_t cap, int32_t *n_records);
+
+/* Device bytes held by the system (its buffers, whichever allocator). */
+vp_status vp_device_bytes(const vp_system *s, int64_t *bytes);
 
 /* Force-kernel timing.  While on != 0, vp_step_batch enqueues its steps by
  * direct kernel launches (no graph replay) with a HIP event recorded on the
@@ -234,10 +307,6 @@ vp_status vp_pair_count(vp_system *s, int32_t rep, int64_t *count);
 /* Sizes: total atoms of the batch and number of replicas. */
 vp_status vp_sizes(const vp_system *s, int64_t *n_atoms_total, int32_t *n_reps);
 
-/* Diagnostics for tests: copy the pair list of replica rep as unordered
- * pairs (i < j, replica-local user indices) whose current FP32 separation
- * passes the membership predicate, into pairs_host HOST [cap][2].
- * *count receives the number of such pairs (which may exceed cap). */
 /* The size buckets of the batch and their force tile shapes, in order of
  * first appearance in the batch: writes min(cap, count) entries to out (HOST,
  * may be NULL when cap is 0) and the count to *n_buckets.  With autotuning,
@@ -269,6 +338,10 @@ vp_status vp_debug_force_dir(vp_system *s, const float *x_dev, const float *dx_d
 vp_status vp_debug_trajectory_state(vp_system *s, double *x_host, double *v_host, double *xt_host,
                                     double *vt_host, double *pd_host);
 
+/* Diagnostics for tests: copy the pair list of replica rep as unordered
+ * pairs (i < j, replica-local user indices) whose current FP32 separation
+ * passes the membership predicate, into pairs_host HOST [cap][2].
+ * *count receives the number of such pairs (which may exceed cap). */
 vp_status vp_debug_pairs(vp_system *s, int32_t rep, int32_t *pairs_host, int64_t cap,
                          int64_t *count);
 

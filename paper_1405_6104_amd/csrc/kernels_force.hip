@@ -59,13 +59,12 @@ __device__ __forceinline__ void stage_neighbourhood(const uint32_t *__restrict__
 
 // One list chunk (8 entries of one atom's list) evaluated against the staged
 // neighbourhood: LJ + reaction-field forces accumulated in the chunk's order
-// into (fx, fy, fz), energies into (elj, erf) when ENERGY.  UNROLL entries
-// share one batch of LDS reads.
-template <bool ENERGY, int UNROLL>
+// into (fx, fy, fz).  UNROLL entries share one batch of LDS reads.
+template <int UNROLL>
 __device__ __forceinline__ void eval_chunk(const uint4 e, const int4 *__restrict__ st,
                                            const char *__restrict__ ldsb, const float4 ti, int wx,
-                                           int wy, int wz, float rc2, float krf2, const RepInfo &R,
-                                           float &fx, float &fy, float &fz, double &elj, double &erf) {
+                                           int wy, int wz, float rc2, float krf2, float &fx, float &fy,
+                                           float &fz) {
   const uint32_t w[4] = {e.x, e.y, e.z, e.w};
 #pragma unroll
   for (int h = 0; h < 8; h += UNROLL) {
@@ -98,15 +97,6 @@ __device__ __forceinline__ void eval_chunk(const uint4 e, const int4 *__restrict
       fx = __builtin_fmaf(-fs, dx, fx);
       fy = __builtin_fmaf(-fs, dy, fy);
       fz = __builtin_fmaf(-fs, dz, fz);
-      if (ENERGY && in) {
-        // ee = 24 eps 2^48, qq = f q q 2^72 (see the type table)
-        const double e4 = (double)ee * (1.0 / 6.0) * (kInvQ * kInvQ);
-        const double s2c = (double)sg * sg / ((double)rc2);
-        const double s6c = s2c * s2c * s2c;
-        elj += e4 * ((double)sr6 * sr6 - sr6) - e4 * (s6c * s6c - s6c);
-        const double fqq = (double)qq * (kInvQ * kInvQ * kInvQ);
-        erf += fqq * ((double)rinv * kQ + R.krf * (double)r2 * (kInvQ * kInvQ) - R.crf);
-      }
     }
   }
 }
@@ -120,9 +110,9 @@ __device__ __forceinline__ void eval_chunk(const uint4 e, const int4 *__restrict
 // into logical accumulator c mod kLogicalParts (each wave holds
 // kLogicalParts / PARTS of them, in chunk order), and the accumulators are
 // added in index order at the end.  Every shape therefore performs the same
-// FP32 operations in the same order, and forces and energies agree bit for
-// bit whichever shape a launch uses.
-template <bool ENERGY, int PARTS, int UNROLL, int MINW>
+// FP32 operations in the same order, and the forces agree bit for bit
+// whichever shape a launch uses.
+template <int PARTS, int UNROLL, int MINW>
 __global__ __launch_bounds__(64 * PARTS) __attribute__((amdgpu_waves_per_eu(MINW))) void k_forces(const RepInfo *__restrict__ info, Work W,
                                                        const int32_t *__restrict__ tile_rep,
                                                        const int32_t *__restrict__ tile_first,
@@ -136,9 +126,8 @@ __global__ __launch_bounds__(64 * PARTS) __attribute__((amdgpu_waves_per_eu(MINW
   int4 *st = lds;                                              // [stage_slots] staged atoms
   float4 *tab = reinterpret_cast<float4 *>(lds + stage_slots);  // the replica's type table
   // after the pair loop the staging area holds the logical partial sums:
-  // forces [3][kLogicalParts][64] FP32, then energies [2][kLogicalParts][64] FP64
+  // forces [3][kLogicalParts][64] FP32
   float *red = reinterpret_cast<float *>(lds);
-  double *ered = reinterpret_cast<double *>(lds) + 3 * kLogicalParts * kBlk / 2;
   const int bt = xcd_tile(blockIdx.x, nblk);
   if (bt < 0) return;
   const int b = blist ? blist[bt] : bt;
@@ -154,7 +143,6 @@ __global__ __launch_bounds__(64 * PARTS) __attribute__((amdgpu_waves_per_eu(MINW
       W.F[W.fstride + slot] = 0;
       W.F[2 * W.fstride + slot] = 0;
     }
-    if (ENERGY && tid < 4) W.epart[4 * (size_t)b + tid] = 0.0;
     return;
   }
   const int Lx = R.Lq[0], Ly = R.Lq[1], Lz = R.Lq[2];
@@ -171,12 +159,8 @@ __global__ __launch_bounds__(64 * PARTS) __attribute__((amdgpu_waves_per_eu(MINW
   const int slot = R.off + p;
   const bool active = p < R.n;
   float fx[SETS], fy[SETS], fz[SETS];
-  double elj[SETS], erf[SETS];
 #pragma unroll
-  for (int k = 0; k < SETS; ++k) {
-    fx[k] = fy[k] = fz[k] = 0.0f;
-    elj[k] = erf[k] = 0.0;
-  }
+  for (int k = 0; k < SETS; ++k) fx[k] = fy[k] = fz[k] = 0.0f;
   int4 xi = make_int4(0, 0, 0, 0);
   int nrot = 0;  // chunks this wave evaluated: set k then holds logical (k + nrot) mod SETS
   if (active) {
@@ -195,18 +179,14 @@ __global__ __launch_bounds__(64 * PARTS) __attribute__((amdgpu_waves_per_eu(MINW
       // the next chunk's indices are fetched while this one is evaluated
       // (the last chunk is fetched again rather than reading past the list)
       const uint4 en = lp[(int64_t)min(c + PARTS, nch - 1) * kBlk];
-      eval_chunk<ENERGY, UNROLL>(e, st, reinterpret_cast<const char *>(lds), ti, wx, wy, wz, rc2, krf2, R,
-                                 fx[0], fy[0], fz[0], elj[0], erf[0]);
+      eval_chunk<UNROLL>(e, st, reinterpret_cast<const char *>(lds), ti, wx, wy, wz, rc2, krf2, fx[0],
+                         fy[0], fz[0]);
       // the sets rotate so that set 0 is always the one the next chunk feeds
 #pragma unroll
       for (int k = 0; k + 1 < SETS; ++k) {
         float t = fx[k]; fx[k] = fx[k + 1]; fx[k + 1] = t;
         t = fy[k]; fy[k] = fy[k + 1]; fy[k + 1] = t;
         t = fz[k]; fz[k] = fz[k + 1]; fz[k + 1] = t;
-        if (ENERGY) {
-          double u = elj[k]; elj[k] = elj[k + 1]; elj[k + 1] = u;
-          u = erf[k]; erf[k] = erf[k + 1]; erf[k + 1] = u;
-        }
       }
       e = en;
     }
@@ -220,15 +200,10 @@ __global__ __launch_bounds__(64 * PARTS) __attribute__((amdgpu_waves_per_eu(MINW
     red[(0 * kLogicalParts + q) * kBlk + lane] = fx[k];
     red[(1 * kLogicalParts + q) * kBlk + lane] = fy[k];
     red[(2 * kLogicalParts + q) * kBlk + lane] = fz[k];
-    if (ENERGY) {
-      ered[(0 * kLogicalParts + q) * kBlk + lane] = elj[k];
-      ered[(1 * kLogicalParts + q) * kBlk + lane] = erf[k];
-    }
   }
   __syncthreads();
   if (part == 0) {
     long long fxs = 0, fys = 0, fzs = 0;
-    double el = 0.0, er = 0.0;
     if (active) {
       float sx = red[lane], sy = red[kLogicalParts * kBlk + lane], sz = red[2 * kLogicalParts * kBlk + lane];
 #pragma unroll 4
@@ -237,12 +212,6 @@ __global__ __launch_bounds__(64 * PARTS) __attribute__((amdgpu_waves_per_eu(MINW
         sy += red[(kLogicalParts + q) * kBlk + lane];
         sz += red[(2 * kLogicalParts + q) * kBlk + lane];
       }
-      if (ENERGY)
-#pragma unroll 2
-        for (int q = 0; q < kLogicalParts; ++q) {
-          el += ered[q * kBlk + lane];
-          er += ered[(kLogicalParts + q) * kBlk + lane];
-        }
       fxs = to_fix((double)sx * kInvQ);
       fys = to_fix((double)sy * kInvQ);
       fzs = to_fix((double)sz * kInvQ);
@@ -250,16 +219,118 @@ __global__ __launch_bounds__(64 * PARTS) __attribute__((amdgpu_waves_per_eu(MINW
     W.F[slot] = fxs;
     W.F[W.fstride + slot] = fys;
     W.F[2 * W.fstride + slot] = fzs;
-    if (ENERGY) {
-      // the block's sums over its 64 atoms (wave 0 alone, fixed butterfly order)
-      const double v0 = wave_sum(0.5 * el), v1 = wave_sum(0.5 * er);
-      if (lane == 0) {
-        W.epart[4 * (size_t)b + 0] = v0;
-        W.epart[4 * (size_t)b + 1] = v1;
-        W.epart[4 * (size_t)b + 2] = 0.0;  // bonded energies: k_bonded
-        W.epart[4 * (size_t)b + 3] = 0.0;
-      }
+  }
+}
+
+// Energies and virial of the pair terms (for vp_forces and the energy records
+// of trajectories), one workgroup of kParts waves per 64-atom block over the
+// same lists and staging as k_forces: per list entry, in FP64 from the FP32
+// quantities of the force kernel, the shifted LJ and reaction-field energies
+// and the virial (1/2) fs q^2 d (x) d (each pair sits in both atoms' lists;
+// with F_j = fs q d the pair's r (x) F_j is fs q^2 d (x) d, symmetric).  The
+// waves' partials are added in wave order and over the block's lanes in a
+// fixed butterfly, into W.epart[b][0, 1] and [b][kEpPairW .. +9).  GATED: returns
+// at once unless the step being completed (*step + 1) is a multiple of nst_out.
+template <bool GATED>
+__global__ __launch_bounds__(kForceThreads) void k_pair_energy(const RepInfo *__restrict__ info, Work W,
+                                                               const int32_t *__restrict__ tile_rep,
+                                                               const int32_t *__restrict__ tile_first,
+                                                               int nblk, const float4 *__restrict__ types,
+                                                               int stage_slots,
+                                                               const long long *__restrict__ step,
+                                                               int nst_out) {
+  if (GATED && (*step + 1) % nst_out != 0) return;
+  extern __shared__ int4 lds[];
+  int4 *st = lds;
+  float4 *tab = reinterpret_cast<float4 *>(lds + stage_slots);
+  double *red = reinterpret_cast<double *>(lds);  // [8 values][kParts][64] after the loop
+  const int b = xcd_tile(blockIdx.x, nblk);
+  if (b < 0) return;
+  const int tile = b / (kTile / kBlk);
+  const RepInfo &R = info[tile_rep[tile]];
+  const int p0 = tile_first[tile] + (b % (kTile / kBlk)) * kBlk;
+  const int tid = threadIdx.x;
+  if (p0 >= R.n) {
+    if (tid < 2) W.epart[kEp * (size_t)b + tid] = 0.0;
+    if (tid < 9) W.epart[kEp * (size_t)b + kEpPairW + tid] = 0.0;
+    return;
+  }
+  const int Lx = R.Lq[0], Ly = R.Lq[1], Lz = R.Lq[2];
+  const int trow = (int)sizeof(int4) * stage_slots;
+  stage_neighbourhood<kForceThreads>(W.stage + (int64_t)b * W.stage_stride, W.stage_n[b], W.xq + R.off, Lx,
+                                     Ly, Lz, trow, tid, st);
+  if (tid == 0) st[R.stage_cap] = make_int4(kDummyCoord, kDummyCoord, kDummyCoord, trow + 16 * R.ntypes);
+  for (int t = tid; t <= R.ntypes; t += kForceThreads) tab[t] = types[R.type_off + t];
+  __syncthreads();
+  const int lane = tid & (kBlk - 1), part = tid / kBlk;
+  const int p = p0 + lane;
+  const int slot = R.off + p;
+  double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // LJ, RF, W xx yy zz xy xz yz
+  if (p < R.n) {
+    const int4 xi = W.xq[slot];
+    const int wr = W.wrap[slot];
+    const int wx = xi.x - unpack_wrap(wr, 0) * Lx, wy = xi.y - unpack_wrap(wr, 1) * Ly,
+              wz = xi.z - unpack_wrap(wr, 2) * Lz;
+    const float4 ti = tab[xi.w];
+    const float rc2 = R.rc2q, krf2 = R.krf2q;
+    const int nent = W.nbcnt[slot];
+    const uint16_t *lp = W.nblist + R.list_off + (int64_t)(b - R.blk0) * R.maxnb * kBlk;
+    for (int k = part; k < nent; k += kParts) {
+      const int L = lp[(((k >> 3) * kBlk) + lane) * 8 + (k & 7)];
+      const int4 sj = st[L];
+      const float4 tj = *reinterpret_cast<const float4 *>(reinterpret_cast<const char *>(lds) + sj.w);
+      const float dx = (float)(sj.x - wx), dy = (float)(sj.y - wy), dz = (float)(sj.z - wz);
+      const float r2 = qr2(dx, dy, dz);
+      if (!(r2 < rc2)) continue;
+      // the force kernel's FP32 quantities
+      const float rinv = __builtin_amdgcn_rsqf(r2);
+      const float r2inv = rinv * rinv;
+      const float sg = ti.y + tj.y;
+      const float sr2 = sg * sg * r2inv;
+      const float sr6 = sr2 * sr2 * sr2;
+      const float ee = ti.z * tj.z;
+      const float c6 = ee * sr6 * __builtin_fmaf(2.0f, sr6, -1.0f);
+      const float qq = ti.x * tj.x;
+      const float cq = qq * __builtin_fmaf(rinv, r2inv, -krf2);
+      const float fs = __builtin_fmaf(c6, r2inv, cq);
+      // ee = 24 eps 2^48, qq = f q q 2^72 (see the type table)
+      const double e4 = (double)ee * (1.0 / 6.0) * (kInvQ * kInvQ);
+      const double s2c = (double)sg * sg / ((double)rc2);
+      const double s6c = s2c * s2c * s2c;
+      acc[0] += e4 * ((double)sr6 * sr6 - sr6) - e4 * (s6c * s6c - s6c);
+      const double fqq = (double)qq * (kInvQ * kInvQ * kInvQ);
+      acc[1] += fqq * ((double)rinv * kQ + R.krf * (double)r2 * (kInvQ * kInvQ) - R.crf);
+      const double w = 0.5 * (double)fs * (kInvQ * kInvQ);
+      const double ddx = dx, ddy = dy, ddz = dz;
+      acc[2] += w * ddx * ddx;
+      acc[3] += w * ddy * ddy;
+      acc[4] += w * ddz * ddz;
+      acc[5] += w * ddx * ddy;
+      acc[6] += w * ddx * ddz;
+      acc[7] += w * ddy * ddz;
     }
+  }
+  __syncthreads();  // the staged neighbourhood is no longer read
+#pragma unroll
+  for (int v = 0; v < 8; ++v) red[(v * kParts + part) * kBlk + lane] = acc[v];
+  __syncthreads();
+  if (part != 0) return;
+  double sum[8];
+#pragma unroll
+  for (int v = 0; v < 8; ++v) {
+    double a = 0.0;
+    for (int q = 0; q < kParts; ++q) a += red[(v * kParts + q) * kBlk + lane];
+    sum[v] = wave_sum(a);
+  }
+  if (lane == 0) {
+    // each pair sits in both atoms' lists: half of every energy
+    double *e = W.epart + kEp * (size_t)b;
+    e[0] = 0.5 * sum[0];
+    e[1] = 0.5 * sum[1];
+    double *wv = e + kEpPairW;
+    wv[0] = sum[2]; wv[1] = sum[5]; wv[2] = sum[6];
+    wv[3] = sum[5]; wv[4] = sum[3]; wv[5] = sum[7];
+    wv[6] = sum[6]; wv[7] = sum[7]; wv[8] = sum[4];
   }
 }
 
@@ -330,23 +401,34 @@ constexpr int kBondBatch = 4;
 // of the replica), so the term ranges and records are read coalesced and the
 // atom's slot comes from one lookup.  Separate from k_forces so that these dependent
 // gathers and long FP64 chains run over the whole chip instead of on one wave
-// of each pair block.  ENERGY: the block's bond and angle energies.
-template <bool ENERGY>
+// of each pair block.  ENERGY (k_bonded_energy): no forces are stored; the
+// block's bond and angle energies and the virial sum_i x_i (x) F_i^bonded go to
+// W.epart[b][2, 3] and [b][kEpBondW .. +9) (each term's forces sum to zero, so
+// this equals the sum over terms of (x_i - x_ref) (x) F_i).  GATED: as in
+// k_pair_energy.
+template <bool ENERGY, bool GATED>
 __global__ __launch_bounds__(kBlk) void k_bonded(const RepInfo *__restrict__ info, Work W,
                                                  const int32_t *__restrict__ tile_rep,
                                                  const int32_t *__restrict__ tile_first, int nblk,
                                                  const int32_t *__restrict__ bt_start,
-                                                 const BTerm *__restrict__ bterms) {
+                                                 const BTerm *__restrict__ bterms,
+                                                 const long long *__restrict__ step, int nst_out) {
+  if (GATED && (*step + 1) % nst_out != 0) return;
   const int b = xcd_tile(blockIdx.x, nblk);
   if (b < 0) return;
   const int tile = b / (kTile / kBlk);
   const RepInfo &R = info[tile_rep[tile]];
   const int p0 = tile_first[tile] + (b % (kTile / kBlk)) * kBlk;
-  if (p0 >= R.n) return;  // padding block: the pair kernel zeroed its forces and energies
+  if (p0 >= R.n) {  // padding block: the pair kernel zeroed its forces
+    if (ENERGY && threadIdx.x < 2) W.epart[kEp * (size_t)b + 2 + threadIdx.x] = 0.0;
+    if (ENERGY && threadIdx.x < 9) W.epart[kEp * (size_t)b + kEpBondW + threadIdx.x] = 0.0;
+    return;
+  }
   const int lane = threadIdx.x;
   const int a = p0 + lane;  // the atom's index in the replica's original order
   const bool active = a < R.n;
   double ebond = 0.0, eangle = 0.0;
+  double vir[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
   if (active) {
     const int ga = R.uoff + a;
     const int slot = W.inv[ga];
@@ -373,17 +455,27 @@ __global__ __launch_bounds__(kBlk) void k_bonded(const RepInfo *__restrict__ inf
       for (int u = 0; u < kBondBatch; ++u)
         if (t + u < t1) bonded_term<ENERGY>(T[u], xi, p1[u], p2[u], bx, by, bz, ebond, eangle);
     }
-    if (t1 > t0) {
+    if (!ENERGY && t1 > t0) {
       W.F[slot] += to_fix(bx);
       W.F[W.fstride + slot] += to_fix(by);
       W.F[2 * W.fstride + slot] += to_fix(bz);
     }
+    if (ENERGY) {
+      const double x[3] = {(double)xi.x * kInvQ, (double)xi.y * kInvQ, (double)xi.z * kInvQ};
+      const double f[3] = {bx, by, bz};
+      for (int u = 0; u < 3; ++u)
+        for (int v = 0; v < 3; ++v) vir[3 * u + v] = x[u] * f[v];
+    }
   }
   if (ENERGY) {
     const double v2 = wave_sum(ebond), v3 = wave_sum(eangle);
+    double w[9];
+    for (int k = 0; k < 9; ++k) w[k] = wave_sum(vir[k]);
     if (lane == 0) {
-      W.epart[4 * (size_t)b + 2] = v2;
-      W.epart[4 * (size_t)b + 3] = v3;
+      double *e = W.epart + kEp * (size_t)b;
+      e[2] = v2;
+      e[3] = v3;
+      for (int k = 0; k < 9; ++k) e[kEpBondW + k] = w[k];
     }
   }
 }
@@ -949,10 +1041,14 @@ __global__ __launch_bounds__(kCvBlock) void k_cv(const RepInfo *__restrict__ inf
         }
       }
     } else if (R.bias == VP_BIAS_CONST) {
+      // F0 = grad z with z = sum_i F0_i . x_i (U_b = -z)
       for (int a = tid; a < ns; a += kCvBlock) {
         const float4 f = cforce[R.sol_off + a];
         W.g[R.sol_off + a] = f;
         gq += ((double)f.x * f.x + (double)f.y * f.y + (double)f.z * f.z) * igm0[R.uoff + a];
+        const int4 x = W.xq[W.inv[R.uoff + a]];
+        zacc += (double)f.x * ((double)x.x * kInvQ) + (double)f.y * ((double)x.y * kInvQ) +
+                (double)f.z * ((double)x.z * kInvQ);
       }
     }
     const double zs = block_sum<kCvBlock>(zacc, s_red);
@@ -973,16 +1069,7 @@ __global__ __launch_bounds__(kCvBlock) void k_cv(const RepInfo *__restrict__ inf
   if (inc_step && r == 0 && tid == 0) *step += 1;
 }
 
-// replica scalars from the CV partials (fixed order)
-__device__ __forceinline__ void cv_sums(const RepInfo &R, const Work &W, int r, double &z,
-                                        double &G) {
-  z = 0.0;
-  G = 0.0;
-  for (int b = 0; b < R.cv_blocks; ++b) {
-    z += W.zpart[(size_t)r * kMaxCvBlocks + b];
-    G += W.gpart[(size_t)r * kMaxCvBlocks + b];
-  }
-}
+
 
 // vp_forces output: total force (fixed point + bias) in user order.
 __global__ __launch_bounds__(kBlock) void k_force_out(const RepInfo *__restrict__ info,
@@ -1011,6 +1098,7 @@ __global__ __launch_bounds__(kBlock) void k_force_out(const RepInfo *__restrict_
     f1 += c * g.y;
     f2 += c * g.z;
   }
+  if (W.flags[r] & VP_REPLICA_LIST_OVERFLOW) f0 = f1 = f2 = NAN;  // pairs were left out
   float *o = f_user + 3ll * (R.uoff + a);
   o[0] = (float)f0;
   o[1] = (float)f1;
@@ -1082,28 +1170,15 @@ __global__ __launch_bounds__(kBlock) void k_scatter_dirs(const RepInfo *__restri
   }
 }
 
-// energy columns: LJ, RF, bond, angle, bias, z, z_ref, S
+// vp_forces energy table: the VP_E_* columns of every replica
 __global__ void k_energy_out(const RepInfo *__restrict__ info, const RepState *__restrict__ state,
                              Work W, double t, double *__restrict__ e_out) {
   const int r = blockIdx.x;
   if (threadIdx.x != 0) return;
   const RepInfo &R = info[r];
-  double e[4] = {0, 0, 0, 0};
-  for (int bb = R.blk0; bb < R.blk0 + R.npad / kBlk; ++bb)
-    for (int k = 0; k < 4; ++k) e[k] += W.epart[4 * (size_t)bb + k];
-  double z, G, zr, ub;
-  cv_sums(R, W, r, z, G);
-  const RepState &S = state[r];
-  const double c = bias_coef(R, z, S.z0, S.z_m, t, false, zr, ub);
-  double *o = e_out + 8 * (size_t)r;
-  o[0] = e[0];
-  o[1] = e[1];
-  o[2] = e[2];
-  o[3] = e[3];
-  o[4] = ub;
-  o[5] = (R.bias == VP_BIAS_CONST || R.bias == VP_BIAS_NONE) ? 0.0 : z;
-  o[6] = zr;
-  o[7] = c * c * G;
+  double *o = e_out + VP_E_COUNT * (size_t)r;
+  energy_columns(R, W, r, state[r].z0, state[r].z_m, t, o);
+  o[VP_E_STATUS] = (W.flags[r] & VP_REPLICA_LIST_OVERFLOW) ? (double)VP_REPLICA_LIST_OVERFLOW : 0.0;
 }
 
 // native contact map of the product X_f: cmap[i][j] = C~(|xf_j - xf_i|) for
@@ -1131,29 +1206,42 @@ static inline int xcd_grid(int nb) { return 8 * ((nb + 7) / 8); }
 
 size_t force_lds_bytes(const vp_system *s) {
   size_t stage = sizeof(int4) * ((size_t)(s->stage_cap_max + 1) + (size_t)(s->ntypes_max + 1));
-  // logical partial sums: forces FP32 [3][kLogicalParts][64], energies FP64 [2][kLogicalParts][64]
-  size_t red = (sizeof(float) * 3 + sizeof(double) * 2) * kLogicalParts * kBlk;
+  // logical partial sums: forces FP32 [3][kLogicalParts][64]
+  size_t red = sizeof(float) * 3 * kLogicalParts * kBlk;
+  return stage > red ? stage : red;
+}
+
+size_t energy_lds_bytes(const vp_system *s) {
+  size_t stage = sizeof(int4) * ((size_t)(s->stage_cap_max + 1) + (size_t)(s->ntypes_max + 1));
+  size_t red = sizeof(double) * 8 * kParts * kBlk;  // [8 values][kParts][64] FP64
   return stage > red ? stage : red;
 }
 
 // the tile shapes the force kernel is built for: (waves per block, entries per batch)
 const ForceShape kForceShapes[kNumForceShapes] = {{8, 8}, {16, 4}, {8, 4}, {4, 8}};
 
-template <bool E, int P, int U, int M>
+template <int P, int U, int M>
 static hipError_t set_lds(int lds) {
-  return hipFuncSetAttribute((const void *)k_forces<E, P, U, M>, hipFuncAttributeMaxDynamicSharedMemorySize,
+  return hipFuncSetAttribute((const void *)k_forces<P, U, M>, hipFuncAttributeMaxDynamicSharedMemorySize,
                              lds);
 }
 
 hipError_t prepare_forces(const vp_system *s) {
   const int lds = (int)force_lds_bytes(s);
   hipError_t e = hipSuccess;
-  for (hipError_t x : {set_lds<false, 8, 8, 1>(lds), set_lds<true, 8, 8, 1>(lds),
-                       set_lds<false, 16, 4, 1>(lds), set_lds<true, 16, 4, 1>(lds),
-                       set_lds<false, 8, 4, 1>(lds), set_lds<true, 8, 4, 1>(lds),
-                       set_lds<false, 4, 8, 1>(lds), set_lds<true, 4, 8, 1>(lds)})
+  for (hipError_t x : {set_lds<8, 8, 1>(lds), set_lds<16, 4, 1>(lds), set_lds<8, 4, 1>(lds),
+                       set_lds<4, 8, 1>(lds)})
     if (x != hipSuccess) e = x;
   return e;
+}
+
+hipError_t prepare_energies(const vp_system *s) {
+  const int lds = (int)energy_lds_bytes(s);
+  hipError_t e = hipFuncSetAttribute((const void *)k_pair_energy<false>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+  hipError_t e2 = hipFuncSetAttribute((const void *)k_pair_energy<true>,
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+  return e != hipSuccess ? e : e2;
 }
 
 void launch_native_map(const float *xf, int ns, int min_sep, float r0, float rs, float rc,
@@ -1163,46 +1251,55 @@ void launch_native_map(const float *xf, int ns, int min_sep, float r0, float rs,
                      min_sep, r0, rs, rc, out);
 }
 
-template <bool E, int P, int U, int M>
+template <int P, int U, int M>
 static void launch_forces_t(vp_system *s, Work &W, const int32_t *blist, int nblk, hipStream_t st) {
-  hipLaunchKernelGGL((k_forces<E, P, U, M>), dim3(xcd_grid(nblk)), dim3(64 * P), force_lds_bytes(s), st,
+  hipLaunchKernelGGL((k_forces<P, U, M>), dim3(xcd_grid(nblk)), dim3(64 * P), force_lds_bytes(s), st,
                      s->info, W, s->tile_rep, s->tile_first, blist, nblk, s->types, s->stage_cap_max + 1);
 }
 
-void launch_forces_shape(vp_system *s, Work &W, bool energy, int shape, const int32_t *blist, int nblk,
-                         hipStream_t st) {
-  switch (shape * 2 + (energy ? 1 : 0)) {
-    case 0: launch_forces_t<false, 8, 8, 1>(s, W, blist, nblk, st); break;
-    case 1: launch_forces_t<true, 8, 8, 1>(s, W, blist, nblk, st); break;
-    case 2: launch_forces_t<false, 16, 4, 1>(s, W, blist, nblk, st); break;
-    case 3: launch_forces_t<true, 16, 4, 1>(s, W, blist, nblk, st); break;
-    case 4: launch_forces_t<false, 8, 4, 1>(s, W, blist, nblk, st); break;
-    case 5: launch_forces_t<true, 8, 4, 1>(s, W, blist, nblk, st); break;
-    case 6: launch_forces_t<false, 4, 8, 1>(s, W, blist, nblk, st); break;
-    default: launch_forces_t<true, 4, 8, 1>(s, W, blist, nblk, st); break;
+void launch_forces_shape(vp_system *s, Work &W, int shape, const int32_t *blist, int nblk, hipStream_t st) {
+  switch (shape) {
+    case 0: launch_forces_t<8, 8, 1>(s, W, blist, nblk, st); break;
+    case 1: launch_forces_t<16, 4, 1>(s, W, blist, nblk, st); break;
+    case 2: launch_forces_t<8, 4, 1>(s, W, blist, nblk, st); break;
+    default: launch_forces_t<4, 8, 1>(s, W, blist, nblk, st); break;
   }
 }
 
-void launch_pair_forces(vp_system *s, Work &W, bool energy, hipStream_t st) {
+void launch_pair_forces(vp_system *s, Work &W, hipStream_t st) {
   if (s->force_plan.empty()) {
-    launch_forces_shape(s, W, energy, s->force_shape, nullptr, s->n_blocks, st);
+    launch_forces_shape(s, W, s->force_shape, nullptr, s->n_blocks, st);
     return;
   }
-  for (const auto &g : s->force_plan) launch_forces_shape(s, W, energy, g.shape, g.blist, g.nblk, st);
+  for (const auto &g : s->force_plan) launch_forces_shape(s, W, g.shape, g.blist, g.nblk, st);
 }
 
-void launch_bonded(vp_system *s, Work &W, bool energy, hipStream_t st) {
-  if (energy)
-    hipLaunchKernelGGL(k_bonded<true>, dim3(xcd_grid(s->n_blocks)), dim3(kBlk), 0, st, s->info, W,
-                       s->tile_rep, s->tile_first, s->n_blocks, s->bt_start, s->bterms);
-  else
-    hipLaunchKernelGGL(k_bonded<false>, dim3(xcd_grid(s->n_blocks)), dim3(kBlk), 0, st, s->info, W,
-                       s->tile_rep, s->tile_first, s->n_blocks, s->bt_start, s->bterms);
+void launch_bonded(vp_system *s, Work &W, hipStream_t st) {
+  hipLaunchKernelGGL((k_bonded<false, false>), dim3(xcd_grid(s->n_blocks)), dim3(kBlk), 0, st, s->info, W,
+                     s->tile_rep, s->tile_first, s->n_blocks, s->bt_start, s->bterms, s->step, 1);
 }
 
-void launch_forces(vp_system *s, Work &W, bool energy, hipStream_t st) {
-  launch_pair_forces(s, W, energy, st);
-  launch_bonded(s, W, energy, st);
+void launch_forces(vp_system *s, Work &W, hipStream_t st) {
+  launch_pair_forces(s, W, st);
+  launch_bonded(s, W, st);
+}
+
+void launch_energies(vp_system *s, Work &W, bool gated, hipStream_t st) {
+  const size_t lds = energy_lds_bytes(s);
+  const int nout = s->opt.nst_out > 0 ? s->opt.nst_out : 1;
+  if (gated) {
+    hipLaunchKernelGGL(k_pair_energy<true>, dim3(xcd_grid(s->n_blocks)), dim3(kForceThreads), lds, st,
+                       s->info, W, s->tile_rep, s->tile_first, s->n_blocks, s->types, s->stage_cap_max + 1,
+                       s->step, nout);
+    hipLaunchKernelGGL((k_bonded<true, true>), dim3(xcd_grid(s->n_blocks)), dim3(kBlk), 0, st, s->info, W,
+                       s->tile_rep, s->tile_first, s->n_blocks, s->bt_start, s->bterms, s->step, nout);
+  } else {
+    hipLaunchKernelGGL(k_pair_energy<false>, dim3(xcd_grid(s->n_blocks)), dim3(kForceThreads), lds, st,
+                       s->info, W, s->tile_rep, s->tile_first, s->n_blocks, s->types, s->stage_cap_max + 1,
+                       s->step, nout);
+    hipLaunchKernelGGL((k_bonded<true, false>), dim3(xcd_grid(s->n_blocks)), dim3(kBlk), 0, st, s->info, W,
+                       s->tile_rep, s->tile_first, s->n_blocks, s->bt_start, s->bterms, s->step, nout);
+  }
 }
 
 void launch_cv(vp_system *s, Work &W, int inc_step, hipStream_t st, bool tan) {

@@ -10,6 +10,10 @@
 // S = c^2 sum_i |dz/dx_i|^2/(gamma_i m_i) = sum_i |F_i^bias|^2/(gamma_i m_i).
 // A FINISH and the next START are fused into one launch inside a block of
 // steps.  INIT evaluates S_0 at creation (Phi_acc = S_0/2: trapezoid weight).
+// A replica whose status has a flag (unstable, or a pair list that overflowed)
+// is frozen.  On record steps (nst_out > 0 divides the completed step) FINISH
+// also leaves each tile's kinetic energy of the completed velocities in
+// ke_tile for the energy record.
 #include "vp_device.h"
 #include "vp_launch.h"
 
@@ -29,8 +33,10 @@ __global__ __launch_bounds__(kBlock) void k_integrate(const RepInfo *__restrict_
                                                       const int32_t *__restrict__ tile_rep,
                                                       const int32_t *__restrict__ tile_first,
                                                       int ntiles,
-                                                      const long long *__restrict__ step) {
+                                                      const long long *__restrict__ step,
+                                                      const double *__restrict__ mass0, int nst_out) {
   __shared__ float s_max[kBlock / 64];
+  __shared__ double s_red[kBlock / 64];
   const int tile = xcd_tile(blockIdx.x, ntiles);
   if (tile < 0) return;
   const int r = tile_rep[tile];
@@ -62,7 +68,7 @@ __global__ __launch_bounds__(kBlock) void k_integrate(const RepInfo *__restrict_
         gd[d] += W.tgpart[((size_t)r * kMaxCvBlocks + b) * 2 + d];
       }
     for (int d = 0; d < 2; ++d) cd[d] = dcdz * zd[d] + dcdth[d];
-    if (p == 0 && (MODE & (MODE_INIT | MODE_FINISH)) && !(S.status & VP_REPLICA_UNSTABLE)) {
+    if (p == 0 && (MODE & (MODE_INIT | MODE_FINISH)) && !S.status) {
       for (int d = 0; d < 2; ++d) {
         const double sd = 2.0 * c * cd[d] * G + c * c * gd[d];
         S.pd_acc[d] = init ? 0.5 * sd : S.pd_acc[d] + sd;
@@ -86,7 +92,13 @@ __global__ __launch_bounds__(kBlock) void k_integrate(const RepInfo *__restrict_
   }
   if (init) return;
   float disp = 0.0f;
-  const int status = S.status & VP_REPLICA_UNSTABLE;
+  const bool rec = (MODE & MODE_FINISH) && nst_out > 0 && n % nst_out == 0;  // uniform
+  double ke = 0.0;
+  const int status = S.status;
+  if (rec && p < R.n && status) {  // a frozen replica keeps its velocities
+    const float4 v = W.vel[slot];
+    ke = 0.5 * mass0[R.uoff + W.orig[slot]] * ((double)v.x * v.x + (double)v.y * v.y + (double)v.z * v.z);
+  }
   if (p < R.n && !status) {
     const int a = W.orig[slot];
     double f0 = from_fix(W.F[slot]), f1 = from_fix(W.F[W.fstride + slot]),
@@ -109,6 +121,7 @@ __global__ __launch_bounds__(kBlock) void k_integrate(const RepInfo *__restrict_
         v.x += kx;
         v.y += ky;
         v.z += kz;
+        if (rec) ke = 0.5 * mass0[R.uoff + a] * ((double)v.x * v.x + (double)v.y * v.y + (double)v.z * v.z);
       }
       if (MODE & MODE_START) {
         // positions are fixed point (unit 2^-24 nm): each drift is rounded once
@@ -172,6 +185,10 @@ __global__ __launch_bounds__(kBlock) void k_integrate(const RepInfo *__restrict_
         }
       }
     }
+  }
+  if (rec) {
+    const double k = block_sum<kBlock>(ke, s_red);
+    if (threadIdx.x == 0) W.ke_tile[tile] = k;
   }
   if (MODE & MODE_START) {
     disp = wave_max(disp);
@@ -349,22 +366,23 @@ template <bool TAN>
 static void launch_integrate_t(vp_system *s, int mode, hipStream_t st) {
   dim3 g(xcd_grid(s->n_tiles)), b(kBlock);
   Work &W = s->traj;
+  const int nout = s->opt.nst_out;
   switch (mode) {
     case MODE_START:
       hipLaunchKernelGGL((k_integrate<MODE_START, TAN>), g, b, 0, st, s->info, s->state, W,
-                         s->tile_rep, s->tile_first, s->n_tiles, s->step);
+                         s->tile_rep, s->tile_first, s->n_tiles, s->step, s->mass0, nout);
       break;
     case MODE_FINISH:
       hipLaunchKernelGGL((k_integrate<MODE_FINISH, TAN>), g, b, 0, st, s->info, s->state, W,
-                         s->tile_rep, s->tile_first, s->n_tiles, s->step);
+                         s->tile_rep, s->tile_first, s->n_tiles, s->step, s->mass0, nout);
       break;
     case MODE_FINISH | MODE_START:
       hipLaunchKernelGGL((k_integrate<MODE_FINISH | MODE_START, TAN>), g, b, 0, st, s->info,
-                         s->state, W, s->tile_rep, s->tile_first, s->n_tiles, s->step);
+                         s->state, W, s->tile_rep, s->tile_first, s->n_tiles, s->step, s->mass0, nout);
       break;
     default:
       hipLaunchKernelGGL((k_integrate<MODE_INIT, TAN>), g, b, 0, st, s->info, s->state, W,
-                         s->tile_rep, s->tile_first, s->n_tiles, s->step);
+                         s->tile_rep, s->tile_first, s->n_tiles, s->step, s->mass0, nout);
   }
 }
 

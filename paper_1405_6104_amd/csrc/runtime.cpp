@@ -34,16 +34,63 @@ vp_status fail(vp_status st, const std::string &msg) {
       return fail(VP_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_));   \
   } while (0)
 
+// Device memory through the caller's allocator (vp_options.dev_alloc) when
+// one is given, else hipMalloc.
+void *raw_alloc(const vp_system *s, size_t bytes) {
+  if (s->opt.dev_alloc) return s->opt.dev_alloc(bytes, s->opt.alloc_ctx);
+  void *q = nullptr;
+  return hipMalloc(&q, bytes) == hipSuccess ? q : nullptr;
+}
+
+void raw_free(const vp_system *s, void *q) {
+  if (!q) return;
+  if (s->opt.dev_free)
+    s->opt.dev_free(q, s->opt.alloc_ctx);
+  else
+    (void)hipFree(q);
+}
+
 template <class T>
 vp_status dalloc(vp_system *s, T **p, size_t count) {
   *p = nullptr;
   if (count == 0) count = 1;
-  void *q = nullptr;
-  hipError_t e = hipMalloc(&q, sizeof(T) * count);
-  if (e != hipSuccess) return fail(VP_ERR_NOMEM, "hipMalloc failed: " + std::to_string(sizeof(T) * count) + " bytes");
+  void *q = raw_alloc(s, sizeof(T) * count);
+  if (!q) return fail(VP_ERR_NOMEM, "device allocation failed: " + std::to_string(sizeof(T) * count) + " bytes");
   s->allocations.push_back(q);
+  s->device_bytes += (int64_t)(sizeof(T) * count);
   *p = (T *)q;
   return VP_OK;
+}
+
+// A temporary device buffer of a diagnostic call, released on scope exit.
+struct TmpBuf {
+  const vp_system *s;
+  void *p = nullptr;
+  TmpBuf(const vp_system *sys, size_t bytes) : s(sys) { p = raw_alloc(sys, bytes ? bytes : 1); }
+  ~TmpBuf() { raw_free(s, p); }
+  TmpBuf(const TmpBuf &) = delete;
+  TmpBuf &operator=(const TmpBuf &) = delete;
+};
+
+// Ordering of the calls of one system across streams: an asynchronous call
+// first waits for the previous call's work if that went to another stream,
+// and records the system's event after its own work.
+hipError_t begin_async(vp_system *s, hipStream_t st) {
+  if (s->done_valid && st != s->last_stream) return hipStreamWaitEvent(st, s->done, 0);
+  return hipSuccess;
+}
+
+hipError_t end_async(vp_system *s, hipStream_t st) {
+  hipError_t e = hipEventRecord(s->done, st);
+  s->done_valid = e == hipSuccess;
+  s->last_stream = st;
+  return e;
+}
+
+// Waits for all work of the system's calls.
+hipError_t sync_system(vp_system *s) {
+  if (s->done_valid) return hipEventSynchronize(s->done);
+  return hipSuccess;
 }
 
 template <class T>
@@ -107,6 +154,9 @@ vp_status validate(const vp_replica_desc &d, int r, bool tangent) {
     if (!(d.bias_k >= 0) || !(d.ramp_rate >= 0)) return bad("bias_k and ramp_rate must be >= 0");
   if (d.bias == VP_BIAS_RG && d.n_solute > kMaxSoluteLds)
     return bad("the radius-of-gyration bias takes at most 4096 solute atoms");
+  if (std::isnan(d.reach_tol) || std::isnan(d.reach_rmsd)) return bad("reach_tol and reach_rmsd must not be NaN");
+  if (std::isfinite(d.reach_rmsd) && (!d.x_final || d.n_solute < 1))
+    return bad("an RMSD criterion (finite reach_rmsd) needs x_final");
   return VP_OK;
 }
 
@@ -138,8 +188,9 @@ static vp_status alloc_work(vp_system *s, Work &W, bool traj) {
   TRY(dalloc(s, &W.ztile, (size_t)std::max<int64_t>(1, s->n_cv_tiles)));
   TRY(dalloc(s, &W.zpart, R * kMaxCvBlocks));
   TRY(dalloc(s, &W.gpart, R * kMaxCvBlocks));
-  TRY(dalloc(s, &W.epart, 4 * B));
+  TRY(dalloc(s, &W.epart, (size_t)kEp * B));
   TRY(dalloc(s, &W.flags, R));
+  if (traj) TRY(dalloc(s, &W.ke_tile, (size_t)s->n_tiles));
   if (s->tangent) {
     const size_t CT = (size_t)std::max<int64_t>(1, s->n_cv_tiles) * kCvTile;
     const size_t NS = (size_t)std::max<int64_t>(1, s->n_solute_total);
@@ -166,7 +217,9 @@ static vp_status alloc_work(vp_system *s, Work &W, bool traj) {
   HIPCHECK(hipMemset(W.wrap, 0, sizeof(int32_t) * S));
   HIPCHECK(hipMemset(W.zpart, 0, sizeof(double) * R * kMaxCvBlocks));
   HIPCHECK(hipMemset(W.gpart, 0, sizeof(double) * R * kMaxCvBlocks));
-  HIPCHECK(hipMemset(W.epart, 0, sizeof(double) * 4 * B));
+  HIPCHECK(hipMemset(W.epart, 0, sizeof(double) * kEp * B));
+  HIPCHECK(hipMemset(W.flags, 0, sizeof(int32_t) * R));
+  if (traj) HIPCHECK(hipMemset(W.ke_tile, 0, sizeof(double) * (size_t)s->n_tiles));
   HIPCHECK(hipMemset(W.F, 0, sizeof(long long) * 3 * S));
   return VP_OK;
 }
@@ -180,8 +233,9 @@ static void free_all(vp_system *s) {
     (void)hipGraphExecDestroy(g.exec);
   }
   s->graphs.clear();
-  for (void *p : s->allocations) (void)hipFree(p);
+  for (void *p : s->allocations) raw_free(s, p);
   s->allocations.clear();
+  s->device_bytes = 0;
 }
 
 // distinct (charge, sigma, epsilon) classes of a replica (its type-table size)
@@ -250,7 +304,7 @@ static vp_status build(vp_system *s, const vp_replica_desc *reps, int32_t n_reps
   for (int r = 0; r < n_reps; ++r) ntypes_all = std::max(ntypes_all, count_types(reps[r]));
   s->R = n_reps;
   s->info_h.resize(n_reps);
-  int64_t off = 0, uoff = 0, cell0 = 0, list_off = 0, sol_off = 0, cv_tiles = 0;
+  int64_t off = 0, uoff = 0, cell0 = 0, list_off = 0, sol_off = 0, cv_tiles = 0, xf_rows = 0;
   int32_t tile0 = 0, type_off = 0;
   std::vector<int32_t> tile_rep, tile_first;
   std::vector<float4> types;
@@ -337,6 +391,12 @@ static vp_status build(vp_system *s, const vp_replica_desc *reps, int32_t n_reps
     R.kT = d.kT;
     R.dt = d.dt;
     R.reach_tol = d.reach_tol;
+    R.reach_rmsd = d.reach_rmsd;
+    R.xf_off = -1;
+    if (d.x_final && d.n_solute > 0) {
+      R.xf_off = (int32_t)xf_rows;
+      xf_rows += d.n_solute;
+    }
     R.seed = d.seed;
     // (charge, sigma, epsilon) classes of this replica; the last entry is inert
     {
@@ -419,11 +479,14 @@ static vp_status build(vp_system *s, const vp_replica_desc *reps, int32_t n_reps
     stage_cap_max = 0;
     for (int r = 0; r < n_reps; ++r) {
       RepInfo &R = s->info_h[r];
-      const long long want = std::min<long long>({(long long)kMaxStage, budget, 27ll * R.n + 8});
-      if (want < R.stage_cap)
+      long long want = std::min<long long>({(long long)kMaxStage, budget, 27ll * R.n + 8});
+      if (o.stage_cap > 0) {
+        want = std::min<long long>(want, o.stage_cap);  // diagnostic: exact-mode builds
+      } else if (want < R.stage_cap) {
         return fail(VP_ERR_ARG, "replica " + std::to_string(r) + ": its neighbourhoods need " +
                                     std::to_string(R.stage_cap) + " staged atoms; the force kernel's LDS holds " +
                                     std::to_string(want));
+      }
       R.stage_cap = (int32_t)want;
       stage_cap_max = std::max(stage_cap_max, R.stage_cap);
     }
@@ -433,6 +496,7 @@ static vp_status build(vp_system *s, const vp_replica_desc *reps, int32_t n_reps
       return fail(VP_ERR_ARG, "force kernel would need " + std::to_string(need) +
                                   " bytes of LDS per workgroup (limit " + std::to_string(kMaxLds) + ")");
     HIPCHECK(prepare_forces(s));
+    HIPCHECK(prepare_energies(s));
     if (s->tangent) {
       const size_t tneed = tangent_lds_bytes(s);
       if (tneed > (size_t)kMaxLdsTangent)
@@ -453,6 +517,7 @@ static vp_status build(vp_system *s, const vp_replica_desc *reps, int32_t n_reps
   std::vector<std::vector<BTerm>> terms(U);
   std::vector<std::vector<int32_t>> excl(U);
   std::vector<float4> cforce(std::max<int64_t>(1, s->n_solute_total), make_float4(0, 0, 0, 0));
+  std::vector<double> xf_h(3 * (size_t)std::max<int64_t>(1, xf_rows), 0.0);
   for (int r = 0; r < n_reps; ++r) {
     const vp_replica_desc &d = reps[r];
     const RepInfo &R = s->info_h[r];
@@ -489,6 +554,8 @@ static vp_status build(vp_system *s, const vp_replica_desc *reps, int32_t n_reps
       excl[R.uoff + i].push_back(j);
       excl[R.uoff + j].push_back(i);
     }
+    if (R.xf_off >= 0)
+      std::memcpy(&xf_h[3 * (size_t)R.xf_off], d.x_final, sizeof(double) * 3 * (size_t)d.n_solute);
     if (d.bias == VP_BIAS_CONST)
       for (int i = 0; i < d.n_solute; ++i)
         cforce[R.sol_off + i] = make_float4((float)d.const_force[3 * i], (float)d.const_force[3 * i + 1],
@@ -527,6 +594,12 @@ static vp_status build(vp_system *s, const vp_replica_desc *reps, int32_t n_reps
   TRY(upload(s, &s->ex_start, ex_start));
   TRY(upload(s, &s->ex_list, ex_list));
   TRY(upload(s, &s->cforce, cforce));
+  TRY(upload(s, &s->xf, xf_h));
+  TRY(dalloc(s, &s->rmsd, (size_t)n_reps));
+  if (o.nst_out > 0) {
+    s->out_cap = o.out_capacity > 0 ? o.out_capacity : 1024;
+    TRY(dalloc(s, &s->records, (size_t)n_reps * s->out_cap * VP_REC_COUNT));
+  }
   TRY(dalloc(s, &s->cmap, (size_t)std::max<int64_t>(1, cmap_total)));
   for (size_t m = 0; m < maps.size(); ++m) {
     const MapKey &k = maps[m];
@@ -571,9 +644,14 @@ static vp_status build(vp_system *s, const vp_replica_desc *reps, int32_t n_reps
   HIPCHECK(hipMemcpy(dhv, has_v.data(), has_v.size(), hipMemcpyHostToDevice));
   launch_init_state(s, dx, dv, dhv, 0);
   launch_rebuild(s, s->traj, 0, nullptr, 0);
-  launch_forces(s, s->traj, false, 0);
+  launch_forces(s, s->traj, 0);
   launch_cv(s, s->traj, 0, 0, s->tangent);
   launch_integrate(s, INT_INIT, 0);
+  if (o.nst_out > 0) {  // the record of step 0
+    launch_energies(s, s->traj, false, 0);
+    launch_kinetic(s, s->traj.ke_tile, 0);
+    launch_record(s, false, 0);
+  }
   HIPCHECK(hipGetLastError());
   HIPCHECK(hipDeviceSynchronize());
   return VP_OK;
@@ -605,7 +683,7 @@ static void make_buckets(vp_system *s) {
 // recompute the full forces of the current state (the same values as before,
 // whatever the tile shape).
 static vp_status restore_forces(vp_system *s) {
-  launch_forces(s, s->traj, false, 0);
+  launch_forces(s, s->traj, 0);
   HIPCHECK(hipGetLastError());
   HIPCHECK(hipDeviceSynchronize());
   return VP_OK;
@@ -621,7 +699,7 @@ static vp_status time_plan(vp_system *s, const std::vector<vp_system::ForceLaunc
   hipError_t e = hipSuccess;
   for (int k = 0; k <= reps && e == hipSuccess; ++k) {
     e = hipEventRecord(a, 0);
-    for (const auto &g : plan) launch_forces_shape(s, s->traj, false, g.shape, g.blist, g.nblk, 0);
+    for (const auto &g : plan) launch_forces_shape(s, s->traj, g.shape, g.blist, g.nblk, 0);
     if (e == hipSuccess) e = hipEventRecord(b, 0);
     if (e == hipSuccess) e = hipEventSynchronize(b);
     float t = 0.0f;
@@ -751,6 +829,10 @@ extern "C" vp_status vp_system_create(const vp_replica_desc *reps, int32_t n_rep
   if (total > ((int64_t)1 << 31) - (int64_t)kTile * n_reps) return fail(VP_ERR_ARG, "batch too large");
   if (opt && (opt->force_shape < 0 || opt->force_shape >= kNumForceShapes))
     return fail(VP_ERR_ARG, "unknown force_shape");
+  if (opt && (opt->nst_out < 0 || opt->out_capacity < 0 || opt->stage_cap < 0))
+    return fail(VP_ERR_ARG, "nst_out, out_capacity and stage_cap must be >= 0");
+  if (opt && ((opt->dev_alloc == nullptr) != (opt->dev_free == nullptr)))
+    return fail(VP_ERR_ARG, "dev_alloc and dev_free go together");
   vp_system *s = new (std::nothrow) vp_system();
   if (!s) return fail(VP_ERR_NOMEM, "host allocation failed");
   vp_options o{};
@@ -760,6 +842,10 @@ extern "C" vp_status vp_system_create(const vp_replica_desc *reps, int32_t n_rep
   s->opt = o;
   s->tangent = o.tangent != 0;
   s->force_shape = o.force_shape;
+  if (hipEventCreateWithFlags(&s->done, hipEventDisableTiming) != hipSuccess) {
+    delete s;
+    return fail(VP_ERR_HIP, "hipEventCreate failed");
+  }
   vp_status st = build(s, reps, n_reps);
   // List capacity: sized from the mean density, then checked against the
   // first build; a replica whose longest list uses more than 80% of it (local
@@ -796,7 +882,9 @@ extern "C" vp_status vp_system_create(const vp_replica_desc *reps, int32_t n_rep
   }
   if (st != VP_OK) {
     std::string msg = g_err;
+    (void)hipDeviceSynchronize();
     free_all(s);
+    (void)hipEventDestroy(s->done);
     delete s;
     g_err = msg;
     return st;
@@ -809,24 +897,31 @@ extern "C" vp_status vp_system_destroy(vp_system *s) {
   if (!s) return VP_OK;
   (void)hipDeviceSynchronize();
   free_all(s);
+  (void)hipEventDestroy(s->done);
   delete s;
   return VP_OK;
 }
 
-// one block of steps: START ... FINISH, with FINISH|START fused inside
+// one block of steps: START ... FINISH, with FINISH|START fused inside; with
+// energy records, the gated energy kernels after the forces of every step and
+// the gated record kernel after every FINISH
 static void enqueue_block(vp_system *s, int steps, hipStream_t st) {
   const bool timing = s->timing;
+  const bool rec = s->opt.nst_out > 0;
   for (int k = 0; k < steps; ++k) {
     launch_integrate(s, k == 0 ? INT_START : (INT_FINISH | INT_START), st);
+    if (rec && k > 0) launch_record(s, true, st);
     launch_rebuild(s, s->traj, 0, nullptr, st);
     if (timing) (void)hipEventRecord(s->ev_before[k], st);
-    launch_pair_forces(s, s->traj, false, st);
+    launch_pair_forces(s, s->traj, st);
     if (timing) (void)hipEventRecord(s->ev_after[k], st);
-    launch_bonded(s, s->traj, false, st);
+    launch_bonded(s, s->traj, st);
+    if (rec) launch_energies(s, s->traj, true, st);
     if (s->tangent) launch_tangent_forces(s, s->traj, st);
     launch_cv(s, s->traj, 1, st, s->tangent);
   }
   launch_integrate(s, INT_FINISH, st);
+  if (rec) launch_record(s, true, st);
 }
 
 static vp_status collect_timing(vp_system *s, int steps) {
@@ -870,8 +965,8 @@ extern "C" vp_status vp_step_batch(vp_system *s, int32_t n_steps, void *hip_stre
   if (!s) return fail(VP_ERR_ARG, "system is NULL");
   if (n_steps < 0) return fail(VP_ERR_ARG, "n_steps must be >= 0");
   hipStream_t st = (hipStream_t)hip_stream;
-  s->last_stream = st;
   if (n_steps == 0) return VP_OK;
+  HIPCHECK(begin_async(s, st));
   const int B = s->opt.steps_per_graph;
   int left = n_steps;
   while (left > 0) {
@@ -888,20 +983,39 @@ extern "C" vp_status vp_step_batch(vp_system *s, int32_t n_steps, void *hip_stre
     left -= k;
   }
   s->host_step += n_steps;
+  HIPCHECK(end_async(s, st));
   return VP_OK;
 }
 
 static vp_status fetch_state(vp_system *s, std::vector<RepState> &st) {
-  HIPCHECK(hipStreamSynchronize(s->last_stream));
+  HIPCHECK(sync_system(s));
   HIPCHECK(hipGetLastError());
   st.resize(s->R);
   HIPCHECK(hipMemcpy(st.data(), s->state, sizeof(RepState) * s->R, hipMemcpyDeviceToHost));
   return VP_OK;
 }
 
+// RMSD of every replica from its X_f (NaN without one); after fetch_state.
+static vp_status fetch_rmsd(vp_system *s, std::vector<double> &rmsd) {
+  launch_rmsd(s, 0);
+  HIPCHECK(hipGetLastError());
+  rmsd.resize(s->R);
+  HIPCHECK(hipMemcpy(rmsd.data(), s->rmsd, sizeof(double) * s->R, hipMemcpyDeviceToHost));
+  return VP_OK;
+}
+
+// A flagged replica (unstable, or a pair list that overflowed) has no finite functional.
 static double phi_of(const RepInfo &R, const RepState &S) {
-  if (S.status & VP_REPLICA_UNSTABLE) return INFINITY;
+  if (S.status) return INFINITY;
   return (S.phi_acc - 0.5 * S.s_last) * R.dt / (4.0 * R.kT);
+}
+
+// The product criterion of vp_select_path.
+static bool reached_of(const RepInfo &R, const RepState &S, double rmsd) {
+  if (S.status) return false;
+  if (!(std::fabs(S.z_last - R.z_target) <= R.reach_tol)) return false;
+  if (std::isfinite(R.reach_rmsd) && !(rmsd <= R.reach_rmsd)) return false;
+  return true;
 }
 
 extern "C" vp_status vp_functional(vp_system *s, double *phi_host, double *dphi_dtheta_host) {
@@ -915,7 +1029,7 @@ extern "C" vp_status vp_functional(vp_system *s, double *phi_host, double *dphi_
     phi_host[r] = phi_of(R, st[r]);
     if (dphi_dtheta_host)
       for (int d = 0; d < 2; ++d)
-        dphi_dtheta_host[2 * r + d] = (st[r].status & VP_REPLICA_UNSTABLE)
+        dphi_dtheta_host[2 * r + d] = st[r].status
                                           ? NAN
                                           : (st[r].pd_acc[d] - 0.5 * st[r].pd_last[d]) * R.dt / (4.0 * R.kT);
   }
@@ -928,17 +1042,17 @@ extern "C" vp_status vp_debug_trajectory_state(vp_system *s, double *x_host, dou
   if ((xt_host || vt_host || pd_host) && !s->tangent)
     return fail(VP_ERR_STATE, "derivatives were not enabled at creation (vp_options.tangent)");
   if ((xt_host == nullptr) != (vt_host == nullptr)) return fail(VP_ERR_ARG, "xt and vt go together");
-  HIPCHECK(hipStreamSynchronize(s->last_stream));
+  HIPCHECK(sync_system(s));
   const size_t n3 = 3 * (size_t)s->n_users;
-  double *d = nullptr;
-  HIPCHECK(hipMalloc(&d, sizeof(double) * n3 * 6));
+  TmpBuf buf(s, sizeof(double) * n3 * 6);
+  if (!buf.p) return fail(VP_ERR_NOMEM, "device allocation failed");
+  double *d = (double *)buf.p;
   launch_export_state(s, d, d + n3, xt_host ? d + 2 * n3 : nullptr, xt_host ? d + 4 * n3 : nullptr, 0);
   hipError_t e = hipDeviceSynchronize();
   if (e == hipSuccess) e = hipMemcpy(x_host, d, sizeof(double) * n3, hipMemcpyDeviceToHost);
   if (e == hipSuccess) e = hipMemcpy(v_host, d + n3, sizeof(double) * n3, hipMemcpyDeviceToHost);
   if (e == hipSuccess && xt_host) e = hipMemcpy(xt_host, d + 2 * n3, sizeof(double) * 2 * n3, hipMemcpyDeviceToHost);
   if (e == hipSuccess && vt_host) e = hipMemcpy(vt_host, d + 4 * n3, sizeof(double) * 2 * n3, hipMemcpyDeviceToHost);
-  (void)hipFree(d);
   if (e != hipSuccess) return fail(VP_ERR_HIP, hipGetErrorString(e));
   if (pd_host) {
     std::vector<RepState> st;
@@ -962,12 +1076,13 @@ extern "C" vp_status vp_debug_force_dir(vp_system *s, const float *x_dev, const 
     TRY(alloc_work(s, s->eval, false));
     s->eval_ready = true;
   }
-  s->last_stream = st;
+  HIPCHECK(begin_async(s, st));
   launch_rebuild(s, s->eval, 1, x_dev, st);
-  launch_forces(s, s->eval, false, st);
+  launch_forces(s, s->eval, st);
   launch_cv(s, s->eval, 0, st, false);
   launch_force_dir(s, s->eval, dx_dev, t, out_dev, st);
   HIPCHECK(hipGetLastError());
+  HIPCHECK(end_async(s, st));
   return VP_OK;
 }
 
@@ -978,11 +1093,12 @@ extern "C" vp_status vp_select_path(vp_system *s, const uint8_t *eligible, int32
   *best_phi = INFINITY;
   std::vector<RepState> st;
   TRY(fetch_state(s, st));
+  std::vector<double> rmsd;
+  TRY(fetch_rmsd(s, rmsd));
   for (int r = 0; r < s->R; ++r) {
     const RepInfo &R = s->info_h[r];
     double phi = phi_of(R, st[r]);
-    bool reached = std::fabs(st[r].z_last - R.z_target) <= R.reach_tol;
-    if (!reached || (eligible && !eligible[r]) || !std::isfinite(phi)) continue;
+    if (!reached_of(R, st[r], rmsd[r]) || (eligible && !eligible[r]) || !std::isfinite(phi)) continue;
     if (*best < 0 || phi < *best_phi) {
       *best = r;
       *best_phi = phi;
@@ -997,25 +1113,28 @@ extern "C" vp_status vp_forces(vp_system *s, const float *x_dev, float *f_dev, d
   if (!s || !x_dev || !f_dev) return fail(VP_ERR_ARG, "NULL argument");
   hipStream_t st = (hipStream_t)hip_stream;
   if (!s->eval_ready) {
-    HIPCHECK(hipDeviceSynchronize());
+    HIPCHECK(sync_system(s));
     TRY(alloc_work(s, s->eval, false));
     s->eval_ready = true;
   }
-  s->last_stream = st;
+  HIPCHECK(begin_async(s, st));
   launch_rebuild(s, s->eval, 1, x_dev, st);
-  launch_forces(s, s->eval, energy_dev != nullptr, st);
+  launch_forces(s, s->eval, st);
+  if (energy_dev) launch_energies(s, s->eval, false, st);
   launch_cv(s, s->eval, 0, st, false);
   launch_force_out(s, s->eval, t, f_dev, energy_dev, st);
   HIPCHECK(hipGetLastError());
+  HIPCHECK(end_async(s, st));
   return VP_OK;
 }
 
 extern "C" vp_status vp_get_state(vp_system *s, float *x_dev, float *v_dev, void *hip_stream) {
   if (!s) return fail(VP_ERR_ARG, "NULL system");
   hipStream_t st = (hipStream_t)hip_stream;
-  s->last_stream = st;
+  HIPCHECK(begin_async(s, st));
   launch_gather_state(s, x_dev, v_dev, st);
   HIPCHECK(hipGetLastError());
+  HIPCHECK(end_async(s, st));
   return VP_OK;
 }
 
@@ -1025,12 +1144,17 @@ extern "C" vp_status vp_observables(vp_system *s, double *obs) {
   TRY(fetch_state(s, st));
   long long step = 0;
   HIPCHECK(hipMemcpy(&step, s->step, sizeof(step), hipMemcpyDeviceToHost));
-  double *ke = nullptr;
-  HIPCHECK(hipMalloc(&ke, sizeof(double) * (size_t)s->n_tiles));
+  std::vector<double> rmsd;
+  TRY(fetch_rmsd(s, rmsd));
+  std::vector<int32_t> eflags(s->R, 0);
+  if (s->eval_ready)
+    HIPCHECK(hipMemcpy(eflags.data(), s->eval.flags, sizeof(int32_t) * s->R, hipMemcpyDeviceToHost));
+  TmpBuf kebuf(s, sizeof(double) * (size_t)s->n_tiles);
+  if (!kebuf.p) return fail(VP_ERR_NOMEM, "device allocation failed");
+  double *ke = (double *)kebuf.p;
   launch_kinetic(s, ke, 0);
   std::vector<double> keh(s->n_tiles);
   hipError_t e = hipMemcpy(keh.data(), ke, sizeof(double) * keh.size(), hipMemcpyDeviceToHost);
-  (void)hipFree(ke);
   if (e != hipSuccess) return fail(VP_ERR_HIP, hipGetErrorString(e));
   for (int r = 0; r < s->R; ++r) {
     const RepInfo &R = s->info_h[r];
@@ -1052,7 +1176,38 @@ extern "C" vp_status vp_observables(vp_system *s, double *obs) {
     o[VP_OBS_EXACT_BUILDS] = st[r].exact_builds;
     o[VP_OBS_SKIN] = R.skin;
     o[VP_OBS_NSTLIST] = R.nstlist;
+    o[VP_OBS_RMSD] = rmsd[r];
+    o[VP_OBS_REACHED] = reached_of(R, st[r], rmsd[r]) ? 1.0 : 0.0;
+    o[VP_OBS_EVAL_STATUS] = (eflags[r] & VP_REPLICA_LIST_OVERFLOW) ? (double)VP_REPLICA_LIST_OVERFLOW : 0.0;
   }
+  return VP_OK;
+}
+
+extern "C" vp_status vp_energy_records(vp_system *s, double *out_host, int32_t cap, int32_t *n_records) {
+  if (!s || !n_records || cap < 0) return fail(VP_ERR_ARG, "invalid argument");
+  if (s->opt.nst_out <= 0) return fail(VP_ERR_STATE, "the system records no energies (vp_options.nst_out = 0)");
+  std::vector<RepState> st;
+  TRY(fetch_state(s, st));
+  const int written = st[0].n_records;  // the same in every replica
+  const int held = std::min(written, s->out_cap);
+  *n_records = held;
+  if (!out_host || cap == 0 || held == 0) return VP_OK;
+  std::vector<double> all((size_t)s->R * s->out_cap * VP_REC_COUNT);
+  HIPCHECK(hipMemcpy(all.data(), s->records, sizeof(double) * all.size(), hipMemcpyDeviceToHost));
+  const int take = std::min(cap, held);
+  for (int r = 0; r < s->R; ++r)
+    for (int k = 0; k < take; ++k) {
+      // oldest held record first: index written - held + k in the ring
+      const int slot = (written - held + k) % s->out_cap;
+      std::memcpy(out_host + ((size_t)r * take + k) * VP_REC_COUNT,
+                  &all[((size_t)r * s->out_cap + slot) * VP_REC_COUNT], sizeof(double) * VP_REC_COUNT);
+    }
+  return VP_OK;
+}
+
+extern "C" vp_status vp_device_bytes(const vp_system *s, int64_t *bytes) {
+  if (!s || !bytes) return fail(VP_ERR_ARG, "NULL argument");
+  *bytes = s->device_bytes;
   return VP_OK;
 }
 
@@ -1095,11 +1250,12 @@ extern "C" vp_status vp_debug_pairs(vp_system *s, int32_t rep, int32_t *pairs_ho
                                     int64_t *count) {
   if (!s || !count || (cap > 0 && !pairs_host)) return fail(VP_ERR_ARG, "NULL argument");
   if (rep < 0 || rep >= s->R) return fail(VP_ERR_ARG, "replica index out of range");
-  HIPCHECK(hipStreamSynchronize(s->last_stream));
-  int2 *d = nullptr;
-  unsigned long long *cnt = nullptr;
-  HIPCHECK(hipMalloc(&d, sizeof(int2) * (size_t)std::max<int64_t>(1, cap)));
-  HIPCHECK(hipMalloc(&cnt, sizeof(unsigned long long)));
+  HIPCHECK(sync_system(s));
+  TmpBuf dbuf(s, sizeof(int2) * (size_t)std::max<int64_t>(1, cap));
+  TmpBuf cbuf(s, sizeof(unsigned long long));
+  if (!dbuf.p || !cbuf.p) return fail(VP_ERR_NOMEM, "device allocation failed");
+  int2 *d = (int2 *)dbuf.p;
+  unsigned long long *cnt = (unsigned long long *)cbuf.p;
   HIPCHECK(hipMemset(cnt, 0, sizeof(unsigned long long)));
   launch_debug_pairs(s, s->traj, rep, d, (unsigned long long)cap, cnt, 0);
   unsigned long long c = 0;
@@ -1107,8 +1263,6 @@ extern "C" vp_status vp_debug_pairs(vp_system *s, int32_t rep, int32_t *pairs_ho
   if (e == hipSuccess && cap > 0)
     e = hipMemcpy(pairs_host, d, sizeof(int2) * (size_t)std::min<int64_t>(cap, (int64_t)c),
                   hipMemcpyDeviceToHost);
-  (void)hipFree(d);
-  (void)hipFree(cnt);
   if (e != hipSuccess) return fail(VP_ERR_HIP, hipGetErrorString(e));
   *count = (int64_t)c;
   return VP_OK;

@@ -147,7 +147,10 @@ __device__ __forceinline__ double bias_coef(const RepInfo &R, double z, double z
                                             double t, bool init, double &zr, double &ub) {
   ub = 0.0;
   zr = 0.0;
-  if (R.bias == VP_BIAS_CONST) return 1.0;
+  if (R.bias == VP_BIAS_CONST) {  // z = sum_i F0_i . x_i, U_b = -z, F^bias = grad z
+    ub = -z;
+    return 1.0;
+  }
   if (R.bias == VP_BIAS_RG || R.bias == VP_BIAS_CONTACT) {
     double zz0 = init ? z : z0;
     double w = 1.0 - R.ramp_rate * t;
@@ -185,6 +188,43 @@ __device__ __forceinline__ void bias_coef_deriv(const RepInfo &R, double z, doub
     dcdth[0] = -(z - zr);
     dcdth[1] = w < 0.0 ? 0.0 : -R.bias_k * (zz0 - R.z_target) * t;
   }
+}
+
+// replica scalars from the CV partials (fixed order)
+__device__ __forceinline__ void cv_sums(const RepInfo &R, const Work &W, int r, double &z,
+                                        double &G) {
+  z = 0.0;
+  G = 0.0;
+  for (int b = 0; b < R.cv_blocks; ++b) {
+    z += W.zpart[(size_t)r * kMaxCvBlocks + b];
+    G += W.gpart[(size_t)r * kMaxCvBlocks + b];
+  }
+}
+
+// Energy columns VP_E_LJ .. VP_E_WZZ of replica r from the per-block partials
+// (added in block order) and the CV partials, at time t with the ramp start
+// z0 and ratchet minimum zm.
+__device__ __forceinline__ void energy_columns(const RepInfo &R, const Work &W, int r, double z0,
+                                               double zm, double t, double *o) {
+  double e[4] = {0, 0, 0, 0}, w[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  for (int bb = R.blk0; bb < R.blk0 + R.npad / kBlk; ++bb) {
+    const double *p = W.epart + kEp * (size_t)bb;
+    for (int k = 0; k < 4; ++k) e[k] += p[k];
+    for (int k = 0; k < 9; ++k) w[k] += p[kEpPairW + k] + p[kEpBondW + k];
+  }
+  double z, G, zr, ub;
+  cv_sums(R, W, r, z, G);
+  const double c = bias_coef(R, z, z0, zm, t, false, zr, ub);
+  o[VP_E_LJ] = e[0];
+  o[VP_E_RF] = e[1];
+  o[VP_E_BOND] = e[2];
+  o[VP_E_ANGLE] = e[3];
+  o[VP_E_BIAS] = ub;
+  o[VP_E_Z] = R.bias == VP_BIAS_NONE ? 0.0 : z;
+  o[VP_E_ZREF] = zr;
+  o[VP_E_S] = c * c * G;
+  o[VP_E_TOTAL] = e[0] + e[1] + e[2] + e[3] + ub;
+  for (int k = 0; k < 9; ++k) o[VP_E_WXX + k] = w[k];
 }
 
 // Value and one directional derivative (forward-mode differentiation of the

@@ -41,6 +41,10 @@ constexpr float kQf = 16777216.0f;
 constexpr float kInvQf = 5.9604644775390625e-8f;  // 2^-24
 constexpr double kInvQ = 5.9604644775390625e-8;
 constexpr int kDummyCoord = 1 << 30;  // staged position of the list padding entry
+// energy partials per 64-atom block: LJ, RF, bond, angle, pair virial [9],
+// bonded virial [9] (each written by one kernel), two unused
+constexpr int kEp = 24;
+constexpr int kEpPairW = 4, kEpBondW = 13;
 
 // Constant per-replica data (device copy in an array indexed by replica).
 struct RepInfo {
@@ -75,6 +79,9 @@ struct RepInfo {
   double rc, krf, crf;
   double bias_k, ramp_rate, z_target;
   double kT, dt, reach_tol;
+  double reach_rmsd;            // +inf: no RMSD criterion
+  int32_t xf_off;               // first row of this replica's X_f in the FP64 copy, -1 without
+  int32_t pad_;
   uint64_t seed;
 };
 
@@ -94,7 +101,7 @@ struct RepState {
   int32_t stage_max;     // largest staged neighbourhood of a block so far
   int32_t list_max;      // longest per-atom list so far (entries needed, before any clamp)
   int32_t exact_builds;  // blocks built again in exact mode (staging capacity reached)
-  int32_t pad;
+  int32_t n_records;     // energy records written
   // derivative of the functional with respect to (bias_k, ramp_rate)
   double pd_acc[2];   // sum_n w_n dS_n/dtheta, w_0 = 1/2
   double pd_last[2];  // dS/dtheta at the latest step
@@ -132,7 +139,8 @@ struct Work {
   double *ztile = nullptr;        // contact map: z partials per (row tile, column tile)
   double *zpart = nullptr;        // [R][kMaxCvBlocks]
   double *gpart = nullptr;        // [R][kMaxCvBlocks] sum |g|^2/(gamma m)
-  double *epart = nullptr;        // [blocks][4] energy partials (LJ, RF, bond, angle)
+  double *epart = nullptr;        // [blocks][kEp] energy and virial partials
+  double *ke_tile = nullptr;      // [tiles] kinetic energy partials (energy records)
   int32_t *flags = nullptr;       // [R] rebuild flag for the eval context
   // tangents along (bias_k, ramp_rate) when derivatives are on: [2][slots]
   // (index p * fstride + slot), xyz used
@@ -187,6 +195,10 @@ struct vp_system {
   int32_t *ex_list = nullptr;   // replica-local user indices
   float *cmap = nullptr;        // native contact maps, [ns][ns] per distinct map
   float4 *cforce = nullptr;     // [solute total] constant bias force
+  double *xf = nullptr;         // [solute rows][3] FP64 X_f of the replicas that give one
+  double *rmsd = nullptr;       // [R] RMSD to X_f (vp_select_path, vp_observables)
+  double *records = nullptr;    // [R][out_cap][VP_REC_COUNT] energy records
+  int32_t out_cap = 0;
   // scratch shared by both contexts (list rebuild)
   int4 *xq_t = nullptr;
   float4 *vel_t = nullptr;
@@ -234,9 +246,12 @@ struct vp_system {
   std::vector<GraphEntry> graphs;
   int64_t host_step = 0;
   hipStream_t last_stream = nullptr;
+  hipEvent_t done = nullptr;  // recorded at the end of every asynchronous call
+  bool done_valid = false;
   bool timing = false;
   std::vector<hipEvent_t> ev_before, ev_after;
   double timing_ms = 0.0;
   int64_t timing_count = 0;
   std::vector<void *> allocations;
+  int64_t device_bytes = 0;
 };

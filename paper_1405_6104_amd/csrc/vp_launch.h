@@ -10,12 +10,22 @@ enum { INT_FINISH = 1, INT_START = 2, INT_INIT = 4 };
 void launch_rebuild(vp_system *s, Work &W, int mode, const float *x_user, hipStream_t st);
 void launch_debug_pairs(vp_system *s, Work &W, int rep, int2 *out, unsigned long long cap,
                         unsigned long long *counter, hipStream_t st);
-void launch_forces(vp_system *s, Work &W, bool energy, hipStream_t st);  // pair + bonded
-void launch_pair_forces(vp_system *s, Work &W, bool energy, hipStream_t st);  // k_forces launches only
-void launch_bonded(vp_system *s, Work &W, bool energy, hipStream_t st);  // adds the bonded forces
+void launch_forces(vp_system *s, Work &W, hipStream_t st);  // pair + bonded
+void launch_pair_forces(vp_system *s, Work &W, hipStream_t st);  // k_forces launches only
+void launch_bonded(vp_system *s, Work &W, hipStream_t st);  // adds the bonded forces
 // one tile shape (index into kForceShapes) over a list of blocks (NULL: all nblk blocks)
-void launch_forces_shape(vp_system *s, Work &W, bool energy, int shape, const int32_t *blist, int nblk,
+void launch_forces_shape(vp_system *s, Work &W, int shape, const int32_t *blist, int nblk,
                          hipStream_t st);
+// energy and virial partials per block into W.epart; gated: only on steps whose
+// count after the step in progress is a multiple of s->opt.nst_out
+void launch_energies(vp_system *s, Work &W, bool gated, hipStream_t st);
+size_t energy_lds_bytes(const vp_system *s);
+hipError_t prepare_energies(const vp_system *s);
+// energy record of every replica into s->records (gated: on record steps only;
+// otherwise the step just completed is recorded unconditionally)
+void launch_record(vp_system *s, bool gated, hipStream_t st);
+// RMSD of every replica's solute from its X_f into s->rmsd
+void launch_rmsd(vp_system *s, hipStream_t st);
 void launch_cv(vp_system *s, Work &W, int inc_step, hipStream_t st, bool tan);
 // derivatives along the tangents in W.tx (both directions)
 void launch_tangent_forces(vp_system *s, Work &W, hipStream_t st);
@@ -34,7 +44,7 @@ void launch_native_map(const float *xf, int ns, int min_sep, float r0, float rs,
 size_t force_lds_bytes(const vp_system *s);
 hipError_t prepare_forces(const vp_system *s);  // dynamic LDS above 64 KB
 void launch_gather_state(vp_system *s, float *x_out, float *v_out, hipStream_t st);
-void launch_kinetic(vp_system *s, double *out, hipStream_t st);
+void launch_kinetic(vp_system *s, double *out, hipStream_t st);  // per-tile partials
 // exact state in user order (device FP64 buffers; xt, vt may be NULL)
 void launch_export_state(vp_system *s, double *x, double *v, double *xt, double *vt, hipStream_t st);
 void launch_debug_noise(uint64_t seed, uint32_t atom0, uint32_t step, uint32_t tag, int n,

@@ -26,8 +26,11 @@ _ip = C.POINTER(C.c_int32)
 
 BIAS_NONE, BIAS_CONST, BIAS_RG, BIAS_CONTACT, BIAS_RMD_CONTACT = 0, 1, 2, 3, 4
 OBS = ("step", "z", "z_ref", "z_min", "phi", "status", "rebuilds", "ke", "stage_max", "stage_cap",
-       "list_max", "list_cap", "exact_builds", "skin", "nstlist")
-ENERGY_COLUMNS = ("lj", "rf", "bond", "angle", "bias", "z", "z_ref", "S")
+       "list_max", "list_cap", "exact_builds", "skin", "nstlist", "rmsd", "reached", "eval_status")
+# columns of the vp_forces energy table (VP_E_*) and of an energy record (VP_REC_*)
+ENERGY_COLUMNS = ("lj", "rf", "bond", "angle", "bias", "z", "z_ref", "S", "total",
+                  "w_xx", "w_xy", "w_xz", "w_yx", "w_yy", "w_yz", "w_zx", "w_zy", "w_zz", "status")
+RECORD_COLUMNS = ENERGY_COLUMNS + ("step", "ke", "phi")
 REPLICA_UNSTABLE, REPLICA_LIST_OVERFLOW = 1, 2
 
 STATUS = {0: "VP_OK", -1: "VP_ERR_ARG", -2: "VP_ERR_HIP", -3: "VP_ERR_NOMEM", -4: "VP_ERR_STATE",
@@ -54,15 +57,21 @@ class ReplicaDesc(C.Structure):
         ("z_target", C.c_double),
         ("contact_r0", C.c_double), ("contact_rs", C.c_double), ("contact_rc", C.c_double),
         ("contact_min_sep", C.c_int32), ("reach_tol", C.c_double), ("seed", C.c_uint64),
-        ("const_force", _dp),
+        ("const_force", _dp), ("reach_rmsd", C.c_double),
     ]
+
+
+DEV_ALLOC = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+DEV_FREE = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
 
 
 class Options(C.Structure):
     _fields_ = [("nstlist", C.c_int32), ("skin", C.c_double), ("steps_per_graph", C.c_int32),
                 ("use_graph", C.c_int32), ("max_neighbors", C.c_int32),
                 ("tangent", C.c_int32), ("force_shape", C.c_int32), ("autotune", C.c_int32),
-                ("reserved", C.c_int32 * 4)]
+                ("nst_out", C.c_int32), ("out_capacity", C.c_int32), ("stage_cap", C.c_int32),
+                ("reserved", C.c_int32),
+                ("dev_alloc", DEV_ALLOC), ("dev_free", DEV_FREE), ("alloc_ctx", C.c_void_p)]
 
 FORCE_SHAPES = 4
 
@@ -112,6 +121,10 @@ _lib.vp_debug_set_tiles.restype = C.c_int
 _lib.vp_debug_set_tiles.argtypes = [_vp, C.POINTER(C.c_int32), C.c_int32]
 _lib.vp_pair_count.restype = C.c_int
 _lib.vp_pair_count.argtypes = [_vp, C.c_int32, C.POINTER(C.c_int64)]
+_lib.vp_energy_records.restype = C.c_int
+_lib.vp_energy_records.argtypes = [_vp, _dp, C.c_int32, C.POINTER(C.c_int32)]
+_lib.vp_device_bytes.restype = C.c_int
+_lib.vp_device_bytes.argtypes = [_vp, C.POINTER(C.c_int64)]
 _lib.vp_last_error.restype = C.c_char_p
 _lib.vp_last_error.argtypes = []
 
@@ -119,7 +132,7 @@ EXPORTED = ("vp_system_create", "vp_system_destroy", "vp_forces", "vp_step_batch
             "vp_functional", "vp_select_path", "vp_get_state", "vp_observables", "vp_sizes",
             "vp_debug_pairs", "vp_debug_noise", "vp_set_timing", "vp_kernel_timing", "vp_pair_count",
             "vp_debug_force_dir", "vp_debug_trajectory_state", "vp_tile_buckets", "vp_debug_set_tiles",
-            "vp_last_error")
+            "vp_energy_records", "vp_device_bytes", "vp_last_error")
 
 
 def _check(st):
@@ -172,15 +185,36 @@ def _desc(d, keep):
     s.contact_r0, s.contact_rs, s.contact_rc = (float(d[k]) for k in ("contact_r0", "contact_rs", "contact_rc"))
     s.contact_min_sep = int(d["contact_min_sep"])
     s.reach_tol = float(d["reach_tol"])
+    s.reach_rmsd = float(d.get("reach_rmsd", float("inf")))
     s.seed = int(d["seed"]) & 0xFFFFFFFFFFFFFFFF
     return s
+
+
+def _torch_allocator():
+    """dev_alloc / dev_free callbacks that take the library's device memory from
+    torch's caching allocator on the current device and stream."""
+    import torch
+
+    def alloc(nbytes, ctx):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes))
+        except RuntimeError:
+            return None
+
+    def free(ptr, ctx):
+        torch.cuda.caching_allocator_delete(int(ptr))
+
+    return DEV_ALLOC(alloc), DEV_FREE(free)
 
 
 class System:
     """A batch of trial trajectories (vp_system)."""
 
     def __init__(self, reps, nstlist=0, skin=0.0, steps_per_graph=0, use_graph=True,
-                 max_neighbors=0, tangent=False, force_shape=0, autotune=False):
+                 max_neighbors=0, tangent=False, force_shape=0, autotune=False, nst_out=0,
+                 out_capacity=0, stage_cap=0, torch_memory=False):
+        """torch_memory: the library takes all its device memory from torch's
+        caching allocator (vp_options.dev_alloc) instead of hipMalloc."""
         keep = []
         descs = (ReplicaDesc * len(reps))(*[_desc(d, keep) for d in reps])
         opt = Options()
@@ -189,6 +223,10 @@ class System:
         opt.tangent = int(bool(tangent))
         opt.force_shape = int(force_shape)
         opt.autotune = int(bool(autotune))
+        opt.nst_out, opt.out_capacity, opt.stage_cap = int(nst_out), int(out_capacity), int(stage_cap)
+        self._alloc = _torch_allocator() if torch_memory else None  # kept alive with the system
+        if self._alloc is not None:
+            opt.dev_alloc, opt.dev_free = self._alloc
         h = _vp()
         _check(_lib.vp_system_create(descs, len(reps), C.byref(opt), C.byref(h)))
         self._h = h
@@ -210,12 +248,13 @@ class System:
 
     # -------------------------------------------------------------------- calls
     def forces(self, x, t=0.0, energies=False):
-        """Total forces (and the [R, 8] FP64 energy table) at positions x
-        (float32 CUDA tensor [N_total, 3], user order)."""
+        """Total forces (and the [R, len(ENERGY_COLUMNS)] FP64 energy table) at
+        positions x (float32 CUDA tensor [N_total, 3], user order)."""
         import torch
         assert x.is_cuda and x.dtype == torch.float32 and x.is_contiguous() and x.shape == (self.n_total, 3)
         f = torch.empty_like(x)
-        e = torch.zeros((self.n_reps, 8), dtype=torch.float64, device=x.device) if energies else None
+        e = (torch.zeros((self.n_reps, len(ENERGY_COLUMNS)), dtype=torch.float64, device=x.device)
+             if energies else None)
         _check(_lib.vp_forces(self._h, _ptr(x), _ptr(f), _ptr(e) if e is not None else None,
                               float(t), _stream()))
         return (f, e) if energies else f
@@ -306,6 +345,21 @@ class System:
         _check(_lib.vp_observables(self._h, o.ctypes.data_as(_dp)))
         return o
 
+    def energy_records(self):
+        """Energy records [R, n, len(RECORD_COLUMNS)] held so far, oldest first
+        (needs nst_out > 0 at creation)."""
+        n = C.c_int32()
+        _check(_lib.vp_energy_records(self._h, None, 0, C.byref(n)))
+        out = np.zeros((self.n_reps, n.value, len(RECORD_COLUMNS)))
+        if n.value:
+            _check(_lib.vp_energy_records(self._h, out.ctypes.data_as(_dp), n.value, C.byref(n)))
+        return out
+
+    def device_bytes(self):
+        b = C.c_int64()
+        _check(_lib.vp_device_bytes(self._h, C.byref(b)))
+        return b.value
+
     def set_timing(self, on):
         _check(_lib.vp_set_timing(self._h, int(bool(on))))
 
@@ -349,7 +403,7 @@ def _energy_autograd():
             f, e = system.forces(x.detach().contiguous(), t, energies=True)
             ctx.save_for_backward(f)
             ctx.offsets = system.offsets
-            return e[:, :5].sum(1)
+            return e[:, ENERGY_COLUMNS.index("total")].clone()
 
         @staticmethod
         def backward(ctx, gout):
