@@ -234,6 +234,21 @@ vp_status vp_system_destroy(vp_system *s);
 vp_status vp_forces(vp_system *s, const float *x_dev, float *f_dev, double *energy_dev, double t,
                     void *hip_stream);
 
+/* vp_forces for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation): the
+ * same evaluation, results bit for bit those of vp_forces, with the evaluation
+ * context (lists, staging, cell index, partial sums) in a static device array
+ * of 64 MiB per GPU that the library holds until the process ends, instead
+ * of buffers it allocates.  Allocates nothing.  Returns VP_ERR_ARG when the
+ * system's context does not fit (about 30 MB for a 12,560-atom replica; a
+ * batch that needs more uses vp_forces).  Every call on a GPU uses that GPU's
+ * one array, so calls that overlap on one GPU -- on different streams, or
+ * from different systems or threads -- race and must be ordered by the
+ * caller.  Overflow reporting as for vp_forces (NaN forces and the status
+ * column), except that VP_OBS_EVAL_STATUS follows vp_forces calls only. */
+vp_status vp_forces_noalloc(vp_system *s, const float *x_dev, float *f_dev, double *energy_dev,
+                            double t, void *hip_stream);
+
 /* Advance every replica by n_steps BAOAB steps of Eq. Lang (>= 0),
  * accumulating Phi.  Asynchronous on hip_stream. */
 vp_status vp_step_batch(vp_system *s, int32_t n_steps, void *hip_stream);

@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libvp.so")
 BUILD_DIR = os.path.join(os.path.dirname(HERE), "_build")
-SOURCES = ["kernels_list.hip", "kernels_force.hip", "kernels_integrate.hip", "kernels_observe.hip",
+SOURCES = ["kernels_list.hip", "kernels_force.hip", "kernels_integrate.hip", "kernels_observe.hip", "noalloc.hip",
            "runtime.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

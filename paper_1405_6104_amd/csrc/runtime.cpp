@@ -1108,6 +1108,28 @@ extern "C" vp_status vp_select_path(vp_system *s, const uint8_t *eligible, int32
   return VP_OK;
 }
 
+namespace vp {
+
+vp_status set_error(vp_status st, const std::string &msg) { return fail(st, msg); }
+
+// The evaluation of vp_forces into the buffers of W (an evaluation context
+// that the call's kernels fill before they read it), ordered after the
+// system's previous calls.
+vp_status enqueue_forces(vp_system *s, Work &W, const float *x_dev, float *f_dev, double *energy_dev,
+                         double t, hipStream_t st) {
+  HIPCHECK(begin_async(s, st));
+  launch_rebuild(s, W, 1, x_dev, st);
+  launch_forces(s, W, st);
+  if (energy_dev) launch_energies(s, W, false, st);
+  launch_cv(s, W, 0, st, false);
+  launch_force_out(s, W, t, f_dev, energy_dev, st);
+  HIPCHECK(hipGetLastError());
+  HIPCHECK(end_async(s, st));
+  return VP_OK;
+}
+
+}  // namespace vp
+
 extern "C" vp_status vp_forces(vp_system *s, const float *x_dev, float *f_dev, double *energy_dev,
                                double t, void *hip_stream) {
   if (!s || !x_dev || !f_dev) return fail(VP_ERR_ARG, "NULL argument");
@@ -1117,15 +1139,7 @@ extern "C" vp_status vp_forces(vp_system *s, const float *x_dev, float *f_dev, d
     TRY(alloc_work(s, s->eval, false));
     s->eval_ready = true;
   }
-  HIPCHECK(begin_async(s, st));
-  launch_rebuild(s, s->eval, 1, x_dev, st);
-  launch_forces(s, s->eval, st);
-  if (energy_dev) launch_energies(s, s->eval, false, st);
-  launch_cv(s, s->eval, 0, st, false);
-  launch_force_out(s, s->eval, t, f_dev, energy_dev, st);
-  HIPCHECK(hipGetLastError());
-  HIPCHECK(end_async(s, st));
-  return VP_OK;
+  return enqueue_forces(s, s->eval, x_dev, f_dev, energy_dev, t, st);
 }
 
 extern "C" vp_status vp_get_state(vp_system *s, float *x_dev, float *v_dev, void *hip_stream) {

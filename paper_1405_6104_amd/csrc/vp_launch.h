@@ -50,4 +50,10 @@ void launch_export_state(vp_system *s, double *x, double *v, double *xt, double 
 void launch_debug_noise(uint64_t seed, uint32_t atom0, uint32_t step, uint32_t tag, int n,
                         float *out, hipStream_t st);
 
+// the evaluation of vp_forces into the buffers of an evaluation context W
+vp_status enqueue_forces(vp_system *s, Work &W, const float *x_dev, float *f_dev, double *energy_dev,
+                         double t, hipStream_t st);
+// sets the message of vp_last_error and returns st
+vp_status set_error(vp_status st, const std::string &msg);
+
 }  // namespace vp

@@ -89,6 +89,8 @@ _lib.vp_system_destroy.restype = C.c_int
 _lib.vp_system_destroy.argtypes = [_vp]
 _lib.vp_forces.restype = C.c_int
 _lib.vp_forces.argtypes = [_vp, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_void_p]
+_lib.vp_forces_noalloc.restype = C.c_int
+_lib.vp_forces_noalloc.argtypes = [_vp, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_void_p]
 _lib.vp_step_batch.restype = C.c_int
 _lib.vp_step_batch.argtypes = [_vp, C.c_int32, C.c_void_p]
 _lib.vp_functional.restype = C.c_int
@@ -132,7 +134,7 @@ EXPORTED = ("vp_system_create", "vp_system_destroy", "vp_forces", "vp_step_batch
             "vp_functional", "vp_select_path", "vp_get_state", "vp_observables", "vp_sizes",
             "vp_debug_pairs", "vp_debug_noise", "vp_set_timing", "vp_kernel_timing", "vp_pair_count",
             "vp_debug_force_dir", "vp_debug_trajectory_state", "vp_tile_buckets", "vp_debug_set_tiles",
-            "vp_energy_records", "vp_device_bytes", "vp_last_error")
+            "vp_energy_records", "vp_device_bytes", "vp_forces_noalloc", "vp_last_error")
 
 
 def _check(st):
@@ -258,6 +260,12 @@ class System:
         _check(_lib.vp_forces(self._h, _ptr(x), _ptr(f), _ptr(e) if e is not None else None,
                               float(t), _stream()))
         return (f, e) if energies else f
+
+    def forces_noalloc(self, x, f, e=None, t=0.0):
+        """vp_forces_noalloc into caller-provided tensors f ([N_total, 3] float32)
+        and e ([R, len(ENERGY_COLUMNS)] float64 or None)."""
+        _check(_lib.vp_forces_noalloc(self._h, _ptr(x), _ptr(f), _ptr(e) if e is not None else None,
+                                      float(t), _stream()))
 
     def step_batch(self, n):
         _check(_lib.vp_step_batch(self._h, int(n), _stream()))
