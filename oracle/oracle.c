@@ -1158,3 +1158,155 @@ void ora_phi_grad(const ora_ctx *c, const ora_state *st, const double *pd, doubl
   for (int k = 0; k < 2; ++k)
     out[k] = st->status ? NAN : (pd[k] - 0.5 * pd[2 + k]) * c->s.dt / (4.0 * c->s.kT);
 }
+
+/* ------------------------------------------------------------------------ */
+/* Toy model (supplement, "Illustrative Application in a Toy Model").        */
+/* ------------------------------------------------------------------------ */
+double ora_toy_potential(const ora_toy_params *p, double x, double y, double *gx, double *gy) {
+  double r2 = x * x + y * y;
+  double d1 = r2 + p->s1 * p->s1, d2 = r2 + p->s2 * p->s2;
+  double dxm = x - p->xm, dym = y - p->ym;
+  double d3 = dxm * dxm + dym * dym + p->s3 * p->s3;
+  double a1 = p->A1 * p->s1 * p->s1, a2 = p->A2 * p->s2 * p->s2, a3 = p->A3 * p->s3 * p->s3;
+  double u = p->w * p->w * r2 * r2 - a1 / (d1 * d1) + a2 / (d2 * d2) - a3 / (d3 * d3);
+  /* d/dr2 of each radial term, then chain rule: d(r2)/dx = 2x */
+  double dr2 = 2.0 * p->w * p->w * r2 + 2.0 * a1 / (d1 * d1 * d1) - 2.0 * a2 / (d2 * d2 * d2);
+  double dd3 = 2.0 * a3 / (d3 * d3 * d3); /* d/d(d3) of -a3/d3^2 */
+  if (gx) *gx = dr2 * 2.0 * x + dd3 * 2.0 * dxm;
+  if (gy) *gy = dr2 * 2.0 * y + dd3 * 2.0 * dym;
+  return u;
+}
+
+/* bias force on the particle for z = |(x, y)|: returns S = |F|^2/(gamma m) */
+static double toy_bias(const ora_toy_params *p, int32_t kind, double k, double x, double y, double zm,
+                       double *fx, double *fy) {
+  double z = sqrt(x * x + y * y);
+  *fx = 0.0;
+  *fy = 0.0;
+  if (kind == ORA_TOY_RMD && z > zm && z > 0.0) {
+    /* Eq. VR: -(k/2)(z - z_m) grad z, grad z = (x, y)/z */
+    double c = -0.5 * k * (z - zm) / z;
+    *fx = c * x;
+    *fy = c * y;
+  } else if (kind == ORA_TOY_SMD) {
+    /* steered MD toward the bottom of the funnel: -K z grad z = -K (x, y) */
+    *fx = -k * x;
+    *fy = -k * y;
+  }
+  return (*fx * *fx + *fy * *fy) / (p->gamma * p->mass);
+}
+
+void ora_toy_run(const ora_toy_params *p, int32_t kind, double k_bias, uint64_t seed, double *out,
+                 double *path) {
+  double x = p->x0, y = p->y0, vx, vy;
+  double g[3];
+  ora_normals(seed, 0u, 0u, 1u, g); /* Maxwell velocities: tag 1 at step 0 */
+  double sd0 = sqrt(p->kT / p->mass);
+  vx = sd0 * g[0];
+  vy = sd0 * g[1];
+  double dt = p->dt, m = p->mass;
+  double c1 = exp(-p->gamma * dt);
+  double sv = sqrt((1.0 - c1 * c1) * p->kT / m);
+  double zm = sqrt(x * x + y * y); /* running minimum: z(X_0) */
+  double ux, uy, bx, by;
+  ora_toy_potential(p, x, y, &ux, &uy);
+  double S = toy_bias(p, kind, k_bias, x, y, zm, &bx, &by);
+  double fx = -ux + bx, fy = -uy + by;
+  double acc = 0.5 * S, s_last = S;
+  long long t_reach = -1;
+  double theta = NAN;
+  double z = zm;
+  if (z <= p->r_product) t_reach = 0;
+  if (z <= p->r_gate) theta = atan2(y, x);
+  if (path) {
+    path[0] = x;
+    path[1] = y;
+  }
+  for (int32_t n = 0; n < p->n_steps; ++n) {
+    ora_normals(seed, 0u, (uint32_t)n, 2u, g);
+    vx += 0.5 * dt * fx / m;
+    vy += 0.5 * dt * fy / m;
+    x += 0.5 * dt * vx;
+    y += 0.5 * dt * vy;
+    vx = c1 * vx + sv * g[0];
+    vy = c1 * vy + sv * g[1];
+    x += 0.5 * dt * vx;
+    y += 0.5 * dt * vy;
+    z = sqrt(x * x + y * y);
+    if (kind == ORA_TOY_RMD && z < zm) zm = z; /* updated before the force (Eq. VR) */
+    ora_toy_potential(p, x, y, &ux, &uy);
+    S = toy_bias(p, kind, k_bias, x, y, zm, &bx, &by);
+    fx = -ux + bx;
+    fy = -uy + by;
+    vx += 0.5 * dt * fx / m;
+    vy += 0.5 * dt * fy / m;
+    acc += S;
+    s_last = S;
+    if (t_reach < 0 && z <= p->r_product) t_reach = n + 1;
+    if (isnan(theta) && z <= p->r_gate) theta = atan2(y, x);
+    if (path) {
+      path[2 * (n + 1)] = x;
+      path[2 * (n + 1) + 1] = y;
+    }
+  }
+  out[ORA_TOY_PHI] = (acc - 0.5 * s_last) * dt / (4.0 * p->kT);
+  out[ORA_TOY_REACHED] = t_reach >= 0 ? 1.0 : 0.0;
+  out[ORA_TOY_T_REACH] = (double)t_reach;
+  out[ORA_TOY_X] = x;
+  out[ORA_TOY_Y] = y;
+  out[ORA_TOY_ZMIN] = kind == ORA_TOY_RMD ? zm : NAN;
+  out[ORA_TOY_THETA_GATE] = theta;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Path similarity (main text, mechanism analysis): the fraction of ordered  */
+/* contact pairs whose formation order is the same in both trajectories.     */
+/* ------------------------------------------------------------------------ */
+static double order_entry(const int64_t *t, int i, int j) {
+  if (t[i] < t[j]) return 1.0;
+  if (t[i] > t[j]) return 0.0;
+  return 0.5;
+}
+
+double ora_path_similarity(int32_t nc, const int64_t *ta, const int64_t *tb) {
+  if (nc < 2) return NAN;
+  int64_t same = 0;
+  for (int i = 0; i < nc; ++i)
+    for (int j = 0; j < nc; ++j) {
+      if (i == j) continue;
+      if (order_entry(ta, i, j) == order_entry(tb, i, j)) ++same;
+    }
+  return (double)same / ((double)nc * (double)(nc - 1));
+}
+
+/* squared distance of atoms i, j of x in squared grid units (exact integers) */
+static int64_t grid_d2(const double *x, int i, int j) {
+  int64_t s = 0;
+  for (int a = 0; a < 3; ++a) {
+    int64_t d = llrint(x[3 * j + a] * ORA_QSCALE) - llrint(x[3 * i + a] * ORA_QSCALE);
+    s += d * d;
+  }
+  return s;
+}
+
+int64_t ora_native_contacts(const ora_ctx *c, int32_t *pairs, int64_t cap) {
+  const ora_sys *s = &c->s;
+  if (!s->x_final) return 0;
+  int64_t r0 = llrint(s->contact_r0 * ORA_QSCALE), n = 0;
+  for (int i = 0; i < s->n_solute; ++i)
+    for (int j = i + s->contact_min_sep + 1; j < s->n_solute; ++j) {
+      if (grid_d2(s->x_final, i, j) > r0 * r0) continue;
+      if (pairs && n < cap) {
+        pairs[2 * n] = i;
+        pairs[2 * n + 1] = j;
+      }
+      ++n;
+    }
+  return n;
+}
+
+void ora_contacts_formed(const ora_ctx *c, const double *x, const int32_t *pairs, int64_t nc,
+                         uint8_t *formed) {
+  int64_t r0 = llrint(c->s.contact_r0 * ORA_QSCALE);
+  for (int64_t k = 0; k < nc; ++k) formed[k] = grid_d2(x, pairs[2 * k], pairs[2 * k + 1]) <= r0 * r0;
+}

@@ -125,6 +125,61 @@ int ora_run_tangent(ora_ctx *c, double *x, double *v, ora_state *st, double *xt,
                     double *pd, int32_t nsteps, int32_t use_cells);
 void ora_phi_grad(const ora_ctx *c, const ora_state *st, const double *pd, double *out);
 
+/* ------------------------------------------------------------------------ */
+/* Toy model (supplement, "Illustrative Application in a Toy Model"): a point  */
+/* particle on the 2-D surface                                                 */
+/*   U(x,y) = w^2 (x^2+y^2)^2 - A1 s1^2/(x^2+y^2+s1^2)^2                       */
+/*          + A2 s2^2/(x^2+y^2+s2^2)^2 - A3 s3^2/((x-xm)^2+(y-ym)^2+s3^2)^2     */
+/* with underdamped Langevin dynamics (BAOAB, as for the atomistic system),  */
+/* noise normals (g0, g1) of Philox counter (0, step, 2, 0) under the trial's  */
+/* key, and a bias on z = sqrt(x^2 + y^2): none (plain), the ratchet of Eq. VR  */
+/* (rMD) or the harmonic steering force -K z grad z (steered MD).  The        */
+/* functional of Eq. VMDcondition accumulates over every step (trapezoid).   */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+  double A1, A2, A3, s1, s2, s3, w, xm, ym;
+  double gamma, mass, kT, dt;
+  double x0, y0;
+  double r_product; /* reached: first step with z <= r_product */
+  double r_gate;    /* theta_gate: polar angle at the first step with z <= r_gate */
+  int32_t n_steps;
+  int32_t pad;
+} ora_toy_params;
+
+enum { ORA_TOY_PLAIN = 0, ORA_TOY_RMD = 1, ORA_TOY_SMD = 2 };
+/* per-trial results: Phi, reached (0/1), first step with z <= r_product (-1),
+ * final x, y, ratchet minimum z_m, polar angle at the first step with
+ * z <= r_gate (NAN if none) */
+enum { ORA_TOY_PHI = 0, ORA_TOY_REACHED, ORA_TOY_T_REACH, ORA_TOY_X, ORA_TOY_Y, ORA_TOY_ZMIN,
+       ORA_TOY_THETA_GATE, ORA_TOY_COUNT };
+
+/* U and its gradient at (x, y) */
+double ora_toy_potential(const ora_toy_params *p, double x, double y, double *gx, double *gy);
+/* one trial: out[ORA_TOY_COUNT]; path (may be NULL): [n_steps + 1][2] positions */
+void ora_toy_run(const ora_toy_params *p, int32_t kind, double k_bias, uint64_t seed, double *out,
+                 double *path);
+
+/* ------------------------------------------------------------------------ */
+/* Order of native-contact formation and path similarity (main text, the    */
+/* matrix M of the mechanism analysis).  t: formation step of each of nc      */
+/* contacts in trajectories a and b (a contact never formed carries the same  */
+/* value as every other unformed one).  M_ij = 1 if t_i < t_j, 0 if t_i > t_j, */
+/* 1/2 if equal; s = (number of ordered pairs i != j with M_ij(a) = M_ij(b))   */
+/* / (nc (nc - 1)).                                                            */
+/* ------------------------------------------------------------------------ */
+double ora_path_similarity(int32_t nc, const int64_t *ta, const int64_t *tb);
+
+/* Native contacts (reading of the main text's "native contacts"): solute
+ * pairs i < j with j - i > contact_min_sep whose distance in X_f is at most
+ * contact_r0 (where C = 3/5); a contact is formed at a configuration where
+ * its distance is at most contact_r0.  Both decisions are taken exactly, on
+ * positions and r0 rounded to the 2^-24 nm grid (squared integer distances).
+ * ora_native_contacts writes up to cap pairs [cap][2] and returns the count;
+ * ora_contacts_formed sets formed[k] for the listed pairs at positions x. */
+int64_t ora_native_contacts(const ora_ctx *c, int32_t *pairs, int64_t cap);
+void ora_contacts_formed(const ora_ctx *c, const double *x, const int32_t *pairs, int64_t nc,
+                         uint8_t *formed);
+
 #ifdef __cplusplus
 }
 #endif

@@ -46,6 +46,15 @@ class State(C.Structure):
                 ("status", C.c_int32), ("pad", C.c_int32)]
 
 
+class ToyParams(C.Structure):
+    _fields_ = [(k, C.c_double) for k in ("A1", "A2", "A3", "s1", "s2", "s3", "w", "xm", "ym",
+                                          "gamma", "mass", "kT", "dt", "x0", "y0", "r_product",
+                                          "r_gate")] + [("n_steps", C.c_int32), ("pad", C.c_int32)]
+
+
+TOY_COLUMNS = ("phi", "reached", "t_reach", "x", "y", "z_min", "theta_gate")
+TOY_PLAIN, TOY_RMD, TOY_SMD = 0, 1, 2
+
 TERMS = ("e_lj", "e_rf", "e_bond", "e_angle", "e_bias", "z", "z_ref", "S", "u_total",
          "w_xx", "w_xy", "w_xz", "w_yx", "w_yy", "w_yz", "w_zx", "w_zy", "w_zz")
 
@@ -94,6 +103,14 @@ def lib():
         L.ora_run_tangent.argtypes = [C.c_void_p, _dp, _dp, C.POINTER(State), _dp, _dp, _dp,
                                       C.c_int32, C.c_int32]
         L.ora_phi_grad.argtypes = [C.c_void_p, C.POINTER(State), _dp, _dp]
+        L.ora_toy_potential.restype = C.c_double
+        L.ora_toy_potential.argtypes = [C.POINTER(ToyParams), C.c_double, C.c_double, _dp, _dp]
+        L.ora_toy_run.argtypes = [C.POINTER(ToyParams), C.c_int32, C.c_double, C.c_uint64, _dp, _dp]
+        L.ora_native_contacts.restype = C.c_int64
+        L.ora_native_contacts.argtypes = [C.c_void_p, _ip, C.c_int64]
+        L.ora_contacts_formed.argtypes = [C.c_void_p, _dp, _ip, C.c_int64, _u8p]
+        L.ora_path_similarity.restype = C.c_double
+        L.ora_path_similarity.argtypes = [C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
         _lib = L
     return _lib
 
@@ -243,6 +260,20 @@ class Oracle:
         xa = None if x is None else _f64(x, (self.n, 3))
         return bool(lib().ora_reached(self.ctx, C.byref(state), _d(xa) if xa is not None else None))
 
+    def native_contacts(self):
+        """Native contact pairs [nc, 2] (i < j) of X_f."""
+        n = lib().ora_native_contacts(self.ctx, None, 0)
+        out = np.zeros((max(n, 1), 2), np.int32)
+        lib().ora_native_contacts(self.ctx, out.ctypes.data_as(_ip), n)
+        return out[:n]
+
+    def contacts_formed(self, x, pairs):
+        pairs = np.ascontiguousarray(pairs, dtype=np.int32)
+        out = np.zeros(len(pairs), np.uint8)
+        lib().ora_contacts_formed(self.ctx, _d(_f64(x, (self.n, 3))), pairs.ctypes.data_as(_ip),
+                                  len(pairs), out.ctypes.data_as(_u8p))
+        return out.astype(bool)
+
     def rmsd(self, x):
         """RMSD of the solute of x ([n][3]) from X_f after optimal superposition."""
         return lib().ora_rmsd(self.ctx, _d(_f64(x, (self.n, 3))))
@@ -292,3 +323,38 @@ def build_command(out=LIB_PATH):
     contraction so that the FP32 pair predicate is evaluated as written)."""
     return ["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
             os.path.join(_HERE, "oracle.c"), "-o", out, "-lm"]
+
+
+# ------------------------------------------------------------------ toy model
+def toy_params(p):
+    """ToyParams from a dict (keys of ToyParams._fields_)."""
+    t = ToyParams()
+    for k, _ in ToyParams._fields_:
+        if k in p:
+            setattr(t, k, p[k])
+    return t
+
+
+def toy_potential(p, x, y):
+    gx, gy = C.c_double(), C.c_double()
+    u = lib().ora_toy_potential(C.byref(toy_params(p)), float(x), float(y), C.byref(gx), C.byref(gy))
+    return u, gx.value, gy.value
+
+
+def toy_run(p, kind, k_bias, seed, path=False):
+    """One toy trial: dict of TOY_COLUMNS (and the path [n_steps + 1, 2])."""
+    t = toy_params(p)
+    out = np.zeros(len(TOY_COLUMNS))
+    pa = np.zeros((t.n_steps + 1, 2)) if path else None
+    lib().ora_toy_run(C.byref(t), int(kind), float(k_bias), int(seed) & 0xFFFFFFFFFFFFFFFF, _d(out),
+                      _d(pa) if path else None)
+    res = dict(zip(TOY_COLUMNS, out.tolist()))
+    return (res, pa) if path else res
+
+
+def path_similarity(ta, tb):
+    a = np.ascontiguousarray(ta, dtype=np.int64)
+    b = np.ascontiguousarray(tb, dtype=np.int64)
+    assert a.shape == b.shape
+    p64 = C.POINTER(C.c_int64)
+    return lib().ora_path_similarity(len(a), a.ctypes.data_as(p64), b.ctypes.data_as(p64))
