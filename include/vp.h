@@ -157,7 +157,9 @@ typedef struct {
                               (a diagnostic: blocks that need more are built again in exact
                               mode, which stages only atoms within the list radius of one of
                               the block's atoms); 0: as large as the force kernel's LDS allows */
-  int32_t reserved;
+  int32_t contact_order;   /* 1: record the step at which each native contact of the replicas
+                              that give x_final first forms (vp_contact_order,
+                              vp_path_similarity); 0: off */
   /* Device memory: when dev_alloc is not NULL every device buffer the system
    * holds is obtained from dev_alloc(bytes, alloc_ctx) (NULL = out of memory)
    * and returned with dev_free(ptr, alloc_ctx) by vp_system_destroy, or by a
@@ -301,6 +303,26 @@ vp_status vp_observables(vp_system *s, double *obs_host);
  * the system records nothing.  Synchronises. */
 vp_status vp_energy_records(vp_system *s, double *out_host, int32_t cap, int32_t *n_records);
 
+/* Order of native-contact formation (main text, mechanism analysis; needs
+ * vp_options.contact_order = 1).  The native contacts of a replica are its
+ * solute pairs i < j with j - i > contact_min_sep and |X_f,i - X_f,j| <=
+ * contact_r0; a contact forms at the first step (0 = the initial state) at
+ * which its distance is <= contact_r0.  Both tests are exact, on squared
+ * integer distances of positions and r0 on the 2^-24 nm grid.  Writes the
+ * number of contacts of replica rep to *n_contacts and, where not NULL, the
+ * first min(cap, n) pairs (HOST int32 [cap][2], replica-local user indices)
+ * and formation steps (HOST int64 [cap], -1 = not formed yet).  Synchronises. */
+vp_status vp_contact_order(vp_system *s, int32_t rep, int32_t *pairs_host, int64_t *steps_host,
+                           int32_t cap, int32_t *n_contacts);
+
+/* Path similarity s(k, k') = (number of ordered contact pairs i != j with
+ * M_ij(k) = M_ij(k')) / (N_c (N_c - 1)), M_ij = 1, 0, 1/2 when contact i forms
+ * before, after or at the same step as j (contacts not formed yet count as
+ * forming together, after all others), for every pair of replicas with the
+ * same native contacts: sim_host HOST [n_reps][n_reps] FP64, NaN where the
+ * contact sets differ or N_c < 2.  Computed on the GPU; synchronises. */
+vp_status vp_path_similarity(vp_system *s, double *sim_host);
+
 /* Device bytes held by the system (its buffers, whichever allocator). */
 vp_status vp_device_bytes(const vp_system *s, int64_t *bytes);
 
@@ -365,6 +387,54 @@ vp_status vp_debug_pairs(vp_system *s, int32_t rep, int32_t *pairs_host, int64_t
  * atom0.  out_dev: DEVICE [n][4] FP32 (g0, g1, g2, first uniform). */
 vp_status vp_debug_noise(uint64_t seed, uint32_t atom0, uint32_t step, uint32_t tag, int32_t n,
                          float *out_dev, void *hip_stream);
+
+/* ---------------------------------------------------------------------------
+ * Toy model (supplement, "Illustrative Application in a Toy Model"): trial
+ * paths of one particle on the 2-D surface
+ *   U(x,y) = w^2 (x^2+y^2)^2 - A1 s1^2/(x^2+y^2+s1^2)^2 + A2 s2^2/(x^2+y^2+s2^2)^2
+ *            - A3 s3^2/((x-xm)^2+(y-ym)^2+s3^2)^2
+ * with the BAOAB Langevin steps of the atomistic trials (FP64; noise normals
+ * of Philox counter (0, step, 2, 0) under the trial's key, Maxwell velocities
+ * from counter (0, 0, 1, 0)), biased on z = sqrt(x^2 + y^2) by nothing
+ * (VP_TOY_PLAIN), the ratchet of Eq. VR with k_R = k (VP_TOY_RMD) or the
+ * steering force -k z grad z (VP_TOY_SMD), each scored by Phi of Eq.
+ * VMDcondition over the whole run.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  double A1, A2, A3, s1, s2, s3, w, xm, ym;  /* the surface (paper: 30, 20, 6, 1, 2, 2, 0.03, 1.5, 0) */
+  double gamma, mass, kT, dt;                /* paper: 1, 1, 0.2, 0.02 */
+  double x0, y0;                             /* start (paper: 0, 5) */
+  double r_product;                          /* reached: z <= r_product at some step */
+  double r_gate;                             /* VP_TOY_THETA_GATE: polar angle at the first step
+                                                with z <= r_gate */
+  int32_t n_steps;                           /* steps per trial */
+  int32_t path_stride;                       /* > 0: positions every path_stride steps */
+} vp_toy_params;
+
+enum { VP_TOY_PLAIN = 0, VP_TOY_RMD = 1, VP_TOY_SMD = 2 };
+/* per-trial results: Phi, reached (0/1), first step with z <= r_product (-1:
+ * none), final x and y, ratchet minimum (NaN for other kinds), polar angle at
+ * the first step with z <= r_gate (NaN: none) */
+enum { VP_TOY_PHI = 0, VP_TOY_REACHED, VP_TOY_T_REACH, VP_TOY_X, VP_TOY_Y, VP_TOY_ZMIN,
+       VP_TOY_THETA_GATE, VP_TOY_COUNT };
+
+/* Run n_trials independent toy trials, one GPU thread each.  p: HOST.
+ * kind_dev, k_dev, seed_dev: DEVICE [n_trials] (kind, bias constant, Philox
+ * key); out_dev: DEVICE [n_trials][VP_TOY_COUNT] FP64; path_dev: DEVICE
+ * [n_trials][n_steps/path_stride + 1][2] FP32 (x, y at steps 0, stride, ...)
+ * or NULL.  Allocates nothing; asynchronous on hip_stream.  VP_ERR_ARG for
+ * n_trials <= 0, n_steps < 0, non-positive mass, dt or kT, negative gamma, or
+ * a path buffer without path_stride > 0. */
+vp_status vp_toy_trials(const vp_toy_params *p, int32_t n_trials, const int32_t *kind_dev,
+                        const double *k_dev, const uint64_t *seed_dev, double *out_dev, float *path_dev,
+                        void *hip_stream);
+
+/* Variational selection over toy results (HOST [n][VP_TOY_COUNT], e.g. copied
+ * from vp_toy_trials): least finite Phi among reached trials whose eligible
+ * flag (HOST [n] or NULL) is set, ties to the lowest index; VP_ERR_NOPATH and
+ * *best = -1 when none qualifies. */
+vp_status vp_toy_select(const double *out_host, int32_t n, const uint8_t *eligible, int32_t *best,
+                        double *best_phi);
 
 const char *vp_last_error(void);
 

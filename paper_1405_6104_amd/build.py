@@ -14,6 +14,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libvp.so")
 BUILD_DIR = os.path.join(os.path.dirname(HERE), "_build")
 SOURCES = ["kernels_list.hip", "kernels_force.hip", "kernels_integrate.hip", "kernels_observe.hip", "noalloc.hip",
+           "kernels_toy.hip",
            "runtime.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

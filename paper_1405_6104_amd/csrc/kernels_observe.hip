@@ -153,3 +153,82 @@ void launch_rmsd(vp_system *s, hipStream_t st) {
 }
 
 }  // namespace vp
+
+namespace vp {
+
+// First-formation step of every native contact not formed yet: formed when
+// the squared integer distance of its two (unwrapped, same-molecule) atoms
+// is at most (r0 in grid units)^2.  One thread per (contact, replica).
+__global__ __launch_bounds__(256) void k_contact_form(const RepInfo *__restrict__ info, Work W,
+                                                      const int2 *__restrict__ cpairs,
+                                                      int32_t *__restrict__ t_form,
+                                                      const long long *__restrict__ step) {
+  const RepInfo &R = info[blockIdx.y];
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= R.n_contacts) return;
+  int32_t *tf = t_form + R.tf_off + k;
+  if (*tf >= 0) return;
+  const int2 pq = cpairs[R.cp_off + k];
+  const int4 a = W.xq[W.inv[R.uoff + pq.x]], b = W.xq[W.inv[R.uoff + pq.y]];
+  const long long dx = (long long)b.x - a.x, dy = (long long)b.y - a.y, dz = (long long)b.z - a.z;
+  const unsigned long long d2 = (unsigned long long)(dx * dx) + (unsigned long long)(dy * dy) +
+                                (unsigned long long)(dz * dz);
+  if (d2 <= (unsigned long long)R.r0q2) *tf = (int32_t)*step;
+}
+
+// Concordant ordered contact pairs of two replicas with the same native
+// contacts: count of (i, j), i != j, whose order entries M_ij (1, 0, 1/2 for
+// formed before, after, together) agree; contacts not formed yet take the
+// same, latest step.  One workgroup per replica pair; formation steps in LDS.
+__global__ __launch_bounds__(256) void k_similarity(const RepInfo *__restrict__ info,
+                                                    const int32_t *__restrict__ t_form,
+                                                    const int2 *__restrict__ pr, int npairs,
+                                                    unsigned long long *__restrict__ out) {
+  extern __shared__ int32_t s_t[];  // [2][nc]
+  __shared__ unsigned long long s_red[4];
+  const int q = blockIdx.x;
+  if (q >= npairs) return;
+  const RepInfo &A = info[pr[q].x], &B = info[pr[q].y];
+  const int nc = A.n_contacts;
+  int32_t *ta = s_t, *tb = s_t + nc;
+  for (int i = threadIdx.x; i < nc; i += blockDim.x) {
+    const int32_t a = t_form[A.tf_off + i], b = t_form[B.tf_off + i];
+    ta[i] = a < 0 ? 0x7fffffff : a;
+    tb[i] = b < 0 ? 0x7fffffff : b;
+  }
+  __syncthreads();
+  unsigned long long same = 0;
+  for (int i = threadIdx.x; i < nc; i += blockDim.x) {
+    const int32_t ai = ta[i], bi = tb[i];
+    for (int j = 0; j < nc; ++j) {
+      const int32_t aj = ta[j], bj = tb[j];
+      const int ma = (ai < aj) ? 2 : (ai > aj ? 0 : 1);
+      const int mb = (bi < bj) ? 2 : (bi > bj ? 0 : 1);
+      same += (ma == mb && j != i) ? 1ull : 0ull;
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) same += __shfl_xor(same, o, 64);
+  if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = same;
+  __syncthreads();
+  if (threadIdx.x == 0) out[q] = s_red[0] + s_red[1] + s_red[2] + s_red[3];
+}
+
+void launch_contact_form(vp_system *s, hipStream_t st) {
+  const int nb = (s->max_contacts + 255) / 256;
+  if (nb == 0) return;
+  hipLaunchKernelGGL(k_contact_form, dim3(nb, s->R), dim3(256), 0, st, s->info, s->traj, s->cpairs, s->t_form,
+                     s->step);
+}
+
+hipError_t prepare_similarity(int max_contacts) {
+  return hipFuncSetAttribute((const void *)k_similarity, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)(sizeof(int32_t) * 2 * (size_t)max_contacts));
+}
+
+void launch_similarity(vp_system *s, const int2 *pr, int npairs, int max_contacts, unsigned long long *out,
+                       hipStream_t st) {
+  hipLaunchKernelGGL(k_similarity, dim3(npairs), dim3(256), sizeof(int32_t) * 2 * (size_t)max_contacts, st,
+                     s->info, s->t_form, pr, npairs, out);
+}
+
+}  // namespace vp

@@ -298,6 +298,63 @@ static void list_params(const vp_replica_desc &d, const vp_options &o, int ntype
   }
 }
 
+// Native contacts of every replica that gives X_f (one list per distinct
+// X_f, min_sep and r0): solute pairs i < j, j - i > min_sep, whose squared
+// distance on the 2^-24 nm grid is at most (r0 on that grid)^2, exactly in
+// integers; the formation steps start at -1.
+static vp_status native_contacts(vp_system *s, const vp_replica_desc *reps) {
+  std::vector<int2> pairs;
+  struct Key {
+    const double *xf;
+    int ns, sep;
+    double r0;
+    int off, n;
+  };
+  std::vector<Key> seen;
+  int64_t tf = 0;
+  for (int r = 0; r < s->R; ++r) {
+    const vp_replica_desc &d = reps[r];
+    RepInfo &R = s->info_h[r];
+    R.n_contacts = 0;
+    R.cp_off = 0;
+    R.tf_off = (int32_t)tf;
+    const int64_t r0q = std::llrint(d.contact_r0 * kQ);
+    R.r0q2 = r0q * r0q;
+    if (!d.x_final || d.n_solute < 2 || !(d.contact_r0 > 0)) continue;
+    int found = -1;
+    for (size_t k = 0; k < seen.size(); ++k)
+      if (seen[k].ns == d.n_solute && seen[k].sep == d.contact_min_sep && seen[k].r0 == d.contact_r0 &&
+          std::memcmp(seen[k].xf, d.x_final, sizeof(double) * 3 * (size_t)d.n_solute) == 0)
+        found = (int)k;
+    if (found < 0) {
+      Key k{d.x_final, d.n_solute, d.contact_min_sep, d.contact_r0, (int)pairs.size(), 0};
+      std::vector<int64_t> q(3 * (size_t)d.n_solute);
+      for (size_t i = 0; i < q.size(); ++i) q[i] = std::llrint(d.x_final[i] * kQ);
+      for (int i = 0; i < d.n_solute; ++i)
+        for (int j = i + std::max(0, d.contact_min_sep) + 1; j < d.n_solute; ++j) {
+          int64_t d2 = 0;
+          for (int a = 0; a < 3; ++a) {
+            const int64_t e = q[3 * j + a] - q[3 * i + a];
+            d2 += e * e;
+          }
+          if (d2 <= R.r0q2) pairs.push_back(make_int2(i, j));
+        }
+      k.n = (int)pairs.size() - k.off;
+      seen.push_back(k);
+      found = (int)seen.size() - 1;
+    }
+    R.cp_off = seen[found].off;
+    R.n_contacts = seen[found].n;
+    tf += R.n_contacts;
+    s->max_contacts = std::max(s->max_contacts, R.n_contacts);
+  }
+  TRY(upload(s, &s->cpairs, pairs));
+  TRY(dalloc(s, &s->t_form, (size_t)std::max<int64_t>(1, tf)));
+  HIPCHECK(hipMemset(s->t_form, 0xff, sizeof(int32_t) * (size_t)std::max<int64_t>(1, tf)));
+  HIPCHECK(hipMemcpy(s->info, s->info_h.data(), sizeof(RepInfo) * s->R, hipMemcpyHostToDevice));
+  return VP_OK;
+}
+
 static vp_status build(vp_system *s, const vp_replica_desc *reps, int32_t n_reps) {
   const vp_options &o = s->opt;
   int ntypes_all = 0;
@@ -595,6 +652,7 @@ static vp_status build(vp_system *s, const vp_replica_desc *reps, int32_t n_reps
   TRY(upload(s, &s->ex_list, ex_list));
   TRY(upload(s, &s->cforce, cforce));
   TRY(upload(s, &s->xf, xf_h));
+  if (o.contact_order) TRY(native_contacts(s, reps));
   TRY(dalloc(s, &s->rmsd, (size_t)n_reps));
   if (o.nst_out > 0) {
     s->out_cap = o.out_capacity > 0 ? o.out_capacity : 1024;
@@ -652,6 +710,7 @@ static vp_status build(vp_system *s, const vp_replica_desc *reps, int32_t n_reps
     launch_kinetic(s, s->traj.ke_tile, 0);
     launch_record(s, false, 0);
   }
+  if (o.contact_order) launch_contact_form(s, 0);  // contacts formed in X_0
   HIPCHECK(hipGetLastError());
   HIPCHECK(hipDeviceSynchronize());
   return VP_OK;
@@ -919,6 +978,7 @@ static void enqueue_block(vp_system *s, int steps, hipStream_t st) {
     if (rec) launch_energies(s, s->traj, true, st);
     if (s->tangent) launch_tangent_forces(s, s->traj, st);
     launch_cv(s, s->traj, 1, st, s->tangent);
+    if (s->opt.contact_order) launch_contact_form(s, st);
   }
   launch_integrate(s, INT_FINISH, st);
   if (rec) launch_record(s, true, st);
@@ -1216,6 +1276,90 @@ extern "C" vp_status vp_energy_records(vp_system *s, double *out_host, int32_t c
       std::memcpy(out_host + ((size_t)r * take + k) * VP_REC_COUNT,
                   &all[((size_t)r * s->out_cap + slot) * VP_REC_COUNT], sizeof(double) * VP_REC_COUNT);
     }
+  return VP_OK;
+}
+
+extern "C" vp_status vp_contact_order(vp_system *s, int32_t rep, int32_t *pairs_host, int64_t *steps_host,
+                                      int32_t cap, int32_t *n_contacts) {
+  if (!s || !n_contacts || cap < 0) return fail(VP_ERR_ARG, "invalid argument");
+  if (rep < 0 || rep >= s->R) return fail(VP_ERR_ARG, "replica index out of range");
+  if (!s->opt.contact_order) return fail(VP_ERR_STATE, "contact order was not enabled at creation (vp_options.contact_order)");
+  const RepInfo &R = s->info_h[rep];
+  *n_contacts = R.n_contacts;
+  const int take = std::min(cap, R.n_contacts);
+  if (take == 0) return VP_OK;
+  HIPCHECK(sync_system(s));
+  if (pairs_host)
+    HIPCHECK(hipMemcpy(pairs_host, s->cpairs + R.cp_off, sizeof(int2) * (size_t)take, hipMemcpyDeviceToHost));
+  if (steps_host) {
+    std::vector<int32_t> t(take);
+    HIPCHECK(hipMemcpy(t.data(), s->t_form + R.tf_off, sizeof(int32_t) * (size_t)take, hipMemcpyDeviceToHost));
+    for (int k = 0; k < take; ++k) steps_host[k] = t[k];
+  }
+  return VP_OK;
+}
+
+extern "C" vp_status vp_path_similarity(vp_system *s, double *sim_host) {
+  if (!s || !sim_host) return fail(VP_ERR_ARG, "NULL argument");
+  if (!s->opt.contact_order) return fail(VP_ERR_STATE, "contact order was not enabled at creation (vp_options.contact_order)");
+  const int R = s->R;
+  std::vector<int2> pr;
+  for (int a = 0; a < R; ++a)
+    for (int b = a + 1; b < R; ++b) {
+      const RepInfo &A = s->info_h[a], &B = s->info_h[b];
+      if (A.n_contacts >= 2 && A.cp_off == B.cp_off && A.n_contacts == B.n_contacts) pr.push_back(make_int2(a, b));
+    }
+  for (int a = 0; a < R; ++a)
+    for (int b = 0; b < R; ++b) sim_host[(size_t)a * R + b] = (a == b && s->info_h[a].n_contacts >= 2) ? 1.0 : NAN;
+  if (pr.empty()) return VP_OK;
+  if ((size_t)s->max_contacts * 2 * sizeof(int32_t) > 160 * 1024)
+    return fail(VP_ERR_ARG, "too many native contacts for the similarity kernel's LDS (at most 20480)");
+  HIPCHECK(sync_system(s));
+  HIPCHECK(prepare_similarity(s->max_contacts));
+  TmpBuf pbuf(s, sizeof(int2) * pr.size()), cbuf(s, sizeof(unsigned long long) * pr.size());
+  if (!pbuf.p || !cbuf.p) return fail(VP_ERR_NOMEM, "device allocation failed");
+  HIPCHECK(hipMemcpy(pbuf.p, pr.data(), sizeof(int2) * pr.size(), hipMemcpyHostToDevice));
+  launch_similarity(s, (const int2 *)pbuf.p, (int)pr.size(), s->max_contacts, (unsigned long long *)cbuf.p, 0);
+  HIPCHECK(hipGetLastError());
+  std::vector<unsigned long long> same(pr.size());
+  HIPCHECK(hipMemcpy(same.data(), cbuf.p, sizeof(unsigned long long) * same.size(), hipMemcpyDeviceToHost));
+  for (size_t q = 0; q < pr.size(); ++q) {
+    const double nc = (double)s->info_h[pr[q].x].n_contacts;
+    const double v = (double)same[q] / (nc * (nc - 1.0));
+    sim_host[(size_t)pr[q].x * R + pr[q].y] = v;
+    sim_host[(size_t)pr[q].y * R + pr[q].x] = v;
+  }
+  return VP_OK;
+}
+
+extern "C" vp_status vp_toy_trials(const vp_toy_params *p, int32_t n_trials, const int32_t *kind_dev,
+                                   const double *k_dev, const uint64_t *seed_dev, double *out_dev,
+                                   float *path_dev, void *hip_stream) {
+  if (!p || !kind_dev || !k_dev || !seed_dev || !out_dev) return fail(VP_ERR_ARG, "NULL argument");
+  if (n_trials <= 0) return fail(VP_ERR_ARG, "n_trials must be positive");
+  if (p->n_steps < 0) return fail(VP_ERR_ARG, "n_steps must be >= 0");
+  if (!(p->mass > 0) || !(p->dt > 0) || !(p->kT > 0) || !(p->gamma >= 0))
+    return fail(VP_ERR_ARG, "mass, dt and kT must be positive and gamma non-negative");
+  if (path_dev && p->path_stride <= 0) return fail(VP_ERR_ARG, "a path buffer needs path_stride > 0");
+  launch_toy(*p, n_trials, kind_dev, k_dev, seed_dev, out_dev, path_dev, (hipStream_t)hip_stream);
+  HIPCHECK(hipGetLastError());
+  return VP_OK;
+}
+
+extern "C" vp_status vp_toy_select(const double *out_host, int32_t n, const uint8_t *eligible, int32_t *best,
+                                   double *best_phi) {
+  if (!out_host || !best || !best_phi || n < 0) return fail(VP_ERR_ARG, "invalid argument");
+  *best = -1;
+  *best_phi = INFINITY;
+  for (int r = 0; r < n; ++r) {
+    const double *o = out_host + (size_t)r * VP_TOY_COUNT;
+    if (!(o[VP_TOY_REACHED] != 0.0) || (eligible && !eligible[r]) || !std::isfinite(o[VP_TOY_PHI])) continue;
+    if (*best < 0 || o[VP_TOY_PHI] < *best_phi) {
+      *best = r;
+      *best_phi = o[VP_TOY_PHI];
+    }
+  }
+  if (*best < 0) return fail(VP_ERR_NOPATH, "no toy trial reached the product with a finite functional");
   return VP_OK;
 }
 

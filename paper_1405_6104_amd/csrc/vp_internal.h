@@ -81,7 +81,10 @@ struct RepInfo {
   double kT, dt, reach_tol;
   double reach_rmsd;            // +inf: no RMSD criterion
   int32_t xf_off;               // first row of this replica's X_f in the FP64 copy, -1 without
-  int32_t pad_;
+  int32_t n_contacts;           // native contacts (contact order on), else 0
+  int32_t cp_off;               // first pair of its native-contact list (shared by equal maps)
+  int32_t tf_off;               // first entry of its formation steps
+  int64_t r0q2;                 // (contact r0 in grid units)^2
   uint64_t seed;
 };
 
@@ -199,6 +202,9 @@ struct vp_system {
   double *rmsd = nullptr;       // [R] RMSD to X_f (vp_select_path, vp_observables)
   double *records = nullptr;    // [R][out_cap][VP_REC_COUNT] energy records
   int32_t out_cap = 0;
+  int2 *cpairs = nullptr;       // native-contact pairs (replica-local user indices) per distinct map
+  int32_t *t_form = nullptr;    // [sum of contacts] first-formation step, -1 = not yet
+  int32_t max_contacts = 0;
   // scratch shared by both contexts (list rebuild)
   int4 *xq_t = nullptr;
   float4 *vel_t = nullptr;

@@ -26,6 +26,16 @@ hipError_t prepare_energies(const vp_system *s);
 void launch_record(vp_system *s, bool gated, hipStream_t st);
 // RMSD of every replica's solute from its X_f into s->rmsd
 void launch_rmsd(vp_system *s, hipStream_t st);
+// first-formation steps of the native contacts at the current step counter
+void launch_contact_form(vp_system *s, hipStream_t st);
+// LDS of the similarity kernel for lists of up to max_contacts contacts
+hipError_t prepare_similarity(int max_contacts);
+// concordant ordered contact pairs of the replica pairs pr [npairs] into out
+void launch_similarity(vp_system *s, const int2 *pr, int npairs, int max_contacts, unsigned long long *out,
+                       hipStream_t st);
+// toy-model trials (one thread each)
+void launch_toy(const vp_toy_params &p, int n, const int32_t *kind, const double *k, const uint64_t *seed,
+                double *out, float *path, hipStream_t st);
 void launch_cv(vp_system *s, Work &W, int inc_step, hipStream_t st, bool tan);
 // derivatives along the tangents in W.tx (both directions)
 void launch_tangent_forces(vp_system *s, Work &W, hipStream_t st);

@@ -70,7 +70,7 @@ class Options(C.Structure):
                 ("use_graph", C.c_int32), ("max_neighbors", C.c_int32),
                 ("tangent", C.c_int32), ("force_shape", C.c_int32), ("autotune", C.c_int32),
                 ("nst_out", C.c_int32), ("out_capacity", C.c_int32), ("stage_cap", C.c_int32),
-                ("reserved", C.c_int32),
+                ("contact_order", C.c_int32),
                 ("dev_alloc", DEV_ALLOC), ("dev_free", DEV_FREE), ("alloc_ctx", C.c_void_p)]
 
 FORCE_SHAPES = 4
@@ -127,6 +127,25 @@ _lib.vp_energy_records.restype = C.c_int
 _lib.vp_energy_records.argtypes = [_vp, _dp, C.c_int32, C.POINTER(C.c_int32)]
 _lib.vp_device_bytes.restype = C.c_int
 _lib.vp_device_bytes.argtypes = [_vp, C.POINTER(C.c_int64)]
+_lib.vp_contact_order.restype = C.c_int
+_lib.vp_contact_order.argtypes = [_vp, C.c_int32, _ip, C.POINTER(C.c_int64), C.c_int32, C.POINTER(C.c_int32)]
+_lib.vp_path_similarity.restype = C.c_int
+_lib.vp_path_similarity.argtypes = [_vp, _dp]
+
+
+class ToyParams(C.Structure):
+    _fields_ = [(k, C.c_double) for k in ("A1", "A2", "A3", "s1", "s2", "s3", "w", "xm", "ym",
+                                          "gamma", "mass", "kT", "dt", "x0", "y0", "r_product",
+                                          "r_gate")] + [("n_steps", C.c_int32), ("path_stride", C.c_int32)]
+
+
+TOY_PLAIN, TOY_RMD, TOY_SMD = 0, 1, 2
+TOY_COLUMNS = ("phi", "reached", "t_reach", "x", "y", "z_min", "theta_gate")
+_lib.vp_toy_trials.restype = C.c_int
+_lib.vp_toy_trials.argtypes = [C.POINTER(ToyParams), C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
+                               C.c_void_p, C.c_void_p, C.c_void_p]
+_lib.vp_toy_select.restype = C.c_int
+_lib.vp_toy_select.argtypes = [_dp, C.c_int32, C.POINTER(C.c_uint8), _ip, _dp]
 _lib.vp_last_error.restype = C.c_char_p
 _lib.vp_last_error.argtypes = []
 
@@ -134,7 +153,8 @@ EXPORTED = ("vp_system_create", "vp_system_destroy", "vp_forces", "vp_step_batch
             "vp_functional", "vp_select_path", "vp_get_state", "vp_observables", "vp_sizes",
             "vp_debug_pairs", "vp_debug_noise", "vp_set_timing", "vp_kernel_timing", "vp_pair_count",
             "vp_debug_force_dir", "vp_debug_trajectory_state", "vp_tile_buckets", "vp_debug_set_tiles",
-            "vp_energy_records", "vp_device_bytes", "vp_forces_noalloc", "vp_last_error")
+            "vp_energy_records", "vp_device_bytes", "vp_forces_noalloc", "vp_contact_order",
+            "vp_path_similarity", "vp_toy_trials", "vp_toy_select", "vp_last_error")
 
 
 def _check(st):
@@ -214,7 +234,7 @@ class System:
 
     def __init__(self, reps, nstlist=0, skin=0.0, steps_per_graph=0, use_graph=True,
                  max_neighbors=0, tangent=False, force_shape=0, autotune=False, nst_out=0,
-                 out_capacity=0, stage_cap=0, torch_memory=False):
+                 out_capacity=0, stage_cap=0, contact_order=False, torch_memory=False):
         """torch_memory: the library takes all its device memory from torch's
         caching allocator (vp_options.dev_alloc) instead of hipMalloc."""
         keep = []
@@ -226,6 +246,7 @@ class System:
         opt.force_shape = int(force_shape)
         opt.autotune = int(bool(autotune))
         opt.nst_out, opt.out_capacity, opt.stage_cap = int(nst_out), int(out_capacity), int(stage_cap)
+        opt.contact_order = int(bool(contact_order))
         self._alloc = _torch_allocator() if torch_memory else None  # kept alive with the system
         if self._alloc is not None:
             opt.dev_alloc, opt.dev_free = self._alloc
@@ -363,6 +384,24 @@ class System:
             _check(_lib.vp_energy_records(self._h, out.ctypes.data_as(_dp), n.value, C.byref(n)))
         return out
 
+    def contact_order(self, rep):
+        """Native contacts of replica rep ([n, 2] int32) and the step at which each
+        first formed ([n] int64, -1 = not yet)."""
+        n = C.c_int32()
+        _check(_lib.vp_contact_order(self._h, int(rep), None, None, 0, C.byref(n)))
+        pairs = np.zeros((max(n.value, 1), 2), np.int32)
+        steps = np.zeros(max(n.value, 1), np.int64)
+        if n.value:
+            _check(_lib.vp_contact_order(self._h, int(rep), pairs.ctypes.data_as(_ip),
+                                         steps.ctypes.data_as(C.POINTER(C.c_int64)), n.value, C.byref(n)))
+        return pairs[: n.value], steps[: n.value]
+
+    def path_similarity(self):
+        """[R, R] path similarity of every pair of replicas with the same native contacts."""
+        out = np.zeros((self.n_reps, self.n_reps))
+        _check(_lib.vp_path_similarity(self._h, out.ctypes.data_as(_dp)))
+        return out
+
     def device_bytes(self):
         b = C.c_int64()
         _check(_lib.vp_device_bytes(self._h, C.byref(b)))
@@ -426,3 +465,42 @@ def _energy_autograd():
 def energy(x, system, t=0.0):
     """Differentiable total energy per replica (torch autograd)."""
     return _energy_autograd().apply(x, system, t)
+
+
+def toy_trials(params, kinds, ks, seeds, path_stride=0):
+    """Toy-model trials on the GPU: params dict (keys of ToyParams), kinds /
+    ks / seeds per trial.  Returns results [n, len(TOY_COLUMNS)] (numpy) and,
+    with path_stride > 0, the paths [n, n_steps // path_stride + 1, 2]."""
+    import torch
+    p = ToyParams()
+    for k, _ in ToyParams._fields_:
+        if k in params:
+            setattr(p, k, params[k])
+    p.path_stride = int(path_stride)
+    n = len(kinds)
+    dev = torch.device("cuda")
+    kd = torch.as_tensor(np.asarray(kinds, np.int32), device=dev)
+    kk = torch.as_tensor(np.asarray(ks, np.float64), device=dev)
+    sd = torch.as_tensor(np.asarray(seeds, np.uint64).view(np.int64), device=dev)
+    out = torch.empty((n, len(TOY_COLUMNS)), dtype=torch.float64, device=dev)
+    path = (torch.empty((n, p.n_steps // path_stride + 1, 2), dtype=torch.float32, device=dev)
+            if path_stride > 0 else None)
+    _check(_lib.vp_toy_trials(C.byref(p), n, _ptr(kd), _ptr(kk), _ptr(sd), _ptr(out),
+                              _ptr(path) if path is not None else None, _stream()))
+    res = out.cpu().numpy()
+    return (res, path.cpu().numpy()) if path is not None else res
+
+
+def toy_select(results, eligible=None):
+    """(best trial or -1, its functional) over toy results."""
+    r = np.ascontiguousarray(results, dtype=np.float64)
+    best = C.c_int32()
+    bp = C.c_double()
+    el = None if eligible is None else np.ascontiguousarray(eligible, dtype=np.uint8)
+    st = _lib.vp_toy_select(r.ctypes.data_as(_dp), len(r),
+                            el.ctypes.data_as(C.POINTER(C.c_uint8)) if el is not None else None,
+                            C.byref(best), C.byref(bp))
+    if st == -5:
+        return -1, float("inf")
+    _check(st)
+    return best.value, bp.value
