@@ -38,6 +38,16 @@ PEAK_FP32_TFLOPS = 157.3    # MI355X FP32 vector peak
 FORCE_TRAFFIC_BYTES = (614404 * 2.000 + 19200 * 1.000) * 1024
 
 
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def _oracle_rate(job):
     """Run the oracle on one replica for about `seconds`: (atom-steps, seconds, steps)."""
     desc, seconds = job
@@ -60,7 +70,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30, help="timed benchmark steps")
     ap.add_argument("--warmup", type=int, default=5, help="untimed benchmark steps")
-    ap.add_argument("--md-per-step", type=int, default=20, help="MD steps per benchmark step")
+    ap.add_argument("--md-per-step", type=int, default=120,
+                    help="MD steps per benchmark step (captured as graphs of 20 steps)")
     ap.add_argument("--replicas", type=int, default=64)
     ap.add_argument("--plain-steps", type=int, default=200)
     ap.add_argument("--timing-steps", type=int, default=5, help="blocks timed with HIP events")
@@ -70,10 +81,12 @@ def main():
                     help="seconds of oracle work per process for the CPU baseline")
     ap.add_argument("--cpu-procs", type=int, default=0,
                     help="oracle processes for the CPU baseline (0: one per core, at most 16)")
-    ap.add_argument("--workload", choices=("batch", "uneven", "derivative"), default="batch",
+    ap.add_argument("--workload", choices=("batch", "uneven", "derivative", "toy"), default="batch",
                     help="batch: 64 replicas of the 12,560-atom system; uneven: 32 replicas of "
                          "5,000-40,000 atoms with cutoffs 0.9 / 1.2 nm; derivative: 16 replicas of the "
-                         "12,560-atom system carrying dPhi/d(bias_k, ramp_rate)")
+                         "12,560-atom system carrying dPhi/d(bias_k, ramp_rate); toy: the 2-D toy "
+                         "funnel, 20,000 plain trials of 90,000 steps and 2,000 ratchet trials of "
+                         "30,000 steps at each of 8 bias constants")
     ap.add_argument("--equilibrate", type=int, default=6000, metavar="MD_STEPS",
                     help="untimed MD steps without bias of each distinct system before the trials "
                          "start: the synthetic start relaxes from ~800 K to 300 K, and the trials "
@@ -103,7 +116,10 @@ def main():
 
     from paper_1405_6104_amd import synth, vp
 
+    if args.workload == "toy":
+        return toy_bench(args)
     B = args.md_per_step
+    G = 20  # MD steps per captured graph
     t0 = time.time()
     if args.workload == "batch":
         base = synth.solvated_chain_12560()
@@ -138,12 +154,19 @@ def main():
             res = pool.map(_oracle_rate, [(reps[k % len(reps)], args.cpu_seconds) for k in range(procs)])
         steps_cpu = sum(n for _, _, n in res)
         sizes = sorted({int(reps[k % len(reps)]["n_atoms"]) for k in range(procs)})
+        # one process alone on the workload's system (and on the 1,512-atom system),
+        # a few seconds each, for the single-core figures
+        alone = _oracle_rate((reps[0], min(5.0, args.cpu_seconds)))
+        small = _oracle_rate((synth.small_chain_system(), min(5.0, args.cpu_seconds)))
         cpu = {"value": sum(a / t for a, t, _ in res), "unit": "atom-steps/s", "cores": procs,
-               "kind": "oracle",
+               "kind": "oracle", "cpu_model": _cpu_model(), "host_cpus": os.cpu_count(),
+               "single_core": {"value": alone[0] / alone[1], "atoms": int(reps[0]["n_atoms"]),
+                               "small_1512_atoms": small[0] / small[1]},
                "sample": f"{procs} processes in parallel, each the single-threaded FP64 oracle (cell-list "
                          f"pairs) on its own replica of the batch ({', '.join(f'{n:,}' for n in sizes)} "
-                         f"atoms) for ~{args.cpu_seconds:.0f} s; {steps_cpu} BAOAB steps in all; one "
-                         f"process alone: {res[0][0] / res[0][1]:.3e} atom-steps/s"}
+                         f"atoms) for ~{args.cpu_seconds:.0f} s; {steps_cpu} BAOAB steps in all; "
+                         f"single_core: one process alone for ~5 s on the same system and on the "
+                         f"1,512-atom system"}
         print(f"# cpu oracle: {cpu['value']:.4e} atom-steps/s on {procs} cores ({time.time() - tc:.1f} s)",
               file=sys.stderr, flush=True)
     torch.cuda.set_device(0)
@@ -156,7 +179,7 @@ def main():
         te = time.time()
         distinct = list(range(len(reps))) if args.workload == "uneven" else [0]
         src = (lambda r: r) if args.workload == "uneven" else (lambda r: 0)
-        eq = vp.System([dict(reps[i], bias=vp.BIAS_NONE) for i in distinct], steps_per_graph=B,
+        eq = vp.System([dict(reps[i], bias=vp.BIAS_NONE) for i in distinct], steps_per_graph=G,
                        nstlist=args.nstlist, skin=args.skin)
         for k in range(0, args.equilibrate, 1000):
             eq.step_batch(min(1000, args.equilibrate - k))
@@ -173,7 +196,7 @@ def main():
         print(f"# equilibrated {len(distinct)} system(s): T = {np.mean(temp):.1f} K "
               f"(min {np.min(temp):.1f}, max {np.max(temp):.1f})", file=sys.stderr, flush=True)
     tangent = args.workload == "derivative"
-    system = vp.System(reps, steps_per_graph=B, force_shape=args.force_shape,
+    system = vp.System(reps, steps_per_graph=G, force_shape=args.force_shape,
                        autotune=not args.no_autotune, nstlist=args.nstlist, skin=args.skin,
                        tangent=tangent)
     buckets, split = system.tile_buckets()
@@ -300,3 +323,57 @@ def main():
 
 if __name__ == "__main__":
     main()
+
+
+def toy_bench(args):
+    """The 2-D toy funnel of the supplement: 20,000 plain trials of 90,000 steps
+    and 2,000 ratchet trials of 30,000 steps at each of 8 bias constants, one
+    GPU thread per trial (FP64).  value = particle-steps/s over both launches;
+    the outcome per bias constant (fraction reached, the selected trial's Phi
+    and gate angle) is reported beside it (parity unpinned: the supplement's
+    figures are not in the text, and its printed constants give no ring
+    barrier)."""
+    import numpy as np
+    import torch
+
+    from paper_1405_6104_amd import vp
+
+    params = dict(A1=30.0, A2=20.0, A3=6.0, s1=1.0, s2=2.0, s3=2.0, w=0.03, xm=1.5, ym=0.0,
+                  gamma=1.0, mass=1.0, kT=0.2, dt=0.02, x0=0.0, y0=5.0, r_product=0.5, r_gate=2.0)
+    kvals = [0.25, 0.5, 1.0, 2.0, 4.0, 8.0, 16.0, 32.0]
+    n_plain, n_rmd = 20000, 2000
+    torch.cuda.set_device(0)
+    plain = dict(params, n_steps=90000)
+    rmd = dict(params, n_steps=30000)
+    # warm-up (short runs of the same kernels)
+    vp.toy_trials(dict(plain, n_steps=100), [vp.TOY_PLAIN] * 64, [0.0] * 64, list(range(64)))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res_p = vp.toy_trials(plain, [vp.TOY_PLAIN] * n_plain, [0.0] * n_plain, list(range(1, n_plain + 1)))
+    kinds = [vp.TOY_RMD] * (n_rmd * len(kvals))
+    ks = [k for k in kvals for _ in range(n_rmd)]
+    res_r = vp.toy_trials(rmd, kinds, ks, list(range(100001, 100001 + len(kinds))))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    steps = n_plain * plain["n_steps"] + len(kinds) * rmd["n_steps"]
+    col = {c: i for i, c in enumerate(vp.TOY_COLUMNS)}
+    outcome = {"plain_reached": float(res_p[:, col["reached"]].mean()),
+               "plain_median_first_passage_steps": float(np.median(res_p[res_p[:, col["reached"]] > 0, col["t_reach"]]))
+               if res_p[:, col["reached"]].any() else None, "rmd": []}
+    for j, k in enumerate(kvals):
+        part = res_r[j * n_rmd:(j + 1) * n_rmd]
+        best, bphi = vp.toy_select(part)
+        outcome["rmd"].append({"k_R": k, "reached": float(part[:, col["reached"]].mean()),
+                               "best_phi": bphi if best >= 0 else None,
+                               "best_theta_gate": float(part[best, col["theta_gate"]]) if best >= 0 else None})
+    out = {
+        "metric": "particle-steps/s of toy-funnel trial paths (supplement toy model)",
+        "value": steps / elapsed, "unit": "particle-steps/s", "n_gpus": 1, "steps": 1, "warmup": 1,
+        "ms_per_step": 1e3 * elapsed, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "toy funnel: 20,000 plain trials x 90,000 steps + 8 x 2,000 ratchet trials x "
+                               "30,000 steps (K_R 0.25-32), dt 0.02, gamma 1, kT 0.2, start (0, 5)"},
+        "outcome": outcome,
+        "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(out))

@@ -162,7 +162,6 @@ __global__ __launch_bounds__(64 * PARTS) __attribute__((amdgpu_waves_per_eu(MINW
 #pragma unroll
   for (int k = 0; k < SETS; ++k) fx[k] = fy[k] = fz[k] = 0.0f;
   int4 xi = make_int4(0, 0, 0, 0);
-  int nrot = 0;  // chunks this wave evaluated: set k then holds logical (k + nrot) mod SETS
   if (active) {
     xi = W.xq[slot];
     const int wr = W.wrap[slot];
@@ -175,28 +174,28 @@ __global__ __launch_bounds__(64 * PARTS) __attribute__((amdgpu_waves_per_eu(MINW
     const uint4 *lp = reinterpret_cast<const uint4 *>(W.nblist + R.list_off +
                                                       (int64_t)(b - R.blk0) * R.maxnb * kBlk) + lane;
     uint4 e = lp[(int64_t)min(part, max(nch - 1, 0)) * kBlk];
-    for (int c = part; c < nch; c += PARTS) {
-      // the next chunk's indices are fetched while this one is evaluated
-      // (the last chunk is fetched again rather than reading past the list)
-      const uint4 en = lp[(int64_t)min(c + PARTS, nch - 1) * kBlk];
-      eval_chunk<UNROLL>(e, st, reinterpret_cast<const char *>(lds), ti, wx, wy, wz, rc2, krf2, fx[0],
-                         fy[0], fz[0]);
-      // the sets rotate so that set 0 is always the one the next chunk feeds
+    // this wave takes chunks part, part + PARTS, ...: its k-th chunk of every
+    // group of SETS feeds set k, which is logical accumulator k PARTS + part
+    for (int c0 = part; c0 < nch; c0 += PARTS * SETS) {
 #pragma unroll
-      for (int k = 0; k + 1 < SETS; ++k) {
-        float t = fx[k]; fx[k] = fx[k + 1]; fx[k + 1] = t;
-        t = fy[k]; fy[k] = fy[k + 1]; fy[k + 1] = t;
-        t = fz[k]; fz[k] = fz[k + 1]; fz[k + 1] = t;
+      for (int k = 0; k < SETS; ++k) {
+        const int c = c0 + k * PARTS;
+        if (c < nch) {
+          // the next chunk's indices are fetched while this one is evaluated
+          // (the last chunk is fetched again rather than reading past the list)
+          const uint4 en = lp[(int64_t)min(c + PARTS, nch - 1) * kBlk];
+          eval_chunk<UNROLL>(e, st, reinterpret_cast<const char *>(lds), ti, wx, wy, wz, rc2, krf2, fx[k],
+                             fy[k], fz[k]);
+          e = en;
+        }
       }
-      e = en;
     }
-    nrot = nch > part ? (nch - part + PARTS - 1) / PARTS : 0;
   }
   // ---- fixed-order sum of the logical partial sums, bonded terms, store
   __syncthreads();  // every wave is done with the staged neighbourhood
 #pragma unroll
   for (int k = 0; k < SETS; ++k) {
-    const int q = ((k + nrot) % SETS) * PARTS + part;  // logical accumulator held in set k
+    const int q = k * PARTS + part;  // logical accumulator held in set k
     red[(0 * kLogicalParts + q) * kBlk + lane] = fx[k];
     red[(1 * kLogicalParts + q) * kBlk + lane] = fy[k];
     red[(2 * kLogicalParts + q) * kBlk + lane] = fz[k];
