@@ -145,7 +145,7 @@ typedef struct {
   int32_t tangent;         /* 1: also propagate dPhi/d(bias_k, ramp_rate) (vp_functional);
                               harmonic and constant biases only */
   int32_t force_shape;     /* tile shape of the force kernel (waves per 64-atom block x list
-                              entries per batch): 0: 8x8 (default), 1: 16x4, 2: 8x4, 3: 4x8 */
+                              entries per batch): 0: 8x4 (default), 1: 8x2, 2: 4x4, 3: 16x2 */
   int32_t autotune;        /* 1: time every tile shape on each size bucket at creation and
                               launch each bucket with its fastest (force_shape is ignored);
                               the forces are bitwise the same for every shape */

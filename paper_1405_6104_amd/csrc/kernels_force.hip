@@ -1217,7 +1217,7 @@ size_t energy_lds_bytes(const vp_system *s) {
 }
 
 // the tile shapes the force kernel is built for: (waves per block, entries per batch)
-const ForceShape kForceShapes[kNumForceShapes] = {{8, 8}, {16, 4}, {8, 4}, {4, 8}};
+const ForceShape kForceShapes[kNumForceShapes] = {{8, 4}, {8, 2}, {4, 4}, {16, 2}};
 
 template <int P, int U, int M>
 static hipError_t set_lds(int lds) {
@@ -1228,8 +1228,8 @@ static hipError_t set_lds(int lds) {
 hipError_t prepare_forces(const vp_system *s) {
   const int lds = (int)force_lds_bytes(s);
   hipError_t e = hipSuccess;
-  for (hipError_t x : {set_lds<8, 8, 1>(lds), set_lds<16, 4, 1>(lds), set_lds<8, 4, 1>(lds),
-                       set_lds<4, 8, 1>(lds)})
+  for (hipError_t x : {set_lds<8, 4, 1>(lds), set_lds<8, 2, 1>(lds), set_lds<4, 4, 1>(lds),
+                       set_lds<16, 2, 1>(lds)})
     if (x != hipSuccess) e = x;
   return e;
 }
@@ -1258,10 +1258,10 @@ static void launch_forces_t(vp_system *s, Work &W, const int32_t *blist, int nbl
 
 void launch_forces_shape(vp_system *s, Work &W, int shape, const int32_t *blist, int nblk, hipStream_t st) {
   switch (shape) {
-    case 0: launch_forces_t<8, 8, 1>(s, W, blist, nblk, st); break;
-    case 1: launch_forces_t<16, 4, 1>(s, W, blist, nblk, st); break;
-    case 2: launch_forces_t<8, 4, 1>(s, W, blist, nblk, st); break;
-    default: launch_forces_t<4, 8, 1>(s, W, blist, nblk, st); break;
+    case 0: launch_forces_t<8, 4, 1>(s, W, blist, nblk, st); break;
+    case 1: launch_forces_t<8, 2, 1>(s, W, blist, nblk, st); break;
+    case 2: launch_forces_t<4, 4, 1>(s, W, blist, nblk, st); break;
+    default: launch_forces_t<16, 2, 1>(s, W, blist, nblk, st); break;
   }
 }
 
