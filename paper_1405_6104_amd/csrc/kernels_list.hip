@@ -287,26 +287,34 @@ __device__ __forceinline__ int quarter_max_i(int v) {
   return v;
 }
 
-// A lane's list entries are collected in its own 16-byte row of LDS (one
-// 16-bit LDS store per entry, no register shuffling) and each full row of
-// eight is copied as one 16-byte write into the [chunk][lane][8] layout
-// through a pointer that advances one chunk (64 rows) per copy; rows past the
-// list's capacity are not stored (entries are still counted: the overflow is
-// flagged).
-__device__ __forceinline__ void list_append(uint16_t (*row)[8], int lane, uint32_t e, int &cnt,
-                                            uint4 *&rowp, const uint4 *rowend) {
-  const int k = cnt & 7;
-  row[lane][k] = (uint16_t)e;
+// A lane's list entries are collected in its own ring of 16 entries in LDS
+// (one 16-bit LDS store per entry, no register shuffling); each time eight
+// entries complete a half of the ring, that half is copied as one 16-byte
+// write into the [chunk][lane][8] layout through a pointer that advances one
+// chunk (64 rows) per copy.  Rows past the list's capacity are not stored
+// (entries are still counted: the overflow is flagged).  Two halves let a
+// batch of up to eight appends run without a per-entry check for a full row.
+typedef uint16_t ListRing[2][kBlk][8];
+__device__ __forceinline__ uint16_t &ring_slot(ListRing &ring, int lane, int cnt) {
+  return ring[(cnt >> 3) & 1][lane][cnt & 7];
+}
+__device__ __forceinline__ void ring_flush(const ListRing &ring, int lane, int half, uint4 *&rowp,
+                                           const uint4 *rowend) {
+  if (rowp < rowend) *rowp = *reinterpret_cast<const uint4 *>(ring[half][lane]);
+  rowp += kBlk;
+}
+__device__ __forceinline__ void list_append(ListRing &ring, int lane, uint32_t e, int &cnt, uint4 *&rowp,
+                                            const uint4 *rowend) {
+  ring_slot(ring, lane, cnt) = (uint16_t)e;
   ++cnt;
-  if (k == 7) {
-    if (rowp < rowend) *rowp = *reinterpret_cast<const uint4 *>(row[lane]);
-    rowp += kBlk;
-  }
+  if ((cnt & 7) == 0) ring_flush(ring, lane, ((cnt - 1) >> 3) & 1, rowp, rowend);
 }
 
 // Staged candidates tested together per step of the list kernel's inner loop
 // (kBlk is a multiple, so reads stay inside the 64-entry batch buffer).
 constexpr int kListBatch = 4;
+// Runs of cells listed per row group of the list kernel's search.
+constexpr int kMaxRuns = 2 * kBlk;
 static_assert(kBlk % kListBatch == 0, "batch must divide the candidate buffer");
 
 // One wave per block of 64 sorted atoms.  The cells that can hold a neighbour
@@ -316,15 +324,15 @@ static_assert(kBlk % kListBatch == 0, "batch must divide the candidate buffer");
 // the fine-cell ordered copy of the positions.  Each range is read 64
 // candidates at a time (one coalesced load per lane): every lane applies the
 // cell's image to its candidate and keeps it if it lies within the list
-// radius of the bounding box of one of the block's quarters (16 atoms).  Every kept candidate receives the next staging
-// index (its slot | image shift is stored) and its position is compacted into
-// LDS; then each lane tests the batch against its own atom, with no
-// communication between lanes, and appends the staging indices of the
-// candidates within the list radius (exclusions removed) to its list.  This
-// test runs in FP32 on coordinates relative to the block's corner, with the
-// radius enlarged by a bound on the rounding (a few units of 2^-24 nm): the
-// list is a superset of the exact list radius, and the force kernel applies
-// the exact cutoff.
+// radius of the bounding box of one of the block's quarters (16 atoms).
+// Every kept candidate receives the next staging index (its slot | image
+// shift is stored) and its position is compacted into LDS; then each lane
+// tests the batch against its own atom, with no communication between lanes,
+// and appends the staging indices of the candidates within the list radius
+// (exclusions removed) to its list.  This test runs in FP32 on coordinates
+// relative to the block's corner, with the radius enlarged by a bound on the
+// rounding (a few hundred units of 2^-24 nm at most): the list is a superset
+// of the exact list radius, and the force kernel applies the exact cutoff.
 template <int MODE>
 // Register budget for seven waves per SIMD (measured: a full rebuild of the
 // 64 x 12,560 batch takes 1.89 ms at seven waves with a few spilled
@@ -346,9 +354,13 @@ __global__ __launch_bounds__(kBlk) __attribute__((amdgpu_waves_per_eu(7))) void 
                                                const float4 *__restrict__ integ0,
                                                const float4 *__restrict__ tx_t,
                                                const float4 *__restrict__ tv_t) {
-  __shared__ float4 s_pos[kBlk];  // kept candidates: position relative to the block, user index
-  __shared__ __align__(16) uint16_t s_row[kBlk][8];  // each lane's list entries not yet stored
+  __shared__ float4 s_pos[kBlk];  // kept candidates: position c relative to the block corner, |c|^2
+  __shared__ __align__(16) int32_t s_uid[kBlk];      // kept candidates: user index
+  __shared__ __align__(16) ListRing s_ring;  // each lane's list entries not yet stored
   __shared__ int s_cidx[3][18];  // fine-cell edges of the replica
+  __shared__ int s_rq0[kMaxRuns];       // runs of a row group: first slot in fine-cell order,
+  __shared__ int s_rimg[kMaxRuns];      // image (packed),
+  __shared__ int s_rpre[kMaxRuns + 1];  // number of candidates before the run
   const int b = xcd_tile(blockIdx.x, nblk);
   if (b < 0) return;
   const int tile = b / (kTile / kBlk);
@@ -427,17 +439,39 @@ __global__ __launch_bounds__(kBlk) __attribute__((amdgpu_waves_per_eu(7))) void 
   const int uz1 = (int)floordiv(((long long)bz1 + rl) * ncz, Lz);
   const double rl2d = (double)rl * (double)rl;
   const float rl2 = R.rl2q;
-  // enlarged radius of the FP32 relative test: coordinates of kept candidates
-  // stay within M = block extent + rl of the corner, each FP32 rounding moves
-  // a coordinate by at most M 2^-24 and a separation by 2^-24 relative, so
-  // 8 + (4 M + 8 rl) 2^-24 units bound the change of a computed distance
-  const long long ext = max(bx1 - bx0, max(by1 - by0, bz1 - bz0));
-  const float rlx = (float)(rl + 8 + ((4 * (ext + rl) + 8 * rl) >> 24) + 1);
-  const float rl2x = rlx * rlx;
-  // the lane's atom relative to the block corner (inactive lanes far away)
-  const float ax = active ? (float)(wx - bx0) : 1.0e9f, ay = active ? (float)(wy - by0) : 1.0e9f,
-              az = active ? (float)(wz - bz0) : 1.0e9f;
-  const int a32 = a - 32;
+  // The candidate test runs in FP32 relative to the block's corner, in the
+  // expanded form |c - a|^2 = |c|^2 - 2 c.a + |a|^2: |c|^2 is formed once per
+  // kept candidate, so a test is three fused multiply-adds against the
+  // threshold rl2x - |a|^2 of the lane.  With Ma >= |a_k| and Mc >= |c_k|
+  // (kept candidates lie within rl of a quarter box, itself inside the block
+  // box), every rounding (coordinates, |c|^2, |a|^2, the products and the
+  // threshold) moves the computed difference by at most 2^-24 times a multiple
+  // of (Mc + Ma)^2 or rl^2; the sum of those terms is below
+  // E = 2^-24 (64 (Mc + Ma)^2 + 2 rl^2) + 16, so with rl2x >= rl^2 + E every
+  // candidate within the list radius passes (the list is a superset of the
+  // exact list, and the force kernel applies the exact cutoff).
+  float m2ax = 0.f, m2ay = 0.f, m2az = 0.f, thr = -INFINITY;
+  {
+    const double ma = (double)max(bx1 - bx0, max(by1 - by0, bz1 - bz0)) + 2.0;
+    const double mc = ma + (double)rl + 64.0;
+    const double e = 0x1p-24 * (64.0 * (mc + ma) * (mc + ma) + 2.0 * rl2d) + 16.0;
+    const float rl2x = (float)((rl2d + e) * (1.0 + 0x1p-20));
+    if (active) {
+      const float ax = (float)(wx - bx0), ay = (float)(wy - by0), az = (float)(wz - bz0);
+      m2ax = -2.f * ax;
+      m2ay = -2.f * ay;
+      m2az = -2.f * az;
+      thr = rl2x - __builtin_fmaf(ax, ax, __builtin_fmaf(ay, ay, az * az));
+    }
+  }
+  // kept candidate c passes the lane's test
+  auto near = [&](const float4 c) {
+    return __builtin_fmaf(c.x, m2ax, __builtin_fmaf(c.y, m2ay, __builtin_fmaf(c.z, m2az, c.w))) < thr;
+  };
+  // exclusion window: for a candidate of user index oj, bit oj - a + 32 of exm
+  // is moved to bit 63 by a left shift of a + 31 - oj (in range iff that
+  // shift is below 64)
+  const int exs = a + 31;
   const int lb = b - R.blk0;
   uint16_t *lst = W.nblist + R.list_off + (int64_t)lb * R.maxnb * kBlk;
   // this lane's row of list chunk 0, and the end of the block's list
@@ -455,6 +489,18 @@ __global__ __launch_bounds__(kBlk) __attribute__((amdgpu_waves_per_eu(7))) void 
   // would exceed the block's staging capacity, the block is built again in
   // exact mode, which stages only candidates within the list radius of at
   // least one atom (a ballot per candidate; rare).
+  // The rows of the search, (uz, uy) with uz outermost, are taken in groups.
+  // One lane per row finds the cells of its row that pass the gap test (the
+  // gap along x first falls, then grows, so they are consecutive) and splits
+  // them at image boundaries into runs, each a range of the fine-cell order.
+  // The group's runs are listed in LDS in row order and their candidates are
+  // read 64 at a time across run boundaries, so every load but the group's
+  // last is full.  The candidates come in the order of a sequential scan of
+  // rows and cells.
+  const int ny = uy1 - uy0 + 1, nrows = (uz1 - uz0 + 1) * ny;
+  const int nimg = (int)(floordiv(ux1, ncx) - floordiv(ux0, ncx)) + 1;  // runs per row at most
+  const int gsize = nimg <= kMaxRuns ? min(kBlk, kMaxRuns / nimg) : 0;
+  if (gsize == 0) bad = true;  // a list radius of more than a hundred box edges
   bool exact = false;
   for (int mode = 0; mode < 2; ++mode) {
     exact = mode == 1;
@@ -462,158 +508,201 @@ __global__ __launch_bounds__(kBlk) __attribute__((amdgpu_waves_per_eu(7))) void 
     cnt = 0;
     rowp = row0;
     bool full = false;
-    int iz = uz0 >= 0 ? uz0 / ncz : -((-uz0 + ncz - 1) / ncz);
-    int cz = uz0 - iz * ncz;
-    for (int uz = uz0; uz <= uz1 && !full; ++uz) {
-      // gap between the cell's slab and the block box along z (coordinate units)
-      const long long zl = (long long)iz * Lz + s_cidx[2][cz], zh = (long long)iz * Lz + s_cidx[2][cz + 1];
-      const double gz = (double)max(0ll, max(zl - bz1, (long long)bz0 - zh));
-      int iy = uy0 >= 0 ? uy0 / ncy : -((-uy0 + ncy - 1) / ncy);
-      int cy = uy0 - iy * ncy;
-      for (int uy = uy0; uy <= uy1 && !full; ++uy) {
-        const long long yl = (long long)iy * Ly + s_cidx[1][cy], yh = (long long)iy * Ly + s_cidx[1][cy + 1];
+    for (int g0 = 0; gsize > 0 && g0 < nrows && !full; g0 += gsize) {
+      // ---- runs of the group's rows
+      int nr = 0, ua = 0, ub = 0, rowcell = 0, iyr = 0, izr = 0;
+      if (lane < gsize && g0 + lane < nrows) {
+        const int row = g0 + lane;
+        const int uz = uz0 + row / ny, uy = uy0 + row % ny;
+        izr = (int)floordiv(uz, ncz);
+        iyr = (int)floordiv(uy, ncy);
+        const int cz = uz - izr * ncz, cy = uy - iyr * ncy;
+        rowcell = (cz * ncy + cy) * ncx;
+        // gaps between the row's slabs and the block box (coordinate units)
+        const long long zl = (long long)izr * Lz + s_cidx[2][cz], zh = (long long)izr * Lz + s_cidx[2][cz + 1];
+        const double gz = (double)max(0ll, max(zl - bz1, (long long)bz0 - zh));
+        const long long yl = (long long)iyr * Ly + s_cidx[1][cy], yh = (long long)iyr * Ly + s_cidx[1][cy + 1];
         const double gy = (double)max(0ll, max(yl - by1, (long long)by0 - yh));
         const double gyz = gz * gz + gy * gy;
         if (gyz <= rl2d) {
-          int ix = ux0 >= 0 ? ux0 / ncx : -((-ux0 + ncx - 1) / ncx);
-          int cx = ux0 - ix * ncx;
-          int ux = ux0;
-          while (ux <= ux1 && !full) {
-            // the next run of cells of this row that pass the gap test and share an image
+          int ix = (int)floordiv(ux0, ncx), cx = ux0 - ix * ncx;
+          bool found = false;
+          for (int ux = ux0; ux <= ux1; ++ux) {
             const long long xl = (long long)ix * Lx + s_cidx[0][cx], xh = (long long)ix * Lx + s_cidx[0][cx + 1];
             const double gx = (double)max(0ll, max(xl - bx1, (long long)bx0 - xh));
-            if (gyz + gx * gx > rl2d) {
-              ++ux;
-              if (++cx == ncx) { cx = 0; ++ix; }
-              continue;
+            if (gyz + gx * gx <= rl2d) {
+              if (!found) ua = ux;
+              ub = ux;
+              found = true;
             }
-            int ce = cx;  // last cell of the run
-            while (ux + (ce - cx) + 1 <= ux1 && ce + 1 < ncx) {
-              // cells to the right only grow apart from the box
-              const double gx2 = (double)max(0ll, (long long)ix * Lx + s_cidx[0][ce + 1] - (long long)bx1);
-              if (gyz + gx2 * gx2 > rl2d) break;
-              ++ce;
-            }
-            const int c0 = (cz * ncy + cy) * ncx + cx;
-            const int q0 = cstart[c0], q1 = cstart[c0 + (ce - cx) + 1];
-            const int six = ix, siy = iy, siz = iz;
-            ux += ce - cx + 1;
-            cx = ce + 1;
-            if (cx == ncx) { cx = 0; ++ix; }
-            for (int qb = q0; qb < q1 && !full; qb += kBlk) {
-              // ---- load 64 candidates, keep those near one of the quarter boxes
-              const int q = qb + lane;
-              bool keep = false;
-              float4 cpos = make_float4(0.f, 0.f, 0.f, 0.f);
-              uint32_t code = 0u;
-              if (q < q1) {
-                const int4 cxq = cellx_t[off + q];
-                const int2 jw = celljw_t[off + q];
-                const int px = cxq.x + six * Lx, py = cxq.y + siy * Ly, pz = cxq.z + siz * Lz;
-                // kept if within the list radius of a quarter box; a box distance
-                // never exceeds an atom distance, also after rounding
-#pragma unroll
-                for (int g = 0; g < 4; ++g) {
-                  const int4 q0 = s_qb[g][0], q1 = s_qb[g][1];
-                  const float gxq = (float)max(0, max(q0.x - px, px - q0.y));
-                  const float gyq = (float)max(0, max(q0.z - py, py - q0.w));
-                  const float gzq = (float)max(0, max(q1.x - pz, pz - q1.y));
-                  keep = keep || (q1.z != 0 && qr2(gxq, gyq, gzq) < rl2);
-                }
-                const int sx = six - unpack_wrap(jw.y, 0), sy = siy - unpack_wrap(jw.y, 1),
-                          sz = siz - unpack_wrap(jw.y, 2);
-                if (keep && (sx < -16 || sx > 15 || sy < -16 || sy > 15 || sz < -16 || sz > 15)) {
-                  bad = true;  // shift not representable: the replica is flagged
-                  keep = false;
-                }
-                cpos = make_float4((float)(px - bx0), (float)(py - by0), (float)(pz - bz0),
-                                   __int_as_float(cxq.w));
-                code = (uint32_t)jw.x | ((uint32_t)((sx + 16) & 31) << 16) |
-                       ((uint32_t)((sy + 16) & 31) << 21) | ((uint32_t)((sz + 16) & 31) << 26);
-              }
-              const uint64_t km = __ballot(keep);
-              const int at = __popcll(km & ((1ull << lane) - 1ull));
-              const int nk = __popcll(km);
-              if (!exact && nst + nk > cap) {
-                full = true;  // uniform: the block is redone in exact mode
-                break;
-              }
-              if (keep) s_pos[at] = cpos;
-              if (!exact && keep) stg[nst + at] = code;  // every kept candidate is staged
-              __syncthreads();
-              if (!exact) {
-                // ---- every staged candidate against the lane's own atom
-                if (!anyfar) {
-                  // kListBatch candidates read and tested together (their LDS
-                  // reads overlap), then appended in order; entries of s_pos
-                  // past nk are stale and masked out
-                  for (int k0 = 0; k0 < nk; k0 += kListBatch) {
-                    float4 c[kListBatch];
-#pragma unroll
-                    for (int u = 0; u < kListBatch; ++u) c[u] = s_pos[k0 + u];
-                    bool in[kListBatch];
-#pragma unroll
-                    for (int u = 0; u < kListBatch; ++u) {
-                      const float dx = c[u].x - ax, dy = c[u].y - ay, dz = c[u].z - az;
-                      const int d = __float_as_int(c[u].w) - a32;
-                      const bool exw = (unsigned)d < 64u && ((exm >> (d & 63)) & 1ull);
-                      in[u] = k0 + u < nk && qr2(dx, dy, dz) < rl2x && !exw;
-                    }
-#pragma unroll
-                    for (int u = 0; u < kListBatch; ++u)
-                      if (in[u])  // entries past maxnb are counted only to flag the overflow
-                        list_append(s_row, lane, (uint32_t)(nst + k0 + u), cnt, rowp, rowend);
-                  }
-                } else {
-                  for (int k = 0; k < nk; ++k) {
-                    const float4 c = s_pos[k];
-                    const float dx = c.x - ax, dy = c.y - ay, dz = c.z - az;
-                    const int oj = __float_as_int(c.w);
-                    const int d = oj - a32;
-                    const bool win = (unsigned)d < 64u;
-                    bool in = qr2(dx, dy, dz) < rl2x && !(win && ((exm >> (d & 63)) & 1ull));
-                    if (in && !win && exfar)
-                      for (int e = e0; e < e1; ++e) in = in && (ex_list[e] != oj);
-                    if (in) {
-                      list_append(s_row, lane, (uint32_t)(nst + k), cnt, rowp, rowend);
-                    }
-                  }
-                }
-                nst += nk;
-              } else {
-                // ---- exact mode: a candidate is staged only if some atom needs it
-                const int nst0 = nst;
-                uint64_t acc = 0ull;
-                for (int k = 0; k < nk; ++k) {
-                  const float4 c = s_pos[k];
-                  const float dx = c.x - ax, dy = c.y - ay, dz = c.z - az;
-                  const int oj = __float_as_int(c.w);
-                  const int d = oj - a32;
-                  const bool win = (unsigned)d < 64u;
-                  bool in = qr2(dx, dy, dz) < rl2x && !(win && ((exm >> (d & 63)) & 1ull));
-                  if (in && !win && exfar)
-                    for (int e = e0; e < e1; ++e) in = in && (ex_list[e] != oj);
-                  if (__ballot(in)) {
-                    if (nst < cap) {
-                      if (in) {
-                        list_append(s_row, lane, (uint32_t)nst, cnt, rowp, rowend);
-                      }
-                      acc |= 1ull << k;
-                      ++nst;
-                    } else {
-                      bad = true;  // staging full even in exact mode: the replica is flagged
-                    }
-                  }
-                }
-                if (keep && ((acc >> at) & 1ull)) stg[nst0 + __popcll(acc & ((1ull << at) - 1ull))] = code;
-              }
-              __syncthreads();
+            if (++cx == ncx) {
+              cx = 0;
+              ++ix;
             }
           }
+          if (found) nr = (int)(floordiv(ub, ncx) - floordiv(ua, ncx)) + 1;
         }
-        if (++cy == ncy) { cy = 0; ++iy; }
       }
-      if (++cz == ncz) { cz = 0; ++iz; }
+      int roff = nr;  // inclusive scan of the run counts
+#pragma unroll
+      for (int o = 1; o < kBlk; o <<= 1) {
+        const int t = __shfl_up(roff, o, kBlk);
+        if (lane >= o) roff += t;
+      }
+      const int nruns = __shfl(roff, kBlk - 1, kBlk);
+      roff -= nr;
+      for (int k = 0; k < nr; ++k) {
+        const int im = (int)floordiv(ua, ncx) + k;
+        const int lo = max(ua, im * ncx), hi = min(ub, im * ncx + ncx - 1);
+        const int c0 = rowcell + lo - im * ncx;
+        const int qs = cstart[c0];
+        s_rq0[roff + k] = qs;
+        s_rpre[roff + k] = cstart[c0 + hi - lo + 1] - qs;  // length, replaced by its prefix below
+        s_rimg[roff + k] = pack_wrap(im, iyr, izr);
+      }
+      __syncthreads();
+      int total = 0;
+      {
+        // exclusive prefix of the run lengths, two runs per lane; entries past
+        // the last run hold the total
+        const int l0 = 2 * lane < nruns ? s_rpre[2 * lane] : 0;
+        const int l1 = 2 * lane + 1 < nruns ? s_rpre[2 * lane + 1] : 0;
+        int incl = l0 + l1;
+#pragma unroll
+        for (int o = 1; o < kBlk; o <<= 1) {
+          const int t = __shfl_up(incl, o, kBlk);
+          if (lane >= o) incl += t;
+        }
+        total = __shfl(incl, kBlk - 1, kBlk);
+        const int ex = incl - l0 - l1;
+        s_rpre[2 * lane] = ex;
+        s_rpre[2 * lane + 1] = ex + l0;
+        if (lane == kBlk - 1) s_rpre[kMaxRuns] = total;
+      }
+      __syncthreads();
+      int rc = 0;  // run of the first candidate of the next load (uniform)
+      for (int t0 = 0; t0 < total && !full; t0 += kBlk) {
+        const int t = t0 + lane;
+        const bool valid = t < total;
+        int run = rc;
+        if (valid)
+          while (s_rpre[run + 1] <= t) ++run;
+        rc = __shfl(run, kBlk - 1, kBlk);  // lane 63 is valid whenever another load follows
+        // ---- load 64 candidates, keep those near one of the quarter boxes
+        bool keep = false;
+        float4 cpos = make_float4(0.f, 0.f, 0.f, 0.f);
+        uint32_t code = 0u;
+        int uid = 0;
+        if (valid) {
+          const int q = s_rq0[run] + (t - s_rpre[run]);
+          const int img = s_rimg[run];
+          const int six = unpack_wrap(img, 0), siy = unpack_wrap(img, 1), siz = unpack_wrap(img, 2);
+          const int4 cxq = cellx_t[off + q];
+          const int2 jw = celljw_t[off + q];
+          const int px = cxq.x + six * Lx, py = cxq.y + siy * Ly, pz = cxq.z + siz * Lz;
+          // kept if within the list radius of a quarter box; a box distance
+          // never exceeds an atom distance, also after rounding
+#pragma unroll
+          for (int g = 0; g < 4; ++g) {
+            const int4 q0 = s_qb[g][0], q1 = s_qb[g][1];
+            const float gxq = (float)max(0, max(q0.x - px, px - q0.y));
+            const float gyq = (float)max(0, max(q0.z - py, py - q0.w));
+            const float gzq = (float)max(0, max(q1.x - pz, pz - q1.y));
+            keep = keep || (q1.z != 0 && qr2(gxq, gyq, gzq) < rl2);
+          }
+          const int sx = six - unpack_wrap(jw.y, 0), sy = siy - unpack_wrap(jw.y, 1),
+                    sz = siz - unpack_wrap(jw.y, 2);
+          if (keep && (sx < -16 || sx > 15 || sy < -16 || sy > 15 || sz < -16 || sz > 15)) {
+            bad = true;  // shift not representable: the replica is flagged
+            keep = false;
+          }
+          const float cx = (float)(px - bx0), cy = (float)(py - by0), cz = (float)(pz - bz0);
+          cpos = make_float4(cx, cy, cz, __builtin_fmaf(cx, cx, __builtin_fmaf(cy, cy, cz * cz)));
+          uid = cxq.w;
+          code = (uint32_t)jw.x | ((uint32_t)((sx + 16) & 31) << 16) |
+                 ((uint32_t)((sy + 16) & 31) << 21) | ((uint32_t)((sz + 16) & 31) << 26);
+        }
+        const uint64_t km = __ballot(keep);
+        const int at = __popcll(km & ((1ull << lane) - 1ull));
+        const int nk = __popcll(km);
+        if (!exact && nst + nk > cap) {
+          full = true;  // uniform: the block is redone in exact mode
+          break;
+        }
+        if (keep) {
+          s_pos[at] = cpos;
+          s_uid[at] = uid;
+        }
+        // the fast test reads whole batches: entries up to the next
+        // multiple of the batch are made inert
+        if (lane >= nk && lane < ((nk + kListBatch - 1) & ~(kListBatch - 1)))
+          s_pos[lane] = make_float4(0.f, 0.f, 0.f, 3.0e38f);
+        if (!exact && keep) stg[nst + at] = code;  // every kept candidate is staged
+        __syncthreads();
+        if (!exact) {
+          // ---- every staged candidate against the lane's own atom
+          if (!anyfar) {
+            // kListBatch candidates read and tested together (their LDS
+            // reads overlap), then appended in order with one check for a
+            // completed half of the ring per batch (a batch adds at most
+            // four entries, so at most one half completes)
+            for (int k0 = 0; k0 < nk; k0 += kListBatch) {
+              float4 c[kListBatch];
+#pragma unroll
+              for (int u = 0; u < kListBatch; ++u) c[u] = s_pos[k0 + u];
+              const int4 oj = *reinterpret_cast<const int4 *>(&s_uid[k0]);
+              const int ojs[kListBatch] = {oj.x, oj.y, oj.z, oj.w};
+              static_assert(kListBatch == 4, "one int4 of user indices per batch");
+              const int cnt0 = cnt;
+#pragma unroll
+              for (int u = 0; u < kListBatch; ++u) {
+                const uint32_t sh = (uint32_t)(exs - ojs[u]);
+                const bool exw = sh < 64u && (int32_t)(uint32_t)((exm << (sh & 63u)) >> 32) < 0;
+                const bool in = near(c[u]) && !exw;
+                if (in) ring_slot(s_ring, lane, cnt) = (uint16_t)(nst + k0 + u);
+                cnt += in ? 1 : 0;
+              }
+              if ((cnt ^ cnt0) & 8) ring_flush(s_ring, lane, (cnt0 >> 3) & 1, rowp, rowend);
+            }
+          } else {
+            for (int k = 0; k < nk; ++k) {
+              const int oj = s_uid[k];
+              const uint32_t sh = (uint32_t)(exs - oj);
+              const bool win = sh < 64u;
+              bool in = near(s_pos[k]) && !(win && (int32_t)(uint32_t)((exm << (sh & 63u)) >> 32) < 0);
+              if (in && !win && exfar)
+                for (int e = e0; e < e1; ++e) in = in && (ex_list[e] != oj);
+              if (in) list_append(s_ring, lane, (uint32_t)(nst + k), cnt, rowp, rowend);
+            }
+          }
+          nst += nk;
+        } else {
+          // ---- exact mode: a candidate is staged only if some atom needs it
+          const int nst0 = nst;
+          uint64_t acc = 0ull;
+          for (int k = 0; k < nk; ++k) {
+            const int oj = s_uid[k];
+            const uint32_t sh = (uint32_t)(exs - oj);
+            const bool win = sh < 64u;
+            bool in = near(s_pos[k]) && !(win && (int32_t)(uint32_t)((exm << (sh & 63u)) >> 32) < 0);
+            if (in && !win && exfar)
+              for (int e = e0; e < e1; ++e) in = in && (ex_list[e] != oj);
+            if (__ballot(in)) {
+              if (nst < cap) {
+                if (in) {
+                  list_append(s_ring, lane, (uint32_t)nst, cnt, rowp, rowend);
+                }
+                acc |= 1ull << k;
+                ++nst;
+              } else {
+                bad = true;  // staging full even in exact mode: the replica is flagged
+              }
+            }
+          }
+          if (keep && ((acc >> at) & 1ull)) stg[nst0 + __popcll(acc & ((1ull << at) - 1ull))] = code;
+        }
+        __syncthreads();
+      }
     }
     if (!full) break;
   }
@@ -624,7 +713,7 @@ __global__ __launch_bounds__(kBlk) __attribute__((amdgpu_waves_per_eu(7))) void 
     cnt = maxnb - 8;
   } else if (active) {
     // pad to a multiple of 8 with the inert staging entry (index cap)
-    while (cnt & 7) list_append(s_row, lane, (uint32_t)cap, cnt, rowp, rowend);
+    while (cnt & 7) list_append(s_ring, lane, (uint32_t)cap, cnt, rowp, rowend);
   }
   W.nbcnt[slot] = active ? cnt : 0;
   if (lane == 0) W.stage_n[b] = nst;
