@@ -171,9 +171,8 @@ __global__ __launch_bounds__(64 * PARTS) __attribute__((amdgpu_waves_per_eu(MINW
     const float4 ti = tab[xi.w];
     const float rc2 = R.rc2q, krf2 = R.krf2q;
     const int nch = W.nbcnt[slot] >> 3;
-    const uint4 *lp = reinterpret_cast<const uint4 *>(W.nblist + R.list_off +
-                                                      (int64_t)(b - R.blk0) * R.maxnb * kBlk) + lane;
-    uint4 e = lp[(int64_t)min(part, max(nch - 1, 0)) * kBlk];
+    const uint4 *lp = reinterpret_cast<const uint4 *>(W.nblist + R.list_off + (int64_t)(b - R.blk0) * R.maxnb * kBlk);
+    uint4 e = lp[list_row(min(part, max(nch - 1, 0)), lane)];
     // this wave takes chunks part, part + PARTS, ...: its k-th chunk of every
     // group of SETS feeds set k, which is logical accumulator k PARTS + part
     for (int c0 = part; c0 < nch; c0 += PARTS * SETS) {
@@ -183,7 +182,7 @@ __global__ __launch_bounds__(64 * PARTS) __attribute__((amdgpu_waves_per_eu(MINW
         if (c < nch) {
           // the next chunk's indices are fetched while this one is evaluated
           // (the last chunk is fetched again rather than reading past the list)
-          const uint4 en = lp[(int64_t)min(c + PARTS, nch - 1) * kBlk];
+          const uint4 en = lp[list_row(min(c + PARTS, nch - 1), lane)];
           eval_chunk<UNROLL>(e, st, reinterpret_cast<const char *>(lds), ti, wx, wy, wz, rc2, krf2, fx[k],
                              fy[k], fz[k]);
           e = en;
@@ -275,7 +274,7 @@ __global__ __launch_bounds__(kForceThreads) void k_pair_energy(const RepInfo *__
     const int nent = W.nbcnt[slot];
     const uint16_t *lp = W.nblist + R.list_off + (int64_t)(b - R.blk0) * R.maxnb * kBlk;
     for (int k = part; k < nent; k += kParts) {
-      const int L = lp[(((k >> 3) * kBlk) + lane) * 8 + (k & 7)];
+      const int L = lp[list_row(k >> 3, lane) * 8 + (k & 7)];
       const int4 sj = st[L];
       const float4 tj = *reinterpret_cast<const float4 *>(reinterpret_cast<const char *>(lds) + sj.w);
       const float dx = (float)(sj.x - wx), dy = (float)(sj.y - wy), dz = (float)(sj.z - wz);
@@ -549,10 +548,9 @@ __global__ __launch_bounds__(kForceThreads) void k_tangent_forces(
     const float4 ti = tab[xi.w];
     const float rc2 = R.rc2q, krf2 = R.krf2q;
     const int nch = W.nbcnt[slot] >> 3;
-    const uint4 *lp = reinterpret_cast<const uint4 *>(W.nblist + R.list_off +
-                                                      (int64_t)(b - R.blk0) * R.maxnb * kBlk) + lane;
+    const uint4 *lp = reinterpret_cast<const uint4 *>(W.nblist + R.list_off + (int64_t)(b - R.blk0) * R.maxnb * kBlk);
     for (int c = part; c < nch; c += kParts) {
-      const uint4 e = lp[(int64_t)c * kBlk];
+      const uint4 e = lp[list_row(c, lane)];
       const uint32_t w[4] = {e.x, e.y, e.z, e.w};
 #pragma unroll
       for (int u = 0; u < 8; ++u) {

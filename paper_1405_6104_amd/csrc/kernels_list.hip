@@ -287,32 +287,57 @@ __device__ __forceinline__ int quarter_max_i(int v) {
   return v;
 }
 
-// A lane's list entries are collected in its own ring of 16 entries in LDS
-// (one 16-bit LDS store per entry, no register shuffling); each time eight
-// entries complete a half of the ring, that half is copied as one 16-byte
-// write into the [chunk][lane][8] layout through a pointer that advances one
-// chunk (64 rows) per copy.  Rows past the list's capacity are not stored
-// (entries are still counted: the overflow is flagged).  Two halves let a
-// batch of up to eight appends run without a per-entry check for a full row.
-typedef uint16_t ListRing[2][kBlk][8];
-__device__ __forceinline__ uint16_t &ring_slot(ListRing &ring, int lane, int cnt) {
-  return ring[(cnt >> 3) & 1][lane][cnt & 7];
-}
-__device__ __forceinline__ void ring_flush(const ListRing &ring, int lane, int half, uint4 *&rowp,
-                                           const uint4 *rowend) {
-  if (rowp < rowend) *rowp = *reinterpret_cast<const uint4 *>(ring[half][lane]);
-  rowp += kBlk;
-}
-__device__ __forceinline__ void list_append(ListRing &ring, int lane, uint32_t e, int &cnt, uint4 *&rowp,
-                                            const uint4 *rowend) {
-  ring_slot(ring, lane, cnt) = (uint16_t)e;
-  ++cnt;
-  if ((cnt & 7) == 0) ring_flush(ring, lane, ((cnt - 1) >> 3) & 1, rowp, rowend);
-}
+// A lane's list entries are collected in LDS, in a buffer of twelve entries
+// of its own, by one 16-bit store per entry at a running address.  When the
+// buffer holds eight or more entries, the first eight are copied as one
+// 16-byte write into the [chunk][lane][8] layout, through a pointer that
+// advances one chunk (64 rows) per copy, and the rest move to the front.
+// Rows past the list's capacity are not stored (entries are still counted:
+// the overflow is flagged).  Twelve entries let a batch of up to four
+// appends run with one check for a full row after it.
+constexpr int kBufLen = 12;
+constexpr int kBufStride = 2 * kBufLen;  // bytes between lanes' buffers
+typedef __attribute__((address_space(3))) uint16_t lds_u16;  // 32-bit LDS addresses
+typedef __attribute__((address_space(3))) uint32_t lds_u32;
+__device__ __forceinline__ lds_u16 *lds16(uint32_t a) { return (lds_u16 *)(size_t)a; }
+__device__ __forceinline__ lds_u32 *lds32(uint32_t a) { return (lds_u32 *)(size_t)a; }
+// the buffer's addresses are kept as plain 32-bit integers, so that an append
+// is a store and an add of 0 or 2
+struct ListBuf {
+  uint32_t base;  // LDS byte address of the lane's entries (4-byte aligned)
+  uint32_t wa;    // LDS byte address of the next free entry
+  uint4 *list;    // the block's list rows
+  int lane;
+  int rowcap;     // rows per lane
+  int rows;       // rows copied out, stored or not
+
+  __device__ __forceinline__ void flush() {
+    const uint4 r = make_uint4(*lds32(base), *lds32(base + 4), *lds32(base + 8), *lds32(base + 12));
+    if (rows < rowcap) list[list_row(rows, lane)] = r;
+    ++rows;
+    const uint32_t t0 = *lds32(base + 16), t1 = *lds32(base + 20);
+    *lds32(base) = t0;
+    *lds32(base + 4) = t1;
+    wa -= 16;
+  }
+  __device__ __forceinline__ void append(uint32_t e) {
+    *lds16(wa) = (uint16_t)e;
+    wa += 2;
+    if (wa == base + 16) flush();
+  }
+  __device__ __forceinline__ bool row_full() const { return wa >= base + 16; }
+  __device__ __forceinline__ int count() const { return 8 * rows + (int)(wa - base) / 2; }
+};
 
 // Staged candidates tested together per step of the list kernel's inner loop
 // (kBlk is a multiple, so reads stay inside the 64-entry batch buffer).
 constexpr int kListBatch = 4;
+// Quantised coordinates of the list test: 14-bit signed values, inert |q|^2,
+// and the replica size below which user indices fit the fast test's 16 bits.
+constexpr int kQMax = 8191;
+constexpr int kQInert = 1200000000;  // > 3 kQMax^2 + 4 kQMax^2 + any threshold, < 2^31 - 4 kQMax^2
+constexpr int kMaxFastAtoms = 32767;
+typedef short short2v __attribute__((ext_vector_type(2)));
 // Runs of cells listed per row group of the list kernel's search.
 constexpr int kMaxRuns = 2 * kBlk;
 static_assert(kBlk % kListBatch == 0, "batch must divide the candidate buffer");
@@ -354,9 +379,10 @@ __global__ __launch_bounds__(kBlk) __attribute__((amdgpu_waves_per_eu(7))) void 
                                                const float4 *__restrict__ integ0,
                                                const float4 *__restrict__ tx_t,
                                                const float4 *__restrict__ tv_t) {
-  __shared__ float4 s_pos[kBlk];  // kept candidates: position c relative to the block corner, |c|^2
-  __shared__ __align__(16) int32_t s_uid[kBlk];      // kept candidates: user index
-  __shared__ __align__(16) ListRing s_ring;  // each lane's list entries not yet stored
+  // kept candidates: quantised position q (x | y << 16, z | user index << 16,
+  // |q|^2) and user index
+  __shared__ __align__(16) int32_t s_qxy[kBlk], s_qzu[kBlk], s_qc2[kBlk], s_uid[kBlk];
+  __shared__ __align__(16) uint8_t s_buf[kBlk * kBufStride];  // each lane's list entries not yet stored
   __shared__ int s_cidx[3][18];  // fine-cell edges of the replica
   __shared__ int s_rq0[kMaxRuns];       // runs of a row group: first slot in fine-cell order,
   __shared__ int s_rimg[kMaxRuns];      // image (packed),
@@ -381,6 +407,8 @@ __global__ __launch_bounds__(kBlk) __attribute__((amdgpu_waves_per_eu(7))) void 
   const int Lx = R.Lq[0], Ly = R.Lq[1], Lz = R.Lq[2];
   const int ncx = R.nc[0], ncy = R.nc[1], ncz = R.nc[2];
   if (lane < 3 * 17) s_cidx[lane / 17][lane % 17] = R.cedge[lane / 17][lane % 17];
+  s_qxy[lane] = 0;  // every record ever read holds bounded values
+  s_qzu[lane] = 0;
   // the lane's atom; an inactive lane sits far away and never matches
   int4 xi = make_int4(0, 0, 0, 0);
   int wx = kDummyCoord, wy = kDummyCoord, wz = kDummyCoord, a = -(1 << 20), e0 = 0, e1 = 0;
@@ -428,7 +456,8 @@ __global__ __launch_bounds__(kBlk) __attribute__((amdgpu_waves_per_eu(7))) void 
       s_qb[lane >> 4][1] = make_int4(qz0, qz1, qact ? 1 : 0, 0);
     }
   }
-  const bool anyfar = __ballot(exfar) != 0ull;
+  // the fast test takes user indices modulo 2^16 and needs them below 2^15
+  const bool anyfar = __ballot(exfar) != 0ull || R.n > kMaxFastAtoms;
   const long long rl = R.rlq;
   // cell ranges (unfolded: u = image * nc + cell)
   const int ux0 = (int)floordiv(((long long)bx0 - rl) * ncx, Lx);
@@ -439,34 +468,38 @@ __global__ __launch_bounds__(kBlk) __attribute__((amdgpu_waves_per_eu(7))) void 
   const int uz1 = (int)floordiv(((long long)bz1 + rl) * ncz, Lz);
   const double rl2d = (double)rl * (double)rl;
   const float rl2 = R.rl2q;
-  // The candidate test runs in FP32 relative to the block's corner, in the
-  // expanded form |c - a|^2 = |c|^2 - 2 c.a + |a|^2: |c|^2 is formed once per
-  // kept candidate, so a test is three fused multiply-adds against the
-  // threshold rl2x - |a|^2 of the lane.  With Ma >= |a_k| and Mc >= |c_k|
-  // (kept candidates lie within rl of a quarter box, itself inside the block
-  // box), every rounding (coordinates, |c|^2, |a|^2, the products and the
-  // threshold) moves the computed difference by at most 2^-24 times a multiple
-  // of (Mc + Ma)^2 or rl^2; the sum of those terms is below
-  // E = 2^-24 (64 (Mc + Ma)^2 + 2 rl^2) + 16, so with rl2x >= rl^2 + E every
-  // candidate within the list radius passes (the list is a superset of the
-  // exact list, and the force kernel applies the exact cutoff).
-  float m2ax = 0.f, m2ay = 0.f, m2az = 0.f, thr = -INFINITY;
+  // The candidate test runs in integers.  Coordinates relative to the block's
+  // centre are divided by 2^qs (floor) and clamped to [-8191, 8191], with qs
+  // the smallest shift that keeps every kept candidate (within rl of the
+  // block box) and every block atom inside that range; then
+  //   |qc - qa|^2 = |qc|^2 - 2 qc.qa + |qa|^2
+  // is exact in 32 bits, |qc|^2 is formed once per kept candidate, and a test
+  // is two signed 16-bit dot products against the lane's threshold
+  // T - |qa|^2.  Flooring moves each component of a separation by less than
+  // one unit, so a pair at distance d has |qc - qa| < d / 2^qs + sqrt(3): with
+  // T = ceil((rl / 2^qs + sqrt(3))^2) every candidate within the list radius
+  // passes (the list is a superset of the exact list, larger by ~0.1% at the
+  // usual block size, and the force kernel applies the exact cutoff).
+  const int ox = bx0 + (bx1 - bx0) / 2, oy = by0 + (by1 - by0) / 2, oz = bz0 + (bz1 - bz0) / 2;
+  int qs = 0;
   {
-    const double ma = (double)max(bx1 - bx0, max(by1 - by0, bz1 - bz0)) + 2.0;
-    const double mc = ma + (double)rl + 64.0;
-    const double e = 0x1p-24 * (64.0 * (mc + ma) * (mc + ma) + 2.0 * rl2d) + 16.0;
-    const float rl2x = (float)((rl2d + e) * (1.0 + 0x1p-20));
-    if (active) {
-      const float ax = (float)(wx - bx0), ay = (float)(wy - by0), az = (float)(wz - bz0);
-      m2ax = -2.f * ax;
-      m2ay = -2.f * ay;
-      m2az = -2.f * az;
-      thr = rl2x - __builtin_fmaf(ax, ax, __builtin_fmaf(ay, ay, az * az));
-    }
+    const long long half = (long long)max(bx1 - bx0, max(by1 - by0, bz1 - bz0)) / 2 + 1 + rl + 64;
+    while ((half >> qs) > (long long)kQMax - 1) ++qs;
   }
-  // kept candidate c passes the lane's test
-  auto near = [&](const float4 c) {
-    return __builtin_fmaf(c.x, m2ax, __builtin_fmaf(c.y, m2ay, __builtin_fmaf(c.z, m2az, c.w))) < thr;
+  const int qthr = (int)ceil(((double)rl / (double)(1ll << qs) + 1.7320508075688772) *
+                             ((double)rl / (double)(1ll << qs) + 1.7320508075688772) + 1e-6);
+  short2v m2axy = {0, 0}, m2az0 = {0, 0};
+  int thr = 0;  // inactive lanes: no candidate passes (|qc|^2 >= 0)
+  if (active) {
+    const int qax = (wx - ox) >> qs, qay = (wy - oy) >> qs, qaz = (wz - oz) >> qs;
+    m2axy = short2v{(short)(-2 * qax), (short)(-2 * qay)};
+    m2az0 = short2v{(short)(-2 * qaz), 0};
+    thr = qthr - (qax * qax + qay * qay + qaz * qaz);
+  }
+  // candidate record (qxy, qzu, |qc|^2) passes the lane's test
+  auto near = [&](int qxy, int qzu, int qc2) {
+    const int t = __builtin_amdgcn_sdot2(__builtin_bit_cast(short2v, qxy), m2axy, qc2, false);
+    return __builtin_amdgcn_sdot2(__builtin_bit_cast(short2v, qzu), m2az0, t, false) < thr;
   };
   // exclusion window: for a candidate of user index oj, bit oj - a + 32 of exm
   // is moved to bit 63 by a left shift of a + 31 - oj (in range iff that
@@ -474,14 +507,12 @@ __global__ __launch_bounds__(kBlk) __attribute__((amdgpu_waves_per_eu(7))) void 
   const int exs = a + 31;
   const int lb = b - R.blk0;
   uint16_t *lst = W.nblist + R.list_off + (int64_t)lb * R.maxnb * kBlk;
-  // this lane's row of list chunk 0, and the end of the block's list
-  uint4 *const row0 = reinterpret_cast<uint4 *>(lst) + lane;
-  const uint4 *const rowend = reinterpret_cast<const uint4 *>(lst) + (size_t)(R.maxnb >> 3) * kBlk;
-  uint4 *rowp = row0;
   uint32_t *stg = W.stage + (int64_t)b * W.stage_stride;
   const int cap = R.stage_cap, maxnb = R.maxnb;
   const int *cstart = W.cell_start + R.cell0;
-  int nst = 0, cnt = 0;
+  int nst = 0;
+  const uint32_t mybuf = (uint32_t)(size_t)(lds_u16 *)(s_buf + lane * kBufStride);
+  ListBuf lbuf{mybuf, mybuf, reinterpret_cast<uint4 *>(lst), lane, R.maxnb >> 3, 0};
 
   bool bad = false;
   __syncthreads();  // cell edges in LDS
@@ -505,8 +536,8 @@ __global__ __launch_bounds__(kBlk) __attribute__((amdgpu_waves_per_eu(7))) void 
   for (int mode = 0; mode < 2; ++mode) {
     exact = mode == 1;
     nst = 0;
-    cnt = 0;
-    rowp = row0;
+    lbuf.wa = lbuf.base;
+    lbuf.rows = 0;
     bool full = false;
     for (int g0 = 0; gsize > 0 && g0 < nrows && !full; g0 += gsize) {
       // ---- runs of the group's rows
@@ -590,7 +621,7 @@ __global__ __launch_bounds__(kBlk) __attribute__((amdgpu_waves_per_eu(7))) void 
         rc = __shfl(run, kBlk - 1, kBlk);  // lane 63 is valid whenever another load follows
         // ---- load 64 candidates, keep those near one of the quarter boxes
         bool keep = false;
-        float4 cpos = make_float4(0.f, 0.f, 0.f, 0.f);
+        int3 cq = make_int3(0, 0, 0);
         uint32_t code = 0u;
         int uid = 0;
         if (valid) {
@@ -616,9 +647,11 @@ __global__ __launch_bounds__(kBlk) __attribute__((amdgpu_waves_per_eu(7))) void 
             bad = true;  // shift not representable: the replica is flagged
             keep = false;
           }
-          const float cx = (float)(px - bx0), cy = (float)(py - by0), cz = (float)(pz - bz0);
-          cpos = make_float4(cx, cy, cz, __builtin_fmaf(cx, cx, __builtin_fmaf(cy, cy, cz * cz)));
+          const int qx = min(max((px - ox) >> qs, -kQMax), kQMax), qy = min(max((py - oy) >> qs, -kQMax), kQMax),
+                    qz = min(max((pz - oz) >> qs, -kQMax), kQMax);
           uid = cxq.w;
+          cq = make_int3((int)(((uint32_t)qx & 0xffffu) | ((uint32_t)qy << 16)),
+                         (int)(((uint32_t)qz & 0xffffu) | ((uint32_t)uid << 16)), qx * qx + qy * qy + qz * qz);
           code = (uint32_t)jw.x | ((uint32_t)((sx + 16) & 31) << 16) |
                  ((uint32_t)((sy + 16) & 31) << 21) | ((uint32_t)((sz + 16) & 31) << 26);
         }
@@ -630,13 +663,14 @@ __global__ __launch_bounds__(kBlk) __attribute__((amdgpu_waves_per_eu(7))) void 
           break;
         }
         if (keep) {
-          s_pos[at] = cpos;
+          s_qxy[at] = cq.x;
+          s_qzu[at] = cq.y;
+          s_qc2[at] = cq.z;
           s_uid[at] = uid;
         }
         // the fast test reads whole batches: entries up to the next
-        // multiple of the batch are made inert
-        if (lane >= nk && lane < ((nk + kListBatch - 1) & ~(kListBatch - 1)))
-          s_pos[lane] = make_float4(0.f, 0.f, 0.f, 3.0e38f);
+        // multiple of the batch are made inert (|qc|^2 beyond any test)
+        if (lane >= nk && lane < ((nk + kListBatch - 1) & ~(kListBatch - 1))) s_qc2[lane] = kQInert;
         if (!exact && keep) stg[nst + at] = code;  // every kept candidate is staged
         __syncthreads();
         if (!exact) {
@@ -647,32 +681,35 @@ __global__ __launch_bounds__(kBlk) __attribute__((amdgpu_waves_per_eu(7))) void 
             // completed half of the ring per batch (a batch adds at most
             // four entries, so at most one half completes)
             for (int k0 = 0; k0 < nk; k0 += kListBatch) {
-              float4 c[kListBatch];
-#pragma unroll
-              for (int u = 0; u < kListBatch; ++u) c[u] = s_pos[k0 + u];
-              const int4 oj = *reinterpret_cast<const int4 *>(&s_uid[k0]);
-              const int ojs[kListBatch] = {oj.x, oj.y, oj.z, oj.w};
-              static_assert(kListBatch == 4, "one int4 of user indices per batch");
-              const int cnt0 = cnt;
+              static_assert(kListBatch == 4, "one 16-byte read per record field and batch");
+              const int4 qxy = *reinterpret_cast<const int4 *>(&s_qxy[k0]);
+              const int4 qzu = *reinterpret_cast<const int4 *>(&s_qzu[k0]);
+              const int4 qc2 = *reinterpret_cast<const int4 *>(&s_qc2[k0]);
+              const int rxy[kListBatch] = {qxy.x, qxy.y, qxy.z, qxy.w};
+              const int rzu[kListBatch] = {qzu.x, qzu.y, qzu.z, qzu.w};
+              const int rc2[kListBatch] = {qc2.x, qc2.y, qc2.z, qc2.w};
 #pragma unroll
               for (int u = 0; u < kListBatch; ++u) {
-                const uint32_t sh = (uint32_t)(exs - ojs[u]);
+                const uint32_t sh = (uint32_t)(exs - (int)((uint32_t)rzu[u] >> 16));
                 const bool exw = sh < 64u && (int32_t)(uint32_t)((exm << (sh & 63u)) >> 32) < 0;
-                const bool in = near(c[u]) && !exw;
-                if (in) ring_slot(s_ring, lane, cnt) = (uint16_t)(nst + k0 + u);
-                cnt += in ? 1 : 0;
+                const bool in = near(rxy[u], rzu[u], rc2[u]) && !exw;
+                // stored by every lane: a rejected candidate's entry is
+                // overwritten by the next one appended (or left past the end)
+                *lds16(lbuf.wa) = (uint16_t)(nst + k0 + u);
+                lbuf.wa += in ? 2u : 0u;
               }
-              if ((cnt ^ cnt0) & 8) ring_flush(s_ring, lane, (cnt0 >> 3) & 1, rowp, rowend);
+              static_assert(kListBatch <= kBufLen - 8, "a batch must fit behind seven entries");
+              if (lbuf.row_full()) lbuf.flush();
             }
           } else {
             for (int k = 0; k < nk; ++k) {
               const int oj = s_uid[k];
               const uint32_t sh = (uint32_t)(exs - oj);
               const bool win = sh < 64u;
-              bool in = near(s_pos[k]) && !(win && (int32_t)(uint32_t)((exm << (sh & 63u)) >> 32) < 0);
+              bool in = near(s_qxy[k], s_qzu[k], s_qc2[k]) && !(win && (int32_t)(uint32_t)((exm << (sh & 63u)) >> 32) < 0);
               if (in && !win && exfar)
                 for (int e = e0; e < e1; ++e) in = in && (ex_list[e] != oj);
-              if (in) list_append(s_ring, lane, (uint32_t)(nst + k), cnt, rowp, rowend);
+              if (in) lbuf.append((uint32_t)(nst + k));
             }
           }
           nst += nk;
@@ -684,13 +721,13 @@ __global__ __launch_bounds__(kBlk) __attribute__((amdgpu_waves_per_eu(7))) void 
             const int oj = s_uid[k];
             const uint32_t sh = (uint32_t)(exs - oj);
             const bool win = sh < 64u;
-            bool in = near(s_pos[k]) && !(win && (int32_t)(uint32_t)((exm << (sh & 63u)) >> 32) < 0);
+            bool in = near(s_qxy[k], s_qzu[k], s_qc2[k]) && !(win && (int32_t)(uint32_t)((exm << (sh & 63u)) >> 32) < 0);
             if (in && !win && exfar)
               for (int e = e0; e < e1; ++e) in = in && (ex_list[e] != oj);
             if (__ballot(in)) {
               if (nst < cap) {
                 if (in) {
-                  list_append(s_ring, lane, (uint32_t)nst, cnt, rowp, rowend);
+                  lbuf.append((uint32_t)nst);
                 }
                 acc |= 1ull << k;
                 ++nst;
@@ -707,13 +744,15 @@ __global__ __launch_bounds__(kBlk) __attribute__((amdgpu_waves_per_eu(7))) void 
     if (!full) break;
   }
   // longest list before any clamp (the capacity check at creation reads it)
+  int cnt = lbuf.count();
   const int cneed = wave_max_i(active ? cnt : 0);
   if (cnt > maxnb - 8) {
     bad = true;
     cnt = maxnb - 8;
   } else if (active) {
     // pad to a multiple of 8 with the inert staging entry (index cap)
-    while (cnt & 7) list_append(s_ring, lane, (uint32_t)cap, cnt, rowp, rowend);
+    while (lbuf.wa != lbuf.base) lbuf.append((uint32_t)cap);
+    cnt = lbuf.count();
   }
   W.nbcnt[slot] = active ? cnt : 0;
   if (lane == 0) W.stage_n[b] = nst;
@@ -768,7 +807,7 @@ __global__ __launch_bounds__(kBlk) void k_debug_pairs(const RepInfo *__restrict_
   const uint32_t *stg = W.stage + (int64_t)b * W.stage_stride;
   const int nst = W.stage_n[b];
   for (int k = 0; k < cnt; ++k) {
-    const int L = lst[(((k >> 3) * kBlk) + threadIdx.x) * 8 + (k & 7)];
+    const int L = lst[list_row(k >> 3, threadIdx.x) * 8 + (k & 7)];
     if (L >= nst) continue;
     const uint32_t e = stg[L];
     const int j = (int)(e & 0xffffu);

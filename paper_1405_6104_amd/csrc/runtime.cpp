@@ -421,7 +421,7 @@ static vp_status build(vp_system *s, const vp_replica_desc *reps, int32_t n_reps
     if (o.max_neighbors <= 0 && r < (int)s->maxnb_override.size() && s->maxnb_override[r] > 0)
       maxnb = s->maxnb_override[r];
     maxnb = std::min(maxnb, d.n_atoms + 8);
-    maxnb = (maxnb + 7) / 8 * 8 + 8;
+    maxnb = ((maxnb + 7) / 8 * 8 + 8 + 8 * kListGroup - 1) / (8 * kListGroup) * (8 * kListGroup);
     R.maxnb = maxnb;
     int cap = std::min(kMaxStage, std::min(stage_estimate(rl, rho), d.n_atoms * 27 + 8));
     R.stage_cap = cap;

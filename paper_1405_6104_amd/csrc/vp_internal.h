@@ -13,6 +13,18 @@ namespace vp {
 constexpr int kBlock = 256;          // threads per workgroup of the per-atom kernels
 constexpr int kTile = 256;           // slots per tile (a tile never crosses replicas)
 constexpr int kBlk = 64;             // atoms per neighbourhood block (one wave)
+// Pair lists of a block: entry k of lane l is element k % 8 of row k / 8 of
+// that lane, a row being 16 bytes (eight 16-bit staging indices).  Row c of
+// lane l is the uint4 at list_row(c, l): rows are grouped by kListGroup per
+// lane, so that a lane's consecutive rows share one 64-byte segment (the
+// list build stores each lane's rows at the lane's own pace, and a segment
+// filled by one lane in a short time combines in the cache before it reaches
+// memory), while row c of all 64 lanes is still one load instruction of the
+// force kernel.  List capacities are multiples of 8 kListGroup entries.
+constexpr int kListGroup = 4;
+__host__ __device__ inline int64_t list_row(int c, int lane) {
+  return ((int64_t)(c / kListGroup) * kBlk + lane) * kListGroup + (c % kListGroup);
+}
 constexpr int kParts = 8;            // waves sharing one block in the force kernel
 constexpr int kForceThreads = kParts * kBlk;
 constexpr int kMaxForceParts = 16;   // largest number of waves per block among the force tile shapes
@@ -130,7 +142,7 @@ struct Work {
   long long *F = nullptr;   // [3][slots] fixed-point forces (without bias), SoA
   int64_t fstride = 0;      // slots: distance between the x, y and z planes of F
   int32_t *nbcnt = nullptr;     // [slots] list length (multiple of 8)
-  uint16_t *nblist = nullptr;   // per block [maxnb/8][64][8] staged indices
+  uint16_t *nblist = nullptr;   // per block: maxnb/8 rows of 8 staged indices per lane, at list_row
   int32_t *stage_n = nullptr;   // [blocks]
   uint32_t *stage = nullptr;    // [blocks][stage_stride] slot | image shifts
   int64_t stage_stride = 0;     // staging entries per block (largest capacity)
