@@ -35,7 +35,7 @@ PEAK_FP32_TFLOPS = 157.3    # MI355X FP32 vector peak
 # HBM bytes per launch of the force kernel on this workload, from rocprofv3
 # FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 (factors from a 256 MiB device copy);
 # see profiles/counters_64x12560.md.  Set to None when the kernel changes.
-FORCE_TRAFFIC_BYTES = (614404 * 2.000 + 19200 * 1.000) * 1024
+FORCE_TRAFFIC_BYTES = (601733 * 2.000 + 19200 * 1.000) * 1024
 
 
 def _cpu_model():
@@ -321,9 +321,6 @@ def main():
     print(json.dumps(out))
 
 
-if __name__ == "__main__":
-    main()
-
 
 def toy_bench(args):
     """The 2-D toy funnel of the supplement: 20,000 plain trials of 90,000 steps
@@ -377,3 +374,7 @@ def toy_bench(args):
         "roofline": None, "cpu_baseline": None,
     }
     print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()
