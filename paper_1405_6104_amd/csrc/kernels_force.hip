@@ -101,6 +101,44 @@ __device__ __forceinline__ void eval_chunk(const uint4 e, const int4 *__restrict
   }
 }
 
+// The same chunk when no entry of it pairs two Lennard-Jones atoms (each pair
+// involves an atom without LJ parameters): only the reaction-field term, and
+// only the charge of each partner is read from its type-table row.  For such
+// pairs the LJ factor of eval_chunk is an exact zero (the product of the two
+// sqrt(24 epsilon) is +0), so both evaluations give the same bits.
+template <int UNROLL>
+__device__ __forceinline__ void eval_chunk_rf(const uint4 e, const int4 *__restrict__ st,
+                                              const char *__restrict__ ldsb, const float qi, int wx, int wy,
+                                              int wz, float rc2, float krf2, float &fx, float &fy, float &fz) {
+  const uint32_t w[4] = {e.x, e.y, e.z, e.w};
+#pragma unroll
+  for (int h = 0; h < 8; h += UNROLL) {
+    int4 sj[UNROLL];
+#pragma unroll
+    for (int v = 0; v < UNROLL; ++v) {
+      const int u = h + v;
+      sj[v] = st[(w[u >> 1] >> (16 * (u & 1))) & 0xffffu];
+    }
+    float qj[UNROLL];
+#pragma unroll
+    for (int v = 0; v < UNROLL; ++v) qj[v] = *reinterpret_cast<const float *>(ldsb + sj[v].w);
+#pragma unroll
+    for (int u = 0; u < UNROLL; ++u) {
+      const float dx = (float)(sj[u].x - wx), dy = (float)(sj[u].y - wy), dz = (float)(sj[u].z - wz);
+      const float r2 = qr2(dx, dy, dz);
+      const bool in = r2 < rc2;
+      const float rinv = __builtin_amdgcn_rsqf(r2);
+      const float r2inv = rinv * rinv;
+      const float qq = qi * qj[u];
+      const float cq = qq * __builtin_fmaf(rinv, r2inv, -krf2);
+      const float fs = in ? cq : 0.0f;
+      fx = __builtin_fmaf(-fs, dx, fx);
+      fy = __builtin_fmaf(-fs, dy, fy);
+      fz = __builtin_fmaf(-fs, dz, fz);
+    }
+  }
+}
+
 // Tile shape: PARTS waves share one block's staged neighbourhood and UNROLL
 // list entries share one batch of LDS reads; MINW asks the compiler for
 // registers that let MINW waves share a SIMD.  blist (or NULL for all blocks)
@@ -170,11 +208,16 @@ __global__ __launch_bounds__(64 * PARTS) __attribute__((amdgpu_waves_per_eu(MINW
     const int wz = xi.z - unpack_wrap(wr, 2) * Lz;
     const float4 ti = tab[xi.w];
     const float rc2 = R.rc2q, krf2 = R.krf2q;
-    const int nch = W.nbcnt[slot] >> 3;
+    const int nch = W.nbcnt[slot] >> 3, nlj = W.nblj[slot], rowcap = R.maxnb >> 3;
     const uint4 *lp = reinterpret_cast<const uint4 *>(W.nblist + R.list_off + (int64_t)(b - R.blk0) * R.maxnb * kBlk);
-    uint4 e = lp[list_row(min(part, max(nch - 1, 0)), lane)];
+    uint4 e = lp[list_row(chunk_row(min(part, max(nch - 1, 0)), nlj, rowcap), lane)];
+    // the lane's atom has Lennard-Jones parameters: the first stream of its
+    // list holds its LJ pairs
+    const bool lji = xi.w < R.nlj_types;
     // this wave takes chunks part, part + PARTS, ...: its k-th chunk of every
-    // group of SETS feeds set k, which is logical accumulator k PARTS + part
+    // group of SETS feeds set k, which is logical accumulator k PARTS + part.
+    // A chunk runs the LJ + reaction-field evaluation when any lane's chunk
+    // holds Lennard-Jones pairs, else the reaction-field one (same bits).
     for (int c0 = part; c0 < nch; c0 += PARTS * SETS) {
 #pragma unroll
       for (int k = 0; k < SETS; ++k) {
@@ -182,9 +225,13 @@ __global__ __launch_bounds__(64 * PARTS) __attribute__((amdgpu_waves_per_eu(MINW
         if (c < nch) {
           // the next chunk's indices are fetched while this one is evaluated
           // (the last chunk is fetched again rather than reading past the list)
-          const uint4 en = lp[list_row(min(c + PARTS, nch - 1), lane)];
-          eval_chunk<UNROLL>(e, st, reinterpret_cast<const char *>(lds), ti, wx, wy, wz, rc2, krf2, fx[k],
-                             fy[k], fz[k]);
+          const uint4 en = lp[list_row(chunk_row(min(c + PARTS, nch - 1), nlj, rowcap), lane)];
+          if (__ballot(lji && c < nlj) != 0ull)
+            eval_chunk<UNROLL>(e, st, reinterpret_cast<const char *>(lds), ti, wx, wy, wz, rc2, krf2, fx[k],
+                               fy[k], fz[k]);
+          else
+            eval_chunk_rf<UNROLL>(e, st, reinterpret_cast<const char *>(lds), ti.x, wx, wy, wz, rc2, krf2,
+                                  fx[k], fy[k], fz[k]);
           e = en;
         }
       }
@@ -200,23 +247,18 @@ __global__ __launch_bounds__(64 * PARTS) __attribute__((amdgpu_waves_per_eu(MINW
     red[(2 * kLogicalParts + q) * kBlk + lane] = fz[k];
   }
   __syncthreads();
-  if (part == 0) {
-    long long fxs = 0, fys = 0, fzs = 0;
+  // wave d (d < 3) sums component d of the block's 64 atoms
+  static_assert(PARTS >= 3, "one wave per force component");
+  if (part < 3) {
+    long long v = 0;
     if (active) {
-      float sx = red[lane], sy = red[kLogicalParts * kBlk + lane], sz = red[2 * kLogicalParts * kBlk + lane];
-#pragma unroll 4
-      for (int q = 1; q < kLogicalParts; ++q) {
-        sx += red[q * kBlk + lane];
-        sy += red[(kLogicalParts + q) * kBlk + lane];
-        sz += red[(2 * kLogicalParts + q) * kBlk + lane];
-      }
-      fxs = to_fix((double)sx * kInvQ);
-      fys = to_fix((double)sy * kInvQ);
-      fzs = to_fix((double)sz * kInvQ);
+      const float *rd = red + part * kLogicalParts * kBlk + lane;
+      float sum = rd[0];
+#pragma unroll 5
+      for (int q = 1; q < kLogicalParts; ++q) sum += rd[q * kBlk];
+      v = to_fix((double)sum * kInvQ);
     }
-    W.F[slot] = fxs;
-    W.F[W.fstride + slot] = fys;
-    W.F[2 * W.fstride + slot] = fzs;
+    W.F[part * W.fstride + slot] = v;
   }
 }
 
@@ -271,10 +313,10 @@ __global__ __launch_bounds__(kForceThreads) void k_pair_energy(const RepInfo *__
               wz = xi.z - unpack_wrap(wr, 2) * Lz;
     const float4 ti = tab[xi.w];
     const float rc2 = R.rc2q, krf2 = R.krf2q;
-    const int nent = W.nbcnt[slot];
+    const int nent = W.nbcnt[slot], nlj = W.nblj[slot], rowcap = R.maxnb >> 3;
     const uint16_t *lp = W.nblist + R.list_off + (int64_t)(b - R.blk0) * R.maxnb * kBlk;
     for (int k = part; k < nent; k += kParts) {
-      const int L = lp[list_row(k >> 3, lane) * 8 + (k & 7)];
+      const int L = lp[list_row(chunk_row(k >> 3, nlj, rowcap), lane) * 8 + (k & 7)];
       const int4 sj = st[L];
       const float4 tj = *reinterpret_cast<const float4 *>(reinterpret_cast<const char *>(lds) + sj.w);
       const float dx = (float)(sj.x - wx), dy = (float)(sj.y - wy), dz = (float)(sj.z - wz);
@@ -547,10 +589,10 @@ __global__ __launch_bounds__(kForceThreads) void k_tangent_forces(
               wz = xi.z - unpack_wrap(wr, 2) * Lz;
     const float4 ti = tab[xi.w];
     const float rc2 = R.rc2q, krf2 = R.krf2q;
-    const int nch = W.nbcnt[slot] >> 3;
+    const int nch = W.nbcnt[slot] >> 3, nlj = W.nblj[slot], rowcap = R.maxnb >> 3;
     const uint4 *lp = reinterpret_cast<const uint4 *>(W.nblist + R.list_off + (int64_t)(b - R.blk0) * R.maxnb * kBlk);
     for (int c = part; c < nch; c += kParts) {
-      const uint4 e = lp[list_row(c, lane)];
+      const uint4 e = lp[list_row(chunk_row(c, nlj, rowcap), lane)];
       const uint32_t w[4] = {e.x, e.y, e.z, e.w};
 #pragma unroll
       for (int u = 0; u < 8; ++u) {

@@ -235,6 +235,7 @@ __global__ __launch_bounds__(kBlock) void k_init_state(const RepInfo *__restrict
     W.wrap[slot] = 0;
     W.integ[slot] = make_float4(0.f, 0.f, 0.f, 0.f);
     W.nbcnt[slot] = 0;
+    W.nblj[slot] = 0;
     return;
   }
   const int u = R.uoff + p;

@@ -213,7 +213,8 @@ __global__ __launch_bounds__(kBinThreads) void k_bin(const RepInfo *__restrict__
 
 // New slot -> source (old slot through the old inverse map, or user index);
 // also records the atom's periodic image at this build and writes its wrapped
-// position, user index, slot and image in fine-cell order.
+// position, user index, slot (with its Lennard-Jones class) and image in
+// fine-cell order.
 template <int MODE>
 __global__ __launch_bounds__(kBlock) void k_permute(const RepInfo *__restrict__ info,
                                                     const RepState *__restrict__ state, Work W,
@@ -262,7 +263,8 @@ __global__ __launch_bounds__(kBlock) void k_permute(const RepInfo *__restrict__ 
   // the same atom in fine-cell order (wrapped position) for the candidate search
   const int q = R.off + cellpos_t[slot];
   cellx_t[q] = make_int4(x.x - kx * R.Lq[0], x.y - ky * R.Lq[1], x.z - kz * R.Lq[2], a);
-  celljw_t[q] = make_int2(p, wr);
+  // the sign bit marks an atom with Lennard-Jones parameters
+  celljw_t[q] = make_int2(p | (x.w < R.nlj_types ? (int)0x80000000u : 0), wr);
 }
 
 __device__ __forceinline__ int wave_min_i(int v) {
@@ -287,14 +289,15 @@ __device__ __forceinline__ int quarter_max_i(int v) {
   return v;
 }
 
-// A lane's list entries are collected in LDS, in a buffer of twelve entries
-// of its own, by one 16-bit store per entry at a running address.  When the
-// buffer holds eight or more entries, the first eight are copied as one
-// 16-byte write into the [chunk][lane][8] layout, through a pointer that
-// advances one chunk (64 rows) per copy, and the rest move to the front.
-// Rows past the list's capacity are not stored (entries are still counted:
-// the overflow is flagged).  Twelve entries let a batch of up to four
-// appends run with one check for a full row after it.
+// A lane's list entries are collected in LDS, one buffer of twelve entries
+// per stream (partners with Lennard-Jones parameters, charge-only partners:
+// chunk_row), by one
+// 16-bit store per entry at a running address.  When a buffer holds eight or
+// more entries, the first eight are copied as one 16-byte row of its stream
+// (upward from row 0, or downward from the last row), and the rest move to
+// the front.  Rows past the list's capacity are not stored (entries are still
+// counted: the overflow is flagged).  Twelve entries let a batch of up to
+// four appends run with one check for a full row after it.
 constexpr int kBufLen = 12;
 constexpr int kBufStride = 2 * kBufLen;  // bytes between lanes' buffers
 typedef __attribute__((address_space(3))) uint16_t lds_u16;  // 32-bit LDS addresses
@@ -310,10 +313,11 @@ struct ListBuf {
   int lane;
   int rowcap;     // rows per lane
   int rows;       // rows copied out, stored or not
+  bool down;      // rows fill the list from its last row downward
 
   __device__ __forceinline__ void flush() {
     const uint4 r = make_uint4(*lds32(base), *lds32(base + 4), *lds32(base + 8), *lds32(base + 12));
-    if (rows < rowcap) list[list_row(rows, lane)] = r;
+    if (rows < rowcap) list[list_row(down ? rowcap - 1 - rows : rows, lane)] = r;
     ++rows;
     const uint32_t t0 = *lds32(base + 16), t1 = *lds32(base + 20);
     *lds32(base) = t0;
@@ -382,7 +386,9 @@ __global__ __launch_bounds__(kBlk) __attribute__((amdgpu_waves_per_eu(7))) void 
   // kept candidates: quantised position q (x | y << 16, z | user index << 16,
   // |q|^2) and user index
   __shared__ __align__(16) int32_t s_qxy[kBlk], s_qzu[kBlk], s_qc2[kBlk], s_uid[kBlk];
-  __shared__ __align__(16) uint8_t s_buf[kBlk * kBufStride];  // each lane's list entries not yet stored
+  // each lane's list entries not yet stored: first stream (LJ partners)
+  // [0, kBlk), second stream (charge-only partners) [kBlk, 2 kBlk)
+  __shared__ __align__(16) uint8_t s_buf[2 * kBlk * kBufStride];
   __shared__ int s_cidx[3][18];  // fine-cell edges of the replica
   __shared__ int s_rq0[kMaxRuns];       // runs of a row group: first slot in fine-cell order,
   __shared__ int s_rimg[kMaxRuns];      // image (packed),
@@ -400,6 +406,7 @@ __global__ __launch_bounds__(kBlk) __attribute__((amdgpu_waves_per_eu(7))) void 
   const bool active = p < R.n;
   if (p0 >= R.n) {
     W.nbcnt[slot] = 0;
+    W.nblj[slot] = 0;
     if (lane == 0) W.stage_n[b] = 0;
     return;
   }
@@ -508,11 +515,14 @@ __global__ __launch_bounds__(kBlk) __attribute__((amdgpu_waves_per_eu(7))) void 
   const int lb = b - R.blk0;
   uint16_t *lst = W.nblist + R.list_off + (int64_t)lb * R.maxnb * kBlk;
   uint32_t *stg = W.stage + (int64_t)b * W.stage_stride;
-  const int cap = R.stage_cap, maxnb = R.maxnb;
+  const int cap = R.stage_cap;
   const int *cstart = W.cell_start + R.cell0;
   int nst = 0;
-  const uint32_t mybuf = (uint32_t)(size_t)(lds_u16 *)(s_buf + lane * kBufStride);
-  ListBuf lbuf{mybuf, mybuf, reinterpret_cast<uint4 *>(lst), lane, R.maxnb >> 3, 0};
+  const uint32_t bufl = (uint32_t)(size_t)(lds_u16 *)(s_buf + lane * kBufStride);
+  const uint32_t bufr = (uint32_t)(size_t)(lds_u16 *)(s_buf + (kBlk + lane) * kBufStride);
+  const int rowcap = R.maxnb >> 3;
+  ListBuf lbl{bufl, bufl, reinterpret_cast<uint4 *>(lst), lane, rowcap, 0, false};
+  ListBuf lbr{bufr, bufr, reinterpret_cast<uint4 *>(lst), lane, rowcap, 0, true};
 
   bool bad = false;
   __syncthreads();  // cell edges in LDS
@@ -536,8 +546,10 @@ __global__ __launch_bounds__(kBlk) __attribute__((amdgpu_waves_per_eu(7))) void 
   for (int mode = 0; mode < 2; ++mode) {
     exact = mode == 1;
     nst = 0;
-    lbuf.wa = lbuf.base;
-    lbuf.rows = 0;
+    lbl.wa = lbl.base;
+    lbl.rows = 0;
+    lbr.wa = lbr.base;
+    lbr.rows = 0;
     bool full = false;
     for (int g0 = 0; gsize > 0 && g0 < nrows && !full; g0 += gsize) {
       // ---- runs of the group's rows
@@ -624,6 +636,7 @@ __global__ __launch_bounds__(kBlk) __attribute__((amdgpu_waves_per_eu(7))) void 
         int3 cq = make_int3(0, 0, 0);
         uint32_t code = 0u;
         int uid = 0;
+        bool ljc = false;
         if (valid) {
           const int q = s_rq0[run] + (t - s_rpre[run]);
           const int img = s_rimg[run];
@@ -650,14 +663,18 @@ __global__ __launch_bounds__(kBlk) __attribute__((amdgpu_waves_per_eu(7))) void 
           const int qx = min(max((px - ox) >> qs, -kQMax), kQMax), qy = min(max((py - oy) >> qs, -kQMax), kQMax),
                     qz = min(max((pz - oz) >> qs, -kQMax), kQMax);
           uid = cxq.w;
+          ljc = jw.x < 0;  // the candidate has Lennard-Jones parameters
           cq = make_int3((int)(((uint32_t)qx & 0xffffu) | ((uint32_t)qy << 16)),
                          (int)(((uint32_t)qz & 0xffffu) | ((uint32_t)uid << 16)), qx * qx + qy * qy + qz * qz);
-          code = (uint32_t)jw.x | ((uint32_t)((sx + 16) & 31) << 16) |
+          code = ((uint32_t)jw.x & 0xffffu) | ((uint32_t)((sx + 16) & 31) << 16) |
                  ((uint32_t)((sy + 16) & 31) << 21) | ((uint32_t)((sz + 16) & 31) << 26);
         }
-        const uint64_t km = __ballot(keep);
-        const int at = __popcll(km & ((1ull << lane) - 1ull));
-        const int nk = __popcll(km);
+        // kept candidates with Lennard-Jones parameters take the first nkl
+        // places of the batch, the others the rest (each group in lane order)
+        const uint64_t km = __ballot(keep), kml = __ballot(keep && ljc);
+        const uint64_t below = (1ull << lane) - 1ull;
+        const int nk = __popcll(km), nkl = __popcll(kml);
+        const int at = ljc ? __popcll(kml & below) : nkl + __popcll(km & ~kml & below);
         if (!exact && nst + nk > cap) {
           full = true;  // uniform: the block is redone in exact mode
           break;
@@ -678,29 +695,37 @@ __global__ __launch_bounds__(kBlk) __attribute__((amdgpu_waves_per_eu(7))) void 
           if (!anyfar) {
             // kListBatch candidates read and tested together (their LDS
             // reads overlap), then appended in order with one check for a
-            // completed half of the ring per batch (a batch adds at most
-            // four entries, so at most one half completes)
-            for (int k0 = 0; k0 < nk; k0 += kListBatch) {
-              static_assert(kListBatch == 4, "one 16-byte read per record field and batch");
-              const int4 qxy = *reinterpret_cast<const int4 *>(&s_qxy[k0]);
-              const int4 qzu = *reinterpret_cast<const int4 *>(&s_qzu[k0]);
-              const int4 qc2 = *reinterpret_cast<const int4 *>(&s_qc2[k0]);
-              const int rxy[kListBatch] = {qxy.x, qxy.y, qxy.z, qxy.w};
-              const int rzu[kListBatch] = {qzu.x, qzu.y, qzu.z, qzu.w};
-              const int rc2[kListBatch] = {qc2.x, qc2.y, qc2.z, qc2.w};
+            // completed row per batch (a batch adds at most four entries).
+            // Places [lo, hi) of the batches from kb on go to buf.
+            auto test_batches = [&](ListBuf &buf, int kb, int lo, int hi) {
+              for (int k0 = kb; k0 < hi; k0 += kListBatch) {
+                static_assert(kListBatch == 4, "one 16-byte read per record field and batch");
+                const int4 qxy = *reinterpret_cast<const int4 *>(&s_qxy[k0]);
+                const int4 qzu = *reinterpret_cast<const int4 *>(&s_qzu[k0]);
+                const int4 qc2 = *reinterpret_cast<const int4 *>(&s_qc2[k0]);
+                const int rxy[kListBatch] = {qxy.x, qxy.y, qxy.z, qxy.w};
+                const int rzu[kListBatch] = {qzu.x, qzu.y, qzu.z, qzu.w};
+                const int rc2[kListBatch] = {qc2.x, qc2.y, qc2.z, qc2.w};
 #pragma unroll
-              for (int u = 0; u < kListBatch; ++u) {
-                const uint32_t sh = (uint32_t)(exs - (int)((uint32_t)rzu[u] >> 16));
-                const bool exw = sh < 64u && (int32_t)(uint32_t)((exm << (sh & 63u)) >> 32) < 0;
-                const bool in = near(rxy[u], rzu[u], rc2[u]) && !exw;
-                // stored by every lane: a rejected candidate's entry is
-                // overwritten by the next one appended (or left past the end)
-                *lds16(lbuf.wa) = (uint16_t)(nst + k0 + u);
-                lbuf.wa += in ? 2u : 0u;
+                for (int u = 0; u < kListBatch; ++u) {
+                  const int k = k0 + u;
+                  const uint32_t sh = (uint32_t)(exs - (int)((uint32_t)rzu[u] >> 16));
+                  const bool exw = sh < 64u && (int32_t)(uint32_t)((exm << (sh & 63u)) >> 32) < 0;
+                  const bool in = near(rxy[u], rzu[u], rc2[u]) && !exw && k >= lo && k < hi;
+                  // stored by every lane: an entry that is not kept is
+                  // overwritten by the next one appended (or left past the end)
+                  *lds16(buf.wa) = (uint16_t)(nst + k);
+                  buf.wa += in ? 2u : 0u;
+                }
+                static_assert(kListBatch <= kBufLen - 8, "a batch must fit behind seven entries");
+                if (buf.row_full()) buf.flush();
               }
-              static_assert(kListBatch <= kBufLen - 8, "a batch must fit behind seven entries");
-              if (lbuf.row_full()) lbuf.flush();
-            }
+            };
+            // candidates with LJ parameters go to the first stream, the
+            // others to the second (the batch holding the boundary is read
+            // by both passes)
+            test_batches(lbl, 0, 0, nkl);
+            test_batches(lbr, nkl & ~(kListBatch - 1), nkl, nk);
           } else {
             for (int k = 0; k < nk; ++k) {
               const int oj = s_uid[k];
@@ -709,7 +734,10 @@ __global__ __launch_bounds__(kBlk) __attribute__((amdgpu_waves_per_eu(7))) void 
               bool in = near(s_qxy[k], s_qzu[k], s_qc2[k]) && !(win && (int32_t)(uint32_t)((exm << (sh & 63u)) >> 32) < 0);
               if (in && !win && exfar)
                 for (int e = e0; e < e1; ++e) in = in && (ex_list[e] != oj);
-              if (in) lbuf.append((uint32_t)(nst + k));
+              if (in) {
+                if (k < nkl) lbl.append((uint32_t)(nst + k));
+                else lbr.append((uint32_t)(nst + k));
+              }
             }
           }
           nst += nk;
@@ -727,7 +755,8 @@ __global__ __launch_bounds__(kBlk) __attribute__((amdgpu_waves_per_eu(7))) void 
             if (__ballot(in)) {
               if (nst < cap) {
                 if (in) {
-                  lbuf.append((uint32_t)nst);
+                  if (k < nkl) lbl.append((uint32_t)nst);
+                  else lbr.append((uint32_t)nst);
                 }
                 acc |= 1ull << k;
                 ++nst;
@@ -743,18 +772,24 @@ __global__ __launch_bounds__(kBlk) __attribute__((amdgpu_waves_per_eu(7))) void 
     }
     if (!full) break;
   }
-  // longest list before any clamp (the capacity check at creation reads it)
-  int cnt = lbuf.count();
-  const int cneed = wave_max_i(active ? cnt : 0);
-  if (cnt > maxnb - 8) {
-    bad = true;
-    cnt = maxnb - 8;
-  } else if (active) {
-    // pad to a multiple of 8 with the inert staging entry (index cap)
-    while (lbuf.wa != lbuf.base) lbuf.append((uint32_t)cap);
-    cnt = lbuf.count();
+  // pad the last row of each stream with the inert staging entry (index cap)
+  if (active) {
+    while (lbl.wa != lbl.base) lbl.append((uint32_t)cap);
+    while (lbr.wa != lbr.base) lbr.append((uint32_t)cap);
   }
-  W.nbcnt[slot] = active ? cnt : 0;
+  // longest list before any clamp (the capacity check at creation reads it)
+  int nlj = lbl.rows, nrf = lbr.rows;
+  const int cneed = wave_max_i(active ? 8 * (nlj + nrf) : 0);
+  if (nlj + nrf > rowcap - 1) {
+    // overflow: the replica is flagged; the rows read stay inside the list
+    // and were all written by this build (the two streams may have
+    // overwritten each other's rows, with staging indices of this build)
+    bad = true;
+    nlj = min(nlj, rowcap - 1);
+    nrf = min(nrf, rowcap - 1 - nlj);
+  }
+  W.nbcnt[slot] = active ? 8 * (nlj + nrf) : 0;
+  W.nblj[slot] = active ? nlj : 0;
   if (lane == 0) W.stage_n[b] = nst;
   if (__ballot(bad) && lane == 0) {
     if (MODE == 0) atomicOr(&state[r].status, VP_REPLICA_LIST_OVERFLOW);
@@ -802,12 +837,12 @@ __global__ __launch_bounds__(kBlk) void k_debug_pairs(const RepInfo *__restrict_
   const int wx = xi.x - unpack_wrap(wr, 0) * R.Lq[0], wy = xi.y - unpack_wrap(wr, 1) * R.Lq[1],
             wz = xi.z - unpack_wrap(wr, 2) * R.Lq[2];
   const int a = W.orig[slot];
-  const int cnt = W.nbcnt[slot];
+  const int cnt = W.nbcnt[slot], nlj = W.nblj[slot], rowcap = R.maxnb >> 3;
   const uint16_t *lst = W.nblist + R.list_off + (int64_t)(b - R.blk0) * R.maxnb * kBlk;
   const uint32_t *stg = W.stage + (int64_t)b * W.stage_stride;
   const int nst = W.stage_n[b];
   for (int k = 0; k < cnt; ++k) {
-    const int L = lst[list_row(k >> 3, threadIdx.x) * 8 + (k & 7)];
+    const int L = lst[list_row(chunk_row(k >> 3, nlj, rowcap), threadIdx.x) * 8 + (k & 7)];
     if (L >= nst) continue;
     const uint32_t e = stg[L];
     const int j = (int)(e & 0xffffu);

@@ -74,6 +74,7 @@ size_t layout(const vp_system *s, unsigned char *base, vp::Work &W) {
   take(&W.F, 3 * S);
   W.fstride = (int64_t)S;
   take(&W.nbcnt, S);
+  take(&W.nblj, S);
   take(&W.nblist, (size_t)s->list_elems);
   take(&W.stage_n, B);
   W.stage_stride = s->stage_cap_max;

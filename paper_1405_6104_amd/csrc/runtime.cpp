@@ -176,6 +176,7 @@ static vp_status alloc_work(vp_system *s, Work &W, bool traj) {
   TRY(dalloc(s, &W.F, 3 * S));
   W.fstride = (int64_t)S;
   TRY(dalloc(s, &W.nbcnt, S));
+  TRY(dalloc(s, &W.nblj, S));
   TRY(dalloc(s, &W.nblist, (size_t)s->list_elems));
   TRY(dalloc(s, &W.stage_n, B));
   W.stage_stride = s->stage_cap_max;
@@ -212,6 +213,7 @@ static vp_status alloc_work(vp_system *s, Work &W, bool traj) {
     HIPCHECK(hipMemset(W.tgpart, 0, sizeof(double) * 2 * R * kMaxCvBlocks));
   }
   HIPCHECK(hipMemset(W.nbcnt, 0, sizeof(int32_t) * S));
+  HIPCHECK(hipMemset(W.nblj, 0, sizeof(int32_t) * S));
   HIPCHECK(hipMemset(W.stage_n, 0, sizeof(int32_t) * B));
   HIPCHECK(hipMemset(W.orig, 0xff, sizeof(int32_t) * S));
   HIPCHECK(hipMemset(W.wrap, 0, sizeof(int32_t) * S));
@@ -455,27 +457,39 @@ static vp_status build(vp_system *s, const vp_replica_desc *reps, int32_t n_reps
       xf_rows += d.n_solute;
     }
     R.seed = d.seed;
-    // (charge, sigma, epsilon) classes of this replica; the last entry is inert
+    // (charge, sigma, epsilon) classes of this replica, those with epsilon > 0
+    // first (in order of first appearance within each group); the last entry
+    // is inert
     {
       std::map<std::tuple<double, double, double>, int> cls;
-      std::vector<float4> tab;
+      std::vector<int> first;  // an atom of each class, by first appearance
+      std::vector<int> cl(d.n_atoms);
       for (int i = 0; i < d.n_atoms; ++i) {
         auto key = std::make_tuple(d.charge[i], d.sigma[i], d.epsilon[i]);
         auto it = cls.find(key);
-        int t;
         if (it == cls.end()) {
-          t = (int)tab.size();
-          cls.emplace(key, t);
+          cl[i] = (int)first.size();
+          cls.emplace(key, cl[i]);
+          first.push_back(i);
+        } else {
+          cl[i] = it->second;
+        }
+      }
+      if ((int)first.size() >= kMaxTypes)
+        return fail(VP_ERR_ARG, "replica " + std::to_string(r) + ": more than 1023 distinct (charge, sigma, epsilon)");
+      std::vector<int> renum(first.size());
+      std::vector<float4> tab;
+      for (int pass = 0; pass < 2; ++pass)
+        for (size_t c = 0; c < first.size(); ++c) {
+          const int i = first[c];
+          if ((d.epsilon[i] > 0.0) != (pass == 0)) continue;
+          renum[c] = (int)tab.size();
           tab.push_back(make_float4((float)(d.charge[i] * std::sqrt(kCoulomb) * kQ * 4096.0),
                                     (float)(0.5 * d.sigma[i] * kQ),
                                     (float)(std::sqrt(24.0 * d.epsilon[i]) * kQ), 0.0f));
-        } else {
-          t = it->second;
+          if (pass == 0) R.nlj_types = (int32_t)tab.size();
         }
-        type0.push_back(t);
-      }
-      if ((int)tab.size() >= kMaxTypes)
-        return fail(VP_ERR_ARG, "replica " + std::to_string(r) + ": more than 1023 distinct (charge, sigma, epsilon)");
+      for (int i = 0; i < d.n_atoms; ++i) type0.push_back(renum[cl[i]]);
       R.ntypes = (int32_t)tab.size();
       R.type_off = type_off;
       tab.push_back(make_float4(0.f, 0.f, 0.f, 0.f));

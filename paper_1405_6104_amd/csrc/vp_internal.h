@@ -25,6 +25,14 @@ constexpr int kListGroup = 4;
 __host__ __device__ inline int64_t list_row(int c, int lane) {
   return ((int64_t)(c / kListGroup) * kBlk + lane) * kListGroup + (c % kListGroup);
 }
+// A lane's list is two streams of rows.  Partners with Lennard-Jones
+// parameters (epsilon > 0) fill rows 0, 1, ... upward; the others (charge-only
+// atoms such as hydrogens) fill rows rowcap - 1, rowcap - 2, ... downward.
+// Chunk c of the list (its c-th row in evaluation order) is row c of the
+// first stream for c < nlj, else the (c - nlj)-th row from the top.
+__host__ __device__ inline int chunk_row(int c, int nlj, int rowcap) {
+  return c < nlj ? c : rowcap - 1 - (c - nlj);
+}
 constexpr int kParts = 8;            // waves sharing one block in the force kernel
 constexpr int kForceThreads = kParts * kBlk;
 constexpr int kMaxForceParts = 16;   // largest number of waves per block among the force tile shapes
@@ -73,6 +81,7 @@ struct RepInfo {
   int32_t maxnb;                // per-atom list capacity (multiple of 8)
   int32_t stage_cap;            // staged atoms per block (<= kMaxStage)
   int32_t ntypes, type_off;     // type table (ntypes + 1 entries, last is inert)
+  int32_t nlj_types;            // types [0, nlj_types) have epsilon > 0, the others none
   int64_t list_off;             // first element of this replica's list storage
   int64_t cmap_off;             // first element of the native contact map (FP32 [ns][ns])
   int32_t cv_blocks;            // contact map: row tiles (ceil(ns / 64)); other kinds: 1
@@ -142,6 +151,7 @@ struct Work {
   long long *F = nullptr;   // [3][slots] fixed-point forces (without bias), SoA
   int64_t fstride = 0;      // slots: distance between the x, y and z planes of F
   int32_t *nbcnt = nullptr;     // [slots] list length (multiple of 8)
+  int32_t *nblj = nullptr;      // [slots] rows of the list's first stream (LJ partners, chunk_row)
   uint16_t *nblist = nullptr;   // per block: maxnb/8 rows of 8 staged indices per lane, at list_row
   int32_t *stage_n = nullptr;   // [blocks]
   uint32_t *stage = nullptr;    // [blocks][stage_stride] slot | image shifts
