@@ -1,19 +1,21 @@
 // Forces of the potential U(X,Y) and the collective variable of the bias.
 //
-// k_forces: one workgroup (8 waves) per block of 64 atoms.  The block's
-// neighbourhood (every atom within r_cut + skin of a block atom, with its
-// periodic image applied as an exact integer shift) is staged in LDS as
-// (x, y, z, type), followed by the replica's (charge, sigma, epsilon) type
-// table; each wave
-// walks every eighth 8-entry chunk of the 64 atoms' full lists (16-bit LDS
-// indices), so every pair is read from LDS instead of gathered from memory
-// and no image arithmetic is left in the pair loop.  Potential-shifted LJ
+// k_forces: one workgroup (PARTS waves) per block of 64 atoms.  The block's
+// neighbourhood (every atom its lists name, with its periodic image applied
+// as an exact integer shift) is staged in LDS as (x, y, z, LDS address of
+// its type-table row), followed by the replica's (charge, sigma, epsilon)
+// type table.  Wave w walks the list chunks (rows of eight 16-bit LDS
+// indices) w, w + PARTS, ... of the 64 atoms' full lists, so every pair is
+// read from LDS instead of gathered from memory and no image arithmetic is
+// left in the pair loop.  A list holds the partners with Lennard-Jones
+// parameters first; a chunk in which no lane with LJ parameters still has
+// such partners runs the reaction-field term alone.  Potential-shifted LJ
 // (Lorentz-Berthelot) + reaction-field Coulomb in FP32 on integer-exact
-// separations; the eight partial forces are summed in a fixed order, the
-// bonded terms the atom owns are added in FP64, and the total is stored as
-// 64-bit fixed point.  Both members of a pair evaluate it (no atomics); the
-// list order is fixed by the deterministic sort, so results do not depend on
-// scheduling.
+// separations; chunk c feeds partial sum c mod 16, the 16 sums are added in
+// index order (one wave per force component) and stored as 64-bit fixed
+// point.  Both members of a pair evaluate it (no atomics), and the list order
+// is fixed by the deterministic sort, so results do not depend on
+// scheduling.  Bonded terms are added by k_bonded.
 //
 // k_cv_pairs / k_cv_reduce / k_cv: collective variable z and dz/dx of the
 // solute (contact map: one wave per 64 x 64 tile of solute pairs, then one
@@ -25,6 +27,11 @@
 #include "vp_launch.h"
 
 namespace vp {
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) const f4v lds_f4;
+typedef __attribute__((address_space(3))) const float lds_f1;
+__device__ __forceinline__ const lds_f4 *lds_row(int a) { return (const lds_f4 *)(size_t)a; }
+__device__ __forceinline__ const lds_f1 *lds_word(int a) { return (const lds_f1 *)(size_t)a; }
 
 // Copies a block's staged neighbourhood into LDS: entry s (slot | 3 x 5-bit
 // image shift) becomes that atom's position shifted by the image, with the
@@ -74,9 +81,9 @@ __device__ __forceinline__ void eval_chunk(const uint4 e, const int4 *__restrict
       const int u = h + v;
       sj[v] = st[(w[u >> 1] >> (16 * (u & 1))) & 0xffffu];
     }
-    float4 tj[UNROLL];
+    f4v tj[UNROLL];
 #pragma unroll
-    for (int v = 0; v < UNROLL; ++v) tj[v] = *reinterpret_cast<const float4 *>(ldsb + sj[v].w);
+    for (int v = 0; v < UNROLL; ++v) tj[v] = *lds_row(sj[v].w);
 #pragma unroll
     for (int u = 0; u < UNROLL; ++u) {
       // every entry is evaluated; the cutoff selects (no divergent branch)
@@ -121,7 +128,7 @@ __device__ __forceinline__ void eval_chunk_rf(const uint4 e, const int4 *__restr
     }
     float qj[UNROLL];
 #pragma unroll
-    for (int v = 0; v < UNROLL; ++v) qj[v] = *reinterpret_cast<const float *>(ldsb + sj[v].w);
+    for (int v = 0; v < UNROLL; ++v) qj[v] = *lds_word(sj[v].w);
 #pragma unroll
     for (int u = 0; u < UNROLL; ++u) {
       const float dx = (float)(sj[u].x - wx), dy = (float)(sj[u].y - wy), dz = (float)(sj[u].z - wz);
@@ -185,7 +192,7 @@ __global__ __launch_bounds__(64 * PARTS) __attribute__((amdgpu_waves_per_eu(MINW
   }
   const int Lx = R.Lq[0], Ly = R.Lq[1], Lz = R.Lq[2];
   // ---- stage the neighbourhood and the type table
-  const int trow = (int)sizeof(int4) * stage_slots;  // LDS byte address of the type table
+  const int trow = (int)(size_t)(const lds_f4 *)tab;  // LDS byte address of the type table
   stage_neighbourhood<NT>(W.stage + (int64_t)b * W.stage_stride, W.stage_n[b], W.xq + R.off, Lx, Ly, Lz,
                           trow, tid, st);
   if (tid == 0) st[R.stage_cap] = make_int4(kDummyCoord, kDummyCoord, kDummyCoord, trow + 16 * R.ntypes);

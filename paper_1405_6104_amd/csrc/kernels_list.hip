@@ -21,6 +21,8 @@
 //              list (slot + image shift), and each such atom's list receives
 //              the candidate's staging index.  The force kernel stages the
 //              listed atoms in LDS with their shifts applied.
+#include <type_traits>
+
 #include "vp_device.h"
 #include "vp_launch.h"
 
@@ -423,6 +425,8 @@ __global__ __launch_bounds__(kBlk) __attribute__((amdgpu_waves_per_eu(7))) void 
   // mask (offset 0 is the atom itself), any others checked against the list
   uint64_t exm = 0;
   bool exfar = false;
+  bool exrun = true;
+  int exlo = 0, excnt = 0;
   int bx0 = 0, bx1 = 0, by0 = 0, by1 = 0, bz0 = 0, bz1 = 0;
   // quarter boxes in LDS (x0, x1, y0, y1 | z0, z1, has an atom): read once per
   // candidate batch rather than held in scalar registers across the cell loops
@@ -444,6 +448,16 @@ __global__ __launch_bounds__(kBlk) __attribute__((amdgpu_waves_per_eu(7))) void 
         if (d >= -32 && d < 32) exm |= 1ull << (d + 32);
         else exfar = true;
       }
+      // the atom and its exclusions as one run of user indices [exlo, exlo +
+      // excnt) when they form one (the three atoms of a water molecule)
+      int mn = a, mx = a;
+      for (int e = e0; e < e1; ++e) {
+        mn = min(mn, ex_list[e]);
+        mx = max(mx, ex_list[e]);
+      }
+      exrun = mx - mn == e1 - e0;
+      exlo = mn;
+      excnt = e1 - e0 + 1;
     }
     // bounding box of the block (wrapped frame)
     const int big = 0x7fffffff;
@@ -465,6 +479,11 @@ __global__ __launch_bounds__(kBlk) __attribute__((amdgpu_waves_per_eu(7))) void 
   }
   // the fast test takes user indices modulo 2^16 and needs them below 2^15
   const bool anyfar = __ballot(exfar) != 0ull || R.n > kMaxFastAtoms;
+  // for every atom of the block the atom and its exclusions form one run of
+  // user indices: the fast test checks the candidate's user index against
+  // the run instead of the window (exclusion lists hold distinct atoms other
+  // than the atom itself, so max - min = count means a run)
+  const bool few = __ballot(!exrun) == 0ull;
   const long long rl = R.rlq;
   // cell ranges (unfolded: u = image * nc + cell)
   const int ux0 = (int)floordiv(((long long)bx0 - rl) * ncx, Lx);
@@ -697,7 +716,8 @@ __global__ __launch_bounds__(kBlk) __attribute__((amdgpu_waves_per_eu(7))) void 
             // reads overlap), then appended in order with one check for a
             // completed row per batch (a batch adds at most four entries).
             // Places [lo, hi) of the batches from kb on go to buf.
-            auto test_batches = [&](ListBuf &buf, int kb, int lo, int hi) {
+            auto test_batches = [&](ListBuf &buf, int kb, int lo, int hi, auto few_tag) {
+              constexpr bool FEW = decltype(few_tag)::value;
               for (int k0 = kb; k0 < hi; k0 += kListBatch) {
                 static_assert(kListBatch == 4, "one 16-byte read per record field and batch");
                 const int4 qxy = *reinterpret_cast<const int4 *>(&s_qxy[k0]);
@@ -709,8 +729,13 @@ __global__ __launch_bounds__(kBlk) __attribute__((amdgpu_waves_per_eu(7))) void 
 #pragma unroll
                 for (int u = 0; u < kListBatch; ++u) {
                   const int k = k0 + u;
-                  const uint32_t sh = (uint32_t)(exs - (int)((uint32_t)rzu[u] >> 16));
-                  const bool exw = sh < 64u && (int32_t)(uint32_t)((exm << (sh & 63u)) >> 32) < 0;
+                  bool exw;
+                  if constexpr (FEW) {
+                    exw = (uint32_t)((int)((uint32_t)rzu[u] >> 16) - exlo) < (uint32_t)excnt;
+                  } else {
+                    const uint32_t sh = (uint32_t)(exs - (int)((uint32_t)rzu[u] >> 16));
+                    exw = sh < 64u && (int32_t)(uint32_t)((exm << (sh & 63u)) >> 32) < 0;
+                  }
                   const bool in = near(rxy[u], rzu[u], rc2[u]) && !exw && k >= lo && k < hi;
                   // stored by every lane: an entry that is not kept is
                   // overwritten by the next one appended (or left past the end)
@@ -724,8 +749,13 @@ __global__ __launch_bounds__(kBlk) __attribute__((amdgpu_waves_per_eu(7))) void 
             // candidates with LJ parameters go to the first stream, the
             // others to the second (the batch holding the boundary is read
             // by both passes)
-            test_batches(lbl, 0, 0, nkl);
-            test_batches(lbr, nkl & ~(kListBatch - 1), nkl, nk);
+            if (few) {
+              test_batches(lbl, 0, 0, nkl, std::true_type{});
+              test_batches(lbr, nkl & ~(kListBatch - 1), nkl, nk, std::true_type{});
+            } else {
+              test_batches(lbl, 0, 0, nkl, std::false_type{});
+              test_batches(lbr, nkl & ~(kListBatch - 1), nkl, nk, std::false_type{});
+            }
           } else {
             for (int k = 0; k < nk; ++k) {
               const int oj = s_uid[k];
