@@ -64,12 +64,34 @@ __device__ __forceinline__ void stage_neighbourhood(const uint32_t *__restrict__
   }
 }
 
-// One list chunk (8 entries of one atom's list) evaluated against the staged
-// neighbourhood: LJ + reaction-field forces accumulated in the chunk's order
-// into (fx, fy, fz).  UNROLL entries share one batch of LDS reads.
+// One pair with the LJ + reaction-field evaluation: the force scalar over
+// one 1/r^2, the cutoff applied by a select (no divergent branch).
+__device__ __forceinline__ void pair_full(const int4 sj, const f4v tj, const float4 ti, int wx, int wy, int wz,
+                                          float rc2, float krf2, float &fx, float &fy, float &fz) {
+  const float dx = (float)(sj.x - wx), dy = (float)(sj.y - wy), dz = (float)(sj.z - wz);
+  const float r2 = qr2(dx, dy, dz);
+  const bool in = r2 < rc2;
+  const float rinv = __builtin_amdgcn_rsqf(r2);
+  const float r2inv = rinv * rinv;
+  const float sg = ti.y + tj.y;
+  const float sr2 = sg * sg * r2inv;
+  const float sr6 = sr2 * sr2 * sr2;
+  const float ee = ti.z * tj.z;
+  const float c6 = ee * sr6 * __builtin_fmaf(2.0f, sr6, -1.0f);
+  const float qq = ti.x * tj.x;
+  const float cq = qq * __builtin_fmaf(rinv, r2inv, -krf2);
+  const float fs = in ? __builtin_fmaf(c6, r2inv, cq) : 0.0f;
+  fx = __builtin_fmaf(-fs, dx, fx);
+  fy = __builtin_fmaf(-fs, dy, fy);
+  fz = __builtin_fmaf(-fs, dz, fz);
+}
+
+// One list chunk (8 single-atom entries of one atom's list) evaluated against
+// the staged neighbourhood: LJ + reaction-field forces accumulated in the
+// chunk's order into (fx, fy, fz).  UNROLL entries share one batch of LDS
+// reads.
 template <int UNROLL>
-__device__ __forceinline__ void eval_chunk(const uint4 e, const int4 *__restrict__ st,
-                                           const char *__restrict__ ldsb, const float4 ti, int wx,
+__device__ __forceinline__ void eval_chunk(const uint4 e, const int4 *__restrict__ st, const float4 ti, int wx,
                                            int wy, int wz, float rc2, float krf2, float &fx, float &fy,
                                            float &fz) {
   const uint32_t w[4] = {e.x, e.y, e.z, e.w};
@@ -85,63 +107,59 @@ __device__ __forceinline__ void eval_chunk(const uint4 e, const int4 *__restrict
 #pragma unroll
     for (int v = 0; v < UNROLL; ++v) tj[v] = *lds_row(sj[v].w);
 #pragma unroll
-    for (int u = 0; u < UNROLL; ++u) {
-      // every entry is evaluated; the cutoff selects (no divergent branch)
-      const float dx = (float)(sj[u].x - wx), dy = (float)(sj[u].y - wy), dz = (float)(sj[u].z - wz);
-      const float r2 = qr2(dx, dy, dz);
-      const bool in = r2 < rc2;
-      const float rinv = __builtin_amdgcn_rsqf(r2);
-      const float r2inv = rinv * rinv;
-      const float sg = ti.y + tj[u].y;
-      const float sr2 = sg * sg * r2inv;
-      const float sr6 = sr2 * sr2 * sr2;
-      const float ee = ti.z * tj[u].z;
-      // force scalar (LJ + reaction field) / r, both terms over one 1/r^2
-      const float c6 = ee * sr6 * __builtin_fmaf(2.0f, sr6, -1.0f);
-      const float qq = ti.x * tj[u].x;
-      const float cq = qq * __builtin_fmaf(rinv, r2inv, -krf2);
-      const float fs = in ? __builtin_fmaf(c6, r2inv, cq) : 0.0f;
-      fx = __builtin_fmaf(-fs, dx, fx);
-      fy = __builtin_fmaf(-fs, dy, fy);
-      fz = __builtin_fmaf(-fs, dz, fz);
-    }
+    for (int u = 0; u < UNROLL; ++u) pair_full(sj[u], tj[u], ti, wx, wy, wz, rc2, krf2, fx, fy, fz);
   }
 }
 
-// The same chunk when no entry of it pairs two Lennard-Jones atoms (each pair
-// involves an atom without LJ parameters): only the reaction-field term, and
-// only the charge of each partner is read from its type-table row.  For such
-// pairs the LJ factor of eval_chunk is an exact zero (the product of the two
-// sqrt(24 epsilon) is +0), so both evaluations give the same bits.
-template <int UNROLL>
-__device__ __forceinline__ void eval_chunk_rf(const uint4 e, const int4 *__restrict__ st,
-                                              const char *__restrict__ ldsb, const float qi, int wx, int wy,
-                                              int wz, float rc2, float krf2, float &fx, float &fy, float &fz) {
+// One chunk of site entries: each entry names a three-atom site staged at
+// three consecutive places (its first atom, then two atoms without LJ
+// parameters).  The first atom takes the LJ + reaction-field evaluation,
+// the other two the reaction-field term alone, read with their charge only
+// (for them the LJ factor of the full evaluation is an exact zero, so the
+// result has the same bits).  Two sites share one batch of LDS reads.
+__device__ __forceinline__ void pair_rf(const int4 sj, const float qj, const float qi, int wx, int wy, int wz,
+                                        float rc2, float krf2, float &fx, float &fy, float &fz) {
+  const float dx = (float)(sj.x - wx), dy = (float)(sj.y - wy), dz = (float)(sj.z - wz);
+  const float r2 = qr2(dx, dy, dz);
+  const bool in = r2 < rc2;
+  const float rinv = __builtin_amdgcn_rsqf(r2);
+  const float r2inv = rinv * rinv;
+  const float qq = qi * qj;
+  const float cq = qq * __builtin_fmaf(rinv, r2inv, -krf2);
+  const float fs = in ? cq : 0.0f;
+  fx = __builtin_fmaf(-fs, dx, fx);
+  fy = __builtin_fmaf(-fs, dy, fy);
+  fz = __builtin_fmaf(-fs, dz, fz);
+}
+__device__ __forceinline__ void eval_chunk_sites(const uint4 e, const int4 *__restrict__ st, const float4 ti,
+                                                 int wx, int wy, int wz, float rc2, float krf2, float &fx,
+                                                 float &fy, float &fz) {
   const uint32_t w[4] = {e.x, e.y, e.z, e.w};
+  constexpr int SB = 2;  // sites per batch of LDS reads
 #pragma unroll
-  for (int h = 0; h < 8; h += UNROLL) {
-    int4 sj[UNROLL];
+  for (int h = 0; h < 8; h += SB) {
+    int4 sj[SB][3];
 #pragma unroll
-    for (int v = 0; v < UNROLL; ++v) {
+    for (int v = 0; v < SB; ++v) {
       const int u = h + v;
-      sj[v] = st[(w[u >> 1] >> (16 * (u & 1))) & 0xffffu];
+      const int L = (w[u >> 1] >> (16 * (u & 1))) & 0xffffu;
+      sj[v][0] = st[L];
+      sj[v][1] = st[L + 1];
+      sj[v][2] = st[L + 2];
     }
-    float qj[UNROLL];
+    f4v t0[SB];
+    float q1[SB], q2[SB];
 #pragma unroll
-    for (int v = 0; v < UNROLL; ++v) qj[v] = *lds_word(sj[v].w);
+    for (int v = 0; v < SB; ++v) {
+      t0[v] = *lds_row(sj[v][0].w);
+      q1[v] = *lds_word(sj[v][1].w);
+      q2[v] = *lds_word(sj[v][2].w);
+    }
 #pragma unroll
-    for (int u = 0; u < UNROLL; ++u) {
-      const float dx = (float)(sj[u].x - wx), dy = (float)(sj[u].y - wy), dz = (float)(sj[u].z - wz);
-      const float r2 = qr2(dx, dy, dz);
-      const bool in = r2 < rc2;
-      const float rinv = __builtin_amdgcn_rsqf(r2);
-      const float r2inv = rinv * rinv;
-      const float qq = qi * qj[u];
-      const float cq = qq * __builtin_fmaf(rinv, r2inv, -krf2);
-      const float fs = in ? cq : 0.0f;
-      fx = __builtin_fmaf(-fs, dx, fx);
-      fy = __builtin_fmaf(-fs, dy, fy);
-      fz = __builtin_fmaf(-fs, dz, fz);
+    for (int v = 0; v < SB; ++v) {
+      pair_full(sj[v][0], t0[v], ti, wx, wy, wz, rc2, krf2, fx, fy, fz);
+      pair_rf(sj[v][1], q1[v], ti.x, wx, wy, wz, rc2, krf2, fx, fy, fz);
+      pair_rf(sj[v][2], q2[v], ti.x, wx, wy, wz, rc2, krf2, fx, fy, fz);
     }
   }
 }
@@ -195,7 +213,7 @@ __global__ __launch_bounds__(64 * PARTS) __attribute__((amdgpu_waves_per_eu(MINW
   const int trow = (int)(size_t)(const lds_f4 *)tab;  // LDS byte address of the type table
   stage_neighbourhood<NT>(W.stage + (int64_t)b * W.stage_stride, W.stage_n[b], W.xq + R.off, Lx, Ly, Lz,
                           trow, tid, st);
-  if (tid == 0) st[R.stage_cap] = make_int4(kDummyCoord, kDummyCoord, kDummyCoord, trow + 16 * R.ntypes);
+  if (tid < kStageDummies) st[R.stage_cap + tid] = make_int4(kDummyCoord, kDummyCoord, kDummyCoord, trow + 16 * R.ntypes);
   for (int t = tid; t <= R.ntypes; t += NT) tab[t] = types[R.type_off + t];
   __syncthreads();
 
@@ -218,13 +236,10 @@ __global__ __launch_bounds__(64 * PARTS) __attribute__((amdgpu_waves_per_eu(MINW
     const int nch = W.nbcnt[slot] >> 3, nlj = W.nblj[slot], rowcap = R.maxnb >> 3;
     const uint4 *lp = reinterpret_cast<const uint4 *>(W.nblist + R.list_off + (int64_t)(b - R.blk0) * R.maxnb * kBlk);
     uint4 e = lp[list_row(chunk_row(min(part, max(nch - 1, 0)), nlj, rowcap), lane)];
-    // the lane's atom has Lennard-Jones parameters: the first stream of its
-    // list holds its LJ pairs
-    const bool lji = xi.w < R.nlj_types;
     // this wave takes chunks part, part + PARTS, ...: its k-th chunk of every
     // group of SETS feeds set k, which is logical accumulator k PARTS + part.
-    // A chunk runs the LJ + reaction-field evaluation when any lane's chunk
-    // holds Lennard-Jones pairs, else the reaction-field one (same bits).
+    // A lane's chunk c < nlj holds single atoms, a later one sites; a chunk
+    // step runs each kind for the lanes that hold it.
     for (int c0 = part; c0 < nch; c0 += PARTS * SETS) {
 #pragma unroll
       for (int k = 0; k < SETS; ++k) {
@@ -233,12 +248,9 @@ __global__ __launch_bounds__(64 * PARTS) __attribute__((amdgpu_waves_per_eu(MINW
           // the next chunk's indices are fetched while this one is evaluated
           // (the last chunk is fetched again rather than reading past the list)
           const uint4 en = lp[list_row(chunk_row(min(c + PARTS, nch - 1), nlj, rowcap), lane)];
-          if (__ballot(lji && c < nlj) != 0ull)
-            eval_chunk<UNROLL>(e, st, reinterpret_cast<const char *>(lds), ti, wx, wy, wz, rc2, krf2, fx[k],
-                               fy[k], fz[k]);
-          else
-            eval_chunk_rf<UNROLL>(e, st, reinterpret_cast<const char *>(lds), ti.x, wx, wy, wz, rc2, krf2,
-                                  fx[k], fy[k], fz[k]);
+          const bool single = c < nlj;
+          if (single) eval_chunk<UNROLL>(e, st, ti, wx, wy, wz, rc2, krf2, fx[k], fy[k], fz[k]);
+          else eval_chunk_sites(e, st, ti, wx, wy, wz, rc2, krf2, fx[k], fy[k], fz[k]);
           e = en;
         }
       }
@@ -306,7 +318,7 @@ __global__ __launch_bounds__(kForceThreads) void k_pair_energy(const RepInfo *__
   const int trow = (int)sizeof(int4) * stage_slots;
   stage_neighbourhood<kForceThreads>(W.stage + (int64_t)b * W.stage_stride, W.stage_n[b], W.xq + R.off, Lx,
                                      Ly, Lz, trow, tid, st);
-  if (tid == 0) st[R.stage_cap] = make_int4(kDummyCoord, kDummyCoord, kDummyCoord, trow + 16 * R.ntypes);
+  if (tid < kStageDummies) st[R.stage_cap + tid] = make_int4(kDummyCoord, kDummyCoord, kDummyCoord, trow + 16 * R.ntypes);
   for (int t = tid; t <= R.ntypes; t += kForceThreads) tab[t] = types[R.type_off + t];
   __syncthreads();
   const int lane = tid & (kBlk - 1), part = tid / kBlk;
@@ -322,8 +334,12 @@ __global__ __launch_bounds__(kForceThreads) void k_pair_energy(const RepInfo *__
     const float rc2 = R.rc2q, krf2 = R.krf2q;
     const int nent = W.nbcnt[slot], nlj = W.nblj[slot], rowcap = R.maxnb >> 3;
     const uint16_t *lp = W.nblist + R.list_off + (int64_t)(b - R.blk0) * R.maxnb * kBlk;
+    // entry k names one atom (chunks below nlj) or a three-atom site
     for (int k = part; k < nent; k += kParts) {
-      const int L = lp[list_row(chunk_row(k >> 3, nlj, rowcap), lane) * 8 + (k & 7)];
+      const int L0 = lp[list_row(chunk_row(k >> 3, nlj, rowcap), lane) * 8 + (k & 7)];
+      const int na = (k >> 3) < nlj ? 1 : 3;
+      for (int m = 0; m < na; ++m) {
+      const int L = L0 + m;
       const int4 sj = st[L];
       const float4 tj = *reinterpret_cast<const float4 *>(reinterpret_cast<const char *>(lds) + sj.w);
       const float dx = (float)(sj.x - wx), dy = (float)(sj.y - wy), dz = (float)(sj.z - wz);
@@ -355,6 +371,7 @@ __global__ __launch_bounds__(kForceThreads) void k_pair_energy(const RepInfo *__
       acc[5] += w * ddx * ddy;
       acc[6] += w * ddx * ddz;
       acc[7] += w * ddy * ddz;
+      }
     }
   }
   __syncthreads();  // the staged neighbourhood is no longer read
@@ -574,9 +591,9 @@ __global__ __launch_bounds__(kForceThreads) void k_tangent_forces(
     for (int k = 0; k < kStageBatch; ++k)
       if (q0 + k * kForceThreads + tid < nst) sxi[q0 + k * kForceThreads + tid] = t[k];
   }
-  if (tid == 0) {
-    st[R.stage_cap] = make_int4(kDummyCoord, kDummyCoord, kDummyCoord, trow + 16 * R.ntypes);
-    sxi[R.stage_cap] = make_float4(0.f, 0.f, 0.f, 0.f);
+  if (tid < kStageDummies) {
+    st[R.stage_cap + tid] = make_int4(kDummyCoord, kDummyCoord, kDummyCoord, trow + 16 * R.ntypes);
+    sxi[R.stage_cap + tid] = make_float4(0.f, 0.f, 0.f, 0.f);
   }
   for (int t = tid; t <= R.ntypes; t += kForceThreads) tab[t] = types[R.type_off + t];
   __syncthreads();
@@ -601,9 +618,13 @@ __global__ __launch_bounds__(kForceThreads) void k_tangent_forces(
     for (int c = part; c < nch; c += kParts) {
       const uint4 e = lp[list_row(chunk_row(c, nlj, rowcap), lane)];
       const uint32_t w[4] = {e.x, e.y, e.z, e.w};
+      // an entry names one atom (chunks below nlj) or a three-atom site
+      const int na = c < nlj ? 1 : 3;
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
-        const int L = (int)((w[u >> 1] >> (16 * (u & 1))) & 0xffffu);
+        const int L0 = (int)((w[u >> 1] >> (16 * (u & 1))) & 0xffffu);
+        for (int m = 0; m < na; ++m) {
+        const int L = L0 + m;
         const int4 sj = st[L];
         const float4 tj = *reinterpret_cast<const float4 *>(reinterpret_cast<const char *>(lds) + sj.w);
         const float4 xj = sxi[L];
@@ -628,6 +649,7 @@ __global__ __launch_bounds__(kForceThreads) void k_tangent_forces(
         gx = __builtin_fmaf(-a, ddx, __builtin_fmaf(-bq, dx, gx));
         gy = __builtin_fmaf(-a, ddy, __builtin_fmaf(-bq, dy, gy));
         gz = __builtin_fmaf(-a, ddz, __builtin_fmaf(-bq, dz, gz));
+        }
       }
     }
   }
@@ -1251,14 +1273,14 @@ __global__ void k_native_map(const float *__restrict__ xf, int ns, int min_sep, 
 static inline int xcd_grid(int nb) { return 8 * ((nb + 7) / 8); }
 
 size_t force_lds_bytes(const vp_system *s) {
-  size_t stage = sizeof(int4) * ((size_t)(s->stage_cap_max + 1) + (size_t)(s->ntypes_max + 1));
+  size_t stage = sizeof(int4) * ((size_t)(s->stage_cap_max + kStageDummies) + (size_t)(s->ntypes_max + 1));
   // logical partial sums: forces FP32 [3][kLogicalParts][64]
   size_t red = sizeof(float) * 3 * kLogicalParts * kBlk;
   return stage > red ? stage : red;
 }
 
 size_t energy_lds_bytes(const vp_system *s) {
-  size_t stage = sizeof(int4) * ((size_t)(s->stage_cap_max + 1) + (size_t)(s->ntypes_max + 1));
+  size_t stage = sizeof(int4) * ((size_t)(s->stage_cap_max + kStageDummies) + (size_t)(s->ntypes_max + 1));
   size_t red = sizeof(double) * 8 * kParts * kBlk;  // [8 values][kParts][64] FP64
   return stage > red ? stage : red;
 }
@@ -1300,7 +1322,7 @@ void launch_native_map(const float *xf, int ns, int min_sep, float r0, float rs,
 template <int P, int U, int M>
 static void launch_forces_t(vp_system *s, Work &W, const int32_t *blist, int nblk, hipStream_t st) {
   hipLaunchKernelGGL((k_forces<P, U, M>), dim3(xcd_grid(nblk)), dim3(64 * P), force_lds_bytes(s), st,
-                     s->info, W, s->tile_rep, s->tile_first, blist, nblk, s->types, s->stage_cap_max + 1);
+                     s->info, W, s->tile_rep, s->tile_first, blist, nblk, s->types, s->stage_cap_max + kStageDummies);
 }
 
 void launch_forces_shape(vp_system *s, Work &W, int shape, const int32_t *blist, int nblk, hipStream_t st) {
@@ -1335,13 +1357,13 @@ void launch_energies(vp_system *s, Work &W, bool gated, hipStream_t st) {
   const int nout = s->opt.nst_out > 0 ? s->opt.nst_out : 1;
   if (gated) {
     hipLaunchKernelGGL(k_pair_energy<true>, dim3(xcd_grid(s->n_blocks)), dim3(kForceThreads), lds, st,
-                       s->info, W, s->tile_rep, s->tile_first, s->n_blocks, s->types, s->stage_cap_max + 1,
+                       s->info, W, s->tile_rep, s->tile_first, s->n_blocks, s->types, s->stage_cap_max + kStageDummies,
                        s->step, nout);
     hipLaunchKernelGGL((k_bonded<true, true>), dim3(xcd_grid(s->n_blocks)), dim3(kBlk), 0, st, s->info, W,
                        s->tile_rep, s->tile_first, s->n_blocks, s->bt_start, s->bterms, s->step, nout);
   } else {
     hipLaunchKernelGGL(k_pair_energy<false>, dim3(xcd_grid(s->n_blocks)), dim3(kForceThreads), lds, st,
-                       s->info, W, s->tile_rep, s->tile_first, s->n_blocks, s->types, s->stage_cap_max + 1,
+                       s->info, W, s->tile_rep, s->tile_first, s->n_blocks, s->types, s->stage_cap_max + kStageDummies,
                        s->step, nout);
     hipLaunchKernelGGL((k_bonded<true, false>), dim3(xcd_grid(s->n_blocks)), dim3(kBlk), 0, st, s->info, W,
                        s->tile_rep, s->tile_first, s->n_blocks, s->bt_start, s->bterms, s->step, nout);
@@ -1375,7 +1397,7 @@ void launch_cv(vp_system *s, Work &W, int inc_step, hipStream_t st, bool tan) {
 }
 
 size_t tangent_lds_bytes(const vp_system *s) {
-  size_t stage = 2 * sizeof(int4) * (size_t)(s->stage_cap_max + 1) + sizeof(int4) * (size_t)(s->ntypes_max + 1);
+  size_t stage = 2 * sizeof(int4) * (size_t)(s->stage_cap_max + kStageDummies) + sizeof(int4) * (size_t)(s->ntypes_max + 1);
   size_t red = sizeof(float) * 3 * kForceThreads;
   return stage > red ? stage : red;
 }
@@ -1389,7 +1411,7 @@ void launch_tangent_forces(vp_system *s, Work &W, hipStream_t st) {
   const size_t lds = tangent_lds_bytes(s);
   for (int d = 0; d < 2; ++d) {
     hipLaunchKernelGGL(k_tangent_forces, dim3(xcd_grid(s->n_blocks)), dim3(kForceThreads), lds, st,
-                       s->info, W, s->tile_rep, s->tile_first, s->n_blocks, s->types, s->stage_cap_max + 1, d);
+                       s->info, W, s->tile_rep, s->tile_first, s->n_blocks, s->types, s->stage_cap_max + kStageDummies, d);
     hipLaunchKernelGGL(k_tangent_bonded, dim3(xcd_grid(s->n_blocks)), dim3(kBlk), 0, st, s->info, W,
                        s->tile_rep, s->tile_first, s->n_blocks, s->bt_start, s->bterms, d);
   }

@@ -214,9 +214,9 @@ __global__ __launch_bounds__(kBinThreads) void k_bin(const RepInfo *__restrict__
 }
 
 // New slot -> source (old slot through the old inverse map, or user index);
-// also records the atom's periodic image at this build and writes its wrapped
-// position, user index, slot (with its Lennard-Jones class) and image in
-// fine-cell order.
+// also records the atom's periodic image at this build, writes its wrapped
+// position, user index, slot (with its Lennard-Jones class and site role) and
+// image in fine-cell order, and its new slot by user index.
 template <int MODE>
 __global__ __launch_bounds__(kBlock) void k_permute(const RepInfo *__restrict__ info,
                                                     const RepState *__restrict__ state, Work W,
@@ -224,6 +224,7 @@ __global__ __launch_bounds__(kBlock) void k_permute(const RepInfo *__restrict__ 
                                                     const int32_t *__restrict__ tile_first,
                                                     int ntiles, const float *__restrict__ x_user,
                                                     const int32_t *__restrict__ type0,
+                                                    const int32_t *__restrict__ role0,
                                                     const int32_t *__restrict__ orig_t,
                                                     int4 *__restrict__ xq_t,
                                                     float4 *__restrict__ vel_t,
@@ -232,7 +233,8 @@ __global__ __launch_bounds__(kBlock) void k_permute(const RepInfo *__restrict__ 
                                                     int4 *__restrict__ cellx_t,
                                                     int2 *__restrict__ celljw_t,
                                                     float4 *__restrict__ tx_t,
-                                                    float4 *__restrict__ tv_t) {
+                                                    float4 *__restrict__ tv_t,
+                                                    int32_t *__restrict__ inv_t) {
   int tile = xcd_tile(blockIdx.x, ntiles);
   if (tile < 0) return;
   const int r = tile_rep[tile];
@@ -265,8 +267,10 @@ __global__ __launch_bounds__(kBlock) void k_permute(const RepInfo *__restrict__ 
   // the same atom in fine-cell order (wrapped position) for the candidate search
   const int q = R.off + cellpos_t[slot];
   cellx_t[q] = make_int4(x.x - kx * R.Lq[0], x.y - ky * R.Lq[1], x.z - kz * R.Lq[2], a);
-  // the sign bit marks an atom with Lennard-Jones parameters
-  celljw_t[q] = make_int2(p | (x.w < R.nlj_types ? (int)0x80000000u : 0), wr);
+  // the sign bit marks an atom with Lennard-Jones parameters, bits 29-30 its
+  // site role
+  celljw_t[q] = make_int2(p | (x.w < R.nlj_types ? (int)0x80000000u : 0) | (role0[R.uoff + a] << 29), wr);
+  inv_t[R.uoff + a] = slot;
 }
 
 __device__ __forceinline__ int wave_min_i(int v) {
@@ -342,7 +346,11 @@ constexpr int kListBatch = 4;
 // and the replica size below which user indices fit the fast test's 16 bits.
 constexpr int kQMax = 8191;
 constexpr int kQInert = 1200000000;  // > 3 kQMax^2 + 4 kQMax^2 + any threshold, < 2^31 - 4 kQMax^2
-constexpr int kMaxFastAtoms = 32767;
+constexpr int kMaxFastAtoms = 65535;
+// Largest distance (squared, coordinate units) between the first atom of a
+// three-atom site and its other atoms: 0.25 nm; a larger one flags the replica.
+constexpr float kSiteMax2 = (float)(0.25 * kQ * 0.25 * kQ);
+constexpr long long kSiteMaxQ = (long long)(0.25 * kQ) + 1;
 typedef short short2v __attribute__((ext_vector_type(2)));
 // Runs of cells listed per row group of the list kernel's search.
 constexpr int kMaxRuns = 2 * kBlk;
@@ -370,7 +378,7 @@ template <int MODE>
 // registers, 2.26 ms at the four that the unconstrained allocation allows,
 // 2.20 ms at eight with more spills): the candidate loop is latency-bound,
 // so more waves in flight beat spill-free code.
-__global__ __launch_bounds__(kBlk) __attribute__((amdgpu_waves_per_eu(7))) void k_list(const RepInfo *__restrict__ info,
+__global__ __launch_bounds__(kBlk) __attribute__((amdgpu_waves_per_eu(5))) void k_list(const RepInfo *__restrict__ info,
                                                RepState *__restrict__ state, Work W,
                                                const int32_t *__restrict__ tile_rep,
                                                const int32_t *__restrict__ tile_first, int nblk,
@@ -384,10 +392,13 @@ __global__ __launch_bounds__(kBlk) __attribute__((amdgpu_waves_per_eu(7))) void 
                                                const int32_t *__restrict__ ex_list,
                                                const float4 *__restrict__ integ0,
                                                const float4 *__restrict__ tx_t,
-                                               const float4 *__restrict__ tv_t) {
+                                               const float4 *__restrict__ tv_t,
+                                               const int32_t *__restrict__ inv_t) {
   // kept candidates: quantised position q (x | y << 16, z | user index << 16,
   // |q|^2) and user index
   __shared__ __align__(16) int32_t s_qxy[kBlk], s_qzu[kBlk], s_qc2[kBlk], s_uid[kBlk];
+  // kept sites: the same records for each of their three atoms
+  __shared__ __align__(16) int32_t s_sxy[3][kBlk], s_szu[3][kBlk], s_sc2[3][kBlk];
   // each lane's list entries not yet stored: first stream (LJ partners)
   // [0, kBlk), second stream (charge-only partners) [kBlk, 2 kBlk)
   __shared__ __align__(16) uint8_t s_buf[2 * kBlk * kBufStride];
@@ -509,7 +520,9 @@ __global__ __launch_bounds__(kBlk) __attribute__((amdgpu_waves_per_eu(7))) void 
   const int ox = bx0 + (bx1 - bx0) / 2, oy = by0 + (by1 - by0) / 2, oz = bz0 + (bz1 - bz0) / 2;
   int qs = 0;
   {
-    const long long half = (long long)max(bx1 - bx0, max(by1 - by0, bz1 - bz0)) / 2 + 1 + rl + 64;
+    // kept sites' atoms lie within two site offsets beyond the list radius
+    const long long half = (long long)max(bx1 - bx0, max(by1 - by0, bz1 - bz0)) / 2 + 1 + rl + 64 +
+                           (anyfar ? 0ll : 2ll * kSiteMaxQ);
     while ((half >> qs) > (long long)kQMax - 1) ++qs;
   }
   const int qthr = (int)ceil(((double)rl / (double)(1ll << qs) + 1.7320508075688772) *
@@ -564,6 +577,8 @@ __global__ __launch_bounds__(kBlk) __attribute__((amdgpu_waves_per_eu(7))) void 
   bool exact = false;
   for (int mode = 0; mode < 2; ++mode) {
     exact = mode == 1;
+    // site mode: the fast test with three-atom sites listed by one entry
+    const bool sm = !exact && !anyfar;
     nst = 0;
     lbl.wa = lbl.base;
     lbl.rows = 0;
@@ -650,12 +665,15 @@ __global__ __launch_bounds__(kBlk) __attribute__((amdgpu_waves_per_eu(7))) void 
         if (valid)
           while (s_rpre[run + 1] <= t) ++run;
         rc = __shfl(run, kBlk - 1, kBlk);  // lane 63 is valid whenever another load follows
-        // ---- load 64 candidates, keep those near one of the quarter boxes
-        bool keep = false;
-        int3 cq = make_int3(0, 0, 0);
-        uint32_t code = 0u;
+        // ---- load 64 candidates, keep those near one of the quarter boxes.
+        // In site mode the first atom of a three-atom site stands for the
+        // site (its other atoms are not candidates): it is kept if within the
+        // list radius plus its larger member offset of a quarter box, and
+        // its three atoms are staged together with its image shift.
+        bool keep = false, site = false;
+        int3 cq = make_int3(0, 0, 0), cm1 = cq, cm2 = cq;
+        uint32_t code = 0u, code1 = 0u, code2 = 0u;
         int uid = 0;
-        bool ljc = false;
         if (valid) {
           const int q = s_rq0[run] + (t - s_rpre[run]);
           const int img = s_rimg[run];
@@ -663,15 +681,35 @@ __global__ __launch_bounds__(kBlk) __attribute__((amdgpu_waves_per_eu(7))) void 
           const int4 cxq = cellx_t[off + q];
           const int2 jw = celljw_t[off + q];
           const int px = cxq.x + six * Lx, py = cxq.y + siy * Ly, pz = cxq.z + siz * Lz;
+          const int role = (jw.x >> 29) & 3;
+          site = sm && role == 1;
+          float krl2 = rl2;
+          int3 d1 = make_int3(0, 0, 0), d2 = d1;
+          int sl1 = 0, sl2 = 0;
+          if (site) {
+            const int4 xh = xq_t[off + (jw.x & 0xffff)];
+            sl1 = inv_t[R.uoff + cxq.w + 1];
+            sl2 = inv_t[R.uoff + cxq.w + 2];
+            const int4 x1 = xq_t[sl1], x2 = xq_t[sl2];
+            d1 = make_int3(x1.x - xh.x, x1.y - xh.y, x1.z - xh.z);
+            d2 = make_int3(x2.x - xh.x, x2.y - xh.y, x2.z - xh.z);
+            const float m2 = fmaxf(qr2((float)d1.x, (float)d1.y, (float)d1.z), qr2((float)d2.x, (float)d2.y, (float)d2.z));
+            if (!(m2 <= kSiteMax2)) bad = true;  // a site torn apart: the replica is flagged
+            // rounding of the two squares and the root is far below the unit added
+            const float kr = (float)R.rlq + __builtin_sqrtf(fminf(m2, kSiteMax2)) + 2.0f;
+            krl2 = kr * kr;
+          }
           // kept if within the list radius of a quarter box; a box distance
           // never exceeds an atom distance, also after rounding
+          if (!(sm && role == 2)) {
 #pragma unroll
-          for (int g = 0; g < 4; ++g) {
-            const int4 q0 = s_qb[g][0], q1 = s_qb[g][1];
-            const float gxq = (float)max(0, max(q0.x - px, px - q0.y));
-            const float gyq = (float)max(0, max(q0.z - py, py - q0.w));
-            const float gzq = (float)max(0, max(q1.x - pz, pz - q1.y));
-            keep = keep || (q1.z != 0 && qr2(gxq, gyq, gzq) < rl2);
+            for (int g = 0; g < 4; ++g) {
+              const int4 q0 = s_qb[g][0], q1 = s_qb[g][1];
+              const float gxq = (float)max(0, max(q0.x - px, px - q0.y));
+              const float gyq = (float)max(0, max(q0.z - py, py - q0.w));
+              const float gzq = (float)max(0, max(q1.x - pz, pz - q1.y));
+              keep = keep || (q1.z != 0 && qr2(gxq, gyq, gzq) < krl2);
+            }
           }
           const int sx = six - unpack_wrap(jw.y, 0), sy = siy - unpack_wrap(jw.y, 1),
                     sz = siz - unpack_wrap(jw.y, 2);
@@ -679,35 +717,70 @@ __global__ __launch_bounds__(kBlk) __attribute__((amdgpu_waves_per_eu(7))) void 
             bad = true;  // shift not representable: the replica is flagged
             keep = false;
           }
-          const int qx = min(max((px - ox) >> qs, -kQMax), kQMax), qy = min(max((py - oy) >> qs, -kQMax), kQMax),
-                    qz = min(max((pz - oz) >> qs, -kQMax), kQMax);
           uid = cxq.w;
-          ljc = jw.x < 0;  // the candidate has Lennard-Jones parameters
-          cq = make_int3((int)(((uint32_t)qx & 0xffffu) | ((uint32_t)qy << 16)),
-                         (int)(((uint32_t)qz & 0xffffu) | ((uint32_t)uid << 16)), qx * qx + qy * qy + qz * qz);
-          code = ((uint32_t)jw.x & 0xffffu) | ((uint32_t)((sx + 16) & 31) << 16) |
-                 ((uint32_t)((sy + 16) & 31) << 21) | ((uint32_t)((sz + 16) & 31) << 26);
+          auto record = [&](int x, int y, int z) {
+            const int qx = min(max((x - ox) >> qs, -kQMax), kQMax), qy = min(max((y - oy) >> qs, -kQMax), kQMax),
+                      qz = min(max((z - oz) >> qs, -kQMax), kQMax);
+            return make_int3((int)(((uint32_t)qx & 0xffffu) | ((uint32_t)qy << 16)),
+                             (int)(((uint32_t)qz & 0xffffu) | ((uint32_t)uid << 16)), qx * qx + qy * qy + qz * qz);
+          };
+          cq = record(px, py, pz);
+          const uint32_t shift = ((uint32_t)((sx + 16) & 31) << 16) | ((uint32_t)((sy + 16) & 31) << 21) |
+                                 ((uint32_t)((sz + 16) & 31) << 26);
+          code = ((uint32_t)jw.x & 0xffffu) | shift;
+          if (site) {
+            cm1 = record(px + d1.x, py + d1.y, pz + d1.z);
+            cm2 = record(px + d2.x, py + d2.y, pz + d2.z);
+            code1 = ((uint32_t)(sl1 - off) & 0xffffu) | shift;
+            code2 = ((uint32_t)(sl2 - off) & 0xffffu) | shift;
+          }
         }
-        // kept candidates with Lennard-Jones parameters take the first nkl
-        // places of the batch, the others the rest (each group in lane order)
-        const uint64_t km = __ballot(keep), kml = __ballot(keep && ljc);
+        // kept single atoms take places [0, n1) of the load's records and
+        // staging, kept sites places [0, ns3) of the site records and three
+        // staging places each after the single atoms (each group in lane
+        // order)
+        const uint64_t km = __ballot(keep), kms = __ballot(keep && site);
         const uint64_t below = (1ull << lane) - 1ull;
-        const int nk = __popcll(km), nkl = __popcll(kml);
-        const int at = ljc ? __popcll(kml & below) : nkl + __popcll(km & ~kml & below);
-        if (!exact && nst + nk > cap) {
+        const int nk = __popcll(km), ns3 = __popcll(kms), n1 = nk - ns3;
+        const int at = site ? __popcll(kms & below) : __popcll(km & ~kms & below);
+        if (!exact && nst + n1 + 3 * ns3 > cap) {
           full = true;  // uniform: the block is redone in exact mode
           break;
         }
-        if (keep) {
+        if (keep && !site) {
           s_qxy[at] = cq.x;
           s_qzu[at] = cq.y;
           s_qc2[at] = cq.z;
           s_uid[at] = uid;
         }
+        if (keep && site) {
+          s_sxy[0][at] = cq.x;
+          s_szu[0][at] = cq.y;
+          s_sc2[0][at] = cq.z;
+          s_sxy[1][at] = cm1.x;
+          s_szu[1][at] = cm1.y;
+          s_sc2[1][at] = cm1.z;
+          s_sxy[2][at] = cm2.x;
+          s_szu[2][at] = cm2.y;
+          s_sc2[2][at] = cm2.z;
+        }
         // the fast test reads whole batches: entries up to the next
         // multiple of the batch are made inert (|qc|^2 beyond any test)
-        if (lane >= nk && lane < ((nk + kListBatch - 1) & ~(kListBatch - 1))) s_qc2[lane] = kQInert;
-        if (!exact && keep) stg[nst + at] = code;  // every kept candidate is staged
+        if (lane >= n1 && lane < ((n1 + kListBatch - 1) & ~(kListBatch - 1))) s_qc2[lane] = kQInert;
+        if (lane >= ns3 && lane < ((ns3 + kListBatch - 1) & ~(kListBatch - 1))) {
+          s_sc2[0][lane] = kQInert;
+          s_sc2[1][lane] = kQInert;
+          s_sc2[2][lane] = kQInert;
+        }
+        if (!exact && keep) {  // every kept candidate is staged
+          if (!site) {
+            stg[nst + at] = code;
+          } else {
+            stg[nst + n1 + 3 * at] = code;
+            stg[nst + n1 + 3 * at + 1] = code1;
+            stg[nst + n1 + 3 * at + 2] = code2;
+          }
+        }
         __syncthreads();
         if (!exact) {
           // ---- every staged candidate against the lane's own atom
@@ -715,10 +788,9 @@ __global__ __launch_bounds__(kBlk) __attribute__((amdgpu_waves_per_eu(7))) void 
             // kListBatch candidates read and tested together (their LDS
             // reads overlap), then appended in order with one check for a
             // completed row per batch (a batch adds at most four entries).
-            // Places [lo, hi) of the batches from kb on go to buf.
-            auto test_batches = [&](ListBuf &buf, int kb, int lo, int hi, auto few_tag) {
+            auto test_singles = [&](ListBuf &buf, int hi, auto few_tag) {
               constexpr bool FEW = decltype(few_tag)::value;
-              for (int k0 = kb; k0 < hi; k0 += kListBatch) {
+              for (int k0 = 0; k0 < hi; k0 += kListBatch) {
                 static_assert(kListBatch == 4, "one 16-byte read per record field and batch");
                 const int4 qxy = *reinterpret_cast<const int4 *>(&s_qxy[k0]);
                 const int4 qzu = *reinterpret_cast<const int4 *>(&s_qzu[k0]);
@@ -728,7 +800,6 @@ __global__ __launch_bounds__(kBlk) __attribute__((amdgpu_waves_per_eu(7))) void 
                 const int rc2[kListBatch] = {qc2.x, qc2.y, qc2.z, qc2.w};
 #pragma unroll
                 for (int u = 0; u < kListBatch; ++u) {
-                  const int k = k0 + u;
                   bool exw;
                   if constexpr (FEW) {
                     exw = (uint32_t)((int)((uint32_t)rzu[u] >> 16) - exlo) < (uint32_t)excnt;
@@ -736,25 +807,43 @@ __global__ __launch_bounds__(kBlk) __attribute__((amdgpu_waves_per_eu(7))) void 
                     const uint32_t sh = (uint32_t)(exs - (int)((uint32_t)rzu[u] >> 16));
                     exw = sh < 64u && (int32_t)(uint32_t)((exm << (sh & 63u)) >> 32) < 0;
                   }
-                  const bool in = near(rxy[u], rzu[u], rc2[u]) && !exw && k >= lo && k < hi;
+                  const bool in = near(rxy[u], rzu[u], rc2[u]) && !exw;
                   // stored by every lane: an entry that is not kept is
                   // overwritten by the next one appended (or left past the end)
-                  *lds16(buf.wa) = (uint16_t)(nst + k);
+                  *lds16(buf.wa) = (uint16_t)(nst + k0 + u);
                   buf.wa += in ? 2u : 0u;
                 }
                 static_assert(kListBatch <= kBufLen - 8, "a batch must fit behind seven entries");
                 if (buf.row_full()) buf.flush();
               }
             };
-            // candidates with LJ parameters go to the first stream, the
-            // others to the second (the batch holding the boundary is read
-            // by both passes)
-            if (few) {
-              test_batches(lbl, 0, 0, nkl, std::true_type{});
-              test_batches(lbr, nkl & ~(kListBatch - 1), nkl, nk, std::true_type{});
-            } else {
-              test_batches(lbl, 0, 0, nkl, std::false_type{});
-              test_batches(lbr, nkl & ~(kListBatch - 1), nkl, nk, std::false_type{});
+            // single atoms go to the first stream
+            if (few) test_singles(lbl, n1, std::true_type{});
+            else test_singles(lbl, n1, std::false_type{});
+            // sites go to the second: listed when one of their three atoms
+            // is within the list radius, unless the lane's atom is one of
+            // them (a site's atoms exclude each other and nothing else)
+            constexpr int SB = 2;  // sites per batch of LDS reads
+            for (int k0 = 0; k0 < ns3; k0 += SB) {
+              int2 rxy[3], rzu[3], rc2[3];
+#pragma unroll
+              for (int m = 0; m < 3; ++m) {
+                rxy[m] = *reinterpret_cast<const int2 *>(&s_sxy[m][k0]);
+                rzu[m] = *reinterpret_cast<const int2 *>(&s_szu[m][k0]);
+                rc2[m] = *reinterpret_cast<const int2 *>(&s_sc2[m][k0]);
+              }
+#pragma unroll
+              for (int u = 0; u < SB; ++u) {
+                const int zu0 = u ? rzu[0].y : rzu[0].x;
+                const bool mine = (uint32_t)(a - (int)((uint32_t)zu0 >> 16)) < 3u;
+                bool in = false;
+#pragma unroll
+                for (int m = 0; m < 3; ++m)
+                  in = in || near(u ? rxy[m].y : rxy[m].x, u ? rzu[m].y : rzu[m].x, u ? rc2[m].y : rc2[m].x);
+                *lds16(lbr.wa) = (uint16_t)(nst + n1 + 3 * (k0 + u));
+                lbr.wa += in && !mine ? 2u : 0u;
+              }
+              if (lbr.row_full()) lbr.flush();
             }
           } else {
             for (int k = 0; k < nk; ++k) {
@@ -764,15 +853,13 @@ __global__ __launch_bounds__(kBlk) __attribute__((amdgpu_waves_per_eu(7))) void 
               bool in = near(s_qxy[k], s_qzu[k], s_qc2[k]) && !(win && (int32_t)(uint32_t)((exm << (sh & 63u)) >> 32) < 0);
               if (in && !win && exfar)
                 for (int e = e0; e < e1; ++e) in = in && (ex_list[e] != oj);
-              if (in) {
-                if (k < nkl) lbl.append((uint32_t)(nst + k));
-                else lbr.append((uint32_t)(nst + k));
-              }
+              if (in) lbl.append((uint32_t)(nst + k));
             }
           }
-          nst += nk;
+          nst += n1 + 3 * ns3;
         } else {
-          // ---- exact mode: a candidate is staged only if some atom needs it
+          // ---- exact mode (single atoms only): a candidate is staged only
+          // if some atom needs it
           const int nst0 = nst;
           uint64_t acc = 0ull;
           for (int k = 0; k < nk; ++k) {
@@ -784,10 +871,7 @@ __global__ __launch_bounds__(kBlk) __attribute__((amdgpu_waves_per_eu(7))) void 
               for (int e = e0; e < e1; ++e) in = in && (ex_list[e] != oj);
             if (__ballot(in)) {
               if (nst < cap) {
-                if (in) {
-                  if (k < nkl) lbl.append((uint32_t)nst);
-                  else lbr.append((uint32_t)nst);
-                }
+                if (in) lbl.append((uint32_t)nst);
                 acc |= 1ull << k;
                 ++nst;
               } else {
@@ -872,7 +956,11 @@ __global__ __launch_bounds__(kBlk) void k_debug_pairs(const RepInfo *__restrict_
   const uint32_t *stg = W.stage + (int64_t)b * W.stage_stride;
   const int nst = W.stage_n[b];
   for (int k = 0; k < cnt; ++k) {
-    const int L = lst[list_row(chunk_row(k >> 3, nlj, rowcap), threadIdx.x) * 8 + (k & 7)];
+    const int L0 = lst[list_row(chunk_row(k >> 3, nlj, rowcap), threadIdx.x) * 8 + (k & 7)];
+    // an entry names one atom (chunks below nlj) or a three-atom site
+    const int na = (k >> 3) < nlj ? 1 : 3;
+    for (int m = 0; m < na; ++m) {
+    const int L = L0 + m;
     if (L >= nst) continue;
     const uint32_t e = stg[L];
     const int j = (int)(e & 0xffffu);
@@ -886,6 +974,7 @@ __global__ __launch_bounds__(kBlk) void k_debug_pairs(const RepInfo *__restrict_
     if (qr2(dx, dy, dz) < R.rc2q) {
       unsigned long long idx = atomicAdd(counter, 1ull);
       if (idx < cap) out[idx] = make_int2(a, bj);
+    }
     }
   }
 }
@@ -901,25 +990,25 @@ void launch_rebuild(vp_system *s, Work &W, int mode, const float *x_user, hipStr
                        x_user, s->cellid_t, s->zkey_t, s->fcell_t, s->bucket_t, s->bkey_t,
                        s->borig_t, s->orig_t, s->cellpos_t, s->step);
     hipLaunchKernelGGL(k_permute<0>, dim3(xcd_grid(s->n_tiles)), dim3(kBlock), 0, st, s->info,
-                       s->state, W, s->tile_rep, s->tile_first, s->n_tiles, x_user, s->type0,
+                       s->state, W, s->tile_rep, s->tile_first, s->n_tiles, x_user, s->type0, s->role0,
                        s->orig_t, s->xq_t, s->vel_t, s->wrap_t, s->cellpos_t, s->cellx_t,
-                       s->celljw_t, s->tx_t, s->tv_t);
+                       s->celljw_t, s->tx_t, s->tv_t, s->inv_t);
     hipLaunchKernelGGL(k_list<0>, dim3(xcd_grid(s->n_blocks)), dim3(kBlk), 0, st, s->info,
                        s->state, W, s->tile_rep, s->tile_first, s->n_blocks, s->xq_t, s->vel_t,
                        s->orig_t, s->wrap_t, s->cellx_t, s->celljw_t, s->ex_start, s->ex_list,
-                       s->integ0, s->tx_t, s->tv_t);
+                       s->integ0, s->tx_t, s->tv_t, s->inv_t);
   } else {
     hipLaunchKernelGGL(k_bin<1>, dim3(s->R), dim3(kBinThreads), 0, st, s->info, s->state, W,
                        x_user, s->cellid_t, s->zkey_t, s->fcell_t, s->bucket_t, s->bkey_t,
                        s->borig_t, s->orig_t, s->cellpos_t, s->step);
     hipLaunchKernelGGL(k_permute<1>, dim3(xcd_grid(s->n_tiles)), dim3(kBlock), 0, st, s->info,
-                       s->state, W, s->tile_rep, s->tile_first, s->n_tiles, x_user, s->type0,
+                       s->state, W, s->tile_rep, s->tile_first, s->n_tiles, x_user, s->type0, s->role0,
                        s->orig_t, s->xq_t, s->vel_t, s->wrap_t, s->cellpos_t, s->cellx_t,
-                       s->celljw_t, s->tx_t, s->tv_t);
+                       s->celljw_t, s->tx_t, s->tv_t, s->inv_t);
     hipLaunchKernelGGL(k_list<1>, dim3(xcd_grid(s->n_blocks)), dim3(kBlk), 0, st, s->info,
                        s->state, W, s->tile_rep, s->tile_first, s->n_blocks, s->xq_t, s->vel_t,
                        s->orig_t, s->wrap_t, s->cellx_t, s->celljw_t, s->ex_start, s->ex_list,
-                       s->integ0, s->tx_t, s->tv_t);
+                       s->integ0, s->tx_t, s->tv_t, s->inv_t);
   }
 }
 

@@ -277,7 +277,7 @@ static void list_params(const vp_replica_desc &d, const vp_options &o, int ntype
   const double half = 0.5 * std::min({d.box[0], d.box[1], d.box[2]});
   double cap = o.skin;
   if (!(cap > 0)) {
-    const long long budget = (long long)kMaxLds / (long long)sizeof(int4) - (ntypes_max + 1) - 1;
+    const long long budget = (long long)kMaxLds / (long long)sizeof(int4) - (ntypes_max + 1) - kStageDummies;
     cap = 0.14;
     while (cap > 0.025 && (stage_estimate(d.r_cut + cap, rho) > std::min<long long>(budget, kMaxStage) ||
                            !(d.r_cut + cap < half)))
@@ -546,7 +546,7 @@ static vp_status build(vp_system *s, const vp_replica_desc *reps, int32_t n_reps
     // force workgroups share a CU (up to the staging array's size), and never
     // less than the estimate above; a block whose candidates would overflow
     // it is built again in exact mode.
-    const long long budget = (long long)kMaxLds / (long long)sizeof(int4) - (ntypes_max + 1) - 1;
+    const long long budget = (long long)kMaxLds / (long long)sizeof(int4) - (ntypes_max + 1) - kStageDummies;
     stage_cap_max = 0;
     for (int r = 0; r < n_reps; ++r) {
       RepInfo &R = s->info_h[r];
@@ -644,6 +644,30 @@ static vp_status build(vp_system *s, const vp_replica_desc *reps, int32_t n_reps
   }
   bt_start[U] = (int32_t)bterms.size();
   ex_start[U] = (int32_t)ex_list.size();
+  // Three-atom sites (water molecules): atoms i, i+1, i+2 of a replica that
+  // exclude each other and nothing else, the last two without LJ parameters.
+  // The list build names such a site by one entry (role 1: its first atom,
+  // role 2: the other two); every other atom is listed on its own (role 0).
+  std::vector<int32_t> role0(U, 0);
+  for (int r = 0; r < n_reps; ++r) {
+    const vp_replica_desc &d = reps[r];
+    const size_t u0 = (size_t)s->info_h[r].uoff;
+    auto only = [&](size_t v, int32_t p, int32_t q) {
+      return excl[v].size() == 2 && excl[v][0] == p && excl[v][1] == q;
+    };
+    for (int i = 0; i + 2 < d.n_atoms;) {
+      const size_t u = u0 + (size_t)i;
+      if (only(u, i + 1, i + 2) && only(u + 1, i, i + 2) && only(u + 2, i, i + 1) && d.epsilon[i + 1] == 0.0 &&
+          d.epsilon[i + 2] == 0.0) {
+        role0[u] = 1;
+        role0[u + 1] = 2;
+        role0[u + 2] = 2;
+        i += 3;
+      } else {
+        ++i;
+      }
+    }
+  }
 
   // ---------------- device allocations and uploads
   TRY(upload(s, &s->info, s->info_h));
@@ -664,6 +688,7 @@ static vp_status build(vp_system *s, const vp_replica_desc *reps, int32_t n_reps
   TRY(upload(s, &s->bterms, bterms));
   TRY(upload(s, &s->ex_start, ex_start));
   TRY(upload(s, &s->ex_list, ex_list));
+  TRY(upload(s, &s->role0, role0));
   TRY(upload(s, &s->cforce, cforce));
   TRY(upload(s, &s->xf, xf_h));
   if (o.contact_order) TRY(native_contacts(s, reps));
@@ -696,6 +721,7 @@ static vp_status build(vp_system *s, const vp_replica_desc *reps, int32_t n_reps
   TRY(dalloc(s, &s->cellpos_t, S));
   TRY(dalloc(s, &s->cellx_t, S));
   TRY(dalloc(s, &s->celljw_t, S));
+  TRY(dalloc(s, &s->inv_t, U));
   if (s->tangent) {
     TRY(dalloc(s, &s->tx_t, 2 * S));
     TRY(dalloc(s, &s->tv_t, 2 * S));

@@ -61,6 +61,9 @@ constexpr float kQf = 16777216.0f;
 constexpr float kInvQf = 5.9604644775390625e-8f;  // 2^-24
 constexpr double kInvQ = 5.9604644775390625e-8;
 constexpr int kDummyCoord = 1 << 30;  // staged position of the list padding entry
+// Staged places after a block's capacity that hold the inert padding entry:
+// three, so that padding read as a three-atom site stays inert.
+constexpr int kStageDummies = 3;
 // energy partials per 64-atom block: LJ, RF, bond, angle, pair virial [9],
 // bonded virial [9] (each written by one kernel), two unused
 constexpr int kEp = 24;
@@ -218,6 +221,7 @@ struct vp_system {
   vp::BTerm *bterms = nullptr;
   int32_t *ex_start = nullptr;  // [users + 1]
   int32_t *ex_list = nullptr;   // replica-local user indices
+  int32_t *role0 = nullptr;     // [users] 0: listed alone, 1: first atom of a three-atom site, 2: other site atom
   float *cmap = nullptr;        // native contact maps, [ns][ns] per distinct map
   float4 *cforce = nullptr;     // [solute total] constant bias force
   double *xf = nullptr;         // [solute rows][3] FP64 X_f of the replicas that give one
@@ -242,7 +246,8 @@ struct vp_system {
   float4 *tx_t = nullptr;       // [2][slots] tangents in the new order (rebuild)
   float4 *tv_t = nullptr;
   int4 *cellx_t = nullptr;      // [slots] fine-cell order: wrapped x, y, z and user index
-  int2 *celljw_t = nullptr;     // [slots] fine-cell order: slot and packed image
+  int2 *celljw_t = nullptr;     // [slots] fine-cell order: slot (| LJ class << 31 | site role << 29) and packed image
+  int32_t *inv_t = nullptr;     // [users] global slot of each atom in the new order (rebuild)
   long long *step = nullptr;  // device step counter
   vp::Work traj, eval;
   bool eval_ready = false;
