@@ -103,7 +103,7 @@ typedef struct {
   const int32_t *excl; /* [n_excl][2]: pairs without nonbonded interaction */
   double box[3];       /* orthorhombic box edges */
   double r_cut, eps_rf, kT, dt;
-  const double *x0;      /* [n_atoms][3] X_i (+ solvent), unwrapped; |x| < 59 nm */
+  const double *x0;      /* [n_atoms][3] X_i (+ solvent), unwrapped; |x| < 238 nm */
   const double *v0;      /* [n_atoms][3] or NULL: Maxwell-Boltzmann from the seed */
   const double *x_final; /* [n_solute][3] X_f (defines the target contact map) or NULL */
   int32_t bias;          /* vp_bias_kind */
@@ -204,10 +204,10 @@ typedef struct {
   double ms[VP_FORCE_SHAPES];
 } vp_tile_bucket;
 
-/* Positions are held as 32-bit fixed point in units of 2^-24 nm, so that
+/* Positions are held as 32-bit fixed point in units of 2^-22 nm, so that
  * periodic images are exact integer shifts: x0 and x_dev are rounded to the
- * nearest multiple of 2^-24 nm (ties to even) on entry and every drift of the
- * integrator is rounded to that grid.  Coordinates must stay within 59 nm of
+ * nearest multiple of 2^-22 nm (ties to even) on entry and every drift of the
+ * integrator is rounded to that grid.  Coordinates must stay within 238 nm of
  * the origin.
  *
  * Create a batch of trial trajectories.  reps: HOST array of n_reps
@@ -276,7 +276,7 @@ vp_status vp_select_path(vp_system *s, const uint8_t *eligible, int32_t *best, d
 /* Copy the current positions and velocities in user order into DEVICE
  * buffers x_dev, v_dev ([sum N][3] FP32; either may be NULL).  Asynchronous.
  * The trajectory state itself lives in the library's own sorted, fixed-point
- * layout (positions in units of 2^-24 nm, reordered at every list rebuild),
+ * layout (positions in units of 2^-22 nm, reordered at every list rebuild),
  * so it is copied out rather than lent as views. */
 vp_status vp_get_state(vp_system *s, float *x_dev, float *v_dev, void *hip_stream);
 
@@ -308,7 +308,7 @@ vp_status vp_energy_records(vp_system *s, double *out_host, int32_t cap, int32_t
  * solute pairs i < j with j - i > contact_min_sep and |X_f,i - X_f,j| <=
  * contact_r0; a contact forms at the first step (0 = the initial state) at
  * which its distance is <= contact_r0.  Both tests are exact, on squared
- * integer distances of positions and r0 on the 2^-24 nm grid.  Writes the
+ * integer distances of positions and r0 on the 2^-22 nm grid.  Writes the
  * number of contacts of replica rep to *n_contacts and, where not NULL, the
  * first min(cap, n) pairs (HOST int32 [cap][2], replica-local user indices)
  * and formation steps (HOST int64 [cap], -1 = not formed yet).  Synchronises. */

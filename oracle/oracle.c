@@ -2,7 +2,7 @@
  *
  * Build: plain C99, -O2 -ffp-contract=off, single-threaded.  Everything is
  * FP64 except the pair-membership predicate, which is defined on fixed-point
- * coordinates (unit 2^-24 nm) with one FP32 rounding of the exact integer
+ * coordinates (unit 2^-22 nm) with one FP32 rounding of the exact integer
  * separation, so that pair *sets* can be compared exactly with the GPU.
  */
 #include "oracle.h"
@@ -15,7 +15,7 @@
 #define COULOMB_F 138.935458 /* kJ mol^-1 nm e^-2 */
 #define TWO_PI 6.283185307179586476925286766559
 #define FORCE_LIMIT 1.0e6 /* kJ/mol/nm: above this a replica is unstable */
-#define ORA_QSCALE 16777216.0 /* 2^24: fixed-point coordinates of the pair predicate */
+#define ORA_QSCALE 4194304.0 /* 2^22: fixed-point coordinates of the pair predicate */
 
 struct ora_ctx {
   ora_sys s;
@@ -23,7 +23,7 @@ struct ora_ctx {
   int32_t *ex_start, *ex_list;
   /* native contact map C~(X_f) for solute pairs, dense [ns][ns] */
   double *cmap_f;
-  /* fixed-point geometry of the pair predicate (unit 2^-24 nm) */
+  /* fixed-point geometry of the pair predicate (unit 2^-22 nm) */
   int64_t Lq[3];
   float rc2_q;
   /* reaction-field constants */
@@ -184,7 +184,7 @@ static int excluded(const ora_ctx *c, int i, int j) {
 }
 
 /* ------------------------------------------------------------------------ */
-/* Pair membership on fixed-point coordinates (unit q = 2^-24 nm):           */
+/* Pair membership on fixed-point coordinates (unit q = 2^-22 nm):           */
 /*   X = round(x / q) (nearest, ties to even), Lq = round(L / q);            */
 /*   D = Xj - Xi - n Lq with n the nearest integer to (Xj - Xi) / Lq;        */
 /*   d = fl32(D);  r2 = fma(dz, dz, fma(dy, dy, fl32(dx * dx)));             */

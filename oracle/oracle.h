@@ -173,7 +173,7 @@ double ora_path_similarity(int32_t nc, const int64_t *ta, const int64_t *tb);
  * pairs i < j with j - i > contact_min_sep whose distance in X_f is at most
  * contact_r0 (where C = 3/5); a contact is formed at a configuration where
  * its distance is at most contact_r0.  Both decisions are taken exactly, on
- * positions and r0 rounded to the 2^-24 nm grid (squared integer distances).
+ * positions and r0 rounded to the 2^-22 nm grid (squared integer distances).
  * ora_native_contacts writes up to cap pairs [cap][2] and returns the count;
  * ora_contacts_formed sets formed[k] for the listed pairs at positions x. */
 int64_t ora_native_contacts(const ora_ctx *c, int32_t *pairs, int64_t cap);

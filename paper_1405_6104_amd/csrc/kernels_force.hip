@@ -64,11 +64,39 @@ __device__ __forceinline__ void stage_neighbourhood(const uint32_t *__restrict__
   }
 }
 
+// The same staging for the pair kernel, with the coordinates stored as FP32
+// values relative to the block centre c (bit patterns in the int4): every
+// such coordinate is an integer below 2^24 grid units (the list build checks
+// it), so it is exact, and so is the FP32 difference of two of them.
+template <int NT>
+__device__ __forceinline__ void stage_neighbourhood_rel(const uint32_t *__restrict__ stg, int nst,
+                                                        const int4 *__restrict__ xr, int Lx, int Ly, int Lz,
+                                                        int trow, int tid, int4 *__restrict__ st, int4 c) {
+  for (int s0 = 0; s0 < nst; s0 += NT * kStageBatch) {
+    uint32_t e[kStageBatch];
+#pragma unroll
+    for (int k = 0; k < kStageBatch; ++k) e[k] = stg[min(s0 + k * NT + tid, nst - 1)];
+    int4 xj[kStageBatch];
+#pragma unroll
+    for (int k = 0; k < kStageBatch; ++k) xj[k] = xr[e[k] & 0xffffu];
+#pragma unroll
+    for (int k = 0; k < kStageBatch; ++k) {
+      const int s = s0 + k * NT + tid;
+      const int sx = (int)((e[k] >> 16) & 31) - 16, sy = (int)((e[k] >> 21) & 31) - 16,
+                sz = (int)((e[k] >> 26) & 31) - 16;
+      if (s < nst)
+        st[s] = make_int4(__float_as_int((float)(xj[k].x + sx * Lx - c.x)),
+                          __float_as_int((float)(xj[k].y + sy * Ly - c.y)),
+                          __float_as_int((float)(xj[k].z + sz * Lz - c.z)), trow + 16 * xj[k].w);
+    }
+  }
+}
+
 // One pair with the LJ + reaction-field evaluation: the force scalar over
 // one 1/r^2, the cutoff applied by a select (no divergent branch).
-__device__ __forceinline__ void pair_full(const int4 sj, const f4v tj, const float4 ti, int wx, int wy, int wz,
-                                          float rc2, float krf2, float &fx, float &fy, float &fz) {
-  const float dx = (float)(sj.x - wx), dy = (float)(sj.y - wy), dz = (float)(sj.z - wz);
+__device__ __forceinline__ void pair_full(const int4 sj, const f4v tj, const float4 ti, float wx, float wy,
+                                          float wz, float rc2, float krf2, float &fx, float &fy, float &fz) {
+  const float dx = __int_as_float(sj.x) - wx, dy = __int_as_float(sj.y) - wy, dz = __int_as_float(sj.z) - wz;
   const float r2 = qr2(dx, dy, dz);
   const bool in = r2 < rc2;
   const float rinv = __builtin_amdgcn_rsqf(r2);
@@ -91,8 +119,8 @@ __device__ __forceinline__ void pair_full(const int4 sj, const f4v tj, const flo
 // chunk's order into (fx, fy, fz).  UNROLL entries share one batch of LDS
 // reads.
 template <int UNROLL>
-__device__ __forceinline__ void eval_chunk(const uint4 e, const int4 *__restrict__ st, const float4 ti, int wx,
-                                           int wy, int wz, float rc2, float krf2, float &fx, float &fy,
+__device__ __forceinline__ void eval_chunk(const uint4 e, const int4 *__restrict__ st, const float4 ti, float wx,
+                                           float wy, float wz, float rc2, float krf2, float &fx, float &fy,
                                            float &fz) {
   const uint32_t w[4] = {e.x, e.y, e.z, e.w};
 #pragma unroll
@@ -117,9 +145,9 @@ __device__ __forceinline__ void eval_chunk(const uint4 e, const int4 *__restrict
 // the other two the reaction-field term alone, read with their charge only
 // (for them the LJ factor of the full evaluation is an exact zero, so the
 // result has the same bits).  Two sites share one batch of LDS reads.
-__device__ __forceinline__ void pair_rf(const int4 sj, const float qj, const float qi, int wx, int wy, int wz,
-                                        float rc2, float krf2, float &fx, float &fy, float &fz) {
-  const float dx = (float)(sj.x - wx), dy = (float)(sj.y - wy), dz = (float)(sj.z - wz);
+__device__ __forceinline__ void pair_rf(const int4 sj, const float qj, const float qi, float wx, float wy,
+                                        float wz, float rc2, float krf2, float &fx, float &fy, float &fz) {
+  const float dx = __int_as_float(sj.x) - wx, dy = __int_as_float(sj.y) - wy, dz = __int_as_float(sj.z) - wz;
   const float r2 = qr2(dx, dy, dz);
   const bool in = r2 < rc2;
   const float rinv = __builtin_amdgcn_rsqf(r2);
@@ -132,7 +160,7 @@ __device__ __forceinline__ void pair_rf(const int4 sj, const float qj, const flo
   fz = __builtin_fmaf(-fs, dz, fz);
 }
 __device__ __forceinline__ void eval_chunk_sites(const uint4 e, const int4 *__restrict__ st, const float4 ti,
-                                                 int wx, int wy, int wz, float rc2, float krf2, float &fx,
+                                                 float wx, float wy, float wz, float rc2, float krf2, float &fx,
                                                  float &fy, float &fz) {
   const uint32_t w[4] = {e.x, e.y, e.z, e.w};
   constexpr int SB = 2;  // sites per batch of LDS reads
@@ -211,9 +239,13 @@ __global__ __launch_bounds__(64 * PARTS) __attribute__((amdgpu_waves_per_eu(MINW
   const int Lx = R.Lq[0], Ly = R.Lq[1], Lz = R.Lq[2];
   // ---- stage the neighbourhood and the type table
   const int trow = (int)(size_t)(const lds_f4 *)tab;  // LDS byte address of the type table
-  stage_neighbourhood<NT>(W.stage + (int64_t)b * W.stage_stride, W.stage_n[b], W.xq + R.off, Lx, Ly, Lz,
-                          trow, tid, st);
-  if (tid < kStageDummies) st[R.stage_cap + tid] = make_int4(kDummyCoord, kDummyCoord, kDummyCoord, trow + 16 * R.ntypes);
+  const int4 bc = W.bctr[b];
+  stage_neighbourhood_rel<NT>(W.stage + (int64_t)b * W.stage_stride, W.stage_n[b], W.xq + R.off, Lx, Ly, Lz,
+                              trow, tid, st, bc);
+  if (tid < kStageDummies) {
+    const int far = __float_as_int((float)kDummyCoord);
+    st[R.stage_cap + tid] = make_int4(far, far, far, trow + 16 * R.ntypes);
+  }
   for (int t = tid; t <= R.ntypes; t += NT) tab[t] = types[R.type_off + t];
   __syncthreads();
 
@@ -228,9 +260,10 @@ __global__ __launch_bounds__(64 * PARTS) __attribute__((amdgpu_waves_per_eu(MINW
   if (active) {
     xi = W.xq[slot];
     const int wr = W.wrap[slot];
-    const int wx = xi.x - unpack_wrap(wr, 0) * Lx;
-    const int wy = xi.y - unpack_wrap(wr, 1) * Ly;
-    const int wz = xi.z - unpack_wrap(wr, 2) * Lz;
+    // the lane's atom relative to the block centre (exact in FP32)
+    const float wx = (float)(xi.x - unpack_wrap(wr, 0) * Lx - bc.x);
+    const float wy = (float)(xi.y - unpack_wrap(wr, 1) * Ly - bc.y);
+    const float wz = (float)(xi.z - unpack_wrap(wr, 2) * Lz - bc.z);
     const float4 ti = tab[xi.w];
     const float rc2 = R.rc2q, krf2 = R.krf2q;
     const int nch = W.nbcnt[slot] >> 3, nlj = W.nblj[slot], rowcap = R.maxnb >> 3;
@@ -356,7 +389,7 @@ __global__ __launch_bounds__(kForceThreads) void k_pair_energy(const RepInfo *__
       const float qq = ti.x * tj.x;
       const float cq = qq * __builtin_fmaf(rinv, r2inv, -krf2);
       const float fs = __builtin_fmaf(c6, r2inv, cq);
-      // ee = 24 eps 2^48, qq = f q q 2^72 (see the type table)
+      // ee = 24 eps 2^44, qq = f q q 2^66 (see the type table)
       const double e4 = (double)ee * (1.0 / 6.0) * (kInvQ * kInvQ);
       const double s2c = (double)sg * sg / ((double)rc2);
       const double s6c = s2c * s2c * s2c;
@@ -638,7 +671,7 @@ __global__ __launch_bounds__(kForceThreads) void k_tangent_forces(
         const float sr6 = sr2 * sr2 * sr2;
         const float ee = ti.z * tj.z;
         const float qq = ti.x * tj.x;
-        // f(s) and f'(s) in the units of k_forces (coordinates in 2^-24 nm)
+        // f(s) and f'(s) in the units of k_forces (coordinates in 2^-22 nm)
         const float fs = ee * sr6 * __builtin_fmaf(2.0f, sr6, -1.0f) * r2inv +
                          qq * __builtin_fmaf(rinv, r2inv, -krf2);
         const float fsp = r2inv * r2inv *

@@ -124,7 +124,7 @@ __global__ __launch_bounds__(kBlock) void k_integrate(const RepInfo *__restrict_
         if (rec) ke = 0.5 * mass0[R.uoff + a] * ((double)v.x * v.x + (double)v.y * v.y + (double)v.z * v.z);
       }
       if (MODE & MODE_START) {
-        // positions are fixed point (unit 2^-24 nm): each drift is rounded once
+        // positions are fixed point (unit 2^-22 nm): each drift is rounded once
         int4 x = W.xq[slot];
         const float hq = hdt * kQf;
         v.x += kx;

@@ -1,6 +1,6 @@
 // Cell binning, deterministic spatial sort and per-block neighbourhood lists.
 //
-// Coordinates are 32-bit fixed point (unit 2^-24 nm), so image shifts by the
+// Coordinates are 32-bit fixed point (unit 2^-22 nm), so image shifts by the
 // box edge are exact integer additions.  The trajectory state is kept sorted
 // along serpentine xy columns, z inside a column, so 64 consecutive slots form
 // a compact block.  A rebuild (creation, every step whose count n + 1 is a
@@ -370,7 +370,7 @@ static_assert(kBlk % kListBatch == 0, "batch must divide the candidate buffer");
 // and appends the staging indices of the candidates within the list radius
 // (exclusions removed) to its list.  This test runs in FP32 on coordinates
 // relative to the block's corner, with the radius enlarged by a bound on the
-// rounding (a few hundred units of 2^-24 nm at most): the list is a superset
+// rounding (a few hundred grid units at most): the list is a superset
 // of the exact list radius, and the force kernel applies the exact cutoff.
 template <int MODE>
 // Register budget for seven waves per SIMD (measured: a full rebuild of the
@@ -519,12 +519,11 @@ __global__ __launch_bounds__(kBlk) __attribute__((amdgpu_waves_per_eu(5))) void 
   // usual block size, and the force kernel applies the exact cutoff).
   const int ox = bx0 + (bx1 - bx0) / 2, oy = by0 + (by1 - by0) / 2, oz = bz0 + (bz1 - bz0) / 2;
   int qs = 0;
-  {
-    // kept sites' atoms lie within two site offsets beyond the list radius
-    const long long half = (long long)max(bx1 - bx0, max(by1 - by0, bz1 - bz0)) / 2 + 1 + rl + 64 +
-                           (anyfar ? 0ll : 2ll * kSiteMaxQ);
-    while ((half >> qs) > (long long)kQMax - 1) ++qs;
-  }
+  // every coordinate of a staged atom lies within half of the block centre
+  // (kept sites' atoms within two site offsets beyond the list radius)
+  const long long half = (long long)max(bx1 - bx0, max(by1 - by0, bz1 - bz0)) / 2 + 1 + rl + 64 +
+                         (anyfar ? 0ll : 2ll * kSiteMaxQ);
+  while ((half >> qs) > (long long)kQMax - 1) ++qs;
   const int qthr = (int)ceil(((double)rl / (double)(1ll << qs) + 1.7320508075688772) *
                              ((double)rl / (double)(1ll << qs) + 1.7320508075688772) + 1e-6);
   short2v m2axy = {0, 0}, m2az0 = {0, 0};
@@ -556,7 +555,11 @@ __global__ __launch_bounds__(kBlk) __attribute__((amdgpu_waves_per_eu(5))) void 
   ListBuf lbl{bufl, bufl, reinterpret_cast<uint4 *>(lst), lane, rowcap, 0, false};
   ListBuf lbr{bufr, bufr, reinterpret_cast<uint4 *>(lst), lane, rowcap, 0, true};
 
-  bool bad = false;
+  // The force kernel stages positions relative to the block centre in FP32,
+  // exact while every coordinate stays below 2^24 grid units from it (with
+  // 0.1 nm of room for the motion until the next build, which half the skin
+  // bounds); a block beyond that flags its replica.
+  bool bad = half + (long long)(0.1 * kQ) >= (1ll << 24);
   __syncthreads();  // cell edges in LDS
   // Fast mode stages every candidate kept by the quarter boxes.  If that
   // would exceed the block's staging capacity, the block is built again in
@@ -904,7 +907,10 @@ __global__ __launch_bounds__(kBlk) __attribute__((amdgpu_waves_per_eu(5))) void 
   }
   W.nbcnt[slot] = active ? 8 * (nlj + nrf) : 0;
   W.nblj[slot] = active ? nlj : 0;
-  if (lane == 0) W.stage_n[b] = nst;
+  if (lane == 0) {
+    W.stage_n[b] = nst;
+    W.bctr[b] = make_int4(ox, oy, oz, 0);
+  }
   if (__ballot(bad) && lane == 0) {
     if (MODE == 0) atomicOr(&state[r].status, VP_REPLICA_LIST_OVERFLOW);
     else atomicOr(&W.flags[r], 2);

@@ -77,6 +77,7 @@ size_t layout(const vp_system *s, unsigned char *base, vp::Work &W) {
   take(&W.nblj, S);
   take(&W.nblist, (size_t)s->list_elems);
   take(&W.stage_n, B);
+  take(&W.bctr, B);
   W.stage_stride = s->stage_cap_max;
   take(&W.stage, B * (size_t)W.stage_stride);
   take(&W.cell_start, (size_t)s->n_cells);

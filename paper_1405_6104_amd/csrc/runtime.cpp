@@ -179,6 +179,7 @@ static vp_status alloc_work(vp_system *s, Work &W, bool traj) {
   TRY(dalloc(s, &W.nblj, S));
   TRY(dalloc(s, &W.nblist, (size_t)s->list_elems));
   TRY(dalloc(s, &W.stage_n, B));
+  TRY(dalloc(s, &W.bctr, B));
   W.stage_stride = s->stage_cap_max;
   TRY(dalloc(s, &W.stage, B * (size_t)W.stage_stride));
   TRY(dalloc(s, &W.cell_start, (size_t)s->n_cells));
@@ -302,7 +303,7 @@ static void list_params(const vp_replica_desc &d, const vp_options &o, int ntype
 
 // Native contacts of every replica that gives X_f (one list per distinct
 // X_f, min_sep and r0): solute pairs i < j, j - i > min_sep, whose squared
-// distance on the 2^-24 nm grid is at most (r0 on that grid)^2, exactly in
+// distance on the 2^-22 nm grid is at most (r0 on that grid)^2, exactly in
 // integers; the formation steps start at -1.
 static vp_status native_contacts(vp_system *s, const vp_replica_desc *reps) {
   std::vector<int2> pairs;
@@ -484,7 +485,7 @@ static vp_status build(vp_system *s, const vp_replica_desc *reps, int32_t n_reps
           const int i = first[c];
           if ((d.epsilon[i] > 0.0) != (pass == 0)) continue;
           renum[c] = (int)tab.size();
-          tab.push_back(make_float4((float)(d.charge[i] * std::sqrt(kCoulomb) * kQ * 4096.0),
+          tab.push_back(make_float4((float)(d.charge[i] * std::sqrt(kCoulomb) * kQ * std::sqrt(kQ)),
                                     (float)(0.5 * d.sigma[i] * kQ),
                                     (float)(std::sqrt(24.0 * d.epsilon[i]) * kQ), 0.0f));
           if (pass == 0) R.nlj_types = (int32_t)tab.size();
@@ -602,7 +603,7 @@ static vp_status build(vp_system *s, const vp_replica_desc *reps, int32_t n_reps
       for (int a = 0; a < 3; ++a) {
         double xq = d.x0[3 * i + a] * kQ;
         if (!(std::fabs(xq) < 1.0e9))
-          return fail(VP_ERR_ARG, "replica " + std::to_string(r) + ": coordinates must lie within 59 nm of the origin");
+          return fail(VP_ERR_ARG, "replica " + std::to_string(r) + ": coordinates must lie within 238 nm of the origin");
         xh[3 * u + a] = (int32_t)std::llrint(xq);
         if (d.v0) vh[3 * u + a] = (float)d.v0[3 * i + a];
       }

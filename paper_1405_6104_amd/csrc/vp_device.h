@@ -45,7 +45,7 @@ __device__ __forceinline__ float3 noise3(uint64_t seed, uint32_t atom, uint32_t 
 }
 
 // ---------------------------------------------------------------------------
-// Pair membership on fixed-point coordinates (unit 2^-24 nm).  The integer
+// Pair membership on fixed-point coordinates (unit 2^-22 nm).  The integer
 // difference of two images is exact; its single rounding to FP32 and the
 // FMA chain below are the exact operation order the CPU test oracle uses:
 //   d = fl(Xj - Xi - n Lq);  r2 = fma(dz, dz, fma(dy, dy, fl(dx * dx))).

@@ -56,10 +56,14 @@ constexpr int kMaxSoluteLds = 4096;  // solute positions staged in LDS by the Rg
 constexpr double kFixScale = 4294967296.0;  // 2^32: fixed-point force unit
 constexpr double kForceLimit = 1.0e6;       // kJ/mol/nm: above this a replica is unstable
 constexpr double kCoulomb = 138.935458;
-constexpr double kQ = 16777216.0;           // 2^24: coordinate unit is 2^-24 nm
-constexpr float kQf = 16777216.0f;
-constexpr float kInvQf = 5.9604644775390625e-8f;  // 2^-24
-constexpr double kInvQ = 5.9604644775390625e-8;
+// 2^22: coordinate unit is 2^-22 nm.  A coordinate relative to a point within
+// 4 nm (a block's staged neighbourhood around its centre) is an integer below
+// 2^24 and so exact in FP32, and the difference of two such values is an
+// exact FP32 subtraction.
+constexpr double kQ = 4194304.0;
+constexpr float kQf = 4194304.0f;
+constexpr float kInvQf = 2.384185791015625e-7f;  // 2^-22
+constexpr double kInvQ = 2.384185791015625e-7;
 constexpr int kDummyCoord = 1 << 30;  // staged position of the list padding entry
 // Staged places after a block's capacity that hold the inert padding entry:
 // three, so that padding read as a three-atom site stays inert.
@@ -144,7 +148,7 @@ struct BTerm {
 
 // Device buffers of one evaluation context (trajectory or vp_forces).
 struct Work {
-  int4 *xq = nullptr;       // [slots] x, y, z (unwrapped, units of 2^-24 nm), type
+  int4 *xq = nullptr;       // [slots] x, y, z (unwrapped, units of 2^-22 nm), type
   float4 *vel = nullptr;    // [slots] vx, vy, vz, 0
   float4 *integ = nullptr;  // [slots] 1/m, c1, sigma_v, 0
   int32_t *orig = nullptr;  // [slots] replica-local user index or -1
@@ -157,6 +161,7 @@ struct Work {
   int32_t *nblj = nullptr;      // [slots] rows of the list's first stream (LJ partners, chunk_row)
   uint16_t *nblist = nullptr;   // per block: maxnb/8 rows of 8 staged indices per lane, at list_row
   int32_t *stage_n = nullptr;   // [blocks]
+  int4 *bctr = nullptr;         // [blocks] centre of the block's box at the last build (wrapped frame)
   uint32_t *stage = nullptr;    // [blocks][stage_stride] slot | image shifts
   int64_t stage_stride = 0;     // staging entries per block (largest capacity)
   int32_t *cell_start = nullptr;  // [sum ncell + R] fine-cell CSR offsets (replica-local)
@@ -213,7 +218,7 @@ struct vp_system {
   int32_t *tile_first = nullptr;  // [tiles] first slot of each tile
   // constant per-atom data in user order
   int32_t *type0 = nullptr;  // [users] type of each atom
-  float4 *types = nullptr;   // type tables: (q sqrt(f) 2^36, sigma/2 2^24, sqrt(24 eps) 2^24, 0)
+  float4 *types = nullptr;   // type tables: (q sqrt(f) 2^33, sigma/2 2^22, sqrt(24 eps) 2^22, 0)
   float4 *integ0 = nullptr;  // [users]
   double *igm0 = nullptr;    // [users] 1/(gamma m) (solute entries used)
   double *mass0 = nullptr;   // [users] masses

@@ -24,7 +24,7 @@ from paper_1405_6104_amd import synth, vp  # noqa: E402
 pytestmark = pytest.mark.gpu
 
 F_REL, F_MAX, X_TOL, PHI_REL = 1e-5, 1e-4, 1e-4, 1e-4
-GRID = 2.0 ** 24
+GRID = 2.0 ** 22
 COL = {k: i for i, k in enumerate(vp.OBS)}
 E = {k: i for i, k in enumerate(vp.RECORD_COLUMNS)}
 WCOLS = [E[k] for k in ("w_xx", "w_xy", "w_xz", "w_yx", "w_yy", "w_yz", "w_zx", "w_zy", "w_zz")]

@@ -9,7 +9,7 @@ Tolerances (stated per quantity):
   functional            relative 1e-4 (plus 1e-12 absolute)
   dPhi/d(k, rho), force directional derivatives   relative 1e-4
 Both sides start from the generator's inputs; the oracle is evaluated at the
-positions the library holds (FP32 values on its 2^-24 nm grid) for
+positions the library holds (FP32 values on its 2^-22 nm grid) for
 single-frame comparisons.
 """
 import math
@@ -33,12 +33,12 @@ def say(*a):
     print(*a, flush=True)
 
 
-GRID = 2.0 ** 24  # the library holds positions in units of 2^-24 nm
+GRID = 2.0 ** 22  # the library holds positions in units of 2^-22 nm
 
 
 def f32(x):
     """FP32 positions on the library's grid, as float64.  The library rounds
-    every position it receives to the nearest multiple of 2^-24 nm; below
+    every position it receives to the nearest multiple of 2^-22 nm; below
     1 nm that moves an FP32 value by up to 3e-8 nm, which alone changes the
     net forces of stiff water by ~1e-5 relative, so the oracle is given the
     configuration the library evaluates.  The values are exact in FP32, so
@@ -49,7 +49,7 @@ def f32(x):
 
 def x0_of(d):
     """Initial positions of a description as the library holds them (the FP64
-    x0 rounded once to the 2^-24 nm grid)."""
+    x0 rounded once to the 2^-22 nm grid)."""
     return np.rint(np.asarray(d["x0"], np.float64) * GRID) / GRID
 
 

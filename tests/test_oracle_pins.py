@@ -122,9 +122,9 @@ def test_pair_forces_match_finite_differences(oracle_mod):
 # --------------------------------------------------------------- pair sets
 def _numpy_pairs(x, L, rc, excl):
     """Independent vectorised statement of the fixed-point membership
-    predicate: X = round(x 2^24), nearest image in integers, one rounding to
-    FP32, r2 = fma(dz, dz, fma(dy, dy, dx*dx)) < fl32((rc 2^24)^2)."""
-    q = 2.0 ** 24
+    predicate: X = round(x 2^22), nearest image in integers, one rounding to
+    FP32, r2 = fma(dz, dz, fma(dy, dy, dx*dx)) < fl32((rc 2^22)^2)."""
+    q = 2.0 ** 22
     X = np.rint(x * q).astype(np.int64)
     Lq = int(np.rint(L * q))
     n = len(x)

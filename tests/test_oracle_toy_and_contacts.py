@@ -150,7 +150,7 @@ def test_path_similarity_without_ties_is_kendall_concordance(oracle_mod):
 
 def test_native_contacts_and_formation_brute_force(oracle_mod):
     """Native contacts: j - i > min_sep and |X_f,i - X_f,j| <= r0 (squared
-    integer distances on the 2^-24 nm grid); formation at a configuration by
+    integer distances on the 2^-22 nm grid); formation at a configuration by
     the same rule."""
     d = synth.tiny(seed=6)
     o = oracle_mod.Oracle(d)

@@ -16,7 +16,7 @@ from paper_1405_6104_amd import synth, vp  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
-GRID = 2.0 ** 24
+GRID = 2.0 ** 22
 
 
 def positions(reps):
