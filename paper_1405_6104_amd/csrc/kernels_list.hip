@@ -91,8 +91,7 @@ __global__ __launch_bounds__(kBinThreads) void k_bin(const RepInfo *__restrict__
                                                      int32_t *__restrict__ zkey_t,
                                                      int32_t *__restrict__ fcell_t,
                                                      int32_t *__restrict__ bucket_t,
-                                                     int32_t *__restrict__ bkey_t,
-                                                     int32_t *__restrict__ borig_t,
+                                                     int2 *__restrict__ bko_t,
                                                      int32_t *__restrict__ orig_t,
                                                      int32_t *__restrict__ cellpos_t,
                                                      const long long *__restrict__ step) {
@@ -129,6 +128,7 @@ __global__ __launch_bounds__(kBinThreads) void k_bin(const RepInfo *__restrict__
   if (!s_need) return;
   const int off = R.off;
   // ---- keys of every atom (old slot order)
+#pragma unroll 4
   for (int p = tid; p < R.n; p += kBinThreads) {
     int X, Y, Z;
     if (MODE == 0) {
@@ -170,22 +170,25 @@ __global__ __launch_bounds__(kBinThreads) void k_bin(const RepInfo *__restrict__
     const int bk = bkt_t[off + p];
     const int pos = atomicAdd(&s_cnt[bk], 1);
     bucket_t[off + pos] = p;
-    bkey_t[off + pos] = zkey_t[off + p];
-    borig_t[off + pos] = (MODE == 0) ? W.orig[off + p] : p;
+    bko_t[off + pos] = make_int2(zkey_t[off + p], (MODE == 0) ? W.orig[off + p] : p);
   }
   __syncthreads();
   // ---- rank inside a bucket by (z key, user index)
   for (int s = tid; s < R.n; s += kBinThreads) {
     const int p = bucket_t[off + s];
     const int bk = bkt_t[off + p];
-    const int key = bkey_t[off + s], me = borig_t[off + s];
-    int rank = 0;
-    for (int q = s_start[bk]; q < s_start[bk + 1]; ++q) {
-      const int kq = bkey_t[off + q];
-      rank += (kq < key) || (kq == key && borig_t[off + q] < me);
+    const int2 me = bko_t[off + s];
+    auto before = [&](int2 o) { return (o.x < me.x || (o.x == me.x && o.y < me.y)) ? 1 : 0; };
+    // the bucket's entries are independent loads: four in flight at a time
+    int rank = 0, q = s_start[bk];
+    const int qe = s_start[bk + 1];
+    for (; q + 4 <= qe; q += 4) {
+      const int2 o0 = bko_t[off + q], o1 = bko_t[off + q + 1], o2 = bko_t[off + q + 2], o3 = bko_t[off + q + 3];
+      rank += before(o0) + before(o1) + before(o2) + before(o3);
     }
+    for (; q < qe; ++q) rank += before(bko_t[off + q]);
     const int ns = s_start[bk] + rank;
-    orig_t[off + ns] = me;
+    orig_t[off + ns] = me.y;
     W.cell_of[off + ns] = fcell_t[off + p];
   }
   __syncthreads();
@@ -206,8 +209,14 @@ __global__ __launch_bounds__(kBinThreads) void k_bin(const RepInfo *__restrict__
   for (int q = tid; q < R.n; q += kBinThreads) {
     const int s = bucket_t[off + q];
     const int c = W.cell_of[off + s];
-    int rank = 0;
-    for (int t = s_start[c]; t < s_start[c + 1]; ++t) rank += (bucket_t[off + t] < s);
+    int rank = 0, t = s_start[c];
+    const int te = s_start[c + 1];
+    for (; t + 4 <= te; t += 4) {
+      const int b0 = bucket_t[off + t], b1 = bucket_t[off + t + 1], b2 = bucket_t[off + t + 2],
+                b3 = bucket_t[off + t + 3];
+      rank += (b0 < s) + (b1 < s) + (b2 < s) + (b3 < s);
+    }
+    for (; t < te; ++t) rank += (bucket_t[off + t] < s);
     W.cell_slots[off + s_start[c] + rank] = s;
     cellpos_t[off + s] = s_start[c] + rank;
   }
@@ -993,8 +1002,8 @@ static inline int xcd_grid(int nb) { return 8 * ((nb + 7) / 8); }
 void launch_rebuild(vp_system *s, Work &W, int mode, const float *x_user, hipStream_t st) {
   if (mode == 0) {
     hipLaunchKernelGGL(k_bin<0>, dim3(s->R), dim3(kBinThreads), 0, st, s->info, s->state, W,
-                       x_user, s->cellid_t, s->zkey_t, s->fcell_t, s->bucket_t, s->bkey_t,
-                       s->borig_t, s->orig_t, s->cellpos_t, s->step);
+                       x_user, s->cellid_t, s->zkey_t, s->fcell_t, s->bucket_t, s->bko_t,
+                       s->orig_t, s->cellpos_t, s->step);
     hipLaunchKernelGGL(k_permute<0>, dim3(xcd_grid(s->n_tiles)), dim3(kBlock), 0, st, s->info,
                        s->state, W, s->tile_rep, s->tile_first, s->n_tiles, x_user, s->type0, s->role0,
                        s->orig_t, s->xq_t, s->vel_t, s->wrap_t, s->cellpos_t, s->cellx_t,
@@ -1005,8 +1014,8 @@ void launch_rebuild(vp_system *s, Work &W, int mode, const float *x_user, hipStr
                        s->integ0, s->tx_t, s->tv_t, s->inv_t);
   } else {
     hipLaunchKernelGGL(k_bin<1>, dim3(s->R), dim3(kBinThreads), 0, st, s->info, s->state, W,
-                       x_user, s->cellid_t, s->zkey_t, s->fcell_t, s->bucket_t, s->bkey_t,
-                       s->borig_t, s->orig_t, s->cellpos_t, s->step);
+                       x_user, s->cellid_t, s->zkey_t, s->fcell_t, s->bucket_t, s->bko_t,
+                       s->orig_t, s->cellpos_t, s->step);
     hipLaunchKernelGGL(k_permute<1>, dim3(xcd_grid(s->n_tiles)), dim3(kBlock), 0, st, s->info,
                        s->state, W, s->tile_rep, s->tile_first, s->n_tiles, x_user, s->type0, s->role0,
                        s->orig_t, s->xq_t, s->vel_t, s->wrap_t, s->cellpos_t, s->cellx_t,

@@ -717,8 +717,7 @@ static vp_status build(vp_system *s, const vp_replica_desc *reps, int32_t n_reps
   TRY(dalloc(s, &s->zkey_t, S));
   TRY(dalloc(s, &s->fcell_t, S));
   TRY(dalloc(s, &s->bucket_t, S));
-  TRY(dalloc(s, &s->bkey_t, S));
-  TRY(dalloc(s, &s->borig_t, S));
+  TRY(dalloc(s, &s->bko_t, S));
   TRY(dalloc(s, &s->cellpos_t, S));
   TRY(dalloc(s, &s->cellx_t, S));
   TRY(dalloc(s, &s->celljw_t, S));

@@ -245,8 +245,7 @@ struct vp_system {
   int32_t *zkey_t = nullptr;    // [slots] serpentine z key of each old slot
   int32_t *fcell_t = nullptr;   // [slots] fine cell of each old slot
   int32_t *bucket_t = nullptr;  // [slots] old slots grouped by column / new slots by cell
-  int32_t *bkey_t = nullptr;    // [slots] z keys in bucket order
-  int32_t *borig_t = nullptr;   // [slots] user indices in bucket order
+  int2 *bko_t = nullptr;        // [slots] (z key, user index) in bucket order
   int32_t *cellpos_t = nullptr; // [slots] position of each new slot in fine-cell order
   float4 *tx_t = nullptr;       // [2][slots] tangents in the new order (rebuild)
   float4 *tv_t = nullptr;
