@@ -119,6 +119,47 @@ def test_pair_set_exact_solvated(solvated):
     assert_same_pairs(system.debug_pairs(0), want)
 
 
+def _waters_not_consecutive(d):
+    """The same system with its waters' atoms reordered (all oxygens, then
+    all first hydrogens, then all second hydrogens), so that no three
+    consecutive atoms form a water and the library lists every atom alone.
+    Returns the description and new_of_old (old atom index -> new index)."""
+    ns, n = int(d["n_solute"]), int(d["n_atoms"])
+    w = np.arange(ns, n).reshape(-1, 3)
+    old_of_new = np.concatenate([np.arange(ns), w[:, 0], w[:, 1], w[:, 2]])
+    new_of_old = np.empty(n, np.int64)
+    new_of_old[old_of_new] = np.arange(n)
+    e = dict(d)
+    for k in ("mass", "gamma", "charge", "sigma", "epsilon", "x0"):
+        e[k] = np.ascontiguousarray(np.asarray(d[k])[old_of_new])
+    for k in ("bonds", "angles", "excl"):
+        e[k] = np.ascontiguousarray(new_of_old[np.asarray(d[k])].astype(np.int32))
+    return e, new_of_old
+
+
+def test_water_sites_and_single_atom_lists_agree():
+    """Lists that name a water molecule by one entry and lists of single
+    atoms (the same system with its water atoms reordered, so no site is
+    found) hold the same pairs, give the same forces up to the FP32
+    summation order, and the site lists are the shorter ones."""
+    say("pairs/forces: water sites vs single atoms")
+    d = synth.small_chain_system()
+    e, new_of_old = _waters_not_consecutive(d)
+    sa, sb = vp.System([d]), vp.System([e])
+    col = list(vp.OBS).index("list_max")
+    la, lb = sa.observables()[0][col], sb.observables()[0][col]
+    say(f"  longest list: {la:.0f} entries with sites, {lb:.0f} without")
+    assert la < 0.6 * lb
+    pa = new_of_old[np.asarray(sa.debug_pairs(0), np.int64)]
+    assert_same_pairs(pa, np.sort(np.asarray(sb.debug_pairs(0), np.int64), axis=1))
+    x = f32(d["x0"])
+    fa, _ = gpu_forces(sa, [x])
+    fb, _ = gpu_forces(sb, [x[np.argsort(new_of_old)]])
+    rel, mx = force_errors(fa[np.argsort(new_of_old)], fb)
+    say(f"  forces rel {rel:.2e}, max {mx:.2e}")
+    assert rel <= 2e-6 and mx <= 2e-5
+
+
 # ------------------------------------------------------------------ forces
 @pytest.mark.parametrize("name", ["tiny", "small", "tiny_rg", "no_solute"])
 def test_forces_small(name):
