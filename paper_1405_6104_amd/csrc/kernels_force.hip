@@ -15,7 +15,8 @@
 // index order (one wave per force component) and stored as 64-bit fixed
 // point.  Both members of a pair evaluate it (no atomics), and the list order
 // is fixed by the deterministic sort, so results do not depend on
-// scheduling.  Bonded terms are added by k_bonded.
+// scheduling.  Bonded terms are added by k_bonded_forces (one thread per
+// water-like group of three atoms or per other atom with terms).
 //
 // k_cv_pairs / k_cv_reduce / k_cv: collective variable z and dz/dx of the
 // solute (contact map: one wave per 64 x 64 tile of solute pairs, then one
@@ -485,40 +486,160 @@ __device__ __forceinline__ void bonded_term(const BTerm &T, const int4 xi, const
   }
 }
 
-// Terms gathered per pass of k_bonded: their records, partner slots and
-// partner positions are each loaded together, so an atom's terms cost three
-// dependent loads per pass instead of three per term.
+// Terms gathered per pass of a per-atom bonded loop: their records, partner
+// slots and partner positions are each loaded together, so an atom's terms
+// cost three dependent loads per pass instead of three per term.
 constexpr int kBondBatch = 4;
 
+// Threads per workgroup of k_bonded_forces.
+constexpr int kBondedThreads = 256;
+
+// The force of one bonded group's term on its three atoms (f[3 m + k] for
+// atom m, component k), with the arithmetic of bonded_term: a bond as its
+// first atom evaluates it (its partner takes the negated force), an angle as
+// its first end evaluates it (the vertex takes -(ga + gb), the other end gb).
+// Local indices pick values by selects, so nothing is indexed at run time.
+__device__ __forceinline__ void group_term(int code, double k, double r0, const int4 p0, const int4 p1,
+                                           const int4 p2, double (&f)[9]) {
+  const int kind = code & 15, li = (code >> 4) & 15, lc = (code >> 8) & 15, lj = (code >> 12) & 15;
+  auto pick = [&](int m, int a0, int a1, int a2) { return m == 0 ? a0 : (m == 1 ? a1 : a2); };
+  const int ix = pick(li, p0.x, p1.x, p2.x), iy = pick(li, p0.y, p1.y, p2.y), iz = pick(li, p0.z, p1.z, p2.z);
+  const int jx = pick(lj, p0.x, p1.x, p2.x), jy = pick(lj, p0.y, p1.y, p2.y), jz = pick(lj, p0.z, p1.z, p2.z);
+  if (kind == 0) {
+    const double d0 = (double)(jx - ix) * kInvQ, d1 = (double)(jy - iy) * kInvQ, d2 = (double)(jz - iz) * kInvQ;
+    const double rr = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+    const double g = k * (rr - r0) / rr;
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+      const double c = m == li ? g : (m == lj ? -g : 0.0);
+      f[3 * m] = __builtin_fma(c, d0, f[3 * m]);
+      f[3 * m + 1] = __builtin_fma(c, d1, f[3 * m + 1]);
+      f[3 * m + 2] = __builtin_fma(c, d2, f[3 * m + 2]);
+    }
+  } else {
+    const int cx = pick(lc, p0.x, p1.x, p2.x), cy = pick(lc, p0.y, p1.y, p2.y), cz = pick(lc, p0.z, p1.z, p2.z);
+    const double u0 = (double)(ix - cx) * kInvQ, u1 = (double)(iy - cy) * kInvQ, u2 = (double)(iz - cz) * kInvQ;
+    const double w0 = (double)(jx - cx) * kInvQ, w1 = (double)(jy - cy) * kInvQ, w2 = (double)(jz - cz) * kInvQ;
+    const double uu = u0 * u0 + u1 * u1 + u2 * u2, ww = w0 * w0 + w1 * w1 + w2 * w2;
+    const double uw = u0 * w0 + u1 * w1 + u2 * w2;
+    const double inn = 1.0 / sqrt(uu * ww), iuu = 1.0 / uu, iww = 1.0 / ww;
+    double cs = uw * inn;
+    cs = cs > 1.0 ? 1.0 : (cs < -1.0 ? -1.0 : cs);
+    const double th = acos(cs);
+    double sn = sqrt(1.0 - cs * cs);
+    sn = sn < 1e-12 ? 1e-12 : sn;
+    const double dv = k * (th - r0) / sn;
+    const double ga0 = w0 * inn - cs * u0 * iuu, ga1 = w1 * inn - cs * u1 * iuu, ga2 = w2 * inn - cs * u2 * iuu;
+    const double gb0 = u0 * inn - cs * w0 * iww, gb1 = u1 * inn - cs * w1 * iww, gb2 = u2 * inn - cs * w2 * iww;
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+      const bool a = m == li, bb = m == lj;
+      f[3 * m] = __builtin_fma(dv, a ? ga0 : (bb ? gb0 : -(ga0 + gb0)), f[3 * m]);
+      f[3 * m + 1] = __builtin_fma(dv, a ? ga1 : (bb ? gb1 : -(ga1 + gb1)), f[3 * m + 1]);
+      f[3 * m + 2] = __builtin_fma(dv, a ? ga2 : (bb ? gb2 : -(ga2 + gb2)), f[3 * m + 2]);
+    }
+  }
+}
+
 // Bonded forces (harmonic bonds and angles, FP64 on the exact integer
-// separations), one thread per atom, added to the fixed-point forces the pair
-// kernel stored: every atom evaluates the terms it belongs to (an angle by its
-// two ends and its vertex), so each force is written by its own thread.
-// Threads take atoms in their original order (block b, lane l: atom 64 b + l
-// of the replica), so the term ranges and records are read coalesced and the
-// atom's slot comes from one lookup.  Separate from k_forces so that these dependent
-// gathers and long FP64 chains run over the whole chip instead of on one wave
-// of each pair block.  ENERGY (k_bonded_energy): no forces are stored; the
-// block's bond and angle energies and the virial sum_i x_i (x) F_i^bonded go to
-// W.epart[b][2, 3] and [b][kEpBondW .. +9) (each term's forces sum to zero, so
-// this equals the sum over terms of (x_i - x_ref) (x) F_i).  GATED: as in
-// k_pair_energy.
-template <bool ENERGY, bool GATED>
-__global__ __launch_bounds__(kBlk) void k_bonded(const RepInfo *__restrict__ info, Work W,
-                                                 const int32_t *__restrict__ tile_rep,
-                                                 const int32_t *__restrict__ tile_first, int nblk,
-                                                 const int32_t *__restrict__ bt_start,
-                                                 const BTerm *__restrict__ bterms,
-                                                 const long long *__restrict__ step, int nst_out) {
+// separations) added to the fixed-point forces the pair kernel stored.  The
+// first nwa workgroups (after the XCD deal) take the atoms outside bonded
+// groups that have terms, one atom per thread, which evaluates every term it
+// belongs to (an angle by its two ends and its vertex), kBondBatch terms per
+// pass; the next nwg take the bonded groups, one group per thread, whose
+// terms are evaluated once and whose three atoms' forces it stores.  Every
+// atom's force is thus written by one thread, and each atom sums its terms in
+// the order of its own term list, as the energy kernel below does.  Both
+// ranges are dealt to the XCDs in contiguous pieces (atoms and groups are in
+// replica order), so each XCD's L2 holds the forces and positions of a few
+// replicas; the atoms' longer dependent chains start first.
+__global__ __launch_bounds__(kBondedThreads) void k_bonded_forces(Work W, const int32_t *__restrict__ atoms,
+                                                                  const int32_t *__restrict__ start,
+                                                                  const BTerm *__restrict__ terms, int na,
+                                                                  int nwa, const BGroup *__restrict__ groups,
+                                                                  int ng, int nwg) {
+  const int nba = 8 * ((nwa + 7) / 8);
+  if ((int)blockIdx.x >= nba) {
+    const int wg = xcd_tile((int)blockIdx.x - nba, nwg);
+    if (wg < 0) return;
+    const int t = wg * kBondedThreads + threadIdx.x;
+    if (t >= ng) return;
+    const BGroup G = groups[t];
+    const int s0 = W.inv[G.ga], s1 = W.inv[G.ga + 1], s2 = W.inv[G.ga + 2];
+    const int4 p0 = W.xq[s0], p1 = W.xq[s1], p2 = W.xq[s2];
+    double f[9] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int q = 0; q < kGroupTerms; ++q) group_term(G.code[q], G.k[q], G.r0[q], p0, p1, p2, f);
+    const int64_t fs = W.fstride;
+    W.F[s0] += to_fix(f[0]);
+    W.F[fs + s0] += to_fix(f[1]);
+    W.F[2 * fs + s0] += to_fix(f[2]);
+    W.F[s1] += to_fix(f[3]);
+    W.F[fs + s1] += to_fix(f[4]);
+    W.F[2 * fs + s1] += to_fix(f[5]);
+    W.F[s2] += to_fix(f[6]);
+    W.F[fs + s2] += to_fix(f[7]);
+    W.F[2 * fs + s2] += to_fix(f[8]);
+    return;
+  }
+  const int wg = xcd_tile((int)blockIdx.x, nwa);
+  if (wg < 0) return;
+  const int k = wg * kBondedThreads + threadIdx.x;
+  if (k >= na) return;
+  const int ga = atoms[k];
+  const int slot = W.inv[ga];
+  const int4 xi = W.xq[slot];
+  double bx = 0.0, by = 0.0, bz = 0.0, ebond = 0.0, eangle = 0.0;
+  const int t0 = start[k], t1 = start[k + 1];
+  for (int u0 = t0; u0 < t1; u0 += kBondBatch) {
+    BTerm T[kBondBatch];
+#pragma unroll
+    for (int u = 0; u < kBondBatch; ++u) T[u] = terms[min(u0 + u, t1 - 1)];
+    int q1[kBondBatch], q2[kBondBatch];
+#pragma unroll
+    for (int u = 0; u < kBondBatch; ++u) {
+      q1[u] = W.inv[T[u].a];
+      q2[u] = W.inv[T[u].kind == 0 ? T[u].a : T[u].b];
+    }
+    int4 x1[kBondBatch], x2[kBondBatch];
+#pragma unroll
+    for (int u = 0; u < kBondBatch; ++u) {
+      x1[u] = W.xq[q1[u]];
+      x2[u] = W.xq[q2[u]];
+    }
+#pragma unroll
+    for (int u = 0; u < kBondBatch; ++u)
+      if (u0 + u < t1) bonded_term<false>(T[u], xi, x1[u], x2[u], bx, by, bz, ebond, eangle);
+  }
+  W.F[slot] += to_fix(bx);
+  W.F[W.fstride + slot] += to_fix(by);
+  W.F[2 * W.fstride + slot] += to_fix(bz);
+}
+
+// Bonded energies and virial (no forces), one thread per atom: every atom
+// evaluates the terms it belongs to; the block's bond and angle energies and
+// the virial sum_i x_i (x) F_i^bonded go to W.epart[b][2, 3] and
+// [b][kEpBondW .. +9) (each term's forces sum to zero, so this equals the sum
+// over terms of (x_i - x_ref) (x) F_i).  Threads take atoms in their original
+// order (block b, lane l: atom 64 b + l of the replica), so the term ranges
+// and records are read coalesced and the atom's slot comes from one lookup.
+// GATED: as in k_pair_energy.
+template <bool GATED>
+__global__ __launch_bounds__(kBlk) void k_bonded_energy(const RepInfo *__restrict__ info, Work W,
+                                                        const int32_t *__restrict__ tile_rep,
+                                                        const int32_t *__restrict__ tile_first, int nblk,
+                                                        const int32_t *__restrict__ bt_start,
+                                                        const BTerm *__restrict__ bterms,
+                                                        const long long *__restrict__ step, int nst_out) {
   if (GATED && (*step + 1) % nst_out != 0) return;
   const int b = xcd_tile(blockIdx.x, nblk);
   if (b < 0) return;
   const int tile = b / (kTile / kBlk);
   const RepInfo &R = info[tile_rep[tile]];
   const int p0 = tile_first[tile] + (b % (kTile / kBlk)) * kBlk;
-  if (p0 >= R.n) {  // padding block: the pair kernel zeroed its forces
-    if (ENERGY && threadIdx.x < 2) W.epart[kEp * (size_t)b + 2 + threadIdx.x] = 0.0;
-    if (ENERGY && threadIdx.x < 9) W.epart[kEp * (size_t)b + kEpBondW + threadIdx.x] = 0.0;
+  if (p0 >= R.n) {  // padding block
+    if (threadIdx.x < 2) W.epart[kEp * (size_t)b + 2 + threadIdx.x] = 0.0;
+    if (threadIdx.x < 9) W.epart[kEp * (size_t)b + kEpBondW + threadIdx.x] = 0.0;
     return;
   }
   const int lane = threadIdx.x;
@@ -550,30 +671,21 @@ __global__ __launch_bounds__(kBlk) void k_bonded(const RepInfo *__restrict__ inf
       }
 #pragma unroll
       for (int u = 0; u < kBondBatch; ++u)
-        if (t + u < t1) bonded_term<ENERGY>(T[u], xi, p1[u], p2[u], bx, by, bz, ebond, eangle);
+        if (t + u < t1) bonded_term<true>(T[u], xi, p1[u], p2[u], bx, by, bz, ebond, eangle);
     }
-    if (!ENERGY && t1 > t0) {
-      W.F[slot] += to_fix(bx);
-      W.F[W.fstride + slot] += to_fix(by);
-      W.F[2 * W.fstride + slot] += to_fix(bz);
-    }
-    if (ENERGY) {
-      const double x[3] = {(double)xi.x * kInvQ, (double)xi.y * kInvQ, (double)xi.z * kInvQ};
-      const double f[3] = {bx, by, bz};
-      for (int u = 0; u < 3; ++u)
-        for (int v = 0; v < 3; ++v) vir[3 * u + v] = x[u] * f[v];
-    }
+    const double x[3] = {(double)xi.x * kInvQ, (double)xi.y * kInvQ, (double)xi.z * kInvQ};
+    const double f[3] = {bx, by, bz};
+    for (int u = 0; u < 3; ++u)
+      for (int v = 0; v < 3; ++v) vir[3 * u + v] = x[u] * f[v];
   }
-  if (ENERGY) {
-    const double v2 = wave_sum(ebond), v3 = wave_sum(eangle);
-    double w[9];
-    for (int k = 0; k < 9; ++k) w[k] = wave_sum(vir[k]);
-    if (lane == 0) {
-      double *e = W.epart + kEp * (size_t)b;
-      e[2] = v2;
-      e[3] = v3;
-      for (int k = 0; k < 9; ++k) e[kEpBondW + k] = w[k];
-    }
+  const double v2 = wave_sum(ebond), v3 = wave_sum(eangle);
+  double w[9];
+  for (int k = 0; k < 9; ++k) w[k] = wave_sum(vir[k]);
+  if (lane == 0) {
+    double *e = W.epart + kEp * (size_t)b;
+    e[2] = v2;
+    e[3] = v3;
+    for (int k = 0; k < 9; ++k) e[kEpBondW + k] = w[k];
   }
 }
 
@@ -706,7 +818,8 @@ __global__ __launch_bounds__(kForceThreads) void k_tangent_forces(
 // Bonded part of the tangent forces (one direction per launch): the FP64
 // bonds and angles of each atom differentiated along the tangent on dual
 // numbers, one thread per atom, added to the pair part k_tangent_forces
-// stored (separate for the same reason as k_bonded).
+// stored (separate so that its dependent gathers and FP64 chains run over the
+// whole chip instead of on one wave of each pair block).
 __global__ __launch_bounds__(kBlk) void k_tangent_bonded(const RepInfo *__restrict__ info, Work W,
                                                          const int32_t *__restrict__ tile_rep,
                                                          const int32_t *__restrict__ tile_first, int nblk,
@@ -716,7 +829,7 @@ __global__ __launch_bounds__(kBlk) void k_tangent_bonded(const RepInfo *__restri
   if (b < 0) return;
   const int tile = b / (kTile / kBlk);
   const RepInfo &R = info[tile_rep[tile]];
-  // atoms in their original order, as in k_bonded
+  // atoms in their original order, as in k_bonded_energy
   const int a = tile_first[tile] + (b % (kTile / kBlk)) * kBlk + (int)threadIdx.x;
   if (a >= R.n) return;
   const int slot = W.inv[R.uoff + a];
@@ -1376,8 +1489,11 @@ void launch_pair_forces(vp_system *s, Work &W, hipStream_t st) {
 }
 
 void launch_bonded(vp_system *s, Work &W, hipStream_t st) {
-  hipLaunchKernelGGL((k_bonded<false, false>), dim3(xcd_grid(s->n_blocks)), dim3(kBlk), 0, st, s->info, W,
-                     s->tile_rep, s->tile_first, s->n_blocks, s->bt_start, s->bterms, s->step, 1);
+  const int nwa = (s->n_bf_atoms + kBondedThreads - 1) / kBondedThreads;
+  const int nwg = (s->n_bgroups + kBondedThreads - 1) / kBondedThreads;
+  if (nwa + nwg == 0) return;
+  hipLaunchKernelGGL(k_bonded_forces, dim3(xcd_grid(nwa) + xcd_grid(nwg)), dim3(kBondedThreads), 0, st, W,
+                     s->bf_atoms, s->bf_start, s->bf_terms, s->n_bf_atoms, nwa, s->bgroups, s->n_bgroups, nwg);
 }
 
 void launch_forces(vp_system *s, Work &W, hipStream_t st) {
@@ -1392,13 +1508,13 @@ void launch_energies(vp_system *s, Work &W, bool gated, hipStream_t st) {
     hipLaunchKernelGGL(k_pair_energy<true>, dim3(xcd_grid(s->n_blocks)), dim3(kForceThreads), lds, st,
                        s->info, W, s->tile_rep, s->tile_first, s->n_blocks, s->types, s->stage_cap_max + kStageDummies,
                        s->step, nout);
-    hipLaunchKernelGGL((k_bonded<true, true>), dim3(xcd_grid(s->n_blocks)), dim3(kBlk), 0, st, s->info, W,
+    hipLaunchKernelGGL((k_bonded_energy<true>), dim3(xcd_grid(s->n_blocks)), dim3(kBlk), 0, st, s->info, W,
                        s->tile_rep, s->tile_first, s->n_blocks, s->bt_start, s->bterms, s->step, nout);
   } else {
     hipLaunchKernelGGL(k_pair_energy<false>, dim3(xcd_grid(s->n_blocks)), dim3(kForceThreads), lds, st,
                        s->info, W, s->tile_rep, s->tile_first, s->n_blocks, s->types, s->stage_cap_max + kStageDummies,
                        s->step, nout);
-    hipLaunchKernelGGL((k_bonded<true, false>), dim3(xcd_grid(s->n_blocks)), dim3(kBlk), 0, st, s->info, W,
+    hipLaunchKernelGGL((k_bonded_energy<false>), dim3(xcd_grid(s->n_blocks)), dim3(kBlk), 0, st, s->info, W,
                        s->tile_rep, s->tile_first, s->n_blocks, s->bt_start, s->bterms, s->step, nout);
   }
 }

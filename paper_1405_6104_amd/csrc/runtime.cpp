@@ -611,14 +611,15 @@ static vp_status build(vp_system *s, const vp_replica_desc *reps, int32_t n_reps
     has_v[r] = d.v0 ? 1 : 0;
     for (int b = 0; b < d.n_bonds; ++b) {
       int i = d.bonds[2 * b], j = d.bonds[2 * b + 1];
-      terms[R.uoff + i].push_back({0, j, 0, 0, d.bond_k[b], d.bond_r0[b]});
-      terms[R.uoff + j].push_back({0, i, 0, 0, d.bond_k[b], d.bond_r0[b]});
+      terms[R.uoff + i].push_back({0, j, 0, b, d.bond_k[b], d.bond_r0[b]});
+      terms[R.uoff + j].push_back({0, i, 0, b, d.bond_k[b], d.bond_r0[b]});
     }
     for (int b = 0; b < d.n_angles; ++b) {
       int i = d.angles[3 * b], c = d.angles[3 * b + 1], j = d.angles[3 * b + 2];
-      terms[R.uoff + i].push_back({1, c, j, 0, d.angle_k[b], d.angle_theta0[b]});
-      terms[R.uoff + j].push_back({1, c, i, 0, d.angle_k[b], d.angle_theta0[b]});
-      terms[R.uoff + c].push_back({2, i, j, 0, d.angle_k[b], d.angle_theta0[b]});
+      const int ord = d.n_bonds + b;
+      terms[R.uoff + i].push_back({1, c, j, ord, d.angle_k[b], d.angle_theta0[b]});
+      terms[R.uoff + j].push_back({1, c, i, ord, d.angle_k[b], d.angle_theta0[b]});
+      terms[R.uoff + c].push_back({2, i, j, ord, d.angle_k[b], d.angle_theta0[b]});
     }
     for (int e = 0; e < d.n_excl; ++e) {
       int i = d.excl[2 * e], j = d.excl[2 * e + 1];
@@ -670,6 +671,75 @@ static vp_status build(vp_system *s, const vp_replica_desc *reps, int32_t n_reps
     }
   }
 
+  // Force-only bonded tables.  Bonded groups: three consecutive atoms i, i+1,
+  // i+2 of a replica, each with terms only among the three and at most
+  // kGroupTerms terms in all (water molecules); each group's terms are
+  // evaluated once.  Every other atom with terms keeps its own term list,
+  // partners renumbered to global user indices.
+  std::vector<BGroup> bgroups;
+  std::vector<int32_t> bf_atoms, bf_start;
+  std::vector<BTerm> bf_terms;
+  for (int r = 0; r < n_reps; ++r) {
+    const vp_replica_desc &d = reps[r];
+    const int32_t uoff = s->info_h[r].uoff;
+    auto inside = [&](int i, int v) { return v >= i && v < i + 3; };
+    auto closed = [&](int i) {  // every term of atoms i..i+2 lies among them
+      if (i + 2 >= d.n_atoms) return false;
+      for (int m = 0; m < 3; ++m)
+        for (const BTerm &T : terms[(size_t)uoff + i + m])
+          if (!inside(i, T.a) || (T.kind != 0 && !inside(i, T.b))) return false;
+      return true;
+    };
+    for (int i = 0; i < d.n_atoms;) {
+      if (closed(i)) {
+        // the group's distinct terms (by their place in the description), in order
+        std::vector<const BTerm *> tl;
+        for (int m = 0; m < 3; ++m)
+          for (const BTerm &T : terms[(size_t)uoff + i + m])
+            if (std::none_of(tl.begin(), tl.end(), [&](const BTerm *x) { return x->order == T.order; }))
+              tl.push_back(&T);
+        std::sort(tl.begin(), tl.end(), [](const BTerm *x, const BTerm *y) { return x->order < y->order; });
+        if (!tl.empty() && (int)tl.size() <= kGroupTerms) {
+          BGroup G{};
+          G.ga = uoff + i;
+          for (int t = 0; t < kGroupTerms; ++t) {
+            if (t < (int)tl.size()) {
+              const int ord = tl[t]->order;
+              if (ord < d.n_bonds) {  // bond i--j as the description names it
+                G.code[t] = 0 | (d.bonds[2 * ord] - i) << 4 | (d.bonds[2 * ord + 1] - i) << 12;
+              } else {  // angle i--c--j as the description names it
+                const int q = ord - d.n_bonds;
+                G.code[t] = 1 | (d.angles[3 * q] - i) << 4 | (d.angles[3 * q + 1] - i) << 8 |
+                            (d.angles[3 * q + 2] - i) << 12;
+              }
+              G.k[t] = tl[t]->k;
+              G.r0[t] = tl[t]->r0;
+            } else {
+              G.code[t] = 0 | 0 << 4 | 1 << 12;  // bond 0--1 with k = 0
+            }
+          }
+          bgroups.push_back(G);
+          i += 3;
+          continue;
+        }
+      }
+      const size_t u = (size_t)uoff + i;
+      if (!terms[u].empty()) {
+        bf_atoms.push_back((int32_t)u);
+        bf_start.push_back((int32_t)bf_terms.size());
+        for (BTerm T : terms[u]) {
+          T.a += uoff;
+          if (T.kind != 0) T.b += uoff;
+          bf_terms.push_back(T);
+        }
+      }
+      ++i;
+    }
+  }
+  bf_start.push_back((int32_t)bf_terms.size());
+  s->n_bgroups = (int32_t)bgroups.size();
+  s->n_bf_atoms = (int32_t)bf_atoms.size();
+
   // ---------------- device allocations and uploads
   TRY(upload(s, &s->info, s->info_h));
   std::vector<RepState> st(n_reps);
@@ -687,6 +757,10 @@ static vp_status build(vp_system *s, const vp_replica_desc *reps, int32_t n_reps
   TRY(upload(s, &s->mass0, mass0));
   TRY(upload(s, &s->bt_start, bt_start));
   TRY(upload(s, &s->bterms, bterms));
+  TRY(upload(s, &s->bgroups, bgroups));
+  TRY(upload(s, &s->bf_atoms, bf_atoms));
+  TRY(upload(s, &s->bf_start, bf_start));
+  TRY(upload(s, &s->bf_terms, bf_terms));
   TRY(upload(s, &s->ex_start, ex_start));
   TRY(upload(s, &s->ex_list, ex_list));
   TRY(upload(s, &s->role0, role0));

@@ -142,8 +142,22 @@ struct RepState {
 struct BTerm {
   int32_t kind;  // 0: bond to a; 1: angle end (vertex a, other end b); 2: angle vertex (ends a, b)
   int32_t a, b;
-  int32_t pad;
+  int32_t order;  // host only: the term's place in the description (bonds, then angles)
   double k, r0;
+};
+
+// A bonded group: three consecutive atoms of a replica whose bonds and angles
+// all lie among themselves (a water molecule), at most kGroupTerms of them,
+// evaluated once by one thread.  Term t: code[t] = kind | i << 4 | c << 8 |
+// j << 12 with local atom indices 0..2 (kind 0: bond i--j; kind 1: angle
+// i--c--j, vertex c); unused terms are bonds 0--1 with k = 0.  Terms are in
+// the description's order, so each atom sums its forces in the order its
+// own term list holds them.
+constexpr int kGroupTerms = 3;
+struct alignas(16) BGroup {
+  int32_t ga;                  // global user index of the first atom
+  int32_t code[kGroupTerms];
+  double k[kGroupTerms], r0[kGroupTerms];
 };
 
 // Device buffers of one evaluation context (trajectory or vp_forces).
@@ -223,7 +237,15 @@ struct vp_system {
   double *igm0 = nullptr;    // [users] 1/(gamma m) (solute entries used)
   double *mass0 = nullptr;   // [users] masses
   int32_t *bt_start = nullptr;  // [users + 1]
-  vp::BTerm *bterms = nullptr;
+  vp::BTerm *bterms = nullptr;  // partners as replica-local user indices
+  // force-only bonded tables: the groups, then the other atoms with terms
+  // (global user indices, partners global too)
+  vp::BGroup *bgroups = nullptr;
+  int32_t n_bgroups = 0;
+  int32_t *bf_atoms = nullptr;   // [n_bf_atoms]
+  int32_t *bf_start = nullptr;   // [n_bf_atoms + 1]
+  vp::BTerm *bf_terms = nullptr;
+  int32_t n_bf_atoms = 0;
   int32_t *ex_start = nullptr;  // [users + 1]
   int32_t *ex_list = nullptr;   // replica-local user indices
   int32_t *role0 = nullptr;     // [users] 0: listed alone, 1: first atom of a three-atom site, 2: other site atom

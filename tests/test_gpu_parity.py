@@ -184,6 +184,54 @@ def test_forces_small(name):
         assert abs(e[0, col] - terms[k]) <= 2e-5 * scale + 1e-9, (k, e[0, col], terms[k])
 
 
+def test_bonded_groups_of_every_form():
+    """Water molecules whose bonded terms take every form a three-atom group
+    can hold, against the oracle: as generated (two bonds and the angle), bonds
+    and angle written from the other end, no angle, the angle alone, and an
+    extra H-H bond (four terms: evaluated per atom instead)."""
+    say("forces: bonded groups of every form")
+    d = dict(synth.small_chain_system())
+    ns, n = int(d["n_solute"]), int(d["n_atoms"])
+    bonds = [tuple(b) for b in np.asarray(d["bonds"]) if b[0] < ns]
+    bk = [k for b, k in zip(np.asarray(d["bonds"]), d["bond_k"]) if b[0] < ns]
+    br = [r for b, r in zip(np.asarray(d["bonds"]), d["bond_r0"]) if b[0] < ns]
+    angles = [tuple(a) for a in np.asarray(d["angles"]) if a[0] < ns]
+    ak = [k for a, k in zip(np.asarray(d["angles"]), d["angle_k"]) if a[0] < ns]
+    at = [t for a, t in zip(np.asarray(d["angles"]), d["angle_theta0"]) if a[0] < ns]
+    wb = {(int(b[0]), int(b[1])): (k, r) for b, k, r in zip(np.asarray(d["bonds"]), d["bond_k"], d["bond_r0"])
+          if b[0] >= ns}
+    wa = {int(a[1]): (k, t) for a, k, t in zip(np.asarray(d["angles"]), d["angle_k"], d["angle_theta0"])
+          if a[1] >= ns}
+    for w, o in enumerate(range(ns, n, 3)):
+        h1, h2 = o + 1, o + 2
+        (k1, r1), (k2, r2) = wb[(o, h1)], wb[(o, h2)]
+        ka, ta = wa[o]
+        form = w % 5
+        if form in (0, 2, 3):
+            bonds += [(o, h1), (o, h2)]; bk += [k1, k2]; br += [r1, r2]
+        elif form == 1:
+            bonds += [(h2, o), (h1, o)]; bk += [k2, k1]; br += [r2, r1]
+        if form == 3:
+            bonds.append((h1, h2)); bk.append(0.5 * k1); br.append(0.15)
+        if form in (0, 3, 4):
+            angles.append((h1, o, h2)); ak.append(ka); at.append(ta)
+        elif form == 1:
+            angles.append((h2, o, h1)); ak.append(ka); at.append(ta)
+    d.update(bonds=np.asarray(bonds, np.int32), bond_k=np.asarray(bk), bond_r0=np.asarray(br),
+             angles=np.asarray(angles, np.int32), angle_k=np.asarray(ak), angle_theta0=np.asarray(at))
+    system = vp.System([d])
+    # off the generated equilibrium geometry, so every bonded term carries force
+    x = f32(np.asarray(d["x0"]) + np.random.default_rng(11).normal(0.0, 0.005, (n, 3)))
+    fg, e = gpu_forces(system, [x], 0.0)
+    o = O.Oracle(d)
+    fo, _, terms = o.forces(x, 0.0, o.init(x))
+    rel, mx = force_errors(fg, fo)
+    say(f"  rel {rel:.2e} max {mx:.2e}; bond {terms['e_bond']:.3f} angle {terms['e_angle']:.3f}")
+    assert rel <= F_REL and mx <= F_MAX
+    for k, col in (("e_bond", 2), ("e_angle", 3)):
+        assert abs(e[0, col] - terms[k]) <= 2e-5 * max(1.0, abs(terms["e_lj"])), (k, e[0, col], terms[k])
+
+
 def test_forces_solvated_frame(solvated):
     say("forces: solvated frame")
     system = vp.System([solvated])
