@@ -1094,9 +1094,13 @@ __global__ __launch_bounds__(kCvTile) void k_cv_tangent_pairs(const RepInfo *__r
 // in order, sum_i |dz/dx_i|^2/(gamma_i m_i) and the tile's part of z.
 // With TAN, also the tangents: (d grad z)[xi_p] summed over the column tiles,
 // dz/dtheta_p = sum_i g_i . xi_p,i and sum_i 2 g_i . (d g_i)[xi_p] / (gamma_i m_i).
+// When every replica carries a contact-map bias k_cv is not launched, and this
+// kernel advances the step counter instead (inc_step; no block reads it).
 template <bool TAN>
 __global__ __launch_bounds__(kCvTile) void k_cv_reduce(const RepInfo *__restrict__ info, Work W,
-                                                       const double *__restrict__ igm0) {
+                                                       const double *__restrict__ igm0, int inc_step,
+                                                       long long *__restrict__ step) {
+  if (inc_step && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *step += 1;
   const int r = blockIdx.y;
   const RepInfo &R = info[r];
   if (R.bias != VP_BIAS_CONTACT && R.bias != VP_BIAS_RMD_CONTACT) return;
@@ -1521,25 +1525,32 @@ void launch_energies(vp_system *s, Work &W, bool gated, hipStream_t st) {
 
 void launch_cv(vp_system *s, Work &W, int inc_step, hipStream_t st, bool tan) {
   int nt = 0, nsmax = 1;
-  bool any_single = false;
+  bool any_single = false, any_other = false;
   for (const RepInfo &R : s->info_h) {
     if (R.bias == VP_BIAS_CONTACT || R.bias == VP_BIAS_RMD_CONTACT) {
       nt = R.cv_blocks > nt ? R.cv_blocks : nt;
     } else {
+      any_other = true;
       any_single = any_single || R.bias == VP_BIAS_RG;
       if (R.bias == VP_BIAS_RG) nsmax = R.ns > nsmax ? R.ns : nsmax;
     }
   }
+  // k_cv handles the other kinds and advances the step counter; with contact
+  // maps alone, k_cv_reduce advances it and k_cv is not needed
+  const int reduce_inc = any_other ? 0 : inc_step;
   if (nt > 0) {
     hipLaunchKernelGGL(k_cv_pairs, dim3(nt * nt, s->R), dim3(kCvTile), 0, st, s->info, W, s->cmap);
     if (tan) {
       hipLaunchKernelGGL(k_cv_tangent_pairs, dim3(nt * nt, s->R), dim3(kCvTile), 0, st, s->info, W,
                          s->cmap);
-      hipLaunchKernelGGL(k_cv_reduce<true>, dim3(nt, s->R), dim3(kCvTile), 0, st, s->info, W, s->igm0);
+      hipLaunchKernelGGL(k_cv_reduce<true>, dim3(nt, s->R), dim3(kCvTile), 0, st, s->info, W, s->igm0,
+                         reduce_inc, s->step);
     } else {
-      hipLaunchKernelGGL(k_cv_reduce<false>, dim3(nt, s->R), dim3(kCvTile), 0, st, s->info, W, s->igm0);
+      hipLaunchKernelGGL(k_cv_reduce<false>, dim3(nt, s->R), dim3(kCvTile), 0, st, s->info, W, s->igm0,
+                         reduce_inc, s->step);
     }
   }
+  if (!any_other && nt > 0) return;
   size_t lds = any_single ? sizeof(int4) * (size_t)nsmax : 0;
   hipLaunchKernelGGL(k_cv, dim3(s->R), dim3(kCvBlock), lds, st, s->info, W, s->igm0, s->mass0,
                      s->cforce, inc_step, s->step, tan ? 1 : 0);
