@@ -908,16 +908,47 @@ __global__ __launch_bounds__(kBlk) void k_tangent_bonded(const RepInfo *__restri
 // collective variable of the bias
 // ---------------------------------------------------------------------------
 
+// The switched contact function C~ = C(u) sw(r), u = (r/r0)^2, and (dC~/dr)/r
+// at squared distance r2 (nm^2), in FP32.
+__device__ __forceinline__ void contact_tilde(float r2, float ir02, float iw, float rs, float rs2, float rc2,
+                                              float &ct, float &dct_r) {
+  const float rinv = __builtin_amdgcn_rsqf(r2);
+  // C(u) and dC/du
+  const float u = r2 * ir02, u2 = u * u;
+  const float num = 1.0f + u + u2;
+  const float den = num + u2 * u + u2 * u2;
+  const float iden = __builtin_amdgcn_rcpf(den);
+  const float c = num * iden;
+  const float dnum = __builtin_fmaf(2.0f, u, 1.0f);
+  const float dden = dnum + u2 * __builtin_fmaf(4.0f, u, 3.0f);
+  const float dcdu = (dnum - c * dden) * iden;
+  // quintic switch on r
+  const float rr = r2 * rinv;
+  const float t = (rr - rs) * iw;
+  const float t2 = t * t;
+  const float swp = 1.0f - t2 * t * __builtin_fmaf(t, __builtin_fmaf(6.0f, t, -15.0f), 10.0f);
+  const float dswp = -30.0f * t2 * (1.0f - t) * (1.0f - t) * iw;
+  const bool inner = r2 <= rs2, outer = r2 >= rc2;
+  const float sw = inner ? 1.0f : (outer ? 0.0f : swp);
+  const float dsw = (inner || outer) ? 0.0f : dswp;
+  ct = c * sw;
+  dct_r = 2.0f * ir02 * dcdu * sw + c * dsw * rinv;
+}
+
 // Contact-map CV (supplement, "Collective coordinate"), one wave per tile of
 // 64 rows i x 64 columns j of one replica's solute:
 //   z = sum_{i<j, j-i>min_sep} (C~(r_ij) - C~f_ij)^2,
 //   dz/dx_i = -sum_j 2 (C~(r_ij) - C~f_ij) (dC~/dr)/r (x_j - x_i),
 // with C = (1+u+u^2)/(1+u+u^2+u^3+u^4), u = (r/r0)^2, times a quintic switch
-// from 1 at r_s to 0 at r_c.  Both orderings of a pair are visited, each
-// contributing to its own row's gradient; z takes the pairs j > i.  The
-// column-tile partials are reduced in a fixed order by k_cv_reduce.
+// from 1 at r_s to 0 at r_c.  A tile above the diagonal evaluates each of its
+// pairs once and stores the row sums and the column sums (as the partials the
+// mirrored tile below the diagonal would give); a diagonal tile visits both
+// orderings of each pair, each contributing to its own row's gradient, and z
+// takes its pairs j > i.  The column-tile partials are reduced in a fixed
+// order by k_cv_reduce.
 __global__ __launch_bounds__(kCvTile) void k_cv_pairs(const RepInfo *__restrict__ info, Work W,
-                                                      const float *__restrict__ cmap) {
+                                                      const float *__restrict__ cmap,
+                                                      const float *__restrict__ cskew) {
   __shared__ int4 s_x[kCvTile];
   const int r = blockIdx.y;
   const RepInfo &R = info[r];
@@ -926,17 +957,66 @@ __global__ __launch_bounds__(kCvTile) void k_cv_pairs(const RepInfo *__restrict_
   if ((int)blockIdx.x >= nt * nt) return;
   const int it = blockIdx.x / nt, jc = blockIdx.x % nt;
   const int lane = threadIdx.x, ns = R.ns;
+  if (jc < it) {  // these pairs are evaluated once, by the tile (jc, it) above the diagonal
+    if (lane == 0) W.ztile[R.cvt_off + (int64_t)it * nt + jc] = 0.0;
+    return;
+  }
   const int i = it * kCvTile + lane;
   const int j0 = jc * kCvTile, jn = min(kCvTile, ns - j0);
-  if (lane < jn) s_x[lane] = W.xq[W.inv[R.uoff + j0 + lane]];
+  s_x[lane] = lane < jn ? W.xq[W.inv[R.uoff + j0 + lane]] : make_int4(0, 0, 0, 0);
   const bool row = i < ns;
   const int4 xi = row ? W.xq[W.inv[R.uoff + i]] : make_int4(0, 0, 0, 0);
   __syncthreads();
-  const float *cf = cmap + R.cmap_off + (int64_t)j0 * ns + (row ? i : 0);
   const float ir02 = R.cinv_r02, iw = R.cinv_w, rs = R.crs, rs2 = R.crs2, rc2 = R.crc2;
   const int msep = R.min_sep;
   float gx = 0.0f, gy = 0.0f, gz = 0.0f;
   double zacc = 0.0;
+  if (jc > it) {
+    // Every pair once: at step k lane l takes column (l + k) mod 64, adds the
+    // pair's gradient to its row (i) and to a column sum (j, opposite sign);
+    // the column sums move one lane down after each step, so after the 64
+    // steps lane l holds column l's.  The reference values come from the
+    // map's copy in the same diagonal order (one coalesced load per step).
+    const float *sk = cskew + R.cskew_off + ((int64_t)it * nt + jc) * kCvTile * kCvTile + lane;
+    const int nxt = (lane + 1) & (kCvTile - 1);
+    float hx = 0.0f, hy = 0.0f, hz = 0.0f;
+    for (int k = 0; k < kCvTile; ++k) {
+      const int c = (lane + k) & (kCvTile - 1);
+      const int j = j0 + c;
+      const int4 xj = s_x[c];
+      const float dx = (float)(xj.x - xi.x) * kInvQf, dy = (float)(xj.y - xi.y) * kInvQf,
+                  dz = (float)(xj.z - xi.z) * kInvQf;
+      const float r2 = qr2(dx, dy, dz);
+      const bool valid = row && c < jn && j - i > msep;
+      const float cref = sk[k * kCvTile];
+      if (__ballot(valid && r2 < rc2) != 0ull) {
+        float ct, dct_r;
+        contact_tilde(r2, ir02, iw, rs, rs2, rc2, ct, dct_r);
+        const float diff = ct - cref;
+        const float coef = valid ? 2.0f * diff * dct_r : 0.0f;
+        gx = __builtin_fmaf(-coef, dx, gx);
+        gy = __builtin_fmaf(-coef, dy, gy);
+        gz = __builtin_fmaf(-coef, dz, gz);
+        hx = __builtin_fmaf(coef, dx, hx);
+        hy = __builtin_fmaf(coef, dy, hy);
+        hz = __builtin_fmaf(coef, dz, hz);
+        if (valid) zacc += (double)diff * (double)diff;
+      } else if (valid) {
+        // every pair of this step is beyond the switch: C~ is 0 there
+        zacc += (double)cref * (double)cref;
+      }
+      hx = __shfl(hx, nxt, kCvTile);
+      hy = __shfl(hy, nxt, kCvTile);
+      hz = __shfl(hz, nxt, kCvTile);
+    }
+    W.gtile[(R.cvt_off + (int64_t)jc * nt + it) * kCvTile + lane] = make_float4(gx, gy, gz, 0.0f);
+    W.gtile[(R.cvt_off + (int64_t)it * nt + jc) * kCvTile + lane] = make_float4(hx, hy, hz, 0.0f);
+    const double zs = wave_sum(zacc);
+    if (lane == 0) W.ztile[R.cvt_off + (int64_t)it * nt + jc] = zs;
+    return;
+  }
+  // diagonal tile: both orderings of each pair, each adding to its own row
+  const float *cf = cmap + R.cmap_off + (int64_t)j0 * ns + (row ? i : 0);
   for (int k = 0; k < jn; ++k) {
     const int j = j0 + k;
     const int4 xj = s_x[k];
@@ -953,28 +1033,8 @@ __global__ __launch_bounds__(kCvTile) void k_cv_pairs(const RepInfo *__restrict_
       if (valid && j > i) zacc += (double)diff * (double)diff;
       continue;
     }
-    const float rinv = __builtin_amdgcn_rsqf(r2);
-    // C(u) and dC/du
-    const float u = r2 * ir02, u2 = u * u;
-    const float num = 1.0f + u + u2;
-    const float den = num + u2 * u + u2 * u2;
-    const float iden = __builtin_amdgcn_rcpf(den);
-    const float c = num * iden;
-    const float dnum = __builtin_fmaf(2.0f, u, 1.0f);
-    const float dden = dnum + u2 * __builtin_fmaf(4.0f, u, 3.0f);
-    const float dcdu = (dnum - c * dden) * iden;
-    // quintic switch on r
-    const float rr = r2 * rinv;
-    const float t = (rr - rs) * iw;
-    const float t2 = t * t;
-    const float swp = 1.0f - t2 * t * __builtin_fmaf(t, __builtin_fmaf(6.0f, t, -15.0f), 10.0f);
-    const float dswp = -30.0f * t2 * (1.0f - t) * (1.0f - t) * iw;
-    const bool inner = r2 <= rs2, outer = r2 >= rc2;
-    const float sw = inner ? 1.0f : (outer ? 0.0f : swp);
-    const float dsw = (inner || outer) ? 0.0f : dswp;
-    // C~ and (dC~/dr)/r
-    const float ct = c * sw;
-    const float dct_r = 2.0f * ir02 * dcdu * sw + c * dsw * rinv;
+    float ct, dct_r;
+    contact_tilde(r2, ir02, iw, rs, rs2, rc2, ct, dct_r);
     const float diff = ct - cref;
     const float coef = valid ? 2.0f * diff * dct_r : 0.0f;
     gx = __builtin_fmaf(-coef, dx, gx);
@@ -1417,6 +1477,21 @@ __global__ void k_native_map(const float *__restrict__ xf, int ns, int min_sep, 
   out[k] = v;
 }
 
+// A contact map's copy per 64 x 64 tile in diagonal order:
+// skew[tile][k][l] = C~f(row 64 it + l, column 64 jc + (l + k) mod 64), zero
+// outside the map; one wave per tile.
+__global__ __launch_bounds__(kCvTile) void k_cv_skew(const float *__restrict__ cmap, int ns,
+                                                     float *__restrict__ skew) {
+  const int nt = (ns + kCvTile - 1) / kCvTile;
+  const int it = blockIdx.x / nt, jc = blockIdx.x % nt, l = threadIdx.x;
+  const int i = it * kCvTile + l;
+  float *o = skew + (int64_t)blockIdx.x * kCvTile * kCvTile + l;
+  for (int k = 0; k < kCvTile; ++k) {
+    const int j = jc * kCvTile + ((l + k) & (kCvTile - 1));
+    o[k * kCvTile] = (i < ns && j < ns) ? cmap[(int64_t)j * ns + i] : 0.0f;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
@@ -1467,6 +1542,11 @@ void launch_native_map(const float *xf, int ns, int min_sep, float r0, float rs,
   int64_t n = (int64_t)ns * ns;
   hipLaunchKernelGGL(k_native_map, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, xf, ns,
                      min_sep, r0, rs, rc, out);
+}
+
+void launch_cv_skew(const float *cmap, int ns, float *skew, hipStream_t st) {
+  const int nt = (ns + kCvTile - 1) / kCvTile;
+  hipLaunchKernelGGL(k_cv_skew, dim3(nt * nt), dim3(kCvTile), 0, st, cmap, ns, skew);
 }
 
 template <int P, int U, int M>
@@ -1539,7 +1619,7 @@ void launch_cv(vp_system *s, Work &W, int inc_step, hipStream_t st, bool tan) {
   // maps alone, k_cv_reduce advances it and k_cv is not needed
   const int reduce_inc = any_other ? 0 : inc_step;
   if (nt > 0) {
-    hipLaunchKernelGGL(k_cv_pairs, dim3(nt * nt, s->R), dim3(kCvTile), 0, st, s->info, W, s->cmap);
+    hipLaunchKernelGGL(k_cv_pairs, dim3(nt * nt, s->R), dim3(kCvTile), 0, st, s->info, W, s->cmap, s->cskew);
     if (tan) {
       hipLaunchKernelGGL(k_cv_tangent_pairs, dim3(nt * nt, s->R), dim3(kCvTile), 0, st, s->info, W,
                          s->cmap);

@@ -375,8 +375,8 @@ static vp_status build(vp_system *s, const vp_replica_desc *reps, int32_t n_reps
     double r0, rs, rc;
   };
   std::vector<MapKey> maps;
-  std::vector<int64_t> map_off;
-  int64_t cmap_total = 0;
+  std::vector<int64_t> map_off, skew_off;
+  int64_t cmap_total = 0, skew_total = 0;
   int stage_cap_max = 0, ntypes_max = 0;
   const double cell_target = 0.45;  // nm: fine cells of the candidate search
   const double col_target = 0.8;    // nm: xy columns of the sort order
@@ -507,6 +507,7 @@ static vp_status build(vp_system *s, const vp_replica_desc *reps, int32_t n_reps
     R.crs2 = (float)(d.contact_rs * d.contact_rs);
     R.crc2 = (float)(d.contact_rc * d.contact_rc);
     R.cmap_off = 0;
+    R.cskew_off = 0;
     if (contact) {
       int found = -1;
       for (size_t m = 0; m < maps.size(); ++m) {
@@ -522,9 +523,12 @@ static vp_status build(vp_system *s, const vp_replica_desc *reps, int32_t n_reps
         maps.push_back({d.x_final, d.n_solute, d.contact_min_sep, d.contact_r0, d.contact_rs, d.contact_rc});
         map_off.push_back(cmap_total);
         cmap_total += (int64_t)d.n_solute * d.n_solute;
+        skew_off.push_back(skew_total);
+        skew_total += (int64_t)R.cv_blocks * R.cv_blocks * kCvTile * kCvTile;
         found = (int)maps.size() - 1;
       }
       R.cmap_off = map_off[found];
+      R.cskew_off = skew_off[found];
     }
     off += R.npad;
     uoff += R.n;
@@ -782,6 +786,9 @@ static vp_status build(vp_system *s, const vp_replica_desc *reps, int32_t n_reps
     HIPCHECK(hipMemcpy(dxf, xf.data(), sizeof(float) * xf.size(), hipMemcpyHostToDevice));
     launch_native_map(dxf, k.ns, k.sep, (float)k.r0, (float)k.rs, (float)k.rc, s->cmap + map_off[m], 0);
   }
+  TRY(dalloc(s, &s->cskew, (size_t)std::max<int64_t>(1, skew_total)));
+  for (size_t m = 0; m < maps.size(); ++m)
+    launch_cv_skew(s->cmap + map_off[m], maps[m].ns, s->cskew + skew_off[m], 0);
   const size_t S = (size_t)s->n_slots;
   TRY(dalloc(s, &s->xq_t, S));
   TRY(dalloc(s, &s->vel_t, S));

@@ -91,6 +91,7 @@ struct RepInfo {
   int32_t nlj_types;            // types [0, nlj_types) have epsilon > 0, the others none
   int64_t list_off;             // first element of this replica's list storage
   int64_t cmap_off;             // first element of the native contact map (FP32 [ns][ns])
+  int64_t cskew_off;            // first element of its copy in tile-diagonal order (64 x 64 per tile)
   int32_t cv_blocks;            // contact map: row tiles (ceil(ns / 64)); other kinds: 1
   int64_t cvt_off;              // first entry of this replica's contact-map tile partials
   float cinv_r02, cinv_w;       // contact map: 1/r0^2, 1/(r_c - r_s) (nm)
@@ -250,6 +251,7 @@ struct vp_system {
   int32_t *ex_list = nullptr;   // replica-local user indices
   int32_t *role0 = nullptr;     // [users] 0: listed alone, 1: first atom of a three-atom site, 2: other site atom
   float *cmap = nullptr;        // native contact maps, [ns][ns] per distinct map
+  float *cskew = nullptr;       // the same maps per tile in diagonal order: [tile][k][lane] = C~f(row lane, column (lane + k) mod 64)
   float4 *cforce = nullptr;     // [solute total] constant bias force
   double *xf = nullptr;         // [solute rows][3] FP64 X_f of the replicas that give one
   double *rmsd = nullptr;       // [R] RMSD to X_f (vp_select_path, vp_observables)

@@ -51,6 +51,8 @@ void launch_init_state(vp_system *s, const int32_t *xq_user, const float *v_user
                        const uint8_t *has_v, hipStream_t st);
 void launch_native_map(const float *xf, int ns, int min_sep, float r0, float rs, float rc,
                        float *out, hipStream_t st);
+// the same map per 64 x 64 tile in diagonal order (k_cv_pairs reads it above the diagonal)
+void launch_cv_skew(const float *cmap, int ns, float *skew, hipStream_t st);
 size_t force_lds_bytes(const vp_system *s);
 hipError_t prepare_forces(const vp_system *s);  // dynamic LDS above 64 KB
 void launch_gather_state(vp_system *s, float *x_out, float *v_out, hipStream_t st);
