@@ -94,10 +94,10 @@ typedef struct {
   int32_t n_solute;  /* 0 <= n_solute <= n_atoms; atoms [0, n_solute) are X */
   const double *mass, *gamma, *charge, *sigma, *epsilon; /* [n_atoms] */
   int32_t n_bonds;
-  const int32_t *bonds; /* [n_bonds][2] */
+  const int32_t *bonds; /* [n_bonds][2], two distinct atoms */
   const double *bond_k, *bond_r0;
   int32_t n_angles;
-  const int32_t *angles; /* [n_angles][3]: end, vertex, end */
+  const int32_t *angles; /* [n_angles][3]: end, vertex, end (three distinct atoms) */
   const double *angle_k, *angle_theta0;
   int32_t n_excl;
   const int32_t *excl; /* [n_excl][2]: pairs without nonbonded interaction */

@@ -130,11 +130,17 @@ vp_status validate(const vp_replica_desc &d, int r, bool tangent) {
   for (int b = 0; b < d.n_bonds; ++b)
     for (int k = 0; k < 2; ++k)
       if (d.bonds[2 * b + k] < 0 || d.bonds[2 * b + k] >= d.n_atoms) return bad("bond index out of range");
+  for (int b = 0; b < d.n_bonds; ++b)
+    if (d.bonds[2 * b] == d.bonds[2 * b + 1]) return bad("a bond joins an atom to itself");
   if (d.n_angles < 0 || (d.n_angles > 0 && (!d.angles || !d.angle_k || !d.angle_theta0)))
     return bad("angle arrays");
   for (int b = 0; b < d.n_angles; ++b)
     for (int k = 0; k < 3; ++k)
       if (d.angles[3 * b + k] < 0 || d.angles[3 * b + k] >= d.n_atoms) return bad("angle index out of range");
+  for (int b = 0; b < d.n_angles; ++b) {
+    const int32_t *q = d.angles + 3 * b;
+    if (q[0] == q[1] || q[1] == q[2] || q[0] == q[2]) return bad("an angle names one atom twice");
+  }
   if (d.n_excl < 0 || (d.n_excl > 0 && !d.excl)) return bad("exclusion array");
   for (int b = 0; b < d.n_excl; ++b)
     for (int k = 0; k < 2; ++k)

@@ -45,6 +45,14 @@ def test_invalid_arguments_are_rejected_without_a_gpu():
     with pytest.raises(vp.VpError) as e:
         vp.System([bad])
     assert e.value.status == -1 and "bond index" in str(e.value)
+    bad = dict(d, bonds=np.array([[3, 3]], np.int32), bond_k=np.ones(1), bond_r0=np.ones(1))
+    with pytest.raises(vp.VpError) as e:
+        vp.System([bad])
+    assert e.value.status == -1 and "itself" in str(e.value)
+    bad = dict(d, angles=np.array([[2, 3, 2]], np.int32), angle_k=np.ones(1), angle_theta0=np.ones(1))
+    with pytest.raises(vp.VpError) as e:
+        vp.System([bad])
+    assert e.value.status == -1 and "twice" in str(e.value)
     bad = dict(d, x_final=None)
     with pytest.raises(vp.VpError) as e:
         vp.System([bad])
