@@ -940,47 +940,59 @@ __device__ __forceinline__ void contact_tilde(float r2, float ir02, float iw, fl
 //   z = sum_{i<j, j-i>min_sep} (C~(r_ij) - C~f_ij)^2,
 //   dz/dx_i = -sum_j 2 (C~(r_ij) - C~f_ij) (dC~/dr)/r (x_j - x_i),
 // with C = (1+u+u^2)/(1+u+u^2+u^3+u^4), u = (r/r0)^2, times a quintic switch
-// from 1 at r_s to 0 at r_c.  A tile above the diagonal evaluates each of its
-// pairs once and stores the row sums and the column sums (as the partials the
-// mirrored tile below the diagonal would give); a diagonal tile visits both
-// orderings of each pair, each contributing to its own row's gradient, and z
-// takes its pairs j > i.  The column-tile partials are reduced in a fixed
-// order by k_cv_reduce.
-__global__ __launch_bounds__(kCvTile) void k_cv_pairs(const RepInfo *__restrict__ info, Work W,
-                                                      const float *__restrict__ cmap,
-                                                      const float *__restrict__ cskew) {
+// from 1 at r_s to 0 at r_c.  Only the tiles on and above the diagonal are
+// launched, those above it first, two waves per tile, each wave taking half of
+// the tile's 64 column steps; the two halves are added in wave order.  A tile
+// above the diagonal evaluates each of its pairs once and stores the row sums
+// and the column sums (as the partials the mirrored tile below the diagonal
+// would give); a diagonal tile visits both orderings of each pair, each
+// contributing to its own row's gradient, and z takes its pairs j > i.  The
+// column-tile partials are reduced in a fixed order by k_cv_reduce.
+constexpr int kCvHalf = kCvTile / 2;  // column steps per wave
+__global__ __launch_bounds__(2 * kCvTile) void k_cv_pairs(const RepInfo *__restrict__ info, Work W,
+                                                          const float *__restrict__ cmap,
+                                                          const float *__restrict__ cskew) {
   __shared__ int4 s_x[kCvTile];
+  __shared__ float4 s_g[2][kCvTile];  // wave 1's row and column sums
+  __shared__ double s_z;
   const int r = blockIdx.y;
   const RepInfo &R = info[r];
   if (R.bias != VP_BIAS_CONTACT && R.bias != VP_BIAS_RMD_CONTACT) return;
-  const int nt = R.cv_blocks;
-  if ((int)blockIdx.x >= nt * nt) return;
-  const int it = blockIdx.x / nt, jc = blockIdx.x % nt;
-  const int lane = threadIdx.x, ns = R.ns;
-  if (jc < it) {  // these pairs are evaluated once, by the tile (jc, it) above the diagonal
-    if (lane == 0) W.ztile[R.cvt_off + (int64_t)it * nt + jc] = 0.0;
-    return;
+  const int nt = R.cv_blocks, noff = nt * (nt - 1) / 2;
+  if ((int)blockIdx.x >= noff + nt) return;
+  int it, jc;
+  if ((int)blockIdx.x < noff) {  // the b-th tile above the diagonal, row tiles in order
+    int b = blockIdx.x;
+    it = 0;
+    while (b >= nt - 1 - it) {
+      b -= nt - 1 - it;
+      ++it;
+    }
+    jc = it + 1 + b;
+  } else {
+    it = jc = (int)blockIdx.x - noff;
   }
+  const int lane = threadIdx.x & (kCvTile - 1), wv = threadIdx.x / kCvTile, ns = R.ns;
   const int i = it * kCvTile + lane;
   const int j0 = jc * kCvTile, jn = min(kCvTile, ns - j0);
-  s_x[lane] = lane < jn ? W.xq[W.inv[R.uoff + j0 + lane]] : make_int4(0, 0, 0, 0);
+  if (wv == 0) s_x[lane] = lane < jn ? W.xq[W.inv[R.uoff + j0 + lane]] : make_int4(0, 0, 0, 0);
   const bool row = i < ns;
   const int4 xi = row ? W.xq[W.inv[R.uoff + i]] : make_int4(0, 0, 0, 0);
   __syncthreads();
   const float ir02 = R.cinv_r02, iw = R.cinv_w, rs = R.crs, rs2 = R.crs2, rc2 = R.crc2;
   const int msep = R.min_sep;
-  float gx = 0.0f, gy = 0.0f, gz = 0.0f;
+  float gx = 0.0f, gy = 0.0f, gz = 0.0f, hx = 0.0f, hy = 0.0f, hz = 0.0f;
   double zacc = 0.0;
+  const int k0 = wv * kCvHalf;
   if (jc > it) {
     // Every pair once: at step k lane l takes column (l + k) mod 64, adds the
     // pair's gradient to its row (i) and to a column sum (j, opposite sign);
-    // the column sums move one lane down after each step, so after the 64
-    // steps lane l holds column l's.  The reference values come from the
-    // map's copy in the same diagonal order (one coalesced load per step).
+    // the column sums move one lane down after each step.  The reference
+    // values come from the map's copy in the same diagonal order (one
+    // coalesced load per step).
     const float *sk = cskew + R.cskew_off + ((int64_t)it * nt + jc) * kCvTile * kCvTile + lane;
     const int nxt = (lane + 1) & (kCvTile - 1);
-    float hx = 0.0f, hy = 0.0f, hz = 0.0f;
-    for (int k = 0; k < kCvTile; ++k) {
+    for (int k = k0; k < k0 + kCvHalf; ++k) {
       const int c = (lane + k) & (kCvTile - 1);
       const int j = j0 + c;
       const int4 xj = s_x[c];
@@ -1009,42 +1021,63 @@ __global__ __launch_bounds__(kCvTile) void k_cv_pairs(const RepInfo *__restrict_
       hy = __shfl(hy, nxt, kCvTile);
       hz = __shfl(hz, nxt, kCvTile);
     }
-    W.gtile[(R.cvt_off + (int64_t)jc * nt + it) * kCvTile + lane] = make_float4(gx, gy, gz, 0.0f);
-    W.gtile[(R.cvt_off + (int64_t)it * nt + jc) * kCvTile + lane] = make_float4(hx, hy, hz, 0.0f);
-    const double zs = wave_sum(zacc);
-    if (lane == 0) W.ztile[R.cvt_off + (int64_t)it * nt + jc] = zs;
-    return;
-  }
-  // diagonal tile: both orderings of each pair, each adding to its own row
-  const float *cf = cmap + R.cmap_off + (int64_t)j0 * ns + (row ? i : 0);
-  for (int k = 0; k < jn; ++k) {
-    const int j = j0 + k;
-    const int4 xj = s_x[k];
-    const float dx = (float)(xj.x - xi.x) * kInvQf, dy = (float)(xj.y - xi.y) * kInvQf,
-                dz = (float)(xj.z - xi.z) * kInvQf;
-    const float r2 = qr2(dx, dy, dz);
-    const bool valid = row && abs(j - i) > msep;
-    const float cref = cf[(int64_t)k * ns];
-    if (__ballot(row && r2 < rc2) == 0ull) {
-      // every row of the tile is beyond the switch: C~ and its derivative are
-      // exactly 0 there, so the gradient gains nothing and z only the
-      // reference term (the same bits as the full evaluation below)
-      const float diff = 0.0f - cref;
-      if (valid && j > i) zacc += (double)diff * (double)diff;
-      continue;
+    // after its 32 steps wave 1's lane l holds column l's sum, wave 0's
+    // column (l + 32) mod 64's: move those by half a wave
+    if (wv == 0) {
+      const int half = (lane + kCvHalf) & (kCvTile - 1);
+      hx = __shfl(hx, half, kCvTile);
+      hy = __shfl(hy, half, kCvTile);
+      hz = __shfl(hz, half, kCvTile);
     }
-    float ct, dct_r;
-    contact_tilde(r2, ir02, iw, rs, rs2, rc2, ct, dct_r);
-    const float diff = ct - cref;
-    const float coef = valid ? 2.0f * diff * dct_r : 0.0f;
-    gx = __builtin_fmaf(-coef, dx, gx);
-    gy = __builtin_fmaf(-coef, dy, gy);
-    gz = __builtin_fmaf(-coef, dz, gz);
-    if (valid && j > i) zacc += (double)diff * (double)diff;
+  } else {
+    // diagonal tile: both orderings of each pair, each adding to its own row
+    const float *cf = cmap + R.cmap_off + (int64_t)j0 * ns + (row ? i : 0);
+    for (int k = k0; k < min(jn, k0 + kCvHalf); ++k) {
+      const int j = j0 + k;
+      const int4 xj = s_x[k];
+      const float dx = (float)(xj.x - xi.x) * kInvQf, dy = (float)(xj.y - xi.y) * kInvQf,
+                  dz = (float)(xj.z - xi.z) * kInvQf;
+      const float r2 = qr2(dx, dy, dz);
+      const bool valid = row && abs(j - i) > msep;
+      const float cref = cf[(int64_t)k * ns];
+      if (__ballot(row && r2 < rc2) == 0ull) {
+        // every row of the tile is beyond the switch: C~ and its derivative
+        // are exactly 0 there, so the gradient gains nothing and z only the
+        // reference term (the same bits as the full evaluation below)
+        const float diff = 0.0f - cref;
+        if (valid && j > i) zacc += (double)diff * (double)diff;
+        continue;
+      }
+      float ct, dct_r;
+      contact_tilde(r2, ir02, iw, rs, rs2, rc2, ct, dct_r);
+      const float diff = ct - cref;
+      const float coef = valid ? 2.0f * diff * dct_r : 0.0f;
+      gx = __builtin_fmaf(-coef, dx, gx);
+      gy = __builtin_fmaf(-coef, dy, gy);
+      gz = __builtin_fmaf(-coef, dz, gz);
+      if (valid && j > i) zacc += (double)diff * (double)diff;
+    }
   }
-  W.gtile[(R.cvt_off + (int64_t)jc * nt + it) * kCvTile + lane] = make_float4(gx, gy, gz, 0.0f);
   const double zs = wave_sum(zacc);
-  if (lane == 0) W.ztile[R.cvt_off + (int64_t)it * nt + jc] = zs;
+  if (wv == 1) {
+    s_g[0][lane] = make_float4(gx, gy, gz, 0.0f);
+    s_g[1][lane] = make_float4(hx, hy, hz, 0.0f);
+    if (lane == 0) s_z = zs;
+  }
+  __syncthreads();
+  if (wv == 1) return;
+  const float4 g1 = s_g[0][lane];
+  W.gtile[(R.cvt_off + (int64_t)jc * nt + it) * kCvTile + lane] =
+      make_float4(gx + g1.x, gy + g1.y, gz + g1.z, 0.0f);
+  if (jc > it) {
+    const float4 h1 = s_g[1][lane];
+    W.gtile[(R.cvt_off + (int64_t)it * nt + jc) * kCvTile + lane] =
+        make_float4(hx + h1.x, hy + h1.y, hz + h1.z, 0.0f);
+  }
+  if (lane == 0) {
+    W.ztile[R.cvt_off + (int64_t)it * nt + jc] = zs + s_z;
+    if (jc > it) W.ztile[R.cvt_off + (int64_t)jc * nt + it] = 0.0;  // the mirrored tile's share
+  }
 }
 
 // Tangent of the contact-map gradient, one wave per 64 x 64 tile as in
@@ -1619,7 +1652,8 @@ void launch_cv(vp_system *s, Work &W, int inc_step, hipStream_t st, bool tan) {
   // maps alone, k_cv_reduce advances it and k_cv is not needed
   const int reduce_inc = any_other ? 0 : inc_step;
   if (nt > 0) {
-    hipLaunchKernelGGL(k_cv_pairs, dim3(nt * nt, s->R), dim3(kCvTile), 0, st, s->info, W, s->cmap, s->cskew);
+    hipLaunchKernelGGL(k_cv_pairs, dim3(nt * (nt + 1) / 2, s->R), dim3(2 * kCvTile), 0, st, s->info, W, s->cmap,
+                       s->cskew);
     if (tan) {
       hipLaunchKernelGGL(k_cv_tangent_pairs, dim3(nt * nt, s->R), dim3(kCvTile), 0, st, s->info, W,
                          s->cmap);
