@@ -567,19 +567,17 @@ __global__ __launch_bounds__(kBondedThreads) void k_bonded_forces(Work W, const 
     const BGroup G = groups[t];
     const int s0 = W.inv[G.ga], s1 = W.inv[G.ga + 1], s2 = W.inv[G.ga + 2];
     const int4 p0 = W.xq[s0], p1 = W.xq[s1], p2 = W.xq[s2];
+    // the pair forces these terms are added to, loaded with the positions
+    const int64_t fs = W.fstride;
+    const int64_t at[9] = {s0, fs + s0, 2 * fs + s0, s1, fs + s1, 2 * fs + s1, s2, fs + s2, 2 * fs + s2};
+    long long fp[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) fp[q] = W.F[at[q]];
     double f[9] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int q = 0; q < kGroupTerms; ++q) group_term(G.code[q], G.k[q], G.r0[q], p0, p1, p2, f);
-    const int64_t fs = W.fstride;
-    W.F[s0] += to_fix(f[0]);
-    W.F[fs + s0] += to_fix(f[1]);
-    W.F[2 * fs + s0] += to_fix(f[2]);
-    W.F[s1] += to_fix(f[3]);
-    W.F[fs + s1] += to_fix(f[4]);
-    W.F[2 * fs + s1] += to_fix(f[5]);
-    W.F[s2] += to_fix(f[6]);
-    W.F[fs + s2] += to_fix(f[7]);
-    W.F[2 * fs + s2] += to_fix(f[8]);
+#pragma unroll
+    for (int q = 0; q < 9; ++q) W.F[at[q]] = fp[q] + to_fix(f[q]);
     return;
   }
   const int wg = xcd_tile((int)blockIdx.x, nwa);
@@ -589,6 +587,7 @@ __global__ __launch_bounds__(kBondedThreads) void k_bonded_forces(Work W, const 
   const int ga = atoms[k];
   const int slot = W.inv[ga];
   const int4 xi = W.xq[slot];
+  const long long f0 = W.F[slot], f1 = W.F[W.fstride + slot], f2 = W.F[2 * W.fstride + slot];
   double bx = 0.0, by = 0.0, bz = 0.0, ebond = 0.0, eangle = 0.0;
   const int t0 = start[k], t1 = start[k + 1];
   for (int u0 = t0; u0 < t1; u0 += kBondBatch) {
@@ -611,9 +610,9 @@ __global__ __launch_bounds__(kBondedThreads) void k_bonded_forces(Work W, const 
     for (int u = 0; u < kBondBatch; ++u)
       if (u0 + u < t1) bonded_term<false>(T[u], xi, x1[u], x2[u], bx, by, bz, ebond, eangle);
   }
-  W.F[slot] += to_fix(bx);
-  W.F[W.fstride + slot] += to_fix(by);
-  W.F[2 * W.fstride + slot] += to_fix(bz);
+  W.F[slot] = f0 + to_fix(bx);
+  W.F[W.fstride + slot] = f1 + to_fix(by);
+  W.F[2 * W.fstride + slot] = f2 + to_fix(bz);
 }
 
 // Bonded energies and virial (no forces), one thread per atom: every atom
