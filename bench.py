@@ -35,7 +35,7 @@ PEAK_FP32_TFLOPS = 157.3    # MI355X FP32 vector peak
 # HBM bytes per launch of the force kernel on this workload, from rocprofv3
 # FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 (factors from a 256 MiB device copy);
 # see profiles/counters_64x12560.md.  Set to None when the kernel changes.
-FORCE_TRAFFIC_BYTES = (306592 * 2.000 + 19200 * 1.000) * 1024
+FORCE_TRAFFIC_BYTES = (306680 * 2.000 + 19200 * 1.000) * 1024
 
 
 def _cpu_model():

@@ -875,7 +875,7 @@ static vp_status restore_forces(vp_system *s) {
   return VP_OK;
 }
 
-// Shortest of `reps` timed executions of the launches `plan` (after one untimed).
+// Shortest of `reps` timed executions of the launches `plan`.
 static vp_status time_plan(vp_system *s, const std::vector<vp_system::ForceLaunch> &plan, int reps,
                            double *ms) {
   hipEvent_t a, b;
@@ -883,20 +883,37 @@ static vp_status time_plan(vp_system *s, const std::vector<vp_system::ForceLaunc
   HIPCHECK(hipEventCreate(&b));
   double best = 1e30;
   hipError_t e = hipSuccess;
-  for (int k = 0; k <= reps && e == hipSuccess; ++k) {
+  for (int k = 0; k < reps && e == hipSuccess; ++k) {
     e = hipEventRecord(a, 0);
     for (const auto &g : plan) launch_forces_shape(s, s->traj, g.shape, g.blist, g.nblk, 0);
     if (e == hipSuccess) e = hipEventRecord(b, 0);
     if (e == hipSuccess) e = hipEventSynchronize(b);
     float t = 0.0f;
     if (e == hipSuccess) e = hipEventElapsedTime(&t, a, b);
-    if (k > 0 && t < best) best = t;
+    if (t < best) best = t;
   }
   (void)hipEventDestroy(a);
   (void)hipEventDestroy(b);
   if (e == hipSuccess) e = hipGetLastError();
   if (e != hipSuccess) return fail(VP_ERR_HIP, std::string("autotune: ") + hipGetErrorString(e));
   *ms = best;
+  return VP_OK;
+}
+
+// The best launch time of each plan, the plans taken in turn over `rounds`
+// rounds (one untimed launch of each first), so that a clock still settling
+// favours none of them.
+static vp_status time_plans(vp_system *s, const std::vector<std::vector<vp_system::ForceLaunch>> &plans,
+                            int rounds, std::vector<double> &ms) {
+  ms.assign(plans.size(), 1e30);
+  for (const auto &plan : plans)
+    for (const auto &g : plan) launch_forces_shape(s, s->traj, g.shape, g.blist, g.nblk, 0);
+  for (int k = 0; k < rounds; ++k)
+    for (size_t i = 0; i < plans.size(); ++i) {
+      double t = 0.0;
+      TRY(time_plan(s, plans[i], 1, &t));
+      ms[i] = std::min(ms[i], t);
+    }
   return VP_OK;
 }
 
@@ -928,10 +945,14 @@ static vp_status autotune(vp_system *s) {
     int32_t *p = nullptr;
     TRY(upload(s, &p, b.blocks));
     dev[i] = p;
+    std::vector<std::vector<vp_system::ForceLaunch>> plans;
+    for (int k = 0; k < kNumForceShapes; ++k) plans.push_back({{k, p, (int)b.blocks.size()}});
+    std::vector<double> t;
+    TRY(time_plans(s, plans, kReps, t));
     int best = 0;
     for (int k = 0; k < kNumForceShapes; ++k) {
-      TRY(time_plan(s, {{k, p, (int)b.blocks.size()}}, kReps, &b.ms[k]));
-      if (b.ms[k] < b.ms[best]) best = k;
+      b.ms[k] = t[k];
+      if (t[k] < t[best]) best = k;
     }
     b.shape = best;
   }
@@ -943,17 +964,18 @@ static vp_status autotune(vp_system *s) {
     s->plan_split = false;
     return restore_forces(s);
   }
-  double t_split = 0.0, t_one = 1e30;
+  std::vector<std::vector<vp_system::ForceLaunch>> plans{split};
+  for (int k = 0; k < kNumForceShapes; ++k) plans.push_back({{k, nullptr, s->n_blocks}});
+  std::vector<double> t;
+  TRY(time_plans(s, plans, kReps, t));
+  const double t_split = t[0];
+  double t_one = 1e30;
   int one = 0;
-  TRY(time_plan(s, split, kReps, &t_split));
-  for (int k = 0; k < kNumForceShapes; ++k) {
-    double t = 0.0;
-    TRY(time_plan(s, {{k, nullptr, s->n_blocks}}, kReps, &t));
-    if (t < t_one) {
-      t_one = t;
+  for (int k = 0; k < kNumForceShapes; ++k)
+    if (t[1 + k] < t_one) {
+      t_one = t[1 + k];
       one = k;
     }
-  }
   if (t_split < t_one) {
     s->force_plan = split;
     s->plan_split = true;
