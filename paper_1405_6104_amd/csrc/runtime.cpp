@@ -902,18 +902,24 @@ static vp_status time_plan(vp_system *s, const std::vector<vp_system::ForceLaunc
 
 // The best launch time of each plan, the plans taken in turn over `rounds`
 // rounds (one untimed launch of each first), so that a clock still settling
-// favours none of them.
+// favours none of them; before each timed launch a 256 MiB read evicts the
+// last-level cache, as the other kernels of a step do between two force
+// launches of a trajectory.
 static vp_status time_plans(vp_system *s, const std::vector<std::vector<vp_system::ForceLaunch>> &plans,
                             int rounds, std::vector<double> &ms) {
+  constexpr size_t kFlush = size_t(256) << 20;
+  TmpBuf flush(s, kFlush), sink(s, sizeof(int));
   ms.assign(plans.size(), 1e30);
   for (const auto &plan : plans)
     for (const auto &g : plan) launch_forces_shape(s, s->traj, g.shape, g.blist, g.nblk, 0);
   for (int k = 0; k < rounds; ++k)
     for (size_t i = 0; i < plans.size(); ++i) {
+      if (flush.p && sink.p) launch_touch(flush.p, kFlush, (int *)sink.p, 0);
       double t = 0.0;
       TRY(time_plan(s, plans[i], 1, &t));
       ms[i] = std::min(ms[i], t);
     }
+  HIPCHECK(hipDeviceSynchronize());  // the temporary buffers are released on return
   return VP_OK;
 }
 

@@ -53,6 +53,8 @@ void launch_native_map(const float *xf, int ns, int min_sep, float r0, float rs,
                        float *out, hipStream_t st);
 // the same map per 64 x 64 tile in diagonal order (k_cv_pairs reads it above the diagonal)
 void launch_cv_skew(const float *cmap, int ns, float *skew, hipStream_t st);
+// reads `bytes` of device memory (autotuning: evicts the last-level cache between timed launches)
+void launch_touch(const void *p, size_t bytes, int *sink, hipStream_t st);
 size_t force_lds_bytes(const vp_system *s);
 hipError_t prepare_forces(const vp_system *s);  // dynamic LDS above 64 KB
 void launch_gather_state(vp_system *s, float *x_out, float *v_out, hipStream_t st);
